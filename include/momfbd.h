@@ -1,0 +1,161 @@
+/*
+ * libmomfbd -- C-ABI of the MOMFBD hot path on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Asensio Ramos et al., "torchmfbd: a flexible multi-object
+ * multi-frame blind deconvolution code"):
+ *   for every patch p, channel c (an object/diversity pair) and frame j
+ *     phi   = sum_m alpha[p][j][m] Z_c,m + theta_c           (Eq. wavefront)
+ *     P     = A_c exp(i phi)                                  (Sect. "Wavefronts")
+ *     s     = kappa_c |IDFT(P)|^2, kappa_c = 1/(N^2 sum A_c^2) (Eq. pupil_func;
+ *             unit integral of the PSF, Sect. "PSF")
+ *     S     = DFT(s)
+ *   for every object k (channels c with channel_object[c] == k)
+ *     O_k   = sum w D conj(S) / (sum w |S|^2 + gamma_k)       (Eq. object_optimization)
+ *     L_p   = sum_k sum_u [ sum_{c,j} w |D - O_k S|^2 + gamma_k |O_k|^2 ]
+ *           = Eq. loss_momfbd evaluated at the Wiener object
+ *   and dL/dalpha by the adjoint of that chain with the object held at its
+ *   optimum.
+ *
+ * Conventions
+ *   DFT(x)(u) = sum_r x(r) exp(-2 pi i u.r/N); IDFT is the same sum with +i
+ *   and no 1/N^2.  No fftshift: the PSF of a flat wavefront peaks at pixel
+ *   (0,0).  Half spectra are [N][N/2+1] arrays of interleaved complex64
+ *   (kx fastest).  The loss sums over the full N x N frequency grid.
+ *   Phases are in radians at the reference wavelength; a channel at another
+ *   wavelength carries the lambda_0/lambda_c factor inside its basis.
+ *   The frame weights w are the gamma_kj of Eq. log_posterior; "gamma" here
+ *   is the Wiener constant S_n/S_0 of Eq. object_optimization.
+ *
+ * Memory and threading
+ *   All array arguments of the per-call functions are DEVICE pointers owned
+ *   by the caller, C-order and contiguous, on the device the plan was
+ *   created on.  Plan creation reads HOST arrays and copies what it needs.
+ *   Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *   nothing synchronises.  No function allocates device memory after plan
+ *   creation; scratch comes from the caller's workspace.  A plan and its
+ *   workspace may be used by one stream at a time.
+ *
+ * Errors
+ *   Every function returns MOMFBD_OK or a negative status.  Argument errors
+ *   are detected before any work is enqueued, and outputs are then left
+ *   untouched.  MOMFBD_EDEVICE reports a HIP error, including one left by an
+ *   earlier asynchronous launch.  NaN or Inf in the inputs are not checked:
+ *   they propagate into the loss of the affected patch.
+ */
+#ifndef MOMFBD_H
+#define MOMFBD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOMFBD_OK 0
+#define MOMFBD_EINVAL (-1)        /* NULL pointer, bad size, bad channel map   */
+#define MOMFBD_EUNSUPPORTED (-2)  /* patch size, mode count or pupil not supported */
+#define MOMFBD_EWORKSPACE (-3)    /* workspace missing or misaligned           */
+#define MOMFBD_EDEVICE (-4)       /* HIP error                                 */
+
+typedef struct momfbd_plan_s* momfbd_plan;
+
+typedef struct {
+  int N;   /* patch side in pixels; 64 is supported                          */
+  int P;   /* number of patches                                              */
+  int C;   /* number of channels (object/diversity pairs), 1..32             */
+  int K;   /* number of objects, 1..32                                       */
+  int J;   /* frames per channel                                             */
+  int M;   /* wavefront modes, 1..256; J*M <= 8192                           */
+  const int* channel_object; /* HOST [C]: object of each channel, in [0,K);
+                                every object must own at least one channel  */
+} momfbd_desc;
+
+/* Create a plan (Sect. "Wavefronts").
+ *   pupil     HOST float [C][N][N]: aperture transmission A_c(v) >= 0.  Its
+ *             support must fit in an (N/2) x (N/2) box (a pupil diameter below
+ *             N/2 pixels, which also keeps the OTF free of aliasing); the plan
+ *             translates it to the centre of the grid, which leaves the PSF
+ *             unchanged.
+ *   basis     HOST float [C][M][N][N]: modes Z_c,m in radians (already scaled
+ *             by lambda_0/lambda_c).
+ *   diversity HOST float [C][N][N] in radians, or NULL for none.
+ *   out       receives the plan.
+ * Allocates device tables on the current device.
+ * Errors: EINVAL (NULL, sizes, channel map, zero pupil), EUNSUPPORTED (N,
+ * M, J*M, pupil support), EDEVICE. */
+int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float* basis,
+                       const float* diversity, momfbd_plan* out);
+
+/* Release a plan (NULL is accepted).  The caller must have synchronised any
+ * stream still using it. */
+int momfbd_plan_destroy(momfbd_plan plan);
+
+/* Bytes of device workspace needed by every per-call function of this plan.
+ * The workspace must be 256-byte aligned. */
+int momfbd_workspace_size(momfbd_plan plan, size_t* bytes);
+
+/* Data preparation (Sect. "Division in patches and apodization").
+ *   frames  DEVICE float [C][J][H][W] observed images.
+ *   stride  patch step: corners y0 = i*stride, i = 0..(H-N)/stride, same
+ *           for x; patches ordered row-major; their count must equal P.
+ *   apod    DEVICE float [N][N] apodization window W.
+ *   D       DEVICE complex64 [P][C][J][N][N/2+1] output:
+ *           D = DFT(W (x - m) + m), m the mean of each patch frame.
+ * Errors: EINVAL (NULL, H/W/stride inconsistent with P), EWORKSPACE, EDEVICE. */
+int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int stride,
+                        const float* apod, void* D, void* ws, void* stream);
+
+/* Forward model only: PSFs and/or OTFs for coefficients alpha.
+ *   alpha   DEVICE float [P][J][M].
+ *   psf     DEVICE float [P][C][J][N][N] unit-sum PSFs, or NULL.
+ *   otf     DEVICE complex64 [P][C][J][N][N/2+1] OTF half spectra, or NULL.
+ * Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, void* ws,
+                   void* stream);
+
+/* Loss and gradient (Eqs. object_optimization and loss_momfbd).
+ *   alpha        DEVICE float [P][J][M]
+ *   D            DEVICE complex64 [P][C][J][N][N/2+1] data spectra
+ *   gamma        DEVICE float [K][N][N/2+1] per-frequency Wiener constant, or
+ *                NULL to use gamma_scalar for every object and frequency
+ *   weights      DEVICE float [C][J] frame weights w, or NULL for 1
+ *   loss         DEVICE double [P]: L_p (FP64 reduction)
+ *   grad         DEVICE float [P][J][M]: dL_p/dalpha, or NULL for loss only
+ * Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                     float gamma_scalar, const float* weights, double* loss, float* grad,
+                     void* ws, void* stream);
+
+/* Wiener object estimate in pixel space (Eq. object_optimization):
+ *   obj  DEVICE float [P][K][N][N], o_k = Re IDFT(O_k) / N^2 -- the restored
+ *        apodized patch in the units of the frames.
+ * Other arguments as momfbd_loss_grad.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
+                           const float* gamma, float gamma_scalar, const float* weights,
+                           float* obj, void* ws, void* stream);
+
+/* Kernel timing for measurement.  After momfbd_profile_start, every kernel
+ * launched by this plan's calls (up to max_launches launches) is bracketed
+ * by a pair of HIP events recorded on the call's stream.  Events are created
+ * here, not in the calls.  Errors: EINVAL, EDEVICE. */
+int momfbd_profile_start(momfbd_plan plan, int max_launches);
+
+/* Synchronise on the recorded events, stop timing, and report per kernel
+ * kind: a static name ("phase", "forward", "object", "adjoint", "grad",
+ * "prepare", "objimg"), the summed milliseconds and the launch count, for at
+ * most `cap` kinds.  Returns the number of kinds written (>= 0) or a
+ * negative status. */
+int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* total_ms,
+                        int* launches);
+
+/* Human-readable text of a status code. */
+const char* momfbd_status_string(int status);
+
+/* Sizes the plan was created with (any out pointer may be NULL). */
+int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOMFBD_H */

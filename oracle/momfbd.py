@@ -43,18 +43,27 @@ def _dft_matrix(N: int, sign: int) -> np.ndarray:
     return _MAT_CACHE[key]
 
 
+def _apply2(x: np.ndarray, sign: int) -> np.ndarray:
+    """F0 x F1^T over the last two axes of a stack, as two large matrix products
+    (the stack is folded into the free dimension of each product)."""
+    x = np.asarray(x, dtype=np.complex128)
+    n0, n1 = x.shape[-2], x.shape[-1]
+    F0 = _dft_matrix(n0, sign)
+    F1 = _dft_matrix(n1, sign)
+    lead = x.shape[:-2]
+    y = (x.reshape(-1, n1) @ F1.T).reshape(lead + (n0, n1))          # along columns
+    y = np.swapaxes(y, -1, -2).reshape(-1, n0) @ F0.T                 # along rows
+    return np.ascontiguousarray(np.swapaxes(y.reshape(lead + (n1, n0)), -1, -2))
+
+
 def dft2(x: np.ndarray) -> np.ndarray:
     """Unnormalised forward 2-D DFT over the last two axes."""
-    F0 = _dft_matrix(x.shape[-2], -1)
-    F1 = _dft_matrix(x.shape[-1], -1)
-    return F0 @ np.asarray(x, dtype=np.complex128) @ F1.T
+    return _apply2(x, -1)
 
 
 def idft2_un(X: np.ndarray) -> np.ndarray:
     """Unnormalised inverse 2-D DFT (exp(+2 pi i u.r/N), no 1/N^2)."""
-    G0 = _dft_matrix(X.shape[-2], +1)
-    G1 = _dft_matrix(X.shape[-1], +1)
-    return G0 @ np.asarray(X, dtype=np.complex128) @ G1.T
+    return _apply2(X, +1)
 
 
 def expand_half(Xh: np.ndarray, N: int) -> np.ndarray:
@@ -293,12 +302,13 @@ def simulate_frames(objects, alpha, basis, diversity, pupil, chan_obj, noise=Non
     C = len(chan_obj)
     N = pupil.shape[-1]
     out = np.empty((P, C, J, N, N))
-    for p in range(P):
-        Ok = [dft2(objects[p, k]) for k in range(objects.shape[1])]
-        for c in range(C):
-            for j in range(J):
-                phi = wavefront(alpha[p, j], basis[c], diversity[c])
-                s = psf(pupil[c], phi)
-                img = idft2_un(Ok[int(chan_obj[c])] * otf(s)).real / float(N * N)
-                out[p, c, j] = img if noise is None else img + noise[p, c, j]
+    Ok = dft2(objects)                                          # [P][K][N][N]
+    a = np.asarray(alpha, np.float64)
+    for c in range(C):
+        # all patches and frames of the channel at once (stacked 2-D transforms)
+        phi = np.tensordot(a, np.asarray(basis[c], np.float64), axes=(2, 0)) \
+            + np.asarray(diversity[c], np.float64)              # [P][J][N][N]
+        s = psf(pupil[c], phi)
+        img = idft2_un(Ok[:, int(chan_obj[c])][:, None] * otf(s)).real / float(N * N)
+        out[:, c] = img if noise is None else img + noise[:, c]
     return out

@@ -1,0 +1,31 @@
+"""MI355X-native MOMFBD hot path: loss, gradient and Wiener object of
+multi-object multi-frame blind deconvolution on hand-written gfx950 kernels.
+
+The compute lives in libmomfbd.so (C-ABI declared in include/momfbd.h);
+this package is its binding.  `import paper_2505_10639_amd` does not load
+the library; the first call does, and fails loudly if it is not built.
+"""
+
+from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_create,
+                   momfbd_plan_destroy, momfbd_workspace_size, momfbd_plan_dims,
+                   momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
+                   momfbd_object_estimate, momfbd_profile_start,
+                   momfbd_profile_stop, lib)
+
+__all__ = [
+    "MomfbdError", "LIB_PATH", "momfbd_status_string", "momfbd_plan_create",
+    "momfbd_plan_destroy", "momfbd_workspace_size", "momfbd_plan_dims", "momfbd_prepare_data",
+    "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",
+    "momfbd_profile_stop", "lib", "Plan",
+    "MomfbdLoss", "momfbd_loss",
+]
+
+
+def __getattr__(name):
+    if name == "Plan":
+        from .plan import Plan
+        return Plan
+    if name in ("MomfbdLoss", "momfbd_loss"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

@@ -1,0 +1,173 @@
+"""ctypes binding of libmomfbd.so: the C-ABI functions under the same names.
+
+Argument marshalling only.  Device arrays are torch tensors (their data
+pointers are passed); host arrays for plan creation are numpy arrays.  The
+stream defaults to torch's current stream on the tensors' device.  There is
+no fallback: if the library is not built, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmomfbd.so")
+
+MOMFBD_OK = 0
+MOMFBD_EINVAL = -1
+MOMFBD_EUNSUPPORTED = -2
+MOMFBD_EWORKSPACE = -3
+MOMFBD_EDEVICE = -4
+
+
+class MomfbdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {momfbd_status_string(status)} (status {status})")
+
+
+class momfbd_desc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int),
+                ("K", ctypes.c_int), ("J", ctypes.c_int), ("M", ctypes.c_int),
+                ("channel_object", ctypes.POINTER(ctypes.c_int))]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
+           -3: "workspace missing or misaligned", -4: "HIP device error"}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MomfbdError(MOMFBD_EDEVICE, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        i, f, d = ctypes.c_int, ctypes.c_float, ctypes.c_double
+        L.momfbd_plan_create.argtypes = [ctypes.POINTER(momfbd_desc), _vp, _vp, _vp,
+                                         ctypes.POINTER(_vp)]
+        L.momfbd_plan_destroy.argtypes = [_vp]
+        L.momfbd_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.momfbd_prepare_data.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, _vp]
+        L.momfbd_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.momfbd_loss_grad.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, _vp]
+        L.momfbd_object_estimate.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
+        L.momfbd_status_string.argtypes = [i]
+        L.momfbd_status_string.restype = ctypes.c_char_p
+        L.momfbd_plan_dims.argtypes = [_vp] + [ctypes.POINTER(i)] * 6
+        L.momfbd_profile_start.argtypes = [_vp, i]
+        L.momfbd_profile_stop.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_char_p),
+                                          ctypes.POINTER(d), ctypes.POINTER(i)]
+        for name in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
+                     "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
+                     "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
+                     "momfbd_profile_stop"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != MOMFBD_OK:
+        raise MomfbdError(status, where)
+
+
+def _ptr(t):
+    """Device/host pointer of a tensor or ndarray; None -> NULL."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream, *tensors):
+    if stream is not None:
+        return stream
+    import torch
+    for t in tensors:
+        if t is not None and hasattr(t, "is_cuda") and t.is_cuda:
+            return torch.cuda.current_stream(t.device).cuda_stream
+    return None
+
+
+def momfbd_status_string(status: int) -> str:
+    if _lib is None and not os.path.exists(LIB_PATH):
+        return _STATUS.get(status, "unknown status")
+    return lib().momfbd_status_string(status).decode()
+
+
+def momfbd_plan_create(N, P, C, K, J, M, channel_object, pupil, basis, diversity=None):
+    """Create a plan from host arrays; returns the opaque plan handle (int)."""
+    co = (ctypes.c_int * C)(*[int(v) for v in channel_object])
+    desc = momfbd_desc(N, P, C, K, J, M, co)
+    pupil = np.ascontiguousarray(pupil, dtype=np.float32)
+    basis = np.ascontiguousarray(basis, dtype=np.float32)
+    if pupil.size != C * N * N or basis.size != C * M * N * N:
+        raise MomfbdError(MOMFBD_EINVAL, "momfbd_plan_create: array sizes")
+    div = None if diversity is None else np.ascontiguousarray(diversity, dtype=np.float32)
+    if div is not None and div.size != C * N * N:
+        raise MomfbdError(MOMFBD_EINVAL, "momfbd_plan_create: diversity size")
+    out = _vp()
+    _check(lib().momfbd_plan_create(ctypes.byref(desc), _ptr(pupil), _ptr(basis), _ptr(div),
+                                    ctypes.byref(out)), "momfbd_plan_create")
+    return out.value
+
+
+def momfbd_plan_destroy(plan):
+    _check(lib().momfbd_plan_destroy(plan), "momfbd_plan_destroy")
+
+
+def momfbd_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().momfbd_workspace_size(plan, ctypes.byref(n)), "momfbd_workspace_size")
+    return n.value
+
+
+def momfbd_plan_dims(plan):
+    v = [ctypes.c_int() for _ in range(6)]
+    _check(lib().momfbd_plan_dims(plan, *[ctypes.byref(x) for x in v]), "momfbd_plan_dims")
+    return tuple(x.value for x in v)
+
+
+def momfbd_prepare_data(plan, frames, H, W, stride, apod, D, ws, stream=None):
+    _check(lib().momfbd_prepare_data(plan, _ptr(frames), H, W, stride, _ptr(apod), _ptr(D),
+                                     _ptr(ws), _stream(stream, frames)), "momfbd_prepare_data")
+
+
+def momfbd_forward(plan, alpha, psf, otf, ws, stream=None):
+    _check(lib().momfbd_forward(plan, _ptr(alpha), _ptr(psf), _ptr(otf), _ptr(ws),
+                                _stream(stream, alpha)), "momfbd_forward")
+
+
+def momfbd_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, loss, grad, ws, stream=None):
+    _check(lib().momfbd_loss_grad(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                                  _ptr(weights), _ptr(loss), _ptr(grad), _ptr(ws),
+                                  _stream(stream, alpha)), "momfbd_loss_grad")
+
+
+def momfbd_object_estimate(plan, alpha, D, gamma, gamma_scalar, weights, obj, ws, stream=None):
+    _check(lib().momfbd_object_estimate(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
+                                        float(gamma_scalar), _ptr(weights), _ptr(obj), _ptr(ws),
+                                        _stream(stream, alpha)), "momfbd_object_estimate")
+
+
+def momfbd_profile_start(plan, max_launches: int):
+    _check(lib().momfbd_profile_start(plan, int(max_launches)), "momfbd_profile_start")
+
+
+def momfbd_profile_stop(plan) -> dict:
+    """{kernel name: (total ms, launches)} since momfbd_profile_start."""
+    cap = 16
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int * cap)()
+    n = lib().momfbd_profile_stop(plan, cap, names, ms, cnt)
+    if n < 0:
+        raise MomfbdError(n, "momfbd_profile_stop")
+    return {names[k].decode(): (ms[k], cnt[k]) for k in range(n)}

@@ -1,0 +1,191 @@
+// Host emulation of the 64x64 wave operators -- test infrastructure.
+//
+// Runs the per-lane phases of ops64.h lane by lane on the CPU with an
+// ordinary array standing in for LDS, so that the index logic of the GPU
+// transforms can be checked without a GPU.  The GPU library never loads
+// this file's library.
+#include <cmath>
+#include <cstring>
+
+#include "ops64.h"
+
+using namespace mfbd;
+using namespace mfbd::n64;
+
+namespace {
+
+struct Wave {
+  float2 T[LDS_MAIN];
+  float2 Taux[LDS_AUX];
+};
+
+// half spectrum [64][33] <-> spectral layout
+void load_sl(const float* half, float2 (&X)[64][32], float2 (&x32)[64]) {
+  const float2* h = reinterpret_cast<const float2*>(half);
+  for (int l = 0; l < 64; ++l) {
+    for (int m = 0; m < 32; ++m) X[l][m] = h[sl_index(l, m)];
+    x32[l] = h[sl_index32(l)];
+  }
+}
+
+void store_sl(float* half, const float2 (&X)[64][32], const float2 (&x32)[64]) {
+  float2* h = reinterpret_cast<float2*>(half);
+  for (int l = 0; l < 64; ++l) {
+    for (int m = 0; m < 32; ++m) h[sl_index(l, m)] = X[l][m];
+    h[sl_index32(l)] = x32[l];
+  }
+}
+
+void r2c(Wave& w, const float* img, float2 (&X)[64][32], float2 (&x32)[64]) {
+  for (int l = 0; l < 64; ++l) {
+    float se[32], so[32];
+    for (int n = 0; n < 32; ++n) {
+      se[n] = img[l * 64 + 2 * n];
+      so[n] = img[l * 64 + 2 * n + 1];
+    }
+    op2_rows(se, so, w.T, l);
+  }
+  for (int l = 0; l < 64; ++l) op2_cols(w.T, w.Taux, l, X[l]);
+  for (int l = 0; l < 64; ++l) x32[l] = op2_spread(w.Taux, l);
+}
+
+void c2r(Wave& w, float2 (&X)[64][32], const float2 (&x32)[64], float* img) {
+  for (int l = 0; l < 64; ++l) op3_gather(x32[l], w.Taux, l);
+  for (int l = 0; l < 64; ++l) op3_cols(X[l], w.Taux, w.T, l);
+  for (int l = 0; l < 64; ++l) {
+    float ge[32], go[32];
+    op3_rows(w.T, l, ge, go);
+    for (int n = 0; n < 32; ++n) {
+      img[l * 64 + 2 * n] = ge[n];
+      img[l * 64 + 2 * n + 1] = go[n];
+    }
+  }
+}
+
+// pupil band (A, phase in turns) -> complex amplitude p, row layout
+void pupil_to_p(Wave& w, const float* A, const float* ph, float2 (&pe)[64][32],
+                float2 (&po)[64][32], float2 (&Pk)[64][16]) {
+  for (int l = 0; l < 64; ++l) {
+    const int q = l >> 1, b = l & 1;
+    float2 P[32], y[32];
+    for (int n = 0; n < 32; ++n) {
+      const double ang = 2.0 * M_PI * (double)ph[n * 32 + q];
+      const float a = A[n * 32 + q];
+      P[n] = make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang));
+    }
+    static_for<0, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      y[n] = b ? twmul<+1, 64, 16 + n>(P[n]) : P[n];
+    });
+    for (int i = 0; i < 16; ++i) Pk[l][i] = P[2 * i + b];
+    op1_cols(y, w.T, l);
+  }
+  for (int l = 0; l < 64; ++l) op1_rows(w.T, l, pe[l], po[l]);
+}
+
+}  // namespace
+
+extern "C" {
+
+// fft32 in place on 32 interleaved complex values; dir = -1 or +1
+void emu_fft32(float* x, int dir) {
+  float2 v[32];
+  std::memcpy(v, x, sizeof(v));
+  if (dir < 0) fft32<-1>(v); else fft32<+1>(v);
+  std::memcpy(x, v, sizeof(v));
+}
+
+void emu_fft64(float* x, int dir) {
+  float2 v[64];
+  std::memcpy(v, x, sizeof(v));
+  if (dir < 0) fft64<-1>(v); else fft64<+1>(v);
+  std::memcpy(x, v, sizeof(v));
+}
+
+// real 64x64 image -> half spectrum [64][33] complex
+void emu_r2c(const float* img, float* half) {
+  static Wave w;
+  static float2 X[64][32], x32[64];
+  r2c(w, img, X, x32);
+  store_sl(half, X, x32);
+}
+
+// Hermitian half spectrum [64][33] -> real image (unnormalised inverse)
+void emu_c2r(const float* half, float* img) {
+  static Wave w;
+  static float2 X[64][32], x32[64];
+  load_sl(half, X, x32);
+  c2r(w, X, x32, img);
+}
+
+// band pupil -> complex amplitude p [64][64] (interleaved complex)
+void emu_pupil_ifft(const float* A, const float* ph, float* p) {
+  static Wave w;
+  static float2 pe[64][32], po[64][32], Pk[64][16];
+  pupil_to_p(w, A, ph, pe, po, Pk);
+  float2* o = reinterpret_cast<float2*>(p);
+  for (int l = 0; l < 64; ++l)
+    for (int n = 0; n < 32; ++n) {
+      o[l * 64 + 2 * n] = pe[l][n];
+      o[l * 64 + 2 * n + 1] = po[l][n];
+    }
+}
+
+// complex image [64][64] -> forward DFT sampled on the band [32][32]
+void emu_fft_to_band(const float* h, float* band) {
+  static Wave w;
+  const float2* H = reinterpret_cast<const float2*>(h);
+  for (int l = 0; l < 64; ++l) {
+    float2 he[32], ho[32];
+    for (int n = 0; n < 32; ++n) {
+      he[n] = H[l * 64 + 2 * n];
+      ho[n] = H[l * 64 + 2 * n + 1];
+    }
+    op4_rows(he, ho, w.T, l);
+  }
+  float2* o = reinterpret_cast<float2*>(band);
+  for (int l = 0; l < 64; ++l) {
+    float2 GP[16];
+    op4_cols(w.T, l, GP);
+    const int q = l >> 1, b = l & 1;
+    for (int i = 0; i < 16; ++i) o[(2 * i + b) * 32 + q] = GP[i];
+  }
+}
+
+// Whole unit: forward PSF/OTF, then the adjoint for a given G half spectrum.
+void emu_unit(const float* A, const float* ph, float kappa, const float* G_half, float* psf,
+              float* S_half, float* gphi) {
+  static Wave w;
+  static float2 pe[64][32], po[64][32], Pk[64][16], X[64][32], x32[64];
+  static float img[64 * 64], g[64 * 64];
+  pupil_to_p(w, A, ph, pe, po, Pk);
+  for (int l = 0; l < 64; ++l)
+    for (int n = 0; n < 32; ++n) {
+      img[l * 64 + 2 * n] = kappa * cabs2(pe[l][n]);
+      img[l * 64 + 2 * n + 1] = kappa * cabs2(po[l][n]);
+    }
+  std::memcpy(psf, img, sizeof(img));
+  r2c(w, img, X, x32);
+  store_sl(S_half, X, x32);
+  load_sl(G_half, X, x32);
+  c2r(w, X, x32, g);
+  for (int l = 0; l < 64; ++l) {
+    float2 he[32], ho[32];
+    for (int n = 0; n < 32; ++n) {
+      he[n] = cscale(pe[l][n], 2.0f * kappa * g[l * 64 + 2 * n]);
+      ho[n] = cscale(po[l][n], 2.0f * kappa * g[l * 64 + 2 * n + 1]);
+    }
+    op4_rows(he, ho, w.T, l);
+  }
+  for (int l = 0; l < 64; ++l) {
+    float2 GP[16];
+    op4_cols(w.T, l, GP);
+    const int q = l >> 1, b = l & 1;
+    for (int i = 0; i < 16; ++i) {
+      const float2 pk = Pk[l][i], gp = GP[i];
+      gphi[(2 * i + b) * 32 + q] = pk.x * gp.y - pk.y * gp.x;
+    }
+  }
+}
+
+}  // extern "C"

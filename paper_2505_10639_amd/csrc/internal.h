@@ -1,0 +1,63 @@
+// Internal declarations shared by the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace mfbd {
+
+constexpr int kMaxC = 32;
+constexpr int kMaxK = 32;
+constexpr int kMaxM = 256;
+constexpr int kBand = 32;            // band width for N = 64
+constexpr int kBandPix = kBand * kBand;
+
+struct Dims {
+  int N, P, C, K, J, M;
+};
+
+// Channel tables passed by value to kernels.
+struct ChanTab {
+  int chan_obj[kMaxC];     // object of each channel
+  float kappa[kMaxC];      // 1 / (N^2 sum A^2) per channel
+  int obj_first[kMaxK + 1];// channels of object k: obj_chans[obj_first[k] .. obj_first[k+1])
+  int obj_chans[kMaxC];
+};
+
+// Loss/gradient inputs common to several kernels.
+struct LossArgs {
+  const float2* D;         // [P][C][J][N][N/2+1]
+  const float* gamma;      // [K][N][N/2+1] or null
+  float gamma_scalar;
+  const float* weights;    // [C][J] or null (= 1)
+};
+
+// Workspace carve-up.
+struct Workspace {
+  float* phi;              // [P][C][J][32][32]  phase in turns on the pupil band
+  float2* S;               // [P][C][J][N][N/2+1] OTF half spectra
+  float2* O;               // [P][K][N][N/2+1]    object spectra
+  float* gphi;             // [P][C][J][32][32]  dL/dphi (rad^-1) on the band
+};
+
+size_t workspace_bytes(const Dims& d);
+Workspace carve_workspace(const Dims& d, void* base);
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_phase(const Dims& d, const float* alpha, const float* Zt, const float* thetat,
+                        float* phi, hipStream_t s);
+hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const float* Ab, const float* phi,
+                            float* psf, float2* S, hipStream_t s);
+hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float2* S,
+                           float2* O, double* loss, hipStream_t s);
+hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float* Ab,
+                            const float* phi, const float2* S, const float2* O, float* gphi,
+                            hipStream_t s);
+hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
+                       hipStream_t s);
+hipError_t launch_prepare64(const Dims& d, const float* frames, int H, int W, int stride,
+                            const float* apod, float2* D, hipStream_t s);
+hipError_t launch_objimg64(const Dims& d, const float2* O, float* obj, hipStream_t s);
+
+}  // namespace mfbd

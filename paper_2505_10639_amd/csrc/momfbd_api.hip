@@ -1,0 +1,423 @@
+// C-ABI layer of libmomfbd: argument checks, plan tables, workspace, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "momfbd.h"
+
+using namespace mfbd;
+
+enum KernelKind { KK_PHASE, KK_FORWARD, KK_OBJECT, KK_ADJOINT, KK_GRAD, KK_PREPARE, KK_OBJIMG,
+                  KK_COUNT };
+static const char* kKernelNames[KK_COUNT] = {"phase", "forward", "object", "adjoint", "grad",
+                                             "prepare", "objimg"};
+
+// Optional kernel timing: an event pair around every launch, on its stream.
+struct Profiler {
+  bool on = false;
+  int used = 0;
+  std::vector<hipEvent_t> ev0, ev1;
+  std::vector<int> kind;
+};
+
+struct momfbd_plan_s {
+  Dims d;
+  Profiler prof;
+  ChanTab ct;
+  int device = -1;
+  int shift_y[kMaxC];      // translation applied to each channel's pupil
+  int shift_x[kMaxC];
+  float* Ab = nullptr;     // [C][32][32]   aperture on the band
+  float* Zt = nullptr;     // [C][M][32][32] modes in turns
+  float* thetat = nullptr; // [C][32][32]   diversity in turns
+};
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_dims(const momfbd_desc* d) {
+  return d && d->P >= 1 && d->C >= 1 && d->K >= 1 && d->J >= 1 && d->M >= 1 && d->N >= 1 &&
+         d->channel_object != nullptr;
+}
+
+// Bounding interval [lo, lo+len) of the rows (or columns) in use, allowing
+// wrap-around: the shortest cyclic interval covering every used index.
+bool cyclic_extent(const std::vector<char>& used, int N, int* start, int* len) {
+  int count = 0;
+  for (int i = 0; i < N; ++i) count += used[i] ? 1 : 0;
+  if (count == 0) return false;
+  // largest run of unused indices (cyclic) defines the complement
+  int best_gap = 0, best_end = 0;
+  for (int i = 0; i < N; ++i) {
+    if (used[i]) continue;
+    int g = 0;
+    while (g < N && !used[(i + g) % N]) ++g;
+    if (g > best_gap) {
+      best_gap = g;
+      best_end = (i + g) % N;
+    }
+  }
+  *start = best_end;
+  *len = N - best_gap;
+  return true;
+}
+
+// Records a start event before and an end event after one launch when the
+// plan's profiler is on (no effect otherwise).
+struct ProfScope {
+  Profiler* pr;
+  hipStream_t s;
+  int slot = -1;
+  ProfScope(momfbd_plan plan, int kind, hipStream_t st) : pr(&plan->prof), s(st) {
+    if (pr->on && pr->used < (int)pr->ev0.size()) {
+      slot = pr->used++;
+      pr->kind[slot] = kind;
+      (void)hipEventRecord(pr->ev0[slot], s);
+    }
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(pr->ev1[slot], s);
+  }
+};
+
+int check_call(momfbd_plan plan, const void* ws) {
+  if (!plan) return MOMFBD_EINVAL;
+  if (!ws) return MOMFBD_EWORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return MOMFBD_EWORKSPACE;
+  return MOMFBD_OK;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? MOMFBD_OK : MOMFBD_EDEVICE; }
+
+// Any error left by earlier asynchronous work is reported before new work.
+int pending_error() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MOMFBD_OK : MOMFBD_EDEVICE;
+}
+
+}  // namespace
+
+namespace mfbd {
+
+size_t workspace_bytes(const Dims& d) {
+  const size_t units = (size_t)d.P * d.C * d.J;
+  const size_t hs = (size_t)d.N * (d.N / 2 + 1);
+  size_t b = 0;
+  b += align256(units * kBandPix * sizeof(float));          // phi
+  b += align256(units * hs * sizeof(float2));                // S
+  b += align256((size_t)d.P * d.K * hs * sizeof(float2));    // O
+  b += align256(units * kBandPix * sizeof(float));          // gphi
+  return b;
+}
+
+Workspace carve_workspace(const Dims& d, void* base) {
+  const size_t units = (size_t)d.P * d.C * d.J;
+  const size_t hs = (size_t)d.N * (d.N / 2 + 1);
+  char* p = static_cast<char*>(base);
+  Workspace w;
+  w.phi = reinterpret_cast<float*>(p);
+  p += align256(units * kBandPix * sizeof(float));
+  w.S = reinterpret_cast<float2*>(p);
+  p += align256(units * hs * sizeof(float2));
+  w.O = reinterpret_cast<float2*>(p);
+  p += align256((size_t)d.P * d.K * hs * sizeof(float2));
+  w.gphi = reinterpret_cast<float*>(p);
+  return w;
+}
+
+}  // namespace mfbd
+
+static void profile_free(Profiler& pr);
+
+extern "C" {
+
+const char* momfbd_status_string(int status) {
+  switch (status) {
+    case MOMFBD_OK: return "ok";
+    case MOMFBD_EINVAL: return "invalid argument";
+    case MOMFBD_EUNSUPPORTED: return "unsupported configuration";
+    case MOMFBD_EWORKSPACE: return "workspace missing or misaligned";
+    case MOMFBD_EDEVICE: return "HIP device error";
+    default: return "unknown status";
+  }
+}
+
+int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float* basis,
+                       const float* diversity, momfbd_plan* out) {
+  if (!out) return MOMFBD_EINVAL;
+  if (!valid_dims(desc) || !pupil || !basis) return MOMFBD_EINVAL;
+  const int N = desc->N, C = desc->C, K = desc->K, M = desc->M, J = desc->J;
+  if (C > kMaxC || K > kMaxK) return MOMFBD_EUNSUPPORTED;
+  for (int c = 0; c < C; ++c)
+    if (desc->channel_object[c] < 0 || desc->channel_object[c] >= K) return MOMFBD_EINVAL;
+  for (int k = 0; k < K; ++k) {
+    bool any = false;
+    for (int c = 0; c < C; ++c) any |= desc->channel_object[c] == k;
+    if (!any) return MOMFBD_EINVAL;
+  }
+  if (N != 64) return MOMFBD_EUNSUPPORTED;
+  if (M > kMaxM || (long)J * M > 8192) return MOMFBD_EUNSUPPORTED;
+
+  momfbd_plan_s* pl = new (std::nothrow) momfbd_plan_s();
+  if (!pl) return MOMFBD_EDEVICE;
+  pl->d = Dims{N, desc->P, C, K, J, M};
+  std::memset(&pl->ct, 0, sizeof(pl->ct));
+  int nfill = 0;
+  for (int k = 0; k < K; ++k) {
+    pl->ct.obj_first[k] = nfill;
+    for (int c = 0; c < C; ++c)
+      if (desc->channel_object[c] == k) pl->ct.obj_chans[nfill++] = c;
+  }
+  pl->ct.obj_first[K] = nfill;
+
+  const int B = kBand, B0 = N / 4;
+  std::vector<float> hA((size_t)C * kBandPix, 0.f), hT((size_t)C * kBandPix, 0.f);
+  std::vector<float> hZ((size_t)C * M * kBandPix, 0.f);
+  for (int c = 0; c < C; ++c) {
+    pl->ct.chan_obj[c] = desc->channel_object[c];
+    const float* A = pupil + (size_t)c * N * N;
+    std::vector<char> rows(N, 0), cols(N, 0);
+    double sumA2 = 0.0;
+    for (int y = 0; y < N; ++y)
+      for (int x = 0; x < N; ++x) {
+        const float a = A[y * N + x];
+        if (!(a >= 0.f) || !std::isfinite(a)) { delete pl; return MOMFBD_EINVAL; }
+        if (a != 0.f) {
+          rows[y] = cols[x] = 1;
+          sumA2 += (double)a * a;
+        }
+      }
+    int y0, ly, x0, lx;
+    if (!cyclic_extent(rows, N, &y0, &ly) || !cyclic_extent(cols, N, &x0, &lx) || sumA2 <= 0.0) {
+      delete pl;
+      return MOMFBD_EINVAL;
+    }
+    if (ly > B || lx > B) { delete pl; return MOMFBD_EUNSUPPORTED; }
+    // place the support at the start of the band, centred within it
+    const int oy = (B - ly) / 2, ox = (B - lx) / 2;
+    pl->shift_y[c] = B0 + oy - y0;
+    pl->shift_x[c] = B0 + ox - x0;
+    pl->ct.kappa[c] = (float)(1.0 / ((double)N * N * sumA2));
+    for (int n = 0; n < B; ++n)
+      for (int qx = 0; qx < B; ++qx) {
+        const int y = ((y0 - oy + n) % N + N) % N, x = ((x0 - ox + qx) % N + N) % N;
+        const size_t src = (size_t)y * N + x, dst = (size_t)n * B + qx;
+        hA[(size_t)c * kBandPix + dst] = A[src];
+        const double th = diversity ? diversity[(size_t)c * N * N + src] : 0.0;
+        hT[(size_t)c * kBandPix + dst] = (float)(th / kTwoPi);
+        for (int m = 0; m < M; ++m)
+          hZ[((size_t)c * M + m) * kBandPix + dst] =
+              (float)((double)basis[((size_t)c * M + m) * N * N + src] / kTwoPi);
+      }
+  }
+  if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
+  bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->Zt, hZ.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
+            hipMemcpy(pl->Ab, hA.data(), hA.size() * sizeof(float), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(pl->Zt, hZ.data(), hZ.size() * sizeof(float), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(pl->thetat, hT.data(), hT.size() * sizeof(float), hipMemcpyHostToDevice) ==
+                hipSuccess;
+  if (!ok) {
+    momfbd_plan_destroy(pl);
+    return MOMFBD_EDEVICE;
+  }
+  *out = pl;
+  return MOMFBD_OK;
+}
+
+int momfbd_plan_destroy(momfbd_plan plan) {
+  if (!plan) return MOMFBD_OK;
+  profile_free(plan->prof);
+  if (plan->Ab) (void)hipFree(plan->Ab);
+  if (plan->Zt) (void)hipFree(plan->Zt);
+  if (plan->thetat) (void)hipFree(plan->thetat);
+  delete plan;
+  return MOMFBD_OK;
+}
+
+int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M) {
+  if (!plan) return MOMFBD_EINVAL;
+  if (N) *N = plan->d.N;
+  if (P) *P = plan->d.P;
+  if (C) *C = plan->d.C;
+  if (K) *K = plan->d.K;
+  if (J) *J = plan->d.J;
+  if (M) *M = plan->d.M;
+  return MOMFBD_OK;
+}
+
+int momfbd_workspace_size(momfbd_plan plan, size_t* bytes) {
+  if (!plan || !bytes) return MOMFBD_EINVAL;
+  *bytes = workspace_bytes(plan->d);
+  return MOMFBD_OK;
+}
+
+int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int stride,
+                        const float* apod, void* D, void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!frames || !apod || !D || stride < 1) return MOMFBD_EINVAL;
+  const int N = plan->d.N;
+  if (H < N || W < N) return MOMFBD_EINVAL;
+  const long ny = (H - N) / stride + 1, nx = (W - N) / stride + 1;
+  if (ny * nx != plan->d.P) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  ProfScope ps(plan, KK_PREPARE, (hipStream_t)stream);
+  return to_status(launch_prepare64(plan->d, frames, H, W, stride, apod,
+                                    static_cast<float2*>(D), (hipStream_t)stream));
+}
+
+int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, void* ws,
+                   void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || (!psf && !otf)) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  const Workspace w = carve_workspace(plan->d, ws);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps(plan, KK_PHASE, s);
+    e = launch_phase(plan->d, alpha, plan->Zt, plan->thetat, w.phi, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, KK_FORWARD, s);
+    e = launch_forward64(plan->d, plan->ct, plan->Ab, w.phi, psf,
+                         otf ? static_cast<float2*>(otf) : w.S, s);
+  }
+  return to_status(e);
+}
+
+static int run_object(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                      float gamma_scalar, const float* weights, double* loss, void* ws,
+                      hipStream_t s, Workspace* wout) {
+  const Workspace w = carve_workspace(plan->d, ws);
+  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
+  hipError_t e;
+  {
+    ProfScope ps(plan, KK_PHASE, s);
+    e = launch_phase(plan->d, alpha, plan->Zt, plan->thetat, w.phi, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, KK_FORWARD, s);
+    e = launch_forward64(plan->d, plan->ct, plan->Ab, w.phi, nullptr, w.S, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, KK_OBJECT, s);
+    e = launch_object64(plan->d, plan->ct, la, w.S, w.O, loss, s);
+  }
+  *wout = w;
+  return to_status(e);
+}
+
+int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                     float gamma_scalar, const float* weights, double* loss, float* grad,
+                     void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || !D || !loss) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Workspace w;
+  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, loss, ws, s, &w);
+  if (st || !grad) return st;
+  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
+  hipError_t e;
+  {
+    ProfScope ps(plan, KK_ADJOINT, s);
+    e = launch_adjoint64(plan->d, plan->ct, la, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, KK_GRAD, s);
+    e = launch_grad(plan->d, plan->Zt, w.gphi, grad, s);
+  }
+  return to_status(e);
+}
+
+int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
+                           const float* gamma, float gamma_scalar, const float* weights,
+                           float* obj, void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || !D || !obj) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Workspace w;
+  // the per-patch loss is produced on the way; it lands in the gphi scratch
+  double* scratch_loss = reinterpret_cast<double*>(carve_workspace(plan->d, ws).gphi);
+  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, scratch_loss, ws, s, &w);
+  if (st) return st;
+  ProfScope ps(plan, KK_OBJIMG, s);
+  return to_status(launch_objimg64(plan->d, w.O, obj, s));
+}
+
+}  // extern "C"
+
+static void profile_free(Profiler& pr) {
+  for (auto e : pr.ev0) (void)hipEventDestroy(e);
+  for (auto e : pr.ev1) (void)hipEventDestroy(e);
+  pr.ev0.clear();
+  pr.ev1.clear();
+  pr.kind.clear();
+  pr.on = false;
+  pr.used = 0;
+}
+
+extern "C" {
+
+int momfbd_profile_start(momfbd_plan plan, int max_launches) {
+  if (!plan || max_launches < 1) return MOMFBD_EINVAL;
+  profile_free(plan->prof);
+  Profiler& pr = plan->prof;
+  pr.ev0.resize(max_launches);
+  pr.ev1.resize(max_launches);
+  pr.kind.assign(max_launches, -1);
+  for (int i = 0; i < max_launches; ++i)
+    if (hipEventCreate(&pr.ev0[i]) != hipSuccess || hipEventCreate(&pr.ev1[i]) != hipSuccess) {
+      pr.ev0.resize(i);
+      pr.ev1.resize(i);
+      profile_free(pr);
+      return MOMFBD_EDEVICE;
+    }
+  pr.on = true;
+  return MOMFBD_OK;
+}
+
+int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* total_ms,
+                        int* launches) {
+  if (!plan || cap < 0 || (cap > 0 && (!names || !total_ms || !launches))) return MOMFBD_EINVAL;
+  Profiler& pr = plan->prof;
+  double tot[KK_COUNT] = {0};
+  int cnt[KK_COUNT] = {0};
+  int st = MOMFBD_OK;
+  for (int i = 0; i < pr.used; ++i) {
+    if (hipEventSynchronize(pr.ev1[i]) != hipSuccess) { st = MOMFBD_EDEVICE; break; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.ev0[i], pr.ev1[i]) != hipSuccess) { st = MOMFBD_EDEVICE; break; }
+    tot[pr.kind[i]] += ms;
+    cnt[pr.kind[i]] += 1;
+  }
+  int n = 0;
+  for (int k = 0; k < KK_COUNT && n < cap; ++k) {
+    if (!cnt[k]) continue;
+    names[n] = kKernelNames[k];
+    total_ms[n] = tot[k];
+    launches[n] = cnt[k];
+    ++n;
+  }
+  profile_free(pr);
+  return st ? st : n;
+}
+
+}  // extern "C"

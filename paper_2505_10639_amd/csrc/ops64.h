@@ -1,0 +1,237 @@
+// Wave-level 2-D transforms of one 64x64 MOMFBD unit (one wavefront = 64 lanes).
+//
+// Data layouts inside a wave (lane l, q = l >> 1, b = l & 1):
+//   band-column layout  lane (q,b) holds the pupil band column vx = 16 + q,
+//                       rows vy = 16 + n, n in [0,32);
+//   row layout          lane l holds image row r = l, columns in two 32-element
+//                       halves: even columns (2n) and odd columns (2n+1);
+//   spectral layout SL  lane (q,b) holds X(ky = 2m + b, kx = q), m in [0,32)
+//                       (kx = 0 for q = 0), plus one extra value X(ky = l, kx = 32).
+//
+// The pupil support is confined to the central band [16,48) of both axes
+// (diameter < N/2, which also keeps the OTF free of aliasing), so the first
+// inverse transform of the pupil and the last forward transform back to it
+// only touch a 32-wide band.  Every 64-point transform is then assembled from
+// in-lane 32-point FFTs:
+//   * a 64-point sum whose input lives in a 32-wide band, or whose output is
+//     wanted at one parity of frequency, folds into a 32-point DFT;
+//   * lane pairs (q,0), (q,1) split the two output parities of a column.
+// One transpose through LDS per 2-D transform.
+//
+// Each operator is split into phases separated by a wave barrier; phases are
+// per-lane functions so that a host harness can run them lane by lane.
+#pragma once
+
+#include "fft_lane.h"
+
+namespace mfbd {
+namespace n64 {
+
+constexpr int N = 64;
+constexpr int HC = 33;       // N/2 + 1 columns of a half spectrum
+constexpr int BAND0 = 16;    // first row/column of the pupil band
+constexpr int BW = 32;       // band width
+
+// LDS strides in float2 units, chosen so that both the writing and the
+// reading pattern of each transpose hit distinct banks.
+constexpr int T1 = 66;       // [q][ky]     band-column IFFT -> rows
+constexpr int T2 = 33;       // [r][q]      rows -> columns
+constexpr int T3 = 65;       // [r'][2q+b]  columns -> rows (c2r)
+constexpr int LDS_MAIN = 64 * T2 + 32;   // float2 elements of the main buffer (>= 32*T1, 32*T3)
+constexpr int LDS_AUX = 64;              // float2 elements of the side buffer
+
+// Index of spectral-layout element m of lane l in a [N][N/2+1] array.
+MFBD_HDI int sl_index(int lane, int m) { return (2 * m + (lane & 1)) * HC + (lane >> 1); }
+MFBD_HDI int sl_index32(int lane) { return lane * HC + 32; }
+
+// ---------------------------------------------------------------------------
+// Op 1: inverse 2-D DFT of the band-limited pupil field -> complex PSF amplitude.
+//   p(r) = sum_v P(v) exp(+2 pi i v.r / 64), P zero outside the band.
+// Input of lane (q,b): y[n] = P(16+n, 16+q) * W64^{+b(16+n)}.
+// ---------------------------------------------------------------------------
+MFBD_HDI void op1_cols(float2 (&y)[32], float2* T, int lane) {
+  const int q = lane >> 1, b = lane & 1;
+  fft32<+1>(y);
+  // column value at ky = 2m + b is (-1)^m y[m]
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    float2 v = (m & 1) ? cneg(y[m]) : y[m];
+    T[q * T1 + 2 * m + b] = v;
+  });
+}
+
+// Output: pe[m] = p(r, 2m), po[m] = p(r, 2m+1) for row r = lane.
+MFBD_HDI void op1_rows(const float2* T, int lane, float2 (&pe)[32], float2 (&po)[32]) {
+  static_for<0, 32>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    float2 c = T[q * T1 + lane];
+    pe[q] = c;
+    po[q] = twmul<+1, 64, 16 + q>(c);
+  });
+  fft32<+1>(pe);
+  fft32<+1>(po);
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    if constexpr (m & 1) {
+      pe[m] = cneg(pe[m]);
+      po[m] = cneg(po[m]);
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Op 2: forward 2-D DFT of a real image held in row layout -> half spectrum
+// in spectral layout.  Input: se[n] = s(r, 2n), so[n] = s(r, 2n+1).
+// ---------------------------------------------------------------------------
+MFBD_HDI void op2_rows(const float (&se)[32], const float (&so)[32], float2* T, int lane) {
+  float2 z[32];
+  static_for<0, 32>([&](auto I) { z[decltype(I)::value] = make_float2(se[decltype(I)::value],
+                                                                     so[decltype(I)::value]); });
+  fft32<-1>(z);
+  // packed real columns kx = 0 and kx = 32
+  T[lane * T2 + 0] = make_float2(z[0].x + z[0].y, z[0].x - z[0].y);
+  static_for<1, 32>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    float2 a = z[k], c = cconj(z[32 - k]);
+    float2 se_k = cscale(cadd(a, c), 0.5f);
+    float2 d = csub(a, c);
+    float2 so_k = make_float2(0.5f * d.y, -0.5f * d.x);   // d / (2i)
+    T[lane * T2 + k] = cadd(se_k, twmul<-1, 64, k>(so_k));
+  });
+}
+
+// Column pass.  Output of lane (q,b): X[m] = S(2m+b, q) (q = 0: column 0),
+// and x32 = S(lane, 32) after op2_spread.
+MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[32]) {
+  const int q = lane >> 1, b = lane & 1;
+  const float sb = b ? -1.0f : 1.0f;
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    float2 lo = T[n * T2 + q], hi = T[(n + 32) * T2 + q];
+    X[n] = make_float2(lo.x + sb * hi.x, lo.y + sb * hi.y);
+  });
+  if (b) {
+    static_for<1, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      X[n] = twmul<-1, 64, n>(X[n]);
+    });
+  }
+  fft32<-1>(X);
+  if (q == 0) {
+    // unpack the two real columns: F = S0 + i S32 with S0, S32 Hermitian in ky;
+    // -ky has the same parity: element m pairs with m' = 32-m (b=0) or 31-m (b=1)
+    float2 F[32];
+    static_for<0, 32>([&](auto I) { F[decltype(I)::value] = X[decltype(I)::value]; });
+    static_for<0, 32>([&](auto I) {
+      constexpr int m = decltype(I)::value;
+      constexpr int m0 = (32 - m) & 31, m1 = 31 - m;
+      float2 c = cconj(b ? F[m1] : F[m0]);
+      float2 s0 = cscale(cadd(F[m], c), 0.5f);
+      float2 d = csub(F[m], c);
+      X[m] = s0;
+      Taux[2 * m + b] = make_float2(0.5f * d.y, -0.5f * d.x);   // S(2m+b, 32)
+    });
+  }
+}
+
+MFBD_HDI float2 op2_spread(const float2* Taux, int lane) { return Taux[lane]; }
+
+// ---------------------------------------------------------------------------
+// Op 3: inverse 2-D DFT of a Hermitian half spectrum in spectral layout ->
+// real image in row layout: g(r) = sum_{u in N x N} G(u) exp(+2 pi i u.r/64).
+// ---------------------------------------------------------------------------
+MFBD_HDI void op3_gather(float2 x32, float2* Taux, int lane) { Taux[lane] = x32; }
+
+MFBD_HDI void op3_cols(float2 (&X)[32], const float2* Taux, float2* T, int lane) {
+  const int q = lane >> 1, b = lane & 1;
+  if (q == 0) {
+    // pack column 0 with column 32: both inverse transforms are real
+    static_for<0, 32>([&](auto I) {
+      constexpr int m = decltype(I)::value;
+      float2 g32 = Taux[2 * m + b];
+      X[m] = make_float2(X[m].x - g32.y, X[m].y + g32.x);
+    });
+  }
+  fft32<+1>(X);   // lane b: E (b=0) or O (b=1) of the even/odd split along ky
+  if (b) {
+    static_for<1, 32>([&](auto I) {
+      constexpr int r = decltype(I)::value;
+      X[r] = twmul<+1, 64, r>(X[r]);
+    });
+  }
+  static_for<0, 32>([&](auto I) {
+    constexpr int r = decltype(I)::value;
+    T[r * T3 + lane] = X[r];     // lane = 2q + b
+  });
+}
+
+// Output: ge[n] = g(r, 2n), go[n] = g(r, 2n+1) for r = lane.
+MFBD_HDI void op3_rows(const float2* T, int lane, float (&ge)[32], float (&go)[32]) {
+  const int rp = lane & 31;
+  const float sg = (lane < 32) ? 1.0f : -1.0f;
+  float2 Xr[32];
+  static_for<0, 32>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    float2 e = T[rp * T3 + 2 * q], wo = T[rp * T3 + 2 * q + 1];
+    Xr[q] = make_float2(e.x + sg * wo.x, e.y + sg * wo.y);
+  });
+  // Xr[0] = (X(r,0), X(r,32)), both real; Xr[k] = X(r,k) for k in [1,32)
+  float2 Z[32];
+  Z[0] = make_float2(Xr[0].x + Xr[0].y, Xr[0].x - Xr[0].y);
+  static_for<1, 32>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    float2 a = Xr[k], c = cconj(Xr[32 - k]);
+    float2 s = cadd(a, c);
+    float2 t = twmul<+1, 64, k>(csub(a, c));
+    Z[k] = make_float2(s.x - t.y, s.y + t.x);    // s + i t
+  });
+  fft32<+1>(Z);
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    ge[n] = Z[n].x;
+    go[n] = Z[n].y;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Op 4: forward 2-D DFT of a complex image in row layout, evaluated only on
+// the pupil band: G(v) = sum_r H(r) exp(-2 pi i v.r/64), v in [16,48)^2.
+// Output of lane (q,b): GP[i] = G(vy = 16 + 2i + b, vx = 16 + q), i in [0,16).
+// ---------------------------------------------------------------------------
+MFBD_HDI void op4_rows(float2 (&he)[32], float2 (&ho)[32], float2* T, int lane) {
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    if constexpr (n & 1) {
+      he[n] = cneg(he[n]);
+      ho[n] = cneg(ho[n]);
+    }
+  });
+  fft32<-1>(he);
+  fft32<-1>(ho);
+  static_for<0, 32>([&](auto V) {
+    constexpr int v = decltype(V)::value;
+    T[lane * T2 + v] = cadd(he[v], twmul<-1, 64, 16 + v>(ho[v]));
+  });
+}
+
+MFBD_HDI void op4_cols(const float2* T, int lane, float2 (&GP)[16]) {
+  const int q = lane >> 1, b = lane & 1;
+  const float sb = b ? -1.0f : 1.0f;
+  float2 X[32];
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    float2 lo = T[n * T2 + q], hi = T[(n + 32) * T2 + q];
+    X[n] = make_float2(lo.x + sb * hi.x, lo.y + sb * hi.y);
+  });
+  if (b) {
+    static_for<1, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      X[n] = twmul<-1, 64, n>(X[n]);
+    });
+  }
+  fft32<-1>(X);
+  static_for<0, 16>([&](auto I) { GP[decltype(I)::value] = X[8 + decltype(I)::value]; });
+}
+
+}  // namespace n64
+}  // namespace mfbd

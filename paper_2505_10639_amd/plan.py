@@ -1,0 +1,126 @@
+"""Convenience wrapper: a plan with its workspace, checked tensor arguments.
+
+Every computation runs in libmomfbd's kernels; this module only checks
+shapes, dtypes and devices, allocates outputs with torch and passes
+pointers.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _need(t, shape, dtype, name, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype} != {dtype}")
+    if t.device != device:
+        raise ValueError(f"{name}: device {t.device} != {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """A libmomfbd plan on one GPU plus a workspace tensor.
+
+    pupil [C][N][N], basis [C][M][N][N] (rad), diversity [C][N][N] (rad) or
+    None are host (numpy) arrays; channel_object lists the object of each
+    channel.
+    """
+
+    def __init__(self, N, P, J, channel_object, pupil, basis, diversity=None, device="cuda:0"):
+        self.device = torch.device(device)
+        channel_object = [int(v) for v in channel_object]
+        self.N, self.P, self.J = int(N), int(P), int(J)
+        self.C = len(channel_object)
+        self.K = max(channel_object) + 1
+        self.M = int(np.asarray(basis).shape[1])
+        with torch.cuda.device(self.device):
+            self.handle = _lib.momfbd_plan_create(self.N, self.P, self.C, self.K, self.J, self.M,
+                                                  channel_object, pupil, basis, diversity)
+            nbytes = _lib.momfbd_workspace_size(self.handle)
+            self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _lib.momfbd_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    @property
+    def half(self):
+        return (self.N, self.N // 2 + 1)
+
+    def _alpha(self, alpha):
+        return _need(alpha, (self.P, self.J, self.M), torch.float32, "alpha", self.device)
+
+    def _D(self, D):
+        return _need(D, (self.P, self.C, self.J) + self.half, torch.complex64, "D", self.device)
+
+    def _gamma(self, gamma):
+        if gamma is None or isinstance(gamma, (int, float)):
+            return None, float(0.0 if gamma is None else gamma)
+        return _need(gamma, (self.K,) + self.half, torch.float32, "gamma", self.device), 0.0
+
+    def _weights(self, w):
+        return _need(w, (self.C, self.J), torch.float32, "weights", self.device)
+
+    def prepare_data(self, frames, stride, apod, D=None):
+        C, J, H, W = frames.shape
+        _need(frames, (self.C, self.J, H, W), torch.float32, "frames", self.device)
+        _need(apod, (self.N, self.N), torch.float32, "apod", self.device)
+        if D is None:
+            D = torch.empty((self.P, self.C, self.J) + self.half, dtype=torch.complex64,
+                            device=self.device)
+        self._D(D)
+        _lib.momfbd_prepare_data(self.handle, frames, H, W, stride, apod, D, self.ws)
+        return D
+
+    def forward(self, alpha, want_psf=True, want_otf=True):
+        self._alpha(alpha)
+        shp = (self.P, self.C, self.J)
+        psf = torch.empty(shp + (self.N, self.N), dtype=torch.float32,
+                          device=self.device) if want_psf else None
+        otf = torch.empty(shp + self.half, dtype=torch.complex64,
+                          device=self.device) if want_otf else None
+        _lib.momfbd_forward(self.handle, alpha, psf, otf, self.ws)
+        return psf, otf
+
+    def loss_grad(self, alpha, D, gamma=1e-3, weights=None, want_grad=True, loss=None, grad=None):
+        self._alpha(alpha)
+        self._D(D)
+        g_arr, g_sc = self._gamma(gamma)
+        self._weights(weights)
+        if loss is None:
+            loss = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        if want_grad and grad is None:
+            grad = torch.empty((self.P, self.J, self.M), dtype=torch.float32, device=self.device)
+        _lib.momfbd_loss_grad(self.handle, alpha, D, g_arr, g_sc, weights, loss,
+                              grad if want_grad else None, self.ws)
+        return loss, (grad if want_grad else None)
+
+    def object_estimate(self, alpha, D, gamma=1e-3, weights=None):
+        self._alpha(alpha)
+        self._D(D)
+        g_arr, g_sc = self._gamma(gamma)
+        self._weights(weights)
+        obj = torch.empty((self.P, self.K, self.N, self.N), dtype=torch.float32,
+                          device=self.device)
+        _lib.momfbd_object_estimate(self.handle, alpha, D, g_arr, g_sc, weights, obj, self.ws)
+        return obj

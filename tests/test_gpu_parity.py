@@ -1,0 +1,182 @@
+"""GPU parity: libmomfbd (hand-written gfx950 kernels through the C-ABI)
+against the FP64 oracle, element by element on the same seeded inputs."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import (GRAD_RTOL, LOSS_RTOL, OBJ_RMS, alpha_points, fast_simulate_D,
+                     grad_errs, simulate_D)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2505_10639_amd import _lib
+    _lib.lib()      # raises if the library is not built
+    return torch.device("cuda:0")
+
+
+def make_plan(pr, dev):
+    from paper_2505_10639_amd import Plan
+    return Plan(pr.N, pr.P, pr.J, pr.channel_object, pr.pupil, pr.basis, pr.diversity, dev)
+
+
+def to_dev(x, dev, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    return t.to(dev) if dtype is None else t.to(dev, dtype)
+
+
+def run_gpu(plan, alpha, D, gamma, weights, dev):
+    loss, grad = plan.loss_grad(to_dev(alpha, dev), D, gamma,
+                                None if weights is None else to_dev(weights, dev))
+    torch.cuda.synchronize()
+    return loss.cpu().numpy(), grad.cpu().numpy()
+
+
+def check_patchwise(pr, D_np, alphas, dev, gamma=None, weights=None, patches=None):
+    plan = make_plan(pr, dev)
+    D = to_dev(D_np, dev)
+    g = pr.gamma if gamma is None else gamma
+    for name, a in alphas.items():
+        print(f"[parity] N={pr.N} P={pr.P} C={pr.C} K={pr.K} J={pr.J} M={pr.M} alpha={name}",
+              flush=True)
+        loss, grad = run_gpu(plan, a, D, g if np.isscalar(g) else to_dev(g, dev), weights, dev)
+        idx = range(pr.P) if patches is None else patches
+        g_ref = g if np.isscalar(g) else oracle.expand_half(g, pr.N).real
+        ref = oracle.evaluate(a, D_np, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
+                              g_ref, weights, patches=list(idx))
+        lrel = np.abs(loss[list(idx)] - ref["loss"]) / np.abs(ref["loss"])
+        assert np.all(lrel < LOSS_RTOL), (name, lrel.max())
+        gerr = grad_errs(grad[list(idx)], ref["grad"])
+        assert max(gerr) < GRAD_RTOL, (name, max(gerr))
+    plan.close()
+
+
+def test_config0_loss_and_gradient(dev):
+    pr = synth.config0()
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr), dev)
+
+
+def test_ragged_multi_patch_phase_diversity(dev):
+    # 3 patches, one object seen in focus and with +1 wave defocus, 5 frames
+    pr = synth.make_problem(41, N=64, P=3, J=5, M=20, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=np.array([6.0, 12.0, 18.0]))
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 1), dev)
+
+
+def test_two_objects_weights_and_gamma_array(dev):
+    pr = synth.make_problem(42, N=64, P=2, J=3, M=30, channels=((0, 0.0), (1, 1.0), (1, 0.0)),
+                            d_over_r0=10.0)
+    w = np.array([[1.0, 0.5, 2.0], [0.7, 1.3, 1.0], [1.1, 0.9, 0.4]], np.float32)
+    ky = np.fft.fftfreq(64)[:, None]
+    kx = np.arange(33)[None, :] / 64.0
+    gam = np.stack([1e-3 + 0.02 * (np.sin(np.pi * ky) ** 2 + np.sin(np.pi * kx) ** 2),
+                    np.full((64, 33), 5e-3)]).astype(np.float32)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 2), dev, gamma=gam, weights=w)
+
+
+def test_single_frame_single_mode(dev):
+    pr = synth.make_problem(43, N=64, P=1, J=1, M=1, d_over_r0=5.0)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 3), dev)
+
+
+def test_forward_psf_and_otf(dev):
+    pr = synth.make_problem(44, N=64, P=2, J=3, M=44, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=15.0)
+    plan = make_plan(pr, dev)
+    psf, otf = plan.forward(to_dev(pr.alpha_true, dev))
+    psf, otf = psf.cpu().numpy(), otf.cpu().numpy()
+    for p in range(2):
+        for c in range(2):
+            for j in range(3):
+                phi = oracle.wavefront(pr.alpha_true[p, j], pr.basis[c], pr.diversity[c])
+                s = oracle.psf(pr.pupil[c], phi)
+                assert np.abs(psf[p, c, j] - s).max() <= 2e-6 * s.max()
+                assert abs(psf[p, c, j].astype(np.float64).sum() - 1.0) < 1e-5
+                S = oracle.otf(s)[:, :33]
+                assert np.abs(otf[p, c, j] - S).max() <= 2e-6
+    # flat wavefront: peak N_A/N^2 at pixel (0,0)
+    psf0, _ = plan.forward(torch.zeros((2, 3, 44), device=dev), want_otf=False)
+    assert abs(float(psf0[0, 0, 0, 0, 0]) - 657 / 4096) < 1e-6
+    plan.close()
+
+
+def test_object_estimate(dev):
+    pr = synth.config0()
+    D = simulate_D(pr)
+    plan = make_plan(pr, dev)
+    for name, a in alpha_points(pr, 4).items():
+        obj = plan.object_estimate(to_dev(a, dev), to_dev(D, dev), pr.gamma).cpu().numpy()
+        ref = oracle.evaluate(a, D, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
+                              pr.gamma, want_grad=False)
+        o_ref = oracle.object_image(ref["O"][0, 0])
+        rms = np.sqrt(np.mean((obj[0, 0] - o_ref) ** 2))
+        assert rms < OBJ_RMS, (name, rms)
+    plan.close()
+
+
+def test_prepare_data_ragged_grid(dev):
+    rng = np.random.default_rng(45)
+    C, J, H, W, stride = 2, 3, 150, 171, 40
+    frames = (1.0 + 0.1 * rng.standard_normal((C, J, H, W))).astype(np.float32)
+    win = synth.hann_window(64, 6).astype(np.float32)
+    ny, nx = (H - 64) // stride + 1, (W - 64) // stride + 1
+    pr = synth.make_problem(45, N=64, P=ny * nx, J=J, M=4, channels=((0, 0.0), (0, 1.0)))
+    plan = make_plan(pr, dev)
+    D = plan.prepare_data(to_dev(frames, dev), stride, to_dev(win, dev)).cpu().numpy()
+    ref = oracle.prepare_data(frames, win, 64, stride)
+    assert D.shape == ref.shape
+    assert np.abs(D - ref).max() <= 1e-6 * np.abs(ref).max()
+    plan.close()
+
+
+def test_nan_propagates_to_its_patch_only(dev):
+    pr = synth.make_problem(46, N=64, P=3, J=2, M=10)
+    D = to_dev(simulate_D(pr), dev)
+    plan = make_plan(pr, dev)
+    a = pr.alpha_true.copy()
+    l0, _ = run_gpu(plan, a, D, pr.gamma, None, dev)
+    a[1, 0, 3] = np.nan
+    l1, g1 = run_gpu(plan, a, D, pr.gamma, None, dev)
+    assert np.isnan(l1[1]) and np.all(np.isnan(g1[1]))
+    assert l1[0] == l0[0] and l1[2] == l0[2]
+    plan.close()
+
+
+def test_autograd_function(dev):
+    from paper_2505_10639_amd import momfbd_loss
+    pr = synth.config0()
+    D = to_dev(simulate_D(pr), dev)
+    plan = make_plan(pr, dev)
+    a = to_dev(pr.alpha_true, dev).requires_grad_(True)
+    L = momfbd_loss(a, plan, D, pr.gamma)
+    (3.0 * L).backward()
+    loss, grad = plan.loss_grad(a.detach(), D, pr.gamma)
+    assert float(L) == float(loss.sum())
+    assert torch.equal(a.grad, 3.0 * grad)
+    plan.close()
+
+
+def test_config1_full_size_sampled_patches(dev):
+    """Full-field workload (961 patches, 12 frames, 2 objects, 66 modes) in the
+    launch configuration of the benchmark; outputs compared on sampled patches.
+
+    The data of every patch is synthesised with numpy.fft (inputs only); for
+    the sampled patches it is replaced by the oracle's own simulation, which
+    must agree with the fast one."""
+    sample = [0, 30, 480, 517, 930, 960]
+    pr_all = synth.config1_problem()
+    D = fast_simulate_D(pr_all)
+    D_s = simulate_D(synth.config1_problem(sample))
+    assert np.abs(D[sample] - D_s).max() <= 1e-5 * np.abs(D_s).max()
+    D[sample] = D_s
+    rng = np.random.default_rng(47)
+    alphas = {"perturbed": (pr_all.alpha_true
+                            + 0.3 * rng.standard_normal(pr_all.alpha_true.shape)).astype(np.float32)}
+    check_patchwise(pr_all, D, alphas, dev, patches=sample)

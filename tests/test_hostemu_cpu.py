@@ -1,0 +1,106 @@
+"""The GPU wave operators (ops64.h), run lane by lane on the CPU by the host
+emulation harness, against numpy's FFT and the FP64 oracle.
+
+This checks the index logic of the transforms the kernels use -- the same
+source code -- without a GPU.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(os.path.dirname(HERE), "paper_2505_10639_amd", "libmomfbd_hostemu.so")
+FP = ctypes.POINTER(ctypes.c_float)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    if not os.path.exists(EMU):
+        pytest.fail("libmomfbd_hostemu.so is not built: run __graft_entry__.build()")
+    return ctypes.CDLL(EMU)
+
+
+def ptr(a):
+    return a.ctypes.data_as(FP)
+
+
+def rng(k):
+    return np.random.default_rng(500 + k)
+
+
+@pytest.mark.parametrize("L,d", [(32, -1), (32, 1), (64, -1), (64, 1)])
+def test_in_lane_fft(emu, L, d):
+    x = (rng(L).standard_normal(L) + 1j * rng(L + 1).standard_normal(L)).astype(np.complex64)
+    y = x.copy()
+    (emu.emu_fft32 if L == 32 else emu.emu_fft64)(ptr(y.view(np.float32)), d)
+    ref = np.fft.fft(x.astype(complex)) if d < 0 else np.fft.ifft(x.astype(complex)) * L
+    assert np.abs(y - ref).max() <= 3e-7 * np.abs(ref).max()
+
+
+def test_real_forward_2d(emu):
+    img = rng(1).standard_normal((64, 64)).astype(np.float32)
+    half = np.zeros((64, 33), np.complex64)
+    emu.emu_r2c(ptr(img), ptr(half.view(np.float32)))
+    ref = oracle.dft2(img)[:, :33]
+    assert np.abs(half - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_hermitian_inverse_2d(emu):
+    H = oracle.dft2(rng(2).standard_normal((64, 64)))
+    half = H[:, :33].astype(np.complex64)
+    out = np.zeros((64, 64), np.float32)
+    emu.emu_c2r(ptr(half.view(np.float32)), ptr(out))
+    ref = oracle.idft2_un(oracle.expand_half(half, 64)).real
+    assert np.abs(out - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_band_pupil_inverse(emu):
+    A = synth.pupil_mask(64)[16:48, 16:48].astype(np.float32)
+    ph = (0.2 * rng(3).standard_normal((32, 32))).astype(np.float32)
+    p = np.zeros((64, 64), np.complex64)
+    emu.emu_pupil_ifft(ptr(A), ptr(ph), ptr(p.view(np.float32)))
+    P = np.zeros((64, 64), complex)
+    P[16:48, 16:48] = A * np.exp(2j * np.pi * ph.astype(np.float64))
+    ref = oracle.idft2_un(P)
+    assert np.abs(p - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_forward_on_band(emu):
+    h = (rng(4).standard_normal((64, 64)) + 1j * rng(5).standard_normal((64, 64))).astype(np.complex64)
+    band = np.zeros((32, 32), np.complex64)
+    emu.emu_fft_to_band(ptr(h.view(np.float32)), ptr(band.view(np.float32)))
+    ref = oracle.dft2(h)[16:48, 16:48]
+    assert np.abs(band - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_unit_chain_matches_oracle_gradient(emu):
+    """PSF, OTF and dL/dphi of one unit against the oracle's formulas."""
+    pr = synth.make_problem(31, N=64, P=1, J=1, M=20, d_over_r0=12.0)
+    A = pr.pupil[0].astype(np.float64)
+    phi = oracle.wavefront(pr.alpha_true[0, 0], pr.basis[0], pr.diversity[0])
+    Ab = A[16:48, 16:48].astype(np.float32)
+    ph = (phi[16:48, 16:48] / (2 * np.pi)).astype(np.float32)
+    kap = 1.0 / (64 * 64 * A.sum())
+    G = oracle.dft2(rng(6).standard_normal((64, 64)))      # any Hermitian spectrum
+    Gh = G[:, :33].astype(np.complex64)
+    psf = np.zeros((64, 64), np.float32)
+    S = np.zeros((64, 33), np.complex64)
+    gphi = np.zeros((32, 32), np.float32)
+    emu.emu_unit(ptr(Ab), ptr(ph), ctypes.c_float(kap), ptr(Gh.view(np.float32)), ptr(psf),
+                 ptr(S.view(np.float32)), ptr(gphi))
+    P = oracle.pupil_field(A, phi)
+    p = oracle.psf_field(P)
+    s = kap * np.abs(p) ** 2
+    assert np.abs(psf - s).max() <= 1e-6 * s.max()
+    S_ref = oracle.otf(s)[:, :33]
+    assert np.abs(S - S_ref).max() <= 1e-6
+    g_s = oracle.idft2_un(oracle.expand_half(Gh, 64)).real
+    GP = oracle.dft2(2 * kap * g_s * p)
+    ref = (np.conj(P) * GP).imag[16:48, 16:48]
+    assert np.abs(gphi - ref).max() <= 2e-5 * np.abs(ref).max()

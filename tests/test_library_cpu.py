@@ -1,0 +1,98 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "momfbd.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2505_10639_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmomfbd.so is not built: run __graft_entry__.build()")
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(momfbd_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
+                     "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
+                     "momfbd_object_estimate", "momfbd_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    from paper_2505_10639_amd import momfbd_status_string
+    assert momfbd_status_string(0) == "ok"
+    assert momfbd_status_string(-1) == "invalid argument"
+    assert momfbd_status_string(-2) == "unsupported configuration"
+    assert momfbd_status_string(-3).startswith("workspace")
+    assert momfbd_status_string(-4).startswith("HIP")
+
+
+def _arrays(N=64, C=1, M=6, frac=0.45):
+    A = np.broadcast_to(synth.pupil_mask(N, frac), (C, N, N)).astype(np.float32)
+    Z = np.broadcast_to(synth.zernike_basis(N, M, frac), (C, M, N, N)).astype(np.float32)
+    return np.ascontiguousarray(A), np.ascontiguousarray(Z)
+
+
+def _create(L, N=64, P=2, C=1, K=1, J=3, M=6, co=None, A=None, Z=None, desc_null=False):
+    from paper_2505_10639_amd._lib import momfbd_desc
+    co = co if co is not None else [0] * C
+    arr = (ctypes.c_int * C)(*co)
+    desc = momfbd_desc(N, P, C, K, J, M, arr)
+    if A is None:
+        A, Z = _arrays(N, C, M)
+    out = ctypes.c_void_p()
+    st = L.momfbd_plan_create(None if desc_null else ctypes.byref(desc),
+                              A.ctypes.data if A is not None else None,
+                              Z.ctypes.data if Z is not None else None, None, ctypes.byref(out))
+    return st, out
+
+
+def test_plan_create_rejects_bad_arguments_without_a_device(L):
+    assert _create(L, desc_null=True)[0] == -1
+    assert _create(L, P=0)[0] == -1
+    assert _create(L, J=0)[0] == -1
+    assert _create(L, C=2, K=1, co=[0, 1])[0] == -1           # object id out of range
+    assert _create(L, C=2, K=2, co=[0, 0])[0] == -1           # object 1 owns no channel
+    A, Z = _arrays(80, 1, 6)
+    assert _create(L, N=80, A=A, Z=Z)[0] == -2                # patch size unsupported
+    assert _create(L, M=300, A=_arrays(64, 1, 300)[0], Z=_arrays(64, 1, 300)[1])[0] == -2
+    assert _create(L, J=100, M=100, A=_arrays(64, 1, 100)[0], Z=_arrays(64, 1, 100)[1])[0] == -2
+    A, Z = _arrays(64, 1, 6, frac=0.6)                        # pupil wider than N/2
+    assert _create(L, A=A, Z=Z)[0] == -2
+    A0 = np.zeros((1, 64, 64), np.float32)
+    assert _create(L, A=A0, Z=_arrays(64, 1, 6)[1])[0] == -1  # empty pupil
+    An = _arrays(64, 1, 6)[0].copy()
+    An[0, 30, 30] = np.nan
+    assert _create(L, A=An, Z=_arrays(64, 1, 6)[1])[0] == -1  # NaN in the pupil
+
+
+def test_calls_reject_null_plan_and_workspace(L):
+    assert L.momfbd_loss_grad(None, None, None, None, 1e-3, None, None, None, None, None) == -1
+    assert L.momfbd_forward(None, None, None, None, None, None) == -1
+    assert L.momfbd_object_estimate(None, None, None, None, 1e-3, None, None, None, None) == -1
+    assert L.momfbd_prepare_data(None, None, 64, 64, 32, None, None, None, None) == -1
+    assert L.momfbd_plan_destroy(None) == 0
+    n = ctypes.c_size_t()
+    assert L.momfbd_workspace_size(None, ctypes.byref(n)) == -1
