@@ -81,9 +81,20 @@ def test_two_objects_weights_and_gamma_array(dev):
     check_patchwise(pr, simulate_D(pr), alpha_points(pr, 2), dev, gamma=gam, weights=w)
 
 
-def test_single_frame_single_mode(dev):
-    pr = synth.make_problem(43, N=64, P=1, J=1, M=1, d_over_r0=5.0)
-    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 3), dev)
+def test_single_frame_phase_diversity(dev):
+    # One frame seen in focus and with +1 wave defocus (single-frame phase
+    # diversity, as for the IMaX data of the results section).  Tip and tilt
+    # then shift both images alike, to which the loss is exactly invariant, so
+    # their gradient vanishes.
+    pr = synth.make_problem(43, N=64, P=1, J=1, M=10, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=8.0)
+    D = simulate_D(pr)
+    check_patchwise(pr, D, alpha_points(pr, 3), dev)
+    plan = make_plan(pr, dev)
+    _, grad = run_gpu(plan, alpha_points(pr, 3)["perturbed"], to_dev(D, dev), pr.gamma, None,
+                      dev)
+    assert np.all(np.abs(grad[0, 0, :2]) <= 1e-4 * np.linalg.norm(grad[0, 0, 2:]))
+    plan.close()
 
 
 def test_forward_psf_and_otf(dev):
