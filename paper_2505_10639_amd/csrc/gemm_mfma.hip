@@ -1,0 +1,159 @@
+// Dense modal contractions on the matrix cores (FP32 MFMA, gfx950).
+//
+//   phase : phi[p][c][j][px] = theta_c[px] + sum_m Z_c[m][px] alpha[p][j][m]
+//           (Eq. wavefront on the 32x32 pupil band, in turns)
+//   grad  : dL/dalpha[p][j][m] = 2 pi sum_c sum_px Z_c[m][px] gphi[p][c][j][px]
+//
+// Both use v_mfma_f32_16x16x4f32.  Operand layout of that instruction: lane l
+// supplies A[i = l%16][k = l/16] and B[k = l/16][j = l%16]; the 16x16 result
+// sits in 4 registers per lane, D[4 (l/16) + e][l%16], e = 0..3.
+// The k order is free, so lane group g = l/16 takes k = k0 + 4g + s at step s:
+// every lane then loads its four operands of a 16-wide k chunk as one float4.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mfbd {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, floatx4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
+  return acc;
+}
+
+// One block = 4 waves = 16 rows (p,j) x all mode columns; wave w sums the
+// quarter [w K/4, (w+1) K/4) of k = c*1024 + px; the partial sums are added
+// in fixed order (wave 0 + 1 + 2 + 3) through LDS.
+template <int MT>
+__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M,
+                                                   const float* __restrict__ Zt,
+                                                   const float* __restrict__ gphi,
+                                                   float* __restrict__ grad) {
+  __shared__ floatx4 red[3][MT][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * 16;
+  const int r = r0 + i16;
+  const bool rok = r < R;
+  const int p = rok ? r / J : 0, j = rok ? r % J : 0;
+  floatx4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int Kq = C * kBandPix / 4;
+  for (int kk = wave * Kq; kk < (wave + 1) * Kq; kk += 16) {
+    const int c = kk / kBandPix, px = kk % kBandPix + 4 * g;
+    const floatx4 a4 = rok ? *reinterpret_cast<const floatx4*>(
+                                 gphi + (((size_t)p * C + c) * J + j) * kBandPix + px)
+                           : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int m = t * 16 + i16;
+      const floatx4 b4 = (m < M) ? *reinterpret_cast<const floatx4*>(
+                                       Zt + ((size_t)c * M + m) * kBandPix + px)
+                                 : floatx4{0.f, 0.f, 0.f, 0.f};
+      acc[t] = mfma4(a4, b4, acc[t]);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) red[wave - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    floatx4 v = acc[t];
+    v += red[0][t][lane];
+    v += red[1][t][lane];
+    v += red[2][t][lane];
+    const int m = t * 16 + i16;
+    if (m >= M) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = r0 + 4 * g + e;
+      if (row < R) grad[(size_t)row * M + m] = 6.283185307179586f * v[e];
+    }
+  }
+}
+
+// phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
+// Block = 4 waves: 64 pixels (a 16-row tile per wave) x 64 columns (4 tiles).
+__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp,
+                                                    const float* __restrict__ ZtT,
+                                                    const float* __restrict__ theta,
+                                                    const float* __restrict__ alpha,
+                                                    float* __restrict__ phi) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int c = blockIdx.x / (kBandPix / 64);
+  const int px0 = (blockIdx.x % (kBandPix / 64)) * 64 + wave * 16;
+  const int col0 = blockIdx.y * 64;
+  floatx4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float* arow = ZtT + ((size_t)c * kBandPix + px0 + i16) * Mp;
+  for (int kk = 0; kk < Mp; kk += 16) {
+    const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = col0 + t * 16 + i16;
+      floatx4 b4;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int m = kk + 4 * g + s;
+        b4[s] = (col < R && m < M) ? alpha[(size_t)col * M + m] : 0.f;
+      }
+      acc[t] = mfma4(a4, b4, acc[t]);
+    }
+  }
+  const floatx4 th = *reinterpret_cast<const floatx4*>(theta + c * kBandPix + px0 + 4 * g);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = col0 + t * 16 + i16;
+    if (col >= R) continue;
+    const int p = col / J, j = col % J;
+    *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + c) * J + j) * kBandPix + px0 + 4 * g) =
+        acc[t] + th;
+  }
+}
+
+template <int MT>
+void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
+                   hipStream_t s) {
+  const int R = d.P * d.J;
+  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M,
+                     Zt, gphi, grad);
+}
+
+}  // namespace
+
+hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
+                       hipStream_t s) {
+  const int mt = (d.M + 15) / 16;
+  switch (mt) {
+#define MFBD_CASE(n) \
+  case n: launch_grad_t<n>(d, Zt, gphi, grad, s); break;
+    MFBD_CASE(1) MFBD_CASE(2) MFBD_CASE(3) MFBD_CASE(4) MFBD_CASE(5) MFBD_CASE(6)
+    MFBD_CASE(7) MFBD_CASE(8) MFBD_CASE(9) MFBD_CASE(10) MFBD_CASE(11) MFBD_CASE(12)
+    MFBD_CASE(13) MFBD_CASE(14) MFBD_CASE(15) MFBD_CASE(16)
+#undef MFBD_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
+                        const float* thetat, float* phi, hipStream_t s) {
+  const int R = d.P * d.J;
+  dim3 grid(d.C * (kBandPix / 64), (R + 63) / 64);
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), 0, s, R, d.J, d.C, d.M, Mp, ZtT, thetat,
+                     alpha, phi);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

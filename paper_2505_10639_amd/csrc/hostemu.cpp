@@ -188,4 +188,48 @@ void emu_unit(const float* A, const float* ph, float kappa, const float* G_half,
   }
 }
 
+// Same as emu_unit's adjoint half, through the fused op14 path.
+void emu_unit_fused(const float* A, const float* ph, float kappa, const float* G_half,
+                    float* gphi) {
+  static Wave w;
+  static float2 pe[64][32], po[64][32], Pk[64][16], X[64][32], x32[64], Gr[64][32];
+  static float g[64 * 64];
+  load_sl(G_half, X, x32);
+  c2r(w, X, x32, g);
+  pupil_to_p(w, A, ph, pe, po, Pk);   // leaves op1_cols output in w.T
+  // pupil_to_p ran op1_rows as well, which only reads T: redo op1_cols so T holds it
+  for (int l = 0; l < 64; ++l) {
+    const int q = l >> 1, b = l & 1;
+    float2 P[32], y[32];
+    for (int n = 0; n < 32; ++n) {
+      const double ang = 2.0 * M_PI * (double)ph[n * 32 + q];
+      const float a = A[n * 32 + q];
+      P[n] = make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang));
+    }
+    static_for<0, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      y[n] = b ? twmul<+1, 64, 16 + n>(P[n]) : P[n];
+    });
+    op1_cols(y, w.T, l);
+  }
+  for (int l = 0; l < 64; ++l) {
+    float ge[32], go[32];
+    for (int n = 0; n < 32; ++n) {
+      ge[n] = g[l * 64 + 2 * n];
+      go[n] = g[l * 64 + 2 * n + 1];
+    }
+    op14_rows(w.T, l, ge, go, 2.0f * kappa, Gr[l]);
+  }
+  for (int l = 0; l < 64; ++l) op14_write(Gr[l], w.T, l);
+  for (int l = 0; l < 64; ++l) {
+    float2 GP[16];
+    op4_cols(w.T, l, GP);
+    const int q = l >> 1, b = l & 1;
+    for (int i = 0; i < 16; ++i) {
+      const float2 pk = Pk[l][i], gp = GP[i];
+      gphi[(2 * i + b) * 32 + q] = pk.x * gp.y - pk.y * gp.x;
+    }
+  }
+}
+
 }  // extern "C"

@@ -45,8 +45,8 @@ size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_phase(const Dims& d, const float* alpha, const float* Zt, const float* thetat,
-                        float* phi, hipStream_t s);
+hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
+                        const float* thetat, float* phi, hipStream_t s);
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const float* Ab, const float* phi,
                             float* psf, float2* S, hipStream_t s);
 hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float2* S,

@@ -14,6 +14,10 @@
 #include "internal.h"
 #include "ops64.h"
 
+#ifndef MFBD_HW_SINCOS
+#define MFBD_HW_SINCOS 1
+#endif
+
 namespace mfbd {
 using namespace n64;
 
@@ -23,23 +27,31 @@ constexpr int kUnitF2 = N * HC;   // float2 elements per half spectrum (2112)
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
-// Pupil field on the band for lane (q,b): P[n] = A exp(2 pi i t), t in turns.
-// y[n] = P[n] * W64^{+b (16+n)}, the input of op1_cols.
+// exp(2 pi i t) for a phase t in turns.  The hardware sine/cosine take
+// turns directly; the argument is first reduced to [0,1).
+__device__ __forceinline__ float2 expi_turns(float t) {
+#if MFBD_HW_SINCOS
+  const float f = __builtin_amdgcn_fractf(t);
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+#else
+  float s, c;
+  sincospif(2.0f * t, &s, &c);
+  return make_float2(c, s);
+#endif
+}
+
+// Input of op1_cols for lane (q,b): y[n] = P(16+n, 16+q) W64^{+b(16+n)} with
+// P = A exp(2 pi i t) on the band; the modulation is a phase ramp of
+// b (16+n)/64 turns added before the exponential.
 __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const float* __restrict__ ph,
-                                            int lane, float2 (&P)[32], float2 (&y)[32]) {
+                                            int lane, float2 (&y)[32]) {
   const int q = lane >> 1, b = lane & 1;
 #pragma unroll
   for (int n = 0; n < 32; ++n) {
-    float a = A[n * kBand + q];
-    float t = ph[n * kBand + q];
-    float s, c;
-    sincospif(2.0f * t, &s, &c);
-    P[n] = make_float2(a * c, a * s);
+    const float a = A[n * kBand + q];
+    const float t = ph[n * kBand + q] + (b ? (16 + n) * (1.0f / 64.0f) : 0.0f);
+    y[n] = cscale(expi_turns(t), a);
   }
-  static_for<0, 32>([&](auto I) {
-    constexpr int n = decltype(I)::value;
-    y[n] = b ? twmul<+1, 64, 16 + n>(P[n]) : P[n];
-  });
 }
 
 template <bool WANT_PSF>
@@ -54,8 +66,8 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
   if (u >= units) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
-  float2 P[32], y[32];
-  build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, P, y);
+  float2 y[32];
+  build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, y);
   op1_cols(y, T, lane);
   wave_sync();
   float2 pe[32], po[32];
@@ -89,6 +101,10 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
 }
 
 // One block per patch; loops over objects and the half-spectrum frequencies.
+// One pass over D and S: N = sum w D conj(S), Q = gamma + sum w |S|^2 and
+// E = sum w |D|^2 are accumulated in FP64, where the products of FP32 inputs
+// are exact, so the loss term E - |N|^2/Q (Eq. loss_momfbd at the Wiener
+// object, equal to the residual form) keeps full accuracy.
 __global__ __launch_bounds__(256) void k_object64(int P, int C, int J, int K, ChanTab ct,
                                                   LossArgs la, const float2* __restrict__ S,
                                                   float2* __restrict__ O,
@@ -101,40 +117,32 @@ __global__ __launch_bounds__(256) void k_object64(int P, int C, int J, int K, Ch
     const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
     for (int f = tid; f < kUnitF2; f += 256) {
       const int kx = f % HC;
-      const float h = (kx == 0 || kx == HC - 1) ? 1.0f : 2.0f;
-      const float g = la.gamma ? la.gamma[(size_t)k * kUnitF2 + f] : la.gamma_scalar;
-      float nr = 0.f, ni = 0.f, qq = g;
+      const double h = (kx == 0 || kx == HC - 1) ? 1.0 : 2.0;
+      const double g = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f] : (double)la.gamma_scalar;
+      double nr = 0.0, ni = 0.0, qq = g, e = 0.0;
       for (int ci = c0; ci < c1; ++ci) {
         const int c = ct.obj_chans[ci];
+        const float2* Dc = la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f;
+        const float2* Sc = S + ((size_t)(p * C + c) * J) * kUnitF2 + f;
         for (int j = 0; j < J; ++j) {
-          const size_t idx = ((size_t)(p * C + c) * J + j) * kUnitF2 + f;
-          const float w = la.weights ? la.weights[c * J + j] : 1.0f;
-          const float2 d = la.D[idx], s = S[idx];
-          nr += w * (d.x * s.x + d.y * s.y);
-          ni += w * (d.y * s.x - d.x * s.y);
-          qq += w * (s.x * s.x + s.y * s.y);
+          const double w = la.weights ? (double)la.weights[c * J + j] : 1.0;
+          const float2 d = Dc[(size_t)j * kUnitF2], s = Sc[(size_t)j * kUnitF2];
+          const double dx = d.x, dy = d.y, sx = s.x, sy = s.y;
+          nr += w * (dx * sx + dy * sy);
+          ni += w * (dy * sx - dx * sy);
+          qq += w * (sx * sx + sy * sy);
+          e += w * (dx * dx + dy * dy);
         }
       }
-      const float2 o = make_float2(nr / qq, ni / qq);
-      O[((size_t)p * K + k) * kUnitF2 + f] = o;
-      double part = (double)(g * cabs2(o));
-      for (int ci = c0; ci < c1; ++ci) {
-        const int c = ct.obj_chans[ci];
-        for (int j = 0; j < J; ++j) {
-          const size_t idx = ((size_t)(p * C + c) * J + j) * kUnitF2 + f;
-          const float w = la.weights ? la.weights[c * J + j] : 1.0f;
-          const float2 d = la.D[idx], s = S[idx];
-          const float2 r = csub(d, cmul(o, s));
-          part += (double)(w * cabs2(r));
-        }
-      }
-      acc += (double)h * part;
+      const double inv = 1.0 / qq;
+      O[((size_t)p * K + k) * kUnitF2 + f] = make_float2((float)(nr * inv), (float)(ni * inv));
+      acc += h * (e - (nr * nr + ni * ni) * inv);
     }
   }
   red[tid] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] += red[tid + s2];
     __syncthreads();
   }
   if (tid == 0) loss[p] = red[0];
@@ -184,33 +192,31 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, 
   op3_rows(T, lane, ge, go);
   wave_sync();
 
-  // recompute the complex PSF amplitude p
-  float2 Pp[32], y[32];
-  build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, Pp, y);
-  const int b = lane & 1, q = lane >> 1;
-  float2 Pk[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) Pk[i] = b ? Pp[2 * i + 1] : Pp[2 * i];
-  op1_cols(y, T, lane);
-  wave_sync();
-  float2 pe[32], po[32];
-  op1_rows(T, lane, pe, po);
-  wave_sync();
-  const float k2 = 2.0f * ct.kappa[c];
-#pragma unroll
-  for (int n = 0; n < 32; ++n) {
-    pe[n] = cscale(pe[n], k2 * ge[n]);
-    po[n] = cscale(po[n], k2 * go[n]);
+  // recompute the pupil band transform, then H = 2 kappa g p and its
+  // forward transform to the band, half a row spectrum at a time
+  const float* Ac = Ab + c * kBandPix;
+  const float* phu = phi + (size_t)u * kBandPix;
+  {
+    float2 y[32];
+    build_pupil(Ac, phu, lane, y);
+    op1_cols(y, T, lane);
   }
-  op4_rows(pe, po, T, lane);
+  wave_sync();
+  float2 Gr[32];
+  op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c], Gr);
+  wave_sync();
+  op14_write(Gr, T, lane);
   wave_sync();
   float2 GP[16];
   op4_cols(T, lane, GP);
+  const int b = lane & 1, q = lane >> 1;
   float* gout = gphi + (size_t)u * kBandPix;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const float2 pk = Pk[i], gp = GP[i];
-    gout[(2 * i + b) * kBand + q] = pk.x * gp.y - pk.y * gp.x;   // Im(conj(P) G_P)
+    const int n = 2 * i + b;
+    const float2 pk = cscale(expi_turns(phu[n * kBand + q]), Ac[n * kBand + q]);
+    const float2 gp = GP[i];
+    gout[n * kBand + q] = pk.x * gp.y - pk.y * gp.x;   // Im(conj(P) G_P)
   }
 }
 
@@ -287,108 +293,7 @@ __global__ __launch_bounds__(64) void k_objimg64(int items, const float2* __rest
   }
 }
 
-// ---------------------------------------------------------------------------
-// Tiled FP32 GEMM on the vector ALUs: out[r][col] = sum_k A(r,k) B(k,col).
-// 64 x 64 output tile per 256-thread block, 4 x 4 per thread, k chunks of 16.
-// ---------------------------------------------------------------------------
-template <class Prob>
-__global__ __launch_bounds__(256) void k_gemm(Prob pb) {
-  __shared__ float As[16][64 + 4];
-  __shared__ float Bs[16][64 + 4];
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < pb.Kdim; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e / 64, xx = e % 64;
-      As[kk][xx] = pb.a(r0 + xx, k0 + kk);
-      Bs[kk][xx] = pb.b(k0 + kk, c0 + xx);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][tr + 16 * i];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) bv[i] = Bs[kk][tc + 16 * i];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jj] += av[i] * bv[jj];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) pb.store(r0 + tr + 16 * i, c0 + tc + 16 * jj, acc[i][jj]);
-}
-
-// phi[p][c][j][px] = theta[c][px] + sum_m alpha[p][j][m] Z[c][m][px]
-// rows r = p*J + j, columns col = c*1024 + px, k = m
-struct PhaseProb {
-  int Rows, Cols, Kdim, J, C, M;
-  const float* alpha;
-  const float* Z;
-  const float* theta;
-  float* phi;
-  __device__ float a(int r, int k) const {
-    return (r < Rows && k < M) ? alpha[(size_t)r * M + k] : 0.f;
-  }
-  __device__ float b(int k, int col) const {
-    if (k >= M || col >= Cols) return 0.f;
-    const int c = col / kBandPix, px = col % kBandPix;
-    return Z[((size_t)c * M + k) * kBandPix + px];
-  }
-  __device__ void store(int r, int col, float v) const {
-    if (r >= Rows || col >= Cols) return;
-    const int p = r / J, j = r % J, c = col / kBandPix, px = col % kBandPix;
-    phi[(((size_t)p * C + c) * J + j) * kBandPix + px] = v + theta[c * kBandPix + px];
-  }
-};
-
-// grad[p][j][m] = 2 pi sum_c sum_px Z[c][m][px] gphi[p][c][j][px]
-// rows r = p*J + j, columns m, k = c*1024 + px
-struct GradProb {
-  int Rows, Cols, Kdim, J, C, M;
-  const float* Z;
-  const float* gphi;
-  float* grad;
-  __device__ float a(int r, int k) const {
-    if (r >= Rows || k >= Kdim) return 0.f;
-    const int p = r / J, j = r % J, c = k / kBandPix, px = k % kBandPix;
-    return gphi[(((size_t)p * C + c) * J + j) * kBandPix + px];
-  }
-  __device__ float b(int k, int col) const {
-    if (k >= Kdim || col >= Cols) return 0.f;
-    const int c = k / kBandPix, px = k % kBandPix;
-    return Z[((size_t)c * M + col) * kBandPix + px];
-  }
-  __device__ void store(int r, int col, float v) const {
-    if (r >= Rows || col >= Cols) return;
-    grad[(size_t)r * M + col] = 6.283185307179586f * v;
-  }
-};
-
 }  // namespace
-
-hipError_t launch_phase(const Dims& d, const float* alpha, const float* Zt, const float* thetat,
-                        float* phi, hipStream_t s) {
-  PhaseProb pb{d.P * d.J, d.C * kBandPix, d.M, d.J, d.C, d.M, alpha, Zt, thetat, phi};
-  dim3 grid((pb.Cols + 63) / 64, (pb.Rows + 63) / 64);
-  hipLaunchKernelGGL(k_gemm<PhaseProb>, grid, dim3(256), 0, s, pb);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
-                       hipStream_t s) {
-  GradProb pb{d.P * d.J, d.M, d.C * kBandPix, d.J, d.C, d.M, Zt, gphi, grad};
-  dim3 grid((pb.Cols + 63) / 64, (pb.Rows + 63) / 64);
-  hipLaunchKernelGGL(k_gemm<GradProb>, grid, dim3(256), 0, s, pb);
-  return hipGetLastError();
-}
 
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const float* Ab, const float* phi,
                             float* psf, float2* S, hipStream_t s) {

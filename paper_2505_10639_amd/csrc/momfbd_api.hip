@@ -34,6 +34,8 @@ struct momfbd_plan_s {
   int shift_x[kMaxC];
   float* Ab = nullptr;     // [C][32][32]   aperture on the band
   float* Zt = nullptr;     // [C][M][32][32] modes in turns
+  float* ZtT = nullptr;    // [C][32*32][Mp] the same, mode index fastest, zero padded
+  int Mp = 0;              // M rounded up to a multiple of 16
   float* thetat = nullptr; // [C][32][32]   diversity in turns
 };
 
@@ -218,10 +220,19 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
               (float)((double)basis[((size_t)c * M + m) * N * N + src] / kTwoPi);
       }
   }
+  pl->Mp = (M + 15) / 16 * 16;
+  std::vector<float> hZT((size_t)C * kBandPix * pl->Mp, 0.f);
+  for (int c = 0; c < C; ++c)
+    for (int m = 0; m < M; ++m)
+      for (int px = 0; px < kBandPix; ++px)
+        hZT[((size_t)c * kBandPix + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * kBandPix + px];
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->Zt, hZ.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->ZtT, hZT.size() * sizeof(float)) == hipSuccess &&
+            hipMemcpy(pl->ZtT, hZT.data(), hZT.size() * sizeof(float), hipMemcpyHostToDevice) ==
+                hipSuccess &&
             hipMemcpy(pl->Ab, hA.data(), hA.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->Zt, hZ.data(), hZ.size() * sizeof(float), hipMemcpyHostToDevice) ==
@@ -242,6 +253,7 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   if (plan->Ab) (void)hipFree(plan->Ab);
   if (plan->Zt) (void)hipFree(plan->Zt);
   if (plan->thetat) (void)hipFree(plan->thetat);
+  if (plan->ZtT) (void)hipFree(plan->ZtT);
   delete plan;
   return MOMFBD_OK;
 }
@@ -289,7 +301,7 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   hipError_t e;
   {
     ProfScope ps(plan, KK_PHASE, s);
-    e = launch_phase(plan->d, alpha, plan->Zt, plan->thetat, w.phi, s);
+    e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);
@@ -307,7 +319,7 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
   hipError_t e;
   {
     ProfScope ps(plan, KK_PHASE, s);
-    e = launch_phase(plan->d, alpha, plan->Zt, plan->thetat, w.phi, s);
+    e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);

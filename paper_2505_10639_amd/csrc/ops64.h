@@ -233,5 +233,49 @@ MFBD_HDI void op4_cols(const float2* T, int lane, float2 (&GP)[16]) {
   static_for<0, 16>([&](auto I) { GP[decltype(I)::value] = X[8 + decltype(I)::value]; });
 }
 
+// ---------------------------------------------------------------------------
+// Op 1+4 fused for the adjoint: from the band-column transform of the pupil
+// (left in LDS by op1_cols) and the real image g (row layout), form
+//   H = kap2 * g * p  (p the complex PSF amplitude of op1_rows)
+// and run the row pass of op4 on it, one parity half of the columns at a
+// time, so that p never has to be held in full.  The (-1)^m factors of the
+// op1 row output and of the op4 row input cancel.  Result, for row r = lane:
+//   Gr[v'] = G_r(r, 16 + v'), v' in [0,32), to be written by op14_write
+// after a barrier (it overwrites the buffer op1_cols filled).
+// ---------------------------------------------------------------------------
+template <int E>
+MFBD_HDI void op14_half(const float2* T, int lane, const float (&g)[32], float kap2,
+                        float2 (&A)[32]) {
+  static_for<0, 32>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    float2 c = T[q * T1 + lane];
+    A[q] = E ? twmul<+1, 64, 16 + q>(c) : c;
+  });
+  fft32<+1>(A);
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    A[m] = cscale(A[m], kap2 * g[m]);
+  });
+  fft32<-1>(A);
+}
+
+MFBD_HDI void op14_rows(const float2* T, int lane, const float (&ge)[32], const float (&go)[32],
+                        float kap2, float2 (&Gr)[32]) {
+  op14_half<0>(T, lane, ge, kap2, Gr);
+  float2 B[32];
+  op14_half<1>(T, lane, go, kap2, B);
+  static_for<0, 32>([&](auto V) {
+    constexpr int v = decltype(V)::value;
+    Gr[v] = cadd(Gr[v], twmul<-1, 64, 16 + v>(B[v]));
+  });
+}
+
+MFBD_HDI void op14_write(const float2 (&Gr)[32], float2* T, int lane) {
+  static_for<0, 32>([&](auto V) {
+    constexpr int v = decltype(V)::value;
+    T[lane * T2 + v] = Gr[v];
+  });
+}
+
 }  // namespace n64
 }  // namespace mfbd
