@@ -134,6 +134,46 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
                            float* obj, void* ws, void* stream);
 
+/* Per-patch L-BFGS solver (the quasi-Newton alternative to the paper's Adam,
+ * Sect. "Optimization and paralellization"; patches are independent).
+ * Each patch runs the two-loop recursion of limited-memory BFGS and a
+ * bracketing/zoom line search enforcing the strong Wolfe conditions
+ * (Nocedal & Wright, Numerical Optimization, Algorithms 7.4, 3.5, 3.6);
+ * zoom trials are the clamped cubic-interpolation minimiser; all scalars
+ * FP64. */
+typedef struct {
+  int m;           /* stored correction pairs, 1..32 (10 is usual)              */
+  int max_evals;   /* loss+gradient evaluations per line search, 1..1000 (20)  */
+  double c1;       /* sufficient-decrease constant, 0 < c1 < c2 (1e-4)          */
+  double c2;       /* curvature constant, c1 < c2 < 1 (0.9)                     */
+  double ftol;     /* a patch stops when its loss falls by <= ftol*|loss| in one
+                      iteration (0: never)                                      */
+} momfbd_lbfgs_params;
+
+/* Bytes of solver state (device memory, 256-byte aligned, owned by the
+ * caller) for this plan and these parameters.  Errors: EINVAL. */
+int momfbd_lbfgs_state_size(momfbd_plan plan, const momfbd_lbfgs_params* params, size_t* bytes);
+
+/* Start a solve at alpha (DEVICE float [P][J][M]): evaluates loss and
+ * gradient, clears the history.  loss (DEVICE double [P]) may be NULL.
+ * Other arguments as momfbd_loss_grad.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                      const float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                      const float* weights, double* loss, void* ws, void* stream);
+
+/* One L-BFGS iteration for every patch that has not stopped.  alpha is
+ * updated in place (DEVICE float [P][J][M], the same array the solve was
+ * started with).  loss (DEVICE double [P], or NULL) receives each patch's
+ * loss at its accepted point; status (DEVICE int [P], or NULL): 0 running,
+ * 1 converged (relative decrease <= ftol, or zero gradient), 2 stopped
+ * (line search found no strong-Wolfe point within max_evals; alpha is left
+ * at the start of that search).  Evaluations run only for patches still
+ * searching; after each, the call synchronises `stream` to read how many
+ * remain.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                      float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                      const float* weights, double* loss, int* status, void* ws, void* stream);
+
 /* Kernel timing for measurement.  After momfbd_profile_start, every kernel
  * launched by this plan's calls (up to max_launches launches) is bracketed
  * by a pair of HIP events recorded on the call's stream.  Events are created

@@ -10,21 +10,23 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
                    momfbd_plan_destroy, momfbd_workspace_size, momfbd_plan_dims,
                    momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
                    momfbd_object_estimate, momfbd_profile_start,
-                   momfbd_profile_stop, lib)
+                   momfbd_profile_stop, momfbd_lbfgs_state_size, momfbd_lbfgs_init,
+                   momfbd_lbfgs_step, lbfgs_params, lib)
 
 __all__ = [
     "MomfbdError", "LIB_PATH", "momfbd_status_string", "momfbd_plan_create",
     "momfbd_plan_destroy", "momfbd_workspace_size", "momfbd_plan_dims", "momfbd_prepare_data",
     "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",
-    "momfbd_profile_stop", "lib", "Plan",
+    "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init", "momfbd_lbfgs_step",
+    "lbfgs_params", "lib", "Plan", "Solver",
     "MomfbdLoss", "momfbd_loss",
 ]
 
 
 def __getattr__(name):
-    if name == "Plan":
-        from .plan import Plan
-        return Plan
+    if name in ("Plan", "Solver"):
+        from . import plan
+        return getattr(plan, name)
     if name in ("MomfbdLoss", "momfbd_loss"):
         from . import autograd
         return getattr(autograd, name)

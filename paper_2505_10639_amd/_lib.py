@@ -29,6 +29,11 @@ class MomfbdError(RuntimeError):
         super().__init__(f"{where}: {momfbd_status_string(status)} (status {status})")
 
 
+class momfbd_lbfgs_params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("max_evals", ctypes.c_int), ("c1", ctypes.c_double),
+                ("c2", ctypes.c_double), ("ftol", ctypes.c_double)]
+
+
 class momfbd_desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int),
                 ("K", ctypes.c_int), ("J", ctypes.c_int), ("M", ctypes.c_int),
@@ -61,12 +66,17 @@ def lib():
         L.momfbd_status_string.restype = ctypes.c_char_p
         L.momfbd_plan_dims.argtypes = [_vp] + [ctypes.POINTER(i)] * 6
         L.momfbd_profile_start.argtypes = [_vp, i]
+        pp = ctypes.POINTER(momfbd_lbfgs_params)
+        L.momfbd_lbfgs_state_size.argtypes = [_vp, pp, ctypes.POINTER(ctypes.c_size_t)]
+        L.momfbd_lbfgs_init.argtypes = [_vp, pp, _vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
+        L.momfbd_lbfgs_step.argtypes = [_vp, pp, _vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_stop.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_char_p),
                                           ctypes.POINTER(d), ctypes.POINTER(i)]
         for name in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
                      "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
-                     "momfbd_profile_stop"):
+                     "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
+                     "momfbd_lbfgs_step"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -171,3 +181,29 @@ def momfbd_profile_stop(plan) -> dict:
     if n < 0:
         raise MomfbdError(n, "momfbd_profile_stop")
     return {names[k].decode(): (ms[k], cnt[k]) for k in range(n)}
+
+
+def lbfgs_params(m=10, max_evals=20, c1=1e-4, c2=0.9, ftol=0.0):
+    return momfbd_lbfgs_params(int(m), int(max_evals), float(c1), float(c2), float(ftol))
+
+
+def momfbd_lbfgs_state_size(plan, params) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().momfbd_lbfgs_state_size(plan, ctypes.byref(params), ctypes.byref(n)),
+           "momfbd_lbfgs_state_size")
+    return n.value
+
+
+def momfbd_lbfgs_init(plan, params, state, alpha, D, gamma, gamma_scalar, weights, loss, ws,
+                      stream=None):
+    _check(lib().momfbd_lbfgs_init(plan, ctypes.byref(params), _ptr(state), _ptr(alpha), _ptr(D),
+                                   _ptr(gamma), float(gamma_scalar), _ptr(weights), _ptr(loss),
+                                   _ptr(ws), _stream(stream, alpha)), "momfbd_lbfgs_init")
+
+
+def momfbd_lbfgs_step(plan, params, state, alpha, D, gamma, gamma_scalar, weights, loss, status,
+                      ws, stream=None):
+    _check(lib().momfbd_lbfgs_step(plan, ctypes.byref(params), _ptr(state), _ptr(alpha), _ptr(D),
+                                   _ptr(gamma), float(gamma_scalar), _ptr(weights), _ptr(loss),
+                                   _ptr(status), _ptr(ws), _stream(stream, alpha)),
+           "momfbd_lbfgs_step")

@@ -83,16 +83,27 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M,
 
 // phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
 // Block = 4 waves: 64 pixels (a 16-row tile per wave) x 64 columns (4 tiles).
+// The 64 coefficient rows of the block (contiguous in alpha) are staged in
+// LDS with the mode index padded to Mp, so B operands are float4 LDS reads.
 __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp,
                                                     const float* __restrict__ ZtT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
                                                     float* __restrict__ phi) {
+  extern __shared__ float al[];    // [64][Mp + 4]
+  const int ldm = Mp + 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
   const int c = blockIdx.x / (kBandPix / 64);
   const int px0 = (blockIdx.x % (kBandPix / 64)) * 64 + wave * 16;
   const int col0 = blockIdx.y * 64;
+  const int ncol = min(64, R - col0);
+  const float* src = alpha + (size_t)col0 * M;
+  for (int e = threadIdx.x; e < 64 * Mp; e += 256) {
+    const int r = e / Mp, m = e % Mp;
+    al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
+  }
+  __syncthreads();
   floatx4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -101,13 +112,7 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
     const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int col = col0 + t * 16 + i16;
-      floatx4 b4;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int m = kk + 4 * g + s;
-        b4[s] = (col < R && m < M) ? alpha[(size_t)col * M + m] : 0.f;
-      }
+      const floatx4 b4 = *reinterpret_cast<const floatx4*>(al + (t * 16 + i16) * ldm + kk + 4 * g);
       acc[t] = mfma4(a4, b4, acc[t]);
     }
   }
@@ -151,7 +156,13 @@ hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int
                         const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J;
   dim3 grid(d.C * (kBandPix / 64), (R + 63) / 64);
-  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), 0, s, R, d.J, d.C, d.M, Mp, ZtT, thetat,
+  const size_t lds = (size_t)64 * (Mp + 4) * sizeof(float);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, ZtT, thetat,
                      alpha, phi);
   return hipGetLastError();
 }

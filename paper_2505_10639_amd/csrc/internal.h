@@ -47,17 +47,36 @@ Workspace carve_workspace(const Dims& d, void* base);
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
                         const float* thetat, float* phi, hipStream_t s);
-hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const float* Ab, const float* phi,
-                            float* psf, float2* S, hipStream_t s);
-hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float2* S,
-                           float2* O, double* loss, hipStream_t s);
-hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float* Ab,
-                            const float* phi, const float2* S, const float2* O, float* gphi,
-                            hipStream_t s);
+// `active` (nullable, [P]) restricts the unit kernels to patches with a
+// nonzero entry; the others are neither computed nor written.
+hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                            const float* phi, float* psf, float2* S, hipStream_t s);
+hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                           const float2* S, float2* O, double* loss, hipStream_t s);
+hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                            const int* active, const float* Ab, const float* phi, const float2* S,
+                            const float2* O, float* gphi, hipStream_t s);
 hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
                        hipStream_t s);
 hipError_t launch_prepare64(const Dims& d, const float* frames, int H, int W, int stride,
                             const float* apod, float2* D, hipStream_t s);
 hipError_t launch_objimg64(const Dims& d, const float2* O, float* obj, hipStream_t s);
+
+// L-BFGS (per-patch solver state lives in a caller-provided buffer)
+struct LbfgsLayout {
+  int m;              // history pairs
+  int n;              // variables per patch (J*M)
+  size_t hdr, rho, x0, g, d, gt, S, Y, ft, active, counter, total;   // byte offsets
+};
+LbfgsLayout lbfgs_layout(const Dims& d, int m, int max_evals);
+hipError_t launch_lbfgs_init(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
+                             hipStream_t s);
+hipError_t launch_lbfgs_begin(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                              int max_evals, hipStream_t s);
+hipError_t launch_lbfgs_search(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                               int eval, double c1, double c2, int max_evals, double ftol,
+                               hipStream_t s);
+hipError_t launch_lbfgs_finish(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
+                               int* status_out, hipStream_t s);
 
 }  // namespace mfbd

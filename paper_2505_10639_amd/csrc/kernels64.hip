@@ -56,6 +56,7 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const f
 
 template <bool WANT_PSF>
 __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, int J,
+                                                  const int* __restrict__ active,
                                                   const float* __restrict__ Ab,
                                                   const float* __restrict__ phi,
                                                   float* __restrict__ psf,
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
   __shared__ float2 Taux[LDS_AUX];
   const int u = blockIdx.x;
   if (u >= units) return;
+  if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
   float2 y[32];
@@ -100,43 +102,83 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
   out[sl_index32(lane)] = x32;
 }
 
-// One block per patch; loops over objects and the half-spectrum frequencies.
-// One pass over D and S: N = sum w D conj(S), Q = gamma + sum w |S|^2 and
-// E = sum w |D|^2 are accumulated in FP64, where the products of FP32 inputs
-// are exact, so the loss term E - |N|^2/Q (Eq. loss_momfbd at the Wiener
-// object, equal to the residual form) keeps full accuracy.
+// One block per patch; loops over objects and pairs of adjacent half-spectrum
+// frequencies (16-byte loads).  One pass over D and S: N = sum w D conj(S),
+// Q = gamma + sum w |S|^2 and E = sum w |D|^2 are accumulated in FP64, where
+// the products of FP32 inputs are exact, so the loss term E - |N|^2/Q
+// (Eq. loss_momfbd at the Wiener object, equal to the residual form) keeps
+// full accuracy.  Units are read four at a time so that loads overlap.
+struct Acc2 {
+  double nr[2], ni[2], q[2], e[2];
+};
+
+__device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
+  const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
+  const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
+  a.nr[0] += w * (dx0 * sx0 + dy0 * sy0);
+  a.ni[0] += w * (dy0 * sx0 - dx0 * sy0);
+  a.q[0] += w * (sx0 * sx0 + sy0 * sy0);
+  a.e[0] += w * (dx0 * dx0 + dy0 * dy0);
+  a.nr[1] += w * (dx1 * sx1 + dy1 * sy1);
+  a.ni[1] += w * (dy1 * sx1 - dx1 * sy1);
+  a.q[1] += w * (sx1 * sx1 + sy1 * sy1);
+  a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
+}
+
 __global__ __launch_bounds__(256) void k_object64(int P, int C, int J, int K, ChanTab ct,
-                                                  LossArgs la, const float2* __restrict__ S,
+                                                  LossArgs la, const int* __restrict__ active,
+                                                  const float2* __restrict__ S,
                                                   float2* __restrict__ O,
                                                   double* __restrict__ loss) {
   __shared__ double red[256];
   const int p = blockIdx.x;
+  if (active && !active[p]) return;
   const int tid = threadIdx.x;
   double acc = 0.0;
+  constexpr int kPairs = kUnitF2 / 2;
   for (int k = 0; k < K; ++k) {
     const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
-    for (int f = tid; f < kUnitF2; f += 256) {
-      const int kx = f % HC;
-      const double h = (kx == 0 || kx == HC - 1) ? 1.0 : 2.0;
-      const double g = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f] : (double)la.gamma_scalar;
-      double nr = 0.0, ni = 0.0, qq = g, e = 0.0;
+    for (int f2 = tid; f2 < kPairs; f2 += 256) {
+      const int f = 2 * f2;
+      Acc2 a;
+      for (int i = 0; i < 2; ++i) {
+        a.nr[i] = a.ni[i] = a.e[i] = 0.0;
+        a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
+      }
       for (int ci = c0; ci < c1; ++ci) {
         const int c = ct.obj_chans[ci];
-        const float2* Dc = la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f;
-        const float2* Sc = S + ((size_t)(p * C + c) * J) * kUnitF2 + f;
-        for (int j = 0; j < J; ++j) {
-          const double w = la.weights ? (double)la.weights[c * J + j] : 1.0;
-          const float2 d = Dc[(size_t)j * kUnitF2], s = Sc[(size_t)j * kUnitF2];
-          const double dx = d.x, dy = d.y, sx = s.x, sy = s.y;
-          nr += w * (dx * sx + dy * sy);
-          ni += w * (dy * sx - dx * sy);
-          qq += w * (sx * sx + sy * sy);
-          e += w * (dx * dx + dy * dy);
+        const float4* Dc = reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+        const float4* Sc = reinterpret_cast<const float4*>(S + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+        const float* wc = la.weights ? la.weights + c * J : nullptr;
+        int j = 0;
+        for (; j + 4 <= J; j += 4) {
+          float4 d[4], s[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            d[u] = Dc[(size_t)(j + u) * (kUnitF2 / 2)];
+            s[u] = Sc[(size_t)(j + u) * (kUnitF2 / 2)];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
         }
+        for (; j < J; ++j)
+          acc_unit(a, wc ? (double)wc[j] : 1.0, Dc[(size_t)j * (kUnitF2 / 2)],
+                   Sc[(size_t)j * (kUnitF2 / 2)]);
       }
-      const double inv = 1.0 / qq;
-      O[((size_t)p * K + k) * kUnitF2 + f] = make_float2((float)(nr * inv), (float)(ni * inv));
-      acc += h * (e - (nr * nr + ni * ni) * inv);
+      float4 o;
+      double part = 0.0;
+      {
+        const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
+        o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
+                        (float)(a.nr[1] * inv1), (float)(a.ni[1] * inv1));
+        const int kx0 = f % HC, kx1 = (f + 1) % HC;
+        const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
+        const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
+        part = h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
+               h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
+      }
+      reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
+      acc += part;
     }
   }
   red[tid] = acc;
@@ -149,7 +191,8 @@ __global__ __launch_bounds__(256) void k_object64(int P, int C, int J, int K, Ch
 }
 
 __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, int J, int K,
-                                                  LossArgs la, const float* __restrict__ Ab,
+                                                  LossArgs la, const int* __restrict__ active,
+                                                  const float* __restrict__ Ab,
                                                   const float* __restrict__ phi,
                                                   const float2* __restrict__ S,
                                                   const float2* __restrict__ O,
@@ -162,6 +205,7 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, 
   const int j = u % J;
   const int c = (u / J) % C;
   const int p = u / (J * C);
+  if (active && !active[p]) return;
   const int k = ct.chan_obj[c];
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
   const float2* Su = S + (size_t)u * kUnitF2;
@@ -295,31 +339,31 @@ __global__ __launch_bounds__(64) void k_objimg64(int items, const float2* __rest
 
 }  // namespace
 
-hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const float* Ab, const float* phi,
-                            float* psf, float2* S, hipStream_t s) {
+hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                            const float* phi, float* psf, float2* S, hipStream_t s) {
   const int units = d.P * d.C * d.J;
   if (psf)
-    hipLaunchKernelGGL(k_forward64<true>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J, Ab,
-                       phi, psf, S);
+    hipLaunchKernelGGL(k_forward64<true>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J,
+                       active, Ab, phi, psf, S);
   else
-    hipLaunchKernelGGL(k_forward64<false>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J, Ab,
-                       phi, psf, S);
+    hipLaunchKernelGGL(k_forward64<false>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J,
+                       active, Ab, phi, psf, S);
   return hipGetLastError();
 }
 
-hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float2* S,
-                           float2* O, double* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_object64, dim3(d.P), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la, S, O,
-                     loss);
+hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                           const float2* S, float2* O, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_object64, dim3(d.P), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la, active,
+                     S, O, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la, const float* Ab,
-                            const float* phi, const float2* S, const float2* O, float* gphi,
-                            hipStream_t s) {
+hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                            const int* active, const float* Ab, const float* phi, const float2* S,
+                            const float2* O, float* gphi, hipStream_t s) {
   const int units = d.P * d.C * d.J;
-  hipLaunchKernelGGL(k_adjoint64, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J, d.K, la, Ab,
-                     phi, S, O, gphi);
+  hipLaunchKernelGGL(k_adjoint64, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J, d.K, la,
+                     active, Ab, phi, S, O, gphi);
   return hipGetLastError();
 }
 

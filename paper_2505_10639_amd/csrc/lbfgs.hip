@@ -1,0 +1,393 @@
+// Batched per-patch L-BFGS with a strong-Wolfe line search (gfx950).
+//
+// The patches are independent (no coefficient is shared between patches), so
+// every patch runs its own quasi-Newton iteration: the two-loop recursion of
+// limited-memory BFGS for the direction, then a bracketing/zoom line search
+// enforcing the strong Wolfe conditions (Nocedal & Wright, Numerical
+// Optimization, Algorithms 7.4, 3.5 and 3.6).  Trial steps inside the zoom are
+// the minimiser of the cubic through the bracket ends, clamped to its central
+// 80% (bisection when the cubic has no real minimiser).  The first trial step
+// is min(1, 1/||g||_inf) when the history is empty and 1 otherwise.
+//
+// One block of 256 threads per patch; dot products are accumulated in FP64
+// in a fixed order; every scalar of the line search is FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace mfbd {
+
+namespace {
+
+struct Hdr {
+  double f, f0, dphi0, t, t_prev, f_prev, g_prev, lo, flo, glo, hi, fhi, ghi;
+  int phase, n_eval, count, head, iter, status, first, pad;
+};
+
+struct View {
+  Hdr* hdr;
+  double* rho;
+  float *x0, *g, *d, *gt, *S, *Y;
+  double* ft;
+  int* active;
+  int* counter;
+};
+
+__device__ __forceinline__ View view(const LbfgsLayout& L, void* state) {
+  char* b = static_cast<char*>(state);
+  View v;
+  v.hdr = reinterpret_cast<Hdr*>(b + L.hdr);
+  v.rho = reinterpret_cast<double*>(b + L.rho);
+  v.x0 = reinterpret_cast<float*>(b + L.x0);
+  v.g = reinterpret_cast<float*>(b + L.g);
+  v.d = reinterpret_cast<float*>(b + L.d);
+  v.gt = reinterpret_cast<float*>(b + L.gt);
+  v.S = reinterpret_cast<float*>(b + L.S);
+  v.Y = reinterpret_cast<float*>(b + L.Y);
+  v.ft = reinterpret_cast<double*>(b + L.ft);
+  v.active = reinterpret_cast<int*>(b + L.active);
+  v.counter = reinterpret_cast<int*>(b + L.counter);
+  return v;
+}
+
+constexpr int kThreads = 256;
+
+// Sum over the block in a fixed order; every thread receives the result.
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double dot(const float* a, const float* b, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += (double)a[i] * (double)b[i];
+  return block_sum(s, red);
+}
+
+__device__ double cubic_min(double a, double fa, double ga, double b, double fb, double gb) {
+  const double lo = fmin(a, b), hi = fmax(a, b), w = hi - lo;
+  const double d1 = ga + gb - 3.0 * (fa - fb) / (a - b);
+  const double disc = d1 * d1 - ga * gb;
+  if (disc >= 0.0 && w > 0.0) {
+    const double d2 = copysign(sqrt(disc), b - a);
+    const double den = gb - ga + 2.0 * d2;
+    if (den != 0.0) {
+      const double t = b - (b - a) * (gb + d2 - d1) / den;
+      if (isfinite(t)) return fmin(fmax(t, lo + 0.1 * w), hi - 0.1 * w);
+    }
+  }
+  return 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_init(int P, LbfgsLayout L, void* state,
+                                                         double* loss_out) {
+  View v = view(L, state);
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= P) return;
+  Hdr& h = v.hdr[p];
+  h.f = v.ft[p];
+  h.count = 0;
+  h.head = 0;
+  h.iter = 0;
+  h.status = 0;
+  h.phase = 0;
+  h.n_eval = 0;
+  v.active[p] = 0;
+  if (loss_out) loss_out[p] = h.f;
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_begin(LbfgsLayout L, void* state,
+                                                          float* __restrict__ alpha,
+                                                          int max_evals) {
+  __shared__ double red[kThreads];
+  __shared__ double coef[32];
+  View v = view(L, state);
+  const int p = blockIdx.x, n = L.n, m = L.m, tid = threadIdx.x;
+  if (p == 0)
+    for (int i = tid; i <= max_evals; i += kThreads) v.counter[i] = 0;
+  Hdr& h = v.hdr[p];
+  if (h.status != 0) {
+    if (tid == 0) v.active[p] = 0;
+    return;
+  }
+  const float* g = v.g + (size_t)p * n;
+  float* q = v.d + (size_t)p * n;
+  float* x0 = v.x0 + (size_t)p * n;
+  float* a = alpha + (size_t)p * n;
+  const size_t hb = (size_t)p * m;
+  for (int i = tid; i < n; i += kThreads) q[i] = g[i];
+  __syncthreads();
+  const int count = h.count, head = h.head;
+  // two-loop recursion, newest pair first
+  for (int k = count - 1; k >= 0; --k) {
+    const int slot = (head + k) % m;
+    const float* s = v.S + (hb + slot) * n;
+    const float* y = v.Y + (hb + slot) * n;
+    const double ak = v.rho[hb + slot] * dot(s, q, n, red);
+    if (tid == 0) coef[k] = ak;
+    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] - ak * (double)y[i]);
+    __syncthreads();
+  }
+  if (count > 0) {
+    const int last = (head + count - 1) % m;
+    const float* s = v.S + (hb + last) * n;
+    const float* y = v.Y + (hb + last) * n;
+    const double gam = dot(s, y, n, red) / dot(y, y, n, red);
+    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] * gam);
+    __syncthreads();
+  }
+  for (int k = 0; k < count; ++k) {
+    const int slot = (head + k) % m;
+    const float* s = v.S + (hb + slot) * n;
+    const float* y = v.Y + (hb + slot) * n;
+    const double beta = v.rho[hb + slot] * dot(y, q, n, red);
+    const double ak = coef[k];
+    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] + (ak - beta) * (double)s[i]);
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += kThreads) q[i] = -q[i];
+  __syncthreads();
+  double dphi0 = dot(g, q, n, red);
+  bool reset = !(dphi0 < 0.0);
+  if (reset) {          // not a descent direction: restart from steepest descent
+    for (int i = tid; i < n; i += kThreads) q[i] = -g[i];
+    __syncthreads();
+    dphi0 = -dot(g, g, n, red);
+  }
+  double gl = 0.0;
+  for (int i = tid; i < n; i += kThreads) gl = fmax(gl, fabs((double)g[i]));
+  const double gmax = block_max(gl, red);
+  if (gmax == 0.0) {
+    if (tid == 0) {
+      h.status = 1;
+      v.active[p] = 0;
+    }
+    return;
+  }
+  const int cnt = reset ? 0 : count;
+  const double t0 = (cnt == 0) ? fmin(1.0, 1.0 / gmax) : 1.0;
+  for (int i = tid; i < n; i += kThreads) {
+    x0[i] = a[i];
+    a[i] = (float)((double)a[i] + t0 * (double)q[i]);
+  }
+  if (tid == 0) {
+    if (reset) {
+      h.count = 0;
+      h.head = 0;
+    }
+    h.f0 = h.f;
+    h.dphi0 = dphi0;
+    h.t = t0;
+    h.t_prev = 0.0;
+    h.f_prev = h.f;
+    h.g_prev = dphi0;
+    h.phase = 0;
+    h.first = 1;
+    h.n_eval = 0;
+    v.active[p] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* state,
+                                                           float* __restrict__ alpha, int eval,
+                                                           double c1, double c2, int max_evals,
+                                                           double ftol) {
+  __shared__ double red[kThreads];
+  __shared__ int action;          // 0 accept, 1 next trial, 2 failed
+  __shared__ double t_next;
+  View v = view(L, state);
+  const int p = blockIdx.x, n = L.n, m = L.m, tid = threadIdx.x;
+  if (!v.active[p]) return;
+  Hdr& h = v.hdr[p];
+  const float* d = v.d + (size_t)p * n;
+  const float* gt = v.gt + (size_t)p * n;
+  float* g = v.g + (size_t)p * n;
+  const float* x0 = v.x0 + (size_t)p * n;
+  float* a = alpha + (size_t)p * n;
+  const double ft = v.ft[p];
+  const double dt = dot(gt, d, n, red);
+  if (tid == 0) {
+    const double t = h.t, f0 = h.f0, dphi0 = h.dphi0;
+    const bool armijo_fail = !isfinite(ft) || ft > f0 + c1 * t * dphi0;
+    int act = 1;
+    double tn = t;
+    h.n_eval += 1;
+    if (h.phase == 0) {
+      if (armijo_fail || (!h.first && ft >= h.f_prev)) {
+        h.lo = h.t_prev; h.flo = h.f_prev; h.glo = h.g_prev;
+        h.hi = t; h.fhi = ft; h.ghi = dt;
+        h.phase = 1;
+        tn = cubic_min(h.lo, h.flo, h.glo, h.hi, h.fhi, h.ghi);
+      } else if (fabs(dt) <= -c2 * dphi0) {
+        act = 0;
+      } else if (dt >= 0.0) {
+        h.lo = t; h.flo = ft; h.glo = dt;
+        h.hi = h.t_prev; h.fhi = h.f_prev; h.ghi = h.g_prev;
+        h.phase = 1;
+        tn = cubic_min(h.lo, h.flo, h.glo, h.hi, h.fhi, h.ghi);
+      } else {
+        h.t_prev = t; h.f_prev = ft; h.g_prev = dt;
+        h.first = 0;
+        tn = 2.0 * t;
+      }
+    } else {
+      if (armijo_fail || ft >= h.flo) {
+        h.hi = t; h.fhi = ft; h.ghi = dt;
+      } else {
+        if (fabs(dt) <= -c2 * dphi0) {
+          act = 0;
+        } else {
+          if (dt * (h.hi - h.lo) >= 0.0) {
+            h.hi = h.lo; h.fhi = h.flo; h.ghi = h.glo;
+          }
+          h.lo = t; h.flo = ft; h.glo = dt;
+        }
+      }
+      if (act) tn = cubic_min(h.lo, h.flo, h.glo, h.hi, h.fhi, h.ghi);
+    }
+    if (act == 1 && h.n_eval >= max_evals) act = 2;
+    action = act;
+    t_next = tn;
+  }
+  __syncthreads();
+  if (action == 0) {
+    // accepted: history update with s = t d, y = g_new - g.  The header is
+    // read by every thread before the reductions' barriers; thread 0 writes
+    // it only after them.
+    const double t = h.t;
+    const int count = h.count, head = h.head;
+    double sy = 0.0, yy = 0.0;
+    for (int i = tid; i < n; i += kThreads) {
+      const double si = (double)(float)(t * (double)d[i]);
+      const double yi = (double)gt[i] - (double)g[i];
+      sy += si * yi;
+      yy += yi * yi;
+    }
+    sy = block_sum(sy, red);
+    yy = block_sum(yy, red);
+    const bool store = sy > 1e-12 * yy;
+    const int slot = (count < m) ? (head + count) % m : head;
+    const size_t hb = (size_t)p * m;
+    float* S = v.S + (hb + slot) * n;
+    float* Y = v.Y + (hb + slot) * n;
+    for (int i = tid; i < n; i += kThreads) {
+      if (store) {
+        S[i] = (float)(t * (double)d[i]);
+        Y[i] = gt[i] - g[i];
+      }
+      g[i] = gt[i];
+    }
+    if (tid == 0) {
+      if (store) {
+        v.rho[hb + slot] = 1.0 / sy;
+        if (count < m) h.count = count + 1; else h.head = (head + 1) % m;
+      }
+      const double df = h.f - ft;
+      h.f = ft;
+      h.iter += 1;
+      if (ftol > 0.0 && df <= ftol * fmax(fabs(ft), 1e-300)) h.status = 1;
+      v.active[p] = 0;
+    }
+  } else if (action == 1) {
+    const double tn = t_next;
+    for (int i = tid; i < n; i += kThreads) a[i] = (float)((double)x0[i] + tn * (double)d[i]);
+    if (tid == 0) {
+      h.t = tn;
+      atomicAdd(v.counter + eval, 1);
+    }
+  } else {
+    // line search failed: keep the starting point and stop this patch
+    for (int i = tid; i < n; i += kThreads) a[i] = x0[i];
+    if (tid == 0) {
+      h.status = 2;
+      v.active[p] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_finish(int P, LbfgsLayout L, void* state,
+                                                           double* loss_out, int* status_out) {
+  View v = view(L, state);
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= P) return;
+  if (loss_out) loss_out[p] = v.hdr[p].f;
+  if (status_out) status_out[p] = v.hdr[p].status;
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+LbfgsLayout lbfgs_layout(const Dims& d, int m, int max_evals) {
+  LbfgsLayout L;
+  L.m = m;
+  L.n = d.J * d.M;
+  const size_t P = d.P, n = L.n;
+  size_t o = 0;
+  L.hdr = o;     o = a256(o + P * sizeof(Hdr));
+  L.rho = o;     o = a256(o + P * m * sizeof(double));
+  L.x0 = o;      o = a256(o + P * n * sizeof(float));
+  L.g = o;       o = a256(o + P * n * sizeof(float));
+  L.d = o;       o = a256(o + P * n * sizeof(float));
+  L.gt = o;      o = a256(o + P * n * sizeof(float));
+  L.S = o;       o = a256(o + P * m * n * sizeof(float));
+  L.Y = o;       o = a256(o + P * m * n * sizeof(float));
+  L.ft = o;      o = a256(o + P * sizeof(double));
+  L.active = o;  o = a256(o + P * sizeof(int));
+  L.counter = o; o = a256(o + (size_t)(max_evals + 1) * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+hipError_t launch_lbfgs_init(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_init, dim3((d.P + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     d.P, L, state, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_begin(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                              int max_evals, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_begin, dim3(d.P), dim3(kThreads), 0, s, L, state, alpha, max_evals);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_search(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                               int eval, double c1, double c2, int max_evals, double ftol,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_search, dim3(d.P), dim3(kThreads), 0, s, L, state, alpha, eval, c1,
+                     c2, max_evals, ftol);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_finish(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
+                               int* status_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_finish, dim3((d.P + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     d.P, L, state, loss_out, status_out);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

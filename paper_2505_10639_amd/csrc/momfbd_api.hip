@@ -37,6 +37,7 @@ struct momfbd_plan_s {
   float* ZtT = nullptr;    // [C][32*32][Mp] the same, mode index fastest, zero padded
   int Mp = 0;              // M rounded up to a multiple of 16
   float* thetat = nullptr; // [C][32][32]   diversity in turns
+  int* hflag = nullptr;    // pinned host word for the solver's "still searching" count
 };
 
 namespace {
@@ -227,6 +228,7 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
       for (int px = 0; px < kBandPix; ++px)
         hZT[((size_t)c * kBandPix + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * kBandPix + px];
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
+  if (hipHostMalloc(&pl->hflag, sizeof(int)) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->Zt, hZ.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
@@ -254,6 +256,7 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   if (plan->Zt) (void)hipFree(plan->Zt);
   if (plan->thetat) (void)hipFree(plan->thetat);
   if (plan->ZtT) (void)hipFree(plan->ZtT);
+  if (plan->hflag) (void)hipHostFree(plan->hflag);
   delete plan;
   return MOMFBD_OK;
 }
@@ -305,15 +308,15 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward64(plan->d, plan->ct, plan->Ab, w.phi, psf,
+    e = launch_forward64(plan->d, plan->ct, nullptr, plan->Ab, w.phi, psf,
                          otf ? static_cast<float2*>(otf) : w.S, s);
   }
   return to_status(e);
 }
 
 static int run_object(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
-                      float gamma_scalar, const float* weights, double* loss, void* ws,
-                      hipStream_t s, Workspace* wout) {
+                      float gamma_scalar, const float* weights, const int* active, double* loss,
+                      void* ws, hipStream_t s, Workspace* wout) {
   const Workspace w = carve_workspace(plan->d, ws);
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
   hipError_t e;
@@ -323,13 +326,33 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward64(plan->d, plan->ct, plan->Ab, w.phi, nullptr, w.S, s);
+    e = launch_forward64(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_OBJECT, s);
-    e = launch_object64(plan->d, plan->ct, la, w.S, w.O, loss, s);
+    e = launch_object64(plan->d, plan->ct, la, active, w.S, w.O, loss, s);
   }
   *wout = w;
+  return to_status(e);
+}
+
+// Loss and (if grad) gradient of the patches selected by `active` (all when null).
+static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                         float gamma_scalar, const float* weights, const int* active,
+                         double* loss, float* grad, void* ws, hipStream_t s) {
+  Workspace w;
+  int st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, active, loss, ws, s, &w);
+  if (st || !grad) return st;
+  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
+  hipError_t e;
+  {
+    ProfScope ps(plan, KK_ADJOINT, s);
+    e = launch_adjoint64(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(plan, KK_GRAD, s);
+    e = launch_grad(plan->d, plan->Zt, w.gphi, grad, s);
+  }
   return to_status(e);
 }
 
@@ -340,21 +363,8 @@ int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const 
   if (st) return st;
   if (!alpha || !D || !loss) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
-  hipStream_t s = (hipStream_t)stream;
-  Workspace w;
-  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, loss, ws, s, &w);
-  if (st || !grad) return st;
-  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
-  hipError_t e;
-  {
-    ProfScope ps(plan, KK_ADJOINT, s);
-    e = launch_adjoint64(plan->d, plan->ct, la, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
-  }
-  if (e == hipSuccess) {
-    ProfScope ps(plan, KK_GRAD, s);
-    e = launch_grad(plan->d, plan->Zt, w.gphi, grad, s);
-  }
-  return to_status(e);
+  return run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws,
+                       (hipStream_t)stream);
 }
 
 int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
@@ -368,10 +378,73 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
   Workspace w;
   // the per-patch loss is produced on the way; it lands in the gphi scratch
   double* scratch_loss = reinterpret_cast<double*>(carve_workspace(plan->d, ws).gphi);
-  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, scratch_loss, ws, s, &w);
+  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, scratch_loss, ws, s, &w);
   if (st) return st;
   ProfScope ps(plan, KK_OBJIMG, s);
   return to_status(launch_objimg64(plan->d, w.O, obj, s));
+}
+
+}  // extern "C"
+
+static bool lbfgs_params_ok(const momfbd_lbfgs_params* pr) {
+  return pr && pr->m >= 1 && pr->m <= 32 && pr->max_evals >= 1 && pr->max_evals <= 1000 &&
+         pr->c1 > 0.0 && pr->c1 < pr->c2 && pr->c2 < 1.0 && pr->ftol >= 0.0;
+}
+
+extern "C" {
+
+int momfbd_lbfgs_state_size(momfbd_plan plan, const momfbd_lbfgs_params* params, size_t* bytes) {
+  if (!plan || !bytes || !lbfgs_params_ok(params)) return MOMFBD_EINVAL;
+  *bytes = lbfgs_layout(plan->d, params->m, params->max_evals).total;
+  return MOMFBD_OK;
+}
+
+int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                      const float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                      const float* weights, double* loss, void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!lbfgs_params_ok(params) || !state || !alpha || !D) return MOMFBD_EINVAL;
+  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  char* b = static_cast<char*>(state);
+  st = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr,
+                     reinterpret_cast<double*>(b + L.ft), reinterpret_cast<float*>(b + L.g), ws, s);
+  if (st) return st;
+  return to_status(launch_lbfgs_init(plan->d, L, state, loss, s));
+}
+
+int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                      float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                      const float* weights, double* loss, int* status, void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!lbfgs_params_ok(params) || !state || !alpha || !D) return MOMFBD_EINVAL;
+  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  char* b = static_cast<char*>(state);
+  const int* active = reinterpret_cast<const int*>(b + L.active);
+  const int* counter = reinterpret_cast<const int*>(b + L.counter);
+  hipError_t e = launch_lbfgs_begin(plan->d, L, state, alpha, params->max_evals, s);
+  for (int ev = 0; e == hipSuccess && ev < params->max_evals; ++ev) {
+    st = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, active,
+                       reinterpret_cast<double*>(b + L.ft), reinterpret_cast<float*>(b + L.gt), ws,
+                       s);
+    if (st) return st;
+    e = launch_lbfgs_search(plan->d, L, state, alpha, ev, params->c1, params->c2,
+                            params->max_evals, params->ftol, s);
+    if (e != hipSuccess) break;
+    // how many patches still search: decides whether another evaluation is needed
+    e = hipMemcpyAsync(plan->hflag, counter + ev, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && *plan->hflag == 0) break;
+  }
+  if (e == hipSuccess) e = launch_lbfgs_finish(plan->d, L, state, loss, status, s);
+  return to_status(e);
 }
 
 }  // extern "C"

@@ -124,3 +124,31 @@ class Plan:
                           device=self.device)
         _lib.momfbd_object_estimate(self.handle, alpha, D, g_arr, g_sc, weights, obj, self.ws)
         return obj
+
+
+class Solver:
+    """Per-patch L-BFGS on a plan (momfbd_lbfgs_init / momfbd_lbfgs_step).
+
+    alpha (device float32 [P][J][M]) is updated in place by step().
+    """
+
+    def __init__(self, plan: Plan, alpha, D, gamma=1e-3, weights=None, m=10, max_evals=20,
+                 c1=1e-4, c2=0.9, ftol=0.0):
+        self.plan = plan
+        self.alpha = plan._alpha(alpha)
+        self.D = plan._D(D)
+        self.gamma_arr, self.gamma_sc = plan._gamma(gamma)
+        self.weights = plan._weights(weights)
+        self.params = _lib.lbfgs_params(m, max_evals, c1, c2, ftol)
+        nbytes = _lib.momfbd_lbfgs_state_size(plan.handle, self.params)
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=plan.device)
+        self.loss = torch.empty(plan.P, dtype=torch.float64, device=plan.device)
+        self.status = torch.zeros(plan.P, dtype=torch.int32, device=plan.device)
+        _lib.momfbd_lbfgs_init(plan.handle, self.params, self.state, self.alpha, self.D,
+                               self.gamma_arr, self.gamma_sc, self.weights, self.loss, plan.ws)
+
+    def step(self):
+        _lib.momfbd_lbfgs_step(self.plan.handle, self.params, self.state, self.alpha, self.D,
+                               self.gamma_arr, self.gamma_sc, self.weights, self.loss,
+                               self.status, self.plan.ws)
+        return self.loss, self.status
