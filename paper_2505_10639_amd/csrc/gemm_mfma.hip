@@ -30,7 +30,7 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
 // quarter [w K/4, (w+1) K/4) of k = c*1024 + px; the partial sums are added
 // in fixed order (wave 0 + 1 + 2 + 3) through LDS.
 template <int MT>
-__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M,
+__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, int lbp,
                                                    const float* __restrict__ Zt,
                                                    const float* __restrict__ gphi,
                                                    float* __restrict__ grad) {
@@ -44,19 +44,33 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M,
   floatx4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int Kq = C * kBandPix / 4;
-  for (int kk = wave * Kq; kk < (wave + 1) * Kq; kk += 16) {
-    const int c = kk / kBandPix, px = kk % kBandPix + 4 * g;
-    const floatx4 a4 = rok ? *reinterpret_cast<const floatx4*>(
-                                 gphi + (((size_t)p * C + c) * J + j) * kBandPix + px)
-                           : floatx4{0.f, 0.f, 0.f, 0.f};
+  const int bp = 1 << lbp;            // band pixels per channel
+  const int Kq = C * bp / 4;
+  const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
+  // operands of chunk kk: a from gphi row r, b[t] from mode rows t*16 + i16;
+  // the next chunk's operands are loaded before the current chunk's MFMAs
+  auto load = [&](int kk, floatx4& a4, floatx4 (&b4)[MT]) {
+    const int c = kk >> lbp, px = (kk & (bp - 1)) + 4 * g;
+    a4 = rok ? *reinterpret_cast<const floatx4*>(gphi + ((((size_t)p * C + c) * J + j) << lbp) + px)
+             : floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int m = t * 16 + i16;
-      const floatx4 b4 = (m < M) ? *reinterpret_cast<const floatx4*>(
-                                       Zt + ((size_t)c * M + m) * kBandPix + px)
-                                 : floatx4{0.f, 0.f, 0.f, 0.f};
-      acc[t] = mfma4(a4, b4, acc[t]);
+      b4[t] = (m < M) ? *reinterpret_cast<const floatx4*>(Zt + (((size_t)c * M + m) << lbp) + px)
+                      : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  floatx4 a_cur, b_cur[MT];
+  load(k_begin, a_cur, b_cur);
+  for (int kk = k_begin; kk < k_end; kk += 16) {
+    floatx4 a_nxt, b_nxt[MT];
+    if (kk + 16 < k_end) load(kk + 16, a_nxt, b_nxt);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = mfma4(a_cur, b_cur[t], acc[t]);
+    if (kk + 16 < k_end) {
+      a_cur = a_nxt;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) b_cur[t] = b_nxt[t];
     }
   }
   if (wave > 0) {
@@ -82,10 +96,11 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M,
 }
 
 // phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
-// Block = 4 waves: 64 pixels (a 16-row tile per wave) x 64 columns (4 tiles).
-// The 64 coefficient rows of the block (contiguous in alpha) are staged in
-// LDS with the mode index padded to Mp, so B operands are float4 LDS reads.
-__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp,
+// Block = 4 waves, (channel, 64 columns, a quarter of the 1024 band pixels):
+// the block's 64 coefficient rows (contiguous in alpha) are staged once in
+// LDS with the mode index padded to Mp; each wave then walks 4 tiles of 16
+// pixels x 64 columns, taking its B operands as float4 LDS reads.
+__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp, int lbp,
                                                     const float* __restrict__ ZtT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
@@ -94,36 +109,40 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
   const int ldm = Mp + 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
-  const int c = blockIdx.x / (kBandPix / 64);
-  const int px0 = (blockIdx.x % (kBandPix / 64)) * 64 + wave * 16;
+  const int c = blockIdx.x >> 2, quarter = blockIdx.x & 3;
   const int col0 = blockIdx.y * 64;
   const int ncol = min(64, R - col0);
   const float* src = alpha + (size_t)col0 * M;
-  for (int e = threadIdx.x; e < 64 * Mp; e += 256) {
-    const int r = e / Mp, m = e % Mp;
-    al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
-  }
+  for (int r = wave; r < 64; r += 4)
+    for (int m = lane; m < Mp; m += 64)
+      al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
   __syncthreads();
-  floatx4 acc[4];
+  const int bp = 1 << lbp;
+  const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
+  for (int tile = 0; tile < ntile; ++tile) {
+    const int px0 = quarter * (bp / 4) + (tile * 4 + wave) * 16;
+    floatx4 acc[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const float* arow = ZtT + ((size_t)c * kBandPix + px0 + i16) * Mp;
-  for (int kk = 0; kk < Mp; kk += 16) {
-    const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
+    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* arow = ZtT + ((size_t)c * bp + px0 + i16) * Mp;
+    for (int kk = 0; kk < Mp; kk += 16) {
+      const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const floatx4 b4 =
+            *reinterpret_cast<const floatx4*>(al + (t * 16 + i16) * ldm + kk + 4 * g);
+        acc[t] = mfma4(a4, b4, acc[t]);
+      }
+    }
+    const floatx4 th = *reinterpret_cast<const floatx4*>(theta + (size_t)c * bp + px0 + 4 * g);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const floatx4 b4 = *reinterpret_cast<const floatx4*>(al + (t * 16 + i16) * ldm + kk + 4 * g);
-      acc[t] = mfma4(a4, b4, acc[t]);
+      const int col = col0 + t * 16 + i16;
+      if (col >= R) continue;
+      const int p = col / J, j = col % J;
+      *reinterpret_cast<floatx4*>(phi + ((((size_t)p * C + c) * J + j) << lbp) + px0 + 4 * g) =
+          acc[t] + th;
     }
-  }
-  const floatx4 th = *reinterpret_cast<const floatx4*>(theta + c * kBandPix + px0 + 4 * g);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = col0 + t * 16 + i16;
-    if (col >= R) continue;
-    const int p = col / J, j = col % J;
-    *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + c) * J + j) * kBandPix + px0 + 4 * g) =
-        acc[t] + th;
   }
 }
 
@@ -131,7 +150,8 @@ template <int MT>
 void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
                    hipStream_t s) {
   const int R = d.P * d.J;
-  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M,
+  const int lbp = d.N == 64 ? 10 : 12;
+  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M, lbp,
                      Zt, gphi, grad);
 }
 
@@ -155,14 +175,15 @@ hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float*
 hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
                         const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J;
-  dim3 grid(d.C * (kBandPix / 64), (R + 63) / 64);
+  dim3 grid(d.C * 4, (R + 63) / 64);
   const size_t lds = (size_t)64 * (Mp + 4) * sizeof(float);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, ZtT, thetat,
+  const int lbp = d.N == 64 ? 10 : 12;
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, lbp, ZtT, thetat,
                      alpha, phi);
   return hipGetLastError();
 }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "ops128.h"
 #include "ops64.h"
 
 using namespace mfbd;
@@ -230,6 +231,117 @@ void emu_unit_fused(const float* A, const float* ph, float kappa, const float* G
       gphi[(2 * i + b) * 32 + q] = pk.x * gp.y - pk.y * gp.x;
     }
   }
+}
+
+// ------------------------------------------------------------- N = 128
+namespace e128 {
+using namespace mfbd::n128;
+struct WG {
+  float2 T[n128::LDS_MAIN];
+  float2 Taux[n128::LDS_AUX];
+};
+constexpr int L = 256;
+
+// band pupil [64][64] (A, turns) -> p in row-parity layout; Pk = P at the band
+// rows of the column-pair lanes' parity (for dL/dphi)
+void pupil_to_p(WG& w, const float* A, const float* ph, float2 (&p)[L][64]) {
+  for (int l = 0; l < L; ++l) {
+    const int q = l >> 2, r = l & 3;
+    float2 z[32];
+    for (int n = 0; n < 32; ++n) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int h = 0; h < 2; ++h) {
+        const int nn = n + 32 * h;
+        const double ang = 2.0 * M_PI * ((double)ph[nn * 64 + q] + (32.0 + nn) * r / 128.0);
+        const float a = A[nn * 64 + q];
+        acc = cadd(acc, make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang)));
+      }
+      z[n] = acc;
+    }
+    n128::op1_cols(z, w.T, l);
+  }
+  for (int l = 0; l < L; ++l) n128::op1_rows(w.T, l, p[l]);
+}
+
+void r2c(WG& w, const float (&s)[L][64], float2 (&X)[128][64], float2 (&x64)[128]) {
+  static float keep[L][32], send[L][32], other[L][32];
+  for (int l = 0; l < L; ++l) n128::op2_rows_fold(s[l], keep[l], send[l], l);
+  float* Xf = reinterpret_cast<float*>(w.T);
+  for (int l = 0; l < L; ++l) n128::xput(send[l], Xf, l);
+  for (int l = 0; l < L; ++l) n128::xget(Xf, l, other[l]);
+  for (int l = 0; l < L; ++l) n128::op2_rows_finish(keep[l], other[l], w.T, l);
+  for (int l = 0; l < 128; ++l) n128::op2_cols(w.T, w.Taux, l, X[l]);
+  for (int l = 0; l < 128; ++l) x64[l] = w.Taux[l];
+}
+
+void c2r(WG& w, float2 (&X)[128][64], const float2 (&x64)[128], float (&g)[L][64]) {
+  static float keep[L][32], send[L][32], other[L][32];
+  for (int l = 0; l < 128; ++l) w.Taux[l] = x64[l];
+  for (int l = 0; l < 128; ++l) n128::op3_cols(X[l], w.Taux, w.T, l);
+  for (int l = 0; l < L; ++l) n128::op3_rows_compute(w.T, l, keep[l], send[l]);
+  float* Xf = reinterpret_cast<float*>(w.T);
+  for (int l = 0; l < L; ++l) n128::xput(send[l], Xf, l);
+  for (int l = 0; l < L; ++l) n128::xget(Xf, l, other[l]);
+  for (int l = 0; l < L; ++l) n128::op3_rows_finish(keep[l], other[l], l, g[l]);
+}
+
+void to_band(WG& w, float2 (&H)[L][64], float2 (&GP)[128][32]) {
+  static float2 keep[L][32], send[L][32], other[L][32];
+  for (int l = 0; l < L; ++l) n128::op4_rows_fft(H[l], keep[l], send[l], l);
+  for (int l = 0; l < L; ++l) n128::xput(send[l], w.T, l);
+  for (int l = 0; l < L; ++l) n128::xget(w.T, l, other[l]);
+  for (int l = 0; l < L; ++l) n128::op4_rows_finish(keep[l], other[l], w.T, l);
+  for (int l = 0; l < 128; ++l) n128::op4_cols(w.T, l, GP[l]);
+}
+}  // namespace e128
+
+void emu128_pupil_ifft(const float* A, const float* ph, float* p) {
+  static e128::WG w;
+  static float2 pp[256][64];
+  e128::pupil_to_p(w, A, ph, pp);
+  float2* o = reinterpret_cast<float2*>(p);
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) o[(l >> 1) * 128 + 2 * m + (l & 1)] = pp[l][m];
+}
+
+void emu128_r2c(const float* img, float* half) {
+  static e128::WG w;
+  static float s[256][64];
+  static float2 X[128][64], x64[128];
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) s[l][m] = img[(l >> 1) * 128 + 2 * m + (l & 1)];
+  e128::r2c(w, s, X, x64);
+  float2* h = reinterpret_cast<float2*>(half);
+  for (int l = 0; l < 128; ++l) {
+    for (int m = 0; m < 64; ++m) h[n128::sl_index(l, m)] = X[l][m];
+    h[n128::sl_index64(l)] = x64[l];
+  }
+}
+
+void emu128_c2r(const float* half, float* img) {
+  static e128::WG w;
+  static float g[256][64];
+  static float2 X[128][64], x64[128];
+  const float2* h = reinterpret_cast<const float2*>(half);
+  for (int l = 0; l < 128; ++l) {
+    for (int m = 0; m < 64; ++m) X[l][m] = h[n128::sl_index(l, m)];
+    x64[l] = h[n128::sl_index64(l)];
+  }
+  e128::c2r(w, X, x64, g);
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) img[(l >> 1) * 128 + 2 * m + (l & 1)] = g[l][m];
+}
+
+void emu128_fft_to_band(const float* hc, float* band) {
+  static e128::WG w;
+  static float2 H[256][64], GP[128][32];
+  const float2* h = reinterpret_cast<const float2*>(hc);
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) H[l][m] = h[(l >> 1) * 128 + 2 * m + (l & 1)];
+  e128::to_band(w, H, GP);
+  float2* o = reinterpret_cast<float2*>(band);
+  for (int l = 0; l < 128; ++l)
+    for (int i = 0; i < 32; ++i) o[(2 * i + (l & 1)) * 64 + (l >> 1)] = GP[l][i];
 }
 
 }  // extern "C"

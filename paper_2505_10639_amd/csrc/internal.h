@@ -15,6 +15,9 @@ constexpr int kBandPix = kBand * kBand;
 
 struct Dims {
   int N, P, C, K, J, M;
+  int band() const { return N / 2; }                 // pupil band width
+  int bandpix() const { return (N / 2) * (N / 2); }  // pixels of the band
+  int half() const { return N * (N / 2 + 1); }       // complex values of a half spectrum
 };
 
 // Channel tables passed by value to kernels.
@@ -35,32 +38,52 @@ struct LossArgs {
 
 // Workspace carve-up.
 struct Workspace {
-  float* phi;              // [P][C][J][32][32]  phase in turns on the pupil band
+  float* phi;              // [P][C][J][N/2][N/2]  phase in turns on the pupil band
   float2* S;               // [P][C][J][N][N/2+1] OTF half spectra
   float2* O;               // [P][K][N][N/2+1]    object spectra
-  float* gphi;             // [P][C][J][32][32]  dL/dphi (rad^-1) on the band
+  float* gphi;             // [P][C][J][N/2][N/2]  dL/dphi (rad^-1) on the band
+  double* loss_pk;         // [P][K] per-object loss terms
 };
 
 size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);
 
-// Launchers (return hipSuccess or the launch error).
+// Launchers (return hipSuccess or the launch error); dispatch on d.N.
 hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
                         const float* thetat, float* phi, hipStream_t s);
 // `active` (nullable, [P]) restricts the unit kernels to patches with a
 // nonzero entry; the others are neither computed nor written.
+hipError_t launch_forward(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                          const float* phi, float* psf, float2* S, hipStream_t s);
+hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                         const float2* S, float2* O, double* loss_pk, double* loss,
+                         hipStream_t s);
+hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                          const float* Ab, const float* phi, const float2* S, const float2* O,
+                          float* gphi, hipStream_t s);
+hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
+                       hipStream_t s);
+hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
+                          const float* apod, float2* D, hipStream_t s);
+hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s);
+
+// per-size implementations
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                             const float* phi, float* psf, float2* S, hipStream_t s);
-hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
-                           const float2* S, float2* O, double* loss, hipStream_t s);
 hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la,
                             const int* active, const float* Ab, const float* phi, const float2* S,
                             const float2* O, float* gphi, hipStream_t s);
-hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
-                       hipStream_t s);
 hipError_t launch_prepare64(const Dims& d, const float* frames, int H, int W, int stride,
                             const float* apod, float2* D, hipStream_t s);
 hipError_t launch_objimg64(const Dims& d, const float2* O, float* obj, hipStream_t s);
+hipError_t launch_forward128(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                             const float* phi, float* psf, float2* S, hipStream_t s);
+hipError_t launch_adjoint128(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                             const int* active, const float* Ab, const float* phi, const float2* S,
+                             const float2* O, float* gphi, hipStream_t s);
+hipError_t launch_prepare128(const Dims& d, const float* frames, int H, int W, int stride,
+                             const float* apod, float2* D, hipStream_t s);
+hipError_t launch_objimg128(const Dims& d, const float2* O, float* obj, hipStream_t s);
 
 // L-BFGS (per-patch solver state lives in a caller-provided buffer)
 struct LbfgsLayout {

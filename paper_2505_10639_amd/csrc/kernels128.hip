@@ -1,0 +1,335 @@
+// Unit kernels of the MOMFBD hot path for 128x128 patches (gfx950).
+//
+// One workgroup of four wavefronts (256 lanes) per unit (patch, channel,
+// frame); the wave-level transforms are those of ops128.h.  The pupil band is
+// 64x64 (rows and columns [32,96) of the grid).  Same algebra as the 64x64
+// kernels: forward PSF/OTF, adjoint to dL/dphi, patch preparation, object
+// image.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "ops128.h"
+
+namespace mfbd {
+using namespace n128;
+
+namespace {
+
+constexpr int kUnitF2 = N * HC;        // 8320 float2 per half spectrum
+constexpr int kB = 64;                 // band width
+constexpr int kBP = kB * kB;           // band pixels
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void sync() { __syncthreads(); }
+
+__device__ __forceinline__ float2 expi_turns(float t) {
+  const float f = __builtin_amdgcn_fractf(t);
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+}
+
+// op1 column-pass input of lane (q, r): z[n] = y[n] + y[n+32] with
+// y[n] = P(32+n, 32+q) W128^{+(32+n) r}, P = A exp(2 pi i t) on the band; the
+// modulation is a phase ramp of (32+n) r / 128 turns.
+__device__ __forceinline__ void build_pupil(const float* __restrict__ A,
+                                            const float* __restrict__ ph, int lane,
+                                            float2 (&z)[32]) {
+  const int q = lane >> 2, r = lane & 3;
+#pragma unroll
+  for (int n = 0; n < 32; ++n) {
+    const int n1 = n + 32;
+    const float2 y0 = cscale(expi_turns(ph[n * kB + q] + (32 + n) * r * (1.0f / 128.0f)),
+                             A[n * kB + q]);
+    const float2 y1 = cscale(expi_turns(ph[n1 * kB + q] + (32 + n1) * r * (1.0f / 128.0f)),
+                             A[n1 * kB + q]);
+    z[n] = cadd(y0, y1);
+  }
+}
+
+// |.|^2 of the PSF amplitude, then the real forward transform; lanes < 128
+// end with S in spectral layout.
+__device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* psf_row_or_null,
+                                           float2* T, float2* Taux, int lane, float2 (&X)[64],
+                                           float2& x64) {
+  float s[64];
+#pragma unroll
+  for (int m = 0; m < 64; ++m) s[m] = kap * cabs2(p[m]);
+  if (psf_row_or_null) {
+    const int e = lane & 1;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) psf_row_or_null[2 * m + e] = s[m];
+  }
+  float keep[32], send[32], other[32];
+  op2_rows_fold(s, keep, send, lane);
+  xput(send, reinterpret_cast<float*>(T), lane);
+  sync();
+  xget(reinterpret_cast<const float*>(T), lane, other);
+  sync();
+  op2_rows_finish(keep, other, T, lane);
+  sync();
+  if (lane < 128) op2_cols(T, Taux, lane, X);
+  sync();
+  if (lane < 128) x64 = Taux[lane];
+}
+
+template <bool WANT_PSF>
+__global__ __launch_bounds__(kThreads) void k_forward128(int units, ChanTab ct, int C, int J,
+                                                         const int* __restrict__ active,
+                                                         const float* __restrict__ Ab,
+                                                         const float* __restrict__ phi,
+                                                         float* __restrict__ psf,
+                                                         float2* __restrict__ S) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  if (active && !active[u / (J * C)]) return;
+  const int lane = threadIdx.x;
+  const int c = (u / J) % C;
+  {
+    float2 z[32];
+    build_pupil(Ab + (size_t)c * kBP, phi + (size_t)u * kBP, lane, z);
+    op1_cols(z, T, lane);
+  }
+  sync();
+  float2 p[64];
+  op1_rows(T, lane, p);
+  sync();
+  float2 X[64], x64;
+  float* row = WANT_PSF ? psf + (size_t)u * N * N + (lane >> 1) * N : nullptr;
+  psf_to_otf(p, ct.kappa[c], row, T, Taux, lane, X, x64);
+  if (lane < 128) {
+    float2* out = S + (size_t)u * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) out[sl_index(lane, m)] = X[m];
+    out[sl_index64(lane)] = x64;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_adjoint128(int units, ChanTab ct, int C, int J,
+                                                         int K, LossArgs la,
+                                                         const int* __restrict__ active,
+                                                         const float* __restrict__ Ab,
+                                                         const float* __restrict__ phi,
+                                                         const float2* __restrict__ S,
+                                                         const float2* __restrict__ O,
+                                                         float* __restrict__ gphi) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  // XCD-aware order: consecutive units (frames of one patch-object) on one XCD
+  const int per = (units + kXcds - 1) / kXcds;
+  const int u = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (u >= units) return;
+  const int lane = threadIdx.x;
+  const int j = u % J;
+  const int c = (u / J) % C;
+  const int p = u / (J * C);
+  if (active && !active[p]) return;
+  const int k = ct.chan_obj[c];
+  const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
+
+  // G = -2 w conj(O)(D - O S) in spectral layout (lanes < 128)
+  float2 G[64];
+  if (lane < 128) {
+    const float2* Su = S + (size_t)u * kUnitF2;
+    const float2* Du = la.D + (size_t)u * kUnitF2;
+    const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) {
+      const int idx = sl_index(lane, m);
+      const float2 o = Ok[idx];
+      G[m] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+    }
+    const int idx = sl_index64(lane);
+    const float2 o = Ok[idx];
+    Taux[lane] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+  }
+  sync();
+  if (lane < 128) op3_cols(G, Taux, T, lane);
+  sync();
+  float g[64];
+  {
+    float keep[32], send[32], other[32];
+    op3_rows_compute(T, lane, keep, send);
+    sync();
+    xput(send, reinterpret_cast<float*>(T), lane);
+    sync();
+    xget(reinterpret_cast<const float*>(T), lane, other);
+    sync();
+    op3_rows_finish(keep, other, lane, g);
+  }
+  // recompute the PSF amplitude p and form H = 2 kappa g p
+  const float* Ac = Ab + (size_t)c * kBP;
+  const float* phu = phi + (size_t)u * kBP;
+  {
+    float2 z[32];
+    build_pupil(Ac, phu, lane, z);
+    op1_cols(z, T, lane);
+  }
+  sync();
+  float2 H[64];
+  op1_rows(T, lane, H);
+  const float k2 = 2.0f * ct.kappa[c];
+#pragma unroll
+  for (int m = 0; m < 64; ++m) H[m] = cscale(H[m], k2 * g[m]);
+  sync();
+  {
+    float2 keep[32], send[32], other[32];
+    op4_rows_fft(H, keep, send, lane);
+    xput(send, T, lane);
+    sync();
+    xget(T, lane, other);
+    sync();
+    op4_rows_finish(keep, other, T, lane);
+  }
+  sync();
+  if (lane < 128) {
+    float2 GP[32];
+    op4_cols(T, lane, GP);
+    const int b = lane & 1, q = lane >> 1;
+    float* gout = gphi + (size_t)u * kBP;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int n = 2 * i + b;
+      const float2 pk = cscale(expi_turns(phu[n * kB + q]), Ac[n * kB + q]);
+      gout[n * kB + q] = pk.x * GP[i].y - pk.y * GP[i].x;   // Im(conj(P) G_P)
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J, int H, int W,
+                                                         int stride, int nx,
+                                                         const float* __restrict__ frames,
+                                                         const float* __restrict__ apod,
+                                                         float2* __restrict__ D) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  __shared__ float red[kThreads];
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int lane = threadIdx.x;
+  const int j = u % J;
+  const int c = (u / J) % C;
+  const int p = u / (J * C);
+  const int y0 = (p / nx) * stride, x0 = (p % nx) * stride;
+  float* Tf = reinterpret_cast<float*>(T);
+  const float* src = frames + ((size_t)(c * J + j) * H + y0) * W + x0;
+  for (int e = lane; e < N * N; e += kThreads) {
+    const int r = e >> 7, x = e & 127;
+    Tf[r * 129 + x] = src[(size_t)r * W + x];
+  }
+  sync();
+  const int y = lane >> 1, e = lane & 1;
+  float s[64];
+  float sum = 0.f;
+#pragma unroll
+  for (int m = 0; m < 64; ++m) {
+    s[m] = Tf[y * 129 + 2 * m + e];
+    sum += s[m];
+  }
+  red[lane] = sum;
+  sync();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (lane < h) red[lane] += red[lane + h];
+    sync();
+  }
+  const float mean = red[0] * (1.0f / (N * N));
+  const float* wr = apod + y * N;
+#pragma unroll
+  for (int m = 0; m < 64; ++m) s[m] = wr[2 * m + e] * (s[m] - mean) + mean;
+  float2 X[64], x64;
+  {
+    float keep[32], send[32], other[32];
+    op2_rows_fold(s, keep, send, lane);
+    xput(send, Tf, lane);
+    sync();
+    xget(Tf, lane, other);
+    sync();
+    op2_rows_finish(keep, other, T, lane);
+  }
+  sync();
+  if (lane < 128) op2_cols(T, Taux, lane, X);
+  sync();
+  if (lane < 128) {
+    x64 = Taux[lane];
+    float2* out = D + (size_t)u * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) out[sl_index(lane, m)] = X[m];
+    out[sl_index64(lane)] = x64;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_objimg128(int items, const float2* __restrict__ O,
+                                                        float* __restrict__ obj) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int it = blockIdx.x;
+  if (it >= items) return;
+  const int lane = threadIdx.x;
+  const float2* Oi = O + (size_t)it * kUnitF2;
+  float2 X[64];
+  if (lane < 128) {
+#pragma unroll
+    for (int m = 0; m < 64; ++m) X[m] = Oi[sl_index(lane, m)];
+    Taux[lane] = Oi[sl_index64(lane)];
+  }
+  sync();
+  if (lane < 128) op3_cols(X, Taux, T, lane);
+  sync();
+  float g[64];
+  {
+    float keep[32], send[32], other[32];
+    op3_rows_compute(T, lane, keep, send);
+    sync();
+    xput(send, reinterpret_cast<float*>(T), lane);
+    sync();
+    xget(reinterpret_cast<const float*>(T), lane, other);
+    op3_rows_finish(keep, other, lane, g);
+  }
+  float* row = obj + (size_t)it * N * N + (lane >> 1) * N;
+  const int e = lane & 1;
+  const float inv = 1.0f / (N * N);
+#pragma unroll
+  for (int m = 0; m < 64; ++m) row[2 * m + e] = g[m] * inv;
+}
+
+}  // namespace
+
+hipError_t launch_forward128(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                             const float* phi, float* psf, float2* S, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  if (psf)
+    hipLaunchKernelGGL(k_forward128<true>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+                       active, Ab, phi, psf, S);
+  else
+    hipLaunchKernelGGL(k_forward128<false>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C,
+                       d.J, active, Ab, phi, psf, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint128(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                             const int* active, const float* Ab, const float* phi,
+                             const float2* S, const float2* O, float* gphi, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  const int per = (units + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_adjoint128, dim3(kXcds * per), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+                     d.K, la, active, Ab, phi, S, O, gphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare128(const Dims& d, const float* frames, int H, int W, int stride,
+                             const float* apod, float2* D, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  const int nx = (W - N) / stride + 1;
+  hipLaunchKernelGGL(k_prepare128, dim3(units), dim3(kThreads), 0, s, units, d.C, d.J, H, W,
+                     stride, nx, frames, apod, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_objimg128(const Dims& d, const float2* O, float* obj, hipStream_t s) {
+  const int items = d.P * d.K;
+  hipLaunchKernelGGL(k_objimg128, dim3(items), dim3(kThreads), 0, s, items, O, obj);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

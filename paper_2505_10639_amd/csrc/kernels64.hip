@@ -27,6 +27,17 @@ constexpr int kUnitF2 = N * HC;   // float2 elements per half spectrum (2112)
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remapping block b to unit (b mod 8) * per + b / 8 gives every XCD a
+// contiguous run of units, so the frames of one patch-object (which share the
+// object spectrum) meet in the same L2.  The grid has 8 * per blocks.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_unit(int per) {
+  const int b = blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+__host__ __device__ inline int xcd_per(int units) { return (units + kXcds - 1) / kXcds; }
+
 // exp(2 pi i t) for a phase t in turns.  The hardware sine/cosine take
 // turns directly; the argument is first reduced to [0,1).
 __device__ __forceinline__ float2 expi_turns(float t) {
@@ -102,94 +113,6 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
   out[sl_index32(lane)] = x32;
 }
 
-// One block per patch; loops over objects and pairs of adjacent half-spectrum
-// frequencies (16-byte loads).  One pass over D and S: N = sum w D conj(S),
-// Q = gamma + sum w |S|^2 and E = sum w |D|^2 are accumulated in FP64, where
-// the products of FP32 inputs are exact, so the loss term E - |N|^2/Q
-// (Eq. loss_momfbd at the Wiener object, equal to the residual form) keeps
-// full accuracy.  Units are read four at a time so that loads overlap.
-struct Acc2 {
-  double nr[2], ni[2], q[2], e[2];
-};
-
-__device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
-  const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
-  const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
-  a.nr[0] += w * (dx0 * sx0 + dy0 * sy0);
-  a.ni[0] += w * (dy0 * sx0 - dx0 * sy0);
-  a.q[0] += w * (sx0 * sx0 + sy0 * sy0);
-  a.e[0] += w * (dx0 * dx0 + dy0 * dy0);
-  a.nr[1] += w * (dx1 * sx1 + dy1 * sy1);
-  a.ni[1] += w * (dy1 * sx1 - dx1 * sy1);
-  a.q[1] += w * (sx1 * sx1 + sy1 * sy1);
-  a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
-}
-
-__global__ __launch_bounds__(256) void k_object64(int P, int C, int J, int K, ChanTab ct,
-                                                  LossArgs la, const int* __restrict__ active,
-                                                  const float2* __restrict__ S,
-                                                  float2* __restrict__ O,
-                                                  double* __restrict__ loss) {
-  __shared__ double red[256];
-  const int p = blockIdx.x;
-  if (active && !active[p]) return;
-  const int tid = threadIdx.x;
-  double acc = 0.0;
-  constexpr int kPairs = kUnitF2 / 2;
-  for (int k = 0; k < K; ++k) {
-    const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
-    for (int f2 = tid; f2 < kPairs; f2 += 256) {
-      const int f = 2 * f2;
-      Acc2 a;
-      for (int i = 0; i < 2; ++i) {
-        a.nr[i] = a.ni[i] = a.e[i] = 0.0;
-        a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
-      }
-      for (int ci = c0; ci < c1; ++ci) {
-        const int c = ct.obj_chans[ci];
-        const float4* Dc = reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
-        const float4* Sc = reinterpret_cast<const float4*>(S + ((size_t)(p * C + c) * J) * kUnitF2 + f);
-        const float* wc = la.weights ? la.weights + c * J : nullptr;
-        int j = 0;
-        for (; j + 4 <= J; j += 4) {
-          float4 d[4], s[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            d[u] = Dc[(size_t)(j + u) * (kUnitF2 / 2)];
-            s[u] = Sc[(size_t)(j + u) * (kUnitF2 / 2)];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
-        }
-        for (; j < J; ++j)
-          acc_unit(a, wc ? (double)wc[j] : 1.0, Dc[(size_t)j * (kUnitF2 / 2)],
-                   Sc[(size_t)j * (kUnitF2 / 2)]);
-      }
-      float4 o;
-      double part = 0.0;
-      {
-        const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
-        o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
-                        (float)(a.nr[1] * inv1), (float)(a.ni[1] * inv1));
-        const int kx0 = f % HC, kx1 = (f + 1) % HC;
-        const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
-        const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
-        part = h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
-               h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
-      }
-      reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
-      acc += part;
-    }
-  }
-  red[tid] = acc;
-  __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (tid < s2) red[tid] += red[tid + s2];
-    __syncthreads();
-  }
-  if (tid == 0) loss[p] = red[0];
-}
-
 __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, int J, int K,
                                                   LossArgs la, const int* __restrict__ active,
                                                   const float* __restrict__ Ab,
@@ -199,7 +122,7 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, 
                                                   float* __restrict__ gphi) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = blockIdx.x;
+  const int u = xcd_unit(xcd_per(units));
   if (u >= units) return;
   const int lane = threadIdx.x;
   const int j = u % J;
@@ -351,19 +274,12 @@ hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active,
   return hipGetLastError();
 }
 
-hipError_t launch_object64(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
-                           const float2* S, float2* O, double* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_object64, dim3(d.P), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la, active,
-                     S, O, loss);
-  return hipGetLastError();
-}
-
 hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la,
                             const int* active, const float* Ab, const float* phi, const float2* S,
                             const float2* O, float* gphi, hipStream_t s) {
   const int units = d.P * d.C * d.J;
-  hipLaunchKernelGGL(k_adjoint64, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J, d.K, la,
-                     active, Ab, phi, S, O, gphi);
+  hipLaunchKernelGGL(k_adjoint64, dim3(kXcds * xcd_per(units)), dim3(64), 0, s, units, ct, d.C,
+                     d.J, d.K, la, active, Ab, phi, S, O, gphi);
   return hipGetLastError();
 }
 

@@ -32,11 +32,11 @@ struct momfbd_plan_s {
   int device = -1;
   int shift_y[kMaxC];      // translation applied to each channel's pupil
   int shift_x[kMaxC];
-  float* Ab = nullptr;     // [C][32][32]   aperture on the band
-  float* Zt = nullptr;     // [C][M][32][32] modes in turns
-  float* ZtT = nullptr;    // [C][32*32][Mp] the same, mode index fastest, zero padded
+  float* Ab = nullptr;     // [C][N/2][N/2]    aperture on the band
+  float* Zt = nullptr;     // [C][M][N/2][N/2] modes in turns
+  float* ZtT = nullptr;    // [C][(N/2)^2][Mp] the same, mode index fastest, zero padded
   int Mp = 0;              // M rounded up to a multiple of 16
-  float* thetat = nullptr; // [C][32][32]   diversity in turns
+  float* thetat = nullptr; // [C][N/2][N/2]    diversity in turns
   int* hflag = nullptr;    // pinned host word for the solver's "still searching" count
 };
 
@@ -114,25 +114,30 @@ size_t workspace_bytes(const Dims& d) {
   const size_t units = (size_t)d.P * d.C * d.J;
   const size_t hs = (size_t)d.N * (d.N / 2 + 1);
   size_t b = 0;
-  b += align256(units * kBandPix * sizeof(float));          // phi
+  const size_t bp = d.bandpix();
+  b += align256(units * bp * sizeof(float));                 // phi
   b += align256(units * hs * sizeof(float2));                // S
   b += align256((size_t)d.P * d.K * hs * sizeof(float2));    // O
-  b += align256(units * kBandPix * sizeof(float));          // gphi
+  b += align256(units * bp * sizeof(float));                 // gphi
+  b += align256((size_t)d.P * d.K * sizeof(double));         // loss_pk
   return b;
 }
 
 Workspace carve_workspace(const Dims& d, void* base) {
   const size_t units = (size_t)d.P * d.C * d.J;
   const size_t hs = (size_t)d.N * (d.N / 2 + 1);
+  const size_t bp = d.bandpix();
   char* p = static_cast<char*>(base);
   Workspace w;
   w.phi = reinterpret_cast<float*>(p);
-  p += align256(units * kBandPix * sizeof(float));
+  p += align256(units * bp * sizeof(float));
   w.S = reinterpret_cast<float2*>(p);
   p += align256(units * hs * sizeof(float2));
   w.O = reinterpret_cast<float2*>(p);
   p += align256((size_t)d.P * d.K * hs * sizeof(float2));
   w.gphi = reinterpret_cast<float*>(p);
+  p += align256(units * bp * sizeof(float));
+  w.loss_pk = reinterpret_cast<double*>(p);
   return w;
 }
 
@@ -166,7 +171,7 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
     for (int c = 0; c < C; ++c) any |= desc->channel_object[c] == k;
     if (!any) return MOMFBD_EINVAL;
   }
-  if (N != 64) return MOMFBD_EUNSUPPORTED;
+  if (N != 64 && N != 128) return MOMFBD_EUNSUPPORTED;
   if (M > kMaxM || (long)J * M > 8192) return MOMFBD_EUNSUPPORTED;
 
   momfbd_plan_s* pl = new (std::nothrow) momfbd_plan_s();
@@ -181,9 +186,10 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
   }
   pl->ct.obj_first[K] = nfill;
 
-  const int B = kBand, B0 = N / 4;
-  std::vector<float> hA((size_t)C * kBandPix, 0.f), hT((size_t)C * kBandPix, 0.f);
-  std::vector<float> hZ((size_t)C * M * kBandPix, 0.f);
+  const int B = N / 2, B0 = N / 4;
+  const size_t BP = (size_t)B * B;
+  std::vector<float> hA((size_t)C * BP, 0.f), hT((size_t)C * BP, 0.f);
+  std::vector<float> hZ((size_t)C * M * BP, 0.f);
   for (int c = 0; c < C; ++c) {
     pl->ct.chan_obj[c] = desc->channel_object[c];
     const float* A = pupil + (size_t)c * N * N;
@@ -213,20 +219,20 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
       for (int qx = 0; qx < B; ++qx) {
         const int y = ((y0 - oy + n) % N + N) % N, x = ((x0 - ox + qx) % N + N) % N;
         const size_t src = (size_t)y * N + x, dst = (size_t)n * B + qx;
-        hA[(size_t)c * kBandPix + dst] = A[src];
+        hA[(size_t)c * BP + dst] = A[src];
         const double th = diversity ? diversity[(size_t)c * N * N + src] : 0.0;
-        hT[(size_t)c * kBandPix + dst] = (float)(th / kTwoPi);
+        hT[(size_t)c * BP + dst] = (float)(th / kTwoPi);
         for (int m = 0; m < M; ++m)
-          hZ[((size_t)c * M + m) * kBandPix + dst] =
+          hZ[((size_t)c * M + m) * BP + dst] =
               (float)((double)basis[((size_t)c * M + m) * N * N + src] / kTwoPi);
       }
   }
   pl->Mp = (M + 15) / 16 * 16;
-  std::vector<float> hZT((size_t)C * kBandPix * pl->Mp, 0.f);
+  std::vector<float> hZT((size_t)C * BP * pl->Mp, 0.f);
   for (int c = 0; c < C; ++c)
     for (int m = 0; m < M; ++m)
-      for (int px = 0; px < kBandPix; ++px)
-        hZT[((size_t)c * kBandPix + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * kBandPix + px];
+      for (size_t px = 0; px < BP; ++px)
+        hZT[((size_t)c * BP + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * BP + px];
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   if (hipHostMalloc(&pl->hflag, sizeof(int)) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
@@ -289,7 +295,7 @@ int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int
   if (ny * nx != plan->d.P) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
   ProfScope ps(plan, KK_PREPARE, (hipStream_t)stream);
-  return to_status(launch_prepare64(plan->d, frames, H, W, stride, apod,
+  return to_status(launch_prepare(plan->d, frames, H, W, stride, apod,
                                     static_cast<float2*>(D), (hipStream_t)stream));
 }
 
@@ -308,7 +314,7 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward64(plan->d, plan->ct, nullptr, plan->Ab, w.phi, psf,
+    e = launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, psf,
                          otf ? static_cast<float2*>(otf) : w.S, s);
   }
   return to_status(e);
@@ -326,11 +332,11 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward64(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
+    e = launch_forward(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_OBJECT, s);
-    e = launch_object64(plan->d, plan->ct, la, active, w.S, w.O, loss, s);
+    e = launch_object(plan->d, plan->ct, la, active, w.S, w.O, w.loss_pk, loss, s);
   }
   *wout = w;
   return to_status(e);
@@ -347,7 +353,7 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
   hipError_t e;
   {
     ProfScope ps(plan, KK_ADJOINT, s);
-    e = launch_adjoint64(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
+    e = launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
   }
   if (e == hipSuccess) {
     ProfScope ps(plan, KK_GRAD, s);
@@ -381,7 +387,7 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
   st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, scratch_loss, ws, s, &w);
   if (st) return st;
   ProfScope ps(plan, KK_OBJIMG, s);
-  return to_status(launch_objimg64(plan->d, w.O, obj, s));
+  return to_status(launch_objimg(plan->d, w.O, obj, s));
 }
 
 }  // extern "C"

@@ -1,0 +1,147 @@
+// Wiener object and patch loss (Eqs. object_optimization and loss_momfbd),
+// and the size dispatch of the unit kernels.
+//
+// One block per (patch, object); threads walk pairs of adjacent half-spectrum
+// frequencies (16-byte loads).  One pass over D and S: N = sum w D conj(S),
+// Q = gamma + sum w |S|^2 and E = sum w |D|^2 are accumulated in FP64, where
+// the products of FP32 inputs are exact, so the loss term E - |N|^2/Q (the
+// loss at the Wiener object, equal to the residual form
+// sum w |D - O S|^2 + gamma |O|^2) keeps full accuracy.  On the half spectrum
+// the columns 1..N/2-1 stand for two frequencies and count twice.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mfbd {
+
+namespace {
+
+struct Acc2 {
+  double nr[2], ni[2], q[2], e[2];
+};
+
+__device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
+  const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
+  const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
+  a.nr[0] += w * (dx0 * sx0 + dy0 * sy0);
+  a.ni[0] += w * (dy0 * sx0 - dx0 * sy0);
+  a.q[0] += w * (sx0 * sx0 + sy0 * sy0);
+  a.e[0] += w * (dx0 * dx0 + dy0 * dy0);
+  a.nr[1] += w * (dx1 * sx1 + dy1 * sy1);
+  a.ni[1] += w * (dy1 * sx1 - dx1 * sy1);
+  a.q[1] += w * (sx1 * sx1 + sy1 * sy1);
+  a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
+}
+
+template <int NN>
+__global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, ChanTab ct,
+                                                LossArgs la, const int* __restrict__ active,
+                                                const float2* __restrict__ S,
+                                                float2* __restrict__ O,
+                                                double* __restrict__ loss_pk) {
+  constexpr int HC = NN / 2 + 1;
+  constexpr int kUnitF2 = NN * HC;
+  constexpr int kPairs = kUnitF2 / 2;
+  __shared__ double red[256];
+  const int p = blockIdx.x / K, k = blockIdx.x % K;
+  if (active && !active[p]) return;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
+  for (int f2 = tid; f2 < kPairs; f2 += 256) {
+    const int f = 2 * f2;
+    Acc2 a;
+    for (int i = 0; i < 2; ++i) {
+      a.nr[i] = a.ni[i] = a.e[i] = 0.0;
+      a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
+    }
+    for (int ci = c0; ci < c1; ++ci) {
+      const int c = ct.obj_chans[ci];
+      const float4* Dc = reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+      const float4* Sc = reinterpret_cast<const float4*>(S + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+      const float* wc = la.weights ? la.weights + c * J : nullptr;
+      int j = 0;
+      for (; j + 6 <= J; j += 6) {
+        float4 d[6], s[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+          d[u] = Dc[(size_t)(j + u) * (kUnitF2 / 2)];
+          s[u] = Sc[(size_t)(j + u) * (kUnitF2 / 2)];
+        }
+#pragma unroll
+        for (int u = 0; u < 6; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
+      }
+      for (; j < J; ++j)
+        acc_unit(a, wc ? (double)wc[j] : 1.0, Dc[(size_t)j * (kUnitF2 / 2)],
+                 Sc[(size_t)j * (kUnitF2 / 2)]);
+    }
+    const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
+    const float4 o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
+                                 (float)(a.nr[1] * inv1), (float)(a.ni[1] * inv1));
+    const int kx0 = f % HC, kx1 = (f + 1) % HC;
+    const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
+    const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
+    acc += h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
+           h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
+    reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] += red[tid + s2];
+    __syncthreads();
+  }
+  if (tid == 0) loss_pk[(size_t)p * K + k] = red[0];
+}
+
+// loss[p] = sum over objects, in order
+__global__ __launch_bounds__(256) void k_loss_sum(int P, int K, const int* __restrict__ active,
+                                                  const double* __restrict__ loss_pk,
+                                                  double* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P || (active && !active[p])) return;
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) s += loss_pk[(size_t)p * K + k];
+  loss[p] = s;
+}
+
+}  // namespace
+
+hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                         const float2* S, float2* O, double* loss_pk, double* loss,
+                         hipStream_t s) {
+  if (d.N == 64)
+    hipLaunchKernelGGL(k_object<64>, dim3(d.P * d.K), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la,
+                       active, S, O, loss_pk);
+  else
+    hipLaunchKernelGGL(k_object<128>, dim3(d.P * d.K), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct,
+                       la, active, S, O, loss_pk);
+  hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K, active,
+                     loss_pk, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                          const float* phi, float* psf, float2* S, hipStream_t s) {
+  return d.N == 64 ? launch_forward64(d, ct, active, Ab, phi, psf, S, s)
+                   : launch_forward128(d, ct, active, Ab, phi, psf, S, s);
+}
+
+hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                          const float* Ab, const float* phi, const float2* S, const float2* O,
+                          float* gphi, hipStream_t s) {
+  return d.N == 64 ? launch_adjoint64(d, ct, la, active, Ab, phi, S, O, gphi, s)
+                   : launch_adjoint128(d, ct, la, active, Ab, phi, S, O, gphi, s);
+}
+
+hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
+                          const float* apod, float2* D, hipStream_t s) {
+  return d.N == 64 ? launch_prepare64(d, frames, H, W, stride, apod, D, s)
+                   : launch_prepare128(d, frames, H, W, stride, apod, D, s);
+}
+
+hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s) {
+  return d.N == 64 ? launch_objimg64(d, O, obj, s) : launch_objimg128(d, O, obj, s);
+}
+
+}  // namespace mfbd

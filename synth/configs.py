@@ -75,17 +75,19 @@ def make_problem(key, N=64, P=1, J=8, M=44, channels=((0, 0.0),),
     ``channels`` lists (object id, diversity in waves PV of defocus) per
     channel.  ``lam_ratios`` optionally gives lambda_0/lambda_c per channel:
     the basis and the diversity of that channel are scaled by it (wavefront
-    equation of Sect. "Wavefronts").
+    equation of Sect. "Wavefronts") and its pupil diameter in pixels too.
     """
     rng_obj, rng_wf, rng_noise, _ = _streams(key)
     C = len(channels)
     chan_obj = np.array([c[0] for c in channels], dtype=np.int32)
     K = int(chan_obj.max()) + 1
     lam = np.ones(C) if lam_ratios is None else np.asarray(lam_ratios, float)
-    A = pupil_mask(N, diameter_frac)
-    Z = zernike_basis(N, M, diameter_frac)
-    basis = np.stack([Z * lam[c] for c in range(C)])
-    div = np.stack([defocus_diversity(N, channels[c][1], diameter_frac) * lam[c]
+    # a channel at lambda_c = lambda_0 / lam[c] sees a pupil of diameter
+    # d lam[c] pixels (sampling D pix / lambda) and phases scaled by lam[c]
+    fracs = [diameter_frac * lam[c] for c in range(C)]
+    A = np.stack([pupil_mask(N, fracs[c]) for c in range(C)])
+    basis = np.stack([zernike_basis(N, M, fracs[c]) * lam[c] for c in range(C)])
+    div = np.stack([defocus_diversity(N, channels[c][1], fracs[c]) * lam[c]
                     if channels[c][1] != 0.0 else np.zeros((N, N))
                     for c in range(C)])
     d_r0 = np.broadcast_to(np.asarray(d_over_r0, float), (P,)).copy()
@@ -95,7 +97,7 @@ def make_problem(key, N=64, P=1, J=8, M=44, channels=((0, 0.0),),
                             for _ in range(P)])
     noise = gaussian_noise(rng_noise, (P, C, J, N, N), noise_sigma)
     return Problem(N=N, P=P, C=C, K=K, J=J, M=M, channel_object=chan_obj,
-                   pupil=np.broadcast_to(A, (C, N, N)).astype(np.float32),
+                   pupil=A.astype(np.float32),
                    basis=basis.astype(np.float32), diversity=div.astype(np.float32),
                    alpha_true=alpha.astype(np.float32),
                    window=hann_window(N, border).astype(np.float32), gamma=float(gamma),

@@ -238,3 +238,61 @@ def test_lbfgs_first_step_matches_oracle_and_converges(dev):
     l_chk, _ = run_gpu(plan, alpha.cpu().numpy(), D, pr.gamma, None, dev)
     np.testing.assert_allclose(l_chk, hist[-1], rtol=1e-12)
     plan.close()
+
+
+# ------------------------------------------------------------ 128 x 128 patches
+
+def test_n128_loss_and_gradient(dev):
+    # config-4 patch size: 128x128 patches, 12-pixel apodization border
+    pr = synth.make_problem(50, N=128, P=2, J=3, M=44, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=np.array([10.0, 15.0]), border=12)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 5), dev)
+
+
+def test_n128_multi_wavelength_objects(dev):
+    # four objects at lambda_0/lambda = 1, 1/0.95, 1/1.05, 1/1.1 sharing the
+    # wavefront coefficients (phases and pupil sizes scaled per channel)
+    lam = [1.0, 1 / 0.95, 1 / 1.05, 1 / 1.1]
+    pr = synth.make_problem(51, N=128, P=1, J=2, M=30,
+                            channels=((0, 0.0), (1, 0.0), (2, 0.0), (3, 0.0)),
+                            lam_ratios=lam, d_over_r0=15.0, border=12)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 6), dev)
+
+
+def test_n128_forward_object_prepare(dev):
+    pr = synth.make_problem(52, N=128, P=2, J=2, M=20, d_over_r0=15.0, border=12)
+    plan = make_plan(pr, dev)
+    psf, otf = plan.forward(to_dev(pr.alpha_true, dev))
+    psf, otf = psf.cpu().numpy(), otf.cpu().numpy()
+    for p in range(2):
+        for j in range(2):
+            phi = oracle.wavefront(pr.alpha_true[p, j], pr.basis[0], pr.diversity[0])
+            s = oracle.psf(pr.pupil[0], phi)
+            assert np.abs(psf[p, 0, j] - s).max() <= 2e-6 * s.max()
+            assert np.abs(otf[p, 0, j] - oracle.otf(s)[:, :65]).max() <= 2e-6
+    psf0, _ = plan.forward(torch.zeros((2, 2, 20), device=dev), want_otf=False)
+    assert abs(float(psf0[0, 0, 0, 0, 0]) - 2601 / 16384) < 1e-6
+    D = simulate_D(pr)
+    obj = plan.object_estimate(to_dev(pr.alpha_true, dev), to_dev(D, dev), pr.gamma).cpu().numpy()
+    ref = oracle.evaluate(pr.alpha_true, D, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
+                          pr.gamma, want_grad=False)
+    for p in range(2):
+        rms = np.sqrt(np.mean((obj[p, 0] - oracle.object_image(ref["O"][p, 0])) ** 2))
+        assert rms < OBJ_RMS, rms
+    plan.close()
+    rng = np.random.default_rng(53)
+    frames = (1.0 + 0.1 * rng.standard_normal((1, 2, 300, 260))).astype(np.float32)
+    win = synth.hann_window(128, 12).astype(np.float32)
+    ny, nx = (300 - 128) // 64 + 1, (260 - 128) // 64 + 1
+    pr2 = synth.make_problem(54, N=128, P=ny * nx, J=2, M=4)
+    plan2 = make_plan(pr2, dev)
+    Dg = plan2.prepare_data(to_dev(frames, dev), 64, to_dev(win, dev)).cpu().numpy()
+    ref = oracle.prepare_data(frames, win, 128, 64)
+    assert np.abs(Dg - ref).max() <= 1e-6 * np.abs(ref).max()
+    plan2.close()
+
+
+def test_multi_wavelength_n64(dev):
+    pr = synth.make_problem(55, N=64, P=2, J=3, M=36, channels=((0, 0.0), (1, 0.0), (1, 1.0)),
+                            lam_ratios=[1.0, 1 / 1.1, 1 / 1.1], d_over_r0=10.0)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 7), dev)
