@@ -1,12 +1,17 @@
 """Benchmark of the MOMFBD hot path on one MI355X.
 
-Workload (full-field plain MOMFBD): 1024 x 1024 frames cut into 64 x 64
-patches at stride 32 (961 patches), 12 frames, 2 objects (a wideband
+Headline workload (full-field plain MOMFBD): 1024 x 1024 frames cut into
+64 x 64 patches at stride 32 (961 patches), 12 frames, 2 objects (a wideband
 channel and a +1 wave defocus phase-diversity channel sharing the modal
 coefficients), 66 Zernike modes (Noll 2..67), D/r0 from 5 to 20 across the
 field.  One step = one momfbd_loss_grad call: modal synthesis, pupil, PSF,
 OTF, Wiener object, FP64 patch loss, adjoint and gradient contraction for
 every (patch, channel, frame).  Inputs are resident in HBM before timing.
+
+A second block ("large_multi_object") times the same step on 2048 x 2048
+frames in 128 x 128 patches at stride 64 (961 patches), 24 frames, four
+objects at lambda/lambda_0 = 1.0/0.95/1.05/1.1, 150 modes, D/r0 = 15, with
+the object smoothness prior as a per-frequency gamma.
 
 Prints ONE JSON line.  --gpus N > 1 is refused (one-GPU build).
 """
@@ -14,6 +19,7 @@ Prints ONE JSON line.  --gpus N > 1 is refused (one-GPU build).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,22 +33,56 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
-N = 64
-FFT_C2C = 5.0 * N * N * np.log2(N * N)       # FFTW convention, 245 760 flop
-FFT_REAL = 0.5 * FFT_C2C                      # r2c or c2r, 122 880 flop
-FLOP_PER_UNIT = 2 * FFT_C2C + 2 * FFT_REAL    # 737 280: 2 c2c + r2c + c2r
-HALF_BYTES = N * (N // 2 + 1) * 8             # one data half spectrum, 16 896 B
 
-# nominal FFT flops each kernel performs per unit (recomputation not counted)
-KERNEL_FLOP_PER_UNIT = {"forward": FFT_C2C + FFT_REAL, "adjoint": FFT_C2C + FFT_REAL}
+def fft_flops(N):
+    """Nominal FFT flops (FFTW convention): c2c, and r2c or c2r, of N x N."""
+    c2c = 5.0 * N * N * np.log2(N * N)
+    return c2c, 0.5 * c2c
+
+
+def unit_flops(N):
+    """Per (patch, channel, frame): 2 c2c + r2c + c2r for loss and gradient;
+    forward and adjoint kernels each carry one c2c and one real transform."""
+    c2c, real = fft_flops(N)
+    return 2 * c2c + 2 * real, {"forward": c2c + real, "adjoint": c2c + real}
+
+
+# HBM traffic per launch of the dominant kernels on the headline workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
+# the reading of the same counter for a plain 256 MiB device copy (FETCH_SIZE
+# reads half the copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid
+# only for the kernel sources they were taken on: a changed source hash
+# reports null.
+KERNEL_SOURCES = {
+    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    "object": ["object.hip", "internal.h"],
+}
+COUNTED_TRAFFIC = {}
+
+
+def sources_sha(kernel):
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_2505_10639_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def counted_traffic(kernel):
+    rec = COUNTED_TRAFFIC.get(kernel)
+    if rec is None or rec["sources_sha1"] != sources_sha(kernel):
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_inputs(dev):
-    """Plan, data spectra D and an evaluation point alpha, all on the GPU.
+def build_full_field(dev):
+    """Plan, data spectra D and an evaluation point alpha of the headline
+    workload, all on the GPU.
 
     D = O_p S_pcj + N_pcj per patch: O_p the spectrum of the apodized patch of
     a k^-3 scene, S the OTFs of the true Kolmogorov coefficients (computed by
@@ -53,6 +93,7 @@ def build_inputs(dev):
     from paper_2505_10639_amd import Plan
 
     g = synth.config1_geometry()
+    N = g["N"]
     pr = synth.make_problem(1, N=N, P=1, J=g["J"], M=g["M"], channels=g["channels"],
                             gamma=g["gamma"], border=g["border"], objects=np.zeros((1, 2, N, N)))
     P, C, J, M = g["P"], g["C"], g["J"], g["M"]
@@ -76,32 +117,122 @@ def build_inputs(dev):
     pert = torch.from_numpy((0.3 * rng.standard_normal((P, J, M))).astype(np.float32)).to(dev)
     alpha = (alpha_true + pert).contiguous()
     torch.cuda.synchronize()
-    return plan, D, alpha, g
+    return plan, D, alpha, g["gamma"], g
 
 
-def cpu_baseline(D_host, alpha_host, g, budget_s=12.0):
-    """The FP64 oracle on a bounded sample of the same workload (the first
-    patches, until the time budget is used)."""
+def build_large(dev):
+    """The 128 x 128, four-object workload; gamma is the smoothness-prior
+    table made by the library."""
+    import torch
+
+    import synth
+    from paper_2505_10639_amd import Plan
+
+    g = synth.config4_geometry()
+    pr = synth.config4_template()
+    N, P, C, J, M = g["N"], g["P"], g["C"], g["J"], g["M"]
+    plan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, dev)
+    win = torch.from_numpy(pr.window).to(dev)
+    alpha_true = torch.from_numpy(synth.config4_alpha()).to(dev)
+    scenes = torch.from_numpy(synth.config4_objects()).to(dev)
+    aux = Plan(N, P, 1, list(range(C)), pr.pupil, pr.basis[:, :1], None, dev)
+    Ohat = aux.prepare_data(scenes.reshape(C, 1, g["H"], g["W"]).contiguous(), g["stride"], win)
+    aux.close()
+    del scenes
+    _, S = plan.forward(alpha_true, want_psf=False)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_ROOT + 4)
+    noise = 0.01 * torch.randn((C, J, g["H"], g["W"]), generator=gen, device=dev)
+    Nhat = plan.prepare_data(noise, g["stride"], win)
+    del noise
+    D = (Ohat * S + Nhat).contiguous()
+    del S, Nhat, Ohat
+    rng = np.random.default_rng(synth.SEED_ROOT + 5)
+    pert = torch.from_numpy((0.3 * rng.standard_normal((P, J, M))).astype(np.float32)).to(dev)
+    alpha = (alpha_true + pert).contiguous()
+    gamma = plan.smoothness_gamma([g["gamma"]] * g["K"], [g["smooth"]] * g["K"])
+    torch.cuda.synchronize()
+    return plan, D, alpha, gamma, g
+
+
+def time_steps(plan, D, alpha, gamma, steps, warmup):
+    """ms per loss+grad step (HIP events on the launch stream) and the
+    per-kernel average durations from the library's own event pairs."""
+    import torch
+
+    from paper_2505_10639_amd import momfbd_profile_start, momfbd_profile_stop
+
+    loss = torch.empty(plan.P, dtype=torch.float64, device=plan.device)
+    grad = torch.empty_like(alpha)
+
+    def step():
+        plan.loss_grad(alpha, D, gamma, None, True, loss, grad)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(plan.device)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert torch.isfinite(loss).all(), "non-finite loss"
+    momfbd_profile_start(plan.handle, 8 * steps)
+    for _ in range(steps):
+        step()
+    kern = momfbd_profile_stop(plan.handle)
+    return ms, {k: v[0] / v[1] for k, v in kern.items()}, loss, grad
+
+
+def roofline(kern_avg, units, N, D_bytes, traffic_of):
+    """Roofline object of the dominant (longest) kernel."""
+    _, per_kernel = unit_flops(N)
+    dom = max(kern_avg, key=kern_avg.get)
+    t = kern_avg[dom] * 1e-3
+    fl = per_kernel.get(dom)
+    if fl is not None:
+        achieved = fl * units / t / 1e12
+        return {"bound": "alu", "kernel": dom, "achieved": achieved,
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic_of(dom),
+                "avg_ms": kern_avg[dom], "flop_per_unit": fl, "units_per_launch": units}
+    # the object kernel: one read of D and one of S (same size)
+    achieved = 2 * D_bytes / t / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_of(dom),
+            "avg_ms": kern_avg[dom]}
+
+
+def cpu_baseline(D_host, alpha_host, g, budget_s):
+    """The FP64 oracle on the same workload, patch after patch, until every
+    patch is done or the time budget is used."""
     import oracle
     import synth
     from threadpoolctl import threadpool_info
 
+    N = g["N"]
     pr = synth.make_problem(1, N=N, P=1, J=g["J"], M=g["M"], channels=g["channels"],
                             gamma=g["gamma"], border=g["border"], objects=np.zeros((1, 2, N, N)))
     t0 = time.perf_counter()
     n = 0
-    while True:
+    while n < len(D_host):
         oracle.evaluate_patch(alpha_host[n], D_host[n], pr.basis, pr.diversity, pr.pupil,
                               pr.channel_object, pr.gamma)
         n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= len(D_host):
+        if time.perf_counter() - t0 >= budget_s:
             break
+    el = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": n * g["J"] / el, "unit": "patch-frame loss+grad evals/s", "cores": threads,
+    return {"value": n * g["J"] / el, "unit": "patch-frame evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {n} of {g['P']} patches ({n * g['J']} patch-frames, "
-                      f"{n * g['J'] * g['C']} units), {el:.1f} s, FP64 direct DFT"}
+            "sample": f"patches 0..{n - 1} of {g['P']} ({n * g['J']} patch-frames, "
+                      f"{n * g['J'] * g['C']} units) in {el:.1f} s, FP64 direct DFT, "
+                      f"{threads} BLAS threads"}
 
 
 def main():
@@ -110,7 +241,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-large", action="store_true", help="skip the 128 x 128 workload")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (for scaling "
                          "hardware byte counters) and exit")
@@ -123,8 +255,6 @@ def main():
 
     import torch
 
-    from paper_2505_10639_amd import momfbd_profile_start, momfbd_profile_stop
-
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -135,54 +265,17 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "copies": 3}), flush=True)
         return
-    log("building inputs")
-    plan, D, alpha, g = build_inputs(dev)
-    P, C, J = g["P"], g["C"], g["J"]
+
+    log("building full-field inputs")
+    plan, D, alpha, gamma, g = build_full_field(dev)
+    N, P, C, J = g["N"], g["P"], g["C"], g["J"]
     units = P * C * J
-    loss = torch.empty(P, dtype=torch.float64, device=dev)
-    grad = torch.empty_like(alpha)
-
-    def step():
-        plan.loss_grad(alpha, D, g["gamma"], None, True, loss, grad)
-
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    assert torch.isfinite(loss).all(), "non-finite loss"
-
-    # per-kernel durations: HIP events recorded by the library on the launch stream
-    log("per-kernel timing")
-    momfbd_profile_start(plan.handle, 8 * args.steps)
-    for _ in range(args.steps):
-        step()
-    kern = momfbd_profile_stop(plan.handle)
-    kern_avg = {k: v[0] / v[1] for k, v in kern.items()}
-    dom = max(kern_avg, key=kern_avg.get)
-    fl = KERNEL_FLOP_PER_UNIT.get(dom)
-    if fl is not None:
-        achieved = fl * units / (kern_avg[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved,
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                "avg_ms": kern_avg[dom]}
-    else:
-        achieved = 2 * HALF_BYTES * units / (kern_avg[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                "avg_ms": kern_avg[dom]}
-
-    step_tflops = FLOP_PER_UNIT * units / (ms * 1e-3) / 1e12
+    log(f"timing {args.steps} steps after {args.warmup} warm-up")
+    ms, kern_avg, _, _ = time_steps(plan, D, alpha, gamma, args.steps, args.warmup)
+    D_bytes = D.numel() * 8
+    roof = roofline(kern_avg, units, N, D_bytes, counted_traffic)
+    flop_unit, _ = unit_flops(N)
+    step_tflops = flop_unit * units / (ms * 1e-3) / 1e12
     out = {
         "metric": "patch-frame loss+grad evals/s",
         "value": P * J / (ms * 1e-3),
@@ -201,13 +294,38 @@ def main():
         "step_frac_of_fp32_peak": step_tflops / PEAK_FP32_VECTOR_TFLOPS,
         "kernels_avg_ms": kern_avg,
     }
+    D_h = a_h = None
+    if not args.no_cpu:
+        D_h = D.cpu().numpy()
+        a_h = alpha.cpu().numpy()
+    plan.close()
+    del D, alpha
+
+    if not args.no_large:
+        log("building 128x128 multi-object inputs")
+        plan4, D4, alpha4, gamma4, g4 = build_large(dev)
+        units4 = g4["P"] * g4["C"] * g4["J"]
+        steps4 = max(2, args.steps // 2)
+        log(f"timing {steps4} steps of the 128x128 workload")
+        ms4, kern4, _, _ = time_steps(plan4, D4, alpha4, gamma4, steps4, min(args.warmup, 2))
+        flop4, _ = unit_flops(g4["N"])
+        t4 = flop4 * units4 / (ms4 * 1e-3) / 1e12
+        out["large_multi_object"] = {
+            "workload": "2048x2048 frames, 961 patches of 128x128 at stride 64, 24 frames, 4 "
+                        "objects at lambda/lambda0 1.0/0.95/1.05/1.1, 150 Zernike modes, "
+                        "D/r0 15, smoothness prior gamma(u)",
+            "value": g4["P"] * g4["J"] / (ms4 * 1e-3), "unit": "patch-frame evals/s",
+            "ms_per_step": ms4, "steps": steps4, "units_per_step": units4,
+            "step_nominal_fft_tflops": t4, "step_frac_of_fp32_peak": t4 / PEAK_FP32_VECTOR_TFLOPS,
+            "roofline": roofline(kern4, units4, g4["N"], D4.numel() * 8, lambda k: None),
+            "kernels_avg_ms": kern4,
+        }
+        plan4.close()
+        del D4, alpha4, gamma4
+
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        n_s = 512
-        D_h = D[:n_s].cpu().numpy()
-        a_h = alpha[:n_s].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(D_h, a_h, g, args.cpu_budget)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

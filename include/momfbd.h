@@ -134,6 +134,18 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
                            float* obj, void* ws, void* stream);
 
+/* Object smoothness prior (Sect. "Smoothness", Eq. regularization_smoothness):
+ * the penalty lambda_k ||grad o_k||^2, with periodic forward differences, added
+ * to the pixel-domain misfit is, in the unnormalised Fourier sum of Eq.
+ * loss_momfbd, the per-frequency Wiener constant
+ *   gamma_k(u) = gamma0_k + lambda_k (4 sin^2(pi u_x/N) + 4 sin^2(pi u_y/N)),
+ * so lambda_k does not depend on N.  Writes that table, float [K][N][N/2+1]
+ * (device, caller-allocated), to be passed as `gamma` to loss_grad,
+ * object_estimate and the solver.  gamma0, lambda: host [K], finite, >= 0.
+ * Errors: EINVAL (NULL or out-of-range constant), EDEVICE. */
+int momfbd_smoothness_gamma(momfbd_plan plan, const float* gamma0, const float* lambda,
+                            float* gamma, void* stream);
+
 /* Per-patch L-BFGS solver (the quasi-Newton alternative to the paper's Adam,
  * Sect. "Optimization and paralellization"; patches are independent).
  * Each patch runs the two-loop recursion of limited-memory BFGS and a

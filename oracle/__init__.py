@@ -9,12 +9,12 @@ the product path never calls it and shares no code with it.
 from .momfbd import (dft2, idft2_un, expand_half, wavefront, pupil_field, psf_field,
                      psf, otf, accumulators, evaluate_patch, evaluate,
                      object_image, prepare_data, patch_spectra, simulate_frames,
-                     loss_literal)
+                     loss_literal, smoothness_gamma)
 from .lbfgs import lbfgs_minimize
 
 __all__ = [
     "dft2", "idft2_un", "expand_half", "wavefront", "pupil_field", "psf_field",
     "psf", "otf", "accumulators", "evaluate_patch", "evaluate", "object_image",
-    "prepare_data", "patch_spectra", "simulate_frames", "loss_literal",
+    "prepare_data", "patch_spectra", "simulate_frames", "loss_literal", "smoothness_gamma",
     "lbfgs_minimize",
 ]

@@ -139,6 +139,27 @@ def _gamma_full(gamma, K: int, N: int) -> np.ndarray:
     raise ValueError("gamma must be scalar, [K][N][N/2+1] or [K][N][N]")
 
 
+def smoothness_gamma(N: int, gamma0, lam) -> np.ndarray:
+    """Per-frequency Wiener constant of the object smoothness prior.
+
+    Sect. "Smoothness" (Eq. regularization_smoothness) penalises
+    lambda_k ||grad o_k||^2.  With periodic forward differences
+    (dx o)(r) = o(r + e_x) - o(r), Parseval turns the penalty into
+    lambda_k / N^2 sum_u |O_k(u)|^2 |e^{2 pi i u_x/N} - 1|^2 + (same in y), and
+    |e^{i t} - 1|^2 = 4 sin^2(t/2).  Scaling the pixel-domain objective by N^2
+    (the unnormalised Fourier sum of Eq. loss_momfbd), a constant gamma0_k plus
+    this penalty is the array gamma_k(u) = gamma0_k + lambda_k (4 sin^2(pi u_x/N)
+    + 4 sin^2(pi u_y/N)) in the denominator of Eq. object_optimization.
+    Returns float64 [K][N][N] on the full grid.
+    """
+    g0 = np.atleast_1d(np.asarray(gamma0, np.float64))
+    lm = np.atleast_1d(np.asarray(lam, np.float64))
+    u = np.arange(N)
+    lap = 4.0 * np.sin(np.pi * u / N) ** 2
+    grid = lap[:, None] + lap[None, :]
+    return g0[:, None, None] + lm[:, None, None] * grid[None]
+
+
 def accumulators(D: np.ndarray, S: np.ndarray, w: np.ndarray, chan_obj, gamma, K: int):
     """N_k = sum_{c in k, j} w D conj(S);  Q_k = sum w |S|^2 + gamma_k.
 

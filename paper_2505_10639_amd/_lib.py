@@ -65,6 +65,7 @@ def lib():
         L.momfbd_status_string.argtypes = [i]
         L.momfbd_status_string.restype = ctypes.c_char_p
         L.momfbd_plan_dims.argtypes = [_vp] + [ctypes.POINTER(i)] * 6
+        L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
         pp = ctypes.POINTER(momfbd_lbfgs_params)
         L.momfbd_lbfgs_state_size.argtypes = [_vp, pp, ctypes.POINTER(ctypes.c_size_t)]
@@ -76,7 +77,7 @@ def lib():
                      "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
                      "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
-                     "momfbd_lbfgs_step"):
+                     "momfbd_lbfgs_step", "momfbd_smoothness_gamma"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -143,6 +144,13 @@ def momfbd_plan_dims(plan):
     v = [ctypes.c_int() for _ in range(6)]
     _check(lib().momfbd_plan_dims(plan, *[ctypes.byref(x) for x in v]), "momfbd_plan_dims")
     return tuple(x.value for x in v)
+
+
+def momfbd_smoothness_gamma(plan, gamma0, lam, gamma, stream=None):
+    g0 = np.ascontiguousarray(gamma0, np.float32)
+    lm = np.ascontiguousarray(lam, np.float32)
+    _check(lib().momfbd_smoothness_gamma(plan, _ptr(g0), _ptr(lm), _ptr(gamma),
+                                         _stream(stream, gamma)), "momfbd_smoothness_gamma")
 
 
 def momfbd_prepare_data(plan, frames, H, W, stride, apod, D, ws, stream=None):

@@ -13,6 +13,9 @@ constexpr int kMaxM = 256;
 constexpr int kBand = 32;            // band width for N = 64
 constexpr int kBandPix = kBand * kBand;
 
+// Blocks of 256 frequency pairs covering one half spectrum of side n.
+__host__ __device__ constexpr int object_blocks(int n) { return (n * (n / 2 + 1) / 2 + 255) / 256; }
+
 struct Dims {
   int N, P, C, K, J, M;
   int band() const { return N / 2; }                 // pupil band width
@@ -36,13 +39,20 @@ struct LossArgs {
   const float* weights;    // [C][J] or null (= 1)
 };
 
+// Smoothness prior constants per object.
+struct PriorTab {
+  float gamma0[kMaxK];
+  float lambda[kMaxK];
+};
+hipError_t launch_smoothness(int N, int K, const PriorTab& t, float* gamma, hipStream_t s);
+
 // Workspace carve-up.
 struct Workspace {
   float* phi;              // [P][C][J][N/2][N/2]  phase in turns on the pupil band
   float2* S;               // [P][C][J][N][N/2+1] OTF half spectra
   float2* O;               // [P][K][N][N/2+1]    object spectra
   float* gphi;             // [P][C][J][N/2][N/2]  dL/dphi (rad^-1) on the band
-  double* loss_pk;         // [P][K] per-object loss terms
+  double* loss_pk;         // [P][K][object_blocks(N)] partial loss terms
 };
 
 size_t workspace_bytes(const Dims& d);

@@ -119,7 +119,7 @@ size_t workspace_bytes(const Dims& d) {
   b += align256(units * hs * sizeof(float2));                // S
   b += align256((size_t)d.P * d.K * hs * sizeof(float2));    // O
   b += align256(units * bp * sizeof(float));                 // gphi
-  b += align256((size_t)d.P * d.K * sizeof(double));         // loss_pk
+  b += align256((size_t)d.P * d.K * object_blocks(d.N) * sizeof(double));  // loss_pk
   return b;
 }
 
@@ -371,6 +371,23 @@ int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const 
   if ((st = pending_error())) return st;
   return run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws,
                        (hipStream_t)stream);
+}
+
+int momfbd_smoothness_gamma(momfbd_plan plan, const float* gamma0, const float* lambda,
+                            float* gamma, void* stream) {
+  if (!plan || !gamma0 || !lambda || !gamma) return MOMFBD_EINVAL;
+  PriorTab t;
+  std::memset(&t, 0, sizeof(t));
+  for (int k = 0; k < plan->d.K; ++k) {
+    if (!(gamma0[k] >= 0.f) || !(lambda[k] >= 0.f) || !std::isfinite(gamma0[k]) ||
+        !std::isfinite(lambda[k]))
+      return MOMFBD_EINVAL;
+    t.gamma0[k] = gamma0[k];
+    t.lambda[k] = lambda[k];
+  }
+  int st = pending_error();
+  if (st) return st;
+  return to_status(launch_smoothness(plan->d.N, plan->d.K, t, gamma, (hipStream_t)stream));
 }
 
 int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,

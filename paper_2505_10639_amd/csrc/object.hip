@@ -1,8 +1,10 @@
 // Wiener object and patch loss (Eqs. object_optimization and loss_momfbd),
 // and the size dispatch of the unit kernels.
 //
-// One block per (patch, object); threads walk pairs of adjacent half-spectrum
-// frequencies (16-byte loads).  One pass over D and S: N = sum w D conj(S),
+// Each (patch, object) plane of the half spectrum is cut into blocks of 256
+// pairs of adjacent frequencies, one pair per thread (16-byte loads); every
+// block leaves one FP64 partial of the loss, summed per patch in a fixed
+// order by k_loss_sum.  One pass over D and S: N = sum w D conj(S),
 // Q = gamma + sum w |S|^2 and E = sum w |D|^2 are accumulated in FP64, where
 // the products of FP32 inputs are exact, so the loss term E - |N|^2/Q (the
 // loss at the Wiener object, equal to the residual form
@@ -38,17 +40,20 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
                                                 LossArgs la, const int* __restrict__ active,
                                                 const float2* __restrict__ S,
                                                 float2* __restrict__ O,
-                                                double* __restrict__ loss_pk) {
+                                                double* __restrict__ loss_part) {
   constexpr int HC = NN / 2 + 1;
   constexpr int kUnitF2 = NN * HC;
   constexpr int kPairs = kUnitF2 / 2;
+  constexpr int kBlocks = object_blocks(NN);
   __shared__ double red[256];
-  const int p = blockIdx.x / K, k = blockIdx.x % K;
+  const int plane = blockIdx.x / kBlocks, part = blockIdx.x % kBlocks;
+  const int p = plane / K, k = plane % K;
   if (active && !active[p]) return;
   const int tid = threadIdx.x;
+  const int f2 = part * 256 + tid;
   double acc = 0.0;
   const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
-  for (int f2 = tid; f2 < kPairs; f2 += 256) {
+  if (f2 < kPairs) {
     const int f = 2 * f2;
     Acc2 a;
     for (int i = 0; i < 2; ++i) {
@@ -81,8 +86,8 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
     const int kx0 = f % HC, kx1 = (f + 1) % HC;
     const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
     const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
-    acc += h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
-           h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
+    acc = h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
+          h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
     reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
   }
   red[tid] = acc;
@@ -91,32 +96,53 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
     if (tid < s2) red[tid] += red[tid + s2];
     __syncthreads();
   }
-  if (tid == 0) loss_pk[(size_t)p * K + k] = red[0];
+  if (tid == 0) loss_part[blockIdx.x] = red[0];
 }
 
-// loss[p] = sum over objects, in order
-__global__ __launch_bounds__(256) void k_loss_sum(int P, int K, const int* __restrict__ active,
-                                                  const double* __restrict__ loss_pk,
+// loss[p] = sum over objects and their blocks, in order
+__global__ __launch_bounds__(256) void k_loss_sum(int P, int nper, const int* __restrict__ active,
+                                                  const double* __restrict__ loss_part,
                                                   double* __restrict__ loss) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= P || (active && !active[p])) return;
   double s = 0.0;
-  for (int k = 0; k < K; ++k) s += loss_pk[(size_t)p * K + k];
+  for (int i = 0; i < nper; ++i) s += loss_part[(size_t)p * nper + i];
   loss[p] = s;
+}
+
+// gamma_k(u) = gamma0_k + lambda_k (4 sin^2(pi u_x/N) + 4 sin^2(pi u_y/N)) on
+// the half spectrum: the smoothness prior lambda_k ||grad o_k||^2 (periodic
+// forward differences) written as a per-frequency Wiener constant.
+__global__ __launch_bounds__(256) void k_smoothness(int N, int K, PriorTab t,
+                                                    float* __restrict__ gamma) {
+  const int HC = N / 2 + 1;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K * N * HC) return;
+  const int k = i / (N * HC), r = i % (N * HC);
+  const int uy = r / HC, ux = r % HC;
+  const double sy = sinpi((double)uy / N), sx = sinpi((double)ux / N);
+  gamma[i] = (float)((double)t.gamma0[k] + (double)t.lambda[k] * 4.0 * (sy * sy + sx * sx));
 }
 
 }  // namespace
 
+hipError_t launch_smoothness(int N, int K, const PriorTab& t, float* gamma, hipStream_t s) {
+  const int n = K * N * (N / 2 + 1);
+  hipLaunchKernelGGL(k_smoothness, dim3((n + 255) / 256), dim3(256), 0, s, N, K, t, gamma);
+  return hipGetLastError();
+}
+
 hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                          const float2* S, float2* O, double* loss_pk, double* loss,
                          hipStream_t s) {
+  const int nb = object_blocks(d.N);
   if (d.N == 64)
-    hipLaunchKernelGGL(k_object<64>, dim3(d.P * d.K), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la,
-                       active, S, O, loss_pk);
+    hipLaunchKernelGGL(k_object<64>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
+                       ct, la, active, S, O, loss_pk);
   else
-    hipLaunchKernelGGL(k_object<128>, dim3(d.P * d.K), dim3(256), 0, s, d.P, d.C, d.J, d.K, ct,
-                       la, active, S, O, loss_pk);
-  hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K, active,
+    hipLaunchKernelGGL(k_object<128>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
+                       ct, la, active, S, O, loss_pk);
+  hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K * nb, active,
                      loss_pk, loss);
   return hipGetLastError();
 }

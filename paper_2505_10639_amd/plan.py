@@ -50,6 +50,16 @@ class Plan:
             nbytes = _lib.momfbd_workspace_size(self.handle)
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
 
+    def smoothness_gamma(self, gamma0, lam):
+        """Per-frequency gamma [K][N][N/2+1] of the object smoothness prior
+        for objects with constants gamma0[K] and lambda[K]."""
+        g0 = np.broadcast_to(np.asarray(gamma0, np.float32), (self.K,))
+        lm = np.broadcast_to(np.asarray(lam, np.float32), (self.K,))
+        out = torch.empty((self.K,) + self.half, dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.momfbd_smoothness_gamma(self.handle, g0, lm, out)
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             torch.cuda.synchronize(self.device)

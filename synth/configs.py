@@ -13,6 +13,11 @@ Workloads (all synthetic; the paper's observations are not available):
     +1 wave peak-to-valley defocus phase-diversity channel) sharing the modal
     coefficients, 66 modes (Noll 2..67), D/r0 rising smoothly from 5 to 20
     across the field.
+  * config4: a 2048x2048 field cut into 128x128 patches at stride 64 (961
+    patches), 24 frames, four objects (one wideband and three narrowband
+    channels at lambda/lambda_0 = 1.0, 0.95, 1.05, 1.1: pupil diameter and
+    phases scaled by lambda_0/lambda), 150 modes (Noll 2..151), D/r0 = 15,
+    and an object smoothness prior.
   * make_problem: the same recipe at any small size, for ragged test cases.
 """
 
@@ -177,3 +182,41 @@ def config1_problem(patches=None) -> Problem:
     base.d_over_r0 = config1_d_over_r0()[sel]
     base.meta.update(patches=sel, key=1)
     return base
+
+
+def config4_geometry():
+    """Sizes of the large multi-object workload: 2048^2, 128^2 patches, stride 64."""
+    H = W = 2048
+    N, stride = 128, 64
+    ys, xs = patch_grid(H, W, N, stride)
+    lam = (1.0, 1.0 / 0.95, 1.0 / 1.05, 1.0 / 1.1)       # lambda_0 / lambda_c
+    return dict(H=H, W=W, N=N, stride=stride, ny=len(ys), nx=len(xs),
+                P=len(ys) * len(xs), J=24, C=4, K=4, M=150, gamma=1e-3, smooth=1e-2,
+                border=12, d_over_r0=15.0, lam_ratios=lam,
+                channels=((0, 0.0), (1, 0.0), (2, 0.0), (3, 0.0)))
+
+
+def config4_template() -> Problem:
+    """Pupils, basis, window and channel map of the large workload (one patch)."""
+    g = config4_geometry()
+    N = g["N"]
+    return make_problem(4, N=N, P=1, J=1, M=g["M"], channels=g["channels"], gamma=g["gamma"],
+                        border=g["border"], lam_ratios=g["lam_ratios"],
+                        objects=np.zeros((1, g["K"], N, N)))
+
+
+def config4_alpha() -> np.ndarray:
+    """Modal coefficients [961][24][150] of the large workload (float32)."""
+    g = config4_geometry()
+    _, rng_wf, _, _ = _streams(4)
+    n = g["P"] * g["J"]
+    a = draw_kolmogorov(rng_wf, n, g["M"], np.full(n, g["d_over_r0"]))
+    return a.reshape(g["P"], g["J"], g["M"]).astype(np.float32)
+
+
+def config4_objects() -> np.ndarray:
+    """Four 2048x2048 k^-3 scenes, one per object (float32)."""
+    g = config4_geometry()
+    rng = _streams(4)[0]
+    return np.stack([object_field(rng, g["H"], g["W"]).astype(np.float32)
+                     for _ in range(g["K"])])

@@ -240,6 +240,30 @@ def test_lbfgs_first_step_matches_oracle_and_converges(dev):
     plan.close()
 
 
+@pytest.mark.parametrize("N", [64, 128])
+def test_smoothness_prior_gamma(dev, N):
+    """The library's smoothness-prior gamma table matches the oracle's, and
+    the loss and gradient under it match the oracle."""
+    pr = synth.make_problem(50 + N, N=N, P=2, J=4, M=24, channels=((0, 0.0), (1, 1.0)),
+                            d_over_r0=np.array([8.0, 14.0]))
+    D_np = fast_simulate_D(pr)
+    plan = make_plan(pr, dev)
+    g0, lam = [1e-3, 4e-3], [0.05, 0.4]
+    g_dev = plan.smoothness_gamma(g0, lam)
+    torch.cuda.synchronize()
+    g_ref = oracle.smoothness_gamma(N, g0, lam)
+    np.testing.assert_allclose(g_dev.cpu().numpy(), g_ref[:, :, : N // 2 + 1], rtol=2e-7, atol=0)
+    D = to_dev(D_np, dev)
+    for name, a in alpha_points(pr, 3).items():
+        print(f"[smoothness] N={N} alpha={name}", flush=True)
+        loss, grad = plan.loss_grad(to_dev(a, dev), D, g_dev)
+        ref = oracle.evaluate(a, D_np, pr.basis, pr.diversity, pr.pupil, pr.channel_object, g_ref)
+        lrel = np.abs(loss.cpu().numpy() - ref["loss"]) / np.abs(ref["loss"])
+        assert np.all(lrel < LOSS_RTOL), (name, lrel.max())
+        assert max(grad_errs(grad.cpu().numpy(), ref["grad"])) < GRAD_RTOL
+    plan.close()
+
+
 # ------------------------------------------------------------ 128 x 128 patches
 
 def test_n128_loss_and_gradient(dev):

@@ -96,3 +96,4 @@ def test_calls_reject_null_plan_and_workspace(L):
     assert L.momfbd_plan_destroy(None) == 0
     n = ctypes.c_size_t()
     assert L.momfbd_workspace_size(None, ctypes.byref(n)) == -1
+    assert L.momfbd_smoothness_gamma(None, None, None, None, None) == -1

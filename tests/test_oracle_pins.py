@@ -281,6 +281,51 @@ def test_loss_equals_dense_real_space_least_squares():
     np.testing.assert_allclose(oracle.object_image(r["O"][0]), o.reshape(N, N), atol=1e-11)
 
 
+def _forward_difference(N, axis):
+    """Dense matrix of the periodic forward difference o(r + e_axis) - o(r)."""
+    n = N * N
+    G = -np.eye(n)
+    for ry in range(N):
+        for rx in range(N):
+            ty, tx = ((ry + 1) % N, rx) if axis == 0 else (ry, (rx + 1) % N)
+            G[ry * N + rx, ty * N + tx] += 1.0
+    return G
+
+
+def test_smoothness_gamma_equals_pixel_gradient_penalty():
+    """The per-frequency gamma of the smoothness prior gives N^2 times the
+    minimum of sum_j w ||d_j - o * s_j||^2 + gamma0 ||o||^2 + lambda ||grad o||^2
+    over real objects, with the gradient as explicit periodic differences."""
+    N, J, M = 8, 3, 5
+    pr, _ = _small_problem(N=N, J=J, M=M)
+    rng = _rng(11)
+    frames = rng.standard_normal((J, N, N)) + 1.0
+    D = oracle.dft2(frames)[:, :, : N // 2 + 1]
+    a = pr.alpha_true[0].astype(np.float64)
+    w = np.array([1.0, 0.5, 2.0])
+    gam0, lam = 0.01, 0.3
+    gam = oracle.smoothness_gamma(N, [gam0], [lam])
+    r = oracle.evaluate_patch(a, D[None], pr.basis, pr.diversity, pr.pupil,
+                              pr.channel_object, gam, w[None], want_grad=False)
+    A = pr.pupil[0].astype(np.float64)
+    Cs = [_circulant(_psf_direct(A, oracle.wavefront(a[j], pr.basis[0], pr.diversity[0])))
+          for j in range(J)]
+    Gy, Gx = _forward_difference(N, 0), _forward_difference(N, 1)
+    n = N * N
+    lhs = (gam0 * np.eye(n) + lam * (Gy.T @ Gy + Gx.T @ Gx)
+           + sum(w[j] * Cs[j].T @ Cs[j] for j in range(J)))
+    rhs = sum(w[j] * Cs[j].T @ frames[j].ravel() for j in range(J))
+    o = np.linalg.solve(lhs, rhs)
+    brute = sum(w[j] * np.sum((frames[j].ravel() - Cs[j] @ o) ** 2) for j in range(J))
+    brute += gam0 * np.sum(o ** 2) + lam * (np.sum((Gy @ o) ** 2) + np.sum((Gx @ o) ** 2))
+    assert abs(r["loss"] - n * brute) <= 1e-11 * abs(r["loss"])
+    np.testing.assert_allclose(oracle.object_image(r["O"][0]), o.reshape(N, N), atol=1e-11)
+    # lambda = 0 reduces to the constant gamma; the table is symmetric in u -> -u
+    np.testing.assert_array_equal(oracle.smoothness_gamma(N, [gam0], [0.0])[0], np.full((N, N), gam0))
+    g = gam[0]
+    np.testing.assert_allclose(g, np.roll(g[::-1, ::-1], 1, (0, 1)), atol=1e-15)
+
+
 def test_noise_free_object_recovers_band_limited_truth():
     N, J = 64, 6
     pr = synth.make_problem(12, N=N, P=1, J=J, M=20, d_over_r0=8.0, noise_sigma=0.0)
