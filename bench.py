@@ -54,11 +54,17 @@ def unit_flops(N):
 # only for the kernel sources they were taken on: a changed source hash
 # reports null.
 KERNEL_SOURCES = {
-    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
-    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
-    "object": ["object.hip", "internal.h"],
+    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h"],
+    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
+    "object": ["object.hip"],
 }
-COUNTED_TRAFFIC = {}
+COPY_FETCH_SCALE = 1.9997781363901774    # 256 MiB copy: FETCH_SIZE read 131086.5 KiB
+COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
+COUNTED_TRAFFIC = {
+    "adjoint": {"fetch_bytes": 1010909823, "write_bytes": 94470144, "sources_sha1": "329df5a02c8d"},
+    "forward": {"fetch_bytes": 94958617, "write_bytes": 395188677, "sources_sha1": "329df5a02c8d"},
+    "object": {"fetch_bytes": 779373168, "write_bytes": 32821939, "sources_sha1": "6a042132d212"},
+}
 
 
 def sources_sha(kernel):
