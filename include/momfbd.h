@@ -146,6 +146,50 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
 int momfbd_smoothness_gamma(momfbd_plan plan, const float* gamma0, const float* lambda,
                             float* gamma, void* stream);
 
+/* Fourier filter of a restored object (Sect. "Fourier filtering"). */
+#define MOMFBD_FILTER_NONE 0
+#define MOMFBD_FILTER_TOPHAT 1     /* H = 1 for f <= f_lo, 0 for f >= f_hi, cosine between */
+#define MOMFBD_FILTER_SCHARMER 2   /* Loefdahl-Scharmer, see momfbd_object_filtered */
+typedef struct {
+  int kind;            /* MOMFBD_FILTER_*                                           */
+  float f_lo, f_hi;    /* top-hat: transition, in units of the diffraction limit     */
+  float diff_limit;    /* top-hat: diffraction-limit frequency in DFT bins, > 0       */
+  float noise_power;   /* Loefdahl-Scharmer: noise power of one data frame per
+                          frequency bin (eta), >= 0                                  */
+} momfbd_filter;
+
+/* Restored objects after a Fourier filter per object (Sect. "Fourier
+ * filtering"): the Wiener objects of momfbd_object_estimate, each spectrum
+ * multiplied by H_k before the inverse transform.  Frequencies f = |u| in
+ * bins with u in (-N/2, N/2].  Loefdahl-Scharmer: H = 1 - eta sum w|S|^2 /
+ * |sum w D conj(S)|^2 over the channels of the object (the printed ratio is
+ * eta = 1; H = 0 where the cross spectrum vanishes), values below 0.2 set to
+ * 0 and above 1 to 1, then a 3x3 median on the periodic frequency grid, then
+ * zero outside the region 4-connected to the zero frequency.  The filter does
+ * not enter the loss.
+ *   filters  host [K]
+ *   obj      [P][K][N][N] float (device), as momfbd_object_estimate
+ *   H        [P][K][N][N/2+1] float (device) receives the filters, or NULL
+ * Errors: EINVAL (NULL, unknown kind, f_hi <= f_lo, diff_limit <= 0,
+ * eta < 0), EWORKSPACE, EDEVICE. */
+int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
+                           const float* gamma, float gamma_scalar, const float* weights,
+                           const momfbd_filter* filters, float* obj, float* H, void* ws,
+                           void* stream);
+
+/* Mosaic of restored patches (Sect. "Division in patches and apodization"):
+ * out_k(y, x) = sum_p w(y - y_p, x - x_p) o_pk(y - y_p, x - x_p) / sum_p w(.)
+ * over the patches covering the pixel, patch p = i*nx + k at
+ * (y_p, x_p) = (i*stride, k*stride), with the separable cosine taper
+ * w1(e) = (1 - cos(pi (e + 1/2)/border))/2 for e = min(x, N-1-x) < border,
+ * else 1 (border = 0: equal weights).
+ *   obj  [P][K][N][N] float (device), P = ny*nx
+ *   out  [K][(ny-1)*stride+N][(nx-1)*stride+N] float (device)
+ * Errors: EINVAL (ny*nx != P, stride outside [1, N], border outside
+ * [0, N/2]), EDEVICE. */
+int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride, int border,
+                  float* out, void* stream);
+
 /* Per-patch L-BFGS solver (the quasi-Newton alternative to the paper's Adam,
  * Sect. "Optimization and paralellization"; patches are independent).
  * Each patch runs the two-loop recursion of limited-memory BFGS and a
@@ -194,7 +238,7 @@ int momfbd_profile_start(momfbd_plan plan, int max_launches);
 
 /* Synchronise on the recorded events, stop timing, and report per kernel
  * kind: a static name ("phase", "forward", "object", "adjoint", "grad",
- * "prepare", "objimg"), the summed milliseconds and the launch count, for at
+ * "prepare", "objimg", "filter", "mosaic"), the summed milliseconds and the launch count, for at
  * most `cap` kinds.  Returns the number of kinds written (>= 0) or a
  * negative status. */
 int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* total_ms,

@@ -8,6 +8,7 @@ the library; the first call does, and fails loudly if it is not built.
 
 from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_create,
                    momfbd_plan_destroy, momfbd_workspace_size, momfbd_plan_dims,
+                   momfbd_object_filtered, momfbd_mosaic, filter_spec,
                    momfbd_smoothness_gamma,
                    momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
                    momfbd_object_estimate, momfbd_profile_start,
@@ -17,6 +18,7 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
 __all__ = [
     "MomfbdError", "LIB_PATH", "momfbd_status_string", "momfbd_plan_create",
     "momfbd_plan_destroy", "momfbd_workspace_size", "momfbd_plan_dims", "momfbd_smoothness_gamma",
+    "momfbd_object_filtered", "momfbd_mosaic", "filter_spec",
     "momfbd_prepare_data",
     "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",
     "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init", "momfbd_lbfgs_step",

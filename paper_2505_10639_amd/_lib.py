@@ -34,6 +34,14 @@ class momfbd_lbfgs_params(ctypes.Structure):
                 ("c2", ctypes.c_double), ("ftol", ctypes.c_double)]
 
 
+MOMFBD_FILTER_NONE, MOMFBD_FILTER_TOPHAT, MOMFBD_FILTER_SCHARMER = 0, 1, 2
+
+
+class momfbd_filter(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("f_lo", ctypes.c_float), ("f_hi", ctypes.c_float),
+                ("diff_limit", ctypes.c_float), ("noise_power", ctypes.c_float)]
+
+
 class momfbd_desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int),
                 ("K", ctypes.c_int), ("J", ctypes.c_int), ("M", ctypes.c_int),
@@ -65,6 +73,9 @@ def lib():
         L.momfbd_status_string.argtypes = [i]
         L.momfbd_status_string.restype = ctypes.c_char_p
         L.momfbd_plan_dims.argtypes = [_vp] + [ctypes.POINTER(i)] * 6
+        L.momfbd_object_filtered.argtypes = [_vp, _vp, _vp, _vp, f, _vp,
+                                             ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
+        L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
         pp = ctypes.POINTER(momfbd_lbfgs_params)
@@ -77,7 +88,8 @@ def lib():
                      "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
                      "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
-                     "momfbd_lbfgs_step", "momfbd_smoothness_gamma"):
+                     "momfbd_lbfgs_step", "momfbd_smoothness_gamma", "momfbd_object_filtered",
+                     "momfbd_mosaic"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -173,6 +185,27 @@ def momfbd_object_estimate(plan, alpha, D, gamma, gamma_scalar, weights, obj, ws
     _check(lib().momfbd_object_estimate(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
                                         float(gamma_scalar), _ptr(weights), _ptr(obj), _ptr(ws),
                                         _stream(stream, alpha)), "momfbd_object_estimate")
+
+
+def filter_spec(kind, f_lo=0.0, f_hi=0.0, diff_limit=0.0, noise_power=0.0):
+    """One object's filter: kind "none", "tophat" or "scharmer"."""
+    k = {"none": MOMFBD_FILTER_NONE, "tophat": MOMFBD_FILTER_TOPHAT,
+         "scharmer": MOMFBD_FILTER_SCHARMER}[kind]
+    return momfbd_filter(k, f_lo, f_hi, diff_limit, noise_power)
+
+
+def momfbd_object_filtered(plan, alpha, D, gamma, gamma_scalar, weights, filters, obj, H, ws,
+                           stream=None):
+    arr = (momfbd_filter * len(filters))(*filters)
+    _check(lib().momfbd_object_filtered(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
+                                        float(gamma_scalar), _ptr(weights), arr, _ptr(obj),
+                                        _ptr(H), _ptr(ws), _stream(stream, alpha)),
+           "momfbd_object_filtered")
+
+
+def momfbd_mosaic(plan, obj, ny, nx, stride, border, out, stream=None):
+    _check(lib().momfbd_mosaic(plan, _ptr(obj), int(ny), int(nx), int(stride), int(border),
+                               _ptr(out), _stream(stream, obj)), "momfbd_mosaic")
 
 
 def momfbd_profile_start(plan, max_launches: int):

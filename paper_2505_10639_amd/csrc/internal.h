@@ -46,6 +46,22 @@ struct PriorTab {
 };
 hipError_t launch_smoothness(int N, int K, const PriorTab& t, float* gamma, hipStream_t s);
 
+// Fourier filter of one object's restored spectrum.
+constexpr int kFilterNone = 0, kFilterTophat = 1, kFilterScharmer = 2;
+struct FilterSpec {
+  int kind;
+  float f_lo, f_hi, diff_limit;   // top-hat (units of the diffraction limit; bins)
+  float noise_power;              // Loefdahl-Scharmer
+};
+struct FilterTab {
+  FilterSpec f[kMaxK];
+};
+hipError_t launch_filter(const Dims& d, const ChanTab& ct, const FilterTab& ft, const float2* D,
+                         const float* weights, const float2* S, float2* O, float* H,
+                         hipStream_t s);
+hipError_t launch_mosaic(const Dims& d, const float* obj, int ny, int nx, int stride, int border,
+                         float* out, hipStream_t s);
+
 // Workspace carve-up.
 struct Workspace {
   float* phi;              // [P][C][J][N/2][N/2]  phase in turns on the pupil band

@@ -13,9 +13,9 @@
 using namespace mfbd;
 
 enum KernelKind { KK_PHASE, KK_FORWARD, KK_OBJECT, KK_ADJOINT, KK_GRAD, KK_PREPARE, KK_OBJIMG,
-                  KK_COUNT };
+                  KK_FILTER, KK_MOSAIC, KK_COUNT };
 static const char* kKernelNames[KK_COUNT] = {"phase", "forward", "object", "adjoint", "grad",
-                                             "prepare", "objimg"};
+                                             "prepare", "objimg", "filter", "mosaic"};
 
 // Optional kernel timing: an event pair around every launch, on its stream.
 struct Profiler {
@@ -405,6 +405,58 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
   if (st) return st;
   ProfScope ps(plan, KK_OBJIMG, s);
   return to_status(launch_objimg(plan->d, w.O, obj, s));
+}
+
+int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
+                           const float* gamma, float gamma_scalar, const float* weights,
+                           const momfbd_filter* filters, float* obj, float* H, void* ws,
+                           void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || !D || !obj || !filters) return MOMFBD_EINVAL;
+  FilterTab ft;
+  std::memset(&ft, 0, sizeof(ft));
+  for (int k = 0; k < plan->d.K; ++k) {
+    const momfbd_filter& f = filters[k];
+    if (f.kind == MOMFBD_FILTER_TOPHAT) {
+      if (!(f.f_lo >= 0.f) || !(f.f_hi > f.f_lo) || !(f.diff_limit > 0.f) ||
+          !std::isfinite(f.f_hi) || !std::isfinite(f.diff_limit))
+        return MOMFBD_EINVAL;
+    } else if (f.kind == MOMFBD_FILTER_SCHARMER) {
+      if (!(f.noise_power >= 0.f) || !std::isfinite(f.noise_power)) return MOMFBD_EINVAL;
+    } else if (f.kind != MOMFBD_FILTER_NONE) {
+      return MOMFBD_EINVAL;
+    }
+    ft.f[k] = FilterSpec{f.kind, f.f_lo, f.f_hi, f.diff_limit, f.noise_power};
+  }
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Workspace w;
+  double* scratch_loss = reinterpret_cast<double*>(carve_workspace(plan->d, ws).gphi);
+  st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, scratch_loss, ws, s, &w);
+  if (st) return st;
+  hipError_t e;
+  {
+    ProfScope ps(plan, KK_FILTER, s);
+    e = launch_filter(plan->d, plan->ct, ft, static_cast<const float2*>(D), weights, w.S, w.O, H,
+                      s);
+  }
+  if (e != hipSuccess) return to_status(e);
+  ProfScope ps(plan, KK_OBJIMG, s);
+  return to_status(launch_objimg(plan->d, w.O, obj, s));
+}
+
+int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride, int border,
+                  float* out, void* stream) {
+  if (!plan || !obj || !out) return MOMFBD_EINVAL;
+  const int N = plan->d.N;
+  if (ny < 1 || nx < 1 || (long)ny * nx != plan->d.P || stride < 1 || stride > N || border < 0 ||
+      border > N / 2)
+    return MOMFBD_EINVAL;
+  int st = pending_error();
+  if (st) return st;
+  ProfScope ps(plan, KK_MOSAIC, (hipStream_t)stream);
+  return to_status(launch_mosaic(plan->d, obj, ny, nx, stride, border, out, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,206 @@
+// Post-processing of the restored objects.
+//
+//   filter : the Fourier filters of Sect. "Fourier filtering" applied to the
+//            Wiener object spectrum O_k of every (patch, object):
+//            top-hat with a cosine transition between f_l and f_u (units of
+//            the diffraction-limit frequency), or the Loefdahl-Scharmer
+//            filter H = 1 - eta sum w|S|^2 / |sum w D conj(S)|^2 (eta the
+//            noise power per frequency of a frame; the printed ratio is
+//            eta = 1) clipped (H < 0.2 -> 0, H > 1 -> 1), 3x3 median on the
+//            periodic frequency grid, and restricted to the region
+//            4-connected to the zero frequency.
+//   mosaic : sum_p w o_p / sum_p w over the patches covering each pixel, with
+//            the separable cosine taper w of Sect. "Division in patches and
+//            apodization".
+//
+// The filter works on the full N x N grid in LDS (H is symmetric under
+// u -> -u, so the half spectrum reads suffice); the island search is a
+// label propagation from the origin repeated until no label changes.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mfbd {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ inline float tophat_value(int uy, int ux, int N, const FilterSpec& f) {
+  const int sy = uy > N / 2 ? uy - N : uy, sx = ux > N / 2 ? ux - N : ux;
+  const double r = sqrt((double)(sy * sy + sx * sx)) / (double)f.diff_limit;
+  if (r <= (double)f.f_lo) return 1.f;
+  if (r >= (double)f.f_hi) return 0.f;
+  return (float)(0.5 * (1.0 + cos(kPi * (r - (double)f.f_lo) / ((double)f.f_hi - (double)f.f_lo))));
+}
+
+__device__ inline float median9(float v[9]) {
+  // insertion sort; the median is one of the inputs, so it is exact
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float x = v[i];
+    int j = i - 1;
+    while (j >= 0 && v[j] > x) {
+      v[j + 1] = v[j];
+      --j;
+    }
+    v[j + 1] = x;
+  }
+  return v[4];
+}
+
+template <int NN>
+__global__ __launch_bounds__(256) void k_filter(int C, int J, int K, ChanTab ct, FilterTab ft,
+                                                const float2* __restrict__ D,
+                                                const float* __restrict__ weights,
+                                                const float2* __restrict__ S,
+                                                float2* __restrict__ O, float* __restrict__ Hout) {
+  constexpr int HC = NN / 2 + 1, UNIT = NN * HC, GRID = NN * NN;
+  extern __shared__ float lds[];
+  float* A = lds;          // clipped H, then the labels
+  float* B = lds + GRID;   // median-filtered H
+  __shared__ int changed;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x / K, k = blockIdx.x % K;
+  const FilterSpec f = ft.f[k];
+  float2* Ok = O + ((size_t)p * K + k) * UNIT;
+  float* Hk = Hout ? Hout + ((size_t)p * K + k) * UNIT : nullptr;
+  if (f.kind != kFilterScharmer) {
+    for (int i = tid; i < UNIT; i += 256) {
+      const float h = f.kind == kFilterTophat ? tophat_value(i / HC, i % HC, NN, f) : 1.f;
+      float2 o = Ok[i];
+      Ok[i] = make_float2(o.x * h, o.y * h);
+      if (Hk) Hk[i] = h;
+    }
+    return;
+  }
+  const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
+  for (int i = tid; i < GRID; i += 256) {
+    const int y = i / NN, x = i % NN;
+    // a frequency right of the half spectrum reads its mirror -u (the
+    // conjugate pair gives the same |num| and den)
+    const int hy = x > NN / 2 ? (NN - y) % NN : y, hx = x > NN / 2 ? NN - x : x;
+    const size_t off = (size_t)hy * HC + hx;
+    double nr = 0.0, ni = 0.0, den = 0.0;
+    for (int ci = c0; ci < c1; ++ci) {
+      const int c = ct.obj_chans[ci];
+      for (int j = 0; j < J; ++j) {
+        const size_t u = ((size_t)(p * C + c) * J + j) * UNIT + off;
+        const double w = weights ? (double)weights[c * J + j] : 1.0;
+        const float2 d = D[u], s = S[u];
+        nr += w * ((double)d.x * s.x + (double)d.y * s.y);
+        ni += w * ((double)d.y * s.x - (double)d.x * s.y);
+        den += w * ((double)s.x * s.x + (double)s.y * s.y);
+      }
+    }
+    const double mag = nr * nr + ni * ni;
+    double h = mag > 0.0 ? 1.0 - (double)f.noise_power * den / mag : 0.0;
+    h = h < 0.2 ? 0.0 : (h > 1.0 ? 1.0 : h);
+    A[i] = (float)h;
+  }
+  __syncthreads();
+  for (int i = tid; i < GRID; i += 256) {
+    const int y = i / NN, x = i % NN;
+    float v[9];
+    int n = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx)
+        v[n++] = A[((y + dy + NN) % NN) * NN + (x + dx + NN) % NN];
+    B[i] = median9(v);
+  }
+  __syncthreads();
+  int* L = reinterpret_cast<int*>(A);
+  for (int i = tid; i < GRID; i += 256) L[i] = (i == 0 && B[0] > 0.f) ? 1 : 0;
+  __syncthreads();
+  // labels only go from 0 to 1, so concurrent sweeps reach the same fixed
+  // point; every pass that changes something adds a cell, so at most GRID
+  // passes run
+  for (int it = 0; it < GRID; ++it) {
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    int ch = 0;
+    for (int i = tid; i < GRID; i += 256) {
+      if (L[i] || !(B[i] > 0.f)) continue;
+      const int y = i / NN, x = i % NN;
+      if (L[((y + 1) % NN) * NN + x] | L[((y + NN - 1) % NN) * NN + x] |
+          L[y * NN + (x + 1) % NN] | L[y * NN + (x + NN - 1) % NN]) {
+        L[i] = 1;
+        ch = 1;
+      }
+    }
+    if (ch) atomicOr(&changed, 1);
+    __syncthreads();
+    const int go = changed;
+    __syncthreads();
+    if (!go) break;
+  }
+  for (int i = tid; i < UNIT; i += 256) {
+    const int g = (i / HC) * NN + i % HC;
+    const float h = L[g] ? B[g] : 0.f;
+    float2 o = Ok[i];
+    Ok[i] = make_float2(o.x * h, o.y * h);
+    if (Hk) Hk[i] = h;
+  }
+}
+
+__device__ inline double taper1(int x, int N, int b) {
+  const int e = min(x, N - 1 - x);
+  return e < b ? 0.5 * (1.0 - cos(kPi * (e + 0.5) / b)) : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_mosaic(int N, int K, int nx, int ny, int stride,
+                                                int border, int Hm, int Wm,
+                                                const float* __restrict__ obj,
+                                                float* __restrict__ out) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)K * Hm * Wm) return;
+  const int k = (int)(idx / ((long)Hm * Wm));
+  const int r = (int)(idx % ((long)Hm * Wm));
+  const int y = r / Wm, x = r % Wm;
+  const int ly = y - N + 1, lx = x - N + 1;
+  const int iy0 = ly <= 0 ? 0 : (ly + stride - 1) / stride, iy1 = min(ny - 1, y / stride);
+  const int ix0 = lx <= 0 ? 0 : (lx + stride - 1) / stride, ix1 = min(nx - 1, x / stride);
+  double acc = 0.0, ws = 0.0;
+  for (int iy = iy0; iy <= iy1; ++iy) {
+    const int ey = y - iy * stride;
+    const double wy = taper1(ey, N, border);
+    for (int ix = ix0; ix <= ix1; ++ix) {
+      const int ex = x - ix * stride;
+      const double w = wy * taper1(ex, N, border);
+      acc += w * (double)obj[(((size_t)(iy * nx + ix) * K + k) * N + ey) * N + ex];
+      ws += w;
+    }
+  }
+  out[idx] = (float)(acc / ws);
+}
+
+}  // namespace
+
+hipError_t launch_filter(const Dims& d, const ChanTab& ct, const FilterTab& ft, const float2* D,
+                         const float* weights, const float2* S, float2* O, float* H,
+                         hipStream_t s) {
+  const size_t lds = 2 * (size_t)d.N * d.N * sizeof(float);
+  if (d.N == 64) {
+    hipLaunchKernelGGL(k_filter<64>, dim3(d.P * d.K), dim3(256), lds, s, d.C, d.J, d.K, ct, ft,
+                       D, weights, S, O, H);
+  } else {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter<128>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_filter<128>, dim3(d.P * d.K), dim3(256), lds, s, d.C, d.J, d.K, ct, ft,
+                       D, weights, S, O, H);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mosaic(const Dims& d, const float* obj, int ny, int nx, int stride, int border,
+                         float* out, hipStream_t s) {
+  const int Hm = (ny - 1) * stride + d.N, Wm = (nx - 1) * stride + d.N;
+  const long n = (long)d.K * Hm * Wm;
+  hipLaunchKernelGGL(k_mosaic, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.N, d.K, nx,
+                     ny, stride, border, Hm, Wm, obj, out);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

@@ -50,6 +50,33 @@ class Plan:
             nbytes = _lib.momfbd_workspace_size(self.handle)
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
 
+    def object_filtered(self, alpha, D, filters, gamma=1e-3, weights=None, want_H=False):
+        """Restored objects [P][K][N][N] after one Fourier filter per object
+        (`filters`: K specs from filter_spec); with want_H also the filters
+        [P][K][N][N/2+1]."""
+        self._alpha(alpha)
+        self._D(D)
+        g_arr, g_sc = self._gamma(gamma)
+        self._weights(weights)
+        if len(filters) != self.K:
+            raise ValueError(f"{len(filters)} filters for {self.K} objects")
+        obj = torch.empty((self.P, self.K, self.N, self.N), dtype=torch.float32,
+                          device=self.device)
+        H = torch.empty((self.P, self.K) + self.half, dtype=torch.float32,
+                        device=self.device) if want_H else None
+        _lib.momfbd_object_filtered(self.handle, alpha, D, g_arr, g_sc, weights, list(filters),
+                                    obj, H, self.ws)
+        return (obj, H) if want_H else obj
+
+    def mosaic(self, obj, ny, nx, stride, border):
+        """Weighted mosaic [K][(ny-1)*stride+N][(nx-1)*stride+N] of restored
+        patches obj [P][K][N][N]."""
+        _need(obj, (self.P, self.K, self.N, self.N), torch.float32, "obj", self.device)
+        out = torch.empty((self.K, (ny - 1) * stride + self.N, (nx - 1) * stride + self.N),
+                          dtype=torch.float32, device=self.device)
+        _lib.momfbd_mosaic(self.handle, obj, ny, nx, stride, border, out)
+        return out
+
     def smoothness_gamma(self, gamma0, lam):
         """Per-frequency gamma [K][N][N/2+1] of the object smoothness prior
         for objects with constants gamma0[K] and lambda[K]."""

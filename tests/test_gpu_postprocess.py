@@ -1,0 +1,95 @@
+"""GPU parity of the object post-processing (Fourier filters, mosaic)
+against the FP64 oracle, through the C-ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import OBJ_RMS, simulate_D
+from oracle import postprocess as pp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2505_10639_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def make_plan(pr, dev):
+    from paper_2505_10639_amd import Plan
+    return Plan(pr.N, pr.P, pr.J, pr.channel_object, pr.pupil, pr.basis, pr.diversity, dev)
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_tophat_and_scharmer_filters(dev, N):
+    from paper_2505_10639_amd import filter_spec
+    pr = synth.make_problem(60 + N, N=N, P=2, J=4, M=20, channels=((0, 0.0), (0, 1.0), (1, 0.0)),
+                            d_over_r0=np.array([7.0, 12.0]))
+    D_np = simulate_D(pr)
+    plan = make_plan(pr, dev)
+    # noise power of the apodized 1% noise per frequency bin, 10% stronger
+    eta = 1.1e-4 * float(np.sum(pr.window.astype(np.float64) ** 2))
+    dl = 0.45 * N
+    filters = [filter_spec("tophat", 0.55, 0.7, dl), filter_spec("scharmer", noise_power=eta)]
+    a = pr.alpha_true
+    print(f"[filters] N={N} eta={eta:.4f}", flush=True)
+    obj, H = plan.object_filtered(torch.from_numpy(a).to(dev), torch.from_numpy(D_np).to(dev),
+                                  filters, pr.gamma, want_H=True)
+    plain = plan.object_estimate(torch.from_numpy(a).to(dev), torch.from_numpy(D_np).to(dev),
+                                 pr.gamma)
+    torch.cuda.synchronize()
+    obj, H, plain = obj.cpu().numpy(), H.cpu().numpy(), plain.cpu().numpy()
+    hc = N // 2 + 1
+    w = np.ones((pr.C, pr.J))
+    Ht = pp.tophat_filter(N, 0.55, 0.7, dl)
+    for p in range(pr.P):
+        r = oracle.evaluate_patch(a[p], D_np[p], pr.basis, pr.diversity, pr.pupil,
+                                  pr.channel_object, pr.gamma, want_grad=False)
+        Dfull = oracle.expand_half(D_np[p], N)
+        raw = pp.scharmer_raw(Dfull, r["S"], w, [2], eta)
+        # the clip decision is taken in FP64 on both sides from OTFs that
+        # agree to FP32 rounding: the case needs no value next to the threshold
+        assert np.min(np.abs(raw - 0.2)) > 5e-5
+        Hs = pp.scharmer_filter(Dfull, r["S"], w, [2], eta)
+        assert 0 < np.count_nonzero(Hs) < Hs.size // 2
+        np.testing.assert_allclose(H[p, 0], Ht[:, :hc], atol=1e-6)
+        np.testing.assert_array_equal(H[p, 1] > 0, Hs[:, :hc] > 0)
+        np.testing.assert_allclose(H[p, 1], Hs[:, :hc], atol=1e-4)
+        for k, Hk in ((0, Ht), (1, Hs)):
+            ref = pp.filtered_object(r["O"][k], Hk)
+            rms = np.sqrt(np.mean((obj[p, k] - ref) ** 2))
+            assert rms < OBJ_RMS, (p, k, rms)
+    # no filter: the Wiener object itself, bit for bit
+    obj0 = plan.object_filtered(torch.from_numpy(a).to(dev), torch.from_numpy(D_np).to(dev),
+                                [filter_spec("none")] * 2, pr.gamma)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(obj0.cpu().numpy(), plain)
+    plan.close()
+
+
+@pytest.mark.parametrize("N,stride,border", [(64, 32, 8), (128, 64, 12), (64, 24, 0)])
+def test_mosaic(dev, N, stride, border):
+    ny, nx = 3, 4
+    pr = synth.make_problem(70, N=N, P=ny * nx, J=1, M=4, channels=((0, 0.0), (1, 0.0)))
+    plan = make_plan(pr, dev)
+    rng = np.random.default_rng(N + stride)
+    obj = rng.standard_normal((pr.P, 2, N, N)).astype(np.float32) + 1.0
+    out = plan.mosaic(torch.from_numpy(obj).to(dev), ny, nx, stride, border).cpu().numpy()
+    for k in range(2):
+        ref = pp.mosaic(obj[:, k].astype(np.float64), ny, nx, stride, border)
+        np.testing.assert_allclose(out[k], ref, rtol=2e-6, atol=2e-6)
+    # patches cut from one image reassemble that image
+    img = rng.standard_normal((2, (ny - 1) * stride + N, (nx - 1) * stride + N)).astype(np.float32)
+    cut = np.stack([img[:, i * stride:i * stride + N, x * stride:x * stride + N]
+                    for i in range(ny) for x in range(nx)])
+    out = plan.mosaic(torch.from_numpy(np.ascontiguousarray(cut)).to(dev), ny, nx, stride,
+                      border).cpu().numpy()
+    np.testing.assert_allclose(out, img, rtol=1e-6, atol=1e-6)
+    plan.close()

@@ -97,3 +97,6 @@ def test_calls_reject_null_plan_and_workspace(L):
     n = ctypes.c_size_t()
     assert L.momfbd_workspace_size(None, ctypes.byref(n)) == -1
     assert L.momfbd_smoothness_gamma(None, None, None, None, None) == -1
+    assert L.momfbd_mosaic(None, None, 1, 1, 1, 0, None, None) == -1
+    assert L.momfbd_object_filtered(None, None, None, None, 1e-3, None, None, None, None, None,
+                                    None) == -1
