@@ -230,6 +230,62 @@ int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
                       float* alpha, const void* D, const float* gamma, float gamma_scalar,
                       const float* weights, double* loss, int* status, void* ws, void* stream);
 
+/* Synthetic bursts through the forward model (Eq. generative_model):
+ * per patch p, channel c, frame j the frame i = o_k * s_pcj + sigma_p n
+ * (circular convolution of the object o_k of the channel with the PSF of
+ * alpha[p][j]), then D = DFT(W(i - m) + m) as momfbd_prepare_data.
+ *   alpha   [P][J][M] float (device)
+ *   O       [P][K][N][N/2+1] complex64 (device): object spectra DFT(o)
+ *   noise   [P][C][J][N][N] float (device): standard normal draws
+ *   sigma   [P] float (device): noise standard deviation per patch
+ *   apod    [N][N] float (device)
+ *   frames  [C][J][P*N][N] float (device): receives the noisy frames
+ *   D       [P][C][J][N][N/2+1] complex64 (device): receives the spectra
+ * N = 64 only (EUNSUPPORTED otherwise).  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
+                      const float* sigma, const float* apod, float* frames, void* D, void* ws,
+                      void* stream);
+
+/* Warm-start network: a 6-layer convolutional regressor from a burst of J
+ * frames (64 x 64) to J x M modal coefficients (Noll j = 2..M+1), with
+ * bfloat16 weights and activations and FP32 accumulation on the matrix
+ * cores.  Layers: four 3x3 stride-2 convolutions (J->32->64->128->128
+ * channels, ReLU), dense 2048->512 (ReLU), dense 512->J*M, times mode_scale.
+ * The input of every burst is its data half spectra D [B][1][J][64][33]
+ * (as for momfbd_loss_grad with one channel); the network sees the
+ * apodized frames IDFT(D)/N^2, each divided by its mean.
+ * Training loss per frame: sum over modes of mode_scale_m^2 / mean(
+ * mode_scale^2) times the squared error in units of mode_scale, after
+ * removing the burst mean of the two tilt modes, taking the smaller of the
+ * errors to the target and to the target with its even-radial-order modes
+ * negated (frames cannot tell these apart without diversity, Sect.
+ * "Wavefronts"); the loss is the mean over bursts and frames.
+ * Parameters are one FP32 vector (weights [out][3][3][in] or [out][in],
+ * then biases, layer by layer); the workspace holds the bfloat16 copy used
+ * by the kernels, refreshed by momfbd_cnn_init, momfbd_cnn_load and
+ * momfbd_cnn_adam. */
+typedef struct momfbd_cnn_s* momfbd_cnn;
+/* mode_scale HOST [M] > 0; J <= 64, J*M <= 1024; batch_max bursts per call. */
+int momfbd_cnn_create(int J, int M, int batch_max, const float* mode_scale, momfbd_cnn* out);
+int momfbd_cnn_destroy(momfbd_cnn net);
+int momfbd_cnn_sizes(momfbd_cnn net, size_t* n_params, size_t* workspace_bytes);
+/* params = normals * He standard deviation per weight (biases 0; the last
+ * layer's weights 10x smaller); normals: [n_params] device draws. */
+int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* ws, void* stream);
+/* refresh the workspace's bfloat16 weights from FP32 params */
+int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, void* stream);
+/* alpha [B][J][M] float (device) predicted from D; B <= batch_max */
+int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, float* alpha,
+                       void* ws, void* stream);
+/* loss (one FP64, device) and grad [n_params] (device) for targets
+ * [B][J][M] float (device) */
+int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, const float* target,
+                         int B, double* loss, float* grad, void* ws, void* stream);
+/* one Adam step (FP32 moments m1, m2 [n_params]; step >= 1) */
+int momfbd_cnn_adam(momfbd_cnn net, float* params, const float* grad, float* m1, float* m2,
+                    int step, float lr, float beta1, float beta2, float eps, void* ws,
+                    void* stream);
+
 /* Kernel timing for measurement.  After momfbd_profile_start, every kernel
  * launched by this plan's calls (up to max_launches launches) is bracketed
  * by a pair of HIP events recorded on the call's stream.  Events are created

@@ -9,6 +9,9 @@ the library; the first call does, and fails loudly if it is not built.
 from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_create,
                    momfbd_plan_destroy, momfbd_workspace_size, momfbd_plan_dims,
                    momfbd_object_filtered, momfbd_mosaic, filter_spec,
+                   momfbd_synthesize, momfbd_cnn_create, momfbd_cnn_destroy,
+                   momfbd_cnn_sizes, momfbd_cnn_init, momfbd_cnn_load, momfbd_cnn_forward,
+                   momfbd_cnn_loss_grad, momfbd_cnn_adam,
                    momfbd_smoothness_gamma,
                    momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
                    momfbd_object_estimate, momfbd_profile_start,
@@ -18,7 +21,10 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
 __all__ = [
     "MomfbdError", "LIB_PATH", "momfbd_status_string", "momfbd_plan_create",
     "momfbd_plan_destroy", "momfbd_workspace_size", "momfbd_plan_dims", "momfbd_smoothness_gamma",
-    "momfbd_object_filtered", "momfbd_mosaic", "filter_spec",
+    "momfbd_object_filtered", "momfbd_mosaic", "filter_spec", "momfbd_synthesize",
+    "momfbd_cnn_create", "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
+    "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad", "momfbd_cnn_adam",
+    "WarmStartNet",
     "momfbd_prepare_data",
     "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",
     "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init", "momfbd_lbfgs_step",
@@ -31,6 +37,9 @@ def __getattr__(name):
     if name in ("Plan", "Solver"):
         from . import plan
         return getattr(plan, name)
+    if name == "WarmStartNet":
+        from . import warmstart
+        return warmstart.WarmStartNet
     if name in ("MomfbdLoss", "momfbd_loss"):
         from . import autograd
         return getattr(autograd, name)

@@ -76,6 +76,16 @@ def lib():
         L.momfbd_object_filtered.argtypes = [_vp, _vp, _vp, _vp, f, _vp,
                                              ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
         L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
+        L.momfbd_synthesize.argtypes = [_vp] * 10
+        L.momfbd_cnn_create.argtypes = [i, i, i, _vp, ctypes.POINTER(_vp)]
+        L.momfbd_cnn_destroy.argtypes = [_vp]
+        L.momfbd_cnn_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+        L.momfbd_cnn_init.argtypes = [_vp] * 5
+        L.momfbd_cnn_load.argtypes = [_vp] * 4
+        L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, _vp, _vp, _vp]
+        L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp]
+        L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
         pp = ctypes.POINTER(momfbd_lbfgs_params)
@@ -89,7 +99,10 @@ def lib():
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
                      "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
                      "momfbd_lbfgs_step", "momfbd_smoothness_gamma", "momfbd_object_filtered",
-                     "momfbd_mosaic"):
+                     "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
+                     "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
+                     "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
+                     "momfbd_cnn_adam"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -206,6 +219,57 @@ def momfbd_object_filtered(plan, alpha, D, gamma, gamma_scalar, weights, filters
 def momfbd_mosaic(plan, obj, ny, nx, stride, border, out, stream=None):
     _check(lib().momfbd_mosaic(plan, _ptr(obj), int(ny), int(nx), int(stride), int(border),
                                _ptr(out), _stream(stream, obj)), "momfbd_mosaic")
+
+
+def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=None):
+    _check(lib().momfbd_synthesize(plan, _ptr(alpha), _ptr(O), _ptr(noise), _ptr(sigma),
+                                   _ptr(apod), _ptr(frames), _ptr(D), _ptr(ws),
+                                   _stream(stream, alpha)), "momfbd_synthesize")
+
+
+def momfbd_cnn_create(J, M, batch_max, mode_scale):
+    sc = np.ascontiguousarray(mode_scale, np.float32)
+    out = _vp()
+    _check(lib().momfbd_cnn_create(int(J), int(M), int(batch_max), sc.ctypes.data,
+                                   ctypes.byref(out)), "momfbd_cnn_create")
+    return out.value
+
+
+def momfbd_cnn_destroy(net):
+    _check(lib().momfbd_cnn_destroy(net), "momfbd_cnn_destroy")
+
+
+def momfbd_cnn_sizes(net):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().momfbd_cnn_sizes(net, ctypes.byref(a), ctypes.byref(b)), "momfbd_cnn_sizes")
+    return a.value, b.value
+
+
+def momfbd_cnn_init(net, normals, params, ws, stream=None):
+    _check(lib().momfbd_cnn_init(net, _ptr(normals), _ptr(params), _ptr(ws),
+                                 _stream(stream, params)), "momfbd_cnn_init")
+
+
+def momfbd_cnn_load(net, params, ws, stream=None):
+    _check(lib().momfbd_cnn_load(net, _ptr(params), _ptr(ws), _stream(stream, params)),
+           "momfbd_cnn_load")
+
+
+def momfbd_cnn_forward(net, params, D, B, alpha, ws, stream=None):
+    _check(lib().momfbd_cnn_forward(net, _ptr(params), _ptr(D), int(B), _ptr(alpha), _ptr(ws),
+                                    _stream(stream, params)), "momfbd_cnn_forward")
+
+
+def momfbd_cnn_loss_grad(net, params, D, target, B, loss, grad, ws, stream=None):
+    _check(lib().momfbd_cnn_loss_grad(net, _ptr(params), _ptr(D), _ptr(target), int(B),
+                                      _ptr(loss), _ptr(grad), _ptr(ws), _stream(stream, params)),
+           "momfbd_cnn_loss_grad")
+
+
+def momfbd_cnn_adam(net, params, grad, m1, m2, step, lr, beta1, beta2, eps, ws, stream=None):
+    _check(lib().momfbd_cnn_adam(net, _ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step),
+                                 float(lr), float(beta1), float(beta2), float(eps), _ptr(ws),
+                                 _stream(stream, params)), "momfbd_cnn_adam")
 
 
 def momfbd_profile_start(plan, max_launches: int):

@@ -260,7 +260,52 @@ __global__ __launch_bounds__(64) void k_objimg64(int items, const float2* __rest
   }
 }
 
+// Synthetic frames: i = IDFT(O_k S_u) / N^2 + sigma_p n_u for unit u = (p, c, j),
+// written to the field layout [C][J][P*N][N] that the prepare kernel reads
+// with a patch grid of one column (stride N).
+__global__ __launch_bounds__(64) void k_synth64(int units, int P, int C, int J, int K, ChanTab ct,
+                                                const float2* __restrict__ O,
+                                                const float2* __restrict__ S,
+                                                const float* __restrict__ noise,
+                                                const float* __restrict__ sigma,
+                                                float* __restrict__ field) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int lane = threadIdx.x;
+  const int j = u % J, c = (u / J) % C, p = u / (J * C);
+  const float2* Ok = O + ((size_t)p * K + ct.chan_obj[c]) * kUnitF2;
+  const float2* Su = S + (size_t)u * kUnitF2;
+  auto cmul = [](float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+  float2 X[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) X[m] = cmul(Ok[sl_index(lane, m)], Su[sl_index(lane, m)]);
+  op3_gather(cmul(Ok[sl_index32(lane)], Su[sl_index32(lane)]), Taux, lane);
+  wave_sync();
+  op3_cols(X, Taux, T, lane);
+  wave_sync();
+  float ge[32], go[32];
+  op3_rows(T, lane, ge, go);
+  const float inv = 1.0f / (N * N), sg = sigma[p];
+  const float* nz = noise + ((size_t)u * N + lane) * N;
+  float* row = field + (((size_t)(c * J + j) * P + p) * N + lane) * N;
+#pragma unroll
+  for (int n = 0; n < 32; ++n) {
+    row[2 * n] = ge[n] * inv + sg * nz[2 * n];
+    row[2 * n + 1] = go[n] * inv + sg * nz[2 * n + 1];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_synth64(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                          const float* noise, const float* sigma, float* field, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  hipLaunchKernelGGL(k_synth64, dim3(units), dim3(64), 0, s, units, d.P, d.C, d.J, d.K, ct, O, S,
+                     noise, sigma, field);
+  return hipGetLastError();
+}
 
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                             const float* phi, float* psf, float2* S, hipStream_t s) {

@@ -446,6 +446,27 @@ int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
   return to_status(launch_objimg(plan->d, w.O, obj, s));
 }
 
+int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
+                      const float* sigma, const float* apod, float* frames, void* D, void* ws,
+                      void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || !O || !noise || !sigma || !apod || !frames || !D) return MOMFBD_EINVAL;
+  if (plan->d.N != 64) return MOMFBD_EUNSUPPORTED;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Workspace w = carve_workspace(plan->d, ws);
+  const int N = plan->d.N;
+  hipError_t e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+  if (e == hipSuccess) e = launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
+  if (e == hipSuccess)
+    e = launch_synth64(plan->d, plan->ct, static_cast<const float2*>(O), w.S, noise, sigma, frames,
+                       s);
+  if (e == hipSuccess)
+    e = launch_prepare(plan->d, frames, plan->d.P * N, N, N, apod, static_cast<float2*>(D), s);
+  return to_status(e);
+}
+
 int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride, int border,
                   float* out, void* stream) {
   if (!plan || !obj || !out) return MOMFBD_EINVAL;

@@ -77,6 +77,21 @@ class Plan:
         _lib.momfbd_mosaic(self.handle, obj, ny, nx, stride, border, out)
         return out
 
+    def synthesize(self, alpha, O, noise, sigma, apod):
+        """Bursts through the forward model: returns (frames [C][J][P*N][N],
+        D [P][C][J][N][N/2+1])."""
+        self._alpha(alpha)
+        _need(O, (self.P, self.K) + self.half, torch.complex64, "O", self.device)
+        _need(noise, (self.P, self.C, self.J, self.N, self.N), torch.float32, "noise", self.device)
+        _need(sigma, (self.P,), torch.float32, "sigma", self.device)
+        _need(apod, (self.N, self.N), torch.float32, "apod", self.device)
+        frames = torch.empty((self.C, self.J, self.P * self.N, self.N), dtype=torch.float32,
+                             device=self.device)
+        D = torch.empty((self.P, self.C, self.J) + self.half, dtype=torch.complex64,
+                        device=self.device)
+        _lib.momfbd_synthesize(self.handle, alpha, O, noise, sigma, apod, frames, D, self.ws)
+        return frames, D
+
     def smoothness_gamma(self, gamma0, lam):
         """Per-frequency gamma [K][N][N/2+1] of the object smoothness prior
         for objects with constants gamma0[K] and lambda[K]."""

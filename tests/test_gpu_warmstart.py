@@ -1,0 +1,145 @@
+"""GPU parity of the burst synthesizer and the warm-start network (forward,
+loss and every parameter gradient) against the FP64 oracles, through the
+C-ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import fast_simulate_D
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LAYERS = [("conv", 12, 32), ("conv", 32, 64), ("conv", 64, 128), ("conv", 128, 128),
+          ("dense", 2048, 512), ("dense", 512, 12 * 44)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2505_10639_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    a = a.astype(np.complex128 if np.iscomplexobj(a) else np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_synthesize_matches_oracle(dev):
+    from paper_2505_10639_amd import Plan
+    pr = synth.make_problem(80, N=64, P=3, J=5, M=20, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=np.array([6.0, 10.0, 16.0]))
+    plan = Plan(64, pr.P, pr.J, pr.channel_object, pr.pupil, pr.basis, pr.diversity, dev)
+    rng = np.random.default_rng(3)
+    normals = rng.standard_normal((pr.P, pr.C, pr.J, 64, 64)).astype(np.float32)
+    sigma = np.array([0.01, 0.02, 0.005], np.float32)
+    O_in = np.fft.fft2(pr.objects)[..., :33].astype(np.complex64)       # input spectra
+    frames, D = plan.synthesize(torch.from_numpy(pr.alpha_true).to(dev),
+                                torch.from_numpy(O_in).to(dev), torch.from_numpy(normals).to(dev),
+                                torch.from_numpy(sigma).to(dev),
+                                torch.from_numpy(pr.window).to(dev))
+    torch.cuda.synchronize()
+    frames = frames.cpu().numpy().reshape(pr.C, pr.J, pr.P, 64, 64).transpose(2, 0, 1, 3, 4)
+    noise = normals.astype(np.float64) * sigma[:, None, None, None, None]
+    ref = oracle.simulate_frames(pr.objects, pr.alpha_true, pr.basis, pr.diversity, pr.pupil,
+                                 pr.channel_object, noise)
+    assert rel(frames, ref) < 1e-5
+    D_ref = oracle.patch_spectra(ref, pr.window)
+    assert rel(D.cpu().numpy(), D_ref) < 1e-5
+    plan.close()
+
+
+def _he_params(net, rng):
+    out = []
+    for kind, a, b in net.layers:
+        k = 9 * a if kind == "conv" else a
+        out.append(rng.standard_normal(b * k) * np.sqrt(2.0 / k))
+        out.append(0.05 * rng.standard_normal(b))
+    return np.concatenate(out).astype(np.float32)
+
+
+def test_network_matches_oracle(dev):
+    from paper_2505_10639_amd import WarmStartNet
+    from paper_2505_10639_amd.warmstart import mode_scale
+    J, M, B = 12, 44, 3
+    pr = synth.make_problem(81, N=64, P=B, J=J, M=M, d_over_r0=np.array([5.0, 10.0, 15.0]))
+    D_np = fast_simulate_D(pr)
+    scale = mode_scale(M)
+    onet = cnn.Network(LAYERS)
+    params = _he_params(onet, np.random.default_rng(4))
+    net = WarmStartNet(J, M, scale, batch_max=4, device=dev)
+    assert net.n_params == onet.count() == params.size
+    net.load(torch.from_numpy(params).to(dev))
+    D = torch.from_numpy(D_np).to(dev)
+    frames = oracle.idft2_un(oracle.expand_half(D_np[:, 0], 64)).real / 4096.0
+    x = cnn.normalize_frames(frames)
+    even = cnn.even_mode_mask(M)
+    p64 = params.astype(np.float64)
+    # Targets with an unambiguous per-frame choice between the target and its
+    # even-mode flip (the loss takes that choice by comparing two sums): the
+    # oracle's own prediction, flipped on every third frame, plus noise.
+    p_o = onet.forward(x, p64, bf16=True)[0][-1].reshape(B, J, M)
+    rng = np.random.default_rng(6)
+    flip = np.where((np.arange(J) % 3 == 0)[None, :, None] & even[None, None, :], -1.0, 1.0)
+    t_n = p_o * flip + 0.4 * np.std(p_o) * rng.standard_normal(p_o.shape)
+    wt = scale.astype(np.float64) ** 2 / np.mean(scale.astype(np.float64) ** 2)
+    _, _, use2 = cnn.burst_loss(p_o, t_n, even, weight=wt)
+    q = t_n.copy()
+    q[:, :, :2] -= q[:, :, :2].mean(axis=1, keepdims=True)
+    pc = p_o.copy()
+    pc[:, :, :2] -= pc[:, :, :2].mean(axis=1, keepdims=True)
+    e1 = np.sum(wt * (pc - q) ** 2, axis=2)
+    e2 = np.sum(wt * (pc - q * np.where(even, -1.0, 1.0)) ** 2, axis=2)
+    assert np.all(np.abs(e1 - e2) > 0.2 * (e1 + e2)) and use2.any() and not use2.all()
+    target = (t_n * scale).astype(np.float32)
+    loss, grad = net.loss_grad(D, torch.from_numpy(target).to(dev))
+    pred = net.predict(D)
+    torch.cuda.synchronize()
+    loss, grad, pred = float(loss.cpu()[0]), grad.cpu().numpy(), pred.cpu().numpy()
+    l_o, g_o, _ = onet.loss_grad(x, p64, target / scale, even, bf16=True, weight=wt)
+    print(f"[cnn] loss gpu {loss:.6g} oracle {l_o:.6g}", flush=True)
+    assert rel(pred, p_o * scale) < 1e-2
+    assert abs(loss - l_o) < 1e-2 * abs(l_o)
+    # Each of the six layers rounds its activations (forward) and its
+    # activation gradients (backward) to bfloat16, a relative step of 2^-8;
+    # FP32 and FP64 accumulation can round a value to neighbouring bfloat16
+    # numbers, so each rounding point may add up to 2^-8 of relative
+    # discrepancy: 6 x 2 x 2^-8 = 4.7e-2 for the gradient of the first layer.
+    errs, o = [], 0
+    for (kind, a, b) in LAYERS:
+        nw = b * (9 * a if kind == "conv" else a)
+        for name, n, tol in (("w", nw, 4.7e-2), ("b", b, 4.7e-2)):
+            errs.append((kind, a, b, name, rel(grad[o:o + n], g_o[o:o + n]), tol))
+            o += n
+    print("[cnn] gradient errors", [(k, a, b, n, f"{e:.2e}") for k, a, b, n, e, _ in errs],
+          flush=True)
+    assert all(e < tol for *_, e, tol in errs), errs
+    net.close()
+
+
+def test_training_reduces_loss_and_is_reproducible(dev):
+    """A few Adam steps on fixed bursts lower the loss; two runs from the
+    same start give the same bits."""
+    from paper_2505_10639_amd import WarmStartNet
+    from paper_2505_10639_amd.warmstart import mode_scale
+    J, M, B = 12, 44, 8
+    pr = synth.make_problem(82, N=64, P=B, J=J, M=M, d_over_r0=8.0)
+    D = torch.from_numpy(fast_simulate_D(pr)).to(dev)
+    tgt = torch.from_numpy(pr.alpha_true).to(dev)
+    runs = []
+    for _ in range(2):
+        net = WarmStartNet(J, M, mode_scale(M), batch_max=B, device=dev)
+        net.init(seed=11)
+        hist = [float(net.train_step(D, tgt, 1e-3).cpu()[0]) for _ in range(30)]
+        runs.append((hist, net.params.cpu().numpy()))
+        net.close()
+    assert runs[0][0][-1] < 0.5 * runs[0][0][0], runs[0][0]
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
