@@ -214,6 +214,67 @@ def roofline(kern_avg, units, N, D_bytes, traffic_of):
             "avg_ms": kern_avg[dom]}
 
 
+def warm_start_block(dev, steps, patches=961):
+    """Learned warm start vs the plain zero start on single-object 64x64
+    bursts (12 frames, 44 modes, D/r0 in 4..20, SNR 50..200): the network is
+    trained on the GPU for `steps` Adam steps of 256 bursts made by the
+    library's forward model; then per-patch L-BFGS from zero runs until the
+    summed loss changes by less than 1e-10 relative over 20 iterations
+    (L_conv), and both starts are timed to sum L <= 1.001 L_conv (the warm
+    start's time includes the network's inference)."""
+    import torch
+
+    import synth
+    from paper_2505_10639_amd import Plan
+    from paper_2505_10639_amd.warmstart import BurstSource, WarmStartNet, mode_scale, solve_until
+
+    J, M = 12, 44
+    tmpl = synth.make_problem(0, N=64, P=1, J=J, M=M)
+    rng = np.random.default_rng(synth.SEED_ROOT + 3)
+    scenes = [synth.object_field(rng, 768, 768) for _ in range(4)]
+    src = BurstSource(tmpl.pupil, tmpl.basis, tmpl.window, J, 256, scenes, seed=1, device=dev)
+    net = WarmStartNet(J, M, mode_scale(M), batch_max=256, device=dev)
+    net.init(seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        D, a = src.next()
+        loss = net.train_step(D, a, 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 2e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    final_train = float(loss.cpu()[0])
+    src.close()
+    ev = BurstSource(tmpl.pupil, tmpl.basis, tmpl.window, J, patches,
+                     [synth.object_field(np.random.default_rng(synth.SEED_ROOT + 6), 1024, 1024)],
+                     seed=7, device=dev)
+    D, a_true = ev.next()
+    ev.close()
+    plan = Plan(64, patches, J, [0], tmpl.pupil, tmpl.basis, None, dev)
+    zero = torch.zeros_like(a_true)
+    h_conv, t_conv, _ = solve_until(plan, zero, D, 1e-3, None, max_iter=3000, stall=20, rtol=1e-10)
+    L_conv = h_conv[-1]
+    target = 1.001 * L_conv
+    hp, tp, _ = solve_until(plan, zero, D, 1e-3, target, max_iter=3000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a0 = net.predict(D)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t1
+    hw, tw, _ = solve_until(plan, a0, D, 1e-3, target, max_iter=3000)
+    L_true = float(plan.loss_grad(a_true, D, 1e-3)[0].sum())
+    plan.close()
+    net.close()
+    return {
+        "workload": f"{patches} bursts of 12 frames 64x64, 44 modes, D/r0 4..20, SNR 50..200",
+        "train_steps": steps, "train_bursts_per_s": steps * 256 / t_train,
+        "train_loss_final": final_train, "L_conv": L_conv, "L_conv_iterations": len(h_conv) - 1,
+        "L_zero": hp[0], "L_cnn": hw[0], "L_true": L_true,
+        "plain_s_to_1.001": tp, "plain_iterations": len(hp) - 1,
+        "warm_s_to_1.001": tw + t_inf, "warm_iterations": len(hw) - 1, "inference_s": t_inf,
+        "speedup": tp / (tw + t_inf),
+    }
+
+
 def cpu_baseline(D_host, alpha_host, g, budget_s):
     """The FP64 oracle on the same workload, patch after patch, until every
     patch is done or the time budget is used."""
@@ -249,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the 128 x 128 workload")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--warm-steps", type=int, default=6000,
+                    help="training steps of the warm-start network (0: skip that block)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (for scaling "
                          "hardware byte counters) and exit")
@@ -328,6 +391,10 @@ def main():
         }
         plan4.close()
         del D4, alpha4, gamma4
+
+    if args.warm_steps > 0:
+        log(f"warm start: {args.warm_steps} training steps, then time to converged loss")
+        out["warm_start"] = warm_start_block(dev, args.warm_steps)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

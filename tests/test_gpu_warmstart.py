@@ -143,3 +143,50 @@ def test_training_reduces_loss_and_is_reproducible(dev):
     assert runs[0][0][-1] < 0.5 * runs[0][0][0], runs[0][0]
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_trained_network_gains_over_zero_start(dev):
+    """Train on forward-model bursts for a few seconds; on held-out bursts the
+    network's coefficients close most of the loss gap between the zero start
+    and the true coefficients, and L-BFGS from them stays ahead of L-BFGS
+    from zero."""
+    from paper_2505_10639_amd import Plan, WarmStartNet
+    from paper_2505_10639_amd.warmstart import BurstSource, mode_scale, solve_until
+    J, M = 12, 44
+    tmpl = synth.make_problem(0, N=64, P=1, J=J, M=M)
+    rng = np.random.default_rng(5)
+    scenes = [synth.object_field(rng, 768, 768) for _ in range(4)]
+    src = BurstSource(tmpl.pupil, tmpl.basis, tmpl.window, J, 256, scenes, seed=1, device=dev)
+    net = WarmStartNet(J, M, mode_scale(M), batch_max=256, device=dev)
+    net.init(seed=3)
+    steps = 6000
+    first = last = None
+    for it in range(steps):
+        D, a = src.next()
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 2e-5
+        loss = net.train_step(D, a, lr)
+        if it == 0:
+            first = float(loss.cpu()[0])
+        if it % 1000 == 0:
+            print(f"[train] step {it} loss {float(loss.cpu()[0]):.3f}", flush=True)
+    last = float(loss.cpu()[0])
+    src.close()
+    ev = BurstSource(tmpl.pupil, tmpl.basis, tmpl.window, J, 64,
+                     [synth.object_field(np.random.default_rng(99), 512, 512)], seed=7, device=dev)
+    D, a_true = ev.next()
+    plan = Plan(64, 64, J, [0], tmpl.pupil, tmpl.basis, None, dev)
+    zero = torch.zeros_like(a_true)
+    a0 = net.predict(D)
+    L = {k: float(plan.loss_grad(v, D, 1e-3)[0].sum()) for k, v in
+         (("zero", zero), ("cnn", a0), ("true", a_true))}
+    hp, _, _ = solve_until(plan, zero, D, 1e-3, None, max_iter=100, stall=1000)
+    hw, _, _ = solve_until(plan, a0, D, 1e-3, None, max_iter=100, stall=1000)
+    print(f"[warm] train loss {first:.2f} -> {last:.2f}; L {L}; after 20/50/100 iterations "
+          f"plain {hp[20]:.0f} {hp[50]:.0f} {hp[100]:.0f} warm {hw[20]:.0f} {hw[50]:.0f} "
+          f"{hw[100]:.0f}", flush=True)
+    assert last < 0.5 * first
+    assert L["cnn"] < L["zero"] - 0.5 * (L["zero"] - L["true"])
+    assert hw[20] < hp[20] and hw[50] < hp[50] and hw[100] < hp[100]
+    ev.close()
+    plan.close()
+    net.close()
