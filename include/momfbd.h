@@ -230,6 +230,28 @@ int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
                       float* alpha, const void* D, const float* gamma, float gamma_scalar,
                       const float* weights, double* loss, int* status, void* ws, void* stream);
 
+/* Solver rounds without host synchronisation, for HIP graph capture.  A
+ * round gives every running patch one line-search trial: a patch that is
+ * not inside a line search first starts its next iteration (two-loop
+ * direction, first trial step), then the loss and gradient of all patches
+ * inside a search are evaluated, then each advances its search (accept,
+ * next trial, or fail after max_evals trials).  Patches advance
+ * independently, so each follows the trajectory it follows under
+ * momfbd_lbfgs_step; the call enqueues a fixed sequence of kernels
+ * (rounds x (prep, evaluation, search), then publish and finish) with no
+ * read-back and no memset.
+ *   alpha           in/out: a patch inside a search holds its trial point
+ *   loss, status    [P] (device, may be NULL): last accepted loss; 0 running,
+ *                   1 converged (ftol), 2 line search failed
+ *   alpha_accepted  [P][J][M] (device, may be NULL): the last accepted
+ *                   coefficients of every patch
+ * momfbd_lbfgs_step after rounds restarts searching patches from their
+ * accepted point.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                        float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                        const float* weights, int rounds, double* loss, int* status,
+                        float* alpha_accepted, void* ws, void* stream);
+
 /* Synthetic bursts through the forward model (Eq. generative_model):
  * per patch p, channel c, frame j the frame i = o_k * s_pcj + sigma_p n
  * (circular convolution of the object o_k of the channel with the PSF of

@@ -77,6 +77,8 @@ def lib():
                                              ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
         L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
         L.momfbd_synthesize.argtypes = [_vp] * 10
+        L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, _vp, _vp,
+                                          _vp, f, _vp, i, _vp, _vp, _vp, _vp, _vp]
         L.momfbd_cnn_create.argtypes = [i, i, i, _vp, ctypes.POINTER(_vp)]
         L.momfbd_cnn_destroy.argtypes = [_vp]
         L.momfbd_cnn_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t),
@@ -102,7 +104,7 @@ def lib():
                      "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
                      "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
-                     "momfbd_cnn_adam"):
+                     "momfbd_cnn_adam", "momfbd_lbfgs_rounds"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -219,6 +221,15 @@ def momfbd_object_filtered(plan, alpha, D, gamma, gamma_scalar, weights, filters
 def momfbd_mosaic(plan, obj, ny, nx, stride, border, out, stream=None):
     _check(lib().momfbd_mosaic(plan, _ptr(obj), int(ny), int(nx), int(stride), int(border),
                                _ptr(out), _stream(stream, obj)), "momfbd_mosaic")
+
+
+def momfbd_lbfgs_rounds(plan, params, state, alpha, D, gamma, gamma_scalar, weights, rounds, loss,
+                        status, alpha_accepted, ws, stream=None):
+    _check(lib().momfbd_lbfgs_rounds(plan, ctypes.byref(params), _ptr(state), _ptr(alpha),
+                                     _ptr(D), _ptr(gamma), float(gamma_scalar), _ptr(weights),
+                                     int(rounds), _ptr(loss), _ptr(status),
+                                     _ptr(alpha_accepted), _ptr(ws), _stream(stream, alpha)),
+           "momfbd_lbfgs_rounds")
 
 
 def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=None):

@@ -124,6 +124,10 @@ hipError_t launch_lbfgs_init(const Dims& d, const LbfgsLayout& L, void* state, d
                              hipStream_t s);
 hipError_t launch_lbfgs_begin(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
                               int max_evals, hipStream_t s);
+hipError_t launch_lbfgs_prep(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                             hipStream_t s);
+hipError_t launch_lbfgs_publish(const Dims& d, const LbfgsLayout& L, void* state,
+                                const float* alpha, float* out, hipStream_t s);
 hipError_t launch_lbfgs_search(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
                                int eval, double c1, double c2, int max_evals, double ftol,
                                hipStream_t s);

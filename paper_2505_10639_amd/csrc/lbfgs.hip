@@ -119,20 +119,12 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_init(int P, LbfgsLayout L, v
   if (loss_out) loss_out[p] = h.f;
 }
 
-__global__ __launch_bounds__(kThreads) void k_lbfgs_begin(LbfgsLayout L, void* state,
-                                                          float* __restrict__ alpha,
-                                                          int max_evals) {
-  __shared__ double red[kThreads];
-  __shared__ double coef[32];
-  View v = view(L, state);
-  const int p = blockIdx.x, n = L.n, m = L.m, tid = threadIdx.x;
-  if (p == 0)
-    for (int i = tid; i <= max_evals; i += kThreads) v.counter[i] = 0;
+// Start the next iteration of patch p (status 0): two-loop direction, first
+// trial step, x0 = alpha, alpha = x0 + t0 d, active = 1.
+__device__ void begin_patch(const LbfgsLayout& L, View& v, int p, float* __restrict__ alpha,
+                            double* red, double* coef) {
+  const int n = L.n, m = L.m, tid = threadIdx.x;
   Hdr& h = v.hdr[p];
-  if (h.status != 0) {
-    if (tid == 0) v.active[p] = 0;
-    return;
-  }
   const float* g = v.g + (size_t)p * n;
   float* q = v.d + (size_t)p * n;
   float* x0 = v.x0 + (size_t)p * n;
@@ -209,6 +201,45 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_begin(LbfgsLayout L, void* s
     h.n_eval = 0;
     v.active[p] = 1;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_begin(LbfgsLayout L, void* state,
+                                                          float* __restrict__ alpha,
+                                                          int max_evals) {
+  __shared__ double red[kThreads];
+  __shared__ double coef[32];
+  View v = view(L, state);
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (p == 0)
+    for (int i = tid; i <= max_evals; i += kThreads) v.counter[i] = 0;
+  if (v.hdr[p].status != 0) {
+    if (tid == 0) v.active[p] = 0;
+    return;
+  }
+  if (v.active[p]) {
+    // left inside a line search by round mode: restart from the accepted point
+    const int n = L.n;
+    for (int i = tid; i < n; i += kThreads)
+      alpha[(size_t)p * n + i] = v.x0[(size_t)p * n + i];
+    __syncthreads();
+  }
+  begin_patch(L, v, p, alpha, red, coef);
+}
+
+// Round mode: a patch that is still running and not inside a line search
+// starts its next iteration; a patch inside a search keeps its trial point.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_prep(LbfgsLayout L, void* state,
+                                                         float* __restrict__ alpha) {
+  __shared__ double red[kThreads];
+  __shared__ double coef[32];
+  View v = view(L, state);
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (v.hdr[p].status != 0) {
+    if (tid == 0) v.active[p] = 0;
+    return;
+  }
+  if (v.active[p]) return;
+  begin_patch(L, v, p, alpha, red, coef);
 }
 
 __global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* state,
@@ -316,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* 
     for (int i = tid; i < n; i += kThreads) a[i] = (float)((double)x0[i] + tn * (double)d[i]);
     if (tid == 0) {
       h.t = tn;
-      atomicAdd(v.counter + eval, 1);
+      if (eval >= 0) atomicAdd(v.counter + eval, 1);
     }
   } else {
     // line search failed: keep the starting point and stop this patch
@@ -326,6 +357,18 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* 
       v.active[p] = 0;
     }
   }
+}
+
+// The accepted point of every patch: x0 while inside a line search.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_publish(int P, LbfgsLayout L, void* state,
+                                                            const float* __restrict__ alpha,
+                                                            float* __restrict__ out) {
+  View v = view(L, state);
+  const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+  const long n = L.n;
+  if (i >= (long)P * n) return;
+  const int p = (int)(i / n);
+  out[i] = v.active[p] ? v.x0[i] : alpha[i];
 }
 
 __global__ __launch_bounds__(kThreads) void k_lbfgs_finish(int P, LbfgsLayout L, void* state,
@@ -372,6 +415,20 @@ hipError_t launch_lbfgs_init(const Dims& d, const LbfgsLayout& L, void* state, d
 hipError_t launch_lbfgs_begin(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
                               int max_evals, hipStream_t s) {
   hipLaunchKernelGGL(k_lbfgs_begin, dim3(d.P), dim3(kThreads), 0, s, L, state, alpha, max_evals);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_prep(const Dims& d, const LbfgsLayout& L, void* state, float* alpha,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_prep, dim3(d.P), dim3(kThreads), 0, s, L, state, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_publish(const Dims& d, const LbfgsLayout& L, void* state,
+                                const float* alpha, float* out, hipStream_t s) {
+  const long n = (long)d.P * L.n;
+  hipLaunchKernelGGL(k_lbfgs_publish, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, d.P, L, state, alpha, out);
   return hipGetLastError();
 }
 

@@ -543,6 +543,36 @@ int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
   return to_status(e);
 }
 
+int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
+                        float* alpha, const void* D, const float* gamma, float gamma_scalar,
+                        const float* weights, int rounds, double* loss, int* status,
+                        float* alpha_accepted, void* ws, void* stream) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!lbfgs_params_ok(params) || !state || !alpha || !D || rounds < 0) return MOMFBD_EINVAL;
+  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  char* b = static_cast<char*>(state);
+  const int* active = reinterpret_cast<const int*>(b + L.active);
+  hipError_t e = hipSuccess;
+  for (int r = 0; e == hipSuccess && r < rounds; ++r) {
+    e = launch_lbfgs_prep(plan->d, L, state, alpha, s);
+    if (e != hipSuccess) break;
+    st = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, active,
+                       reinterpret_cast<double*>(b + L.ft), reinterpret_cast<float*>(b + L.gt), ws,
+                       s);
+    if (st) return st;
+    e = launch_lbfgs_search(plan->d, L, state, alpha, -1, params->c1, params->c2,
+                            params->max_evals, params->ftol, s);
+  }
+  if (e == hipSuccess && alpha_accepted)
+    e = launch_lbfgs_publish(plan->d, L, state, alpha, alpha_accepted, s);
+  if (e == hipSuccess) e = launch_lbfgs_finish(plan->d, L, state, loss, status, s);
+  return to_status(e);
+}
+
 }  // extern "C"
 
 static void profile_free(Profiler& pr) {

@@ -199,6 +199,14 @@ class Solver:
         _lib.momfbd_lbfgs_init(plan.handle, self.params, self.state, self.alpha, self.D,
                                self.gamma_arr, self.gamma_sc, self.weights, self.loss, plan.ws)
 
+    def rounds(self, n, alpha_accepted=None):
+        """n solver rounds (one line-search trial per running patch each)
+        with no host synchronisation; capturable in a HIP graph."""
+        _lib.momfbd_lbfgs_rounds(self.plan.handle, self.params, self.state, self.alpha, self.D,
+                                 self.gamma_arr, self.gamma_sc, self.weights, n, self.loss,
+                                 self.status, alpha_accepted, self.plan.ws)
+        return self.loss, self.status
+
     def step(self):
         _lib.momfbd_lbfgs_step(self.plan.handle, self.params, self.state, self.alpha, self.D,
                                self.gamma_arr, self.gamma_sc, self.weights, self.loss,

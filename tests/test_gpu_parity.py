@@ -264,6 +264,70 @@ def test_smoothness_prior_gamma(dev, N):
     plan.close()
 
 
+def test_lbfgs_rounds_follow_the_step_trajectories(dev):
+    """Round mode (no host read-back) runs every patch through the same
+    iterations as step mode: run both until every patch has stopped and
+    compare the accepted coefficients and losses bit for bit."""
+    from paper_2505_10639_amd import Solver
+    pr = synth.make_problem(58, N=64, P=4, J=5, M=24, d_over_r0=np.array([6.0, 9.0, 12.0, 15.0]))
+    D = to_dev(fast_simulate_D(pr), dev)
+    plan = make_plan(pr, dev)
+    x1 = torch.zeros((pr.P, pr.J, pr.M), device=dev)
+    s1 = Solver(plan, x1, D, pr.gamma, ftol=1e-4)
+    for _ in range(600):
+        _, st = s1.step()
+        if bool((st != 0).all()):
+            break
+    assert bool((s1.status != 0).all())
+    x2 = torch.zeros_like(x1)
+    out = torch.empty_like(x1)
+    s2 = Solver(plan, x2, D, pr.gamma, ftol=1e-4)
+    for _ in range(100):
+        s2.rounds(25, out)
+        if bool((s2.status != 0).all()):
+            break
+    torch.cuda.synchronize()
+    assert bool((s2.status != 0).all())
+    assert torch.equal(s1.status, s2.status)
+    assert torch.equal(s1.loss, s2.loss)
+    assert torch.equal(x1, out)
+    plan.close()
+
+
+def test_lbfgs_rounds_replay_from_a_hip_graph(dev):
+    """Rounds captured once in a HIP graph and replayed four times, with
+    other eager work in between, match eager rounds bit for bit."""
+    from paper_2505_10639_amd import Solver
+    pr = synth.make_problem(59, N=64, P=5, J=6, M=30, channels=((0, 0.0), (1, 1.0)))
+    D = to_dev(fast_simulate_D(pr), dev)
+    plan = make_plan(pr, dev)
+    xa = torch.zeros((pr.P, pr.J, pr.M), device=dev)
+    oa = torch.empty_like(xa)
+    sa = Solver(plan, xa, D, pr.gamma)
+    ref = []
+    for _ in range(4):
+        sa.rounds(5, oa)
+        torch.cuda.synchronize()
+        ref.append((oa.clone(), sa.loss.clone(), sa.status.clone()))
+    xb = torch.zeros_like(xa)
+    ob = torch.empty_like(xa)
+    sb = Solver(plan, xb, D, pr.gamma)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sb.rounds(5, ob)
+    other = to_dev(alpha_points(pr, 4)["perturbed"], dev)
+    for k in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        print(f"[graph] replay {k} loss {float(sb.loss.sum()):.6f}", flush=True)
+        assert torch.equal(ob, ref[k][0]) and torch.equal(sb.loss, ref[k][1])
+        assert torch.equal(sb.status, ref[k][2])
+        plan.loss_grad(other, D, pr.gamma)        # eager work on the same plan in between
+        torch.cuda.synchronize()
+    plan.close()
+
+
 # ------------------------------------------------------------ 128 x 128 patches
 
 def test_n128_loss_and_gradient(dev):
