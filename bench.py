@@ -275,6 +275,70 @@ def warm_start_block(dev, steps, patches=961):
     }
 
 
+def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
+    """Independent 512^2 fields with patch sizes 64 or 128 (stride N/2),
+    frame counts 6..24, 44..88 modes and 1..3 objects (one channel each),
+    D/r0 5..20: every field's solver rounds captured into one HIP graph.
+    Reports the time of one graph launch (one line-search trial for every
+    patch of every field) against the same rounds issued eagerly."""
+    import torch
+
+    import synth
+    from paper_2505_10639_amd import Plan
+    from paper_2505_10639_amd.batch import Field, FieldBatch
+
+    rng = np.random.default_rng(synth.SEED_ROOT + 8)
+    fields, units, pf = [], 0, 0
+    for i in range(n_fields):
+        N = int(rng.choice([64, 128]))
+        J = int(rng.integers(6, 25))
+        M = int(rng.integers(44, 89))
+        K = int(rng.integers(1, 4))
+        stride = N // 2
+        n = (fov - N) // stride + 1
+        P = n * n
+        ch = tuple((k, 0.0) for k in range(K))
+        pr = synth.make_problem(1000 + i, N=N, P=1, J=J, M=M, channels=ch, gamma=1e-3,
+                                border=6 if N == 64 else 12, objects=np.zeros((1, K, N, N)))
+        plan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, dev)
+        win = torch.from_numpy(pr.window).to(dev)
+        scene = torch.from_numpy(np.stack([synth.object_field(rng, fov, fov) for _ in range(K)])
+                                 .astype(np.float32)).to(dev)
+        aux = Plan(N, P, 1, list(range(K)), pr.pupil, pr.basis[:, :1], None, dev)
+        Ohat = aux.prepare_data(scene.reshape(K, 1, fov, fov).contiguous(), stride, win)
+        aux.close()
+        d_r0 = rng.uniform(5.0, 20.0)
+        a_true = synth.draw_kolmogorov(rng, P * J, M, d_r0).reshape(P, J, M).astype(np.float32)
+        _, S = plan.forward(torch.from_numpy(a_true).to(dev), want_psf=False)
+        noise = 0.01 * torch.randn((K, J, fov, fov), device=dev)
+        D = (Ohat * S + plan.prepare_data(noise, stride, win)).contiguous()
+        plan.close()
+        fields.append(Field(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, D, 1e-3,
+                            device=dev))
+        units += P * K * J
+        pf += P * J
+    batch = FieldBatch(fields, rounds_per_launch=1)
+    batch.eager()                               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        batch.eager()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / rounds
+    batch.capture()
+    batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.launch(rounds)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / rounds
+    batch.close()
+    return {"workload": f"{n_fields} fields of {fov}^2: N in {{64,128}} at stride N/2, J 6..24, "
+                        f"M 44..88, K 1..3, D/r0 5..20", "units": units, "patch_frames": pf,
+            "ms_per_round_graph": 1e3 * t_graph, "ms_per_round_eager": 1e3 * t_eager,
+            "patch_frame_evals_per_s_graph": pf / t_graph}
+
+
 def cpu_baseline(D_host, alpha_host, g, budget_s):
     """The FP64 oracle on the same workload, patch after patch, until every
     patch is done or the time budget is used."""
@@ -391,6 +455,10 @@ def main():
         }
         plan4.close()
         del D4, alpha4, gamma4
+
+    if not args.no_large:
+        log("uneven fields in one HIP graph")
+        out["uneven_fields"] = uneven_fields_block(dev)
 
     if args.warm_steps > 0:
         log(f"warm start: {args.warm_steps} training steps, then time to converged loss")
