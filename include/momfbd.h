@@ -190,6 +190,22 @@ int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
 int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride, int border,
                   float* out, void* stream);
 
+/* Power spectrum of an L x L image (L a power of two, 16..4096) and its
+ * average over 30-degree sectors along the +-45 degree directions as a
+ * function of the radial frequency (Sect. "Results"):
+ *   power[u_y][u_x] = |DFT(w (x - mean x))|^2   (float, device, [L][L])
+ *   sector[k] = mean of power over the sector frequencies with
+ *               round(|u|) = k, k = 0..nbins-1 (double, device; 0 where no
+ *               frequency falls), counts[k] their number (int, device, or NULL)
+ * with u in (-L/2, L/2] and the sector 30..60 degrees from the axes in all
+ * four quadrants.  window: [L][L] float (device) or NULL (= 1); sector NULL
+ * skips the averaging.  Workspace from momfbd_power_spectrum_workspace
+ * (device, 256-byte aligned).  1 <= nbins <= L.
+ * Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_power_spectrum_workspace(int L, int nbins, size_t* bytes);
+int momfbd_power_spectrum(int L, const float* image, const float* window, float* power,
+                          double* sector, int* counts, int nbins, void* ws, void* stream);
+
 /* Per-patch L-BFGS solver (the quasi-Newton alternative to the paper's Adam,
  * Sect. "Optimization and paralellization"; patches are independent).
  * Each patch runs the two-loop recursion of limited-memory BFGS and a

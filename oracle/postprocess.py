@@ -32,7 +32,7 @@ from collections import deque
 
 import numpy as np
 
-from .momfbd import idft2_un
+from .momfbd import dft2, idft2_un
 
 
 def frequency_radius(N: int) -> np.ndarray:
@@ -129,3 +129,42 @@ def mosaic(patches: np.ndarray, ny: int, nx: int, stride: int, border: int) -> n
             wsum[y0:y0 + N, x0:x0 + N] += wt
     return acc / wsum
 
+
+
+def power_spectrum(image: np.ndarray, window=None) -> np.ndarray:
+    """|DFT(w (x - mean))|^2 of a square image (direct DFT, FP64)."""
+    x = np.asarray(image, np.float64)
+    w = np.ones_like(x) if window is None else np.asarray(window, np.float64)
+    X = dft2(w * (x - x.mean()))
+    return X.real ** 2 + X.imag ** 2
+
+
+def sector_masks(L: int):
+    """Radial bin k = round(|u|) and the +-45 degree sector flag on the full
+    grid, u in (-L/2, L/2]; decided with integer arithmetic:
+    (2k-1)^2 <= 4|u|^2 < (2k+1)^2, and 30..60 degrees from the axes as
+    u_x^2 <= 3 u_y^2 and u_y^2 <= 3 u_x^2 (both nonzero)."""
+    u = np.arange(L)
+    u = np.where(u > L // 2, u - L, u).astype(np.int64)
+    uy, ux = np.meshgrid(u, u, indexing="ij")
+    r4 = 4 * (ux ** 2 + uy ** 2)
+    k = np.zeros_like(r4)
+    while True:
+        up = r4 >= (2 * k + 1) ** 2
+        if not up.any():
+            break
+        k = k + up
+    sector = (ux != 0) & (uy != 0) & (ux ** 2 <= 3 * uy ** 2) & (uy ** 2 <= 3 * ux ** 2)
+    return k, sector
+
+
+def sector_spectrum(P: np.ndarray, nbins: int):
+    """Mean of P over the +-45 degree sectors (30 degrees wide) in each
+    radial bin k = 0..nbins-1 (Sect. "Results"); returns (mean, count)."""
+    k, sector = sector_masks(P.shape[0])
+    sel = sector & (k < nbins)
+    s = np.bincount(k[sel], weights=P[sel], minlength=nbins)[:nbins]
+    c = np.bincount(k[sel], minlength=nbins)[:nbins]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = np.where(c > 0, s / np.maximum(c, 1), 0.0)
+    return mean, c

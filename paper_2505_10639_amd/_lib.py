@@ -77,6 +77,8 @@ def lib():
                                              ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
         L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
         L.momfbd_synthesize.argtypes = [_vp] * 10
+        L.momfbd_power_spectrum_workspace.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
+        L.momfbd_power_spectrum.argtypes = [i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp]
         L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, _vp, _vp,
                                           _vp, f, _vp, i, _vp, _vp, _vp, _vp, _vp]
         L.momfbd_cnn_create.argtypes = [i, i, i, _vp, ctypes.POINTER(_vp)]
@@ -104,7 +106,8 @@ def lib():
                      "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
                      "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
-                     "momfbd_cnn_adam", "momfbd_lbfgs_rounds"):
+                     "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
+                     "momfbd_power_spectrum"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -230,6 +233,27 @@ def momfbd_lbfgs_rounds(plan, params, state, alpha, D, gamma, gamma_scalar, weig
                                      int(rounds), _ptr(loss), _ptr(status),
                                      _ptr(alpha_accepted), _ptr(ws), _stream(stream, alpha)),
            "momfbd_lbfgs_rounds")
+
+
+def momfbd_power_spectrum(image, window=None, nbins=None, stream=None):
+    """(power [L][L], sector mean [nbins] FP64, counts [nbins]) of a square
+    device image (torch float32)."""
+    import torch
+    L = int(image.shape[0])
+    if image.shape != (L, L) or image.dtype != torch.float32 or not image.is_contiguous():
+        raise ValueError("image must be a contiguous float32 [L][L] tensor")
+    nb = L // 2 + 1 if nbins is None else int(nbins)
+    n = ctypes.c_size_t()
+    _check(lib().momfbd_power_spectrum_workspace(L, nb, ctypes.byref(n)),
+           "momfbd_power_spectrum_workspace")
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=image.device)
+    power = torch.empty((L, L), dtype=torch.float32, device=image.device)
+    sector = torch.empty(nb, dtype=torch.float64, device=image.device)
+    counts = torch.empty(nb, dtype=torch.int32, device=image.device)
+    _check(lib().momfbd_power_spectrum(L, _ptr(image), _ptr(window), _ptr(power), _ptr(sector),
+                                       _ptr(counts), nb, _ptr(ws), _stream(stream, image)),
+           "momfbd_power_spectrum")
+    return power, sector, counts
 
 
 def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=None):

@@ -10,7 +10,7 @@ here; neither imports the other.
 
 from .geometry import (noll_to_nm, zernike_basis, pupil_mask, pupil_radius_px,
                        hann_window, defocus_diversity)
-from .turbulence import noll_covariance, draw_kolmogorov
+from .turbulence import noll_covariance, draw_kolmogorov, kl_transform, kl_basis
 from .fields import object_field, gaussian_noise
 from .configs import (Problem, make_problem, config0, config1_geometry,
                       config1_alpha, config1_object, config1_problem,
@@ -19,7 +19,8 @@ from .configs import (Problem, make_problem, config0, config1_geometry,
 
 __all__ = [
     "noll_to_nm", "zernike_basis", "pupil_mask", "pupil_radius_px", "hann_window",
-    "defocus_diversity", "noll_covariance", "draw_kolmogorov", "object_field",
+    "defocus_diversity", "noll_covariance", "draw_kolmogorov", "kl_transform", "kl_basis",
+    "object_field",
     "gaussian_noise", "Problem", "make_problem", "config0", "config1_geometry",
     "config1_alpha", "config1_object", "config1_problem", "config1_d_over_r0",
     "config4_geometry", "config4_template", "config4_alpha", "config4_objects",

@@ -63,3 +63,41 @@ def draw_kolmogorov(rng: np.random.Generator, n_draws: int, n_modes: int,
     a *= (scale ** (5.0 / 6.0))[:, None]
     a[:, :ao_modes] *= ao_factor
     return a
+
+
+def kl_transform(n_modes: int, first_noll: int = 2):
+    """Karhunen-Loeve modes of Kolmogorov turbulence in the span of the first
+    n_modes Zernikes (the paper's default basis, Sect. "Wavefronts": the
+    diagonalisation of the Zernike covariance).
+
+    Returns (U, var): KL_i = sum_j U[j, i] Z_j, ordered by decreasing
+    variance var[i] (at D/r0 = 1).  Noll's covariance couples only modes of
+    equal |m| and parity, so each such block is diagonalised on its own and
+    a KL mode never mixes cos and sin terms.
+    """
+    cov = noll_covariance(n_modes, 1.0, first_noll)
+    nm = [noll_to_nm(first_noll + i) for i in range(n_modes)]
+    key = [(abs(m), 0 if m == 0 else (1 if m > 0 else -1)) for (_, m) in nm]
+    U = np.zeros((n_modes, n_modes))
+    var = np.zeros(n_modes)
+    col = 0
+    for k in sorted(set(key)):
+        idx = [i for i in range(n_modes) if key[i] == k]
+        w, v = np.linalg.eigh(cov[np.ix_(idx, idx)])
+        for e in range(len(idx)):
+            # sign: largest component positive, for a reproducible basis
+            vec = v[:, e] * np.sign(v[np.argmax(np.abs(v[:, e])), e])
+            U[idx, col] = vec
+            var[col] = w[e]
+            col += 1
+    order = np.argsort(-var, kind="stable")
+    return U[:, order], var[order]
+
+
+def kl_basis(N: int, n_modes: int, diameter_frac: float = 0.45, scale: float = 1.0):
+    """KL modes [n_modes][N][N] (radians per unit coefficient) and their
+    variances at D/r0 = 1."""
+    from .geometry import zernike_basis
+    U, var = kl_transform(n_modes)
+    Z = zernike_basis(N, n_modes, diameter_frac, scale=scale)
+    return np.tensordot(U.T, Z, axes=1), var

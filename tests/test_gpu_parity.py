@@ -328,6 +328,19 @@ def test_lbfgs_rounds_replay_from_a_hip_graph(dev):
     plan.close()
 
 
+def test_karhunen_loeve_basis(dev):
+    """The same data with the KL modes as the basis (the paper's default):
+    loss and gradient at the KL coefficients of the same wavefronts."""
+    pr = synth.make_problem(57, N=64, P=2, J=6, M=30, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=np.array([8.0, 14.0]))
+    D_np = simulate_D(pr)
+    U, _ = synth.kl_transform(pr.M)
+    KL, _ = synth.kl_basis(64, pr.M, 0.45)
+    pr.basis = np.stack([KL] * pr.C).astype(np.float32)
+    pr.alpha_true = (pr.alpha_true.astype(np.float64) @ U).astype(np.float32)
+    check_patchwise(pr, D_np, alpha_points(pr, 5), dev)
+
+
 # ------------------------------------------------------------ 128 x 128 patches
 
 def test_n128_loss_and_gradient(dev):

@@ -93,3 +93,22 @@ def test_mosaic(dev, N, stride, border):
                       border).cpu().numpy()
     np.testing.assert_allclose(out, img, rtol=1e-6, atol=1e-6)
     plan.close()
+
+
+@pytest.mark.parametrize("L", [64, 256, 1024])
+def test_power_spectrum_and_sectors(dev, L):
+    from paper_2505_10639_amd import momfbd_power_spectrum
+    img = (synth.object_field(np.random.default_rng(L), L, L)).astype(np.float32)
+    win = synth.hann_window(L, L // 16).astype(np.float32)
+    nb = L // 2 + 8
+    P, sec, cnt = momfbd_power_spectrum(torch.from_numpy(img).to(dev),
+                                        torch.from_numpy(win).to(dev), nb)
+    torch.cuda.synchronize()
+    P, sec, cnt = P.cpu().numpy(), sec.cpu().numpy(), cnt.cpu().numpy()
+    # the oracle transforms the same FP32 inputs in FP64
+    P_ref = pp.power_spectrum(img.astype(np.float64), win.astype(np.float64))
+    assert np.max(np.abs(P - P_ref)) < 2e-5 * P_ref.max()
+    mean_ref, cnt_ref = pp.sector_spectrum(P_ref, nb)
+    np.testing.assert_array_equal(cnt, cnt_ref)
+    sel = cnt_ref > 0
+    np.testing.assert_allclose(sec[sel], mean_ref[sel], rtol=1e-4, atol=1e-6 * mean_ref.max())

@@ -131,3 +131,34 @@ def test_mosaic_weights_closed_form():
     y, x = 2, 5                                  # covered by both: x-x0 = 5 and 1
     ref = (w[y, 5] * 1.0 + w[y, 1] * 3.0) / (w[y, 5] + w[y, 1])
     assert m[y, x] == pytest.approx(ref, abs=1e-15)
+
+
+def test_sector_masks_match_angles_and_radii():
+    L = 64
+    k, sector = pp.sector_masks(L)
+    u = np.arange(L)
+    u = np.where(u > L // 2, u - L, u)
+    uy, ux = np.meshgrid(u, u, indexing="ij")
+    r = np.hypot(ux, uy)
+    np.testing.assert_array_equal(k, np.floor(r + 0.5).astype(int))
+    ang = np.degrees(np.arctan2(np.abs(uy), np.abs(ux)))
+    ref = (ux != 0) & (uy != 0) & (ang >= 30.0 - 1e-9) & (ang <= 60.0 + 1e-9)
+    np.testing.assert_array_equal(sector, ref)
+    assert sector[5, 5] and sector[-5, 5] and not sector[0, 7] and not sector[7, 1]
+
+
+def test_power_spectrum_parseval_and_diagonal_wave():
+    L = 32
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((L, L))
+    P = pp.power_spectrum(x)
+    assert P[0, 0] < 1e-20
+    np.testing.assert_allclose(P.sum(), L * L * np.sum((x - x.mean()) ** 2), rtol=1e-12)
+    # a plane wave along the diagonal, frequency (5, 5): all power at |u| = 7.07 -> bin 7
+    yy, xx = np.mgrid[0:L, 0:L]
+    wave = np.cos(2 * np.pi * 5 * (xx + yy) / L)
+    mean, cnt = pp.sector_spectrum(pp.power_spectrum(wave), L // 2 + 1)
+    assert np.argmax(mean) == 7 and np.count_nonzero(mean > 1e-9) == 1
+    # an axis-aligned wave lies outside the sectors
+    mean2, _ = pp.sector_spectrum(pp.power_spectrum(np.cos(2 * np.pi * 6 * xx / L)), L // 2 + 1)
+    assert np.all(mean2 < 1e-9)
