@@ -58,12 +58,12 @@ KERNEL_SOURCES = {
     "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
     "object": ["object.hip"],
 }
-COPY_FETCH_SCALE = 1.9997781363901774    # 256 MiB copy: FETCH_SIZE read 131086.5 KiB
+COPY_FETCH_SCALE = 1.999779725496011    # 256 MiB copy: FETCH_SIZE read 131086.4 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 COUNTED_TRAFFIC = {
-    "adjoint": {"fetch_bytes": 1010909823, "write_bytes": 94470144, "sources_sha1": "329df5a02c8d"},
-    "forward": {"fetch_bytes": 94958617, "write_bytes": 395188677, "sources_sha1": "329df5a02c8d"},
-    "object": {"fetch_bytes": 779373168, "write_bytes": 32821939, "sources_sha1": "6a042132d212"},
+    "adjoint": {"fetch_bytes": 1011085890, "write_bytes": 94470144, "sources_sha1": "2a4eaefe84bc"},
+    "forward": {"fetch_bytes": 94959930, "write_bytes": 395331504, "sources_sha1": "2a4eaefe84bc"},
+    "object": {"fetch_bytes": 779373583, "write_bytes": 32822483, "sources_sha1": "6a042132d212"},
 }
 
 
