@@ -60,7 +60,7 @@ extern "C" {
 typedef struct momfbd_plan_s* momfbd_plan;
 
 typedef struct {
-  int N;   /* patch side in pixels: 64 or 128                                */
+  int N;   /* patch side in pixels: 64, 96 or 128                            */
   int P;   /* number of patches                                              */
   int C;   /* number of channels (object/diversity pairs), 1..32             */
   int K;   /* number of objects, 1..32                                       */

@@ -30,7 +30,7 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
 // quarter [w K/4, (w+1) K/4) of k = c*1024 + px; the partial sums are added
 // in fixed order (wave 0 + 1 + 2 + 3) through LDS.
 template <int MT>
-__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, int lbp,
+__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, int bp,
                                                    const float* __restrict__ Zt,
                                                    const float* __restrict__ gphi,
                                                    float* __restrict__ grad) {
@@ -44,19 +44,18 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, i
   floatx4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int bp = 1 << lbp;            // band pixels per channel
   const int Kq = C * bp / 4;
   const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
   // operands of chunk kk: a from gphi row r, b[t] from mode rows t*16 + i16;
   // the next chunk's operands are loaded before the current chunk's MFMAs
   auto load = [&](int kk, floatx4& a4, floatx4 (&b4)[MT]) {
-    const int c = kk >> lbp, px = (kk & (bp - 1)) + 4 * g;
-    a4 = rok ? *reinterpret_cast<const floatx4*>(gphi + ((((size_t)p * C + c) * J + j) << lbp) + px)
+    const int c = kk / bp, px = kk % bp + 4 * g;
+    a4 = rok ? *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + c) * J + j) * bp + px)
              : floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int m = t * 16 + i16;
-      b4[t] = (m < M) ? *reinterpret_cast<const floatx4*>(Zt + (((size_t)c * M + m) << lbp) + px)
+      b4[t] = (m < M) ? *reinterpret_cast<const floatx4*>(Zt + ((size_t)c * M + m) * bp + px)
                       : floatx4{0.f, 0.f, 0.f, 0.f};
     }
   };
@@ -100,7 +99,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, i
 // the block's 64 coefficient rows (contiguous in alpha) are staged once in
 // LDS with the mode index padded to Mp; each wave then walks 4 tiles of 16
 // pixels x 64 columns, taking its B operands as float4 LDS reads.
-__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp, int lbp,
+__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp, int bp,
                                                     const float* __restrict__ ZtT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
@@ -117,7 +116,6 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
     for (int m = lane; m < Mp; m += 64)
       al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
   __syncthreads();
-  const int bp = 1 << lbp;
   const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
   for (int tile = 0; tile < ntile; ++tile) {
     const int px0 = quarter * (bp / 4) + (tile * 4 + wave) * 16;
@@ -140,7 +138,7 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
       const int col = col0 + t * 16 + i16;
       if (col >= R) continue;
       const int p = col / J, j = col % J;
-      *reinterpret_cast<floatx4*>(phi + ((((size_t)p * C + c) * J + j) << lbp) + px0 + 4 * g) =
+      *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + c) * J + j) * bp + px0 + 4 * g) =
           acc[t] + th;
     }
   }
@@ -150,8 +148,8 @@ template <int MT>
 void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
                    hipStream_t s) {
   const int R = d.P * d.J;
-  const int lbp = d.N == 64 ? 10 : 12;
-  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M, lbp,
+  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M,
+                     d.bandpix(),
                      Zt, gphi, grad);
 }
 
@@ -182,8 +180,8 @@ hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int lbp = d.N == 64 ? 10 : 12;
-  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, lbp, ZtT, thetat,
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, d.bandpix(), ZtT,
+                     thetat,
                      alpha, phi);
   return hipGetLastError();
 }

@@ -1,4 +1,5 @@
-// Host emulation of the 64x64 wave operators -- test infrastructure.
+// Host emulation of the 64x64, 96x96 and 128x128 unit operators -- test
+// infrastructure.
 //
 // Runs the per-lane phases of ops64.h lane by lane on the CPU with an
 // ordinary array standing in for LDS, so that the index logic of the GPU
@@ -9,6 +10,7 @@
 
 #include "ops128.h"
 #include "ops64.h"
+#include "ops96.h"
 
 using namespace mfbd;
 using namespace mfbd::n64;
@@ -342,6 +344,159 @@ void emu128_fft_to_band(const float* hc, float* band) {
   float2* o = reinterpret_cast<float2*>(band);
   for (int l = 0; l < 128; ++l)
     for (int i = 0; i < 32; ++i) o[(2 * i + (l & 1)) * 64 + (l >> 1)] = GP[l][i];
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- N = 96
+namespace e96 {
+using namespace mfbd::n96;
+struct WG {
+  float2 T[n96::LDS_MAIN];
+  float2 Taux[n96::LDS_AUX];
+};
+constexpr int L = n96::LANES;
+
+void pupil_cols(WG& w, const float* A, const float* ph, float2 (&Pk)[L][24]) {
+  for (int l = 0; l < L; ++l) {
+    const int q = l >> 1, b = l & 1;
+    float2 P[48], y[48];
+    for (int n = 0; n < 48; ++n) {
+      const double ang = 2.0 * M_PI * (double)ph[n * 48 + q];
+      const float a = A[n * 48 + q];
+      P[n] = make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang));
+    }
+    static_for<0, 48>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      y[n] = b ? twmul<+1, 96, 24 + n>(P[n]) : P[n];
+    });
+    for (int i = 0; i < 24; ++i) Pk[l][i] = P[2 * i + b];
+    n96::op1_cols(y, w.T, l);
+  }
+}
+
+void r2c(WG& w, const float* img, float2 (&X)[L][48], float2 (&x48)[L]) {
+  for (int l = 0; l < L; ++l) {
+    float se[48], so[48];
+    for (int n = 0; n < 48; ++n) {
+      se[n] = img[l * 96 + 2 * n];
+      so[n] = img[l * 96 + 2 * n + 1];
+    }
+    n96::op2_rows(se, so, w.T, l);
+  }
+  for (int l = 0; l < L; ++l) n96::op2_cols(w.T, w.Taux, l, X[l]);
+  for (int l = 0; l < L; ++l) x48[l] = n96::op2_spread(w.Taux, l);
+}
+
+void c2r(WG& w, float2 (&X)[L][48], const float2 (&x48)[L], float* img) {
+  for (int l = 0; l < L; ++l) n96::op3_gather(x48[l], w.Taux, l);
+  for (int l = 0; l < L; ++l) n96::op3_cols(X[l], w.Taux, w.T, l);
+  for (int l = 0; l < L; ++l) {
+    float ge[48], go[48];
+    n96::op3_rows(w.T, l, ge, go);
+    for (int n = 0; n < 48; ++n) {
+      img[l * 96 + 2 * n] = ge[n];
+      img[l * 96 + 2 * n + 1] = go[n];
+    }
+  }
+}
+}  // namespace e96
+
+extern "C" {
+
+void emu96_fft48(float* x, int dir) {
+  float2 v[48];
+  std::memcpy(v, x, sizeof(v));
+  if (dir < 0) n96::fft48<-1>(v); else n96::fft48<+1>(v);
+  std::memcpy(x, v, sizeof(v));
+}
+
+// band pupil [48][48] -> complex amplitude p [96][96]
+void emu96_pupil_ifft(const float* A, const float* ph, float* p) {
+  static e96::WG w;
+  static float2 Pk[e96::L][24];
+  e96::pupil_cols(w, A, ph, Pk);
+  float2* o = reinterpret_cast<float2*>(p);
+  for (int l = 0; l < e96::L; ++l) {
+    float2 pe[48], po[48];
+    n96::op1_rows(w.T, l, pe, po);
+    for (int n = 0; n < 48; ++n) {
+      o[l * 96 + 2 * n] = pe[n];
+      o[l * 96 + 2 * n + 1] = po[n];
+    }
+  }
+}
+
+void emu96_r2c(const float* img, float* half) {
+  static e96::WG w;
+  static float2 X[e96::L][48], x48[e96::L];
+  e96::r2c(w, img, X, x48);
+  float2* h = reinterpret_cast<float2*>(half);
+  for (int l = 0; l < e96::L; ++l) {
+    for (int m = 0; m < 48; ++m) h[n96::sl_index(l, m)] = X[l][m];
+    h[n96::sl_index48(l)] = x48[l];
+  }
+}
+
+void emu96_c2r(const float* half, float* img) {
+  static e96::WG w;
+  static float2 X[e96::L][48], x48[e96::L];
+  const float2* h = reinterpret_cast<const float2*>(half);
+  for (int l = 0; l < e96::L; ++l) {
+    for (int m = 0; m < 48; ++m) X[l][m] = h[n96::sl_index(l, m)];
+    x48[l] = h[n96::sl_index48(l)];
+  }
+  e96::c2r(w, X, x48, img);
+}
+
+// Whole unit through the kernels' sequence: PSF, OTF, and the fused adjoint
+// (op14) for a given G half spectrum.
+void emu96_unit(const float* A, const float* ph, float kappa, const float* G_half, float* psf,
+                float* S_half, float* gphi) {
+  static e96::WG w;
+  static float2 Pk[e96::L][24], X[e96::L][48], x48[e96::L], Gr[e96::L][48];
+  static float img[96 * 96], g[96 * 96];
+  e96::pupil_cols(w, A, ph, Pk);
+  for (int l = 0; l < e96::L; ++l) {
+    float2 pe[48], po[48];
+    n96::op1_rows(w.T, l, pe, po);
+    for (int n = 0; n < 48; ++n) {
+      img[l * 96 + 2 * n] = kappa * cabs2(pe[n]);
+      img[l * 96 + 2 * n + 1] = kappa * cabs2(po[n]);
+    }
+  }
+  std::memcpy(psf, img, sizeof(img));
+  e96::r2c(w, img, X, x48);
+  float2* sh = reinterpret_cast<float2*>(S_half);
+  for (int l = 0; l < e96::L; ++l) {
+    for (int m = 0; m < 48; ++m) sh[n96::sl_index(l, m)] = X[l][m];
+    sh[n96::sl_index48(l)] = x48[l];
+  }
+  const float2* gh = reinterpret_cast<const float2*>(G_half);
+  for (int l = 0; l < e96::L; ++l) {
+    for (int m = 0; m < 48; ++m) X[l][m] = gh[n96::sl_index(l, m)];
+    x48[l] = gh[n96::sl_index48(l)];
+  }
+  e96::c2r(w, X, x48, g);
+  e96::pupil_cols(w, A, ph, Pk);
+  for (int l = 0; l < e96::L; ++l) {
+    float ge[48], go[48];
+    for (int n = 0; n < 48; ++n) {
+      ge[n] = g[l * 96 + 2 * n];
+      go[n] = g[l * 96 + 2 * n + 1];
+    }
+    n96::op14_rows(w.T, l, ge, go, 2.0f * kappa, Gr[l]);
+  }
+  for (int l = 0; l < e96::L; ++l) n96::op14_write(Gr[l], w.T, l);
+  for (int l = 0; l < e96::L; ++l) {
+    float2 GP[24];
+    n96::op4_cols(w.T, l, GP);
+    const int q = l >> 1, b = l & 1;
+    for (int i = 0; i < 24; ++i) {
+      const float2 pk = Pk[l][i], gp = GP[i];
+      gphi[(2 * i + b) * 48 + q] = pk.x * gp.y - pk.y * gp.x;
+    }
+  }
 }
 
 }  // extern "C"

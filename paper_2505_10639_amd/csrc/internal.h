@@ -104,6 +104,14 @@ hipError_t launch_prepare64(const Dims& d, const float* frames, int H, int W, in
 hipError_t launch_objimg64(const Dims& d, const float2* O, float* obj, hipStream_t s);
 hipError_t launch_synth64(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
                           const float* noise, const float* sigma, float* field, hipStream_t s);
+hipError_t launch_forward96(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                            const float* phi, float* psf, float2* S, hipStream_t s);
+hipError_t launch_adjoint96(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                            const int* active, const float* Ab, const float* phi, const float2* S,
+                            const float2* O, float* gphi, hipStream_t s);
+hipError_t launch_prepare96(const Dims& d, const float* frames, int H, int W, int stride,
+                            const float* apod, float2* D, hipStream_t s);
+hipError_t launch_objimg96(const Dims& d, const float2* O, float* obj, hipStream_t s);
 hipError_t launch_forward128(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                              const float* phi, float* psf, float2* S, hipStream_t s);
 hipError_t launch_adjoint128(const Dims& d, const ChanTab& ct, const LossArgs& la,

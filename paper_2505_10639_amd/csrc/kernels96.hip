@@ -1,0 +1,292 @@
+// Unit kernels of the MOMFBD hot path for 96x96 patches (gfx950).
+//
+// One workgroup = two wavefronts = one unit (patch p, channel c, frame j);
+// lanes 0..95 carry the lines of the 96-point transforms, lanes 96..127 only
+// take part in the barriers.  Same stages as the 64x64 kernels:
+//   forward : phase -> pupil -> inverse 2-D DFT -> |.|^2 -> forward 2-D DFT
+//   adjoint : G = -2 w conj(O)(D - O S) -> inverse DFT -> H = 2 kappa g p
+//             -> forward DFT on the pupil band -> dL/dphi = Im(conj(P) G_P)
+//   prepare : patch cut, mean removal, apodization, mean restore, 2-D DFT
+//   objimg  : object spectrum -> real image / N^2
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "ops96.h"
+
+namespace mfbd {
+using namespace n96;
+
+namespace {
+
+constexpr int kUnitF2 = N * HC;        // 4704
+constexpr int kB = 48;                 // band width
+constexpr int kBP = kB * kB;           // band pixels, 2304
+constexpr int kThreads = 128;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void sync() { __syncthreads(); }
+
+__device__ __forceinline__ float2 expi_turns(float t) {
+  const float f = __builtin_amdgcn_fractf(t);
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+}
+
+// Input of op1_cols for lane (q,b): y[n] = P(24+n, 24+q) W96^{+b(24+n)}.
+__device__ __forceinline__ void build_pupil(const float* __restrict__ A,
+                                            const float* __restrict__ ph, int lane,
+                                            float2 (&y)[48]) {
+  const int q = lane >> 1, b = lane & 1;
+#pragma unroll
+  for (int n = 0; n < 48; ++n) {
+    const float a = A[n * kB + q];
+    const float t = ph[n * kB + q] + (b ? (24 + n) * (1.0f / 96.0f) : 0.0f);
+    y[n] = cscale(expi_turns(t), a);
+  }
+}
+
+template <bool WANT_PSF>
+__global__ __launch_bounds__(kThreads) void k_forward96(int units, ChanTab ct, int C, int J,
+                                                        const int* __restrict__ active,
+                                                        const float* __restrict__ Ab,
+                                                        const float* __restrict__ phi,
+                                                        float* __restrict__ psf,
+                                                        float2* __restrict__ S) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  if (active && !active[u / (J * C)]) return;
+  const int lane = threadIdx.x;
+  const bool on = lane < LANES;
+  const int c = (u / J) % C;
+  if (on) {
+    float2 y[48];
+    build_pupil(Ab + c * kBP, phi + (size_t)u * kBP, lane, y);
+    op1_cols(y, T, lane);
+  }
+  sync();
+  float se[48], so[48];
+  if (on) {
+    float2 pe[48], po[48];
+    op1_rows(T, lane, pe, po);
+    const float kap = ct.kappa[c];
+#pragma unroll
+    for (int n = 0; n < 48; ++n) {
+      se[n] = kap * cabs2(pe[n]);
+      so[n] = kap * cabs2(po[n]);
+    }
+    if (WANT_PSF) {
+      float* row = psf + (size_t)u * N * N + lane * N;
+#pragma unroll
+      for (int n = 0; n < 48; ++n) {
+        row[2 * n] = se[n];
+        row[2 * n + 1] = so[n];
+      }
+    }
+  }
+  sync();
+  if (on) op2_rows(se, so, T, lane);
+  sync();
+  float2 X[48];
+  if (on) op2_cols(T, Taux, lane, X);
+  sync();
+  if (on) {
+    float2* out = S + (size_t)u * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 48; ++m) out[sl_index(lane, m)] = X[m];
+    out[sl_index48(lane)] = op2_spread(Taux, lane);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_adjoint96(int units, ChanTab ct, int C, int J,
+                                                        int K, LossArgs la,
+                                                        const int* __restrict__ active,
+                                                        const float* __restrict__ Ab,
+                                                        const float* __restrict__ phi,
+                                                        const float2* __restrict__ S,
+                                                        const float2* __restrict__ O,
+                                                        float* __restrict__ gphi) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int per = (units + kXcds - 1) / kXcds;
+  const int u = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (u >= units) return;
+  const int lane = threadIdx.x;
+  const bool on = lane < LANES;
+  const int j = u % J, c = (u / J) % C, p = u / (J * C);
+  if (active && !active[p]) return;
+  const int k = ct.chan_obj[c];
+  const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
+  float2 G[48];
+  if (on) {
+    const float2* Su = S + (size_t)u * kUnitF2;
+    const float2* Du = la.D + (size_t)u * kUnitF2;
+    const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 48; ++m) {
+      const int idx = sl_index(lane, m);
+      const float2 o = Ok[idx];
+      G[m] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+    }
+    const int idx = sl_index48(lane);
+    const float2 o = Ok[idx];
+    op3_gather(cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2), Taux, lane);
+  }
+  sync();
+  if (on) op3_cols(G, Taux, T, lane);
+  sync();
+  float ge[48], go[48];
+  if (on) op3_rows(T, lane, ge, go);
+  sync();
+  const float* Ac = Ab + c * kBP;
+  const float* phu = phi + (size_t)u * kBP;
+  if (on) {
+    float2 y[48];
+    build_pupil(Ac, phu, lane, y);
+    op1_cols(y, T, lane);
+  }
+  sync();
+  float2 Gr[48];
+  if (on) op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c], Gr);
+  sync();
+  if (on) op14_write(Gr, T, lane);
+  sync();
+  if (on) {
+    float2 GP[24];
+    op4_cols(T, lane, GP);
+    const int b = lane & 1, q = lane >> 1;
+    float* gout = gphi + (size_t)u * kBP;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      const int n = 2 * i + b;
+      const float2 pk = cscale(expi_turns(phu[n * kB + q]), Ac[n * kB + q]);
+      gout[n * kB + q] = pk.x * GP[i].y - pk.y * GP[i].x;   // Im(conj(P) G_P)
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_prepare96(int units, int C, int J, int H, int W,
+                                                        int stride, int nx,
+                                                        const float* __restrict__ frames,
+                                                        const float* __restrict__ apod,
+                                                        float2* __restrict__ D) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  __shared__ float red[kThreads];
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int lane = threadIdx.x;
+  const bool on = lane < LANES;
+  const int j = u % J, c = (u / J) % C, p = u / (J * C);
+  const int y0 = (p / nx) * stride, x0 = (p % nx) * stride;
+  const float* src = frames + ((size_t)(c * J + j) * H + y0) * W + x0;
+  float se[48], so[48];
+  float sum = 0.f;
+  if (on) {
+    const float* row = src + (size_t)lane * W;
+#pragma unroll
+    for (int n = 0; n < 48; ++n) {
+      se[n] = row[2 * n];
+      so[n] = row[2 * n + 1];
+      sum += se[n] + so[n];
+    }
+  }
+  red[lane] = sum;
+  sync();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (lane < h) red[lane] += red[lane + h];
+    sync();
+  }
+  const float mean = red[0] * (1.0f / (N * N));
+  if (on) {
+    const float* wr = apod + lane * N;
+#pragma unroll
+    for (int n = 0; n < 48; ++n) {
+      se[n] = wr[2 * n] * (se[n] - mean) + mean;
+      so[n] = wr[2 * n + 1] * (so[n] - mean) + mean;
+    }
+    op2_rows(se, so, T, lane);
+  }
+  sync();
+  float2 X[48];
+  if (on) op2_cols(T, Taux, lane, X);
+  sync();
+  if (on) {
+    float2* out = D + (size_t)u * kUnitF2;
+#pragma unroll
+    for (int m = 0; m < 48; ++m) out[sl_index(lane, m)] = X[m];
+    out[sl_index48(lane)] = op2_spread(Taux, lane);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_objimg96(int items, const float2* __restrict__ O,
+                                                       float* __restrict__ obj) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
+  const int it = blockIdx.x;
+  if (it >= items) return;
+  const int lane = threadIdx.x;
+  const bool on = lane < LANES;
+  const float2* Oi = O + (size_t)it * kUnitF2;
+  float2 X[48];
+  if (on) {
+#pragma unroll
+    for (int m = 0; m < 48; ++m) X[m] = Oi[sl_index(lane, m)];
+    op3_gather(Oi[sl_index48(lane)], Taux, lane);
+  }
+  sync();
+  if (on) op3_cols(X, Taux, T, lane);
+  sync();
+  if (on) {
+    float ge[48], go[48];
+    op3_rows(T, lane, ge, go);
+    float* row = obj + (size_t)it * N * N + lane * N;
+    const float inv = 1.0f / (N * N);
+#pragma unroll
+    for (int n = 0; n < 48; ++n) {
+      row[2 * n] = ge[n] * inv;
+      row[2 * n + 1] = go[n] * inv;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_forward96(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
+                            const float* phi, float* psf, float2* S, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  if (psf)
+    hipLaunchKernelGGL(k_forward96<true>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+                       active, Ab, phi, psf, S);
+  else
+    hipLaunchKernelGGL(k_forward96<false>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+                       active, Ab, phi, psf, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint96(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                            const int* active, const float* Ab, const float* phi, const float2* S,
+                            const float2* O, float* gphi, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  const int per = (units + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_adjoint96, dim3(kXcds * per), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+                     d.K, la, active, Ab, phi, S, O, gphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare96(const Dims& d, const float* frames, int H, int W, int stride,
+                            const float* apod, float2* D, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  const int nx = (W - N) / stride + 1;
+  hipLaunchKernelGGL(k_prepare96, dim3(units), dim3(kThreads), 0, s, units, d.C, d.J, H, W,
+                     stride, nx, frames, apod, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_objimg96(const Dims& d, const float2* O, float* obj, hipStream_t s) {
+  const int items = d.P * d.K;
+  hipLaunchKernelGGL(k_objimg96, dim3(items), dim3(kThreads), 0, s, items, O, obj);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

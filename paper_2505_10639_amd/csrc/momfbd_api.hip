@@ -171,7 +171,7 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
     for (int c = 0; c < C; ++c) any |= desc->channel_object[c] == k;
     if (!any) return MOMFBD_EINVAL;
   }
-  if (N != 64 && N != 128) return MOMFBD_EUNSUPPORTED;
+  if (N != 64 && N != 96 && N != 128) return MOMFBD_EUNSUPPORTED;
   if (M > kMaxM || (long)J * M > 8192) return MOMFBD_EUNSUPPORTED;
 
   momfbd_plan_s* pl = new (std::nothrow) momfbd_plan_s();

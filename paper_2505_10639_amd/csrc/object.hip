@@ -139,6 +139,9 @@ hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, c
   if (d.N == 64)
     hipLaunchKernelGGL(k_object<64>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
                        ct, la, active, S, O, loss_pk);
+  else if (d.N == 96)
+    hipLaunchKernelGGL(k_object<96>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
+                       ct, la, active, S, O, loss_pk);
   else
     hipLaunchKernelGGL(k_object<128>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
                        ct, la, active, S, O, loss_pk);
@@ -149,25 +152,30 @@ hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, c
 
 hipError_t launch_forward(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                           const float* phi, float* psf, float2* S, hipStream_t s) {
-  return d.N == 64 ? launch_forward64(d, ct, active, Ab, phi, psf, S, s)
-                   : launch_forward128(d, ct, active, Ab, phi, psf, S, s);
+  return d.N == 64   ? launch_forward64(d, ct, active, Ab, phi, psf, S, s)
+         : d.N == 96 ? launch_forward96(d, ct, active, Ab, phi, psf, S, s)
+                     : launch_forward128(d, ct, active, Ab, phi, psf, S, s);
 }
 
 hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                           const float* Ab, const float* phi, const float2* S, const float2* O,
                           float* gphi, hipStream_t s) {
-  return d.N == 64 ? launch_adjoint64(d, ct, la, active, Ab, phi, S, O, gphi, s)
-                   : launch_adjoint128(d, ct, la, active, Ab, phi, S, O, gphi, s);
+  return d.N == 64   ? launch_adjoint64(d, ct, la, active, Ab, phi, S, O, gphi, s)
+         : d.N == 96 ? launch_adjoint96(d, ct, la, active, Ab, phi, S, O, gphi, s)
+                     : launch_adjoint128(d, ct, la, active, Ab, phi, S, O, gphi, s);
 }
 
 hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
                           const float* apod, float2* D, hipStream_t s) {
-  return d.N == 64 ? launch_prepare64(d, frames, H, W, stride, apod, D, s)
-                   : launch_prepare128(d, frames, H, W, stride, apod, D, s);
+  return d.N == 64   ? launch_prepare64(d, frames, H, W, stride, apod, D, s)
+         : d.N == 96 ? launch_prepare96(d, frames, H, W, stride, apod, D, s)
+                     : launch_prepare128(d, frames, H, W, stride, apod, D, s);
 }
 
 hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s) {
-  return d.N == 64 ? launch_objimg64(d, O, obj, s) : launch_objimg128(d, O, obj, s);
+  return d.N == 64   ? launch_objimg64(d, O, obj, s)
+         : d.N == 96 ? launch_objimg96(d, O, obj, s)
+                     : launch_objimg128(d, O, obj, s);
 }
 
 }  // namespace mfbd

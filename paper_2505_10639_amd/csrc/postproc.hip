@@ -184,6 +184,12 @@ hipError_t launch_filter(const Dims& d, const ChanTab& ct, const FilterTab& ft, 
   if (d.N == 64) {
     hipLaunchKernelGGL(k_filter<64>, dim3(d.P * d.K), dim3(256), lds, s, d.C, d.J, d.K, ct, ft,
                        D, weights, S, O, H);
+  } else if (d.N == 96) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter<96>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_filter<96>, dim3(d.P * d.K), dim3(256), lds, s, d.C, d.J, d.K, ct, ft,
+                       D, weights, S, O, H);
   } else {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter<128>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

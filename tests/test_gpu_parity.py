@@ -397,3 +397,54 @@ def test_multi_wavelength_n64(dev):
     pr = synth.make_problem(55, N=64, P=2, J=3, M=36, channels=((0, 0.0), (1, 0.0), (1, 1.0)),
                             lam_ratios=[1.0, 1 / 1.1, 1 / 1.1], d_over_r0=10.0)
     check_patchwise(pr, simulate_D(pr), alpha_points(pr, 7), dev)
+
+
+# ------------------------------------------------------------ 96 x 96 patches
+
+def test_n96_loss_and_gradient(dev):
+    # 96x96 patches (radix-3 transforms), phase diversity, two objects
+    pr = synth.make_problem(60, N=96, P=3, J=3, M=40, channels=((0, 0.0), (0, 1.0), (1, 0.0)),
+                            d_over_r0=np.array([8.0, 12.0, 16.0]), border=9)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 8), dev)
+
+
+def test_n96_multi_wavelength_and_smoothness(dev):
+    lam = [1.0, 1 / 0.95, 1 / 1.1]
+    pr = synth.make_problem(61, N=96, P=2, J=2, M=24, channels=((0, 0.0), (1, 0.0), (2, 0.0)),
+                            lam_ratios=lam, d_over_r0=12.0, border=9)
+    g = oracle.smoothness_gamma(96, [1e-3] * 3, [0.05] * 3)[:, :, :49].astype(np.float32)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 9), dev, gamma=g)
+
+
+def test_n96_forward_object_prepare(dev):
+    pr = synth.make_problem(62, N=96, P=2, J=2, M=20, d_over_r0=12.0, border=9)
+    plan = make_plan(pr, dev)
+    psf, otf = plan.forward(to_dev(pr.alpha_true, dev))
+    psf, otf = psf.cpu().numpy(), otf.cpu().numpy()
+    for p in range(2):
+        for j in range(2):
+            phi = oracle.wavefront(pr.alpha_true[p, j], pr.basis[0], pr.diversity[0])
+            s = oracle.psf(pr.pupil[0], phi)
+            assert np.abs(psf[p, 0, j] - s).max() <= 2e-6 * s.max()
+            assert np.abs(otf[p, 0, j] - oracle.otf(s)[:, :49]).max() <= 2e-6
+    psf0, _ = plan.forward(torch.zeros((2, 2, 20), device=dev), want_otf=False)
+    NA = float(pr.pupil[0].sum())
+    assert abs(float(psf0[0, 0, 0, 0, 0]) - NA / 9216) < 1e-6
+    D = simulate_D(pr)
+    obj = plan.object_estimate(to_dev(pr.alpha_true, dev), to_dev(D, dev), pr.gamma).cpu().numpy()
+    ref = oracle.evaluate(pr.alpha_true, D, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
+                          pr.gamma, want_grad=False)
+    for p in range(2):
+        rms = np.sqrt(np.mean((obj[p, 0] - oracle.object_image(ref["O"][p, 0])) ** 2))
+        assert rms < OBJ_RMS, rms
+    plan.close()
+    rng = np.random.default_rng(63)
+    frames = (1.0 + 0.1 * rng.standard_normal((1, 2, 250, 200))).astype(np.float32)
+    win = synth.hann_window(96, 9).astype(np.float32)
+    ny, nx = (250 - 96) // 48 + 1, (200 - 96) // 48 + 1
+    pr2 = synth.make_problem(64, N=96, P=ny * nx, J=2, M=4)
+    plan2 = make_plan(pr2, dev)
+    Dg = plan2.prepare_data(to_dev(frames, dev), 48, to_dev(win, dev)).cpu().numpy()
+    ref = oracle.prepare_data(frames, win, 96, 48)
+    assert np.abs(Dg - ref).max() <= 1e-6 * np.abs(ref).max()
+    plan2.close()

@@ -112,3 +112,22 @@ def test_power_spectrum_and_sectors(dev, L):
     np.testing.assert_array_equal(cnt, cnt_ref)
     sel = cnt_ref > 0
     np.testing.assert_allclose(sec[sel], mean_ref[sel], rtol=1e-4, atol=1e-6 * mean_ref.max())
+
+
+def test_filters_at_96(dev):
+    from paper_2505_10639_amd import filter_spec
+    pr = synth.make_problem(66, N=96, P=1, J=3, M=16, channels=((0, 0.0),), d_over_r0=9.0)
+    D_np = simulate_D(pr)
+    plan = make_plan(pr, dev)
+    dl = 0.45 * 96
+    obj, H = plan.object_filtered(torch.from_numpy(pr.alpha_true).to(dev),
+                                  torch.from_numpy(D_np).to(dev),
+                                  [filter_spec("tophat", 0.5, 0.65, dl)], pr.gamma, want_H=True)
+    torch.cuda.synchronize()
+    r = oracle.evaluate_patch(pr.alpha_true[0], D_np[0], pr.basis, pr.diversity, pr.pupil,
+                              pr.channel_object, pr.gamma, want_grad=False)
+    Ht = pp.tophat_filter(96, 0.5, 0.65, dl)
+    np.testing.assert_allclose(H.cpu().numpy()[0, 0], Ht[:, :49], atol=1e-6)
+    ref = pp.filtered_object(r["O"][0], Ht)
+    assert np.sqrt(np.mean((obj.cpu().numpy()[0, 0] - ref) ** 2)) < OBJ_RMS
+    plan.close()

@@ -165,3 +165,62 @@ def test_n128_forward_on_band(emu):
     emu.emu128_fft_to_band(ptr(h.view(np.float32)), ptr(band.view(np.float32)))
     ref = oracle.dft2(h)[32:96, 32:96]
     assert np.abs(band - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ N = 96
+
+@pytest.mark.parametrize("d", [-1, 1])
+def test_n96_fft48(emu, d):
+    x = (rng(20).standard_normal(48) + 1j * rng(21).standard_normal(48)).astype(np.complex64)
+    y = x.copy()
+    emu.emu96_fft48(ptr(y.view(np.float32)), d)
+    ref = np.fft.fft(x.astype(complex)) if d < 0 else np.fft.ifft(x.astype(complex)) * 48
+    assert np.abs(y - ref).max() <= 3e-7 * np.abs(ref).max()
+
+
+def test_n96_band_pupil_inverse(emu):
+    A = synth.pupil_mask(96)[24:72, 24:72].astype(np.float32)
+    ph = (0.2 * rng(22).standard_normal((48, 48))).astype(np.float32)
+    p = np.zeros((96, 96), np.complex64)
+    emu.emu96_pupil_ifft(ptr(A), ptr(ph), ptr(p.view(np.float32)))
+    P = np.zeros((96, 96), complex)
+    P[24:72, 24:72] = A * np.exp(2j * np.pi * ph.astype(np.float64))
+    ref = oracle.idft2_un(P)
+    assert np.abs(p - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_n96_real_forward_and_inverse(emu):
+    img = rng(23).standard_normal((96, 96)).astype(np.float32)
+    half = np.zeros((96, 49), np.complex64)
+    emu.emu96_r2c(ptr(img), ptr(half.view(np.float32)))
+    ref = oracle.dft2(img)[:, :49]
+    assert np.abs(half - ref).max() <= 5e-7 * np.abs(ref).max()
+    H = oracle.dft2(rng(24).standard_normal((96, 96)))
+    hh = H[:, :49].astype(np.complex64)
+    out = np.zeros((96, 96), np.float32)
+    emu.emu96_c2r(ptr(hh.view(np.float32)), ptr(out))
+    ref = oracle.idft2_un(oracle.expand_half(hh, 96)).real
+    assert np.abs(out - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_n96_unit_chain_matches_oracle_gradient(emu):
+    pr = synth.make_problem(33, N=96, P=1, J=1, M=20, d_over_r0=12.0)
+    A = pr.pupil[0].astype(np.float64)
+    phi = oracle.wavefront(pr.alpha_true[0, 0], pr.basis[0], pr.diversity[0])
+    Ab = A[24:72, 24:72].astype(np.float32)
+    ph = (phi[24:72, 24:72] / (2 * np.pi)).astype(np.float32)
+    kap = 1.0 / (96 * 96 * A.sum())
+    Gh = oracle.dft2(rng(25).standard_normal((96, 96)))[:, :49].astype(np.complex64)
+    psf = np.zeros((96, 96), np.float32)
+    S = np.zeros((96, 49), np.complex64)
+    gphi = np.zeros((48, 48), np.float32)
+    emu.emu96_unit(ptr(Ab), ptr(ph), ctypes.c_float(kap), ptr(Gh.view(np.float32)), ptr(psf),
+                   ptr(S.view(np.float32)), ptr(gphi))
+    P = oracle.pupil_field(A, phi)
+    p = oracle.psf_field(P)
+    s = kap * np.abs(p) ** 2
+    assert np.abs(psf - s).max() <= 1e-6 * s.max()
+    assert np.abs(S - oracle.otf(s)[:, :49]).max() <= 1e-6
+    g_s = oracle.idft2_un(oracle.expand_half(Gh, 96)).real
+    ref = (np.conj(P) * oracle.dft2(2 * kap * g_s * p)).imag[24:72, 24:72]
+    assert np.abs(gphi - ref).max() <= 2e-5 * np.abs(ref).max()
