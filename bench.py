@@ -276,7 +276,7 @@ def warm_start_block(dev, steps, patches=961):
 
 
 def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
-    """Independent 512^2 fields with patch sizes 64 or 128 (stride N/2),
+    """Independent 512^2 fields with patch sizes 64, 96 or 128 (stride N/2),
     frame counts 6..24, 44..88 modes and 1..3 objects (one channel each),
     D/r0 5..20: every field's solver rounds captured into one HIP graph.
     Reports the time of one graph launch (one line-search trial for every
@@ -290,7 +290,7 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     rng = np.random.default_rng(synth.SEED_ROOT + 8)
     fields, units, pf = [], 0, 0
     for i in range(n_fields):
-        N = int(rng.choice([64, 128]))
+        N = int(rng.choice([64, 96, 128]))
         J = int(rng.integers(6, 25))
         M = int(rng.integers(44, 89))
         K = int(rng.integers(1, 4))
@@ -299,7 +299,7 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
         P = n * n
         ch = tuple((k, 0.0) for k in range(K))
         pr = synth.make_problem(1000 + i, N=N, P=1, J=J, M=M, channels=ch, gamma=1e-3,
-                                border=6 if N == 64 else 12, objects=np.zeros((1, K, N, N)))
+                                border=N // 10, objects=np.zeros((1, K, N, N)))
         plan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, dev)
         win = torch.from_numpy(pr.window).to(dev)
         scene = torch.from_numpy(np.stack([synth.object_field(rng, fov, fov) for _ in range(K)])
@@ -333,7 +333,7 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / rounds
     batch.close()
-    return {"workload": f"{n_fields} fields of {fov}^2: N in {{64,128}} at stride N/2, J 6..24, "
+    return {"workload": f"{n_fields} fields of {fov}^2: N in {{64,96,128}} at stride N/2, J 6..24, "
                         f"M 44..88, K 1..3, D/r0 5..20", "units": units, "patch_frames": pf,
             "ms_per_round_graph": 1e3 * t_graph, "ms_per_round_eager": 1e3 * t_eager,
             "patch_frame_evals_per_s_graph": pf / t_graph}

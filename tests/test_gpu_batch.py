@@ -17,6 +17,7 @@ SHAPES = [  # N, P, J, M, channels (object, defocus waves)
     (128, 2, 6, 24, ((0, 0.0), (1, 0.0))),
     (64, 4, 8, 30, ((0, 0.0), (0, 1.0))),
     (128, 1, 3, 16, ((0, 0.0),)),
+    (96, 2, 4, 28, ((0, 0.0), (0, 1.0))),
     (64, 2, 5, 44, ((0, 0.0), (1, 1.0), (2, 0.0))),
 ]
 
