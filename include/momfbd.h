@@ -341,6 +341,30 @@ int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* t
 /* Human-readable text of a status code. */
 const char* momfbd_status_string(int status);
 
+/* Launch schedules of a plan: how units and frequencies map to workgroups.
+ * Results are the same for every schedule up to the order of floating-point
+ * sums (the unit order changes nothing; the object kernel's pairs per
+ * thread change the grouping of the FP64 loss partials, the gradient
+ * contraction's waves the grouping of its FP32 partial sums). */
+typedef struct {
+  int xcd_forward;              /* 1: units of a patch-object on one XCD (L2)   */
+  int xcd_adjoint;              /* same for the adjoint kernel                  */
+  int object_pairs_per_thread;  /* 1, 2 or 4 frequency pairs per thread         */
+  int grad_waves;               /* 4 or 8 waves per row tile (8 needs M <= 128) */
+} momfbd_tuning;
+/* Errors: EINVAL (NULL or a value out of range). */
+int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
+int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
+/* Choose the schedules by timing: one knob at a time, every candidate value
+ * is timed over `reps` loss+gradient evaluations of the caller's data (HIP
+ * events on `stream`, which this call synchronises) and the fastest kept.
+ * loss [P] and grad [P][J][M] (device) receive the last evaluation.  The
+ * choice is stored in the plan and, if `chosen` is not NULL, returned.
+ * Errors: EINVAL, EWORKSPACE, EDEVICE. */
+int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                         float gamma_scalar, const float* weights, int reps, double* loss,
+                         float* grad, void* ws, void* stream, momfbd_tuning* chosen);
+
 /* Sizes the plan was created with (any out pointer may be NULL). */
 int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M);
 

@@ -10,6 +10,7 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
                    momfbd_plan_destroy, momfbd_workspace_size, momfbd_plan_dims,
                    momfbd_object_filtered, momfbd_mosaic, filter_spec,
                    momfbd_synthesize, momfbd_lbfgs_rounds, momfbd_power_spectrum,
+                   momfbd_plan_set_tuning, momfbd_plan_get_tuning, momfbd_plan_autotune,
                    momfbd_cnn_create, momfbd_cnn_destroy,
                    momfbd_cnn_sizes, momfbd_cnn_init, momfbd_cnn_load, momfbd_cnn_forward,
                    momfbd_cnn_loss_grad, momfbd_cnn_adam,
@@ -23,7 +24,8 @@ __all__ = [
     "MomfbdError", "LIB_PATH", "momfbd_status_string", "momfbd_plan_create",
     "momfbd_plan_destroy", "momfbd_workspace_size", "momfbd_plan_dims", "momfbd_smoothness_gamma",
     "momfbd_object_filtered", "momfbd_mosaic", "filter_spec", "momfbd_synthesize",
-    "momfbd_lbfgs_rounds", "momfbd_power_spectrum",
+    "momfbd_lbfgs_rounds", "momfbd_power_spectrum", "momfbd_plan_set_tuning",
+    "momfbd_plan_get_tuning", "momfbd_plan_autotune",
     "momfbd_cnn_create", "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
     "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad", "momfbd_cnn_adam",
     "WarmStartNet",

@@ -42,6 +42,14 @@ class momfbd_filter(ctypes.Structure):
                 ("diff_limit", ctypes.c_float), ("noise_power", ctypes.c_float)]
 
 
+class momfbd_tuning(ctypes.Structure):
+    _fields_ = [("xcd_forward", ctypes.c_int), ("xcd_adjoint", ctypes.c_int),
+                ("object_pairs_per_thread", ctypes.c_int), ("grad_waves", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class momfbd_desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("C", ctypes.c_int),
                 ("K", ctypes.c_int), ("J", ctypes.c_int), ("M", ctypes.c_int),
@@ -77,6 +85,10 @@ def lib():
                                              ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
         L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
         L.momfbd_synthesize.argtypes = [_vp] * 10
+        tp = ctypes.POINTER(momfbd_tuning)
+        L.momfbd_plan_set_tuning.argtypes = [_vp, tp]
+        L.momfbd_plan_get_tuning.argtypes = [_vp, tp]
+        L.momfbd_plan_autotune.argtypes = [_vp, _vp, _vp, _vp, f, _vp, i, _vp, _vp, _vp, _vp, tp]
         L.momfbd_power_spectrum_workspace.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
         L.momfbd_power_spectrum.argtypes = [i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp]
         L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, _vp, _vp,
@@ -107,7 +119,8 @@ def lib():
                      "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
                      "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
-                     "momfbd_power_spectrum"):
+                     "momfbd_power_spectrum", "momfbd_plan_set_tuning", "momfbd_plan_get_tuning",
+                     "momfbd_plan_autotune"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -254,6 +267,27 @@ def momfbd_power_spectrum(image, window=None, nbins=None, stream=None):
                                        _ptr(counts), nb, _ptr(ws), _stream(stream, image)),
            "momfbd_power_spectrum")
     return power, sector, counts
+
+
+def momfbd_plan_set_tuning(plan, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves):
+    t = momfbd_tuning(xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves)
+    _check(lib().momfbd_plan_set_tuning(plan, ctypes.byref(t)), "momfbd_plan_set_tuning")
+
+
+def momfbd_plan_get_tuning(plan):
+    t = momfbd_tuning()
+    _check(lib().momfbd_plan_get_tuning(plan, ctypes.byref(t)), "momfbd_plan_get_tuning")
+    return t.as_dict()
+
+
+def momfbd_plan_autotune(plan, alpha, D, gamma, gamma_scalar, weights, reps, loss, grad, ws,
+                         stream=None):
+    t = momfbd_tuning()
+    _check(lib().momfbd_plan_autotune(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                                      _ptr(weights), int(reps), _ptr(loss), _ptr(grad), _ptr(ws),
+                                      _stream(stream, alpha), ctypes.byref(t)),
+           "momfbd_plan_autotune")
+    return t.as_dict()
 
 
 def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=None):

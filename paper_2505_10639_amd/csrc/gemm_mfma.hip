@@ -26,15 +26,16 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
   return acc;
 }
 
-// One block = 4 waves = 16 rows (p,j) x all mode columns; wave w sums the
-// quarter [w K/4, (w+1) K/4) of k = c*1024 + px; the partial sums are added
-// in fixed order (wave 0 + 1 + 2 + 3) through LDS.
-template <int MT>
-__global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, int bp,
-                                                   const float* __restrict__ Zt,
-                                                   const float* __restrict__ gphi,
-                                                   float* __restrict__ grad) {
-  __shared__ floatx4 red[3][MT][64];
+// One block = W waves = 16 rows (p,j) x all mode columns; wave w sums the
+// slice [w K/W, (w+1) K/W) of k = c*bp + px; the partial sums are added in
+// fixed order (wave 0 + 1 + ... + W-1) through LDS.  W (4 or 8) is a launch
+// schedule the autotuner picks.
+template <int MT, int W>
+__global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int M, int bp,
+                                                      const float* __restrict__ Zt,
+                                                      const float* __restrict__ gphi,
+                                                      float* __restrict__ grad) {
+  __shared__ floatx4 red[W - 1][MT][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
   const int r0 = blockIdx.x * 16;
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, i
   floatx4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int Kq = C * bp / 4;
+  const int Kq = C * bp / W;
   const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
   // operands of chunk kk: a from gphi row r, b[t] from mode rows t*16 + i16;
   // the next chunk's operands are loaded before the current chunk's MFMAs
@@ -81,9 +82,8 @@ __global__ __launch_bounds__(256) void k_grad_mfma(int R, int J, int C, int M, i
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     floatx4 v = acc[t];
-    v += red[0][t][lane];
-    v += red[1][t][lane];
-    v += red[2][t][lane];
+#pragma unroll
+    for (int w = 0; w < W - 1; ++w) v += red[w][t][lane];
     const int m = t * 16 + i16;
     if (m >= M) continue;
 #pragma unroll
@@ -148,8 +148,13 @@ template <int MT>
 void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
                    hipStream_t s) {
   const int R = d.P * d.J;
-  hipLaunchKernelGGL(k_grad_mfma<MT>, dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C, d.M,
-                     d.bandpix(),
+  // eight waves only while the partial sums fit in 64 KB of LDS
+  if (MT <= 8 && d.grad_waves == 8)
+    hipLaunchKernelGGL((k_grad_mfma<MT, (MT <= 8 ? 8 : 4)>), dim3((R + 15) / 16), dim3(512), 0, s,
+                       R, d.J, d.C, d.M, d.bandpix(), Zt, gphi, grad);
+  else
+    hipLaunchKernelGGL((k_grad_mfma<MT, 4>), dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C,
+                       d.M, d.bandpix(),
                      Zt, gphi, grad);
 }
 

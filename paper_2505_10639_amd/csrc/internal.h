@@ -13,11 +13,18 @@ constexpr int kMaxM = 256;
 constexpr int kBand = 32;            // band width for N = 64
 constexpr int kBandPix = kBand * kBand;
 
-// Blocks of 256 frequency pairs covering one half spectrum of side n.
-__host__ __device__ constexpr int object_blocks(int n) { return (n * (n / 2 + 1) / 2 + 255) / 256; }
+// Blocks of 256 threads, `ppt` frequency pairs per thread, covering one
+// half spectrum of side n.
+__host__ __device__ constexpr int object_blocks(int n, int ppt = 1) {
+  return (n * (n / 2 + 1) / 2 + 256 * ppt - 1) / (256 * ppt);
+}
 
 struct Dims {
   int N, P, C, K, J, M;
+  // launch schedules (chosen by momfbd_plan_autotune): XCD-grouped unit
+  // order of the forward / adjoint grids, frequency pairs per thread of the
+  // object kernel, waves per row tile of the gradient contraction
+  int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4;
   int band() const { return N / 2; }                 // pupil band width
   int bandpix() const { return (N / 2) * (N / 2); }  // pixels of the band
   int half() const { return N * (N / 2 + 1); }       // complex values of a half spectrum

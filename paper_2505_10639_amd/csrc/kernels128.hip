@@ -73,7 +73,7 @@ __device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* ps
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(kThreads) void k_forward128(int units, ChanTab ct, int C, int J,
+__global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, ChanTab ct, int C, int J,
                                                          const int* __restrict__ active,
                                                          const float* __restrict__ Ab,
                                                          const float* __restrict__ phi,
@@ -81,7 +81,8 @@ __global__ __launch_bounds__(kThreads) void k_forward128(int units, ChanTab ct, 
                                                          float2* __restrict__ S) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = blockIdx.x;
+  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
+                   : blockIdx.x;
   if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_forward128(int units, ChanTab ct, 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_adjoint128(int units, ChanTab ct, int C, int J,
+__global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, ChanTab ct, int C, int J,
                                                          int K, LossArgs la,
                                                          const int* __restrict__ active,
                                                          const float* __restrict__ Ab,
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, ChanTab ct, 
   __shared__ float2 Taux[LDS_AUX];
   // XCD-aware order: consecutive units (frames of one patch-object) on one XCD
   const int per = (units + kXcds - 1) / kXcds;
-  const int u = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (u >= units) return;
   const int lane = threadIdx.x;
   const int j = u % J;
@@ -298,11 +299,12 @@ __global__ __launch_bounds__(kThreads) void k_objimg128(int items, const float2*
 hipError_t launch_forward128(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                              const float* phi, float* psf, float2* S, hipStream_t s) {
   const int units = d.P * d.C * d.J;
+  const dim3 grid(d.xcd_fwd ? kXcds * ((units + kXcds - 1) / kXcds) : units);
   if (psf)
-    hipLaunchKernelGGL(k_forward128<true>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+    hipLaunchKernelGGL(k_forward128<true>, grid, dim3(kThreads), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
   else
-    hipLaunchKernelGGL(k_forward128<false>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C,
+    hipLaunchKernelGGL(k_forward128<false>, grid, dim3(kThreads), 0, s, units, d.xcd_fwd, ct, d.C,
                        d.J, active, Ab, phi, psf, S);
   return hipGetLastError();
 }
@@ -312,7 +314,8 @@ hipError_t launch_adjoint128(const Dims& d, const ChanTab& ct, const LossArgs& l
                              const float2* S, const float2* O, float* gphi, hipStream_t s) {
   const int units = d.P * d.C * d.J;
   const int per = (units + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL(k_adjoint128, dim3(kXcds * per), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+  hipLaunchKernelGGL(k_adjoint128, dim3(d.xcd_adj ? kXcds * per : units), dim3(kThreads), 0, s,
+                     units, d.xcd_adj, ct, d.C, d.J,
                      d.K, la, active, Ab, phi, S, O, gphi);
   return hipGetLastError();
 }

@@ -66,7 +66,7 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const f
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, int J,
+__global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct, int C, int J,
                                                   const int* __restrict__ active,
                                                   const float* __restrict__ Ab,
                                                   const float* __restrict__ phi,
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
                                                   float2* __restrict__ S) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = blockIdx.x;
+  const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
   if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
@@ -113,7 +113,8 @@ __global__ __launch_bounds__(64) void k_forward64(int units, ChanTab ct, int C, 
   out[sl_index32(lane)] = x32;
 }
 
-__global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, int J, int K,
+__global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct, int C, int J,
+                                                  int K,
                                                   LossArgs la, const int* __restrict__ active,
                                                   const float* __restrict__ Ab,
                                                   const float* __restrict__ phi,
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, ChanTab ct, int C, 
                                                   float* __restrict__ gphi) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = xcd_unit(xcd_per(units));
+  const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
   if (u >= units) return;
   const int lane = threadIdx.x;
   const int j = u % J;
@@ -310,11 +311,12 @@ hipError_t launch_synth64(const Dims& d, const ChanTab& ct, const float2* O, con
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                             const float* phi, float* psf, float2* S, hipStream_t s) {
   const int units = d.P * d.C * d.J;
+  const dim3 grid(d.xcd_fwd ? kXcds * xcd_per(units) : units);
   if (psf)
-    hipLaunchKernelGGL(k_forward64<true>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J,
+    hipLaunchKernelGGL(k_forward64<true>, grid, dim3(64), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
   else
-    hipLaunchKernelGGL(k_forward64<false>, dim3(units), dim3(64), 0, s, units, ct, d.C, d.J,
+    hipLaunchKernelGGL(k_forward64<false>, grid, dim3(64), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
   return hipGetLastError();
 }
@@ -323,8 +325,9 @@ hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la
                             const int* active, const float* Ab, const float* phi, const float2* S,
                             const float2* O, float* gphi, hipStream_t s) {
   const int units = d.P * d.C * d.J;
-  hipLaunchKernelGGL(k_adjoint64, dim3(kXcds * xcd_per(units)), dim3(64), 0, s, units, ct, d.C,
-                     d.J, d.K, la, active, Ab, phi, S, O, gphi);
+  const dim3 grid(d.xcd_adj ? kXcds * xcd_per(units) : units);
+  hipLaunchKernelGGL(k_adjoint64, grid, dim3(64), 0, s, units, d.xcd_adj, ct, d.C, d.J, d.K, la,
+                     active, Ab, phi, S, O, gphi);
   return hipGetLastError();
 }
 

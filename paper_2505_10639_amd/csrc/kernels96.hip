@@ -45,7 +45,7 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A,
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(kThreads) void k_forward96(int units, ChanTab ct, int C, int J,
+__global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, ChanTab ct, int C, int J,
                                                         const int* __restrict__ active,
                                                         const float* __restrict__ Ab,
                                                         const float* __restrict__ phi,
@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_forward96(int units, ChanTab ct, i
                                                         float2* __restrict__ S) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = blockIdx.x;
+  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
+                   : blockIdx.x;
   if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_forward96(int units, ChanTab ct, i
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_adjoint96(int units, ChanTab ct, int C, int J,
+__global__ __launch_bounds__(kThreads) void k_adjoint96(int units, int xcd, ChanTab ct, int C, int J,
                                                         int K, LossArgs la,
                                                         const int* __restrict__ active,
                                                         const float* __restrict__ Ab,
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint96(int units, ChanTab ct, i
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
   const int per = (units + kXcds - 1) / kXcds;
-  const int u = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (u >= units) return;
   const int lane = threadIdx.x;
   const bool on = lane < LANES;
@@ -255,11 +256,12 @@ __global__ __launch_bounds__(kThreads) void k_objimg96(int items, const float2* 
 hipError_t launch_forward96(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                             const float* phi, float* psf, float2* S, hipStream_t s) {
   const int units = d.P * d.C * d.J;
+  const dim3 grid(d.xcd_fwd ? kXcds * ((units + kXcds - 1) / kXcds) : units);
   if (psf)
-    hipLaunchKernelGGL(k_forward96<true>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+    hipLaunchKernelGGL(k_forward96<true>, grid, dim3(kThreads), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
   else
-    hipLaunchKernelGGL(k_forward96<false>, dim3(units), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+    hipLaunchKernelGGL(k_forward96<false>, grid, dim3(kThreads), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
   return hipGetLastError();
 }
@@ -269,7 +271,8 @@ hipError_t launch_adjoint96(const Dims& d, const ChanTab& ct, const LossArgs& la
                             const float2* O, float* gphi, hipStream_t s) {
   const int units = d.P * d.C * d.J;
   const int per = (units + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL(k_adjoint96, dim3(kXcds * per), dim3(kThreads), 0, s, units, ct, d.C, d.J,
+  hipLaunchKernelGGL(k_adjoint96, dim3(d.xcd_adj ? kXcds * per : units), dim3(kThreads), 0, s,
+                     units, d.xcd_adj, ct, d.C, d.J,
                      d.K, la, active, Ab, phi, S, O, gphi);
   return hipGetLastError();
 }

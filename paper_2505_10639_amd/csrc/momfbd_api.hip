@@ -267,6 +267,32 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   return MOMFBD_OK;
 }
 
+static bool tuning_ok(const momfbd_tuning* t, int M) {
+  return t && (t->xcd_forward == 0 || t->xcd_forward == 1) &&
+         (t->xcd_adjoint == 0 || t->xcd_adjoint == 1) &&
+         (t->object_pairs_per_thread == 1 || t->object_pairs_per_thread == 2 ||
+          t->object_pairs_per_thread == 4) &&
+         (t->grad_waves == 4 || (t->grad_waves == 8 && (M + 15) / 16 <= 8));
+}
+
+int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
+  if (!plan || !tuning_ok(t, plan->d.M)) return MOMFBD_EINVAL;
+  plan->d.xcd_fwd = t->xcd_forward;
+  plan->d.xcd_adj = t->xcd_adjoint;
+  plan->d.obj_ppt = t->object_pairs_per_thread;
+  plan->d.grad_waves = t->grad_waves;
+  return MOMFBD_OK;
+}
+
+int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* t) {
+  if (!plan || !t) return MOMFBD_EINVAL;
+  t->xcd_forward = plan->d.xcd_fwd;
+  t->xcd_adjoint = plan->d.xcd_adj;
+  t->object_pairs_per_thread = plan->d.obj_ppt;
+  t->grad_waves = plan->d.grad_waves;
+  return MOMFBD_OK;
+}
+
 int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M) {
   if (!plan) return MOMFBD_EINVAL;
   if (N) *N = plan->d.N;
@@ -571,6 +597,58 @@ int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, voi
     e = launch_lbfgs_publish(plan->d, L, state, alpha, alpha_accepted, s);
   if (e == hipSuccess) e = launch_lbfgs_finish(plan->d, L, state, loss, status, s);
   return to_status(e);
+}
+
+// Greedy search over the launch schedules, one knob at a time, timing whole
+// loss+gradient evaluations on the caller's data with events on `stream`.
+int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
+                         float gamma_scalar, const float* weights, int reps, double* loss,
+                         float* grad, void* ws, void* stream, momfbd_tuning* chosen) {
+  int st = check_call(plan, ws);
+  if (st) return st;
+  if (!alpha || !D || !loss || !grad || reps < 1) return MOMFBD_EINVAL;
+  if ((st = pending_error())) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return MOMFBD_EDEVICE;
+  }
+  auto timed = [&](float* ms) -> int {
+    int r = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws, s);
+    if (r) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return MOMFBD_EDEVICE;
+    for (int i = 0; i < reps; ++i) {
+      r = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws, s);
+      if (r) return r;
+    }
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return MOMFBD_EDEVICE;
+    return MOMFBD_OK;
+  };
+  int* knobs[4] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves};
+  const std::vector<int> values[4] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}};
+  for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
+    int best = *knobs[k];
+    float best_ms = 1e30f;
+    for (int v : values[k]) {
+      if (k == 3 && v == 8 && (plan->d.M + 15) / 16 > 8) continue;
+      *knobs[k] = v;
+      float ms = 0.f;
+      if ((st = timed(&ms))) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    *knobs[k] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (chosen) momfbd_plan_get_tuning(plan, chosen);
+  return MOMFBD_OK;
 }
 
 }  // extern "C"

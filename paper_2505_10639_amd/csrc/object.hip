@@ -2,7 +2,8 @@
 // and the size dispatch of the unit kernels.
 //
 // Each (patch, object) plane of the half spectrum is cut into blocks of 256
-// pairs of adjacent frequencies, one pair per thread (16-byte loads); every
+// threads, each thread taking PPT pairs of adjacent frequencies (16-byte
+// loads; PPT is a launch schedule the autotuner picks); every
 // block leaves one FP64 partial of the loss, summed per patch in a fixed
 // order by k_loss_sum.  One pass over D and S: N = sum w D conj(S),
 // Q = gamma + sum w |S|^2 and E = sum w |D|^2 are accumulated in FP64, where
@@ -35,7 +36,7 @@ __device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) 
   a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
 }
 
-template <int NN>
+template <int NN, int PPT>
 __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, ChanTab ct,
                                                 LossArgs la, const int* __restrict__ active,
                                                 const float2* __restrict__ S,
@@ -44,16 +45,17 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
   constexpr int HC = NN / 2 + 1;
   constexpr int kUnitF2 = NN * HC;
   constexpr int kPairs = kUnitF2 / 2;
-  constexpr int kBlocks = object_blocks(NN);
+  constexpr int kBlocks = object_blocks(NN, PPT);
   __shared__ double red[256];
   const int plane = blockIdx.x / kBlocks, part = blockIdx.x % kBlocks;
   const int p = plane / K, k = plane % K;
   if (active && !active[p]) return;
   const int tid = threadIdx.x;
-  const int f2 = part * 256 + tid;
   double acc = 0.0;
   const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
-  if (f2 < kPairs) {
+  for (int e = 0; e < PPT; ++e) {
+    const int f2 = (part * PPT + e) * 256 + tid;
+    if (f2 >= kPairs) break;
     const int f = 2 * f2;
     Acc2 a;
     for (int i = 0; i < 2; ++i) {
@@ -86,8 +88,8 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
     const int kx0 = f % HC, kx1 = (f + 1) % HC;
     const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
     const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
-    acc = h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
-          h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
+    acc += h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
+           h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
     reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
   }
   red[tid] = acc;
@@ -132,19 +134,32 @@ hipError_t launch_smoothness(int N, int K, const PriorTab& t, float* gamma, hipS
   return hipGetLastError();
 }
 
+template <int NN>
+void launch_object_n(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
+                     const float2* S, float2* O, double* loss_pk, hipStream_t s) {
+  const int ppt = d.obj_ppt;
+  const dim3 grid(d.P * d.K * object_blocks(NN, ppt));
+  if (ppt == 4)
+    hipLaunchKernelGGL((k_object<NN, 4>), grid, dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la,
+                       active, S, O, loss_pk);
+  else if (ppt == 2)
+    hipLaunchKernelGGL((k_object<NN, 2>), grid, dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la,
+                       active, S, O, loss_pk);
+  else
+    hipLaunchKernelGGL((k_object<NN, 1>), grid, dim3(256), 0, s, d.P, d.C, d.J, d.K, ct, la,
+                       active, S, O, loss_pk);
+}
+
 hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                          const float2* S, float2* O, double* loss_pk, double* loss,
                          hipStream_t s) {
-  const int nb = object_blocks(d.N);
   if (d.N == 64)
-    hipLaunchKernelGGL(k_object<64>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
-                       ct, la, active, S, O, loss_pk);
+    launch_object_n<64>(d, ct, la, active, S, O, loss_pk, s);
   else if (d.N == 96)
-    hipLaunchKernelGGL(k_object<96>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
-                       ct, la, active, S, O, loss_pk);
+    launch_object_n<96>(d, ct, la, active, S, O, loss_pk, s);
   else
-    hipLaunchKernelGGL(k_object<128>, dim3(d.P * d.K * nb), dim3(256), 0, s, d.P, d.C, d.J, d.K,
-                       ct, la, active, S, O, loss_pk);
+    launch_object_n<128>(d, ct, la, active, S, O, loss_pk, s);
+  const int nb = object_blocks(d.N, d.obj_ppt);
   hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K * nb, active,
                      loss_pk, loss);
   return hipGetLastError();

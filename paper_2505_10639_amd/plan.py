@@ -92,6 +92,25 @@ class Plan:
         _lib.momfbd_synthesize(self.handle, alpha, O, noise, sigma, apod, frames, D, self.ws)
         return frames, D
 
+    def tuning(self):
+        return _lib.momfbd_plan_get_tuning(self.handle)
+
+    def set_tuning(self, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves):
+        _lib.momfbd_plan_set_tuning(self.handle, xcd_forward, xcd_adjoint,
+                                    object_pairs_per_thread, grad_waves)
+
+    def autotune(self, alpha, D, gamma=1e-3, weights=None, reps=5):
+        """Time the launch schedules on this data and keep the fastest."""
+        self._alpha(alpha)
+        self._D(D)
+        g_arr, g_sc = self._gamma(gamma)
+        self._weights(weights)
+        loss = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        grad = torch.empty((self.P, self.J, self.M), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            return _lib.momfbd_plan_autotune(self.handle, alpha, D, g_arr, g_sc, weights, reps,
+                                             loss, grad, self.ws)
+
     def smoothness_gamma(self, gamma0, lam):
         """Per-frequency gamma [K][N][N/2+1] of the object smoothness prior
         for objects with constants gamma0[K] and lambda[K]."""

@@ -341,6 +341,50 @@ def test_karhunen_loeve_basis(dev):
     check_patchwise(pr, D_np, alpha_points(pr, 5), dev)
 
 
+@pytest.mark.parametrize("N", [64, 96, 128])
+def test_launch_schedules_and_autotune(dev, N):
+    """Every launch schedule gives the default results: bit for bit where
+    only the order of the work changes (unit order), to the rounding of a
+    regrouped sum where the grouping of partial sums changes (object pairs
+    per thread: FP64 loss; gradient waves: FP32 gradient).  The autotuned
+    plan still matches the oracle."""
+    pr = synth.make_problem(70 + N, N=N, P=3, J=3, M=28, channels=((0, 0.0), (1, 1.0)),
+                            d_over_r0=np.array([7.0, 11.0, 15.0]), border=N // 10)
+    D_np = simulate_D(pr)
+    D = to_dev(D_np, dev)
+    a = to_dev(alpha_points(pr, 10)["perturbed"], dev)
+    plan = make_plan(pr, dev)
+    assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
+                             "grad_waves": 4}
+    l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
+    for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
+                  (1, 0, 4, 8)]:
+        print(f"[tuning] N={N} {knobs}", flush=True)
+        plan.set_tuning(*knobs)
+        l1, g1 = plan.loss_grad(a, D, pr.gamma)
+        torch.cuda.synchronize()
+        if knobs[2] == 1:
+            assert torch.equal(l1, l0)
+        else:
+            assert float(((l1 - l0).abs() / l0.abs()).max()) < 1e-12
+        if knobs[3] == 4:
+            assert torch.equal(g1, g0)
+        else:
+            assert float((g1 - g0).norm() / g0.norm()) < 1e-6
+    plan.set_tuning(0, 1, 1, 4)
+    chosen = plan.autotune(a, D, pr.gamma, reps=2)
+    print(f"[tuning] N={N} autotuned {chosen}", flush=True)
+    assert chosen == plan.tuning()
+    loss, grad = run_gpu(plan, alpha_points(pr, 10)["perturbed"], D, pr.gamma, None, dev)
+    ref = oracle.evaluate(alpha_points(pr, 10)["perturbed"], D_np, pr.basis, pr.diversity,
+                          pr.pupil, pr.channel_object, pr.gamma)
+    assert np.all(np.abs(loss - ref["loss"]) / np.abs(ref["loss"]) < LOSS_RTOL)
+    assert max(grad_errs(grad, ref["grad"])) < GRAD_RTOL
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 3, 4)
+    plan.close()
+
+
 # ------------------------------------------------------------ 128 x 128 patches
 
 def test_n128_loss_and_gradient(dev):

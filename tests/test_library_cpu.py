@@ -104,3 +104,7 @@ def test_calls_reject_null_plan_and_workspace(L):
     assert L.momfbd_power_spectrum_workspace(100, 10, ctypes.byref(n)) == -1   # not a power of two
     assert L.momfbd_power_spectrum_workspace(64, 65, ctypes.byref(n)) == -1    # nbins > L
     assert L.momfbd_power_spectrum_workspace(64, 33, ctypes.byref(n)) == 0 and n.value > 64 * 64 * 8
+    assert L.momfbd_plan_set_tuning(None, None) == -1
+    assert L.momfbd_plan_get_tuning(None, None) == -1
+    assert L.momfbd_plan_autotune(None, None, None, None, 1e-3, None, 1, None, None, None, None,
+                                  None) == -1
