@@ -51,19 +51,26 @@ def unit_flops(N):
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
 # the reading of the same counter for a plain 256 MiB device copy (FETCH_SIZE
 # reads half the copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid
-# only for the kernel sources they were taken on: a changed source hash
-# reports null.
+# only for the kernel sources they were taken on (a changed source hash
+# reports null) and looked up by the value of the launch-schedule knob that
+# changes the kernel's traffic.
 KERNEL_SOURCES = {
     "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h"],
     "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
     "object": ["object.hip"],
 }
-COPY_FETCH_SCALE = 1.999779725496011    # 256 MiB copy: FETCH_SIZE read 131086.4 KiB
+COPY_FETCH_SCALE = 1.9997741954186083    # 256 MiB copy: FETCH_SIZE read 131086.8 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
+# per kernel: the knob and, per value of it, (HBM bytes read, written) per
+# launch
 COUNTED_TRAFFIC = {
-    "adjoint": {"fetch_bytes": 1011085890, "write_bytes": 94470144, "sources_sha1": "2a4eaefe84bc"},
-    "forward": {"fetch_bytes": 94959930, "write_bytes": 395331504, "sources_sha1": "2a4eaefe84bc"},
-    "object": {"fetch_bytes": 779373583, "write_bytes": 32822483, "sources_sha1": "6a042132d212"},
+    "adjoint": {"sources_sha1": "1577f6f374fb", "knob": "xcd_adjoint",
+                "by_value": {1: (1010802857, 94470144), 0: (1306376709, 94470144)}},
+    "forward": {"sources_sha1": "1577f6f374fb", "knob": "xcd_forward",
+                "by_value": {0: (94961203, 395071989), 1: (94962541, 392118775)}},
+    "object": {"sources_sha1": "26d2c7680506", "knob": "object_pairs_per_thread",
+               "by_value": {1: (779376483, 32826246), 2: (779377533, 32670008),
+                            4: (779374621, 32605784)}},
 }
 
 
@@ -75,11 +82,12 @@ def sources_sha(kernel):
     return h.hexdigest()[:12]
 
 
-def counted_traffic(kernel):
+def counted_traffic(kernel, schedule):
     rec = COUNTED_TRAFFIC.get(kernel)
     if rec is None or rec["sources_sha1"] != sources_sha(kernel):
         return None
-    return rec["fetch_bytes"] + rec["write_bytes"]
+    rw = rec["by_value"].get(schedule.get(rec["knob"]))
+    return None if rw is None else rw[0] + rw[1]
 
 
 def log(msg):
@@ -161,12 +169,24 @@ def build_large(dev):
     return plan, D, alpha, gamma, g
 
 
-def time_steps(plan, D, alpha, gamma, steps, warmup):
-    """ms per loss+grad step (HIP events on the launch stream) and the
-    per-kernel average durations from the library's own event pairs."""
+KINDS = ("phase", "forward", "object", "adjoint", "grad")
+
+
+def time_steps(plan, D, alpha, gamma, steps, warmup, tune=True, reps=10):
+    """ms per loss+grad step (HIP events on the launch stream) and two sets
+    of per-kernel average durations from the library's event pairs on the
+    same stream: back to back (each launch of one kind issued `reps` times
+    in a row inside one pair, as the kernels run inside a step, with no idle
+    gap in front) and isolated (one pair around every launch).  The plan's
+    launch schedules are first chosen by the library's autotuner on the
+    same data (a setup step, outside the timed region)."""
     import torch
 
-    from paper_2505_10639_amd import momfbd_profile_start, momfbd_profile_stop
+    if tune:
+        plan.autotune(alpha, D, gamma, None, reps=3)
+
+    from paper_2505_10639_amd import (momfbd_profile_repeat, momfbd_profile_start,
+                                      momfbd_profile_stop)
 
     loss = torch.empty(plan.P, dtype=torch.float64, device=plan.device)
     grad = torch.empty_like(alpha)
@@ -192,7 +212,16 @@ def time_steps(plan, D, alpha, gamma, steps, warmup):
     for _ in range(steps):
         step()
     kern = momfbd_profile_stop(plan.handle)
-    return ms, {k: v[0] / v[1] for k, v in kern.items()}, loss, grad
+    isolated = {k: v[0] / v[1] for k, v in kern.items()}
+    b2b = {}
+    for kind in KINDS:
+        momfbd_profile_start(plan.handle, 8)
+        momfbd_profile_repeat(plan.handle, kind, reps)
+        for _ in range(3):
+            step()
+        k = momfbd_profile_stop(plan.handle)[kind]
+        b2b[kind] = k[0] / k[1]
+    return ms, b2b, isolated, loss, grad
 
 
 def roofline(kern_avg, units, N, D_bytes, traffic_of):
@@ -373,6 +402,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the 128 x 128 workload")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch schedules instead of autotuning them")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--warm-steps", type=int, default=6000,
                     help="training steps of the warm-start network (0: skip that block)")
@@ -404,9 +435,11 @@ def main():
     N, P, C, J = g["N"], g["P"], g["C"], g["J"]
     units = P * C * J
     log(f"timing {args.steps} steps after {args.warmup} warm-up")
-    ms, kern_avg, _, _ = time_steps(plan, D, alpha, gamma, args.steps, args.warmup)
+    ms, kern_avg, kern_iso, _, _ = time_steps(plan, D, alpha, gamma, args.steps, args.warmup,
+                                              not args.no_tune)
     D_bytes = D.numel() * 8
-    roof = roofline(kern_avg, units, N, D_bytes, counted_traffic)
+    sched = plan.tuning()
+    roof = roofline(kern_avg, units, N, D_bytes, lambda k: counted_traffic(k, sched))
     flop_unit, _ = unit_flops(N)
     step_tflops = flop_unit * units / (ms * 1e-3) / 1e12
     out = {
@@ -420,12 +453,14 @@ def main():
                                "64x64 at stride 32, 12 frames, 2 objects (wideband + "
                                "phase diversity), 66 Zernike modes, D/r0 5..20",
                    "patches": P, "frames": J, "channels": C, "objects": g["K"],
-                   "modes": g["M"], "N": N, "units_per_step": units},
+                   "modes": g["M"], "N": N, "units_per_step": units,
+                   "launch_schedule": plan.tuning()},
         "roofline": roof,
         "units_per_s": units / (ms * 1e-3),
         "step_nominal_fft_tflops": step_tflops,
         "step_frac_of_fp32_peak": step_tflops / PEAK_FP32_VECTOR_TFLOPS,
         "kernels_avg_ms": kern_avg,
+        "kernels_avg_ms_isolated": kern_iso,
     }
     D_h = a_h = None
     if not args.no_cpu:
@@ -440,7 +475,8 @@ def main():
         units4 = g4["P"] * g4["C"] * g4["J"]
         steps4 = max(2, args.steps // 2)
         log(f"timing {steps4} steps of the 128x128 workload")
-        ms4, kern4, _, _ = time_steps(plan4, D4, alpha4, gamma4, steps4, min(args.warmup, 2))
+        ms4, kern4, kern4_iso, _, _ = time_steps(plan4, D4, alpha4, gamma4, steps4,
+                                                 min(args.warmup, 2), not args.no_tune)
         flop4, _ = unit_flops(g4["N"])
         t4 = flop4 * units4 / (ms4 * 1e-3) / 1e12
         out["large_multi_object"] = {
@@ -451,7 +487,9 @@ def main():
             "ms_per_step": ms4, "steps": steps4, "units_per_step": units4,
             "step_nominal_fft_tflops": t4, "step_frac_of_fp32_peak": t4 / PEAK_FP32_VECTOR_TFLOPS,
             "roofline": roofline(kern4, units4, g4["N"], D4.numel() * 8, lambda k: None),
+            "launch_schedule": plan4.tuning(),
             "kernels_avg_ms": kern4,
+            "kernels_avg_ms_isolated": kern4_iso,
         }
         plan4.close()
         del D4, alpha4, gamma4

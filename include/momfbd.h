@@ -327,8 +327,19 @@ int momfbd_cnn_adam(momfbd_cnn net, float* params, const float* grad, float* m1,
 /* Kernel timing for measurement.  After momfbd_profile_start, every kernel
  * launched by this plan's calls (up to max_launches launches) is bracketed
  * by a pair of HIP events recorded on the call's stream.  Events are created
- * here, not in the calls.  Errors: EINVAL, EDEVICE. */
+ * here, not in the calls, with a device-scope release (no system-scope cache
+ * write-back between the timed kernels).  Errors: EINVAL, EDEVICE. */
 int momfbd_profile_start(momfbd_plan plan, int max_launches);
+
+/* Back-to-back timing of one kernel kind (after momfbd_profile_start): from
+ * now until momfbd_profile_stop only the launches of `kind` are bracketed,
+ * and each is issued `reps` times in a row inside its event pair, so the
+ * kernel is timed without the idle gaps that per-launch events put in front
+ * of it.  Every kernel overwrites its outputs, so results are unchanged;
+ * "filter" (which scales the object spectrum in place) is refused.  The
+ * reported launch count includes the repeats.  Errors: EINVAL (no timing
+ * started, unknown kind, reps < 1). */
+int momfbd_profile_repeat(momfbd_plan plan, const char* kind, int reps);
 
 /* Synchronise on the recorded events, stop timing, and report per kernel
  * kind: a static name ("phase", "forward", "object", "adjoint", "grad",
@@ -357,7 +368,9 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
 int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
 /* Choose the schedules by timing: one knob at a time, every candidate value
  * is timed over `reps` loss+gradient evaluations of the caller's data (HIP
- * events on `stream`, which this call synchronises) and the fastest kept.
+ * events on `stream`, which this call synchronises) and the fastest kept;
+ * the first candidate of each knob is the library default, and another
+ * value replaces the best so far only when at least 1% faster.
  * loss [P] and grad [P][J][M] (device) receive the last evaluation.  The
  * choice is stored in the plan and, if `chosen` is not NULL, returned.
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */

@@ -16,7 +16,7 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
                    momfbd_cnn_loss_grad, momfbd_cnn_adam,
                    momfbd_smoothness_gamma,
                    momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
-                   momfbd_object_estimate, momfbd_profile_start,
+                   momfbd_object_estimate, momfbd_profile_start, momfbd_profile_repeat,
                    momfbd_profile_stop, momfbd_lbfgs_state_size, momfbd_lbfgs_init,
                    momfbd_lbfgs_step, lbfgs_params, lib)
 
@@ -31,7 +31,8 @@ __all__ = [
     "WarmStartNet",
     "momfbd_prepare_data",
     "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",
-    "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init", "momfbd_lbfgs_step",
+    "momfbd_profile_repeat", "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
+    "momfbd_lbfgs_step",
     "lbfgs_params", "lib", "Plan", "Solver",
     "MomfbdLoss", "momfbd_loss",
 ]

@@ -104,6 +104,7 @@ def lib():
         L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
+        L.momfbd_profile_repeat.argtypes = [_vp, ctypes.c_char_p, i]
         pp = ctypes.POINTER(momfbd_lbfgs_params)
         L.momfbd_lbfgs_state_size.argtypes = [_vp, pp, ctypes.POINTER(ctypes.c_size_t)]
         L.momfbd_lbfgs_init.argtypes = [_vp, pp, _vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
@@ -113,9 +114,9 @@ def lib():
         for name in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
                      "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
-                     "momfbd_profile_stop", "momfbd_lbfgs_state_size", "momfbd_lbfgs_init",
-                     "momfbd_lbfgs_step", "momfbd_smoothness_gamma", "momfbd_object_filtered",
-                     "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
+                     "momfbd_profile_repeat", "momfbd_profile_stop", "momfbd_lbfgs_state_size",
+                     "momfbd_lbfgs_init", "momfbd_lbfgs_step", "momfbd_smoothness_gamma",
+                     "momfbd_object_filtered", "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
                      "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
                      "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
@@ -343,6 +344,10 @@ def momfbd_cnn_adam(net, params, grad, m1, m2, step, lr, beta1, beta2, eps, ws, 
 
 def momfbd_profile_start(plan, max_launches: int):
     _check(lib().momfbd_profile_start(plan, int(max_launches)), "momfbd_profile_start")
+
+
+def momfbd_profile_repeat(plan, kind: str, reps: int):
+    _check(lib().momfbd_profile_repeat(plan, kind.encode(), int(reps)), "momfbd_profile_repeat")
 
 
 def momfbd_profile_stop(plan) -> dict:

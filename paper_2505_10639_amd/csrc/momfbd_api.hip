@@ -17,12 +17,15 @@ enum KernelKind { KK_PHASE, KK_FORWARD, KK_OBJECT, KK_ADJOINT, KK_GRAD, KK_PREPA
 static const char* kKernelNames[KK_COUNT] = {"phase", "forward", "object", "adjoint", "grad",
                                              "prepare", "objimg", "filter", "mosaic"};
 
-// Optional kernel timing: an event pair around every launch, on its stream.
+// Optional kernel timing: an event pair around every launch, on its stream;
+// or, with a repeat kind set, only around the launches of that kind, each
+// issued `reps` times in a row inside its pair.
 struct Profiler {
   bool on = false;
   int used = 0;
+  int rep_kind = -1, reps = 1;
   std::vector<hipEvent_t> ev0, ev1;
-  std::vector<int> kind;
+  std::vector<int> kind, count;
 };
 
 struct momfbd_plan_s {
@@ -75,21 +78,25 @@ bool cyclic_extent(const std::vector<char>& used, int N, int* start, int* len) {
 
 // Records a start event before and an end event after one launch when the
 // plan's profiler is on (no effect otherwise).
-struct ProfScope {
-  Profiler* pr;
-  hipStream_t s;
+// Issue one launch (the callable returns its hipError_t) under the plan's
+// profiler.  Every kernel overwrites its outputs, so a repeated launch
+// leaves the results unchanged.
+template <class F>
+hipError_t prof_launch(momfbd_plan plan, int kind, hipStream_t s, F&& launch) {
+  Profiler& pr = plan->prof;
+  const bool rep = pr.on && pr.rep_kind == kind;
   int slot = -1;
-  ProfScope(momfbd_plan plan, int kind, hipStream_t st) : pr(&plan->prof), s(st) {
-    if (pr->on && pr->used < (int)pr->ev0.size()) {
-      slot = pr->used++;
-      pr->kind[slot] = kind;
-      (void)hipEventRecord(pr->ev0[slot], s);
-    }
+  if (pr.on && (pr.rep_kind < 0 || rep) && pr.used < (int)pr.ev0.size()) {
+    slot = pr.used++;
+    pr.kind[slot] = kind;
+    pr.count[slot] = rep ? pr.reps : 1;
+    (void)hipEventRecord(pr.ev0[slot], s);
   }
-  ~ProfScope() {
-    if (slot >= 0) (void)hipEventRecord(pr->ev1[slot], s);
-  }
-};
+  hipError_t e = launch();
+  for (int i = 1; rep && i < pr.reps && e == hipSuccess; ++i) e = launch();
+  if (slot >= 0) (void)hipEventRecord(pr.ev1[slot], s);
+  return e;
+}
 
 int check_call(momfbd_plan plan, const void* ws) {
   if (!plan) return MOMFBD_EINVAL;
@@ -320,9 +327,10 @@ int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int
   const long ny = (H - N) / stride + 1, nx = (W - N) / stride + 1;
   if (ny * nx != plan->d.P) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
-  ProfScope ps(plan, KK_PREPARE, (hipStream_t)stream);
-  return to_status(launch_prepare(plan->d, frames, H, W, stride, apod,
-                                    static_cast<float2*>(D), (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  return to_status(prof_launch(plan, KK_PREPARE, s, [&] {
+    return launch_prepare(plan->d, frames, H, W, stride, apod, static_cast<float2*>(D), s);
+  }));
 }
 
 int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, void* ws,
@@ -333,16 +341,14 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   if ((st = pending_error())) return st;
   const Workspace w = carve_workspace(plan->d, ws);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e;
-  {
-    ProfScope ps(plan, KK_PHASE, s);
-    e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
-  }
-  if (e == hipSuccess) {
-    ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, psf,
-                         otf ? static_cast<float2*>(otf) : w.S, s);
-  }
+  hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
+    return launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+  });
+  if (e == hipSuccess)
+    e = prof_launch(plan, KK_FORWARD, s, [&] {
+      return launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, psf,
+                            otf ? static_cast<float2*>(otf) : w.S, s);
+    });
   return to_status(e);
 }
 
@@ -351,19 +357,17 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
                       void* ws, hipStream_t s, Workspace* wout) {
   const Workspace w = carve_workspace(plan->d, ws);
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
-  hipError_t e;
-  {
-    ProfScope ps(plan, KK_PHASE, s);
-    e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
-  }
-  if (e == hipSuccess) {
-    ProfScope ps(plan, KK_FORWARD, s);
-    e = launch_forward(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
-  }
-  if (e == hipSuccess) {
-    ProfScope ps(plan, KK_OBJECT, s);
-    e = launch_object(plan->d, plan->ct, la, active, w.S, w.O, w.loss_pk, loss, s);
-  }
+  hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
+    return launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+  });
+  if (e == hipSuccess)
+    e = prof_launch(plan, KK_FORWARD, s, [&] {
+      return launch_forward(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
+    });
+  if (e == hipSuccess)
+    e = prof_launch(plan, KK_OBJECT, s, [&] {
+      return launch_object(plan->d, plan->ct, la, active, w.S, w.O, w.loss_pk, loss, s);
+    });
   *wout = w;
   return to_status(e);
 }
@@ -376,15 +380,11 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
   int st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, active, loss, ws, s, &w);
   if (st || !grad) return st;
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
-  hipError_t e;
-  {
-    ProfScope ps(plan, KK_ADJOINT, s);
-    e = launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
-  }
-  if (e == hipSuccess) {
-    ProfScope ps(plan, KK_GRAD, s);
-    e = launch_grad(plan->d, plan->Zt, w.gphi, grad, s);
-  }
+  hipError_t e = prof_launch(plan, KK_ADJOINT, s, [&] {
+    return launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
+  });
+  if (e == hipSuccess)
+    e = prof_launch(plan, KK_GRAD, s, [&] { return launch_grad(plan->d, plan->Zt, w.gphi, grad, s); });
   return to_status(e);
 }
 
@@ -429,8 +429,8 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
   double* scratch_loss = reinterpret_cast<double*>(carve_workspace(plan->d, ws).gphi);
   st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, scratch_loss, ws, s, &w);
   if (st) return st;
-  ProfScope ps(plan, KK_OBJIMG, s);
-  return to_status(launch_objimg(plan->d, w.O, obj, s));
+  return to_status(
+      prof_launch(plan, KK_OBJIMG, s, [&] { return launch_objimg(plan->d, w.O, obj, s); }));
 }
 
 int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
@@ -461,15 +461,14 @@ int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
   double* scratch_loss = reinterpret_cast<double*>(carve_workspace(plan->d, ws).gphi);
   st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, scratch_loss, ws, s, &w);
   if (st) return st;
-  hipError_t e;
-  {
-    ProfScope ps(plan, KK_FILTER, s);
-    e = launch_filter(plan->d, plan->ct, ft, static_cast<const float2*>(D), weights, w.S, w.O, H,
-                      s);
-  }
+  // the filter scales O in place; momfbd_profile_repeat refuses its kind
+  hipError_t e = prof_launch(plan, KK_FILTER, s, [&] {
+    return launch_filter(plan->d, plan->ct, ft, static_cast<const float2*>(D), weights, w.S, w.O,
+                         H, s);
+  });
   if (e != hipSuccess) return to_status(e);
-  ProfScope ps(plan, KK_OBJIMG, s);
-  return to_status(launch_objimg(plan->d, w.O, obj, s));
+  return to_status(
+      prof_launch(plan, KK_OBJIMG, s, [&] { return launch_objimg(plan->d, w.O, obj, s); }));
 }
 
 int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
@@ -502,8 +501,10 @@ int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride
     return MOMFBD_EINVAL;
   int st = pending_error();
   if (st) return st;
-  ProfScope ps(plan, KK_MOSAIC, (hipStream_t)stream);
-  return to_status(launch_mosaic(plan->d, obj, ny, nx, stride, border, out, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  return to_status(prof_launch(plan, KK_MOSAIC, s, [&] {
+    return launch_mosaic(plan->d, obj, ny, nx, stride, border, out, s);
+  }));
 }
 
 }  // extern "C"
@@ -610,7 +611,8 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   if ((st = pending_error())) return st;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  if (hipEventCreateWithFlags(&e0, hipEventReleaseToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&e1, hipEventReleaseToDevice) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     return MOMFBD_EDEVICE;
   }
@@ -627,19 +629,25 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       return MOMFBD_EDEVICE;
     return MOMFBD_OK;
   };
+  // The first value of each knob is the library default; another value
+  // replaces the best so far only when at least 1% faster, so that timing
+  // noise between near-equal schedules does not decide (the XCD-grouped
+  // orders read less from HBM at equal speed).
   int* knobs[4] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves};
   const std::vector<int> values[4] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}};
   for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
     int best = *knobs[k];
-    float best_ms = 1e30f;
+    float best_ms = 0.f;
+    bool first = true;
     for (int v : values[k]) {
       if (k == 3 && v == 8 && (plan->d.M + 15) / 16 > 8) continue;
       *knobs[k] = v;
       float ms = 0.f;
       if ((st = timed(&ms))) break;
-      if (ms < best_ms) {
+      if (first || ms < 0.99f * best_ms) {
         best_ms = ms;
         best = v;
+        first = false;
       }
     }
     *knobs[k] = best;
@@ -659,8 +667,11 @@ static void profile_free(Profiler& pr) {
   pr.ev0.clear();
   pr.ev1.clear();
   pr.kind.clear();
+  pr.count.clear();
   pr.on = false;
   pr.used = 0;
+  pr.rep_kind = -1;
+  pr.reps = 1;
 }
 
 extern "C" {
@@ -672,8 +683,12 @@ int momfbd_profile_start(momfbd_plan plan, int max_launches) {
   pr.ev0.resize(max_launches);
   pr.ev1.resize(max_launches);
   pr.kind.assign(max_launches, -1);
+  pr.count.assign(max_launches, 0);
+  pr.rep_kind = -1;
+  pr.reps = 1;
   for (int i = 0; i < max_launches; ++i)
-    if (hipEventCreate(&pr.ev0[i]) != hipSuccess || hipEventCreate(&pr.ev1[i]) != hipSuccess) {
+    if (hipEventCreateWithFlags(&pr.ev0[i], hipEventReleaseToDevice) != hipSuccess ||
+        hipEventCreateWithFlags(&pr.ev1[i], hipEventReleaseToDevice) != hipSuccess) {
       pr.ev0.resize(i);
       pr.ev1.resize(i);
       profile_free(pr);
@@ -681,6 +696,18 @@ int momfbd_profile_start(momfbd_plan plan, int max_launches) {
     }
   pr.on = true;
   return MOMFBD_OK;
+}
+
+int momfbd_profile_repeat(momfbd_plan plan, const char* kind, int reps) {
+  if (!plan || !kind || reps < 1 || !plan->prof.on) return MOMFBD_EINVAL;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (std::strcmp(kind, kKernelNames[k]) != 0) continue;
+    if (k == KK_FILTER) return MOMFBD_EINVAL;
+    plan->prof.rep_kind = k;
+    plan->prof.reps = reps;
+    return MOMFBD_OK;
+  }
+  return MOMFBD_EINVAL;
 }
 
 int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* total_ms,
@@ -695,7 +722,7 @@ int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* t
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pr.ev0[i], pr.ev1[i]) != hipSuccess) { st = MOMFBD_EDEVICE; break; }
     tot[pr.kind[i]] += ms;
-    cnt[pr.kind[i]] += 1;
+    cnt[pr.kind[i]] += pr.count[i];
   }
   int n = 0;
   for (int k = 0; k < KK_COUNT && n < cap; ++k) {

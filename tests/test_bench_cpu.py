@@ -1,0 +1,62 @@
+"""Host logic of bench.py: the counted-traffic lookup, the roofline object
+and the one-GPU guard (no GPU needed)."""
+
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_counted_traffic_follows_schedule(bench):
+    sched = {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1, "grad_waves": 4}
+    for kern, rec in bench.COUNTED_TRAFFIC.items():
+        if rec["sources_sha1"] != bench.sources_sha(kern):
+            assert bench.counted_traffic(kern, sched) is None
+            continue
+        for v, (rd, wr) in rec["by_value"].items():
+            assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: v})) == rd + wr
+        # a knob value the counters were not taken for reports nothing
+        assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: 99})) is None
+    assert bench.counted_traffic("no_such_kernel", sched) is None
+
+
+def test_counted_traffic_stale_source(bench, monkeypatch):
+    monkeypatch.setitem(bench.COUNTED_TRAFFIC, "adjoint",
+                        dict(bench.COUNTED_TRAFFIC["adjoint"], sources_sha1="000000000000"))
+    assert bench.counted_traffic("adjoint", {"xcd_adjoint": 1}) is None
+
+
+def test_roofline_alu_and_hbm(bench):
+    N, units = 64, 1000
+    _, per_kernel = bench.unit_flops(N)
+    r = bench.roofline({"adjoint": 2.0, "forward": 1.0}, units, N, 0, lambda k: 123)
+    assert r["kernel"] == "adjoint" and r["bound"] == "alu" and r["traffic"] == 123
+    assert r["achieved"] == pytest.approx(per_kernel["adjoint"] * units / 2e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    r = bench.roofline({"object": 4.0, "adjoint": 1.0}, units, N, 10**9, lambda k: None)
+    assert r["bound"] == "hbm" and r["traffic"] is None
+    assert r["achieved"] == pytest.approx(2e9 / 4e-3 / 1e9)
+
+
+def test_fft_flop_count(bench):
+    # 5 N^2 log2(N^2) for a complex N x N transform; the real one half of it
+    c2c, real = bench.fft_flops(64)
+    assert c2c == pytest.approx(5 * 64 * 64 * 12) and real == pytest.approx(c2c / 2)
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0 and "one GPU" in p.stdout + p.stderr

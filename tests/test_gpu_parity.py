@@ -385,6 +385,44 @@ def test_launch_schedules_and_autotune(dev, N):
     plan.close()
 
 
+def test_kernel_timing_leaves_results_unchanged(dev):
+    """The library's kernel timing (an event pair per launch, or one kind
+    repeated back to back inside its pair) changes no result bit."""
+    from paper_2505_10639_amd import (momfbd_profile_repeat, momfbd_profile_start,
+                                      momfbd_profile_stop)
+
+    pr = synth.make_problem(77, N=64, P=3, J=3, M=21, channels=((0, 0.0), (1, 1.0)),
+                            d_over_r0=np.array([6.0, 10.0, 14.0]), border=6)
+    D = to_dev(simulate_D(pr), dev)
+    a = to_dev(alpha_points(pr, 11)["perturbed"], dev)
+    plan = make_plan(pr, dev)
+    l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
+    momfbd_profile_start(plan.handle, 64)
+    l1, g1 = plan.loss_grad(a, D, pr.gamma)
+    kern = momfbd_profile_stop(plan.handle)
+    assert torch.equal(l1, l0) and torch.equal(g1, g0)
+    assert {k: v[1] for k, v in kern.items()} == {"phase": 1, "forward": 1, "object": 1,
+                                                  "adjoint": 1, "grad": 1}
+    for kind in ("phase", "forward", "object", "adjoint", "grad"):
+        print(f"[timing] repeat {kind}", flush=True)
+        momfbd_profile_start(plan.handle, 8)
+        momfbd_profile_repeat(plan.handle, kind, 3)
+        for _ in range(2):
+            l1, g1 = plan.loss_grad(a, D, pr.gamma)
+        kern = momfbd_profile_stop(plan.handle)
+        assert torch.equal(l1, l0) and torch.equal(g1, g0)
+        assert list(kern) == [kind] and kern[kind][1] == 6 and kern[kind][0] > 0
+    momfbd_profile_start(plan.handle, 8)
+    with pytest.raises(Exception):
+        momfbd_profile_repeat(plan.handle, "filter", 2)
+    with pytest.raises(Exception):
+        momfbd_profile_repeat(plan.handle, "no_such_kernel", 2)
+    momfbd_profile_stop(plan.handle)
+    with pytest.raises(Exception):   # no timing started
+        momfbd_profile_repeat(plan.handle, "adjoint", 2)
+    plan.close()
+
+
 # ------------------------------------------------------------ 128 x 128 patches
 
 def test_n128_loss_and_gradient(dev):

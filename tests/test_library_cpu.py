@@ -108,3 +108,4 @@ def test_calls_reject_null_plan_and_workspace(L):
     assert L.momfbd_plan_get_tuning(None, None) == -1
     assert L.momfbd_plan_autotune(None, None, None, None, 1e-3, None, 1, None, None, None, None,
                                   None) == -1
+    assert L.momfbd_profile_repeat(None, b"adjoint", 4) == -1
