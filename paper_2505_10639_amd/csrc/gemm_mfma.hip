@@ -4,6 +4,11 @@
 //           (Eq. wavefront on the 32x32 pupil band, in turns)
 //   grad  : dL/dalpha[p][j][m] = 2 pi sum_c sum_px Z_c[m][px] gphi[p][c][j][px]
 //
+// When every channel has the same band basis (zc = 1) the phase product is
+// formed once and written for each channel with its own theta_c, and the
+// gradient contracts Z with sum_c gphi[p][c][j][px] (channels summed first,
+// in channel order): half the matrix-core work at two channels.
+//
 // Both use v_mfma_f32_16x16x4f32.  Operand layout of that instruction: lane l
 // supplies A[i = l%16][k = l/16] and B[k = l/16][j = l%16]; the 16x16 result
 // sits in 4 registers per lane, D[4 (l/16) + e][l%16], e = 0..3.
@@ -31,7 +36,7 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
 // fixed order (wave 0 + 1 + ... + W-1) through LDS.  W (4 or 8) is a launch
 // schedule the autotuner picks.
 template <int MT, int W>
-__global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int M, int bp,
+__global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int zc, int M, int bp,
                                                       const float* __restrict__ Zt,
                                                       const float* __restrict__ gphi,
                                                       float* __restrict__ grad) {
@@ -45,14 +50,21 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int M
   floatx4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int Kq = C * bp / W;
+  const int Kq = zc * bp / W;
   const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
   // operands of chunk kk: a from gphi row r, b[t] from mode rows t*16 + i16;
   // the next chunk's operands are loaded before the current chunk's MFMAs
   auto load = [&](int kk, floatx4& a4, floatx4 (&b4)[MT]) {
     const int c = kk / bp, px = kk % bp + 4 * g;
-    a4 = rok ? *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + c) * J + j) * bp + px)
-             : floatx4{0.f, 0.f, 0.f, 0.f};
+    a4 = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (rok) {
+      if (zc == C) {
+        a4 = *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + c) * J + j) * bp + px);
+      } else {
+        for (int ch = 0; ch < C; ++ch)
+          a4 += *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + ch) * J + j) * bp + px);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int m = t * 16 + i16;
@@ -95,11 +107,13 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int M
 }
 
 // phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
-// Block = 4 waves, (channel, 64 columns, a quarter of the 1024 band pixels):
+// Block = 4 waves, (basis, 64 columns, a quarter of the band pixels); with
+// one shared basis the block writes every channel's phi from one product:
 // the block's 64 coefficient rows (contiguous in alpha) are staged once in
 // LDS with the mode index padded to Mp; each wave then walks 4 tiles of 16
 // pixels x 64 columns, taking its B operands as float4 LDS reads.
-__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, int Mp, int bp,
+__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mp,
+                                                    int bp,
                                                     const float* __restrict__ ZtT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
@@ -132,14 +146,18 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
         acc[t] = mfma4(a4, b4, acc[t]);
       }
     }
-    const floatx4 th = *reinterpret_cast<const floatx4*>(theta + (size_t)c * bp + px0 + 4 * g);
+    const int c_lo = zc == C ? c : 0, c_hi = zc == C ? c + 1 : C;
+    for (int ch = c_lo; ch < c_hi; ++ch) {
+      const floatx4 th =
+          *reinterpret_cast<const floatx4*>(theta + (size_t)ch * bp + px0 + 4 * g);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int col = col0 + t * 16 + i16;
-      if (col >= R) continue;
-      const int p = col / J, j = col % J;
-      *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + c) * J + j) * bp + px0 + 4 * g) =
-          acc[t] + th;
+      for (int t = 0; t < 4; ++t) {
+        const int col = col0 + t * 16 + i16;
+        if (col >= R) continue;
+        const int p = col / J, j = col % J;
+        *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + ch) * J + j) * bp + px0 + 4 * g) =
+            acc[t] + th;
+      }
     }
   }
 }
@@ -147,15 +165,14 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int M, 
 template <int MT>
 void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
                    hipStream_t s) {
-  const int R = d.P * d.J;
+  const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
   // eight waves only while the partial sums fit in 64 KB of LDS
   if (MT <= 8 && d.grad_waves == 8)
     hipLaunchKernelGGL((k_grad_mfma<MT, (MT <= 8 ? 8 : 4)>), dim3((R + 15) / 16), dim3(512), 0, s,
-                       R, d.J, d.C, d.M, d.bandpix(), Zt, gphi, grad);
+                       R, d.J, d.C, zc, d.M, d.bandpix(), Zt, gphi, grad);
   else
     hipLaunchKernelGGL((k_grad_mfma<MT, 4>), dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C,
-                       d.M, d.bandpix(),
-                     Zt, gphi, grad);
+                       zc, d.M, d.bandpix(), Zt, gphi, grad);
 }
 
 }  // namespace
@@ -177,17 +194,16 @@ hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float*
 
 hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
                         const float* thetat, float* phi, hipStream_t s) {
-  const int R = d.P * d.J;
-  dim3 grid(d.C * 4, (R + 63) / 64);
+  const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
+  dim3 grid(zc * 4, (R + 63) / 64);
   const size_t lds = (size_t)64 * (Mp + 4) * sizeof(float);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, d.M, Mp, d.bandpix(), ZtT,
-                     thetat,
-                     alpha, phi);
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, zc, d.M, Mp, d.bandpix(),
+                     ZtT, thetat, alpha, phi);
   return hipGetLastError();
 }
 

@@ -25,10 +25,23 @@ struct Dims {
   // order of the forward / adjoint grids, frequency pairs per thread of the
   // object kernel, waves per row tile of the gradient contraction
   int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4;
+  // distinct modal bases on the band: 1 when every channel's band-sampled
+  // basis is the same (the contractions then run once for all channels),
+  // else C; 0 is read as C
+  int zc = 0;
   int band() const { return N / 2; }                 // pupil band width
   int bandpix() const { return (N / 2) * (N / 2); }  // pixels of the band
   int half() const { return N * (N / 2 + 1); }       // complex values of a half spectrum
 };
+
+// Loads of data a kernel reads once per launch (the object kernel's data
+// and OTF spectra): nontemporal, so that they do not displace cached lines.
+// (In the adjoint kernels the same hint made the step slower.)
+typedef float mfbd_fx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 stream_load(const float4* p) {
+  const mfbd_fx4 v = __builtin_nontemporal_load(reinterpret_cast<const mfbd_fx4*>(p));
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
 
 // Channel tables passed by value to kernels.
 struct ChanTab {

@@ -234,6 +234,12 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
               (float)((double)basis[((size_t)c * M + m) * N * N + src] / kTwoPi);
       }
   }
+  // one basis for all channels when their band-sampled bases agree bit for bit
+  bool shared = true;
+  for (int c = 1; c < C && shared; ++c)
+    shared = std::memcmp(hZ.data() + (size_t)c * M * BP, hZ.data(),
+                         (size_t)M * BP * sizeof(float)) == 0;
+  pl->d.zc = shared ? 1 : C;
   pl->Mp = (M + 15) / 16 * 16;
   std::vector<float> hZT((size_t)C * BP * pl->Mp, 0.f);
   for (int c = 0; c < C; ++c)

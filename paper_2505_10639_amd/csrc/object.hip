@@ -23,6 +23,7 @@ struct Acc2 {
   double nr[2], ni[2], q[2], e[2];
 };
 
+
 __device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
   const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
   const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
@@ -72,15 +73,15 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
         float4 d[6], s[6];
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
-          d[u] = Dc[(size_t)(j + u) * (kUnitF2 / 2)];
-          s[u] = Sc[(size_t)(j + u) * (kUnitF2 / 2)];
+          d[u] = stream_load(Dc + (size_t)(j + u) * (kUnitF2 / 2));
+          s[u] = stream_load(Sc + (size_t)(j + u) * (kUnitF2 / 2));
         }
 #pragma unroll
         for (int u = 0; u < 6; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
       }
       for (; j < J; ++j)
-        acc_unit(a, wc ? (double)wc[j] : 1.0, Dc[(size_t)j * (kUnitF2 / 2)],
-                 Sc[(size_t)j * (kUnitF2 / 2)]);
+        acc_unit(a, wc ? (double)wc[j] : 1.0, stream_load(Dc + (size_t)j * (kUnitF2 / 2)),
+                 stream_load(Sc + (size_t)j * (kUnitF2 / 2)));
     }
     const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
     const float4 o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
