@@ -475,6 +475,55 @@ def test_n128_forward_object_prepare(dev):
     plan2.close()
 
 
+def test_shared_basis_matches_separate_bases(dev):
+    """Channels with the same basis take one contraction for all channels
+    (phase formed once, gradient over the channel sum); a plan whose third
+    channel's basis differs in the last bits takes the per-channel
+    contractions.  Both give the same loss, gradient and OTFs to within
+    that perturbation."""
+    from paper_2505_10639_amd import Plan
+
+    pr = synth.make_problem(58, N=64, P=3, J=4, M=30, channels=((0, 0.0), (0, 1.0), (1, 0.0)),
+                            d_over_r0=np.array([6.0, 10.0, 14.0]))
+    D = to_dev(simulate_D(pr), dev)
+    a = to_dev(alpha_points(pr, 12)["perturbed"], dev)
+    basis2 = pr.basis.copy()
+    basis2[2] *= 1.0 + 2.0 ** -20
+    shared = make_plan(pr, dev)
+    separate = Plan(pr.N, pr.P, pr.J, pr.channel_object, pr.pupil, basis2, pr.diversity, dev)
+    l1, g1 = (t.clone() for t in shared.loss_grad(a, D, pr.gamma))
+    l2, g2 = separate.loss_grad(a, D, pr.gamma)
+    _, S1 = shared.forward(a, want_psf=False)
+    _, S2 = separate.forward(a, want_psf=False)
+    torch.cuda.synchronize()
+    assert float(((l1 - l2).abs() / l2.abs()).max()) < 1e-5
+    assert float((g1 - g2).norm() / g2.norm()) < 1e-4
+    # channels 0 and 1 share the unperturbed basis in both plans
+    s1, s2 = S1.reshape(pr.P, 3, -1), S2.reshape(pr.P, 3, -1)
+    assert float((s1[:, :2] - s2[:, :2]).abs().max()) < 1e-6
+    assert float((s1[:, 2] - s2[:, 2]).abs().max()) < 1e-4
+    shared.close()
+    separate.close()
+
+
+@pytest.mark.parametrize("M", [1, 16, 17, 256])
+def test_mode_count_extremes(dev, M):
+    """One mode, a whole number of 16-mode tiles, one past it, and the
+    largest basis the plan accepts (256 modes: 16 tiles in the gradient
+    contraction, a 66 KB coefficient tile in the phase contraction)."""
+    pr = synth.make_problem(200 + M, N=64, P=2, J=2, M=M, channels=((0, 0.0), (0, 1.0)),
+                            d_over_r0=8.0)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, M), dev)
+
+
+def test_many_channels_and_objects(dev):
+    """Eight channels: four objects, each seen in focus and with diversity
+    (the shared-basis contraction sums eight channels)."""
+    ch = tuple((k, d) for k in range(4) for d in (0.0, 1.0))
+    pr = synth.make_problem(210, N=64, P=2, J=2, M=20, channels=ch, d_over_r0=9.0)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 3), dev)
+
+
 def test_multi_wavelength_n64(dev):
     pr = synth.make_problem(55, N=64, P=2, J=3, M=36, channels=((0, 0.0), (1, 0.0), (1, 1.0)),
                             lam_ratios=[1.0, 1 / 1.1, 1 / 1.1], d_over_r0=10.0)
