@@ -59,18 +59,18 @@ KERNEL_SOURCES = {
     "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
     "object": ["object.hip"],
 }
-COPY_FETCH_SCALE = 1.9997741954186083    # 256 MiB copy: FETCH_SIZE read 131086.8 KiB
+COPY_FETCH_SCALE = 1.9997784542111419    # 256 MiB copy: FETCH_SIZE read 131086.5 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per kernel: the knob and, per value of it, (HBM bytes read, written) per
 # launch
 COUNTED_TRAFFIC = {
     "adjoint": {"sources_sha1": "1577f6f374fb", "knob": "xcd_adjoint",
-                "by_value": {1: (1010802857, 94470144), 0: (1306376709, 94470144)}},
+                "by_value": {1: (1010644356, 94470144), 0: (1305731088, 94470144)}},
     "forward": {"sources_sha1": "1577f6f374fb", "knob": "xcd_forward",
-                "by_value": {0: (94961203, 395071989), 1: (94962541, 392118775)}},
-    "object": {"sources_sha1": "26d2c7680506", "knob": "object_pairs_per_thread",
-               "by_value": {1: (779376483, 32826246), 2: (779377533, 32670008),
-                            4: (779374621, 32605784)}},
+                "by_value": {0: (94962088, 395020016), 1: (94961000, 392398192)}},
+    "object": {"sources_sha1": "5fb361e02b19", "knob": "object_pairs_per_thread",
+               "by_value": {1: (779372755, 32783371), 2: (779372217, 32667856),
+                            4: (779372217, 32597480)}},
 }
 
 
