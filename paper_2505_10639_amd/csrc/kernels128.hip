@@ -129,21 +129,35 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
   const int k = ct.chan_obj[c];
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
 
-  // G = -2 w conj(O)(D - O S) in spectral layout (lanes < 128)
+  // G = -2 w conj(O)(D - O S) in spectral layout, held by lanes < 128.  All
+  // four waves load: spectral lane sl = lane & 127 takes m in [0,32) on the
+  // lower half of the workgroup and m in [32,64) on the upper half, which
+  // passes its values on through LDS.
   float2 G[64];
-  if (lane < 128) {
+  {
+    const int upper = lane >> 7, sl = lane & 127;
     const float2* Su = S + (size_t)u * kUnitF2;
     const float2* Du = la.D + (size_t)u * kUnitF2;
     const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
 #pragma unroll
-    for (int m = 0; m < 64; ++m) {
-      const int idx = sl_index(lane, m);
+    for (int i = 0; i < 32; ++i) {
+      const int idx = sl_index(sl, i + 32 * upper);
       const float2 o = Ok[idx];
-      G[m] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+      G[i] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
     }
-    const int idx = sl_index64(lane);
-    const float2 o = Ok[idx];
-    Taux[lane] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+    if (upper) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) T[sl * 33 + i] = G[i];
+    } else {
+      const int idx = sl_index64(sl);
+      const float2 o = Ok[idx];
+      Taux[sl] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+    }
+  }
+  sync();
+  if (lane < 128) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) G[32 + i] = T[lane * 33 + i];
   }
   sync();
   if (lane < 128) op3_cols(G, Taux, T, lane);
