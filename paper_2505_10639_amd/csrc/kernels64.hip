@@ -135,6 +135,12 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
   const float2* Su = S + (size_t)u * kUnitF2;
   const float2* Du = la.D + (size_t)u * kUnitF2;
   const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
+  const float* Ac = Ab + c * kBandPix;
+  const float* phu = phi + (size_t)u * kBandPix;
+  // the pupil band field (recomputed below to form p) depends only on phi:
+  // build it first so that its loads overlap those of G
+  float2 y[32];
+  build_pupil(Ac, phu, lane, y);
 
   // G = -2 w conj(O) (D - O S) in spectral layout
   float2 G[32];
@@ -162,13 +168,7 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
 
   // recompute the pupil band transform, then H = 2 kappa g p and its
   // forward transform to the band, half a row spectrum at a time
-  const float* Ac = Ab + c * kBandPix;
-  const float* phu = phi + (size_t)u * kBandPix;
-  {
-    float2 y[32];
-    build_pupil(Ac, phu, lane, y);
-    op1_cols(y, T, lane);
-  }
+  op1_cols(y, T, lane);
   wave_sync();
   float2 Gr[32];
   op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c], Gr);
