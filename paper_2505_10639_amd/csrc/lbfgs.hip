@@ -54,29 +54,27 @@ __device__ __forceinline__ View view(const LbfgsLayout& L, void* state) {
 
 constexpr int kThreads = 256;
 
-// Sum over the block in a fixed order; every thread receives the result.
+// Sum over the block in a fixed order: a butterfly of shuffles inside each
+// wave (every lane ends with the same bits, as each stage adds the same two
+// values in either order), then the wave sums in wave order.  Every thread
+// receives the result.
+constexpr int kWaves = kThreads / 64;
 __device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < kWaves; ++w) r += red[w];
   __syncthreads();
   return r;
 }
 
 __device__ double block_max(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmax(red[t], red[t + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < kWaves; ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
 }
