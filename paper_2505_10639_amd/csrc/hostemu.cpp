@@ -288,9 +288,8 @@ void c2r(WG& w, float2 (&X)[128][64], const float2 (&x64)[128], float (&g)[L][64
 }
 
 void to_band(WG& w, float2 (&H)[L][64], float2 (&GP)[128][32]) {
-  static float2 keep[L][32], send[L][32], other[L][32];
-  for (int l = 0; l < L; ++l) n128::op4_rows_fft(H[l], keep[l], send[l], l);
-  for (int l = 0; l < L; ++l) n128::xput(send[l], w.T, l);
+  static float2 keep[L][32], other[L][32];
+  for (int l = 0; l < L; ++l) n128::op4_rows_fft(H[l], keep[l], w.T, l);
   for (int l = 0; l < L; ++l) n128::xget(w.T, l, other[l]);
   for (int l = 0; l < L; ++l) n128::op4_rows_finish(keep[l], other[l], w.T, l);
   for (int l = 0; l < 128; ++l) n128::op4_cols(w.T, l, GP[l]);

@@ -189,9 +189,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
   for (int m = 0; m < 64; ++m) H[m] = cscale(H[m], k2 * g[m]);
   sync();
   {
-    float2 keep[32], send[32], other[32];
-    op4_rows_fft(H, keep, send, lane);
-    xput(send, T, lane);
+    float2 keep[32], other[32];
+    op4_rows_fft(H, keep, T, lane);
     sync();
     xget(T, lane, other);
     sync();

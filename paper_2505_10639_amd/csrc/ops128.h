@@ -224,32 +224,64 @@ MFBD_HDI void op3_cols(float2 (&X)[64], const float2* Taux, float2* T, int lane)
 // Row pass (all lanes): lane (y, f) forms the row half spectrum, then the
 // parity-f half of the packed inverse, z[2n'+f], n' in [0,32).  It keeps the
 // part of z that belongs to its own column parity and sends the other part.
+//   X[k] (k in [0,64]) from the column pass: X(r,k) +- X(r,k+64) folded;
+//   Z[k] = (X[k] + X[k+64]) + i W128^{+k} (X[k] - X[k+64]), X[k+64] = conj X[64-k];
+//   w[k'] = Z[k'] + (-1)^f Z[k'+32], k' in [0,32).
+// The values are read from LDS in groups {k, 64-k, 32+k, 32-k}, which give
+// Z at those four points and hence w[k] and w[32-k]; neither X nor Z is
+// ever held whole (register pressure).
 MFBD_HDI void op3_rows_compute(const float2* T, int lane, float (&keep)[32], float (&send)[32]) {
   const int y = lane >> 1, f = lane & 1;
   const int rp = y & 63;
   const float sg = (y < 64) ? 1.0f : -1.0f;
-  float2 Xr[64];
-  static_for<0, 64>([&](auto Q) {
-    constexpr int q = decltype(Q)::value;
-    float2 ev = T[rp * U3 + 2 * q], wo = T[rp * U3 + 2 * q + 1];
-    Xr[q] = make_float2(ev.x + sg * wo.x, ev.y + sg * wo.y);
-  });
-  // Z[k] = (X[k] + X[k+64]) + i W128^{+k} (X[k] - X[k+64]), X[k+64] = conj X[64-k]
-  float2 Z[64];
-  Z[0] = make_float2(Xr[0].x + Xr[0].y, Xr[0].x - Xr[0].y);
-  static_for<1, 64>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    float2 a = Xr[k], c = cconj(Xr[64 - k]);
-    float2 s = cadd(a, c);
-    float2 t = twmul<+1, 128, k>(csub(a, c));
-    Z[k] = make_float2(s.x - t.y, s.y + t.x);
-  });
-  // z[2n'+f] = sum_k' (Z[k'] + (-1)^f Z[k'+32]) W64^{k' f} W32^{k' n'}
   const float sf = f ? -1.0f : 1.0f;
+  auto xr = [&](int q) {
+    const float2 ev = T[rp * U3 + 2 * q], wo = T[rp * U3 + 2 * q + 1];
+    return make_float2(ev.x + sg * wo.x, ev.y + sg * wo.y);
+  };
+  // Z at k and 64 - k from X[k], X[64-k] (1 <= k <= 63)
+  auto zpair = [&](auto K, float2 xa, float2 xb, float2& za, float2& zb) {
+    constexpr int k = decltype(K)::value;
+    {
+      const float2 c = cconj(xb);
+      const float2 s = cadd(xa, c);
+      const float2 t = twmul<+1, 128, k>(csub(xa, c));
+      za = make_float2(s.x - t.y, s.y + t.x);
+    }
+    {
+      const float2 c = cconj(xa);
+      const float2 s = cadd(xb, c);
+      const float2 t = twmul<+1, 128, 64 - k>(csub(xb, c));
+      zb = make_float2(s.x - t.y, s.y + t.x);
+    }
+  };
+  auto wmix = [&](float2 za, float2 zb) {
+    return make_float2(za.x + sf * zb.x, za.y + sf * zb.y);
+  };
   float2 w[32];
-  static_for<0, 32>([&](auto I) {
-    constexpr int k = decltype(I)::value;
-    w[k] = make_float2(Z[k].x + sf * Z[k + 32].x, Z[k].y + sf * Z[k + 32].y);
+  {
+    // k = 0 (X[0] packs the real X(r,0), X(r,64)) and k = 32 (its own pair)
+    const float2 x0 = xr(0), x32 = xr(32);
+    const float2 z0 = make_float2(x0.x + x0.y, x0.x - x0.y);
+    const float2 c = cconj(x32);
+    const float2 s2 = cadd(x32, c);
+    const float2 t = twmul<+1, 128, 32>(csub(x32, c));
+    const float2 z32 = make_float2(s2.x - t.y, s2.y + t.x);
+    w[0] = wmix(z0, z32);
+  }
+  {
+    // k = 16: Z[16], Z[48] from X[16], X[48]
+    float2 z16, z48;
+    zpair(std::integral_constant<int, 16>{}, xr(16), xr(48), z16, z48);
+    w[16] = wmix(z16, z48);
+  }
+  static_for<1, 16>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    float2 zk, z64k, z32k, z32mk;
+    zpair(std::integral_constant<int, k>{}, xr(k), xr(64 - k), zk, z64k);
+    zpair(std::integral_constant<int, 32 - k>{}, xr(32 - k), xr(32 + k), z32mk, z32k);
+    w[k] = wmix(zk, z32k);             // Z[k] +- Z[k+32]
+    w[32 - k] = wmix(z32mk, z64k);     // Z[32-k] +- Z[64-k]
   });
   if (f) {
     static_for<1, 32>([&](auto I) {
@@ -285,20 +317,38 @@ MFBD_HDI void op3_rows_finish(const float (&keep)[32], const float (&other)[32],
 // band: G(vy, vx) for vx in [32,96) (rows), then vy in [32,96) (columns).
 // Row pass: lane (y, e) transforms its parity half, F = DFT64((-1)^m H_e);
 // G_r(32 + v') = F_0[v'] + W128^{-(32+v')} F_1[v'].  Lane 0 produces
-// v' in [0,32), lane 1 v' in [32,64); each sends the other half it holds.
-// ---------------------------------------------------------------------------
-MFBD_HDI void op4_rows_fft(float2 (&H)[64], float2 (&keep)[32], float2 (&send)[32], int lane) {
-  const int e = lane & 1;
+// v' in [0,32), lane 1 v' in [32,64); each keeps the half it uses (lane 0:
+// F_0[v], lane 1: F_1[32+v]) in keep and stages the other in X for its
+// partner (same LDS rules as xput).  The 8 x 8 transform hands its outputs
+// over group by group: output k1 + 8j of group k1 pairs with k1 + 8(j+4),
+// so the 64 outputs are never held at once, and the halves are chosen value
+// by value (selects, never a runtime index into an array).
+MFBD_HDI void op4_rows_fft(float2 (&H)[64], float2 (&keep)[32], float2* X, int lane) {
+  const bool odd = lane & 1;
   static_for<0, 64>([&](auto I) {
     constexpr int m = decltype(I)::value;
     if constexpr (m & 1) H[m] = cneg(H[m]);
   });
-  fft64<-1>(H);
-  static_for<0, 32>([&](auto I) {
-    constexpr int v = decltype(I)::value;
-    // lane 0 keeps F_0[v] (v < 32) and sends F_0[32+v]; lane 1 keeps F_1[32+v], sends F_1[v]
-    keep[v] = e ? H[32 + v] : H[v];
-    send[v] = e ? H[v] : H[32 + v];
+  static_for<0, 8>([&](auto N2) {
+    constexpr int n2 = decltype(N2)::value;
+    dft8<-1>(H[n2], H[8 + n2], H[16 + n2], H[24 + n2], H[32 + n2], H[40 + n2], H[48 + n2],
+             H[56 + n2]);
+    static_for<1, 8>([&](auto K1) {
+      constexpr int k1 = decltype(K1)::value;
+      H[8 * k1 + n2] = twmul<-1, 64, n2 * k1>(H[8 * k1 + n2]);
+    });
+  });
+  static_for<0, 8>([&](auto K1) {
+    constexpr int k1 = decltype(K1)::value;
+    float2 a0 = H[8 * k1 + 0], a1 = H[8 * k1 + 1], a2 = H[8 * k1 + 2], a3 = H[8 * k1 + 3];
+    float2 a4 = H[8 * k1 + 4], a5 = H[8 * k1 + 5], a6 = H[8 * k1 + 6], a7 = H[8 * k1 + 7];
+    dft8<-1>(a0, a1, a2, a3, a4, a5, a6, a7);
+    const float2 lo[4] = {a0, a1, a2, a3}, hi[4] = {a4, a5, a6, a7};   // F[v], F[32 + v]
+    static_for<0, 4>([&](auto J) {
+      constexpr int j = decltype(J)::value, v = k1 + 8 * j;
+      keep[v] = odd ? hi[j] : lo[j];
+      X[lane * 33 + v] = odd ? lo[j] : hi[j];
+    });
   });
 }
 
@@ -307,12 +357,12 @@ MFBD_HDI void op4_rows_finish(const float2 (&keep)[32], const float2 (&other)[32
   const int y = lane >> 1, e = lane & 1;
   if (e == 0) {
     static_for<0, 32>([&](auto I) {
-      constexpr int v = decltype(I)::value;       // other = F_1[v]
+      constexpr int v = decltype(I)::value;       // keep = F_0[v], other = F_1[v]
       T[y * U2 + v] = cadd(keep[v], twmul<-1, 128, 32 + v>(other[v]));
     });
   } else {
     static_for<0, 32>([&](auto I) {
-      constexpr int v = decltype(I)::value;       // other = F_0[32+v]
+      constexpr int v = decltype(I)::value;       // keep = F_1[32+v], other = F_0[32+v]
       T[y * U2 + 32 + v] = cadd(other[v], twmul<-1, 128, 64 + v>(keep[v]));
     });
   }
