@@ -289,14 +289,43 @@ MFBD_HDI void op14_half(const float2* T, int lane, const float (&g)[48], float k
   fft48<-1>(A);
 }
 
-MFBD_HDI void op14_rows(const float2* T, int lane, const float (&ge)[48], const float (&go)[48],
+MFBD_HDI void op14_rows(float2* T, int lane, const float (&ge)[48], const float (&go)[48],
                         float kap2, float2 (&Gr)[48]) {
   op14_half<0>(T, lane, ge, kap2, Gr);
+  // Odd half.  The band-transform values this lane reads, T[q T1 + lane],
+  // are read by no other lane: each is loaded (twiddled) into B and the
+  // even-half result parked in its slot, so one 48-element array is live
+  // at a time; the last radix-3 stage of B's forward transform adds each
+  // output, twiddled, to the parked value (register pressure).
   float2 B[48];
-  op14_half<1>(T, lane, go, kap2, B);
-  static_for<0, 48>([&](auto V) {
-    constexpr int v = decltype(V)::value;
-    Gr[v] = cadd(Gr[v], twmul<-1, 96, 24 + v>(B[v]));
+  static_for<0, 48>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    const float2 c = T[q * T1 + lane];
+    T[q * T1 + lane] = Gr[q];
+    B[q] = twmul<+1, 96, 24 + q>(c);
+  });
+  fft48<+1>(B);
+  static_for<0, 48>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    B[m] = cscale(B[m], kap2 * go[m]);
+  });
+  static_for<0, 3>([&](auto N2) {
+    constexpr int n2 = decltype(N2)::value;
+    float2 t[16];
+    static_for<0, 16>([&](auto I) { t[decltype(I)::value] = B[3 * decltype(I)::value + n2]; });
+    fft16<-1>(t);
+    static_for<0, 16>([&](auto K1) {
+      constexpr int k1 = decltype(K1)::value;
+      B[3 * k1 + n2] = twmul<-1, 48, n2 * k1>(t[k1]);
+    });
+  });
+  static_for<0, 16>([&](auto K1) {
+    constexpr int k1 = decltype(K1)::value;
+    float2 a0 = B[3 * k1], a1 = B[3 * k1 + 1], a2 = B[3 * k1 + 2];
+    dft3<-1>(a0, a1, a2);      // outputs k1, k1 + 16, k1 + 32 of the transform
+    Gr[k1] = cadd(T[k1 * T1 + lane], twmul<-1, 96, 24 + k1>(a0));
+    Gr[k1 + 16] = cadd(T[(k1 + 16) * T1 + lane], twmul<-1, 96, 40 + k1>(a1));
+    Gr[k1 + 32] = cadd(T[(k1 + 32) * T1 + lane], twmul<-1, 96, 56 + k1>(a2));
   });
 }
 
