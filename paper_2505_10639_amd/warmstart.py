@@ -146,6 +146,38 @@ def mode_scale(M, r0_range=(4.0, 20.0), ao_modes=9, ao_factor=0.3):
     return s.astype(np.float32)
 
 
+def solve_rounds_until(plan, alpha0, D, gamma, target_loss=None, max_rounds=6000, chunk=8,
+                       stall=5, rtol=1e-10):
+    """Per-patch L-BFGS from alpha0 in solver rounds (momfbd_lbfgs_rounds:
+    each round gives every running patch one line-search trial, with no host
+    synchronisation), `chunk` rounds between reads of the summed accepted
+    loss.  Stops when that sum is <= target_loss, or (no target) when it
+    changes by less than rtol over `stall` chunks, or after max_rounds.
+    Patches do not wait for one another's line searches, so a round costs
+    one evaluation of the running patches.  Returns (history of sums, one
+    per chunk, seconds, accepted alpha, rounds run)."""
+    alpha = alpha0.clone().contiguous()
+    accepted = torch.empty_like(alpha)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = Solver(plan, alpha, D, gamma)
+    hist = [float(sol.loss.sum())]
+    rounds = 0
+    while rounds < max_rounds:
+        loss, _ = sol.rounds(chunk)
+        rounds += chunk
+        hist.append(float(loss.sum()))
+        if target_loss is not None and hist[-1] <= target_loss:
+            break
+        if target_loss is None and len(hist) > stall and \
+                abs(hist[-1 - stall] - hist[-1]) <= rtol * abs(hist[-1]):
+            break
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sol.rounds(0, accepted)
+    return hist, elapsed, accepted, rounds
+
+
 def solve_until(plan, alpha0, D, gamma, target_loss=None, max_iter=300, stall=20, rtol=1e-10):
     """Per-patch L-BFGS from alpha0.  Stops when sum_p L_p <= target_loss, or
     (no target) when the summed loss changes by less than rtol over `stall`

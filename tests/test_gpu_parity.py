@@ -294,6 +294,27 @@ def test_lbfgs_rounds_follow_the_step_trajectories(dev):
     plan.close()
 
 
+def test_solve_rounds_until_reports_the_accepted_point(dev):
+    """The chunked round driver: the summed accepted loss never rises from
+    chunk to chunk, it stops at the target, and the coefficients it returns
+    have exactly the loss it reports."""
+    from paper_2505_10639_amd.warmstart import solve_rounds_until
+    pr = synth.make_problem(59, N=64, P=4, J=5, M=24, d_over_r0=np.array([6.0, 9.0, 12.0, 15.0]))
+    D = to_dev(fast_simulate_D(pr), dev)
+    plan = make_plan(pr, dev)
+    zero = torch.zeros((pr.P, pr.J, pr.M), device=dev)
+    h, _, acc, r = solve_rounds_until(plan, zero, D, pr.gamma, None, max_rounds=800, chunk=8,
+                                      stall=5, rtol=1e-9)
+    assert all(b <= a for a, b in zip(h, h[1:])) and h[-1] < 0.9 * h[0]
+    assert r % 8 == 0 and r <= 800
+    L = float(plan.loss_grad(acc, D, pr.gamma)[0].sum())
+    assert L == pytest.approx(h[-1], rel=1e-12)
+    target = h[0] - 0.9 * (h[0] - h[-1])
+    h2, _, acc2, r2 = solve_rounds_until(plan, zero, D, pr.gamma, target, chunk=8)
+    assert h2[-1] <= target and (len(h2) < 3 or h2[-2] > target) and r2 <= r
+    plan.close()
+
+
 def test_lbfgs_rounds_replay_from_a_hip_graph(dev):
     """Rounds captured once in a HIP graph and replayed four times, with
     other eager work in between, match eager rounds bit for bit."""
