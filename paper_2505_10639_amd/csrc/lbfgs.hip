@@ -117,6 +117,92 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_init(int P, LbfgsLayout L, v
   if (loss_out) loss_out[p] = h.f;
 }
 
+// Two-loop recursion with the direction q held in registers (E elements per
+// thread, n <= 256 E) and each history pair loaded one step ahead, so that
+// the chain of dependent block sums does not also wait on memory.  Same
+// arithmetic and summation order as the in-memory loop in begin_patch.
+// Leaves -H g in q_out.
+template <int E>
+__device__ void two_loop_regs(int n, int m, int count, int head, const float* __restrict__ g,
+                              float* __restrict__ q_out, const float* __restrict__ S,
+                              const float* __restrict__ Y, const double* __restrict__ rho,
+                              double* red, double* coef) {
+  const int tid = threadIdx.x;
+  float q[E], s[E], y[E], sn[E], yn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = tid + e * kThreads;
+    q[e] = i < n ? g[i] : 0.f;
+  }
+  auto load = [&](int k, float (&sv)[E], float (&yv)[E]) {
+    const size_t slot = (size_t)((head + k) % m);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = tid + e * kThreads;
+      sv[e] = i < n ? S[slot * n + i] : 0.f;
+      yv[e] = i < n ? Y[slot * n + i] : 0.f;
+    }
+  };
+  auto slot_of = [&](int k) { return (head + k) % m; };
+  // newest pair first
+  if (count > 0) load(count - 1, s, y);
+  for (int k = count - 1; k >= 0; --k) {
+    if (k > 0) load(k - 1, sn, yn);
+    double part = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) part += (double)s[e] * (double)q[e];
+    const double ak = rho[slot_of(k)] * block_sum(part, red);
+    if (tid == 0) coef[k] = ak;
+#pragma unroll
+    for (int e = 0; e < E; ++e) q[e] = (float)((double)q[e] - ak * (double)y[e]);
+    if (k > 0) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        s[e] = sn[e];
+        y[e] = yn[e];
+      }
+    }
+  }
+  if (count > 0) {
+    load(count - 1, s, y);
+    double psy = 0.0, pyy = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      psy += (double)s[e] * (double)y[e];
+      pyy += (double)y[e] * (double)y[e];
+    }
+    const double sy = block_sum(psy, red);
+    const double gam = sy / block_sum(pyy, red);
+#pragma unroll
+    for (int e = 0; e < E; ++e) q[e] = (float)((double)q[e] * gam);
+    load(0, s, y);
+  }
+  __syncthreads();   // coef[] written by thread 0 above
+  for (int k = 0; k < count; ++k) {
+    if (k + 1 < count) load(k + 1, sn, yn);
+    double part = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) part += (double)y[e] * (double)q[e];
+    const double beta = rho[slot_of(k)] * block_sum(part, red);
+    const double ak = coef[k];
+#pragma unroll
+    for (int e = 0; e < E; ++e) q[e] = (float)((double)q[e] + (ak - beta) * (double)s[e]);
+    if (k + 1 < count) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        s[e] = sn[e];
+        y[e] = yn[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = tid + e * kThreads;
+    if (i < n) q_out[i] = -q[e];
+  }
+  __syncthreads();
+}
+
 // Start the next iteration of patch p (status 0): two-loop direction, first
 // trial step, x0 = alpha, alpha = x0 + t0 d, active = 1.
 __device__ void begin_patch(const LbfgsLayout& L, View& v, int p, float* __restrict__ alpha,
@@ -128,38 +214,43 @@ __device__ void begin_patch(const LbfgsLayout& L, View& v, int p, float* __restr
   float* x0 = v.x0 + (size_t)p * n;
   float* a = alpha + (size_t)p * n;
   const size_t hb = (size_t)p * m;
-  for (int i = tid; i < n; i += kThreads) q[i] = g[i];
-  __syncthreads();
   const int count = h.count, head = h.head;
-  // two-loop recursion, newest pair first
-  for (int k = count - 1; k >= 0; --k) {
-    const int slot = (head + k) % m;
-    const float* s = v.S + (hb + slot) * n;
-    const float* y = v.Y + (hb + slot) * n;
-    const double ak = v.rho[hb + slot] * dot(s, q, n, red);
-    if (tid == 0) coef[k] = ak;
-    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] - ak * (double)y[i]);
+  if (n <= kThreads * 8) {
+    two_loop_regs<8>(n, m, count, head, g, q, v.S + hb * n, v.Y + hb * n, v.rho + hb, red, coef);
+  } else {
+    for (int i = tid; i < n; i += kThreads) q[i] = g[i];
+    __syncthreads();
+    // two-loop recursion, newest pair first
+    for (int k = count - 1; k >= 0; --k) {
+      const int slot = (head + k) % m;
+      const float* s = v.S + (hb + slot) * n;
+      const float* y = v.Y + (hb + slot) * n;
+      const double ak = v.rho[hb + slot] * dot(s, q, n, red);
+      if (tid == 0) coef[k] = ak;
+      for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] - ak * (double)y[i]);
+      __syncthreads();
+    }
+    if (count > 0) {
+      const int last = (head + count - 1) % m;
+      const float* s = v.S + (hb + last) * n;
+      const float* y = v.Y + (hb + last) * n;
+      const double gam = dot(s, y, n, red) / dot(y, y, n, red);
+      for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] * gam);
+      __syncthreads();
+    }
+    for (int k = 0; k < count; ++k) {
+      const int slot = (head + k) % m;
+      const float* s = v.S + (hb + slot) * n;
+      const float* y = v.Y + (hb + slot) * n;
+      const double beta = v.rho[hb + slot] * dot(y, q, n, red);
+      const double ak = coef[k];
+      for (int i = tid; i < n; i += kThreads)
+        q[i] = (float)((double)q[i] + (ak - beta) * (double)s[i]);
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += kThreads) q[i] = -q[i];
     __syncthreads();
   }
-  if (count > 0) {
-    const int last = (head + count - 1) % m;
-    const float* s = v.S + (hb + last) * n;
-    const float* y = v.Y + (hb + last) * n;
-    const double gam = dot(s, y, n, red) / dot(y, y, n, red);
-    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] * gam);
-    __syncthreads();
-  }
-  for (int k = 0; k < count; ++k) {
-    const int slot = (head + k) % m;
-    const float* s = v.S + (hb + slot) * n;
-    const float* y = v.Y + (hb + slot) * n;
-    const double beta = v.rho[hb + slot] * dot(y, q, n, red);
-    const double ak = coef[k];
-    for (int i = tid; i < n; i += kThreads) q[i] = (float)((double)q[i] + (ak - beta) * (double)s[i]);
-    __syncthreads();
-  }
-  for (int i = tid; i < n; i += kThreads) q[i] = -q[i];
-  __syncthreads();
   double dphi0 = dot(g, q, n, red);
   bool reset = !(dphi0 < 0.0);
   if (reset) {          // not a descent direction: restart from steepest descent

@@ -264,6 +264,44 @@ def test_smoothness_prior_gamma(dev, N):
     plan.close()
 
 
+def test_lbfgs_later_steps_match_oracle(dev):
+    """Iterations 2-4 (the two-loop recursion with one to three stored
+    pairs): from each of the solver's accepted points, the reference solver
+    given the same history (pairs formed from the solver's points and the
+    oracle's gradients) takes the same step."""
+    from oracle.lbfgs import two_loop, wolfe_search
+    from paper_2505_10639_amd import Solver
+    pr = synth.make_problem(49, N=64, P=2, J=4, M=20, d_over_r0=np.array([8.0, 12.0]))
+    D_np = simulate_D(pr)
+    D = to_dev(D_np, dev)
+    plan = make_plan(pr, dev)
+    alpha = torch.zeros((pr.P, pr.J, pr.M), device=dev)
+    sol = Solver(plan, alpha, D, pr.gamma)
+    xs = [alpha.cpu().numpy().reshape(pr.P, -1).astype(np.float64)]
+    for _ in range(4):
+        sol.step()
+        xs.append(alpha.cpu().numpy().reshape(pr.P, -1).astype(np.float64))
+    for p in range(pr.P):
+        def fg(x):
+            r = oracle.evaluate_patch(x.reshape(pr.J, pr.M), D_np[p], pr.basis, pr.diversity,
+                                      pr.pupil, pr.channel_object, pr.gamma)
+            return r["loss"], r["grad"].ravel()
+        gs = [fg(x[p])[1] for x in xs]
+        for k in range(1, 4):
+            S = [xs[i + 1][p] - xs[i][p] for i in range(k)]
+            Y = [gs[i + 1] - gs[i] for i in range(k)]
+            f, g = fg(xs[k][p])
+            d = two_loop(g, S, Y)
+            t, fn, _, _, ok = wolfe_search(fg, xs[k][p], f, g, d, 1.0)
+            assert ok
+            step_ref, step_gpu = t * d, xs[k + 1][p] - xs[k][p]
+            print(f"[lbfgs] patch {p} iteration {k + 1}: t {t:.4f} "
+                  f"step rel diff {np.linalg.norm(step_gpu - step_ref) / np.linalg.norm(step_ref):.2e}",
+                  flush=True)
+            assert np.linalg.norm(step_gpu - step_ref) < 1e-4 * np.linalg.norm(step_ref)
+    plan.close()
+
+
 def test_lbfgs_rounds_follow_the_step_trajectories(dev):
     """Round mode (no host read-back) runs every patch through the same
     iterations as step mode: run both until every patch has stopped and
