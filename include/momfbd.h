@@ -361,7 +361,8 @@ typedef struct {
   int xcd_forward;              /* 1: units of a patch-object on one XCD (L2)   */
   int xcd_adjoint;              /* same for the adjoint kernel                  */
   int object_pairs_per_thread;  /* 1, 2 or 4 frequency pairs per thread         */
-  int grad_waves;               /* 4 or 8 waves per row tile (8 needs M <= 128) */
+  int grad_waves;               /* gradient contraction: 4 waves x 4 row tiles, or
+                                   8 waves x 2 row tiles per workgroup          */
 } momfbd_tuning;
 /* Errors: EINVAL (NULL or a value out of range). */
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);

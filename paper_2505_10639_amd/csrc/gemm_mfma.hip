@@ -31,76 +31,121 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
   return acc;
 }
 
-// One block = W waves = 16 rows (p,j) x all mode columns; wave w sums the
-// slice [w K/W, (w+1) K/W) of k = c*bp + px; the partial sums are added in
-// fixed order (wave 0 + 1 + ... + W-1) through LDS.  W (4 or 8) is a launch
-// schedule the autotuner picks.
-template <int MT, int W>
+// One block = W waves x RT row tiles (16 RT rows (p,j)) x all mode columns.
+// Each wave sums the slice [w K/W, (w+1) K/W) of k = c*bp + px for all RT
+// row tiles, so every basis chunk it loads serves RT x 16 rows (the basis
+// reads through L2 are what bound this contraction).  Operands are loaded
+// DEPTH chunks ahead.  The partial sums are added in wave order (wave 0,
+// then 1, ..., W-1) in one LDS buffer.  The basis rows are zero-padded to
+// MT*16 per basis, so no mode test is needed inside the loop; rows past R
+// read row R-1 and are not written.  Schedules: W = 4 with RT = 4 and
+// DEPTH = 2, or W = 8 with RT = 2 and DEPTH = 1.  CS is the number of
+// channels summed per load when they share one basis (0: the run-time C),
+// fixed at compile time where it can be so that the loads of a chunk issue
+// together.
+template <int MT, int RT, int W, int DEPTH, int CS>
 __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int zc, int M, int bp,
-                                                      const float* __restrict__ Zt,
+                                                      const float* __restrict__ Ztp,
                                                       const float* __restrict__ gphi,
                                                       float* __restrict__ grad) {
-  __shared__ floatx4 red[W - 1][MT][64];
+  __shared__ floatx4 red[RT * MT][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
-  const int r0 = blockIdx.x * 16;
-  const int r = r0 + i16;
-  const bool rok = r < R;
-  const int p = rok ? r / J : 0, j = rok ? r % J : 0;
-  floatx4 acc[MT];
+  const int r0 = blockIdx.x * 16 * RT;
+  const size_t cstride = (size_t)J * bp;   // between the channels of one (p, j)
+  const float* grow[RT];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < RT; ++q) {
+    const int r = min(r0 + q * 16 + i16, R - 1);
+    grow[q] = gphi + ((size_t)(r / J) * C * J + r % J) * bp + 4 * g;
+  }
+  floatx4 acc[RT][MT];
+#pragma unroll
+  for (int q = 0; q < RT; ++q)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int Kq = zc * bp / W;
   const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
-  // operands of chunk kk: a from gphi row r, b[t] from mode rows t*16 + i16;
-  // the next chunk's operands are loaded before the current chunk's MFMAs
-  auto load = [&](int kk, floatx4& a4, floatx4 (&b4)[MT]) {
-    const int c = kk / bp, px = kk % bp + 4 * g;
-    a4 = floatx4{0.f, 0.f, 0.f, 0.f};
-    if (rok) {
-      if (zc == C) {
-        a4 = *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + c) * J + j) * bp + px);
+  const float* zrow = Ztp + (size_t)i16 * bp + 4 * g;
+  // operands of chunk kk: a[q] from gphi row q*16 + i16 (with one shared
+  // basis, the sum over channels in channel order), b[t] from mode row
+  // t*16 + i16
+  auto load = [&](int kk, floatx4 (&a4)[RT], floatx4 (&b4)[MT]) {
+    const int c = kk / bp, px = kk % bp;
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+      if (CS == 1) {
+        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + c * cstride + px);
+      } else if (CS > 1) {
+        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + px);
+#pragma unroll
+        for (int ch = 1; ch < CS; ++ch)
+          a4[q] += *reinterpret_cast<const floatx4*>(grow[q] + ch * cstride + px);
       } else {
-        for (int ch = 0; ch < C; ++ch)
-          a4 += *reinterpret_cast<const floatx4*>(gphi + (((size_t)p * C + ch) * J + j) * bp + px);
+        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + px);
+        for (int ch = 1; ch < C; ++ch)
+          a4[q] += *reinterpret_cast<const floatx4*>(grow[q] + ch * cstride + px);
       }
     }
+    const float* zb = zrow + (size_t)c * MT * 16 * bp + px;
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int m = t * 16 + i16;
-      b4[t] = (m < M) ? *reinterpret_cast<const floatx4*>(Zt + ((size_t)c * M + m) * bp + px)
-                      : floatx4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int t = 0; t < MT; ++t) b4[t] = *reinterpret_cast<const floatx4*>(zb + (size_t)t * 16 * bp);
   };
-  floatx4 a_cur, b_cur[MT];
-  load(k_begin, a_cur, b_cur);
-  for (int kk = k_begin; kk < k_end; kk += 16) {
-    floatx4 a_nxt, b_nxt[MT];
-    if (kk + 16 < k_end) load(kk + 16, a_nxt, b_nxt);
+  auto compute = [&](const floatx4 (&a4)[RT], const floatx4 (&b4)[MT]) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) acc[t] = mfma4(a_cur, b_cur[t], acc[t]);
-    if (kk + 16 < k_end) {
-      a_cur = a_nxt;
+    for (int q = 0; q < RT; ++q)
 #pragma unroll
-      for (int t = 0; t < MT; ++t) b_cur[t] = b_nxt[t];
+      for (int t = 0; t < MT; ++t) acc[q][t] = mfma4(a4[q], b4[t], acc[q][t]);
+  };
+  if constexpr (DEPTH == 1) {
+    floatx4 a_cur[RT], b_cur[MT];
+    load(k_begin, a_cur, b_cur);
+    for (int kk = k_begin; kk < k_end; kk += 16) {
+      floatx4 a_nxt[RT], b_nxt[MT];
+      if (kk + 16 < k_end) load(kk + 16, a_nxt, b_nxt);
+      compute(a_cur, b_cur);
+      if (kk + 16 < k_end) {
+#pragma unroll
+        for (int q = 0; q < RT; ++q) a_cur[q] = a_nxt[q];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) b_cur[t] = b_nxt[t];
+      }
+    }
+  } else {
+    // two stages; the chunk count per wave, zc*bp/(16 W), is even for
+    // bp in {1024, 2304, 4096} and W in {4, 8}
+    floatx4 a0[RT], b0[MT], a1[RT], b1[MT];
+    load(k_begin, a0, b0);
+    load(k_begin + 16, a1, b1);
+    for (int kk = k_begin; kk < k_end; kk += 32) {
+      compute(a0, b0);
+      if (kk + 32 < k_end) load(kk + 32, a0, b0);
+      compute(a1, b1);
+      if (kk + 48 < k_end) load(kk + 48, a1, b1);
     }
   }
-  if (wave > 0) {
+  for (int w = 0; w < W; ++w) {
+    if (wave == w) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) red[wave - 1][t][lane] = acc[t];
+      for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (w == 0)
+            red[q * MT + t][lane] = acc[q][t];
+          else
+            red[q * MT + t][lane] += acc[q][t];
+        }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (wave != 0) return;
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    floatx4 v = acc[t];
-#pragma unroll
-    for (int w = 0; w < W - 1; ++w) v += red[w][t][lane];
+  for (int qt = wave; qt < RT * MT; qt += W) {
+    const int q = qt / MT, t = qt % MT;
+    const floatx4 v = red[qt][lane];
     const int m = t * 16 + i16;
     if (m >= M) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int row = r0 + 4 * g + e;
+      const int row = r0 + q * 16 + 4 * g + e;
       if (row < R) grad[(size_t)row * M + m] = 6.283185307179586f * v[e];
     }
   }
@@ -162,17 +207,28 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
   }
 }
 
-template <int MT>
-void launch_grad_t(const Dims& d, const float* Zt, const float* gphi, float* grad,
-                   hipStream_t s) {
-  const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
-  // eight waves only while the partial sums fit in 64 KB of LDS
-  if (MT <= 8 && d.grad_waves == 8)
-    hipLaunchKernelGGL((k_grad_mfma<MT, (MT <= 8 ? 8 : 4)>), dim3((R + 15) / 16), dim3(512), 0, s,
-                       R, d.J, d.C, zc, d.M, d.bandpix(), Zt, gphi, grad);
+template <int MT, int CS>
+void launch_grad_cs(const Dims& d, int zc, const float* Ztp, const float* gphi, float* grad,
+                    hipStream_t s) {
+  const int R = d.P * d.J;
+  if (d.grad_waves == 8)
+    hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, 1, CS>), dim3((R + 31) / 32), dim3(512), 0, s, R,
+                       d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad);
   else
-    hipLaunchKernelGGL((k_grad_mfma<MT, 4>), dim3((R + 15) / 16), dim3(256), 0, s, R, d.J, d.C,
-                       zc, d.M, d.bandpix(), Zt, gphi, grad);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, 2, CS>), dim3((R + 63) / 64), dim3(256), 0, s, R,
+                       d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad);
+}
+
+template <int MT>
+void launch_grad_t(const Dims& d, const float* Ztp, const float* gphi, float* grad,
+                   hipStream_t s) {
+  const int zc = d.zc > 0 ? d.zc : d.C;
+  if (zc == d.C)
+    launch_grad_cs<MT, 1>(d, zc, Ztp, gphi, grad, s);
+  else if (d.C == 2)
+    launch_grad_cs<MT, 2>(d, zc, Ztp, gphi, grad, s);
+  else
+    launch_grad_cs<MT, 0>(d, zc, Ztp, gphi, grad, s);
 }
 
 }  // namespace

@@ -1,6 +1,7 @@
 // C-ABI layer of libmomfbd: argument checks, plan tables, workspace, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -36,7 +37,7 @@ struct momfbd_plan_s {
   int shift_y[kMaxC];      // translation applied to each channel's pupil
   int shift_x[kMaxC];
   float* Ab = nullptr;     // [C][N/2][N/2]    aperture on the band
-  float* Zt = nullptr;     // [C][M][N/2][N/2] modes in turns
+  float* Zt = nullptr;     // [C][Mp][N/2][N/2] modes in turns, rows M..Mp-1 zero
   float* ZtT = nullptr;    // [C][(N/2)^2][Mp] the same, mode index fastest, zero padded
   int Mp = 0;              // M rounded up to a multiple of 16
   float* thetat = nullptr; // [C][N/2][N/2]    diversity in turns
@@ -241,7 +242,10 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
                          (size_t)M * BP * sizeof(float)) == 0;
   pl->d.zc = shared ? 1 : C;
   pl->Mp = (M + 15) / 16 * 16;
-  std::vector<float> hZT((size_t)C * BP * pl->Mp, 0.f);
+  std::vector<float> hZT((size_t)C * BP * pl->Mp, 0.f), hZp((size_t)C * pl->Mp * BP, 0.f);
+  for (int c = 0; c < C; ++c)
+    std::copy(hZ.begin() + (size_t)c * M * BP, hZ.begin() + (size_t)(c + 1) * M * BP,
+              hZp.begin() + (size_t)c * pl->Mp * BP);
   for (int c = 0; c < C; ++c)
     for (int m = 0; m < M; ++m)
       for (size_t px = 0; px < BP; ++px)
@@ -249,14 +253,14 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   if (hipHostMalloc(&pl->hflag, sizeof(int)) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
-            hipMalloc(&pl->Zt, hZ.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->Zt, hZp.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->ZtT, hZT.size() * sizeof(float)) == hipSuccess &&
             hipMemcpy(pl->ZtT, hZT.data(), hZT.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->Ab, hA.data(), hA.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
-            hipMemcpy(pl->Zt, hZ.data(), hZ.size() * sizeof(float), hipMemcpyHostToDevice) ==
+            hipMemcpy(pl->Zt, hZp.data(), hZp.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->thetat, hT.data(), hT.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess;
@@ -280,16 +284,16 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   return MOMFBD_OK;
 }
 
-static bool tuning_ok(const momfbd_tuning* t, int M) {
+static bool tuning_ok(const momfbd_tuning* t) {
   return t && (t->xcd_forward == 0 || t->xcd_forward == 1) &&
          (t->xcd_adjoint == 0 || t->xcd_adjoint == 1) &&
          (t->object_pairs_per_thread == 1 || t->object_pairs_per_thread == 2 ||
           t->object_pairs_per_thread == 4) &&
-         (t->grad_waves == 4 || (t->grad_waves == 8 && (M + 15) / 16 <= 8));
+         (t->grad_waves == 4 || t->grad_waves == 8);
 }
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
-  if (!plan || !tuning_ok(t, plan->d.M)) return MOMFBD_EINVAL;
+  if (!plan || !tuning_ok(t)) return MOMFBD_EINVAL;
   plan->d.xcd_fwd = t->xcd_forward;
   plan->d.xcd_adj = t->xcd_adjoint;
   plan->d.obj_ppt = t->object_pairs_per_thread;
@@ -646,7 +650,6 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
     float best_ms = 0.f;
     bool first = true;
     for (int v : values[k]) {
-      if (k == 3 && v == 8 && (plan->d.M + 15) / 16 > 8) continue;
       *knobs[k] = v;
       float ms = 0.f;
       if ((st = timed(&ms))) break;
