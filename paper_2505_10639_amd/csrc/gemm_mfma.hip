@@ -152,40 +152,42 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
 }
 
 // phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
-// Block = 4 waves, (basis, 64 columns, a quarter of the band pixels); with
-// one shared basis the block writes every channel's phi from one product:
-// the block's 64 coefficient rows (contiguous in alpha) are staged once in
-// LDS with the mode index padded to Mp; each wave then walks 4 tiles of 16
-// pixels x 64 columns, taking its B operands as float4 LDS reads.
+// Block = 4 waves, (basis, kCols columns, a quarter of the band pixels);
+// with one shared basis the block writes every channel's phi from one
+// product: the block's kCols coefficient rows (contiguous in alpha) are
+// staged once in LDS with the mode index padded to Mp; each wave then walks
+// tiles of 16 pixels x kCols columns, taking its B operands as float4 LDS
+// reads.  32 columns per block (twice the blocks of 64) measured 7% faster.
+constexpr int kCols = 32, kColTiles = kCols / 16;
 __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mp,
                                                     int bp,
                                                     const float* __restrict__ ZtT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
                                                     float* __restrict__ phi) {
-  extern __shared__ float al[];    // [64][Mp + 4]
+  extern __shared__ float al[];    // [kCols][Mp + 4]
   const int ldm = Mp + 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
   const int c = blockIdx.x >> 2, quarter = blockIdx.x & 3;
-  const int col0 = blockIdx.y * 64;
-  const int ncol = min(64, R - col0);
+  const int col0 = blockIdx.y * kCols;
+  const int ncol = min(kCols, R - col0);
   const float* src = alpha + (size_t)col0 * M;
-  for (int r = wave; r < 64; r += 4)
+  for (int r = wave; r < kCols; r += 4)
     for (int m = lane; m < Mp; m += 64)
       al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
   __syncthreads();
   const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
   for (int tile = 0; tile < ntile; ++tile) {
     const int px0 = quarter * (bp / 4) + (tile * 4 + wave) * 16;
-    floatx4 acc[4];
+    floatx4 acc[kColTiles];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kColTiles; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     const float* arow = ZtT + ((size_t)c * bp + px0 + i16) * Mp;
     for (int kk = 0; kk < Mp; kk += 16) {
       const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kColTiles; ++t) {
         const floatx4 b4 =
             *reinterpret_cast<const floatx4*>(al + (t * 16 + i16) * ldm + kk + 4 * g);
         acc[t] = mfma4(a4, b4, acc[t]);
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
       const floatx4 th =
           *reinterpret_cast<const floatx4*>(theta + (size_t)ch * bp + px0 + 4 * g);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kColTiles; ++t) {
         const int col = col0 + t * 16 + i16;
         if (col >= R) continue;
         const int p = col / J, j = col % J;
@@ -251,8 +253,8 @@ hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float*
 hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
                         const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
-  dim3 grid(zc * 4, (R + 63) / 64);
-  const size_t lds = (size_t)64 * (Mp + 4) * sizeof(float);
+  dim3 grid(zc * 4, (R + kCols - 1) / kCols);
+  const size_t lds = (size_t)kCols * (Mp + 4) * sizeof(float);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
