@@ -302,6 +302,40 @@ def test_lbfgs_later_steps_match_oracle(dev):
     plan.close()
 
 
+def test_lbfgs_long_coefficient_vectors_match_oracle(dev):
+    """J M = 2304 coefficients per patch (past the register-resident
+    two-loop, which holds up to 2048): iterations 2 and 3 match the
+    reference solver from the solver's own points."""
+    from oracle.lbfgs import two_loop, wolfe_search
+    from paper_2505_10639_amd import Solver
+    pr = synth.make_problem(51, N=64, P=1, J=24, M=96, d_over_r0=10.0)
+    D_np = simulate_D(pr)
+    D = to_dev(D_np, dev)
+    plan = make_plan(pr, dev)
+    alpha = torch.zeros((pr.P, pr.J, pr.M), device=dev)
+    sol = Solver(plan, alpha, D, pr.gamma)
+    xs = [alpha.cpu().numpy().reshape(-1).astype(np.float64)]
+    for _ in range(3):
+        sol.step()
+        xs.append(alpha.cpu().numpy().reshape(-1).astype(np.float64))
+
+    def fg(x):
+        r = oracle.evaluate_patch(x.reshape(pr.J, pr.M), D_np[0], pr.basis, pr.diversity,
+                                  pr.pupil, pr.channel_object, pr.gamma)
+        return r["loss"], r["grad"].ravel()
+    gs = [fg(x)[1] for x in xs]
+    for k in (1, 2):
+        S = [xs[i + 1] - xs[i] for i in range(k)]
+        Y = [gs[i + 1] - gs[i] for i in range(k)]
+        f, g = fg(xs[k])
+        d = two_loop(g, S, Y)
+        t, _, _, _, ok = wolfe_search(fg, xs[k], f, g, d, 1.0)
+        assert ok
+        step_ref, step_gpu = t * d, xs[k + 1] - xs[k]
+        assert np.linalg.norm(step_gpu - step_ref) < 1e-4 * np.linalg.norm(step_ref)
+    plan.close()
+
+
 def test_lbfgs_rounds_follow_the_step_trajectories(dev):
     """Round mode (no host read-back) runs every patch through the same
     iterations as step mode: run both until every patch has stopped and
@@ -581,6 +615,13 @@ def test_many_channels_and_objects(dev):
     ch = tuple((k, d) for k in range(4) for d in (0.0, 1.0))
     pr = synth.make_problem(210, N=64, P=2, J=2, M=20, channels=ch, d_over_r0=9.0)
     check_patchwise(pr, simulate_D(pr), alpha_points(pr, 3), dev)
+
+
+def test_largest_channel_and_object_count(dev):
+    """32 channels, each its own object (the most a plan holds)."""
+    ch = tuple((k, 0.0 if k % 2 == 0 else 1.0) for k in range(32))
+    pr = synth.make_problem(211, N=64, P=1, J=1, M=8, channels=ch, d_over_r0=9.0)
+    check_patchwise(pr, simulate_D(pr), alpha_points(pr, 4), dev)
 
 
 def test_multi_wavelength_n64(dev):

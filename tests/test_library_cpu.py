@@ -79,6 +79,8 @@ def test_plan_create_rejects_bad_arguments_without_a_device(L):
     assert _create(L, N=80, A=A, Z=Z)[0] == -2                # patch size unsupported
     assert _create(L, M=300, A=_arrays(64, 1, 300)[0], Z=_arrays(64, 1, 300)[1])[0] == -2
     assert _create(L, J=100, M=100, A=_arrays(64, 1, 100)[0], Z=_arrays(64, 1, 100)[1])[0] == -2
+    A, Z = _arrays(64, 33, 6)
+    assert _create(L, C=33, K=1, A=A, Z=Z)[0] == -2           # more channels than the plan holds
     A, Z = _arrays(64, 1, 6, frac=0.6)                        # pupil wider than N/2
     assert _create(L, A=A, Z=Z)[0] == -2
     A0 = np.zeros((1, 64, 64), np.float32)
