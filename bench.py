@@ -308,6 +308,71 @@ def warm_start_block(dev, steps, patches=961):
     }
 
 
+def crisp_like_block(dev, rounds=150):
+    """End-to-end restoration of one 512 x 512 field shaped like the paper's
+    CRISP run (wideband + narrowband objects, 12 frames, 54 KL modes,
+    patches every 40 px; 96 x 96 patches stand in for its 92 x 92): 121
+    patches, D/r0 = 8.  The data spectra are made with the library's forward
+    model from two independent scenes plus 1% noise, outside the timed part.
+    Timed: plan creation, solver initialisation, `rounds` solver rounds
+    (one line-search trial per patch each), the Loefdahl-Scharmer-filtered
+    objects and their mosaic, with one synchronisation at the end."""
+    import torch
+
+    import synth
+    from paper_2505_10639_amd import Plan, Solver, filter_spec
+
+    N, J, M, fov, stride, border = 96, 12, 54, 512, 40, 9
+    ny = nx = (fov - N) // stride + 1
+    P = ny * nx
+    frac = 0.45
+    A = synth.pupil_mask(N, frac).astype(np.float32)
+    Z, var = synth.kl_basis(N, M, frac)
+    pupil = np.stack([A, A])
+    basis = np.stack([Z, Z]).astype(np.float32)
+    win = torch.from_numpy(synth.hann_window(N, border).astype(np.float32)).to(dev)
+    rng = np.random.default_rng(synth.SEED_ROOT + 9)
+    scenes = torch.from_numpy(np.stack([synth.object_field(rng, fov, fov) for _ in range(2)])
+                              .astype(np.float32)).to(dev)
+    # true coefficients: KL modes are uncorrelated, variance var (D/r0)^(5/3)
+    sd = np.sqrt(var * 8.0 ** (5.0 / 3.0)).astype(np.float32)
+    a_true = torch.from_numpy((rng.standard_normal((P, J, M)) * sd).astype(np.float32)).to(dev)
+    plan0 = Plan(N, P, J, [0, 1], pupil, basis, None, dev)
+    aux = Plan(N, P, 1, [0, 1], pupil, basis[:, :1], None, dev)
+    Ohat = aux.prepare_data(scenes.reshape(2, 1, fov, fov).contiguous(), stride, win)
+    aux.close()
+    _, S = plan0.forward(a_true, want_psf=False)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_ROOT + 10)
+    noise = 0.01 * torch.randn((2, J, fov, fov), generator=gen, device=dev)
+    D = (Ohat * S + plan0.prepare_data(noise, stride, win)).contiguous()
+    plan0.close()
+    del S, Ohat, noise
+    zero = torch.zeros((P, J, M), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan(N, P, J, [0, 1], pupil, basis, None, dev)
+    sol = Solver(plan, zero.clone(), D, 1e-3)
+    loss0 = sol.loss.clone()
+    accepted = torch.empty_like(zero)
+    loss, _ = sol.rounds(rounds, accepted)
+    filt = [filter_spec("scharmer", noise_power=1.0)] * 2
+    obj = plan.object_filtered(accepted, D, filt, 1e-3)
+    mos = plan.mosaic(obj, ny, nx, stride, border)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {
+        "workload": f"512x512 field, {P} patches of 96x96 every 40 px, 2 objects (wideband + "
+                    f"narrowband), 12 frames, 54 KL modes, D/r0 8",
+        "rounds": rounds, "seconds": t, "units": P * 2 * J,
+        "loss_start": float(loss0.sum()), "loss_end": float(loss.sum()),
+        "loss_at_true": float(plan.loss_grad(a_true, D, 1e-3)[0].sum()),
+        "mosaic_shape": list(mos.shape),
+    }
+    plan.close()
+    return out
+
+
 def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     """Independent 512^2 fields with patch sizes 64, 96 or 128 (stride N/2),
     frame counts 6..24, 44..88 modes and 1..3 objects (one channel each),
@@ -501,6 +566,8 @@ def main():
     if not args.no_large:
         log("uneven fields in one HIP graph")
         out["uneven_fields"] = uneven_fields_block(dev)
+        log("CRISP-like field: restoration end to end")
+        out["crisp_like_field"] = crisp_like_block(dev)
 
     if args.warm_steps > 0:
         log(f"warm start: {args.warm_steps} training steps, then time to converged loss")
