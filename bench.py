@@ -59,18 +59,18 @@ KERNEL_SOURCES = {
     "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
     "object": ["object.hip"],
 }
-COPY_FETCH_SCALE = 1.9997759116462532    # 256 MiB copy: FETCH_SIZE read 131086.7 KiB
+COPY_FETCH_SCALE = 1.999774640366233    # 256 MiB copy: FETCH_SIZE read 131086.8 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per kernel: the knob and, per value of it, (HBM bytes read, written) per
 # launch
 COUNTED_TRAFFIC = {
     "adjoint": {"sources_sha1": "ba0585355526", "knob": "xcd_adjoint",
-                "by_value": {1: (1024261705, 94470144), 0: (1342550230, 94470144)}},
+                "by_value": {1: (1024491843, 94470144), 0: (1342813539, 94470144)}},
     "forward": {"sources_sha1": "ba0585355526", "knob": "xcd_forward",
-                "by_value": {0: (94963556, 395093685), 1: (94961679, 392350984)}},
+                "by_value": {0: (94960243, 395098456), 1: (94963762, 392324672)}},
     "object": {"sources_sha1": "5fb361e02b19", "knob": "object_pairs_per_thread",
-               "by_value": {1: (779371655, 32783350), 2: (779372058, 32668352),
-                            4: (779371450, 32597480)}},
+               "by_value": {1: (779371192, 32783368), 2: (779371211, 32668168),
+                            4: (779371595, 32597664)}},
 }
 
 
