@@ -39,15 +39,23 @@ def test_counted_traffic_stale_source(bench, monkeypatch):
 
 
 def test_roofline_alu_and_hbm(bench):
-    N, units = 64, 1000
+    N, P, K, units = 64, 10, 2, 240
     _, per_kernel = bench.unit_flops(N)
-    r = bench.roofline({"adjoint": 2.0, "forward": 1.0}, units, N, 0, lambda k: 123)
+    D_bytes = units * N * (N // 2 + 1) * 8
+    nb = bench.kernel_io_bytes(N, P, K, units, D_bytes)
+    # adjoint: D, S and O read, phi read and dL/dphi written on the 32 x 32 band
+    assert nb["adjoint"] == 2 * D_bytes + P * K * N * 33 * 8 + 2 * units * 1024 * 4
+    assert nb["forward"] == units * 1024 * 4 + D_bytes
+    r = bench.roofline({"adjoint": 2.0, "forward": 1.0}, units, N, nb, lambda k: 123)
     assert r["kernel"] == "adjoint" and r["bound"] == "alu" and r["traffic"] == 123
     assert r["achieved"] == pytest.approx(per_kernel["adjoint"] * units / 2e-3 / 1e12)
-    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
-    r = bench.roofline({"object": 4.0, "adjoint": 1.0}, units, N, 10**9, lambda k: None)
-    assert r["bound"] == "hbm" and r["traffic"] is None
-    assert r["achieved"] == pytest.approx(2e9 / 4e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    hv = r["hbm_view"]
+    assert hv["achieved"] == pytest.approx(nb["adjoint"] / 2e-3 / 1e9)
+    assert hv["frac"] == pytest.approx(hv["achieved"] / 8000.0)
+    r = bench.roofline({"object": 4.0, "adjoint": 1.0}, units, N, nb, lambda k: None)
+    assert r["bound"] == "hbm" and r["traffic"] is None and "hbm_view" not in r
+    assert r["achieved"] == pytest.approx(nb["object"] / 4e-3 / 1e9)
 
 
 def test_fft_flop_count(bench):
