@@ -356,13 +356,17 @@ const char* momfbd_status_string(int status);
  * Results are the same for every schedule up to the order of floating-point
  * sums (the unit order changes nothing; the object kernel's pairs per
  * thread change the grouping of the FP64 loss partials, the gradient
- * contraction's waves the grouping of its FP32 partial sums). */
+ * contraction's waves and splits the grouping of its FP32 partial sums). */
 typedef struct {
   int xcd_forward;              /* 1: units of a patch-object on one XCD (L2)   */
   int xcd_adjoint;              /* same for the adjoint kernel                  */
   int object_pairs_per_thread;  /* 1, 2 or 4 frequency pairs per thread         */
   int grad_waves;               /* gradient contraction: 4 waves x 4 row tiles, or
                                    8 waves x 2 row tiles per workgroup          */
+  int grad_splits;              /* workgroups sharing one row tile's pixel sum:
+                                   1, 2, 4 or 8; 0 on input picks the smallest
+                                   count that gives every CU two workgroups
+                                   (get_tuning reports the count in use)      */
 } momfbd_tuning;
 /* Errors: EINVAL (NULL or a value out of range). */
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);

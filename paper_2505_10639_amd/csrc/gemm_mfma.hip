@@ -31,23 +31,28 @@ __device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, flo
   return acc;
 }
 
-// One block = W waves x RT row tiles (16 RT rows (p,j)) x all mode columns.
-// Each wave sums the slice [w K/W, (w+1) K/W) of k = c*bp + px for all RT
-// row tiles, so every basis chunk it loads serves RT x 16 rows (the basis
-// reads through L2 are what bound this contraction).  Operands are loaded
-// DEPTH chunks ahead.  The partial sums are added in wave order (wave 0,
-// then 1, ..., W-1) in one LDS buffer.  The basis rows are zero-padded to
-// MT*16 per basis, so no mode test is needed inside the loop; rows past R
-// read row R-1 and are not written.  Schedules: W = 4 with RT = 4 and
-// DEPTH = 2, or W = 8 with RT = 2 and DEPTH = 1.  CS is the number of
-// channels summed per load when they share one basis (0: the run-time C),
-// fixed at compile time where it can be so that the loads of a chunk issue
-// together.
+// One block = W waves x RT row tiles (16 RT rows (p,j)) x all mode columns
+// x one of `splits` parts of the k range (blockIdx.y).  The k = c*bp + px
+// range, in 16-wide chunks, is cut into W*splits nearly equal slices; wave w
+// of split s sums slice s*W + w for all RT row tiles, so every basis chunk it
+// loads serves RT x 16 rows (the basis reads through L2 are what bound this
+// contraction).  Splitting k over blocks fills the chip when there are few
+// row tiles.  Operands are loaded DEPTH chunks ahead.  The partial sums of a
+// block are added in wave order (wave 0, then 1, ..., W-1) in one LDS buffer;
+// with one split the block writes 2 pi times its sum to grad, otherwise its
+// sum to part[s][R][M], which k_grad_combine adds in split order.  The
+// basis rows are zero-padded to MT*16 per basis, so no mode test is needed
+// inside the loop; rows past R read row R-1 and are not written.
+// Schedules: W = 4 with RT = 4 and DEPTH = 2, or W = 8 with RT = 2 and
+// DEPTH = 1.  CS is the number of channels summed per load when they share
+// one basis (0: the run-time C), fixed at compile time where it can be so
+// that the loads of a chunk issue together.
 template <int MT, int RT, int W, int DEPTH, int CS>
 __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int zc, int M, int bp,
                                                       const float* __restrict__ Ztp,
                                                       const float* __restrict__ gphi,
-                                                      float* __restrict__ grad) {
+                                                      float* __restrict__ grad,
+                                                      float* __restrict__ part) {
   __shared__ floatx4 red[RT * MT][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
@@ -64,8 +69,11 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
   for (int q = 0; q < RT; ++q)
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int Kq = zc * bp / W;
-  const int k_begin = wave * Kq, k_end = (wave + 1) * Kq;
+  const int splits = gridDim.y, split = blockIdx.y;
+  const int nchunk = zc * bp / 16, slices = W * splits, slice = split * W + wave;
+  const int c_begin = (int)((long)slice * nchunk / slices);
+  const int n = (int)((long)(slice + 1) * nchunk / slices) - c_begin;   // chunks of this wave
+  const int k_begin = 16 * c_begin;
   const float* zrow = Ztp + (size_t)i16 * bp + 4 * g;
   // operands of chunk kk: a[q] from gphi row q*16 + i16 (with one shared
   // basis, the sum over channels in channel order), b[t] from mode row
@@ -99,12 +107,12 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
   };
   if constexpr (DEPTH == 1) {
     floatx4 a_cur[RT], b_cur[MT];
-    load(k_begin, a_cur, b_cur);
-    for (int kk = k_begin; kk < k_end; kk += 16) {
+    if (n > 0) load(k_begin, a_cur, b_cur);
+    for (int i = 0; i < n; ++i) {
       floatx4 a_nxt[RT], b_nxt[MT];
-      if (kk + 16 < k_end) load(kk + 16, a_nxt, b_nxt);
+      if (i + 1 < n) load(k_begin + 16 * (i + 1), a_nxt, b_nxt);
       compute(a_cur, b_cur);
-      if (kk + 16 < k_end) {
+      if (i + 1 < n) {
 #pragma unroll
         for (int q = 0; q < RT; ++q) a_cur[q] = a_nxt[q];
 #pragma unroll
@@ -112,17 +120,19 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
       }
     }
   } else {
-    // two stages; the chunk count per wave, zc*bp/(16 W), is even for
-    // bp in {1024, 2304, 4096} and W in {4, 8}
+    // two stages: chunks i and i + 1 in flight; an odd last chunk is in
+    // stage 0
     floatx4 a0[RT], b0[MT], a1[RT], b1[MT];
-    load(k_begin, a0, b0);
-    load(k_begin + 16, a1, b1);
-    for (int kk = k_begin; kk < k_end; kk += 32) {
+    if (n > 0) load(k_begin, a0, b0);
+    if (n > 1) load(k_begin + 16, a1, b1);
+    int i = 0;
+    for (; i + 2 <= n; i += 2) {
       compute(a0, b0);
-      if (kk + 32 < k_end) load(kk + 32, a0, b0);
+      if (i + 2 < n) load(k_begin + 16 * (i + 2), a0, b0);
       compute(a1, b1);
-      if (kk + 48 < k_end) load(kk + 48, a1, b1);
+      if (i + 3 < n) load(k_begin + 16 * (i + 3), a1, b1);
     }
+    if (i < n) compute(a0, b0);
   }
   for (int w = 0; w < W; ++w) {
     if (wave == w) {
@@ -138,6 +148,8 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
     }
     __syncthreads();
   }
+  float* out = splits == 1 ? grad : part + (size_t)split * R * M;
+  const float scale = splits == 1 ? 6.283185307179586f : 1.0f;
   for (int qt = wave; qt < RT * MT; qt += W) {
     const int q = qt / MT, t = qt % MT;
     const floatx4 v = red[qt][lane];
@@ -146,9 +158,20 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = r0 + q * 16 + 4 * g + e;
-      if (row < R) grad[(size_t)row * M + m] = 6.283185307179586f * v[e];
+      if (row < R) out[(size_t)row * M + m] = scale * v[e];
     }
   }
+}
+
+// grad = 2 pi (part[0] + part[1] + ... + part[splits-1]), in that order.
+__global__ __launch_bounds__(256) void k_grad_combine(long n, int splits,
+                                                      const float* __restrict__ part,
+                                                      float* __restrict__ grad) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float v = part[i];
+  for (int s = 1; s < splits; ++s) v += part[(size_t)s * n + i];
+  grad[i] = 6.283185307179586f * v;
 }
 
 // phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
@@ -210,42 +233,71 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
 }
 
 template <int MT, int CS>
-void launch_grad_cs(const Dims& d, int zc, const float* Ztp, const float* gphi, float* grad,
-                    hipStream_t s) {
+void launch_grad_cs(const Dims& d, int zc, int splits, const float* Ztp, const float* gphi,
+                    float* grad, float* part, hipStream_t s) {
   const int R = d.P * d.J;
   if (d.grad_waves == 8)
-    hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, 1, CS>), dim3((R + 31) / 32), dim3(512), 0, s, R,
-                       d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, 1, CS>), dim3((R + 31) / 32, splits), dim3(512), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
   else
-    hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, 2, CS>), dim3((R + 63) / 64), dim3(256), 0, s, R,
-                       d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, 2, CS>), dim3((R + 63) / 64, splits), dim3(256), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
 }
 
 template <int MT>
-void launch_grad_t(const Dims& d, const float* Ztp, const float* gphi, float* grad,
-                   hipStream_t s) {
+void launch_grad_t(const Dims& d, int splits, const float* Ztp, const float* gphi, float* grad,
+                   float* part, hipStream_t s) {
   const int zc = d.zc > 0 ? d.zc : d.C;
   if (zc == d.C)
-    launch_grad_cs<MT, 1>(d, zc, Ztp, gphi, grad, s);
+    launch_grad_cs<MT, 1>(d, zc, splits, Ztp, gphi, grad, part, s);
   else if (d.C == 2)
-    launch_grad_cs<MT, 2>(d, zc, Ztp, gphi, grad, s);
+    launch_grad_cs<MT, 2>(d, zc, splits, Ztp, gphi, grad, part, s);
   else
-    launch_grad_cs<MT, 0>(d, zc, Ztp, gphi, grad, s);
+    launch_grad_cs<MT, 0>(d, zc, splits, Ztp, gphi, grad, part, s);
 }
 
 }  // namespace
 
+int grad_splits_auto(const Dims& d) {
+  // Measured on the 64x64 and 128x128 full fields: with fewer row-tile
+  // blocks than CUs (256) splitting the pixel sum fills idle CUs; with more,
+  // it only evens out the last round and pays when each wave keeps a long
+  // run of chunks (128x128, four bases: 1.33 -> 1.03 ms at 2 splits), and
+  // it costs when the runs get short (64x64: 40 us unsplit, 50 us at 4).
+  const int R = d.P * d.J, W = d.grad_waves == 8 ? 8 : 4;
+  const long rows = 16L * (W == 8 ? 2 : 4);
+  const long blocks = (R + rows - 1) / rows;
+  const int zc = d.zc > 0 ? d.zc : d.C;
+  const int nchunk = zc * d.bandpix() / 16;
+  int s = 1;
+  while (s < kMaxGradSplits && 2 * s * W <= nchunk) {
+    const bool fill = blocks * 2 * s <= 256;
+    const bool tail = blocks * s < 512 && nchunk / (2 * s * W) >= 64;
+    if (!fill && !(blocks >= 256 && tail)) break;
+    s *= 2;
+  }
+  return s;
+}
+
+int grad_splits_of(const Dims& d) { return d.grad_splits > 0 ? d.grad_splits : grad_splits_auto(d); }
+
 hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
-                       hipStream_t s) {
+                       float* part, hipStream_t s) {
   const int mt = (d.M + 15) / 16;
+  const int splits = grad_splits_of(d);
   switch (mt) {
 #define MFBD_CASE(n) \
-  case n: launch_grad_t<n>(d, Zt, gphi, grad, s); break;
+  case n: launch_grad_t<n>(d, splits, Zt, gphi, grad, part, s); break;
     MFBD_CASE(1) MFBD_CASE(2) MFBD_CASE(3) MFBD_CASE(4) MFBD_CASE(5) MFBD_CASE(6)
     MFBD_CASE(7) MFBD_CASE(8) MFBD_CASE(9) MFBD_CASE(10) MFBD_CASE(11) MFBD_CASE(12)
     MFBD_CASE(13) MFBD_CASE(14) MFBD_CASE(15) MFBD_CASE(16)
 #undef MFBD_CASE
     default: return hipErrorInvalidValue;
+  }
+  if (splits > 1) {
+    const long n = (long)d.P * d.J * d.M;
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       splits, part, grad);
   }
   return hipGetLastError();
 }

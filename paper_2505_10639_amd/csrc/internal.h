@@ -23,8 +23,9 @@ struct Dims {
   int N, P, C, K, J, M;
   // launch schedules (chosen by momfbd_plan_autotune): XCD-grouped unit
   // order of the forward / adjoint grids, frequency pairs per thread of the
-  // object kernel, waves per row tile of the gradient contraction
-  int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4;
+  // object kernel, waves per row tile of the gradient contraction and the
+  // number of blocks its pixel sum is split over (0: grad_splits_auto)
+  int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4, grad_splits = 0;
   // distinct modal bases on the band: 1 when every channel's band-sampled
   // basis is the same (the contractions then run once for all channels),
   // else C; 0 is read as C
@@ -89,7 +90,14 @@ struct Workspace {
   float2* O;               // [P][K][N][N/2+1]    object spectra
   float* gphi;             // [P][C][J][N/2][N/2]  dL/dphi (rad^-1) on the band
   double* loss_pk;         // [P][K][object_blocks(N)] partial loss terms
+  float* gpart;            // [kMaxGradSplits][P][J][M] partial sums of the gradient
 };
+
+// The gradient contraction's pixel sum may be split over up to this many
+// blocks per row tile; grad_splits_of gives the plan's split count.
+constexpr int kMaxGradSplits = 8;
+int grad_splits_auto(const Dims& d);
+int grad_splits_of(const Dims& d);
 
 size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);
@@ -108,7 +116,7 @@ hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, 
                           const float* Ab, const float* phi, const float2* S, const float2* O,
                           float* gphi, hipStream_t s);
 hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
-                       hipStream_t s);
+                       float* gpart, hipStream_t s);
 hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
                           const float* apod, float2* D, hipStream_t s);
 hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s);

@@ -128,6 +128,7 @@ size_t workspace_bytes(const Dims& d) {
   b += align256((size_t)d.P * d.K * hs * sizeof(float2));    // O
   b += align256(units * bp * sizeof(float));                 // gphi
   b += align256((size_t)d.P * d.K * object_blocks(d.N) * sizeof(double));  // loss_pk
+  b += align256((size_t)kMaxGradSplits * d.P * d.J * d.M * sizeof(float));    // gpart
   return b;
 }
 
@@ -146,6 +147,8 @@ Workspace carve_workspace(const Dims& d, void* base) {
   w.gphi = reinterpret_cast<float*>(p);
   p += align256(units * bp * sizeof(float));
   w.loss_pk = reinterpret_cast<double*>(p);
+  p += align256((size_t)d.P * d.K * object_blocks(d.N) * sizeof(double));
+  w.gpart = reinterpret_cast<float*>(p);
   return w;
 }
 
@@ -289,7 +292,9 @@ static bool tuning_ok(const momfbd_tuning* t) {
          (t->xcd_adjoint == 0 || t->xcd_adjoint == 1) &&
          (t->object_pairs_per_thread == 1 || t->object_pairs_per_thread == 2 ||
           t->object_pairs_per_thread == 4) &&
-         (t->grad_waves == 4 || t->grad_waves == 8);
+         (t->grad_waves == 4 || t->grad_waves == 8) &&
+         (t->grad_splits == 0 || t->grad_splits == 1 || t->grad_splits == 2 ||
+          t->grad_splits == 4 || t->grad_splits == 8);
 }
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
@@ -298,6 +303,7 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   plan->d.xcd_adj = t->xcd_adjoint;
   plan->d.obj_ppt = t->object_pairs_per_thread;
   plan->d.grad_waves = t->grad_waves;
+  plan->d.grad_splits = t->grad_splits;
   return MOMFBD_OK;
 }
 
@@ -307,6 +313,7 @@ int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* t) {
   t->xcd_adjoint = plan->d.xcd_adj;
   t->object_pairs_per_thread = plan->d.obj_ppt;
   t->grad_waves = plan->d.grad_waves;
+  t->grad_splits = grad_splits_of(plan->d);
   return MOMFBD_OK;
 }
 
@@ -394,7 +401,9 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
     return launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
   });
   if (e == hipSuccess)
-    e = prof_launch(plan, KK_GRAD, s, [&] { return launch_grad(plan->d, plan->Zt, w.gphi, grad, s); });
+    e = prof_launch(plan, KK_GRAD, s, [&] {
+      return launch_grad(plan->d, plan->Zt, w.gphi, grad, w.gpart, s);
+    });
   return to_status(e);
 }
 
@@ -643,9 +652,19 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // replaces the best so far only when at least 1% faster, so that timing
   // noise between near-equal schedules does not decide (the XCD-grouped
   // orders read less from HBM at equal speed).
-  int* knobs[4] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves};
-  const std::vector<int> values[4] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}};
-  for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
+  // The gradient's split count starts from the automatic one for the
+  // chosen gradient waves; the others follow in increasing order.
+  int* knobs[5] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves,
+                   &plan->d.grad_splits};
+  std::vector<int> values[5] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}, {}};
+  for (int k = 0; k < 5 && st == MOMFBD_OK; ++k) {
+    if (k == 4) {
+      plan->d.grad_splits = 0;
+      const int a = grad_splits_auto(plan->d);
+      values[4] = {a};
+      for (int v = 1; v <= kMaxGradSplits; v *= 2)
+        if (v != a) values[4].push_back(v);
+    }
     int best = *knobs[k];
     float best_ms = 0.f;
     bool first = true;

@@ -95,9 +95,11 @@ class Plan:
     def tuning(self):
         return _lib.momfbd_plan_get_tuning(self.handle)
 
-    def set_tuning(self, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves):
+    def set_tuning(self, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves,
+                   grad_splits=0):
+        """Launch schedules (see momfbd_tuning); grad_splits 0 is automatic."""
         _lib.momfbd_plan_set_tuning(self.handle, xcd_forward, xcd_adjoint,
-                                    object_pairs_per_thread, grad_waves)
+                                    object_pairs_per_thread, grad_waves, grad_splits)
 
     def autotune(self, alpha, D, gamma=1e-3, weights=None, reps=5):
         """Time the launch schedules on this data and keep the fastest."""

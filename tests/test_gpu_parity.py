@@ -439,19 +439,24 @@ def test_launch_schedules_and_autotune(dev, N):
     """Every launch schedule gives the default results: bit for bit where
     only the order of the work changes (unit order), to the rounding of a
     regrouped sum where the grouping of partial sums changes (object pairs
-    per thread: FP64 loss; gradient waves: FP32 gradient).  The autotuned
-    plan still matches the oracle."""
+    per thread: FP64 loss; gradient waves and pixel-sum splits: FP32
+    gradient).  The split counts include ones that leave waves with
+    different chunk counts (N = 96: 144 chunks over 4 x 8 or 8 x 8 slices).
+    The autotuned plan still matches the oracle."""
     pr = synth.make_problem(70 + N, N=N, P=3, J=3, M=28, channels=((0, 0.0), (1, 1.0)),
                             d_over_r0=np.array([7.0, 11.0, 15.0]), border=N // 10)
     D_np = simulate_D(pr)
     D = to_dev(D_np, dev)
     a = to_dev(alpha_points(pr, 10)["perturbed"], dev)
     plan = make_plan(pr, dev)
+    # 9 rows (p, j): one row-tile block, so the automatic split count is the
+    # largest that leaves every wave a chunk of 16 pixels (8)
     assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
-                             "grad_waves": 4}
+                             "grad_waves": 4, "grad_splits": 8}
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
     for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
-                  (1, 0, 4, 8)]:
+                  (1, 0, 4, 8), (0, 1, 1, 4, 8), (0, 1, 1, 4, 1), (0, 1, 1, 4, 2),
+                  (0, 1, 1, 8, 8), (0, 1, 1, 8, 1)]:
         print(f"[tuning] N={N} {knobs}", flush=True)
         plan.set_tuning(*knobs)
         l1, g1 = plan.loss_grad(a, D, pr.gamma)
@@ -460,7 +465,7 @@ def test_launch_schedules_and_autotune(dev, N):
             assert torch.equal(l1, l0)
         else:
             assert float(((l1 - l0).abs() / l0.abs()).max()) < 1e-12
-        if knobs[3] == 4:
+        if knobs[3] == 4 and plan.tuning()["grad_splits"] == 8:
             assert torch.equal(g1, g0)
         else:
             assert float((g1 - g0).norm() / g0.norm()) < 1e-6
@@ -475,6 +480,8 @@ def test_launch_schedules_and_autotune(dev, N):
     assert max(grad_errs(grad, ref["grad"])) < GRAD_RTOL
     with pytest.raises(Exception):
         plan.set_tuning(0, 1, 3, 4)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 4, 3)
     plan.close()
 
 
