@@ -58,7 +58,36 @@ struct LossArgs {
   const float* gamma;      // [K][N][N/2+1] or null
   float gamma_scalar;
   const float* weights;    // [C][J] or null (= 1)
+  const int* supp;         // [K][N/2+1] spectral support of each object (plan table)
 };
+
+// Spectral support of an object.  A channel's OTF is the autocorrelation of
+// its pupil, so it vanishes outside the pupil's difference set; supp[k][kx]
+// is the largest |ky| (ky taken in (-N/2, N/2]) at which any channel of
+// object k can have a nonzero OTF in column kx of the half spectrum (-1:
+// none).  Outside it the Wiener object is zero, the residual is D and G =
+// -2 w conj(O) R vanishes, so the object kernel needs no S and the adjoint
+// no D, S or O there.
+__device__ __forceinline__ bool in_support(int ky, int n, int fmax) {
+  return (ky <= n / 2 ? ky : n - ky) <= fmax;
+}
+
+// Raw buffer view of `bytes` bytes at `base` (gfx9 descriptor, 32-bit
+// elements): a load at an offset at or beyond `bytes` returns zero without
+// a memory access, which skips the spectrum outside the support without a
+// branch.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+typedef unsigned int mfbd_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int mfbd_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 buffer_load_f2(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// 16 bytes with the nontemporal hint (data read once per launch)
+__device__ __forceinline__ float4 buffer_load_f4_stream(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2));
+}
 
 // Smoothness prior constants per object.
 struct PriorTab {

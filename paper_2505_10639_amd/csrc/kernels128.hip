@@ -133,25 +133,32 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
   // four waves load: spectral lane sl = lane & 127 takes m in [0,32) on the
   // lower half of the workgroup and m in [32,64) on the upper half, which
   // passes its values on through LDS.
+  // Zero outside the object's spectral support, where D, S and O are not
+  // read.
   float2 G[64];
   {
     const int upper = lane >> 7, sl = lane & 127;
-    const float2* Su = S + (size_t)u * kUnitF2;
-    const float2* Du = la.D + (size_t)u * kUnitF2;
-    const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
+    constexpr int kOut = kUnitF2 * 8;
+    const __amdgpu_buffer_rsrc_t rS = raw_buffer(S + (size_t)u * kUnitF2, kOut),
+                                 rD = raw_buffer(la.D + (size_t)u * kUnitF2, kOut),
+                                 rO = raw_buffer(O + ((size_t)p * K + k) * kUnitF2, kOut);
+    const int fm = la.supp[k * HC + (sl >> 1)];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
-      const int idx = sl_index(sl, i + 32 * upper);
-      const float2 o = Ok[idx];
-      G[i] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+      const int m = i + 32 * upper;
+      const int off = in_support(2 * m + (sl & 1), N, fm) ? sl_index(sl, m) * 8 : kOut;
+      const float2 o = buffer_load_f2(rO, off);
+      G[i] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+                    w2);
     }
     if (upper) {
 #pragma unroll
       for (int i = 0; i < 32; ++i) T[sl * 33 + i] = G[i];
     } else {
-      const int idx = sl_index64(sl);
-      const float2 o = Ok[idx];
-      Taux[sl] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+      const int off = in_support(sl, N, la.supp[k * HC + 64]) ? sl_index64(sl) * 8 : kOut;
+      const float2 o = buffer_load_f2(rO, off);
+      Taux[sl] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+                        w2);
     }
   }
   sync();

@@ -142,20 +142,25 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
   float2 y[32];
   build_pupil(Ac, phu, lane, y);
 
-  // G = -2 w conj(O) (D - O S) in spectral layout
+  // G = -2 w conj(O) (D - O S) in spectral layout; zero outside the
+  // object's spectral support, where D, S and O are not read
+  constexpr int kOut = kUnitF2 * 8;
+  const __amdgpu_buffer_rsrc_t rD = raw_buffer(Du, kOut), rS = raw_buffer(Su, kOut),
+                               rO = raw_buffer(Ok, kOut);
+  const int fm = la.supp[k * HC + (lane >> 1)];
   float2 G[32];
 #pragma unroll
   for (int m = 0; m < 32; ++m) {
-    const int idx = sl_index(lane, m);
-    const float2 o = Ok[idx];
-    const float2 r = csub(Du[idx], cmul(o, Su[idx]));
+    const int off = in_support(2 * m + (lane & 1), N, fm) ? sl_index(lane, m) * 8 : kOut;
+    const float2 o = buffer_load_f2(rO, off);
+    const float2 r = csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)));
     G[m] = cscale(cmul(cconj(o), r), w2);
   }
   float2 g32;
   {
-    const int idx = sl_index32(lane);
-    const float2 o = Ok[idx];
-    const float2 r = csub(Du[idx], cmul(o, Su[idx]));
+    const int off = in_support(lane, N, la.supp[k * HC + 32]) ? sl_index32(lane) * 8 : kOut;
+    const float2 o = buffer_load_f2(rO, off);
+    const float2 r = csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)));
     g32 = cscale(cmul(cconj(o), r), w2);
   }
   op3_gather(g32, Taux, lane);

@@ -123,18 +123,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
   float2 G[48];
   if (on) {
-    const float2* Su = S + (size_t)u * kUnitF2;
-    const float2* Du = la.D + (size_t)u * kUnitF2;
-    const float2* Ok = O + ((size_t)p * K + k) * kUnitF2;
+    // zero outside the object's spectral support, where D, S and O are not read
+    constexpr int kOut = kUnitF2 * 8;
+    const __amdgpu_buffer_rsrc_t rS = raw_buffer(S + (size_t)u * kUnitF2, kOut),
+                                 rD = raw_buffer(la.D + (size_t)u * kUnitF2, kOut),
+                                 rO = raw_buffer(O + ((size_t)p * K + k) * kUnitF2, kOut);
+    const int fm = la.supp[k * HC + (lane >> 1)];
 #pragma unroll
     for (int m = 0; m < 48; ++m) {
-      const int idx = sl_index(lane, m);
-      const float2 o = Ok[idx];
-      G[m] = cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2);
+      const int off = in_support(2 * m + (lane & 1), N, fm) ? sl_index(lane, m) * 8 : kOut;
+      const float2 o = buffer_load_f2(rO, off);
+      G[m] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+                    w2);
     }
-    const int idx = sl_index48(lane);
-    const float2 o = Ok[idx];
-    op3_gather(cscale(cmul(cconj(o), csub(Du[idx], cmul(o, Su[idx]))), w2), Taux, lane);
+    const int off = in_support(lane, N, la.supp[k * HC + 48]) ? sl_index48(lane) * 8 : kOut;
+    const float2 o = buffer_load_f2(rO, off);
+    op3_gather(cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+                      w2),
+               Taux, lane);
   }
   sync();
   if (on) op3_cols(G, Taux, T, lane);

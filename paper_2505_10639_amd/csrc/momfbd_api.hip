@@ -42,6 +42,7 @@ struct momfbd_plan_s {
   int Mp = 0;              // M rounded up to a multiple of 16
   float* thetat = nullptr; // [C][N/2][N/2]    diversity in turns
   int* hflag = nullptr;    // pinned host word for the solver's "still searching" count
+  int* supp = nullptr;     // [K][N/2+1] spectral support of each object (see LossArgs)
 };
 
 namespace {
@@ -238,6 +239,33 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
               (float)((double)basis[((size_t)c * M + m) * N * N + src] / kTwoPi);
       }
   }
+  // Spectral support of each object: a channel's OTF is nonzero only at
+  // differences of two pupil pixels (its autocorrelation).  Each pair of
+  // band rows contributes the differences between their column spans (the
+  // span of a row with gaps covers more than its pixels, so the result may
+  // exceed the support, never miss part of it); column kx keeps the largest
+  // |row difference| that reaches it, the two signs of a difference giving
+  // the same |kx| and |ky|.
+  std::vector<int> hS((size_t)K * (B + 1), -1);
+  for (int c = 0; c < C; ++c) {
+    std::vector<int> lo(B, B), hi(B, -1);
+    for (int n = 0; n < B; ++n)
+      for (int qx = 0; qx < B; ++qx)
+        if (hA[(size_t)c * BP + (size_t)n * B + qx] != 0.f) {
+          lo[n] = std::min(lo[n], qx);
+          hi[n] = std::max(hi[n], qx);
+        }
+    int* Fk = hS.data() + (size_t)desc->channel_object[c] * (B + 1);
+    for (int y1 = 0; y1 < B; ++y1) {
+      if (hi[y1] < 0) continue;
+      for (int y2 = 0; y2 < B; ++y2) {
+        if (hi[y2] < 0) continue;
+        const int ady = std::abs(y2 - y1);
+        for (int dx = lo[y2] - hi[y1]; dx <= hi[y2] - lo[y1]; ++dx)
+          Fk[std::abs(dx)] = std::max(Fk[std::abs(dx)], ady);
+      }
+    }
+  }
   // one basis for all channels when their band-sampled bases agree bit for bit
   bool shared = true;
   for (int c = 1; c < C && shared; ++c)
@@ -259,6 +287,9 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
             hipMalloc(&pl->Zt, hZp.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->ZtT, hZT.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->supp, hS.size() * sizeof(int)) == hipSuccess &&
+            hipMemcpy(pl->supp, hS.data(), hS.size() * sizeof(int), hipMemcpyHostToDevice) ==
+                hipSuccess &&
             hipMemcpy(pl->ZtT, hZT.data(), hZT.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->Ab, hA.data(), hA.size() * sizeof(float), hipMemcpyHostToDevice) ==
@@ -282,6 +313,7 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   if (plan->Zt) (void)hipFree(plan->Zt);
   if (plan->thetat) (void)hipFree(plan->thetat);
   if (plan->ZtT) (void)hipFree(plan->ZtT);
+  if (plan->supp) (void)hipFree(plan->supp);
   if (plan->hflag) (void)hipHostFree(plan->hflag);
   delete plan;
   return MOMFBD_OK;
@@ -373,7 +405,7 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
                       float gamma_scalar, const float* weights, const int* active, double* loss,
                       void* ws, hipStream_t s, Workspace* wout) {
   const Workspace w = carve_workspace(plan->d, ws);
-  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
+  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
   hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
     return launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
   });
@@ -396,7 +428,7 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
   Workspace w;
   int st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, active, loss, ws, s, &w);
   if (st || !grad) return st;
-  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights};
+  LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
   hipError_t e = prof_launch(plan, KK_ADJOINT, s, [&] {
     return launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
   });

@@ -63,10 +63,17 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
       a.nr[i] = a.ni[i] = a.e[i] = 0.0;
       a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
     }
+    // outside the object's spectral support every S of the pair is zero:
+    // it is not read (N = 0, Q = gamma, O = 0, loss term E)
+    const bool sup = in_support(f / HC, NN, la.supp[k * HC + f % HC]) ||
+                     in_support((f + 1) / HC, NN, la.supp[k * HC + (f + 1) % HC]);
     for (int ci = c0; ci < c1; ++ci) {
       const int c = ct.obj_chans[ci];
       const float4* Dc = reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
-      const float4* Sc = reinterpret_cast<const float4*>(S + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+      const int s_bytes = J * kUnitF2 * 8;
+      const __amdgpu_buffer_rsrc_t rS = raw_buffer(S + ((size_t)(p * C + c) * J) * kUnitF2, s_bytes);
+      const int s_off = sup ? f * 8 : s_bytes;
+      constexpr int kStep = kUnitF2 * 8;   // bytes between frames
       const float* wc = la.weights ? la.weights + c * J : nullptr;
       int j = 0;
       for (; j + 6 <= J; j += 6) {
@@ -74,14 +81,14 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
           d[u] = stream_load(Dc + (size_t)(j + u) * (kUnitF2 / 2));
-          s[u] = stream_load(Sc + (size_t)(j + u) * (kUnitF2 / 2));
+          s[u] = buffer_load_f4_stream(rS, sup ? s_off + (j + u) * kStep : s_bytes);
         }
 #pragma unroll
         for (int u = 0; u < 6; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
       }
       for (; j < J; ++j)
         acc_unit(a, wc ? (double)wc[j] : 1.0, stream_load(Dc + (size_t)j * (kUnitF2 / 2)),
-                 stream_load(Sc + (size_t)j * (kUnitF2 / 2)));
+                 buffer_load_f4_stream(rS, sup ? s_off + j * kStep : s_bytes));
     }
     const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
     const float4 o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
