@@ -55,22 +55,22 @@ def unit_flops(N):
 # reports null) and looked up by the value of the launch-schedule knob that
 # changes the kernel's traffic.
 KERNEL_SOURCES = {
-    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h"],
-    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h"],
-    "object": ["object.hip"],
+    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    "object": ["object.hip", "internal.h"],
 }
-COPY_FETCH_SCALE = 1.999774640366233    # 256 MiB copy: FETCH_SIZE read 131086.8 KiB
+COPY_FETCH_SCALE = 1.9997759116462532   # 256 MiB copy: FETCH_SIZE read 131086.7 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per kernel: the knob and, per value of it, (HBM bytes read, written) per
 # launch
 COUNTED_TRAFFIC = {
-    "adjoint": {"sources_sha1": "ba0585355526", "knob": "xcd_adjoint",
-                "by_value": {1: (1024491843, 94470144), 0: (1342813539, 94470144)}},
-    "forward": {"sources_sha1": "ba0585355526", "knob": "xcd_forward",
-                "by_value": {0: (94960243, 395098456), 1: (94963762, 392324672)}},
-    "object": {"sources_sha1": "5fb361e02b19", "knob": "object_pairs_per_thread",
-               "by_value": {1: (779371192, 32783368), 2: (779371211, 32668168),
-                            4: (779371595, 32597664)}},
+    "adjoint": {"sources_sha1": "6dba66d06fdc", "knob": "xcd_adjoint",
+                "by_value": {1: (895640757, 94470144), 0: (1094377784, 94470144)}},
+    "forward": {"sources_sha1": "6dba66d06fdc", "knob": "xcd_forward",
+                "by_value": {0: (94960911, 395077648), 1: (94965774, 392464936)}},
+    "object": {"sources_sha1": "df21f0b06269", "knob": "object_pairs_per_thread",
+               "by_value": {1: (729196151, 32782479), 2: (729196817, 32666432),
+                            4: (729196305, 32597464)}},
 }
 
 
@@ -131,6 +131,8 @@ def build_full_field(dev):
     pert = torch.from_numpy((0.3 * rng.standard_normal((P, J, M))).astype(np.float32)).to(dev)
     alpha = (alpha_true + pert).contiguous()
     torch.cuda.synchronize()
+    g = dict(g, channel_object=[int(k) for k in pr.channel_object],
+             support_frac=support_fraction(pr.pupil, pr.channel_object, N))
     return plan, D, alpha, g["gamma"], g
 
 
@@ -166,6 +168,8 @@ def build_large(dev):
     alpha = (alpha_true + pert).contiguous()
     gamma = plan.smoothness_gamma([g["gamma"]] * g["K"], [g["smooth"]] * g["K"])
     torch.cuda.synchronize()
+    g = dict(g, channel_object=[int(k) for k in pr.channel_object],
+             support_frac=support_fraction(pr.pupil, pr.channel_object, N))
     return plan, D, alpha, gamma, g
 
 
@@ -224,26 +228,51 @@ def time_steps(plan, D, alpha, gamma, steps, warmup, tune=True, reps=10):
     return ms, b2b, isolated, loss, grad
 
 
-def kernel_io_bytes(N, P, K, units, D_bytes):
-    """Bytes each kernel's inputs and outputs occupy in HBM, each read or
-    written once: the data and OTF half spectra (D_bytes each), the object
-    spectra, and phi and dL/dphi on the (N/2)^2 pupil band (FP32).  Of
-    these only D is algorithmic for the path as a whole; S, O, phi and
-    dL/dphi cross HBM because the path is split into kernels."""
-    band = (N // 2) ** 2 * 4 * units
-    obj = P * K * N * (N // 2 + 1) * 8
-    return {"adjoint": 2 * D_bytes + obj + 2 * band,   # reads D, S, O, phi; writes dL/dphi
-            "forward": band + D_bytes,                 # reads phi; writes S
-            "object": 2 * D_bytes + obj}               # reads D, S; writes O
+def support_fraction(pupils, channel_object, N):
+    """Fraction of the half spectrum inside each object's spectral support,
+    by the library's rule: the differences between the column spans of every
+    pair of pupil rows; column kx keeps the largest |row difference| that
+    reaches it."""
+    K = int(max(channel_object)) + 1
+    F = -np.ones((K, N // 2 + 1), dtype=np.int64)
+    for c, A in enumerate(pupils):
+        rows = [(y, np.flatnonzero(A[y])) for y in range(N) if np.any(A[y])]
+        for y1, x1 in rows:
+            for y2, x2 in rows:
+                lo, hi = x2.min() - x1.max(), x2.max() - x1.min()
+                dx = np.abs(np.arange(lo, hi + 1))
+                dx = dx[dx <= N // 2]
+                np.maximum.at(F[channel_object[c]], dx, abs(y2 - y1))
+    ky = np.arange(N)
+    aky = np.minimum(ky, N - ky)[:, None]
+    return [float(np.mean(aky <= F[k][None, :])) for k in range(K)]
+
+
+def kernel_io_bytes(N, P, J, channel_object, frac):
+    """HBM bytes each kernel must read and write once per launch: the data
+    and OTF half spectra and the object spectra within each object's
+    spectral support (`frac`, the loads beyond it return zero without a
+    memory access), the OTFs and objects written in full, and phi and
+    dL/dphi on the (N/2)^2 pupil band (FP32)."""
+    unit = N * (N // 2 + 1) * 8
+    band = (N // 2) ** 2 * 4
+    C = len(channel_object)
+    K = int(max(channel_object)) + 1
+    units = P * C * J
+    spec_in = sum(P * J * unit * frac[channel_object[c]] for c in range(C))   # D or S
+    obj_in = sum(P * unit * frac[k] for k in range(K))
+    return {"adjoint": 2 * spec_in + obj_in + 2 * units * band,   # reads D, S, O, phi; writes dL/dphi
+            "forward": units * band + units * unit,             # reads phi; writes S
+            "object": units * unit + spec_in + P * K * unit}    # reads D, S; writes O
 
 
 def roofline(kern_avg, units, N, io_bytes, traffic_of):
     """Roofline object of the dominant (longest) kernel.  A transform kernel
     is priced by its nominal FFT flops against the FP32 vector peak (the path
     reads only D from HBM, 43.6 flop/B at N = 64, above the 19.7 flop/B
-    ridge); hbm_view gives the same launch's input and output bytes against
-    the HBM peak.  The object kernel has no transform flops and is priced by
-    its bytes against HBM."""
+    ridge); hbm_view gives the bytes the same launch must read and write
+    against the HBM peak.  The object kernel has no transform flops and is
+    priced by its bytes against HBM."""
     _, per_kernel = unit_flops(N)
     dom = max(kern_avg, key=kern_avg.get)
     t = kern_avg[dom] * 1e-3
@@ -525,9 +554,9 @@ def main():
     log(f"timing {args.steps} steps after {args.warmup} warm-up")
     ms, kern_avg, kern_iso, _, _ = time_steps(plan, D, alpha, gamma, args.steps, args.warmup,
                                               not args.no_tune)
-    D_bytes = D.numel() * 8
     sched = plan.tuning()
-    roof = roofline(kern_avg, units, N, kernel_io_bytes(N, P, g["K"], units, D_bytes),
+    roof = roofline(kern_avg, units, N, kernel_io_bytes(N, P, J, g["channel_object"],
+                                                        g["support_frac"]),
                     lambda k: counted_traffic(k, sched))
     flop_unit, _ = unit_flops(N)
     step_tflops = flop_unit * units / (ms * 1e-3) / 1e12
@@ -576,8 +605,8 @@ def main():
             "ms_per_step": ms4, "steps": steps4, "units_per_step": units4,
             "step_nominal_fft_tflops": t4, "step_frac_of_fp32_peak": t4 / PEAK_FP32_VECTOR_TFLOPS,
             "roofline": roofline(kern4, units4, g4["N"],
-                                 kernel_io_bytes(g4["N"], g4["P"], g4["K"], units4,
-                                                 D4.numel() * 8), lambda k: None),
+                                 kernel_io_bytes(g4["N"], g4["P"], g4["J"], g4["channel_object"],
+                                                 g4["support_frac"]), lambda k: None),
             "launch_schedule": plan4.tuning(),
             "kernels_avg_ms": kern4,
             "kernels_avg_ms_isolated": kern4_iso,

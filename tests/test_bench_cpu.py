@@ -6,9 +6,12 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
 
 
 @pytest.fixture(scope="module")
@@ -39,13 +42,17 @@ def test_counted_traffic_stale_source(bench, monkeypatch):
 
 
 def test_roofline_alu_and_hbm(bench):
-    N, P, K, units = 64, 10, 2, 240
+    N, P, J, units = 64, 10, 12, 240
+    chan_obj, frac = [0, 1], [0.5, 0.25]
     _, per_kernel = bench.unit_flops(N)
-    D_bytes = units * N * (N // 2 + 1) * 8
-    nb = bench.kernel_io_bytes(N, P, K, units, D_bytes)
-    # adjoint: D, S and O read, phi read and dL/dphi written on the 32 x 32 band
-    assert nb["adjoint"] == 2 * D_bytes + P * K * N * 33 * 8 + 2 * units * 1024 * 4
-    assert nb["forward"] == units * 1024 * 4 + D_bytes
+    unit = N * 33 * 8
+    nb = bench.kernel_io_bytes(N, P, J, chan_obj, frac)
+    # adjoint: D, S (one channel per object here) and O within the support,
+    # phi read and dL/dphi written on the 32 x 32 band
+    spec_in = P * J * unit * (0.5 + 0.25)
+    assert nb["adjoint"] == pytest.approx(2 * spec_in + P * unit * 0.75 + 2 * units * 1024 * 4)
+    assert nb["forward"] == units * 1024 * 4 + units * unit
+    assert nb["object"] == pytest.approx(units * unit + spec_in + P * 2 * unit)
     r = bench.roofline({"adjoint": 2.0, "forward": 1.0}, units, N, nb, lambda k: 123)
     assert r["kernel"] == "adjoint" and r["bound"] == "alu" and r["traffic"] == 123
     assert r["achieved"] == pytest.approx(per_kernel["adjoint"] * units / 2e-3 / 1e12)
@@ -56,6 +63,26 @@ def test_roofline_alu_and_hbm(bench):
     r = bench.roofline({"object": 4.0, "adjoint": 1.0}, units, N, nb, lambda k: None)
     assert r["bound"] == "hbm" and r["traffic"] is None and "hbm_view" not in r
     assert r["achieved"] == pytest.approx(nb["object"] / 4e-3 / 1e9)
+
+
+def test_support_fraction(bench):
+    """The bench's support rule against the exact OTF support (where the
+    pupil autocorrelation is nonzero): equal for a disk, a superset for two
+    separate sub-apertures."""
+    import synth
+    N = 64
+    y, x = np.mgrid[0:N, 0:N]
+    two = (((y - 31) ** 2 + (x - 23) ** 2 <= 25) | ((y - 33) ** 2 + (x - 41) ** 2 <= 25))
+    for A, exact_match in ((synth.pupil_mask(N, 0.45) > 0, True), (two, False)):
+        ac = np.real(np.fft.ifft2(np.abs(np.fft.fft2(A.astype(float))) ** 2))
+        exact = float(np.mean(ac[:, : N // 2 + 1] > 0.5))
+        f = bench.support_fraction([A], [0], N)[0]
+        assert f >= exact
+        if exact_match:
+            assert f == pytest.approx(exact)
+    # the 0.45 N disk: 62.4% of the half spectrum
+    assert bench.support_fraction([synth.pupil_mask(N, 0.45) > 0], [0], N)[0] == \
+        pytest.approx(1317 / 2112)
 
 
 def test_fft_flop_count(bench):
