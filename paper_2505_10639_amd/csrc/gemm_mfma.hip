@@ -188,8 +188,13 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
                                                     float* __restrict__ phi) {
-  extern __shared__ float al[];    // [kCols][Mp + 4]
-  const int ldm = Mp + 4;
+  // The coefficient tile is stored mode-major, al[m][col] with row stride
+  // ldc = kCols + 4: a B operand element (k, j) of lane (i16 = j, g) is
+  // al[(kk + 4g + s) ldc + 16t + i16], and with 4 ldc = 16 (mod 64) the 64
+  // lanes of each read fall on distinct banks.  (Column-major rows of
+  // Mp + 4 floats, read as float4, gave 4-way conflicts.)
+  extern __shared__ float al[];    // [Mp][kCols + 4]
+  constexpr int ldc = kCols + 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
   const int c = blockIdx.x >> 2, quarter = blockIdx.x & 3;
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
   const float* src = alpha + (size_t)col0 * M;
   for (int r = wave; r < kCols; r += 4)
     for (int m = lane; m < Mp; m += 64)
-      al[r * ldm + m] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
+      al[m * ldc + r] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
   __syncthreads();
   const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
   for (int tile = 0; tile < ntile; ++tile) {
@@ -211,8 +216,8 @@ __global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc,
       const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
 #pragma unroll
       for (int t = 0; t < kColTiles; ++t) {
-        const floatx4 b4 =
-            *reinterpret_cast<const floatx4*>(al + (t * 16 + i16) * ldm + kk + 4 * g);
+        const float* bp4 = al + (kk + 4 * g) * ldc + t * 16 + i16;
+        const floatx4 b4 = {bp4[0], bp4[ldc], bp4[2 * ldc], bp4[3 * ldc]};
         acc[t] = mfma4(a4, b4, acc[t]);
       }
     }
@@ -306,7 +311,7 @@ hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int
                         const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
   dim3 grid(zc * 4, (R + kCols - 1) / kCols);
-  const size_t lds = (size_t)kCols * (Mp + 4) * sizeof(float);
+  const size_t lds = (size_t)Mp * (kCols + 4) * sizeof(float);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
