@@ -111,3 +111,16 @@ def test_calls_reject_null_plan_and_workspace(L):
     assert L.momfbd_plan_autotune(None, None, None, None, 1e-3, None, 1, None, None, None, None,
                                   None) == -1
     assert L.momfbd_profile_repeat(None, b"adjoint", 4) == -1
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes structures of the binding list the header's fields in the
+    same order (the library reads them by position)."""
+    from paper_2505_10639_amd import _lib
+    text = open(HEADER).read()
+    for cname in ("momfbd_tuning", "momfbd_desc"):
+        body = re.search(r"typedef struct\s*\{((?:(?!typedef struct).)*?)\}\s*" + cname + r"\s*;",
+                         text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"(\w+)\s*;", body)
+        assert [f for f, _ in getattr(_lib, cname)._fields_] == fields, cname
