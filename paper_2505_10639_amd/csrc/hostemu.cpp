@@ -49,7 +49,8 @@ void r2c(Wave& w, const float* img, float2 (&X)[64][32], float2 (&x32)[64]) {
     op2_rows(se, so, w.T, l);
   }
   for (int l = 0; l < 64; ++l) op2_cols(w.T, w.Taux, l, X[l]);
-  for (int l = 0; l < 64; ++l) x32[l] = op2_spread(w.Taux, l);
+  for (int l = 0; l < 64; ++l) x32[l] = op2_unpack(w.Taux, w.T, l);
+  for (int l = 0; l < 64; ++l) op2_collect(w.T, l, X[l]);
 }
 
 void c2r(Wave& w, float2 (&X)[64][32], const float2 (&x32)[64], float* img) {
@@ -273,7 +274,8 @@ void r2c(WG& w, const float (&s)[L][64], float2 (&X)[128][64], float2 (&x64)[128
   for (int l = 0; l < L; ++l) n128::xget(Xf, l, other[l]);
   for (int l = 0; l < L; ++l) n128::op2_rows_finish(keep[l], other[l], w.T, l);
   for (int l = 0; l < 128; ++l) n128::op2_cols(w.T, w.Taux, l, X[l]);
-  for (int l = 0; l < 128; ++l) x64[l] = w.Taux[l];
+  for (int l = 0; l < 128; ++l) x64[l] = n128::op2_unpack(w.Taux, w.T, l);
+  for (int l = 0; l < 128; ++l) n128::op2_collect(w.T, l, X[l]);
 }
 
 void c2r(WG& w, float2 (&X)[128][64], const float2 (&x64)[128], float (&g)[L][64]) {
@@ -384,7 +386,8 @@ void r2c(WG& w, const float* img, float2 (&X)[L][48], float2 (&x48)[L]) {
     n96::op2_rows(se, so, w.T, l);
   }
   for (int l = 0; l < L; ++l) n96::op2_cols(w.T, w.Taux, l, X[l]);
-  for (int l = 0; l < L; ++l) x48[l] = n96::op2_spread(w.Taux, l);
+  for (int l = 0; l < L; ++l) x48[l] = n96::op2_unpack(w.Taux, w.T, l);
+  for (int l = 0; l < L; ++l) n96::op2_collect(w.T, l, X[l]);
 }
 
 void c2r(WG& w, float2 (&X)[L][48], const float2 (&x48)[L], float* img) {

@@ -69,7 +69,9 @@ __device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* ps
   sync();
   if (lane < 128) op2_cols(T, Taux, lane, X);
   sync();
-  if (lane < 128) x64 = Taux[lane];
+  if (lane < 128) x64 = op2_unpack(Taux, T, lane);
+  sync();
+  if (lane < 128) op2_collect(T, lane, X);
 }
 
 template <bool WANT_PSF>
@@ -271,8 +273,10 @@ __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J
   sync();
   if (lane < 128) op2_cols(T, Taux, lane, X);
   sync();
+  if (lane < 128) x64 = op2_unpack(Taux, T, lane);
+  sync();
   if (lane < 128) {
-    x64 = Taux[lane];
+    op2_collect(T, lane, X);
     float2* out = D + (size_t)u * kUnitF2;
 #pragma unroll
     for (int m = 0; m < 64; ++m) out[sl_index(lane, m)] = X[m];

@@ -106,7 +106,9 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
   float2 X[32];
   op2_cols(T, Taux, lane, X);
   wave_sync();
-  float2 x32 = op2_spread(Taux, lane);
+  const float2 x32 = op2_unpack(Taux, T, lane);
+  wave_sync();
+  op2_collect(T, lane, X);
   float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
   for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];
@@ -233,7 +235,9 @@ __global__ __launch_bounds__(64) void k_prepare64(int units, int C, int J, int H
   float2 X[32];
   op2_cols(T, Taux, lane, X);
   wave_sync();
-  float2 x32 = op2_spread(Taux, lane);
+  const float2 x32 = op2_unpack(Taux, T, lane);
+  wave_sync();
+  op2_collect(T, lane, X);
   float2* out = D + (size_t)u * kUnitF2;
 #pragma unroll
   for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];

@@ -91,11 +91,15 @@ __global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, Chan
   float2 X[48];
   if (on) op2_cols(T, Taux, lane, X);
   sync();
+  float2 x48;
+  if (on) x48 = op2_unpack(Taux, T, lane);
+  sync();
   if (on) {
+    op2_collect(T, lane, X);
     float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
     for (int m = 0; m < 48; ++m) out[sl_index(lane, m)] = X[m];
-    out[sl_index48(lane)] = op2_spread(Taux, lane);
+    out[sl_index48(lane)] = x48;
   }
 }
 
@@ -221,11 +225,15 @@ __global__ __launch_bounds__(kThreads) void k_prepare96(int units, int C, int J,
   float2 X[48];
   if (on) op2_cols(T, Taux, lane, X);
   sync();
+  float2 x48;
+  if (on) x48 = op2_unpack(Taux, T, lane);
+  sync();
   if (on) {
+    op2_collect(T, lane, X);
     float2* out = D + (size_t)u * kUnitF2;
 #pragma unroll
     for (int m = 0; m < 48; ++m) out[sl_index(lane, m)] = X[m];
-    out[sl_index48(lane)] = op2_spread(Taux, lane);
+    out[sl_index48(lane)] = x48;
   }
 }
 

@@ -148,8 +148,8 @@ MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32],
   }
 }
 
-// Column pass (lanes < 128): X[m] = S(2m + b, q), m in [0,64); q = 0 unpacks
-// the real columns 0 and 64 and leaves column 64 in Taux[ky].
+// Column pass (lanes < 128): X[m] = S(2m + b, q), m in [0,64), for q >= 1;
+// q = 0 holds the packed real columns 0 and 64 (see op2_unpack).
 MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[64]) {
   const int q = lane >> 1, b = lane & 1;
   const float sb = b ? -1.0f : 1.0f;
@@ -165,33 +165,26 @@ MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[64])
     });
   }
   fft64<-1>(X);
+  // column 0 packs the real columns kx = 0 and 64 (F = S0 + i S64, both
+  // Hermitian in ky): left in Taux[ky] for op2_unpack
   if (q == 0) {
-    // F = S0 + i S64 with S0, S64 Hermitian in ky; -ky has the same parity,
-    // element m pairs with (64 - m) mod 64 (b = 0) or 63 - m (b = 1).  Each
-    // pair is unpacked in place.
-    auto unpack = [&](auto MA, auto MB) {
-      constexpr int ma = decltype(MA)::value, mb = decltype(MB)::value;
-      const float2 fa = X[ma], fb = X[mb];
-      const float2 ca = cconj(fb), cb = cconj(fa);
-      const float2 da = csub(fa, ca), db = csub(fb, cb);
-      X[ma] = cscale(cadd(fa, ca), 0.5f);
-      Taux[2 * ma + b] = make_float2(0.5f * da.y, -0.5f * da.x);
-      if constexpr (ma != mb) {
-        X[mb] = cscale(cadd(fb, cb), 0.5f);
-        Taux[2 * mb + b] = make_float2(0.5f * db.y, -0.5f * db.x);
-      }
-    };
-    if (b == 0) {
-      static_for<0, 33>([&](auto I) {
-        constexpr int m = decltype(I)::value;
-        unpack(std::integral_constant<int, m>{}, std::integral_constant<int, (64 - m) & 63>{});
-      });
-    } else {
-      static_for<0, 32>([&](auto I) {
-        constexpr int m = decltype(I)::value;
-        unpack(std::integral_constant<int, m>{}, std::integral_constant<int, 63 - m>{});
-      });
-    }
+    static_for<0, 64>([&](auto I) { Taux[2 * decltype(I)::value + b] = X[decltype(I)::value]; });
+  }
+}
+
+// After a barrier, lane ky < 128 unpacks row ky: returns S(ky, 64) and leaves
+// S(ky, 0) in T[ky] (the column pass has read T).
+MFBD_HDI float2 op2_unpack(const float2* Taux, float2* T, int lane) {
+  const float2 f = Taux[lane], c = cconj(Taux[(128 - lane) & 127]);
+  const float2 d = csub(f, c);
+  T[lane] = cscale(cadd(f, c), 0.5f);
+  return make_float2(0.5f * d.y, -0.5f * d.x);
+}
+
+// After another barrier, the lanes of column 0 take X[m] = S(2m+b, 0).
+MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[64]) {
+  if ((lane >> 1) == 0) {
+    static_for<0, 64>([&](auto I) { X[decltype(I)::value] = T[2 * decltype(I)::value + (lane & 1)]; });
   }
 }
 

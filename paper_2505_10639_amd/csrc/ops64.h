@@ -100,8 +100,10 @@ MFBD_HDI void op2_rows(const float (&se)[32], const float (&so)[32], float2* T, 
   });
 }
 
-// Column pass.  Output of lane (q,b): X[m] = S(2m+b, q) (q = 0: column 0),
-// and x32 = S(lane, 32) after op2_spread.
+// Column pass.  Output of lane (q,b): X[m] = S(2m+b, q) for q >= 1.  The
+// lanes of q = 0 hold the packed column F = S0 + i S32 (S0, S32 the real
+// columns kx = 0 and 32, each Hermitian in ky) and leave it in Taux[ky] for
+// op2_unpack.
 MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[32]) {
   const int q = lane >> 1, b = lane & 1;
   const float sb = b ? -1.0f : 1.0f;
@@ -118,23 +120,26 @@ MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[32])
   }
   fft32<-1>(X);
   if (q == 0) {
-    // unpack the two real columns: F = S0 + i S32 with S0, S32 Hermitian in ky;
-    // -ky has the same parity: element m pairs with m' = 32-m (b=0) or 31-m (b=1)
-    float2 F[32];
-    static_for<0, 32>([&](auto I) { F[decltype(I)::value] = X[decltype(I)::value]; });
-    static_for<0, 32>([&](auto I) {
-      constexpr int m = decltype(I)::value;
-      constexpr int m0 = (32 - m) & 31, m1 = 31 - m;
-      float2 c = cconj(b ? F[m1] : F[m0]);
-      float2 s0 = cscale(cadd(F[m], c), 0.5f);
-      float2 d = csub(F[m], c);
-      X[m] = s0;
-      Taux[2 * m + b] = make_float2(0.5f * d.y, -0.5f * d.x);   // S(2m+b, 32)
-    });
+    static_for<0, 32>([&](auto I) { Taux[2 * decltype(I)::value + b] = X[decltype(I)::value]; });
   }
 }
 
-MFBD_HDI float2 op2_spread(const float2* Taux, int lane) { return Taux[lane]; }
+// After a barrier, every lane unpacks one row, ky = lane:
+//   S0(ky) = (F(ky) + conj F(-ky)) / 2,  S32(ky) = (F(ky) - conj F(-ky)) / (2i).
+// Returns S(ky, 32) and leaves S(ky, 0) in T[ky] (the column pass has read T).
+MFBD_HDI float2 op2_unpack(const float2* Taux, float2* T, int lane) {
+  const float2 f = Taux[lane], c = cconj(Taux[(64 - lane) & 63]);
+  const float2 d = csub(f, c);
+  T[lane] = cscale(cadd(f, c), 0.5f);
+  return make_float2(0.5f * d.y, -0.5f * d.x);
+}
+
+// After another barrier, the lanes of column 0 take X[m] = S(2m+b, 0).
+MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[32]) {
+  if ((lane >> 1) == 0) {
+    static_for<0, 32>([&](auto I) { X[decltype(I)::value] = T[2 * decltype(I)::value + (lane & 1)]; });
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Op 3: inverse 2-D DFT of a Hermitian half spectrum in spectral layout ->

@@ -156,7 +156,8 @@ MFBD_HDI void op2_rows(const float (&se)[48], const float (&so)[48], float2* T, 
   });
 }
 
-// Column pass.  Output of lane (q,b): X[m] = S(2m+b, q); Taux gets S(., 48).
+// Column pass.  Output of lane (q,b): X[m] = S(2m+b, q) for q >= 1; q = 0
+// holds the packed real columns 0 and 48 (see op2_unpack).
 MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[48]) {
   const int q = lane >> 1, b = lane & 1;
   const float sb = b ? -1.0f : 1.0f;
@@ -172,23 +173,28 @@ MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[48])
     });
   }
   fft48<-1>(X);
+  // column 0 packs the real columns kx = 0 and 48 (F = S0 + i S48, both
+  // Hermitian in ky): left in Taux[ky] for op2_unpack
   if (q == 0) {
-    // unpack the real columns kx = 0 and 48 (both Hermitian in ky); -ky has
-    // the same parity: element m pairs with (48 - m) mod 48 (b=0) or 47 - m (b=1)
-    float2 F[48];
-    static_for<0, 48>([&](auto I) { F[decltype(I)::value] = X[decltype(I)::value]; });
-    static_for<0, 48>([&](auto I) {
-      constexpr int m = decltype(I)::value;
-      constexpr int m0 = (48 - m) % 48, m1 = 47 - m;
-      const float2 c = cconj(b ? F[m1] : F[m0]);
-      const float2 d = csub(F[m], c);
-      X[m] = cscale(cadd(F[m], c), 0.5f);
-      Taux[2 * m + b] = make_float2(0.5f * d.y, -0.5f * d.x);   // S(2m+b, 48)
-    });
+    static_for<0, 48>([&](auto I) { Taux[2 * decltype(I)::value + b] = X[decltype(I)::value]; });
   }
 }
 
-MFBD_HDI float2 op2_spread(const float2* Taux, int lane) { return Taux[lane]; }
+// After a barrier, lane ky < 96 unpacks row ky: returns S(ky, 48) and leaves
+// S(ky, 0) in T[ky] (the column pass has read T).
+MFBD_HDI float2 op2_unpack(const float2* Taux, float2* T, int lane) {
+  const float2 f = Taux[lane], c = cconj(Taux[(96 - lane) % 96]);
+  const float2 d = csub(f, c);
+  T[lane] = cscale(cadd(f, c), 0.5f);
+  return make_float2(0.5f * d.y, -0.5f * d.x);
+}
+
+// After another barrier, the lanes of column 0 take X[m] = S(2m+b, 0).
+MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[48]) {
+  if ((lane >> 1) == 0) {
+    static_for<0, 48>([&](auto I) { X[decltype(I)::value] = T[2 * decltype(I)::value + (lane & 1)]; });
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Op 3: inverse 2-D DFT of a Hermitian half spectrum (SL) -> real image rows.
