@@ -53,6 +53,27 @@ void r2c(Wave& w, const float* img, float2 (&X)[64][32], float2 (&x32)[64]) {
   for (int l = 0; l < 64; ++l) op2_collect(w.T, l, X[l]);
 }
 
+// the same transform through the half-size buffer (the forward kernel's form)
+void r2c_half(Wave& w, const float* img, float2 (&X)[64][32], float2 (&x32)[64]) {
+  static float2 v[64][32];
+  float* Tf = reinterpret_cast<float*>(w.T);
+  for (int l = 0; l < 64; ++l) {
+    float se[32], so[32];
+    for (int n = 0; n < 32; ++n) {
+      se[n] = img[l * 64 + 2 * n];
+      so[n] = img[l * 64 + 2 * n + 1];
+    }
+    op2_rows_values(se, so, v[l]);
+  }
+  for (int l = 0; l < 64; ++l) op2_rows_put<0>(v[l], Tf, l);
+  for (int l = 0; l < 64; ++l) op2_cols_get<0>(Tf, l, X[l]);
+  for (int l = 0; l < 64; ++l) op2_rows_put<1>(v[l], Tf, l);
+  for (int l = 0; l < 64; ++l) op2_cols_get<1>(Tf, l, X[l]);
+  for (int l = 0; l < 64; ++l) op2_cols_finish(X[l], w.Taux, l);
+  for (int l = 0; l < 64; ++l) x32[l] = op2_unpack(w.Taux, w.T, l);
+  for (int l = 0; l < 64; ++l) op2_collect(w.T, l, X[l]);
+}
+
 void c2r(Wave& w, float2 (&X)[64][32], const float2 (&x32)[64], float* img) {
   for (int l = 0; l < 64; ++l) op3_gather(x32[l], w.Taux, l);
   for (int l = 0; l < 64; ++l) op3_cols(X[l], w.Taux, w.T, l);
@@ -87,6 +108,26 @@ void pupil_to_p(Wave& w, const float* A, const float* ph, float2 (&pe)[64][32],
   for (int l = 0; l < 64; ++l) op1_rows(w.T, l, pe[l], po[l]);
 }
 
+// the same through the half-size buffer (the forward kernel's form)
+void pupil_to_p_half(Wave& w, const float* A, const float* ph, float2 (&pe)[64][32],
+                     float2 (&po)[64][32]) {
+  static float2 y[64][32];
+  float* Tf = reinterpret_cast<float*>(w.T);
+  for (int l = 0; l < 64; ++l) {
+    const int q = l >> 1, b = l & 1;
+    for (int n = 0; n < 32; ++n) {
+      const double ang = 2.0 * M_PI * ((double)ph[n * 32 + q] + (b ? (16 + n) / 64.0 : 0.0));
+      const float a = A[n * 32 + q];
+      y[l][n] = make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang));
+    }
+    fft32<+1>(y[l]);
+  }
+  for (int l = 0; l < 64; ++l) op1_cols_put<0>(y[l], Tf, l);
+  for (int l = 0; l < 64; ++l) op1_rows_get0(Tf, l, pe[l]);
+  for (int l = 0; l < 64; ++l) op1_cols_put<1>(y[l], Tf, l);
+  for (int l = 0; l < 64; ++l) op1_rows_get1(Tf, l, pe[l], po[l]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -112,6 +153,27 @@ void emu_r2c(const float* img, float* half) {
   static float2 X[64][32], x32[64];
   r2c(w, img, X, x32);
   store_sl(half, X, x32);
+}
+
+// the same through the half-size buffer
+void emu_r2c_half(const float* img, float* half) {
+  static Wave w;
+  static float2 X[64][32], x32[64];
+  r2c_half(w, img, X, x32);
+  store_sl(half, X, x32);
+}
+
+// band pupil -> complex amplitude p through the half-size buffer
+void emu_pupil_ifft_half(const float* A, const float* ph, float* p) {
+  static Wave w;
+  static float2 pe[64][32], po[64][32];
+  pupil_to_p_half(w, A, ph, pe, po);
+  float2* o = reinterpret_cast<float2*>(p);
+  for (int l = 0; l < 64; ++l)
+    for (int n = 0; n < 32; ++n) {
+      o[l * 64 + 2 * n] = pe[l][n];
+      o[l * 64 + 2 * n + 1] = po[l][n];
+    }
 }
 
 // Hermitian half spectrum [64][33] -> real image (unnormalised inverse)

@@ -65,6 +65,9 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const f
   }
 }
 
+// The two transposes go through a half-size buffer (real parts, then
+// imaginary parts): 9.2 KB of LDS per wave lets a CU hold the 12 waves its
+// registers allow, against 9 with the full-size buffer.
 template <bool WANT_PSF>
 __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct, int C, int J,
                                                   const int* __restrict__ active,
@@ -72,20 +75,27 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
                                                   const float* __restrict__ phi,
                                                   float* __restrict__ psf,
                                                   float2* __restrict__ S) {
-  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Th[LDS_HALF / 2];
   __shared__ float2 Taux[LDS_AUX];
+  float* Tf = reinterpret_cast<float*>(Th);
   const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
   if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
-  float2 y[32];
-  build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, y);
-  op1_cols(y, T, lane);
-  wave_sync();
   float2 pe[32], po[32];
-  op1_rows(T, lane, pe, po);
+  {
+    float2 y[32];
+    build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, y);
+    fft32<+1>(y);
+    op1_cols_put<0>(y, Tf, lane);
+    wave_sync();
+    op1_rows_get0(Tf, lane, pe);
+    wave_sync();
+    op1_cols_put<1>(y, Tf, lane);
+  }
   wave_sync();
+  op1_rows_get1(Tf, lane, pe, po);
   const float kap = ct.kappa[c];
   float se[32], so[32];
 #pragma unroll
@@ -101,14 +111,22 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
       row[2 * n + 1] = so[n];
     }
   }
-  op2_rows(se, so, T, lane);
+  float2 v[32];
+  op2_rows_values(se, so, v);
+  wave_sync();
+  op2_rows_put<0>(v, Tf, lane);
   wave_sync();
   float2 X[32];
-  op2_cols(T, Taux, lane, X);
+  op2_cols_get<0>(Tf, lane, X);
   wave_sync();
-  const float2 x32 = op2_unpack(Taux, T, lane);
+  op2_rows_put<1>(v, Tf, lane);
   wave_sync();
-  op2_collect(T, lane, X);
+  op2_cols_get<1>(Tf, lane, X);
+  op2_cols_finish(X, Taux, lane);
+  wave_sync();
+  const float2 x32 = op2_unpack(Taux, Th, lane);
+  wave_sync();
+  op2_collect(Th, lane, X);
   float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
   for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];

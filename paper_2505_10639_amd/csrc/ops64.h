@@ -142,6 +142,100 @@ MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[32]) {
 }
 
 // ---------------------------------------------------------------------------
+// Half-buffer form of ops 1 and 2 (the forward kernel).  The two transposes
+// move the real parts, then the imaginary parts, through a float buffer of
+// half the size, so that a CU's LDS holds the workgroups of all the waves
+// its registers allow (12 instead of 9).  Same arithmetic as op1_cols /
+// op1_rows / op2_rows / op2_cols; a barrier separates every put from the
+// get that reads it, and every get from the next put.
+// ---------------------------------------------------------------------------
+constexpr int LDS_HALF = 64 * T2 + 64;   // floats (>= 32 * T1; its first 64 float2 serve op2_unpack)
+
+// part P (0: real, 1: imaginary) of the op1 column output; y after fft32<+1>
+template <int P>
+MFBD_HDI void op1_cols_put(const float2 (&y)[32], float* Tf, int lane) {
+  const int q = lane >> 1, b = lane & 1;
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    const float v = P ? y[m].y : y[m].x;
+    Tf[q * T1 + 2 * m + b] = (m & 1) ? -v : v;
+  });
+}
+
+MFBD_HDI void op1_rows_get0(const float* Tf, int lane, float2 (&pe)[32]) {
+  static_for<0, 32>([&](auto Q) { pe[decltype(Q)::value].x = Tf[decltype(Q)::value * T1 + lane]; });
+}
+
+// imaginary parts, then as op1_rows: pe[m] = p(r, 2m), po[m] = p(r, 2m+1)
+MFBD_HDI void op1_rows_get1(const float* Tf, int lane, float2 (&pe)[32], float2 (&po)[32]) {
+  static_for<0, 32>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    pe[q].y = Tf[q * T1 + lane];
+    po[q] = twmul<+1, 64, 16 + q>(pe[q]);
+  });
+  fft32<+1>(pe);
+  fft32<+1>(po);
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    if constexpr (m & 1) {
+      pe[m] = cneg(pe[m]);
+      po[m] = cneg(po[m]);
+    }
+  });
+}
+
+// the values op2_rows writes: v[k] for k in [0,32), v[0] packing columns 0 and 32
+MFBD_HDI void op2_rows_values(const float (&se)[32], const float (&so)[32], float2 (&v)[32]) {
+  float2 z[32];
+  static_for<0, 32>([&](auto I) { z[decltype(I)::value] = make_float2(se[decltype(I)::value],
+                                                                     so[decltype(I)::value]); });
+  fft32<-1>(z);
+  v[0] = make_float2(z[0].x + z[0].y, z[0].x - z[0].y);
+  static_for<1, 32>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    float2 a = z[k], c = cconj(z[32 - k]);
+    float2 se_k = cscale(cadd(a, c), 0.5f);
+    float2 d = csub(a, c);
+    float2 so_k = make_float2(0.5f * d.y, -0.5f * d.x);
+    v[k] = cadd(se_k, twmul<-1, 64, k>(so_k));
+  });
+}
+
+template <int P>
+MFBD_HDI void op2_rows_put(const float2 (&v)[32], float* Tf, int lane) {
+  static_for<0, 32>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    Tf[lane * T2 + k] = P ? v[k].y : v[k].x;
+  });
+}
+
+template <int P>
+MFBD_HDI void op2_cols_get(const float* Tf, int lane, float2 (&X)[32]) {
+  const int q = lane >> 1;
+  const float sb = (lane & 1) ? -1.0f : 1.0f;
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    const float v = Tf[n * T2 + q] + sb * Tf[(n + 32) * T2 + q];
+    if (P) X[n].y = v; else X[n].x = v;
+  });
+}
+
+// rest of op2_cols: odd-row twiddles, the column FFT, column 0 packed in Taux
+MFBD_HDI void op2_cols_finish(float2 (&X)[32], float2* Taux, int lane) {
+  const int q = lane >> 1, b = lane & 1;
+  if (b) {
+    static_for<1, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      X[n] = twmul<-1, 64, n>(X[n]);
+    });
+  }
+  fft32<-1>(X);
+  if (q == 0) {
+    static_for<0, 32>([&](auto I) { Taux[2 * decltype(I)::value + b] = X[decltype(I)::value]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Op 3: inverse 2-D DFT of a Hermitian half spectrum in spectral layout ->
 // real image in row layout: g(r) = sum_{u in N x N} G(u) exp(+2 pi i u.r/64).
 // ---------------------------------------------------------------------------
