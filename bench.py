@@ -59,18 +59,18 @@ KERNEL_SOURCES = {
     "forward": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
     "object": ["object.hip", "internal.h"],
 }
-COPY_FETCH_SCALE = 1.999779407674642   # 256 MiB copy: FETCH_SIZE read 131086.5 KiB
+COPY_FETCH_SCALE = 1.9997752760060412   # 256 MiB copy: FETCH_SIZE read 131086.7 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per kernel: the knob and, per value of it, (HBM bytes read, written) per
 # launch
 COUNTED_TRAFFIC = {
-    "adjoint": {"sources_sha1": "d46904172268", "knob": "xcd_adjoint",
-                "by_value": {1: (895555037, 94470144), 0: (1094349876, 94470144)}},
-    "forward": {"sources_sha1": "d46904172268", "knob": "xcd_forward",
-                "by_value": {0: (94928089, 395101624), 1: (94930072, 393051792)}},
+    "adjoint": {"sources_sha1": "922edbab14c9", "knob": "xcd_adjoint",
+                "by_value": {1: (895543300, 94470144), 0: (1094344991, 94470144)}},
+    "forward": {"sources_sha1": "922edbab14c9", "knob": "xcd_forward",
+                "by_value": {0: (94931348, 395025512), 1: (94927317, 393121584)}},
     "object": {"sources_sha1": "df21f0b06269", "knob": "object_pairs_per_thread",
-               "by_value": {1: (729197496, 32782503), 2: (729198087, 32666088),
-                            4: (729197547, 32597328)}},
+               "by_value": {1: (729195622, 32782523), 2: (729197129, 32666568),
+                            4: (729196009, 32597352)}},
 }
 
 
