@@ -15,7 +15,8 @@ from .fields import object_field, gaussian_noise
 from .configs import (Problem, make_problem, config0, config1_geometry,
                       config1_alpha, config1_object, config1_problem,
                       config1_d_over_r0, config4_geometry, config4_template,
-                      config4_alpha, config4_objects, patch_grid, SEED_ROOT)
+                      config4_alpha, config4_objects, config4_problem, patch_grid,
+                      SEED_ROOT)
 
 __all__ = [
     "noll_to_nm", "zernike_basis", "pupil_mask", "pupil_radius_px", "hann_window",
@@ -24,5 +25,6 @@ __all__ = [
     "gaussian_noise", "Problem", "make_problem", "config0", "config1_geometry",
     "config1_alpha", "config1_object", "config1_problem", "config1_d_over_r0",
     "config4_geometry", "config4_template", "config4_alpha", "config4_objects",
+    "config4_problem",
     "patch_grid", "SEED_ROOT",
 ]

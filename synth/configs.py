@@ -220,3 +220,35 @@ def config4_objects() -> np.ndarray:
     rng = _streams(4)[0]
     return np.stack([object_field(rng, g["H"], g["W"]).astype(np.float32)
                      for _ in range(g["K"])])
+
+
+def config4_problem(patches) -> Problem:
+    """Large multi-object workload restricted to ``patches`` (indices).
+
+    Each patch's four scenes are its cuts of the four 2048^2 fields; its
+    coefficients are its rows of ``config4_alpha``.  Noise is drawn per
+    patch from a stream keyed by the patch index, so any subset is
+    reproducible on its own.
+    """
+    g = config4_geometry()
+    N = g["N"]
+    sel = np.asarray(patches)
+    scenes = config4_objects()
+    ys, xs = patch_grid(g["H"], g["W"], N, g["stride"])
+    objs = np.empty((len(sel), g["K"], N, N))
+    for i, p in enumerate(sel):
+        y0, x0 = ys[p // g["nx"]], xs[p % g["nx"]]
+        objs[i] = scenes[:, y0:y0 + N, x0:x0 + N]
+    base = config4_template()
+    noise = np.empty((len(sel), g["C"], g["J"], N, N), np.float32)
+    for i, p in enumerate(sel):
+        rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 4, 7, int(p)]))
+        noise[i] = gaussian_noise(rng, (g["C"], g["J"], N, N), 0.01)
+    base.P, base.J = len(sel), g["J"]
+    base.alpha_true = config4_alpha()[sel]
+    base.objects = objs
+    base.noise = noise
+    base.weights = np.ones((g["C"], g["J"]), np.float32)
+    base.d_over_r0 = np.full(len(sel), g["d_over_r0"])
+    base.meta.update(patches=sel, key=4)
+    return base

@@ -219,6 +219,48 @@ def test_config1_full_size_sampled_patches(dev):
     check_patchwise(pr_all, D, alphas, dev, patches=sample)
 
 
+def test_config4_full_size_sampled_patches(dev):
+    """Large multi-object workload at full size: 961 patches of 128x128, four
+    objects at four wavelengths, 24 frames, 150 modes and the smoothness
+    prior.  The launch schedule is the autotuned one the benchmark times;
+    outputs are compared on sampled patches.
+
+    Patches are independent, so only the sampled patches need the oracle's
+    simulated data; the others hold seeded random spectra that fill the
+    launch and are not compared."""
+    from paper_2505_10639_amd import Plan
+    sample = [0, 31, 517, 960]
+    g = synth.config4_geometry()
+    N, P, C, J = g["N"], g["P"], g["C"], g["J"]
+    pr = synth.config4_problem(sample)
+    D_s = simulate_D(pr)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_ROOT + 41)
+    D = float(np.sqrt(np.mean(np.abs(D_s) ** 2))) * torch.randn(
+        (P, C, J, N, N // 2 + 1), dtype=torch.complex64, generator=gen, device=dev)
+    D[sample] = to_dev(D_s, dev)
+    rng = np.random.default_rng(48)
+    a_all = synth.config4_alpha()
+    a_all += (0.3 * rng.standard_normal(a_all.shape)).astype(np.float32)
+    alpha = to_dev(a_all, dev)
+    plan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, dev)
+    g0, lam = [g["gamma"]] * g["K"], [g["smooth"]] * g["K"]
+    g_dev = plan.smoothness_gamma(g0, lam)
+    print(f"[config4] P={P} C={C} J={J} M={g['M']}: autotune", flush=True)
+    plan.autotune(alpha, D, g_dev, None, reps=1)
+    print(f"[config4] schedule {plan.tuning()}", flush=True)
+    loss, grad = plan.loss_grad(alpha, D, g_dev)
+    torch.cuda.synchronize()
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    assert np.all(np.isfinite(loss)) and np.all(np.isfinite(grad))
+    ref = oracle.evaluate(a_all[sample], D_s, pr.basis, pr.diversity, pr.pupil,
+                          pr.channel_object, oracle.smoothness_gamma(N, g0, lam))
+    lrel = np.abs(loss[sample] - ref["loss"]) / np.abs(ref["loss"])
+    assert np.all(lrel < LOSS_RTOL), lrel.max()
+    assert max(grad_errs(grad[sample], ref["grad"])) < GRAD_RTOL
+    plan.close()
+
+
 def test_lbfgs_first_step_matches_oracle_and_converges(dev):
     """Per-patch L-BFGS: the first iteration takes the same step as the
     reference solver; the loss never increases; after 150 iterations every
