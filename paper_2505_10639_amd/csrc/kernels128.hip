@@ -91,7 +91,9 @@ __global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, Cha
   const int c = (u / J) % C;
   {
     float2 z[32];
+    __builtin_amdgcn_s_setprio(2);
     build_pupil(Ab + (size_t)c * kBP, phi + (size_t)u * kBP, lane, z);
+    __builtin_amdgcn_s_setprio(0);
     op1_cols(z, T, lane);
   }
   sync();
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
   // Zero outside the object's spectral support, where D, S and O are not
   // read.
   float2 G[64];
+  __builtin_amdgcn_s_setprio(2);
   {
     const int upper = lane >> 7, sl = lane & 127;
     constexpr int kOut = kUnitF2 * 8;
@@ -163,6 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
                         w2);
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   sync();
   if (lane < 128) {
 #pragma unroll

@@ -86,7 +86,11 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
   float2 pe[32], po[32];
   {
     float2 y[32];
+    // a wave that is issuing its loads runs at raised priority, so that
+    // they go out ahead of the transform work of the waves beside it
+    __builtin_amdgcn_s_setprio(2);
     build_pupil(Ab + c * kBandPix, phi + (size_t)u * kBandPix, lane, y);
+    __builtin_amdgcn_s_setprio(0);
     fft32<+1>(y);
     op1_cols_put<0>(y, Tf, lane);
     wave_sync();
@@ -159,6 +163,8 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
   const float* phu = phi + (size_t)u * kBandPix;
   // the pupil band field (recomputed below to form p) depends only on phi:
   // build it first so that its loads overlap those of G
+  // raised priority while the loads of phi, D, S and O are issued
+  __builtin_amdgcn_s_setprio(2);
   float2 y[32];
   build_pupil(Ac, phu, lane, y);
 
@@ -183,6 +189,7 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
     const float2 r = csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)));
     g32 = cscale(cmul(cconj(o), r), w2);
   }
+  __builtin_amdgcn_s_setprio(0);
   op3_gather(g32, Taux, lane);
   wave_sync();
   op3_cols(G, Taux, T, lane);

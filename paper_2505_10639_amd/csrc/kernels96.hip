@@ -62,7 +62,9 @@ __global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, Chan
   const int c = (u / J) % C;
   if (on) {
     float2 y[48];
+    __builtin_amdgcn_s_setprio(2);
     build_pupil(Ab + c * kBP, phi + (size_t)u * kBP, lane, y);
+    __builtin_amdgcn_s_setprio(0);
     op1_cols(y, T, lane);
   }
   sync();
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int k = ct.chan_obj[c];
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
   float2 G[48];
+  __builtin_amdgcn_s_setprio(2);
   if (on) {
     // zero outside the object's spectral support, where D, S and O are not read
     constexpr int kOut = kUnitF2 * 8;
@@ -146,6 +149,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                       w2),
                Taux, lane);
   }
+  __builtin_amdgcn_s_setprio(0);
   sync();
   if (on) op3_cols(G, Taux, T, lane);
   sync();
