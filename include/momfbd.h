@@ -373,9 +373,11 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
 int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
 /* Choose the schedules by timing: one knob at a time, every candidate value
  * is timed over `reps` loss+gradient evaluations of the caller's data (HIP
- * events on `stream`, which this call synchronises) and the fastest kept;
- * the first candidate of each knob is the library default, and another
- * value replaces the best so far only when at least 1% faster.
+ * events on `stream`, which this call synchronises), in three interleaved
+ * rounds; each candidate keeps its fastest round, and the fastest
+ * candidate is kept.  The first candidate of each knob is the library
+ * default, and another value replaces the best so far only when at least
+ * 1% faster.
  * loss [P] and grad [P][J][M] (device) receive the last evaluation.  The
  * choice is stored in the plan and, if `chosen` is not NULL, returned.
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */

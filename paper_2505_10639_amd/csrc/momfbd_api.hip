@@ -680,12 +680,16 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       return MOMFBD_EDEVICE;
     return MOMFBD_OK;
   };
-  // The first value of each knob is the library default; another value
-  // replaces the best so far only when at least 1% faster, so that timing
-  // noise between near-equal schedules does not decide (the XCD-grouped
-  // orders read less from HBM at equal speed).
+  // Every candidate of a knob is timed once per round, the rounds
+  // interleaved, and keeps its fastest round: a clock that is still rising,
+  // or a transient slowdown, then favours no candidate.  The first value of
+  // each knob is the library default; another value replaces the best so
+  // far only when at least 1% faster, so that timing noise between
+  // near-equal schedules does not decide (the XCD-grouped orders read less
+  // from HBM at equal speed).
   // The gradient's split count starts from the automatic one for the
   // chosen gradient waves; the others follow in increasing order.
+  constexpr int kRounds = 3;
   int* knobs[5] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves,
                    &plan->d.grad_splits};
   std::vector<int> values[5] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}, {}};
@@ -697,20 +701,24 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       for (int v = 1; v <= kMaxGradSplits; v *= 2)
         if (v != a) values[4].push_back(v);
     }
-    int best = *knobs[k];
-    float best_ms = 0.f;
-    bool first = true;
-    for (int v : values[k]) {
-      *knobs[k] = v;
-      float ms = 0.f;
-      if ((st = timed(&ms))) break;
-      if (first || ms < 0.99f * best_ms) {
-        best_ms = ms;
-        best = v;
-        first = false;
+    const int keep = *knobs[k];
+    std::vector<float> fastest(values[k].size(), 0.f);
+    for (int r = 0; r < kRounds && st == MOMFBD_OK; ++r) {
+      for (size_t i = 0; i < values[k].size(); ++i) {
+        *knobs[k] = values[k][i];
+        float ms = 0.f;
+        if ((st = timed(&ms))) break;
+        if (r == 0 || ms < fastest[i]) fastest[i] = ms;
       }
     }
-    *knobs[k] = best;
+    if (st) {
+      *knobs[k] = keep;
+      break;
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < values[k].size(); ++i)
+      if (fastest[i] < 0.99f * fastest[best]) best = i;
+    *knobs[k] = values[k][best];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
