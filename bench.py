@@ -64,13 +64,13 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per kernel: the knob and, per value of it, (HBM bytes read, written) per
 # launch
 COUNTED_TRAFFIC = {
-    "adjoint": {"sources_sha1": "17247c43f5fe", "knob": "xcd_adjoint",
-                "by_value": {1: (895413202, 94470144), 0: (1094470129, 94470144)}},
-    "forward": {"sources_sha1": "17247c43f5fe", "knob": "xcd_forward",
-                "by_value": {0: (94883034, 399098456), 1: (94886969, 397290848)}},
-    "object": {"sources_sha1": "df21f0b06269", "knob": "object_pairs_per_thread",
-               "by_value": {1: (729195622, 32782523), 2: (729197129, 32666568),
-                            4: (729196009, 32597352)}},
+    "adjoint": {"sources_sha1": "74eb310aefd5", "knob": "xcd_adjoint",
+                "by_value": {1: (895470860, 94470144), 0: (1094358814, 94470144)}},
+    "forward": {"sources_sha1": "74eb310aefd5", "knob": "xcd_forward",
+                "by_value": {0: (94882586, 400063360), 1: (94881306, 400211848)}},
+    "object": {"sources_sha1": "2f75b2c786e8", "knob": "object_pairs_per_thread",
+               "by_value": {1: (729195683, 32782515), 2: (729196555, 32666627),
+                            4: (729195742, 32597448)}},
 }
 
 

@@ -361,12 +361,18 @@ typedef struct {
   int xcd_forward;              /* 1: units of a patch-object on one XCD (L2)   */
   int xcd_adjoint;              /* same for the adjoint kernel                  */
   int object_pairs_per_thread;  /* 1, 2 or 4 frequency pairs per thread         */
-  int grad_waves;               /* gradient contraction: 4 waves x 4 row tiles, or
-                                   8 waves x 2 row tiles per workgroup          */
+  int grad_waves;               /* gradient contraction: 4 waves x 4 (or 3) row
+                                   tiles, or 8 waves x 2 row tiles per workgroup */
   int grad_splits;              /* workgroups sharing one row tile's pixel sum:
                                    1, 2, 4 or 8; 0 on input picks the smallest
                                    count that gives every CU two workgroups
                                    (get_tuning reports the count in use)      */
+  int grad_row_tiles;           /* row tiles of 16 (patch, frame) rows per
+                                   workgroup: 4 or 3 with 4 waves (3: more,
+                                   smaller workgroups, each basis chunk
+                                   serving fewer rows), 2 with 8 waves; 0 on
+                                   input is 4 or 2 (get_tuning reports the
+                                   count in use)                              */
 } momfbd_tuning;
 /* Errors: EINVAL (NULL or a value out of range). */
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);

@@ -244,6 +244,9 @@ void launch_grad_cs(const Dims& d, int zc, int splits, const float* Ztp, const f
   if (d.grad_waves == 8)
     hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, 1, CS>), dim3((R + 31) / 32, splits), dim3(512), 0,
                        s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
+  else if (grad_row_tiles_of(d) == 3)
+    hipLaunchKernelGGL((k_grad_mfma<MT, 3, 4, 2, CS>), dim3((R + 47) / 48, splits), dim3(256), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
   else
     hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, 2, CS>), dim3((R + 63) / 64, splits), dim3(256), 0,
                        s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
@@ -270,7 +273,7 @@ int grad_splits_auto(const Dims& d) {
   // run of chunks (128x128, four bases: 1.33 -> 1.03 ms at 2 splits), and
   // it costs when the runs get short (64x64: 40 us unsplit, 50 us at 4).
   const int R = d.P * d.J, W = d.grad_waves == 8 ? 8 : 4;
-  const long rows = 16L * (W == 8 ? 2 : 4);
+  const long rows = 16L * grad_row_tiles_of(d);
   const long blocks = (R + rows - 1) / rows;
   const int zc = d.zc > 0 ? d.zc : d.C;
   const int nchunk = zc * d.bandpix() / 16;
@@ -285,6 +288,8 @@ int grad_splits_auto(const Dims& d) {
 }
 
 int grad_splits_of(const Dims& d) { return d.grad_splits > 0 ? d.grad_splits : grad_splits_auto(d); }
+
+int grad_row_tiles_of(const Dims& d) { return d.grad_waves == 8 ? 2 : d.grad_rt == 3 ? 3 : 4; }
 
 hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
                        float* part, hipStream_t s) {

@@ -24,8 +24,10 @@ struct Dims {
   // launch schedules (chosen by momfbd_plan_autotune): XCD-grouped unit
   // order of the forward / adjoint grids, frequency pairs per thread of the
   // object kernel, waves per row tile of the gradient contraction and the
-  // number of blocks its pixel sum is split over (0: grad_splits_auto)
-  int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4, grad_splits = 0;
+  // number of blocks its pixel sum is split over (0: grad_splits_auto) and
+  // its row tiles per block (0: 4 with 4 waves; 3 is the other 4-wave choice;
+  // 8 waves always take 2)
+  int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4, grad_splits = 0, grad_rt = 0;
   // distinct modal bases on the band: 1 when every channel's band-sampled
   // basis is the same (the contractions then run once for all channels),
   // else C; 0 is read as C
@@ -127,6 +129,7 @@ struct Workspace {
 constexpr int kMaxGradSplits = 8;
 int grad_splits_auto(const Dims& d);
 int grad_splits_of(const Dims& d);
+int grad_row_tiles_of(const Dims& d);
 
 size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);

@@ -326,7 +326,10 @@ static bool tuning_ok(const momfbd_tuning* t) {
           t->object_pairs_per_thread == 4) &&
          (t->grad_waves == 4 || t->grad_waves == 8) &&
          (t->grad_splits == 0 || t->grad_splits == 1 || t->grad_splits == 2 ||
-          t->grad_splits == 4 || t->grad_splits == 8);
+          t->grad_splits == 4 || t->grad_splits == 8) &&
+         (t->grad_row_tiles == 0 ||
+          (t->grad_waves == 4 ? t->grad_row_tiles == 3 || t->grad_row_tiles == 4
+                              : t->grad_row_tiles == 2));
 }
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
@@ -336,6 +339,7 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   plan->d.obj_ppt = t->object_pairs_per_thread;
   plan->d.grad_waves = t->grad_waves;
   plan->d.grad_splits = t->grad_splits;
+  plan->d.grad_rt = t->grad_row_tiles == 3 ? 3 : 0;
   return MOMFBD_OK;
 }
 
@@ -346,6 +350,7 @@ int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* t) {
   t->object_pairs_per_thread = plan->d.obj_ppt;
   t->grad_waves = plan->d.grad_waves;
   t->grad_splits = grad_splits_of(plan->d);
+  t->grad_row_tiles = grad_row_tiles_of(plan->d);
   return MOMFBD_OK;
 }
 
@@ -687,19 +692,24 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // far only when at least 1% faster, so that timing noise between
   // near-equal schedules does not decide (the XCD-grouped orders read less
   // from HBM at equal speed).
-  // The gradient's split count starts from the automatic one for the
-  // chosen gradient waves; the others follow in increasing order.
+  // The gradient's row tiles (4 or 3) are a choice only with 4 waves.  Its
+  // split count starts from the automatic one for the chosen waves and row
+  // tiles; the others follow in increasing order.
   constexpr int kRounds = 3;
-  int* knobs[5] = {&plan->d.xcd_adj, &plan->d.xcd_fwd, &plan->d.obj_ppt, &plan->d.grad_waves,
-                   &plan->d.grad_splits};
-  std::vector<int> values[5] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}, {}};
-  for (int k = 0; k < 5 && st == MOMFBD_OK; ++k) {
+  int* knobs[6] = {&plan->d.xcd_adj, &plan->d.xcd_fwd,  &plan->d.obj_ppt,
+                   &plan->d.grad_waves, &plan->d.grad_rt, &plan->d.grad_splits};
+  std::vector<int> values[6] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}, {}, {}};
+  for (int k = 0; k < 6 && st == MOMFBD_OK; ++k) {
     if (k == 4) {
+      plan->d.grad_rt = 0;
+      values[4] = plan->d.grad_waves == 8 ? std::vector<int>{0} : std::vector<int>{0, 3};
+    }
+    if (k == 5) {
       plan->d.grad_splits = 0;
       const int a = grad_splits_auto(plan->d);
-      values[4] = {a};
+      values[5] = {a};
       for (int v = 1; v <= kMaxGradSplits; v *= 2)
-        if (v != a) values[4].push_back(v);
+        if (v != a) values[5].push_back(v);
     }
     const int keep = *knobs[k];
     std::vector<float> fastest(values[k].size(), 0.f);

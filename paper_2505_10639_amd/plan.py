@@ -96,10 +96,12 @@ class Plan:
         return _lib.momfbd_plan_get_tuning(self.handle)
 
     def set_tuning(self, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves,
-                   grad_splits=0):
-        """Launch schedules (see momfbd_tuning); grad_splits 0 is automatic."""
+                   grad_splits=0, grad_row_tiles=0):
+        """Launch schedules (see momfbd_tuning); grad_splits 0 is automatic,
+        grad_row_tiles 0 the default for the waves."""
         _lib.momfbd_plan_set_tuning(self.handle, xcd_forward, xcd_adjoint,
-                                    object_pairs_per_thread, grad_waves, grad_splits)
+                                    object_pairs_per_thread, grad_waves, grad_splits,
+                                    grad_row_tiles)
 
     def autotune(self, alpha, D, gamma=1e-3, weights=None, reps=5):
         """Time the launch schedules on this data and keep the fastest."""

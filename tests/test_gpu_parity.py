@@ -510,7 +510,9 @@ def test_launch_schedules_and_autotune(dev, N):
     per thread: FP64 loss; gradient waves and pixel-sum splits: FP32
     gradient).  The split counts include ones that leave waves with
     different chunk counts (N = 96: 144 chunks over 4 x 8 or 8 x 8 slices).
-    The autotuned plan still matches the oracle."""
+    Three row tiles per workgroup in place of four give the same sums bit
+    for bit (same slices, same order).  The autotuned plan still matches
+    the oracle."""
     pr = synth.make_problem(70 + N, N=N, P=3, J=3, M=28, channels=((0, 0.0), (1, 1.0)),
                             d_over_r0=np.array([7.0, 11.0, 15.0]), border=N // 10)
     D_np = simulate_D(pr)
@@ -520,11 +522,11 @@ def test_launch_schedules_and_autotune(dev, N):
     # 9 rows (p, j): one row-tile block, so the automatic split count is the
     # largest that leaves every wave a chunk of 16 pixels (8)
     assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
-                             "grad_waves": 4, "grad_splits": 8}
+                             "grad_waves": 4, "grad_splits": 8, "grad_row_tiles": 4}
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
     for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
                   (1, 0, 4, 8), (0, 1, 1, 4, 8), (0, 1, 1, 4, 1), (0, 1, 1, 4, 2),
-                  (0, 1, 1, 8, 8), (0, 1, 1, 8, 1)]:
+                  (0, 1, 1, 8, 8), (0, 1, 1, 8, 1), (0, 1, 1, 4, 8, 3), (0, 1, 1, 4, 2, 3)]:
         print(f"[tuning] N={N} {knobs}", flush=True)
         plan.set_tuning(*knobs)
         l1, g1 = plan.loss_grad(a, D, pr.gamma)
@@ -550,6 +552,10 @@ def test_launch_schedules_and_autotune(dev, N):
         plan.set_tuning(0, 1, 3, 4)
     with pytest.raises(Exception):
         plan.set_tuning(0, 1, 1, 4, 3)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 8, 0, 3)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 4, 0, 2)
     plan.close()
 
 
