@@ -35,11 +35,22 @@
  *   creation; scratch comes from the caller's workspace.  A plan and its
  *   workspace may be used by one stream at a time.
  *
+ * Workspace
+ *   Every per-call function takes the caller's workspace as a device
+ *   pointer `ws` and its length in bytes `ws_bytes`.  The pointer must be
+ *   256-byte aligned and the length at least what the size query returns
+ *   (momfbd_workspace_size, momfbd_cnn_sizes,
+ *   momfbd_power_spectrum_workspace); otherwise the call returns
+ *   MOMFBD_EWORKSPACE before anything is enqueued.  The solver calls take
+ *   their state buffer the same way (`state`, `state_bytes`, at least
+ *   momfbd_lbfgs_state_size).
+ *
  * Errors
  *   Every function returns MOMFBD_OK or a negative status.  Argument errors
- *   are detected before any work is enqueued, and outputs are then left
- *   untouched.  MOMFBD_EDEVICE reports a HIP error, including one left by an
- *   earlier asynchronous launch.  NaN or Inf in the inputs are not checked:
+ *   (including a missing, misaligned or short workspace) are detected before
+ *   any work is enqueued, and outputs are then left untouched.
+ *   MOMFBD_EDEVICE reports a HIP error, including one left by an earlier
+ *   asynchronous launch.  NaN or Inf in the inputs are not checked:
  *   they propagate into the loss of the affected patch.
  */
 #ifndef MOMFBD_H
@@ -54,7 +65,7 @@ extern "C" {
 #define MOMFBD_OK 0
 #define MOMFBD_EINVAL (-1)        /* NULL pointer, bad size, bad channel map   */
 #define MOMFBD_EUNSUPPORTED (-2)  /* patch size, mode count or pupil not supported */
-#define MOMFBD_EWORKSPACE (-3)    /* workspace missing or misaligned           */
+#define MOMFBD_EWORKSPACE (-3)    /* workspace missing, misaligned or too small */
 #define MOMFBD_EDEVICE (-4)       /* HIP error                                 */
 
 typedef struct momfbd_plan_s* momfbd_plan;
@@ -103,7 +114,7 @@ int momfbd_workspace_size(momfbd_plan plan, size_t* bytes);
  *           D = DFT(W (x - m) + m), m the mean of each patch frame.
  * Errors: EINVAL (NULL, H/W/stride inconsistent with P), EWORKSPACE, EDEVICE. */
 int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int stride,
-                        const float* apod, void* D, void* ws, void* stream);
+                        const float* apod, void* D, void* ws, size_t ws_bytes, void* stream);
 
 /* Forward model only: PSFs and/or OTFs for coefficients alpha.
  *   alpha   DEVICE float [P][J][M].
@@ -111,7 +122,7 @@ int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int
  *   otf     DEVICE complex64 [P][C][J][N][N/2+1] OTF half spectra, or NULL.
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, void* ws,
-                   void* stream);
+                   size_t ws_bytes, void* stream);
 
 /* Loss and gradient (Eqs. object_optimization and loss_momfbd).
  *   alpha        DEVICE float [P][J][M]
@@ -124,7 +135,7 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                      float gamma_scalar, const float* weights, double* loss, float* grad,
-                     void* ws, void* stream);
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Wiener object estimate in pixel space (Eq. object_optimization):
  *   obj  DEVICE float [P][K][N][N], o_k = Re IDFT(O_k) / N^2 -- the restored
@@ -132,7 +143,7 @@ int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const 
  * Other arguments as momfbd_loss_grad.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
-                           float* obj, void* ws, void* stream);
+                           float* obj, void* ws, size_t ws_bytes, void* stream);
 
 /* Object smoothness prior (Sect. "Smoothness", Eq. regularization_smoothness):
  * the penalty lambda_k ||grad o_k||^2, with periodic forward differences, added
@@ -175,7 +186,7 @@ typedef struct {
 int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
                            const momfbd_filter* filters, float* obj, float* H, void* ws,
-                           void* stream);
+                           size_t ws_bytes, void* stream);
 
 /* Mosaic of restored patches (Sect. "Division in patches and apodization"):
  * out_k(y, x) = sum_p w(y - y_p, x - x_p) o_pk(y - y_p, x - x_p) / sum_p w(.)
@@ -204,7 +215,8 @@ int momfbd_mosaic(momfbd_plan plan, const float* obj, int ny, int nx, int stride
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_power_spectrum_workspace(int L, int nbins, size_t* bytes);
 int momfbd_power_spectrum(int L, const float* image, const float* window, float* power,
-                          double* sector, int* counts, int nbins, void* ws, void* stream);
+                          double* sector, int* counts, int nbins, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* Per-patch L-BFGS solver (the quasi-Newton alternative to the paper's Adam,
  * Sect. "Optimization and paralellization"; patches are independent).
@@ -223,15 +235,18 @@ typedef struct {
 } momfbd_lbfgs_params;
 
 /* Bytes of solver state (device memory, 256-byte aligned, owned by the
- * caller) for this plan and these parameters.  Errors: EINVAL. */
+ * caller) for this plan and these parameters.  Errors: EINVAL.
+ * The solver calls below take the state with its length (`state_bytes`):
+ * a NULL or misaligned state is EINVAL, a shorter one EWORKSPACE. */
 int momfbd_lbfgs_state_size(momfbd_plan plan, const momfbd_lbfgs_params* params, size_t* bytes);
 
 /* Start a solve at alpha (DEVICE float [P][J][M]): evaluates loss and
  * gradient, clears the history.  loss (DEVICE double [P]) may be NULL.
  * Other arguments as momfbd_loss_grad.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                      const float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                      const float* weights, double* loss, void* ws, void* stream);
+                      size_t state_bytes, const float* alpha, const void* D, const float* gamma,
+                      float gamma_scalar, const float* weights, double* loss, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* One L-BFGS iteration for every patch that has not stopped.  alpha is
  * updated in place (DEVICE float [P][J][M], the same array the solve was
@@ -243,8 +258,9 @@ int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
  * searching; after each, the call synchronises `stream` to read how many
  * remain.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                      float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                      const float* weights, double* loss, int* status, void* ws, void* stream);
+                      size_t state_bytes, float* alpha, const void* D, const float* gamma,
+                      float gamma_scalar, const float* weights, double* loss, int* status,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Solver rounds without host synchronisation, for HIP graph capture.  A
  * round gives every running patch one line-search trial: a patch that is
@@ -264,9 +280,10 @@ int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
  * momfbd_lbfgs_step after rounds restarts searching patches from their
  * accepted point.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                        float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                        const float* weights, int rounds, double* loss, int* status,
-                        float* alpha_accepted, void* ws, void* stream);
+                        size_t state_bytes, float* alpha, const void* D, const float* gamma,
+                        float gamma_scalar, const float* weights, int rounds, double* loss,
+                        int* status, float* alpha_accepted, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Synthetic bursts through the forward model (Eq. generative_model):
  * per patch p, channel c, frame j the frame i = o_k * s_pcj + sigma_p n
@@ -282,7 +299,7 @@ int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, voi
  * N = 64 only (EUNSUPPORTED otherwise).  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
                       const float* sigma, const float* apod, float* frames, void* D, void* ws,
-                      void* stream);
+                      size_t ws_bytes, void* stream);
 
 /* Warm-start network: a 6-layer convolutional regressor from a burst of J
  * frames (64 x 64) to J x M modal coefficients (Noll j = 2..M+1), with
@@ -309,20 +326,23 @@ int momfbd_cnn_destroy(momfbd_cnn net);
 int momfbd_cnn_sizes(momfbd_cnn net, size_t* n_params, size_t* workspace_bytes);
 /* params = normals * He standard deviation per weight (biases 0; the last
  * layer's weights 10x smaller); normals: [n_params] device draws. */
-int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* ws, void* stream);
+int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* ws,
+                    size_t ws_bytes, void* stream);
 /* refresh the workspace's bfloat16 weights from FP32 params */
-int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, void* stream);
+int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, size_t ws_bytes,
+                    void* stream);
 /* alpha [B][J][M] float (device) predicted from D; B <= batch_max */
 int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, float* alpha,
-                       void* ws, void* stream);
+                       void* ws, size_t ws_bytes, void* stream);
 /* loss (one FP64, device) and grad [n_params] (device) for targets
  * [B][J][M] float (device) */
 int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, const float* target,
-                         int B, double* loss, float* grad, void* ws, void* stream);
+                         int B, double* loss, float* grad, void* ws, size_t ws_bytes,
+                         void* stream);
 /* one Adam step (FP32 moments m1, m2 [n_params]; step >= 1) */
 int momfbd_cnn_adam(momfbd_cnn net, float* params, const float* grad, float* m1, float* m2,
                     int step, float lr, float beta1, float beta2, float eps, void* ws,
-                    void* stream);
+                    size_t ws_bytes, void* stream);
 
 /* Kernel timing for measurement.  After momfbd_profile_start, every kernel
  * launched by this plan's calls (up to max_launches launches) is bracketed
@@ -389,7 +409,8 @@ int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
  * Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                          float gamma_scalar, const float* weights, int reps, double* loss,
-                         float* grad, void* ws, void* stream, momfbd_tuning* chosen);
+                         float* grad, void* ws, size_t ws_bytes, void* stream,
+                         momfbd_tuning* chosen);
 
 /* Sizes the plan was created with (any out pointer may be NULL). */
 int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M);

@@ -60,7 +60,7 @@ class momfbd_desc(ctypes.Structure):
 _lib = None
 _vp = ctypes.c_void_p
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
-           -3: "workspace missing or misaligned", -4: "HIP device error"}
+           -3: "workspace missing, misaligned or too small", -4: "HIP device error"}
 
 
 def lib():
@@ -75,41 +75,45 @@ def lib():
                                          ctypes.POINTER(_vp)]
         L.momfbd_plan_destroy.argtypes = [_vp]
         L.momfbd_workspace_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
-        L.momfbd_prepare_data.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, _vp]
-        L.momfbd_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
-        L.momfbd_loss_grad.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, _vp]
-        L.momfbd_object_estimate.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
+        z = ctypes.c_size_t
+        L.momfbd_prepare_data.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, z, _vp]
+        L.momfbd_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, z, _vp]
+        L.momfbd_loss_grad.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, z, _vp]
+        L.momfbd_object_estimate.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, z, _vp]
         L.momfbd_status_string.argtypes = [i]
         L.momfbd_status_string.restype = ctypes.c_char_p
         L.momfbd_plan_dims.argtypes = [_vp] + [ctypes.POINTER(i)] * 6
         L.momfbd_object_filtered.argtypes = [_vp, _vp, _vp, _vp, f, _vp,
-                                             ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, _vp]
+                                             ctypes.POINTER(momfbd_filter), _vp, _vp, _vp, z,
+                                             _vp]
         L.momfbd_mosaic.argtypes = [_vp, _vp, i, i, i, i, _vp, _vp]
-        L.momfbd_synthesize.argtypes = [_vp] * 10
+        L.momfbd_synthesize.argtypes = [_vp] * 9 + [z, _vp]
         tp = ctypes.POINTER(momfbd_tuning)
         L.momfbd_plan_set_tuning.argtypes = [_vp, tp]
         L.momfbd_plan_get_tuning.argtypes = [_vp, tp]
-        L.momfbd_plan_autotune.argtypes = [_vp, _vp, _vp, _vp, f, _vp, i, _vp, _vp, _vp, _vp, tp]
+        L.momfbd_plan_autotune.argtypes = [_vp, _vp, _vp, _vp, f, _vp, i, _vp, _vp, _vp, z, _vp,
+                                           tp]
         L.momfbd_power_spectrum_workspace.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
-        L.momfbd_power_spectrum.argtypes = [i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp]
-        L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, _vp, _vp,
-                                          _vp, f, _vp, i, _vp, _vp, _vp, _vp, _vp]
+        L.momfbd_power_spectrum.argtypes = [i, _vp, _vp, _vp, _vp, _vp, i, _vp, z, _vp]
+        L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, z, _vp,
+                                          _vp, _vp, f, _vp, i, _vp, _vp, _vp, _vp, z, _vp]
         L.momfbd_cnn_create.argtypes = [i, i, i, _vp, ctypes.POINTER(_vp)]
         L.momfbd_cnn_destroy.argtypes = [_vp]
         L.momfbd_cnn_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(ctypes.c_size_t)]
-        L.momfbd_cnn_init.argtypes = [_vp] * 5
-        L.momfbd_cnn_load.argtypes = [_vp] * 4
-        L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, _vp, _vp, _vp]
-        L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp]
-        L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, _vp]
+        L.momfbd_cnn_init.argtypes = [_vp] * 4 + [z, _vp]
+        L.momfbd_cnn_load.argtypes = [_vp] * 3 + [z, _vp]
+        L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, _vp, _vp, z, _vp]
+        L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, i, _vp, _vp, _vp, z, _vp]
+        L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, z, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
         L.momfbd_profile_repeat.argtypes = [_vp, ctypes.c_char_p, i]
         pp = ctypes.POINTER(momfbd_lbfgs_params)
         L.momfbd_lbfgs_state_size.argtypes = [_vp, pp, ctypes.POINTER(ctypes.c_size_t)]
-        L.momfbd_lbfgs_init.argtypes = [_vp, pp, _vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
-        L.momfbd_lbfgs_step.argtypes = [_vp, pp, _vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, _vp]
+        L.momfbd_lbfgs_init.argtypes = [_vp, pp, _vp, z, _vp, _vp, _vp, f, _vp, _vp, _vp, z, _vp]
+        L.momfbd_lbfgs_step.argtypes = [_vp, pp, _vp, z, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, z,
+                                        _vp]
         L.momfbd_profile_stop.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_char_p),
                                           ctypes.POINTER(d), ctypes.POINTER(i)]
         for name in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
@@ -140,6 +144,15 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return t.ctypes.data
     return t.data_ptr()
+
+
+def _nbytes(t):
+    """Length in bytes of a workspace or state buffer (tensor or ndarray); 0 for None."""
+    if t is None:
+        return 0
+    if isinstance(t, np.ndarray):
+        return int(t.nbytes)
+    return int(t.numel() * t.element_size())
 
 
 def _stream(stream, *tensors):
@@ -200,24 +213,26 @@ def momfbd_smoothness_gamma(plan, gamma0, lam, gamma, stream=None):
 
 def momfbd_prepare_data(plan, frames, H, W, stride, apod, D, ws, stream=None):
     _check(lib().momfbd_prepare_data(plan, _ptr(frames), H, W, stride, _ptr(apod), _ptr(D),
-                                     _ptr(ws), _stream(stream, frames)), "momfbd_prepare_data")
+                                     _ptr(ws), _nbytes(ws), _stream(stream, frames)),
+           "momfbd_prepare_data")
 
 
 def momfbd_forward(plan, alpha, psf, otf, ws, stream=None):
-    _check(lib().momfbd_forward(plan, _ptr(alpha), _ptr(psf), _ptr(otf), _ptr(ws),
+    _check(lib().momfbd_forward(plan, _ptr(alpha), _ptr(psf), _ptr(otf), _ptr(ws), _nbytes(ws),
                                 _stream(stream, alpha)), "momfbd_forward")
 
 
 def momfbd_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, loss, grad, ws, stream=None):
     _check(lib().momfbd_loss_grad(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
-                                  _ptr(weights), _ptr(loss), _ptr(grad), _ptr(ws),
+                                  _ptr(weights), _ptr(loss), _ptr(grad), _ptr(ws), _nbytes(ws),
                                   _stream(stream, alpha)), "momfbd_loss_grad")
 
 
 def momfbd_object_estimate(plan, alpha, D, gamma, gamma_scalar, weights, obj, ws, stream=None):
     _check(lib().momfbd_object_estimate(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
                                         float(gamma_scalar), _ptr(weights), _ptr(obj), _ptr(ws),
-                                        _stream(stream, alpha)), "momfbd_object_estimate")
+                                        _nbytes(ws), _stream(stream, alpha)),
+           "momfbd_object_estimate")
 
 
 def filter_spec(kind, f_lo=0.0, f_hi=0.0, diff_limit=0.0, noise_power=0.0):
@@ -232,7 +247,7 @@ def momfbd_object_filtered(plan, alpha, D, gamma, gamma_scalar, weights, filters
     arr = (momfbd_filter * len(filters))(*filters)
     _check(lib().momfbd_object_filtered(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
                                         float(gamma_scalar), _ptr(weights), arr, _ptr(obj),
-                                        _ptr(H), _ptr(ws), _stream(stream, alpha)),
+                                        _ptr(H), _ptr(ws), _nbytes(ws), _stream(stream, alpha)),
            "momfbd_object_filtered")
 
 
@@ -243,10 +258,11 @@ def momfbd_mosaic(plan, obj, ny, nx, stride, border, out, stream=None):
 
 def momfbd_lbfgs_rounds(plan, params, state, alpha, D, gamma, gamma_scalar, weights, rounds, loss,
                         status, alpha_accepted, ws, stream=None):
-    _check(lib().momfbd_lbfgs_rounds(plan, ctypes.byref(params), _ptr(state), _ptr(alpha),
-                                     _ptr(D), _ptr(gamma), float(gamma_scalar), _ptr(weights),
-                                     int(rounds), _ptr(loss), _ptr(status),
-                                     _ptr(alpha_accepted), _ptr(ws), _stream(stream, alpha)),
+    _check(lib().momfbd_lbfgs_rounds(plan, ctypes.byref(params), _ptr(state), _nbytes(state),
+                                     _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                                     _ptr(weights), int(rounds), _ptr(loss), _ptr(status),
+                                     _ptr(alpha_accepted), _ptr(ws), _nbytes(ws),
+                                     _stream(stream, alpha)),
            "momfbd_lbfgs_rounds")
 
 
@@ -266,7 +282,8 @@ def momfbd_power_spectrum(image, window=None, nbins=None, stream=None):
     sector = torch.empty(nb, dtype=torch.float64, device=image.device)
     counts = torch.empty(nb, dtype=torch.int32, device=image.device)
     _check(lib().momfbd_power_spectrum(L, _ptr(image), _ptr(window), _ptr(power), _ptr(sector),
-                                       _ptr(counts), nb, _ptr(ws), _stream(stream, image)),
+                                       _ptr(counts), nb, _ptr(ws), _nbytes(ws),
+                                       _stream(stream, image)),
            "momfbd_power_spectrum")
     return power, sector, counts
 
@@ -289,14 +306,14 @@ def momfbd_plan_autotune(plan, alpha, D, gamma, gamma_scalar, weights, reps, los
     t = momfbd_tuning()
     _check(lib().momfbd_plan_autotune(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
                                       _ptr(weights), int(reps), _ptr(loss), _ptr(grad), _ptr(ws),
-                                      _stream(stream, alpha), ctypes.byref(t)),
+                                      _nbytes(ws), _stream(stream, alpha), ctypes.byref(t)),
            "momfbd_plan_autotune")
     return t.as_dict()
 
 
 def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=None):
     _check(lib().momfbd_synthesize(plan, _ptr(alpha), _ptr(O), _ptr(noise), _ptr(sigma),
-                                   _ptr(apod), _ptr(frames), _ptr(D), _ptr(ws),
+                                   _ptr(apod), _ptr(frames), _ptr(D), _ptr(ws), _nbytes(ws),
                                    _stream(stream, alpha)), "momfbd_synthesize")
 
 
@@ -319,30 +336,32 @@ def momfbd_cnn_sizes(net):
 
 
 def momfbd_cnn_init(net, normals, params, ws, stream=None):
-    _check(lib().momfbd_cnn_init(net, _ptr(normals), _ptr(params), _ptr(ws),
+    _check(lib().momfbd_cnn_init(net, _ptr(normals), _ptr(params), _ptr(ws), _nbytes(ws),
                                  _stream(stream, params)), "momfbd_cnn_init")
 
 
 def momfbd_cnn_load(net, params, ws, stream=None):
-    _check(lib().momfbd_cnn_load(net, _ptr(params), _ptr(ws), _stream(stream, params)),
+    _check(lib().momfbd_cnn_load(net, _ptr(params), _ptr(ws), _nbytes(ws),
+                                 _stream(stream, params)),
            "momfbd_cnn_load")
 
 
 def momfbd_cnn_forward(net, params, D, B, alpha, ws, stream=None):
     _check(lib().momfbd_cnn_forward(net, _ptr(params), _ptr(D), int(B), _ptr(alpha), _ptr(ws),
-                                    _stream(stream, params)), "momfbd_cnn_forward")
+                                    _nbytes(ws), _stream(stream, params)), "momfbd_cnn_forward")
 
 
 def momfbd_cnn_loss_grad(net, params, D, target, B, loss, grad, ws, stream=None):
     _check(lib().momfbd_cnn_loss_grad(net, _ptr(params), _ptr(D), _ptr(target), int(B),
-                                      _ptr(loss), _ptr(grad), _ptr(ws), _stream(stream, params)),
+                                      _ptr(loss), _ptr(grad), _ptr(ws), _nbytes(ws),
+                                      _stream(stream, params)),
            "momfbd_cnn_loss_grad")
 
 
 def momfbd_cnn_adam(net, params, grad, m1, m2, step, lr, beta1, beta2, eps, ws, stream=None):
     _check(lib().momfbd_cnn_adam(net, _ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step),
                                  float(lr), float(beta1), float(beta2), float(eps), _ptr(ws),
-                                 _stream(stream, params)), "momfbd_cnn_adam")
+                                 _nbytes(ws), _stream(stream, params)), "momfbd_cnn_adam")
 
 
 def momfbd_profile_start(plan, max_launches: int):
@@ -378,14 +397,15 @@ def momfbd_lbfgs_state_size(plan, params) -> int:
 
 def momfbd_lbfgs_init(plan, params, state, alpha, D, gamma, gamma_scalar, weights, loss, ws,
                       stream=None):
-    _check(lib().momfbd_lbfgs_init(plan, ctypes.byref(params), _ptr(state), _ptr(alpha), _ptr(D),
-                                   _ptr(gamma), float(gamma_scalar), _ptr(weights), _ptr(loss),
-                                   _ptr(ws), _stream(stream, alpha)), "momfbd_lbfgs_init")
+    _check(lib().momfbd_lbfgs_init(plan, ctypes.byref(params), _ptr(state), _nbytes(state),
+                                   _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                                   _ptr(weights), _ptr(loss), _ptr(ws), _nbytes(ws),
+                                   _stream(stream, alpha)), "momfbd_lbfgs_init")
 
 
 def momfbd_lbfgs_step(plan, params, state, alpha, D, gamma, gamma_scalar, weights, loss, status,
                       ws, stream=None):
-    _check(lib().momfbd_lbfgs_step(plan, ctypes.byref(params), _ptr(state), _ptr(alpha), _ptr(D),
-                                   _ptr(gamma), float(gamma_scalar), _ptr(weights), _ptr(loss),
-                                   _ptr(status), _ptr(ws), _stream(stream, alpha)),
-           "momfbd_lbfgs_step")
+    _check(lib().momfbd_lbfgs_step(plan, ctypes.byref(params), _ptr(state), _nbytes(state),
+                                   _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                                   _ptr(weights), _ptr(loss), _ptr(status), _ptr(ws), _nbytes(ws),
+                                   _stream(stream, alpha)), "momfbd_lbfgs_step")

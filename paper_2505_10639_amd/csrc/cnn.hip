@@ -465,10 +465,19 @@ hipError_t run_forward(const momfbd_cnn_s* n, const float* params, const void* D
   return hipSuccess;
 }
 
-int check_net(const momfbd_cnn_s* n, const void* ws, int B) {
-  if (!n || !ws) return MOMFBD_EINVAL;
+// A network and a workspace that is 256-byte aligned and at least
+// momfbd_cnn_sizes' workspace_bytes long.
+int check_ws(const momfbd_cnn_s* n, const void* ws, size_t ws_bytes) {
+  if (!n) return MOMFBD_EINVAL;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < n->ws_bytes)
+    return MOMFBD_EWORKSPACE;
+  return MOMFBD_OK;
+}
+
+int check_net(const momfbd_cnn_s* n, const void* ws, size_t ws_bytes, int B) {
+  const int st = check_ws(n, ws, ws_bytes);
+  if (st) return st;
   if (B < 1 || B > n->batch_max) return MOMFBD_EINVAL;
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return MOMFBD_EWORKSPACE;
   return MOMFBD_OK;
 }
 
@@ -621,8 +630,11 @@ int momfbd_cnn_sizes(momfbd_cnn net, size_t* n_params, size_t* workspace_bytes) 
   return MOMFBD_OK;
 }
 
-int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* ws, void* stream) {
-  if (!net || !normals || !params || !ws) return MOMFBD_EINVAL;
+int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* ws,
+                    size_t ws_bytes, void* stream) {
+  const int st = check_ws(net, ws, ws_bytes);
+  if (st) return st;
+  if (!normals || !params) return MOMFBD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_init, dim3(blocks(net->n_params)), dim3(256), 0, s, net->n_params, normals,
                      net->init_std, params);
@@ -631,8 +643,11 @@ int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* w
   return status_of(hipGetLastError());
 }
 
-int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, void* stream) {
-  if (!net || !params || !ws) return MOMFBD_EINVAL;
+int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, size_t ws_bytes,
+                    void* stream) {
+  const int st = check_ws(net, ws, ws_bytes);
+  if (st) return st;
+  if (!params) return MOMFBD_EINVAL;
   hipLaunchKernelGGL(k_cast_bf16, dim3(blocks(net->n_params)), dim3(256), 0, (hipStream_t)stream,
                      net->n_params, params,
                      reinterpret_cast<uint16_t*>(static_cast<char*>(ws) + net->o_w16));
@@ -640,8 +655,8 @@ int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, void* stream)
 }
 
 int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, float* alpha,
-                       void* ws, void* stream) {
-  int st = check_net(net, ws, B);
+                       void* ws, size_t ws_bytes, void* stream) {
+  int st = check_net(net, ws, ws_bytes, B);
   if (st) return st;
   if (!params || !D || !alpha) return MOMFBD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -655,8 +670,9 @@ int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B
 }
 
 int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, const float* target,
-                         int B, double* loss, float* grad, void* ws, void* stream) {
-  int st = check_net(net, ws, B);
+                         int B, double* loss, float* grad, void* ws, size_t ws_bytes,
+                         void* stream) {
+  int st = check_net(net, ws, ws_bytes, B);
   if (st) return st;
   if (!params || !D || !target || !loss || !grad) return MOMFBD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -720,8 +736,10 @@ int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, con
 
 int momfbd_cnn_adam(momfbd_cnn net, float* params, const float* grad, float* m1, float* m2,
                     int step, float lr, float beta1, float beta2, float eps, void* ws,
-                    void* stream) {
-  if (!net || !params || !grad || !m1 || !m2 || !ws || step < 1) return MOMFBD_EINVAL;
+                    size_t ws_bytes, void* stream) {
+  const int st = check_ws(net, ws, ws_bytes);
+  if (st) return st;
+  if (!params || !grad || !m1 || !m2 || step < 1) return MOMFBD_EINVAL;
   const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(blocks(net->n_params)), dim3(256), 0, (hipStream_t)stream,
                      net->n_params, params, grad, m1, m2,

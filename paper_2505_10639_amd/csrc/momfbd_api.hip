@@ -100,10 +100,21 @@ hipError_t prof_launch(momfbd_plan plan, int kind, hipStream_t s, F&& launch) {
   return e;
 }
 
-int check_call(momfbd_plan plan, const void* ws) {
+// A plan, and a workspace that is present, 256-byte aligned and at least
+// momfbd_workspace_size bytes long; checked before anything is enqueued.
+int check_call(momfbd_plan plan, const void* ws, size_t ws_bytes) {
   if (!plan) return MOMFBD_EINVAL;
   if (!ws) return MOMFBD_EWORKSPACE;
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return MOMFBD_EWORKSPACE;
+  if (ws_bytes < workspace_bytes(plan->d)) return MOMFBD_EWORKSPACE;
+  return MOMFBD_OK;
+}
+
+// The solver state: present, 256-byte aligned and large enough.
+int check_state(const void* state, size_t state_bytes, size_t need) {
+  if (!state) return MOMFBD_EINVAL;
+  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if (state_bytes < need) return MOMFBD_EWORKSPACE;
   return MOMFBD_OK;
 }
 
@@ -164,7 +175,7 @@ const char* momfbd_status_string(int status) {
     case MOMFBD_OK: return "ok";
     case MOMFBD_EINVAL: return "invalid argument";
     case MOMFBD_EUNSUPPORTED: return "unsupported configuration";
-    case MOMFBD_EWORKSPACE: return "workspace missing or misaligned";
+    case MOMFBD_EWORKSPACE: return "workspace missing, misaligned or too small";
     case MOMFBD_EDEVICE: return "HIP device error";
     default: return "unknown status";
   }
@@ -372,8 +383,8 @@ int momfbd_workspace_size(momfbd_plan plan, size_t* bytes) {
 }
 
 int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int stride,
-                        const float* apod, void* D, void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                        const float* apod, void* D, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!frames || !apod || !D || stride < 1) return MOMFBD_EINVAL;
   const int N = plan->d.N;
@@ -388,8 +399,8 @@ int momfbd_prepare_data(momfbd_plan plan, const float* frames, int H, int W, int
 }
 
 int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, void* ws,
-                   void* stream) {
-  int st = check_call(plan, ws);
+                   size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || (!psf && !otf)) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
@@ -446,8 +457,8 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
 
 int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                      float gamma_scalar, const float* weights, double* loss, float* grad,
-                     void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                     void* ws, size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !D || !loss) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
@@ -474,8 +485,8 @@ int momfbd_smoothness_gamma(momfbd_plan plan, const float* gamma0, const float* 
 
 int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
-                           float* obj, void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                           float* obj, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !D || !obj) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
@@ -492,8 +503,8 @@ int momfbd_object_estimate(momfbd_plan plan, const float* alpha, const void* D,
 int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
                            const float* gamma, float gamma_scalar, const float* weights,
                            const momfbd_filter* filters, float* obj, float* H, void* ws,
-                           void* stream) {
-  int st = check_call(plan, ws);
+                           size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !D || !obj || !filters) return MOMFBD_EINVAL;
   FilterTab ft;
@@ -529,8 +540,8 @@ int momfbd_object_filtered(momfbd_plan plan, const float* alpha, const void* D,
 
 int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
                       const float* sigma, const float* apod, float* frames, void* D, void* ws,
-                      void* stream) {
-  int st = check_call(plan, ws);
+                      size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !O || !noise || !sigma || !apod || !frames || !D) return MOMFBD_EINVAL;
   if (plan->d.N != 64) return MOMFBD_EUNSUPPORTED;
@@ -579,15 +590,16 @@ int momfbd_lbfgs_state_size(momfbd_plan plan, const momfbd_lbfgs_params* params,
 }
 
 int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                      const float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                      const float* weights, double* loss, void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                      size_t state_bytes, const float* alpha, const void* D, const float* gamma,
+                      float gamma_scalar, const float* weights, double* loss, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
-  if (!lbfgs_params_ok(params) || !state || !alpha || !D) return MOMFBD_EINVAL;
-  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if (!lbfgs_params_ok(params) || !alpha || !D) return MOMFBD_EINVAL;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  if ((st = check_state(state, state_bytes, L.total))) return st;
   if ((st = pending_error())) return st;
   hipStream_t s = (hipStream_t)stream;
-  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
   char* b = static_cast<char*>(state);
   st = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr,
                      reinterpret_cast<double*>(b + L.ft), reinterpret_cast<float*>(b + L.g), ws, s);
@@ -596,15 +608,16 @@ int momfbd_lbfgs_init(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
 }
 
 int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                      float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                      const float* weights, double* loss, int* status, void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                      size_t state_bytes, float* alpha, const void* D, const float* gamma,
+                      float gamma_scalar, const float* weights, double* loss, int* status,
+                      void* ws, size_t ws_bytes, void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
-  if (!lbfgs_params_ok(params) || !state || !alpha || !D) return MOMFBD_EINVAL;
-  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if (!lbfgs_params_ok(params) || !alpha || !D) return MOMFBD_EINVAL;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  if ((st = check_state(state, state_bytes, L.total))) return st;
   if ((st = pending_error())) return st;
   hipStream_t s = (hipStream_t)stream;
-  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
   char* b = static_cast<char*>(state);
   const int* active = reinterpret_cast<const int*>(b + L.active);
   const int* counter = reinterpret_cast<const int*>(b + L.counter);
@@ -627,16 +640,17 @@ int momfbd_lbfgs_step(momfbd_plan plan, const momfbd_lbfgs_params* params, void*
 }
 
 int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, void* state,
-                        float* alpha, const void* D, const float* gamma, float gamma_scalar,
-                        const float* weights, int rounds, double* loss, int* status,
-                        float* alpha_accepted, void* ws, void* stream) {
-  int st = check_call(plan, ws);
+                        size_t state_bytes, float* alpha, const void* D, const float* gamma,
+                        float gamma_scalar, const float* weights, int rounds, double* loss,
+                        int* status, float* alpha_accepted, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
-  if (!lbfgs_params_ok(params) || !state || !alpha || !D || rounds < 0) return MOMFBD_EINVAL;
-  if (reinterpret_cast<uintptr_t>(state) % 256 != 0) return MOMFBD_EINVAL;
+  if (!lbfgs_params_ok(params) || !alpha || !D || rounds < 0) return MOMFBD_EINVAL;
+  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
+  if ((st = check_state(state, state_bytes, L.total))) return st;
   if ((st = pending_error())) return st;
   hipStream_t s = (hipStream_t)stream;
-  const LbfgsLayout L = lbfgs_layout(plan->d, params->m, params->max_evals);
   char* b = static_cast<char*>(state);
   const int* active = reinterpret_cast<const int*>(b + L.active);
   hipError_t e = hipSuccess;
@@ -660,8 +674,9 @@ int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, voi
 // loss+gradient evaluations on the caller's data with events on `stream`.
 int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                          float gamma_scalar, const float* weights, int reps, double* loss,
-                         float* grad, void* ws, void* stream, momfbd_tuning* chosen) {
-  int st = check_call(plan, ws);
+                         float* grad, void* ws, size_t ws_bytes, void* stream,
+                         momfbd_tuning* chosen) {
+  int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !D || !loss || !grad || reps < 1) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;

@@ -160,12 +160,13 @@ int momfbd_power_spectrum_workspace(int L, int nbins, size_t* bytes) {
 }
 
 int momfbd_power_spectrum(int L, const float* image, const float* window, float* power,
-                          double* sector, int* counts, int nbins, void* ws, void* stream) {
+                          double* sector, int* counts, int nbins, void* ws, size_t ws_bytes,
+                          void* stream) {
   size_t need = 0;
   int st = momfbd_power_spectrum_workspace(L, nbins, &need);
   if (st) return st;
-  if (!image || !power || !ws) return MOMFBD_EINVAL;
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return MOMFBD_EWORKSPACE;
+  if (!image || !power) return MOMFBD_EINVAL;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < need) return MOMFBD_EWORKSPACE;
   if (hipGetLastError() != hipSuccess) return MOMFBD_EDEVICE;
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);

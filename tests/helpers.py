@@ -10,6 +10,7 @@ import synth
 # Tolerances of the GPU path against the FP64 oracle (FP32 arithmetic):
 LOSS_RTOL = 1e-5        # relative, per patch
 GRAD_RTOL = 1e-4        # ||g_gpu - g_ref||_2 / ||g_ref||_2, per patch
+GRAD_ELEM = 1e-4        # max |g_gpu - g_ref| / max |g_ref|, per patch (every element)
 OBJ_RMS = 1e-4          # rms of the restored object difference (frame units)
 
 
@@ -77,3 +78,23 @@ def rel_err(a, b):
 
 def grad_errs(g_gpu, g_ref):
     return [rel_err(g_gpu[p], g_ref[p]) for p in range(g_ref.shape[0])]
+
+
+def grad_elem_errs(g_gpu, g_ref):
+    """Per patch: the largest element-wise gradient difference over the
+    largest reference element, so that an error confined to one mode or one
+    frame cannot hide in the norm."""
+    out = []
+    for p in range(g_ref.shape[0]):
+        r = np.asarray(g_ref[p], np.float64)
+        d = np.abs(np.asarray(g_gpu[p], np.float64) - r)
+        out.append(float(d.max() / max(np.abs(r).max(), 1e-300)))
+    return out
+
+
+def assert_grad_close(g_gpu, g_ref, what=""):
+    """Gradient parity per patch: the norm bound and the element bound."""
+    gn = grad_errs(g_gpu, g_ref)
+    ge = grad_elem_errs(g_gpu, g_ref)
+    assert max(gn) < GRAD_RTOL, (what, "norm", max(gn))
+    assert max(ge) < GRAD_ELEM, (what, "element", max(ge))

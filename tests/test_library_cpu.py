@@ -91,26 +91,86 @@ def test_plan_create_rejects_bad_arguments_without_a_device(L):
 
 
 def test_calls_reject_null_plan_and_workspace(L):
-    assert L.momfbd_loss_grad(None, None, None, None, 1e-3, None, None, None, None, None) == -1
-    assert L.momfbd_forward(None, None, None, None, None, None) == -1
-    assert L.momfbd_object_estimate(None, None, None, None, 1e-3, None, None, None, None) == -1
-    assert L.momfbd_prepare_data(None, None, 64, 64, 32, None, None, None, None) == -1
+    assert L.momfbd_loss_grad(None, None, None, None, 1e-3, None, None, None, None, 0,
+                              None) == -1
+    assert L.momfbd_forward(None, None, None, None, None, 0, None) == -1
+    assert L.momfbd_object_estimate(None, None, None, None, 1e-3, None, None, None, 0,
+                                    None) == -1
+    assert L.momfbd_prepare_data(None, None, 64, 64, 32, None, None, None, 0, None) == -1
     assert L.momfbd_plan_destroy(None) == 0
     n = ctypes.c_size_t()
     assert L.momfbd_workspace_size(None, ctypes.byref(n)) == -1
     assert L.momfbd_smoothness_gamma(None, None, None, None, None) == -1
     assert L.momfbd_mosaic(None, None, 1, 1, 1, 0, None, None) == -1
     assert L.momfbd_object_filtered(None, None, None, None, 1e-3, None, None, None, None, None,
-                                    None) == -1
+                                    0, None) == -1
     n = ctypes.c_size_t()
     assert L.momfbd_power_spectrum_workspace(100, 10, ctypes.byref(n)) == -1   # not a power of two
     assert L.momfbd_power_spectrum_workspace(64, 65, ctypes.byref(n)) == -1    # nbins > L
     assert L.momfbd_power_spectrum_workspace(64, 33, ctypes.byref(n)) == 0 and n.value > 64 * 64 * 8
     assert L.momfbd_plan_set_tuning(None, None) == -1
     assert L.momfbd_plan_get_tuning(None, None) == -1
-    assert L.momfbd_plan_autotune(None, None, None, None, 1e-3, None, 1, None, None, None, None,
-                                  None) == -1
+    assert L.momfbd_plan_autotune(None, None, None, None, 1e-3, None, 1, None, None, None, 0,
+                                  None, None) == -1
     assert L.momfbd_profile_repeat(None, b"adjoint", 4) == -1
+
+
+def _aligned(nbytes, fill):
+    """A 256-byte aligned host buffer (a stand-in pointer: the calls below
+    fail their argument checks before anything reads or writes it)."""
+    raw = np.full(nbytes + 256, fill, np.uint8)
+    off = (-raw.ctypes.data) % 256
+    return raw, raw[off:off + nbytes]
+
+
+def test_short_workspace_is_refused_before_any_work(L):
+    """A workspace one byte short of the size query (or misaligned, or
+    missing) returns EWORKSPACE, and the outputs are not written.  The power
+    spectrum needs no plan, so the check runs here without a device."""
+    Lsz, nb = 64, 33
+    n = ctypes.c_size_t()
+    assert L.momfbd_power_spectrum_workspace(Lsz, nb, ctypes.byref(n)) == 0
+    _, img = _aligned(Lsz * Lsz * 4, 0)
+    _, power = _aligned(Lsz * Lsz * 4, 0xA5)
+    _, sector = _aligned(nb * 8, 0x5A)
+    _, counts = _aligned(nb * 4, 0x3C)
+    raw_ws, ws = _aligned(n.value, 0x77)
+    ptr = lambda a: a.ctypes.data
+    st = L.momfbd_power_spectrum(Lsz, ptr(img), None, ptr(power), ptr(sector), ptr(counts), nb,
+                                 ptr(ws), n.value - 1, None)
+    assert st == -3
+    st = L.momfbd_power_spectrum(Lsz, ptr(img), None, ptr(power), ptr(sector), ptr(counts), nb,
+                                 None, n.value, None)
+    assert st == -3
+    st = L.momfbd_power_spectrum(Lsz, ptr(img), None, ptr(power), ptr(sector), ptr(counts), nb,
+                                 ptr(ws) + 8, n.value, None)
+    assert st == -3
+    assert np.all(power == 0xA5) and np.all(sector == 0x5A) and np.all(counts == 0x3C)
+    assert np.all(raw_ws == 0x77)
+
+
+def _declared_params():
+    """{function: number of parameters} of every declaration in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(?:int|const char\*)\s+(momfbd_\w+)\s*\(([^)]*)\)\s*;", text):
+        args = [a for a in m.group(2).split(",") if a.strip() and a.strip() != "void"]
+        out[m.group(1)] = len(args)
+    return out
+
+
+def test_binding_signatures_match_the_header(L):
+    """Every function the binding declares takes as many arguments as the
+    header gives it (a missing size_t would shift every later argument)."""
+    decl = _declared_params()
+    checked = 0
+    for name, nparams in decl.items():
+        fn = getattr(L, name)
+        if fn.argtypes is None:
+            continue
+        assert len(fn.argtypes) == nparams, (name, len(fn.argtypes), nparams)
+        checked += 1
+    assert checked >= 30
 
 
 def test_binding_structs_match_the_header():

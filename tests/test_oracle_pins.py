@@ -385,6 +385,82 @@ def test_common_tilt_and_even_flip_invariances():
     np.testing.assert_allclose(r1["grad"], F * g, atol=1e-9 * np.abs(g).max())
 
 
+def test_two_objects_decompose_into_single_object_problems():
+    """Objects share no accumulator (Eq. object_optimization is per object):
+    with two objects, each seen through its own channel, the loss and the
+    gradient (the coefficients are shared) are the sums of those of the two
+    one-object problems.  Pins the channel-to-object map: summing the
+    channels of object 1 into object 0's N and Q, or the other way round,
+    changes both."""
+    N, J, M = 32, 3, 8
+    pr = synth.make_problem(27, N=N, P=1, J=J, M=M, channels=((0, 0.0), (1, 1.0), (1, 0.0)),
+                            d_over_r0=7.0, border=3)
+    frames = oracle.simulate_frames(pr.objects, pr.alpha_true, pr.basis, pr.diversity,
+                                    pr.pupil, pr.channel_object, pr.noise)
+    D = oracle.patch_spectra(frames, pr.window)[0]
+    a = pr.alpha_true[0].astype(np.float64) + 0.25 * _rng(27).standard_normal((J, M))
+    w = np.array([[1.0, 0.6, 1.7], [0.8, 1.2, 0.5], [1.4, 0.9, 1.1]])
+    gam = np.stack([np.full((N, N), 2e-3), np.full((N, N), 7e-3)])
+    both = oracle.evaluate_patch(a, D, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
+                                 gam, w)
+    parts = []
+    for k, chans in ((0, [0]), (1, [1, 2])):
+        parts.append(oracle.evaluate_patch(a, D[chans], pr.basis[chans], pr.diversity[chans],
+                                           pr.pupil[chans], np.zeros(len(chans), np.int32),
+                                           gam[k:k + 1], w[chans]))
+    assert abs(both["loss"] - parts[0]["loss"] - parts[1]["loss"]) <= 1e-12 * both["loss"]
+    np.testing.assert_allclose(both["grad"], parts[0]["grad"] + parts[1]["grad"], rtol=0,
+                               atol=1e-11 * np.abs(both["grad"]).max())
+    np.testing.assert_allclose(both["O"][1], parts[1]["O"][0], rtol=0,
+                               atol=1e-12 * np.abs(both["O"][1]).max())
+    # the pooled reading (every channel in one object) is a different problem
+    pooled = oracle.evaluate_patch(a, D, pr.basis, pr.diversity, pr.pupil,
+                                   np.zeros(3, np.int32), gam[:1], w)
+    assert abs(pooled["loss"] - both["loss"]) > 1e-3 * both["loss"]
+
+
+def test_diversity_is_a_known_coefficient_offset():
+    """Eq. wavefront adds the diversity theta_c to the modal sum, so a
+    diversity that is itself a modal sum Z beta gives the loss and gradient
+    of the coefficients alpha + beta without diversity.  Pins the presence and
+    the sign of the diversity term (dropping it or flipping it moves the
+    loss by far more than rounding)."""
+    N, J, M = 32, 3, 8
+    pr, D = _small_problem(N=N, J=J, M=M, C=2, diversity=False)
+    a = pr.alpha_true[0].astype(np.float64)
+    Z = pr.basis.astype(np.float64)
+    beta = np.array([0.4, -0.7, 0.9, 0.0, 0.3, -0.2, 0.5, -0.6])
+    theta = np.stack([np.tensordot(beta, Z[c], axes=(0, 0)) for c in range(2)])
+    theta[1] *= 0.5                     # a different offset per channel
+    # channel c sees alpha + s_c beta; both channels share alpha, so compare
+    # one channel at a time against its own shifted problem
+    for c, sc in ((0, 1.0), (1, 0.5)):
+        one = oracle.evaluate_patch(a, D[0][[c]], Z[[c]], theta[[c]], pr.pupil[[c]],
+                                    np.zeros(1, np.int32), pr.gamma)
+        shifted = oracle.evaluate_patch(a + sc * beta[None, :], D[0][[c]], Z[[c]],
+                                        np.zeros((1, N, N)), pr.pupil[[c]],
+                                        np.zeros(1, np.int32), pr.gamma)
+        assert abs(one["loss"] - shifted["loss"]) <= 1e-12 * shifted["loss"]
+        np.testing.assert_allclose(one["grad"], shifted["grad"], rtol=0,
+                                   atol=1e-11 * np.abs(shifted["grad"]).max())
+        flipped = oracle.evaluate_patch(a - sc * beta[None, :], D[0][[c]], Z[[c]],
+                                        np.zeros((1, N, N)), pr.pupil[[c]],
+                                        np.zeros(1, np.int32), pr.gamma)
+        plain = oracle.evaluate_patch(a, D[0][[c]], Z[[c]], np.zeros((1, N, N)),
+                                      pr.pupil[[c]], np.zeros(1, np.int32), pr.gamma)
+        assert abs(flipped["loss"] - one["loss"]) > 1e-3 * one["loss"]
+        assert abs(plain["loss"] - one["loss"]) > 1e-3 * one["loss"]
+    # with one object fed by both channels the same holds for the shared alpha
+    # when both channels are offset alike
+    theta_same = np.stack([theta[0], theta[0]])
+    both = oracle.evaluate_patch(a, D[0], Z, theta_same, pr.pupil, pr.channel_object, pr.gamma)
+    ref = oracle.evaluate_patch(a + beta[None, :], D[0], Z, np.zeros((2, N, N)), pr.pupil,
+                                pr.channel_object, pr.gamma)
+    assert abs(both["loss"] - ref["loss"]) <= 1e-12 * ref["loss"]
+    np.testing.assert_allclose(both["grad"], ref["grad"], rtol=0,
+                               atol=1e-11 * np.abs(ref["grad"]).max())
+
+
 # --------------------------------------------------- data preparation -------
 
 def test_prepare_data_grid_and_transform():
