@@ -67,6 +67,8 @@ extern "C" {
 #define MOMFBD_EUNSUPPORTED (-2)  /* patch size, mode count or pupil not supported */
 #define MOMFBD_EWORKSPACE (-3)    /* workspace missing, misaligned or too small */
 #define MOMFBD_EDEVICE (-4)       /* HIP error                                 */
+#define MOMFBD_ESCRATCH (-5)      /* problem too large for the fixed scratch of
+                                     momfbd_loss_grad_noalloc                  */
 
 typedef struct momfbd_plan_s* momfbd_plan;
 
@@ -136,6 +138,27 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
 int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                      float gamma_scalar, const float* weights, double* loss, float* grad,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* Loss and gradient without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): momfbd_loss_grad with the workspace taken
+ * from a fixed scratch buffer inside the library instead of the caller.
+ *   Every argument as momfbd_loss_grad; there is no ws argument.
+ *   The scratch is one buffer per device of 64 MiB (67 108 864 bytes),
+ *   created when the library is loaded and kept until the process ends; its device address is looked up once per device by
+ *   momfbd_plan_create.  The call allocates nothing (no hipMalloc, no
+ *   host allocation) and synchronises nothing.
+ *   Every call on one device uses that device's buffer, which keeps the
+ *   last call's intermediates: calls that may overlap on one device (other
+ *   streams, other threads, other plans) race and must be serialised by the
+ *   caller.  No part of the buffer needs clearing between calls (every
+ *   kernel of the chain writes what it later reads).
+ * Errors: EINVAL, ESCRATCH (momfbd_workspace_size of the plan exceeds
+ * 64 MiB, e.g. more than about 100 patches of 64 x 64 with 24 frames over
+ * two channels; use momfbd_loss_grad), EDEVICE. */
+int momfbd_loss_grad_noalloc(momfbd_plan plan, const float* alpha, const void* D,
+                             const float* gamma, float gamma_scalar, const float* weights,
+                             double* loss, float* grad, void* stream);
 
 /* Wiener object estimate in pixel space (Eq. object_optimization):
  *   obj  DEVICE float [P][K][N][N], o_k = Re IDFT(O_k) / N^2 -- the restored

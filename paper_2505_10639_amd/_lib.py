@@ -21,6 +21,7 @@ MOMFBD_EINVAL = -1
 MOMFBD_EUNSUPPORTED = -2
 MOMFBD_EWORKSPACE = -3
 MOMFBD_EDEVICE = -4
+MOMFBD_ESCRATCH = -5
 
 
 class MomfbdError(RuntimeError):
@@ -60,7 +61,8 @@ class momfbd_desc(ctypes.Structure):
 _lib = None
 _vp = ctypes.c_void_p
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
-           -3: "workspace missing, misaligned or too small", -4: "HIP device error"}
+           -3: "workspace missing, misaligned or too small", -4: "HIP device error",
+           -5: "problem needs more scratch than the allocation-free entry point's fixed buffer"}
 
 
 def lib():
@@ -79,6 +81,7 @@ def lib():
         L.momfbd_prepare_data.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, z, _vp]
         L.momfbd_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, z, _vp]
         L.momfbd_loss_grad.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp, z, _vp]
+        L.momfbd_loss_grad_noalloc.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, _vp]
         L.momfbd_object_estimate.argtypes = [_vp, _vp, _vp, _vp, f, _vp, _vp, _vp, z, _vp]
         L.momfbd_status_string.argtypes = [i]
         L.momfbd_status_string.restype = ctypes.c_char_p
@@ -126,7 +129,7 @@ def lib():
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
                      "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
                      "momfbd_power_spectrum", "momfbd_plan_set_tuning", "momfbd_plan_get_tuning",
-                     "momfbd_plan_autotune"):
+                     "momfbd_plan_autotune", "momfbd_loss_grad_noalloc"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -226,6 +229,14 @@ def momfbd_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, loss, grad, w
     _check(lib().momfbd_loss_grad(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
                                   _ptr(weights), _ptr(loss), _ptr(grad), _ptr(ws), _nbytes(ws),
                                   _stream(stream, alpha)), "momfbd_loss_grad")
+
+
+def momfbd_loss_grad_noalloc(plan, alpha, D, gamma, gamma_scalar, weights, loss, grad,
+                             stream=None):
+    _check(lib().momfbd_loss_grad_noalloc(plan, _ptr(alpha), _ptr(D), _ptr(gamma),
+                                          float(gamma_scalar), _ptr(weights), _ptr(loss),
+                                          _ptr(grad), _stream(stream, alpha)),
+           "momfbd_loss_grad_noalloc")
 
 
 def momfbd_object_estimate(plan, alpha, D, gamma, gamma_scalar, weights, obj, ws, stream=None):

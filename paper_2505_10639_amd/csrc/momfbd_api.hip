@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -45,7 +46,39 @@ struct momfbd_plan_s {
   int* supp = nullptr;     // [K][N/2+1] spectral support of each object (see LossArgs)
 };
 
+// Scratch of the allocation-free loss/gradient entry point: one fixed
+// buffer per device, held from library load until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory; its
+// device address is taken once per device (momfbd_plan_create, with that
+// device current) and only that address is handed to kernels.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch, looked up on first use.
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return MOMFBD_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MOMFBD_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return MOMFBD_EDEVICE;
+  }
+  g_scratch_ptr[device] = ptr;
+  return MOMFBD_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
@@ -177,6 +210,8 @@ const char* momfbd_status_string(int status) {
     case MOMFBD_EUNSUPPORTED: return "unsupported configuration";
     case MOMFBD_EWORKSPACE: return "workspace missing, misaligned or too small";
     case MOMFBD_EDEVICE: return "HIP device error";
+    case MOMFBD_ESCRATCH:
+      return "problem needs more scratch than the allocation-free entry point's fixed buffer";
     default: return "unknown status";
   }
 }
@@ -293,6 +328,9 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
       for (size_t px = 0; px < BP; ++px)
         hZT[((size_t)c * BP + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * BP + px];
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
+  // the scratch of momfbd_loss_grad_noalloc on this device (a failure here
+  // only disables that entry point, which then reports EDEVICE)
+  (void)scratch_setup(pl->device);
   if (hipHostMalloc(&pl->hflag, sizeof(int)) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
             hipMalloc(&pl->Zt, hZp.size() * sizeof(float)) == hipSuccess &&
@@ -462,6 +500,21 @@ int momfbd_loss_grad(momfbd_plan plan, const float* alpha, const void* D, const 
   if (st) return st;
   if (!alpha || !D || !loss) return MOMFBD_EINVAL;
   if ((st = pending_error())) return st;
+  return run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws,
+                       (hipStream_t)stream);
+}
+
+int momfbd_loss_grad_noalloc(momfbd_plan plan, const float* alpha, const void* D,
+                             const float* gamma, float gamma_scalar, const float* weights,
+                             double* loss, float* grad, void* stream) {
+  if (!plan) return MOMFBD_EINVAL;
+  if (!alpha || !D || !loss) return MOMFBD_EINVAL;
+  const size_t need = workspace_bytes(plan->d);
+  if (need > kNoallocScratchBytes) return MOMFBD_ESCRATCH;
+  void* ws = scratch_of(plan->device);
+  if (!ws) return MOMFBD_EDEVICE;
+  int st = pending_error();
+  if (st) return st;
   return run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws,
                        (hipStream_t)stream);
 }
