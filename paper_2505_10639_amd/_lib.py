@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmomfbd.so")
+# MOMFBD_LIBRARY names another build of the same sources (the tests' host
+# sanitizer build); by default the in-tree library.
+LIB_PATH = os.environ.get("MOMFBD_LIBRARY") or os.path.join(_HERE, "libmomfbd.so")
 
 MOMFBD_OK = 0
 MOMFBD_EINVAL = -1

@@ -15,7 +15,9 @@ import oracle
 import synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-EMU = os.path.join(os.path.dirname(HERE), "paper_2505_10639_amd", "libmomfbd_hostemu.so")
+EMU = os.environ.get("MOMFBD_HOSTEMU") or os.path.join(os.path.dirname(HERE),
+                                                        "paper_2505_10639_amd",
+                                                        "libmomfbd_hostemu.so")
 FP = ctypes.POINTER(ctypes.c_float)
 
 
