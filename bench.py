@@ -359,9 +359,12 @@ def warm_start_block(dev, steps, patches=961):
 def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     """Independent 512^2 fields with patch sizes 64, 96 or 128 (stride N/2),
     frame counts 6..24, 44..88 modes and 1..3 objects (one channel each),
-    D/r0 5..20: every field's solver rounds captured into one HIP graph.
-    Reports the time of one graph launch (one line-search trial for every
-    patch of every field) against the same rounds issued eagerly."""
+    D/r0 5..20.  One round gives every patch of every field one line-search
+    trial.  Timed three ways from fresh solver states: the fields of each
+    patch size as one library group (one launch per stage for all of them,
+    launch schedules autotuned), eagerly and replayed from one HIP graph;
+    and, for comparison, every field issuing its own rounds as parallel
+    branches of one HIP graph."""
     import torch
 
     import synth
@@ -369,7 +372,7 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     from paper_2505_10639_amd.batch import Field, FieldBatch
 
     rng = np.random.default_rng(synth.SEED_ROOT + 8)
-    fields, units, pf = [], 0, 0
+    specs, units, pf = [], 0, 0
     for i in range(n_fields):
         N = int(rng.choice([64, 96, 128]))
         J = int(rng.integers(6, 25))
@@ -394,30 +397,45 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
         noise = 0.01 * torch.randn((K, J, fov, fov), device=dev)
         D = (Ohat * S + plan.prepare_data(noise, stride, win)).contiguous()
         plan.close()
-        fields.append(Field(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, D, 1e-3,
-                            device=dev))
+        specs.append((N, P, J, pr.channel_object, pr.pupil, pr.basis, D))
         units += P * K * J
         pf += P * J
-    batch = FieldBatch(fields, rounds_per_launch=1)
-    batch.eager()                               # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(rounds):
-        batch.eager()
-    torch.cuda.synchronize()
-    t_eager = (time.perf_counter() - t0) / rounds
-    batch.capture()
-    batch.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.launch(rounds)
-    torch.cuda.synchronize()
-    t_graph = (time.perf_counter() - t0) / rounds
-    batch.close()
-    return {"workload": f"{n_fields} fields of {fov}^2: N in {{64,96,128}} at stride N/2, J 6..24, "
-                        f"M 44..88, K 1..3, D/r0 5..20", "units": units, "patch_frames": pf,
-            "ms_per_round_graph": 1e3 * t_graph, "ms_per_round_eager": 1e3 * t_eager,
-            "patch_frame_evals_per_s_graph": pf / t_graph}
+
+    def fields():
+        return [Field(N, P, J, co, pu, ba, None, D, 1e-3, device=dev)
+                for (N, P, J, co, pu, ba, D) in specs]
+
+    def timed(batch, graph):
+        if graph:
+            batch.capture()
+        run = batch.launch if graph else batch.eager
+        run()                                      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / rounds
+
+    out = {"workload": f"{n_fields} fields of {fov}^2: N in {{64,96,128}} at stride N/2, J 6..24, "
+                       f"M 44..88, K 1..3, D/r0 5..20", "units": units, "patch_frames": pf,
+           "fields_per_size": {str(n): sum(1 for s_ in specs if s_[0] == n) for n in (64, 96, 128)}}
+    grouped = FieldBatch(fields(), mode="group")
+    out["group_schedules"] = {str(g.N): g.autotune(2) for g in grouped.groups}
+    out["ms_per_round_group_eager"] = 1e3 * timed(grouped, False)
+    grouped.close()
+    grouped = FieldBatch(fields(), mode="group")
+    for g, sch in zip(grouped.groups, out["group_schedules"].values()):
+        from paper_2505_10639_amd import _lib
+        _lib.momfbd_group_set_tuning(g.handle, sch["xcd_forward"], sch["xcd_adjoint"],
+                                     sch["grad_splits"], sch["grad_row_tiles"])
+    out["ms_per_round_group_graph"] = 1e3 * timed(grouped, True)
+    grouped.close()
+    branches = FieldBatch(fields(), mode="branches")
+    out["ms_per_round_field_branches_graph"] = 1e3 * timed(branches, True)
+    branches.close()
+    out["patch_frame_evals_per_s_group_graph"] = pf / (1e-3 * out["ms_per_round_group_graph"])
+    return out
 
 
 def _host_cpu():
@@ -543,6 +561,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (for scaling "
                          "hardware byte counters) and exit")
+    ap.add_argument("--only", choices=["uneven", "warm", "large"],
+                    help="run one secondary block alone and print its JSON (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the patches are "
@@ -561,6 +581,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "copies": 3}), flush=True)
+        return
+
+    if args.only:
+        if args.only == "uneven":
+            res = uneven_fields_block(dev)
+        elif args.only == "warm":
+            res = warm_start_block(dev, args.warm_steps)
+        else:
+            plan4, D4, alpha4, gamma4, g4 = build_large(dev)
+            ms4, kern4, _, _, _ = time_steps(plan4, D4, alpha4, gamma4, max(2, args.steps // 2),
+                                             min(args.warmup, 2), not args.no_tune)
+            res = {"ms_per_step": ms4, "kernels_avg_ms": kern4, "launch_schedule": plan4.tuning()}
+            plan4.close()
+        print(json.dumps({args.only: res}), flush=True)
         return
 
     log("building full-field inputs")
@@ -631,7 +665,7 @@ def main():
         del D4, alpha4, gamma4
 
     if not args.no_large:
-        log("uneven fields in one HIP graph")
+        log("uneven fields: groups per patch size, one launch per stage")
         out["uneven_fields"] = uneven_fields_block(dev)
 
     if args.warm_steps > 0:

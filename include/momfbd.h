@@ -435,6 +435,82 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
                          float* grad, void* ws, size_t ws_bytes, void* stream,
                          momfbd_tuning* chosen);
 
+/* Groups: many independent fields of one patch size (for instance the
+ * fields of an observing run, each with its own frame count, mode count,
+ * objects, pupils and data) solved together, with one kernel launch per
+ * stage of the loss/gradient chain and of the solver round covering every
+ * patch of every field (Sect. "Optimization and paralellization": patches
+ * are independent, and batching them fills the GPU).  Each field keeps its
+ * own plan (created as usual), workspace and solver state; the results of
+ * every field are those its own plan gives (the arithmetic per patch is the
+ * same, and so is the order of every sum), only the launches are shared.
+ *
+ * A field binds its device arrays once, at group creation:
+ *   plan           the field's plan; every plan of a group has the same N and
+ *                  was created on the current device
+ *   alpha          [P][J][M] coefficients, read (and, by the solver rounds,
+ *                  updated in place: the trial point of running patches)
+ *   D, gamma, gamma_scalar, weights   as momfbd_loss_grad
+ *   ws, ws_bytes   the field's own workspace (momfbd_workspace_size of its
+ *                  plan); fields must not share workspaces
+ *   state, state_bytes   the field's solver state, started by
+ *                  momfbd_lbfgs_init with the group's params (solver groups
+ *                  only; else NULL)
+ *   loss, grad     [P], [P][J][M] outputs of momfbd_group_loss_grad, or NULL
+ *                  (then that call is refused)
+ *   loss_accepted, status, alpha_accepted   outputs of the solver rounds
+ *                  ([P], [P], [P][J][M]), each may be NULL
+ * The arrays must stay valid, and in place, for the life of the group. */
+typedef struct momfbd_group_s* momfbd_group;
+typedef struct {
+  momfbd_plan plan;
+  float* alpha;
+  const void* D;
+  const float* gamma;
+  float gamma_scalar;
+  const float* weights;
+  void* ws;
+  size_t ws_bytes;
+  void* state;
+  size_t state_bytes;
+  double* loss;
+  float* grad;
+  double* loss_accepted;
+  int* status;
+  float* alpha_accepted;
+} momfbd_field;
+
+/* Create a group of n >= 1 fields (host array `fields`, copied).  params:
+ * the solver parameters the states were started with, or NULL for a group
+ * that only evaluates.  Allocates the group's device tables.
+ * Errors: EINVAL (NULL, mixed N or devices, bad params), EWORKSPACE (a
+ * field's workspace or state missing, misaligned or short), EUNSUPPORTED
+ * (more than 2^30 work items in one stage), EDEVICE. */
+int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_params* params,
+                        momfbd_group* out);
+int momfbd_group_destroy(momfbd_group group);
+
+/* Loss and gradient of every field at its alpha into its loss and grad
+ * (momfbd_loss_grad for each field, in one launch per stage).
+ * Errors: EINVAL (a field without loss or grad outputs), EDEVICE. */
+int momfbd_group_loss_grad(momfbd_group group, void* stream);
+
+/* `rounds` solver rounds of every field (momfbd_lbfgs_rounds for each field,
+ * in one launch per stage), then the accepted loss, status and coefficients
+ * of every field into its bound outputs.  No host synchronisation, no
+ * allocation: capturable in a HIP graph.  Errors: EINVAL (not a solver
+ * group, rounds < 0), EDEVICE. */
+int momfbd_group_lbfgs_rounds(momfbd_group group, int rounds, void* stream);
+
+/* Launch schedules of a group (the fields of momfbd_tuning that apply:
+ * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4 or 3; grad_waves
+ * must be 4).  The autotuner times momfbd_group_loss_grad over `reps`
+ * evaluations per candidate with the plan autotuner's method and keeps the
+ * fastest schedule.  Errors: EINVAL, EDEVICE. */
+int momfbd_group_set_tuning(momfbd_group group, const momfbd_tuning* tuning);
+int momfbd_group_get_tuning(momfbd_group group, momfbd_tuning* tuning);
+int momfbd_group_autotune(momfbd_group group, int reps, void* stream, momfbd_tuning* chosen);
+
 /* Sizes the plan was created with (any out pointer may be NULL). */
 int momfbd_plan_dims(momfbd_plan plan, int* N, int* P, int* C, int* K, int* J, int* M);
 

@@ -60,6 +60,16 @@ class momfbd_desc(ctypes.Structure):
                 ("channel_object", ctypes.POINTER(ctypes.c_int))]
 
 
+class momfbd_field(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("D", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p), ("gamma_scalar", ctypes.c_float),
+                ("weights", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("state", ctypes.c_void_p),
+                ("state_bytes", ctypes.c_size_t), ("loss", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("loss_accepted", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("alpha_accepted", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
@@ -121,6 +131,14 @@ def lib():
                                         _vp]
         L.momfbd_profile_stop.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_char_p),
                                           ctypes.POINTER(d), ctypes.POINTER(i)]
+        L.momfbd_group_create.argtypes = [ctypes.POINTER(momfbd_field), i, pp,
+                                          ctypes.POINTER(_vp)]
+        L.momfbd_group_destroy.argtypes = [_vp]
+        L.momfbd_group_loss_grad.argtypes = [_vp, _vp]
+        L.momfbd_group_lbfgs_rounds.argtypes = [_vp, i, _vp]
+        L.momfbd_group_set_tuning.argtypes = [_vp, tp]
+        L.momfbd_group_get_tuning.argtypes = [_vp, tp]
+        L.momfbd_group_autotune.argtypes = [_vp, i, _vp, tp]
         for name in ("momfbd_plan_create", "momfbd_plan_destroy", "momfbd_workspace_size",
                      "momfbd_prepare_data", "momfbd_forward", "momfbd_loss_grad",
                      "momfbd_object_estimate", "momfbd_plan_dims", "momfbd_profile_start",
@@ -131,7 +149,10 @@ def lib():
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
                      "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
                      "momfbd_power_spectrum", "momfbd_plan_set_tuning", "momfbd_plan_get_tuning",
-                     "momfbd_plan_autotune", "momfbd_loss_grad_noalloc"):
+                     "momfbd_plan_autotune", "momfbd_loss_grad_noalloc",
+                     "momfbd_group_create", "momfbd_group_destroy", "momfbd_group_loss_grad",
+                     "momfbd_group_lbfgs_rounds", "momfbd_group_set_tuning",
+                     "momfbd_group_get_tuning", "momfbd_group_autotune"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -422,3 +443,52 @@ def momfbd_lbfgs_step(plan, params, state, alpha, D, gamma, gamma_scalar, weight
                                    _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
                                    _ptr(weights), _ptr(loss), _ptr(status), _ptr(ws), _nbytes(ws),
                                    _stream(stream, alpha)), "momfbd_lbfgs_step")
+
+
+def field_spec(plan, alpha, D, gamma, gamma_scalar, weights, ws, state=None, loss=None,
+               grad=None, loss_accepted=None, status=None, alpha_accepted=None):
+    """One momfbd_field (device pointers of tensors; None -> NULL)."""
+    return momfbd_field(plan, _ptr(alpha), _ptr(D), _ptr(gamma), float(gamma_scalar),
+                        _ptr(weights), _ptr(ws), _nbytes(ws), _ptr(state), _nbytes(state),
+                        _ptr(loss), _ptr(grad), _ptr(loss_accepted), _ptr(status),
+                        _ptr(alpha_accepted))
+
+
+def momfbd_group_create(fields, params=None):
+    arr = (momfbd_field * len(fields))(*fields)
+    out = _vp()
+    _check(lib().momfbd_group_create(arr, len(fields),
+                                     None if params is None else ctypes.byref(params),
+                                     ctypes.byref(out)), "momfbd_group_create")
+    return out.value
+
+
+def momfbd_group_destroy(group):
+    _check(lib().momfbd_group_destroy(group), "momfbd_group_destroy")
+
+
+def momfbd_group_loss_grad(group, stream):
+    _check(lib().momfbd_group_loss_grad(group, stream), "momfbd_group_loss_grad")
+
+
+def momfbd_group_lbfgs_rounds(group, rounds, stream):
+    _check(lib().momfbd_group_lbfgs_rounds(group, int(rounds), stream),
+           "momfbd_group_lbfgs_rounds")
+
+
+def momfbd_group_set_tuning(group, xcd_forward, xcd_adjoint, grad_splits=0, grad_row_tiles=4):
+    t = momfbd_tuning(xcd_forward, xcd_adjoint, 1, 4, grad_splits, grad_row_tiles)
+    _check(lib().momfbd_group_set_tuning(group, ctypes.byref(t)), "momfbd_group_set_tuning")
+
+
+def momfbd_group_get_tuning(group):
+    t = momfbd_tuning()
+    _check(lib().momfbd_group_get_tuning(group, ctypes.byref(t)), "momfbd_group_get_tuning")
+    return t.as_dict()
+
+
+def momfbd_group_autotune(group, reps, stream):
+    t = momfbd_tuning()
+    _check(lib().momfbd_group_autotune(group, int(reps), stream, ctypes.byref(t)),
+           "momfbd_group_autotune")
+    return t.as_dict()

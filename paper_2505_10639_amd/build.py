@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libmomfbd.so")
 EMU = os.path.join(HERE, "libmomfbd_hostemu.so")
 
 ARCH = "gfx950"
-SOURCES = ["momfbd_api.hip", "kernels64.hip", "kernels96.hip", "kernels128.hip", "object.hip", "gemm_mfma.hip",
+SOURCES = ["momfbd_api.hip", "kernels64.hip", "kernels96.hip", "kernels128.hip", "object.hip", "gemm_mfma.hip", "gemm_group.hip",
            "lbfgs.hip", "postproc.hip", "cnn.hip", "spectra.hip"]
 # Packed FP32 instructions are kept out of every code object; clang forms
 # them from ordinary float code otherwise.

@@ -1,0 +1,93 @@
+// Dense modal contractions for a group of fields (all of one patch size):
+// one launch covers the phase tiles, or the gradient row tiles, of every
+// field, each block finding its field from the stage's prefix sums.  The
+// bodies are those of the single-plan kernels (contract_mfma.h); fields with
+// fewer modes than the group's largest skip the mode tiles they lack.
+#include <hip/hip_runtime.h>
+
+#include "contract_mfma.h"
+#include "internal.h"
+
+namespace mfbd {
+namespace {
+
+using contract::kCols;
+
+__device__ __forceinline__ int zc_of(const Dims& d) { return d.zc > 0 ? d.zc : d.C; }
+
+// grid (4 * largest zc, phase tiles of all fields)
+__global__ __launch_bounds__(256) void k_phase_group(GroupArgs ga) {
+  const int g = blockIdx.y;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  const int zc = zc_of(F.d);
+  if ((int)blockIdx.x >= 4 * zc) return;
+  contract::phase_block(blockIdx.x, g - ga.begin[f], F.d.P * F.d.J, F.d.J, F.d.C, zc, F.d.M,
+                        F.Mp, F.d.bandpix(), F.ZtT, F.thetat, F.alpha, F.w.phi);
+}
+
+// grid (row tiles of all fields, splits); W = 4 waves, RT row tiles each
+template <int MT, int RT>
+__global__ __launch_bounds__(256) void k_grad_group(GroupArgs ga) {
+  const int g = blockIdx.x;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  contract::grad_block<MT, RT, 4, 2, -1>(g - ga.begin[f], blockIdx.y, gridDim.y,
+                                         (F.d.M + 15) / 16, F.d.P * F.d.J, F.d.J, F.d.C,
+                                         zc_of(F.d), F.d.M, F.d.bandpix(), F.Zt, F.w.gphi,
+                                         F.grad, F.w.gpart);
+}
+
+// grad = 2 pi (part[0] + ... + part[splits-1]) per field, in split order
+__global__ __launch_bounds__(256) void k_grad_combine_group(GroupArgs ga, int splits) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  const long n = (long)F.d.P * F.d.J * F.d.M, i = g - ga.begin[f];
+  float v = F.w.gpart[i];
+  for (int s = 1; s < splits; ++s) v += F.w.gpart[(size_t)s * n + i];
+  F.grad[i] = 6.283185307179586f * v;
+}
+
+template <int MT>
+void launch_grad_group_t(const GroupArgs& ga, int row_tiles, int splits, hipStream_t s) {
+  const dim3 grid(ga.total, splits);
+  if (row_tiles == 3)
+    hipLaunchKernelGGL((k_grad_group<MT, 3>), grid, dim3(256), 0, s, ga);
+  else
+    hipLaunchKernelGGL((k_grad_group<MT, 4>), grid, dim3(256), 0, s, ga);
+}
+
+}  // namespace
+
+hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mp_max, hipStream_t s) {
+  const size_t lds = (size_t)Mp_max * (kCols + 4) * sizeof(float);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_group),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_phase_group, dim3(4 * zc_max, ga.total), dim3(256), lds, s, ga);
+  return hipGetLastError();
+}
+
+// ga_tiles: row tiles of 16 * row_tiles rows per field; ga_elems: P J M per field
+hipError_t launch_grad_group(const GroupArgs& ga_tiles, const GroupArgs& ga_elems, int mt_max,
+                             int row_tiles, int splits, hipStream_t s) {
+  switch (mt_max) {
+#define MFBD_CASE(n) \
+  case n: launch_grad_group_t<n>(ga_tiles, row_tiles, splits, s); break;
+    MFBD_CASE(1) MFBD_CASE(2) MFBD_CASE(3) MFBD_CASE(4) MFBD_CASE(5) MFBD_CASE(6)
+    MFBD_CASE(7) MFBD_CASE(8) MFBD_CASE(9) MFBD_CASE(10) MFBD_CASE(11) MFBD_CASE(12)
+    MFBD_CASE(13) MFBD_CASE(14) MFBD_CASE(15) MFBD_CASE(16)
+#undef MFBD_CASE
+    default: return hipErrorInvalidValue;
+  }
+  if (splits > 1)
+    hipLaunchKernelGGL(k_grad_combine_group, dim3((ga_elems.total + 255) / 256), dim3(256), 0, s,
+                       ga_elems, splits);
+  return hipGetLastError();
+}
+
+}  // namespace mfbd

@@ -12,6 +12,7 @@ constexpr int kMaxK = 32;
 constexpr int kMaxM = 256;
 constexpr int kBand = 32;            // band width for N = 64
 constexpr int kBandPix = kBand * kBand;
+constexpr int kPhaseCols = 32;       // (patch, frame) columns per phase-contraction block
 
 // Blocks of 256 threads, `ppt` frequency pairs per thread, covering one
 // half spectrum of side n.
@@ -32,9 +33,9 @@ struct Dims {
   // basis is the same (the contractions then run once for all channels),
   // else C; 0 is read as C
   int zc = 0;
-  int band() const { return N / 2; }                 // pupil band width
-  int bandpix() const { return (N / 2) * (N / 2); }  // pixels of the band
-  int half() const { return N * (N / 2 + 1); }       // complex values of a half spectrum
+  __host__ __device__ int band() const { return N / 2; }                 // pupil band width
+  __host__ __device__ int bandpix() const { return (N / 2) * (N / 2); }  // pixels of the band
+  __host__ __device__ int half() const { return N * (N / 2 + 1); }  // complex values of a half spectrum
 };
 
 // Loads of data a kernel reads once per launch (the object kernel's data
@@ -124,6 +125,59 @@ struct Workspace {
   float* gpart;            // [kMaxGradSplits][P][J][M] partial sums of the gradient
 };
 
+struct LbfgsLayout {
+  int m;              // history pairs
+  int n;              // variables per patch (J*M)
+  size_t hdr, rho, x0, g, d, gt, S, Y, ft, active, counter, total;   // byte offsets
+};
+
+// A group: fields of one patch size whose loss/gradient chain and solver
+// rounds run together, one launch per stage for all of them.  Each field
+// keeps its own plan tables, data, workspace and solver state; FieldDesc
+// holds every per-field argument of the kernels in device memory.  Per
+// stage the group keeps the prefix sums of the work items (units, patches,
+// ...) over its fields: work item g of a launch belongs to the field f with
+// begin[f] <= g < begin[f + 1] and is item g - begin[f] of that field.
+struct FieldDesc {
+  Dims d;
+  int Mp;                  // modes rounded up to 16 (rows of the basis tables)
+  ChanTab ct;
+  LossArgs la;
+  const float* Ab;
+  const float* Zt;
+  const float* ZtT;
+  const float* thetat;
+  float* alpha;            // [P][J][M] coefficients (solver trial point)
+  Workspace w;
+  const int* active;       // [P] patches inside a line search (solver), or null
+  double* loss;            // [P] loss output of the evaluation
+  float* grad;             // [P][J][M] gradient output of the evaluation
+  void* state;             // solver state, or null
+  LbfgsLayout L;
+  double* loss_accepted;   // [P] or null
+  int* status;             // [P] or null
+  float* alpha_accepted;   // [P][J][M] or null
+};
+// work items per field: units P C J; patches P; phase tiles of 32 (patch,
+// frame) rows; object blocks P K object_blocks(N); gradient row tiles of
+// 64 or 48 rows; coefficients P J M
+enum GroupStage { kGsUnits, kGsPatches, kGsPhaseTiles, kGsObjBlocks, kGsGradTiles4,
+                  kGsGradTiles3, kGsElems, kGsCount };
+struct GroupArgs {
+  const FieldDesc* fd;     // [nf] (device)
+  const int* begin;        // [nf + 1] prefix sums of one stage's work items (device)
+  int nf, total;
+};
+// The field of work item g (0 <= g < total): binary search over the prefix sums.
+__device__ __forceinline__ int group_field(const GroupArgs& ga, int g) {
+  int lo = 0, hi = ga.nf;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ga.begin[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // The gradient contraction's pixel sum may be split over up to this many
 // blocks per row tile; grad_splits_of gives the plan's split count.
 constexpr int kMaxGradSplits = 8;
@@ -182,11 +236,6 @@ hipError_t launch_prepare128(const Dims& d, const float* frames, int H, int W, i
 hipError_t launch_objimg128(const Dims& d, const float2* O, float* obj, hipStream_t s);
 
 // L-BFGS (per-patch solver state lives in a caller-provided buffer)
-struct LbfgsLayout {
-  int m;              // history pairs
-  int n;              // variables per patch (J*M)
-  size_t hdr, rho, x0, g, d, gt, S, Y, ft, active, counter, total;   // byte offsets
-};
 LbfgsLayout lbfgs_layout(const Dims& d, int m, int max_evals);
 hipError_t launch_lbfgs_init(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
                              hipStream_t s);
@@ -201,5 +250,27 @@ hipError_t launch_lbfgs_search(const Dims& d, const LbfgsLayout& L, void* state,
                                hipStream_t s);
 hipError_t launch_lbfgs_finish(const Dims& d, const LbfgsLayout& L, void* state, double* loss_out,
                                int* status_out, hipStream_t s);
+
+// Group launches: one launch per stage over every field of a group (all of
+// one patch size).  `ga` carries the stage's prefix sums; the schedules
+// (XCD order, gradient row tiles and splits) are the group's.
+hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mp_max, hipStream_t s);
+hipError_t launch_forward_group(int N, const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_object_group(int N, const GroupArgs& ga_blocks, const GroupArgs& ga_patches,
+                               hipStream_t s);
+hipError_t launch_adjoint_group(int N, const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_grad_group(const GroupArgs& ga_tiles, const GroupArgs& ga_elems, int mt_max,
+                             int row_tiles, int splits, hipStream_t s);
+hipError_t launch_forward64_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_adjoint64_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_forward96_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_adjoint96_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_forward128_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_adjoint128_group(const GroupArgs& ga, int xcd, hipStream_t s);
+hipError_t launch_lbfgs_prep_group(const GroupArgs& ga, hipStream_t s);
+hipError_t launch_lbfgs_search_group(const GroupArgs& ga, double c1, double c2, int max_evals,
+                                     double ftol, hipStream_t s);
+hipError_t launch_lbfgs_publish_group(const GroupArgs& ga_elems, hipStream_t s);
+hipError_t launch_lbfgs_finish_group(const GroupArgs& ga_patches, hipStream_t s);
 
 }  // namespace mfbd

@@ -75,17 +75,14 @@ __device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* ps
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, ChanTab ct, int C, int J,
-                                                         const int* __restrict__ active,
-                                                         const float* __restrict__ Ab,
-                                                         const float* __restrict__ phi,
-                                                         float* __restrict__ psf,
-                                                         float2* __restrict__ S) {
+__device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C, int J,
+                                                const int* __restrict__ active,
+                                                const float* __restrict__ Ab,
+                                                const float* __restrict__ phi,
+                                                float* __restrict__ psf,
+                                                float2* __restrict__ S) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
-                   : blockIdx.x;
-  if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
@@ -111,20 +108,40 @@ __global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, Cha
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, ChanTab ct, int C, int J,
-                                                         int K, LossArgs la,
-                                                         const int* __restrict__ active,
-                                                         const float* __restrict__ Ab,
-                                                         const float* __restrict__ phi,
-                                                         const float2* __restrict__ S,
-                                                         const float2* __restrict__ O,
-                                                         float* __restrict__ gphi) {
+template <bool WANT_PSF>
+__global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, ChanTab ct, int C,
+                                                        int J, const int* __restrict__ active,
+                                                        const float* __restrict__ Ab,
+                                                        const float* __restrict__ phi,
+                                                        float* __restrict__ psf,
+                                                        float2* __restrict__ S) {
+  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
+                    : blockIdx.x;
+  if (u >= units) return;
+  forward128_unit<WANT_PSF>(u, ct, C, J, active, Ab, phi, psf, S);
+}
+
+// Every unit of every field of a group (XCD order over the group's units).
+__global__ __launch_bounds__(kThreads) void k_forward128_group(GroupArgs ga, int xcd) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  forward128_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+                        F.w.S);
+}
+
+__device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C, int J, int K,
+                                                const LossArgs& la,
+                                                const int* __restrict__ active,
+                                                const float* __restrict__ Ab,
+                                                const float* __restrict__ phi,
+                                                const float2* __restrict__ S,
+                                                const float2* __restrict__ O,
+                                                float* __restrict__ gphi) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  // XCD-aware order: consecutive units (frames of one patch-object) on one XCD
-  const int per = (units + kXcds - 1) / kXcds;
-  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
-  if (u >= units) return;
   const int lane = threadIdx.x;
   const int j = u % J;
   const int c = (u / J) % C;
@@ -222,6 +239,27 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128(int units, int xcd, Cha
       gout[n * kB + q] = pk.x * GP[i].y - pk.y * GP[i].x;   // Im(conj(P) G_P)
     }
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_adjoint128(
+    int units, int xcd, ChanTab ct, int C, int J, int K, LossArgs la,
+    const int* __restrict__ active, const float* __restrict__ Ab, const float* __restrict__ phi,
+    const float2* __restrict__ S, const float2* __restrict__ O, float* __restrict__ gphi) {
+  // XCD-aware order: consecutive units (frames of one patch-object) on one XCD
+  const int per = (units + kXcds - 1) / kXcds;
+  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (u >= units) return;
+  adjoint128_unit(u, ct, C, J, K, la, active, Ab, phi, S, O, gphi);
+}
+
+__global__ __launch_bounds__(kThreads) void k_adjoint128_group(GroupArgs ga, int xcd) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  adjoint128_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+                  F.w.S, F.w.O, F.w.gphi);
 }
 
 __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J, int H, int W,
@@ -345,6 +383,20 @@ hipError_t launch_adjoint128(const Dims& d, const ChanTab& ct, const LossArgs& l
   hipLaunchKernelGGL(k_adjoint128, dim3(d.xcd_adj ? kXcds * per : units), dim3(kThreads), 0, s,
                      units, d.xcd_adj, ct, d.C, d.J,
                      d.K, la, active, Ab, phi, S, O, gphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward128_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_forward128_group, dim3(xcd ? kXcds * per : ga.total), dim3(kThreads), 0,
+                     s, ga, xcd);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint128_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_adjoint128_group, dim3(xcd ? kXcds * per : ga.total), dim3(kThreads), 0,
+                     s, ga, xcd);
   return hipGetLastError();
 }
 

@@ -68,18 +68,18 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const f
 // The two transposes go through a half-size buffer (real parts, then
 // imaginary parts): 9.2 KB of LDS per wave lets a CU hold the 12 waves its
 // registers allow, against 9 with the full-size buffer.
+// Unit u of a field (the kernel of one plan and the group kernel both
+// resolve u, then run this).
 template <bool WANT_PSF>
-__global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct, int C, int J,
-                                                  const int* __restrict__ active,
-                                                  const float* __restrict__ Ab,
-                                                  const float* __restrict__ phi,
-                                                  float* __restrict__ psf,
-                                                  float2* __restrict__ S) {
+__device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, int J,
+                                               const int* __restrict__ active,
+                                               const float* __restrict__ Ab,
+                                               const float* __restrict__ phi,
+                                               float* __restrict__ psf,
+                                               float2* __restrict__ S) {
   __shared__ float2 Th[LDS_HALF / 2];
   __shared__ float2 Taux[LDS_AUX];
   float* Tf = reinterpret_cast<float*>(Th);
-  const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
-  if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
@@ -137,18 +137,39 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
   out[sl_index32(lane)] = x32;
 }
 
-__global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct, int C, int J,
-                                                  int K,
-                                                  LossArgs la, const int* __restrict__ active,
+template <bool WANT_PSF>
+__global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct, int C, int J,
+                                                  const int* __restrict__ active,
                                                   const float* __restrict__ Ab,
                                                   const float* __restrict__ phi,
-                                                  const float2* __restrict__ S,
-                                                  const float2* __restrict__ O,
-                                                  float* __restrict__ gphi) {
-  __shared__ float2 T[LDS_MAIN];
-  __shared__ float2 Taux[LDS_AUX];
+                                                  float* __restrict__ psf,
+                                                  float2* __restrict__ S) {
   const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
   if (u >= units) return;
+  forward64_unit<WANT_PSF>(u, ct, C, J, active, Ab, phi, psf, S);
+}
+
+// Every unit of every field of a group; the XCD order runs over the group's
+// unit sequence (fields in order, each field's units in order).
+__global__ __launch_bounds__(64) void k_forward64_group(GroupArgs ga, int xcd) {
+  const int g = xcd ? xcd_unit(xcd_per(ga.total)) : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  forward64_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+                        F.w.S);
+}
+
+__device__ __forceinline__ void adjoint64_unit(int u, const ChanTab& ct, int C, int J, int K,
+                                               const LossArgs& la,
+                                               const int* __restrict__ active,
+                                               const float* __restrict__ Ab,
+                                               const float* __restrict__ phi,
+                                               const float2* __restrict__ S,
+                                               const float2* __restrict__ O,
+                                               float* __restrict__ gphi) {
+  __shared__ float2 T[LDS_MAIN];
+  __shared__ float2 Taux[LDS_AUX];
   const int lane = threadIdx.x;
   const int j = u % J;
   const int c = (u / J) % C;
@@ -218,6 +239,28 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
     const float2 gp = GP[i];
     gout[n * kBand + q] = pk.x * gp.y - pk.y * gp.x;   // Im(conj(P) G_P)
   }
+}
+
+__global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct, int C, int J,
+                                                  int K,
+                                                  LossArgs la, const int* __restrict__ active,
+                                                  const float* __restrict__ Ab,
+                                                  const float* __restrict__ phi,
+                                                  const float2* __restrict__ S,
+                                                  const float2* __restrict__ O,
+                                                  float* __restrict__ gphi) {
+  const int u = xcd ? xcd_unit(xcd_per(units)) : blockIdx.x;
+  if (u >= units) return;
+  adjoint64_unit(u, ct, C, J, K, la, active, Ab, phi, S, O, gphi);
+}
+
+__global__ __launch_bounds__(64) void k_adjoint64_group(GroupArgs ga, int xcd) {
+  const int g = xcd ? xcd_unit(xcd_per(ga.total)) : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  adjoint64_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+                 F.w.S, F.w.O, F.w.gphi);
 }
 
 __global__ __launch_bounds__(64) void k_prepare64(int units, int C, int J, int H, int W,
@@ -362,6 +405,18 @@ hipError_t launch_adjoint64(const Dims& d, const ChanTab& ct, const LossArgs& la
   const dim3 grid(d.xcd_adj ? kXcds * xcd_per(units) : units);
   hipLaunchKernelGGL(k_adjoint64, grid, dim3(64), 0, s, units, d.xcd_adj, ct, d.C, d.J, d.K, la,
                      active, Ab, phi, S, O, gphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward64_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const dim3 grid(xcd ? kXcds * xcd_per(ga.total) : ga.total);
+  hipLaunchKernelGGL(k_forward64_group, grid, dim3(64), 0, s, ga, xcd);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint64_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const dim3 grid(xcd ? kXcds * xcd_per(ga.total) : ga.total);
+  hipLaunchKernelGGL(k_adjoint64_group, grid, dim3(64), 0, s, ga, xcd);
   return hipGetLastError();
 }
 

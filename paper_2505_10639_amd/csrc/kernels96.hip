@@ -45,17 +45,14 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A,
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, ChanTab ct, int C, int J,
-                                                        const int* __restrict__ active,
-                                                        const float* __restrict__ Ab,
-                                                        const float* __restrict__ phi,
-                                                        float* __restrict__ psf,
-                                                        float2* __restrict__ S) {
+__device__ __forceinline__ void forward96_unit(int u, const ChanTab& ct, int C, int J,
+                                                const int* __restrict__ active,
+                                                const float* __restrict__ Ab,
+                                                const float* __restrict__ phi,
+                                                float* __restrict__ psf,
+                                                float2* __restrict__ S) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
-                   : blockIdx.x;
-  if (u >= units) return;
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const bool on = lane < LANES;
@@ -105,22 +102,43 @@ __global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, Chan
   }
 }
 
+template <bool WANT_PSF>
+__global__ __launch_bounds__(kThreads) void k_forward96(int units, int xcd, ChanTab ct, int C,
+                                                        int J, const int* __restrict__ active,
+                                                        const float* __restrict__ Ab,
+                                                        const float* __restrict__ phi,
+                                                        float* __restrict__ psf,
+                                                        float2* __restrict__ S) {
+  const int u = xcd ? (blockIdx.x % kXcds) * ((units + kXcds - 1) / kXcds) + blockIdx.x / kXcds
+                    : blockIdx.x;
+  if (u >= units) return;
+  forward96_unit<WANT_PSF>(u, ct, C, J, active, Ab, phi, psf, S);
+}
+
+// Every unit of every field of a group (XCD order over the group's units).
+__global__ __launch_bounds__(kThreads) void k_forward96_group(GroupArgs ga, int xcd) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  forward96_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+                        F.w.S);
+}
+
 // Two waves per SIMD: the kernel's register demand is a few registers over
 // the 256 that allow it, and holding it there (a 32-byte spill) makes the
 // kernel a third faster than one wave per SIMD.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint96(int units, int xcd, ChanTab ct, int C, int J,
-                                                        int K, LossArgs la,
-                                                        const int* __restrict__ active,
-                                                        const float* __restrict__ Ab,
-                                                        const float* __restrict__ phi,
-                                                        const float2* __restrict__ S,
-                                                        const float2* __restrict__ O,
-                                                        float* __restrict__ gphi) {
+__device__ __forceinline__ void adjoint96_unit(int u, const ChanTab& ct, int C, int J, int K,
+                                                const LossArgs& la,
+                                                const int* __restrict__ active,
+                                                const float* __restrict__ Ab,
+                                                const float* __restrict__ phi,
+                                                const float2* __restrict__ S,
+                                                const float2* __restrict__ O,
+                                                float* __restrict__ gphi) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int per = (units + kXcds - 1) / kXcds;
-  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
-  if (u >= units) return;
   const int lane = threadIdx.x;
   const bool on = lane < LANES;
   const int j = u % J, c = (u / J) % C, p = u / (J * C);
@@ -181,6 +199,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       gout[n * kB + q] = pk.x * GP[i].y - pk.y * GP[i].x;   // Im(conj(P) G_P)
     }
   }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint96(
+    int units, int xcd, ChanTab ct, int C, int J, int K, LossArgs la,
+    const int* __restrict__ active, const float* __restrict__ Ab, const float* __restrict__ phi,
+    const float2* __restrict__ S, const float2* __restrict__ O, float* __restrict__ gphi) {
+  // XCD-aware order: consecutive units (frames of one patch-object) on one XCD
+  const int per = (units + kXcds - 1) / kXcds;
+  const int u = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (u >= units) return;
+  adjoint96_unit(u, ct, C, J, K, la, active, Ab, phi, S, O, gphi);
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint96_group(GroupArgs ga, int xcd) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  adjoint96_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+                  F.w.S, F.w.O, F.w.gphi);
 }
 
 __global__ __launch_bounds__(kThreads) void k_prepare96(int units, int C, int J, int H, int W,
@@ -295,6 +334,20 @@ hipError_t launch_adjoint96(const Dims& d, const ChanTab& ct, const LossArgs& la
   hipLaunchKernelGGL(k_adjoint96, dim3(d.xcd_adj ? kXcds * per : units), dim3(kThreads), 0, s,
                      units, d.xcd_adj, ct, d.C, d.J,
                      d.K, la, active, Ab, phi, S, O, gphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward96_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_forward96_group, dim3(xcd ? kXcds * per : ga.total), dim3(kThreads), 0,
+                     s, ga, xcd);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint96_group(const GroupArgs& ga, int xcd, hipStream_t s) {
+  const int per = (ga.total + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_adjoint96_group, dim3(xcd ? kXcds * per : ga.total), dim3(kThreads), 0,
+                     s, ga, xcd);
   return hipGetLastError();
 }
 

@@ -317,12 +317,12 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_begin(LbfgsLayout L, void* s
 
 // Round mode: a patch that is still running and not inside a line search
 // starts its next iteration; a patch inside a search keeps its trial point.
-__global__ __launch_bounds__(kThreads) void k_lbfgs_prep(LbfgsLayout L, void* state,
-                                                         float* __restrict__ alpha) {
+__device__ __forceinline__ void prep_patch(int p, const LbfgsLayout& L, void* state,
+                                           float* __restrict__ alpha) {
   __shared__ double red[kThreads];
   __shared__ double coef[32];
   View v = view(L, state);
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   if (v.hdr[p].status != 0) {
     if (tid == 0) v.active[p] = 0;
     return;
@@ -331,15 +331,27 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_prep(LbfgsLayout L, void* st
   begin_patch(L, v, p, alpha, red, coef);
 }
 
-__global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* state,
-                                                           float* __restrict__ alpha, int eval,
-                                                           double c1, double c2, int max_evals,
-                                                           double ftol) {
+__global__ __launch_bounds__(kThreads) void k_lbfgs_prep(LbfgsLayout L, void* state,
+                                                         float* __restrict__ alpha) {
+  prep_patch(blockIdx.x, L, state, alpha);
+}
+
+// Every patch of every field of a group.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_prep_group(GroupArgs ga) {
+  const int g = blockIdx.x;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  prep_patch(g - ga.begin[f], F.L, F.state, F.alpha);
+}
+
+__device__ __forceinline__ void search_patch(int p, const LbfgsLayout& L, void* state,
+                                             float* __restrict__ alpha, int eval, double c1,
+                                             double c2, int max_evals, double ftol) {
   __shared__ double red[kThreads];
   __shared__ int action;          // 0 accept, 1 next trial, 2 failed
   __shared__ double t_next;
   View v = view(L, state);
-  const int p = blockIdx.x, n = L.n, m = L.m, tid = threadIdx.x;
+  const int n = L.n, m = L.m, tid = threadIdx.x;
   if (!v.active[p]) return;
   Hdr& h = v.hdr[p];
   const float* d = v.d + (size_t)p * n;
@@ -448,6 +460,22 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* state,
+                                                           float* __restrict__ alpha, int eval,
+                                                           double c1, double c2, int max_evals,
+                                                           double ftol) {
+  search_patch(blockIdx.x, L, state, alpha, eval, c1, c2, max_evals, ftol);
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_search_group(GroupArgs ga, double c1,
+                                                                 double c2, int max_evals,
+                                                                 double ftol) {
+  const int g = blockIdx.x;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  search_patch(g - ga.begin[f], F.L, F.state, F.alpha, -1, c1, c2, max_evals, ftol);
+}
+
 // The accepted point of every patch: x0 while inside a line search.
 __global__ __launch_bounds__(kThreads) void k_lbfgs_publish(int P, LbfgsLayout L, void* state,
                                                             const float* __restrict__ alpha,
@@ -467,6 +495,30 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_finish(int P, LbfgsLayout L,
   if (p >= P) return;
   if (loss_out) loss_out[p] = v.hdr[p].f;
   if (status_out) status_out[p] = v.hdr[p].status;
+}
+
+// The accepted point of element g of the group's coefficients.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_publish_group(GroupArgs ga) {
+  const int g = blockIdx.x * kThreads + threadIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  if (!F.alpha_accepted) return;
+  View v = view(F.L, F.state);
+  const long i = g - ga.begin[f];
+  const int p = (int)(i / F.L.n);
+  F.alpha_accepted[i] = v.active[p] ? v.x0[i] : F.alpha[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_finish_group(GroupArgs ga) {
+  const int g = blockIdx.x * kThreads + threadIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  View v = view(F.L, F.state);
+  const int p = g - ga.begin[f];
+  if (F.loss_accepted) F.loss_accepted[p] = v.hdr[p].f;
+  if (F.status) F.status[p] = v.hdr[p].status;
 }
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -526,6 +578,30 @@ hipError_t launch_lbfgs_search(const Dims& d, const LbfgsLayout& L, void* state,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_lbfgs_search, dim3(d.P), dim3(kThreads), 0, s, L, state, alpha, eval, c1,
                      c2, max_evals, ftol);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_prep_group(const GroupArgs& ga, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_prep_group, dim3(ga.total), dim3(kThreads), 0, s, ga);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_search_group(const GroupArgs& ga, double c1, double c2, int max_evals,
+                                     double ftol, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_search_group, dim3(ga.total), dim3(kThreads), 0, s, ga, c1, c2,
+                     max_evals, ftol);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_publish_group(const GroupArgs& ga_elems, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_publish_group, dim3((ga_elems.total + kThreads - 1) / kThreads),
+                     dim3(kThreads), 0, s, ga_elems);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_finish_group(const GroupArgs& ga_patches, hipStream_t s) {
+  hipLaunchKernelGGL(k_lbfgs_finish_group, dim3((ga_patches.total + kThreads - 1) / kThreads),
+                     dim3(kThreads), 0, s, ga_patches);
   return hipGetLastError();
 }
 

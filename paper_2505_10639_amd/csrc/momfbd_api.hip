@@ -883,3 +883,286 @@ int momfbd_profile_stop(momfbd_plan plan, int cap, const char** names, double* t
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Groups: fields of one patch size solved together, one launch per stage.
+// ---------------------------------------------------------------------------
+
+struct momfbd_group_s {
+  int n = 0, N = 0, device = -1;
+  bool solver = false;
+  momfbd_lbfgs_params params{};
+  FieldDesc* fd_eval = nullptr;   // device [n]: evaluation into the bound loss/grad
+  FieldDesc* fd_solve = nullptr;  // device [n]: solver trial (state ft/gt, active flags)
+  int* begin = nullptr;           // device [kGsCount][n + 1]
+  std::vector<int> hbegin;        // host copy
+  std::vector<char> has_eval;     // per field: loss and grad bound
+  int zc_max = 1, Mp_max = 16, mt_max = 1;
+  long rows = 0;                  // (patch, frame) rows of all fields
+  int xcd_fwd = 0, xcd_adj = 1, grad_rt = 4, grad_splits = 0;
+};
+
+namespace {
+
+GroupArgs group_args(const momfbd_group_s* g, const FieldDesc* fd, int stage) {
+  GroupArgs a;
+  a.fd = fd;
+  a.begin = g->begin + (size_t)stage * (g->n + 1);
+  a.nf = g->n;
+  a.total = g->hbegin[(size_t)stage * (g->n + 1) + g->n];
+  return a;
+}
+
+int group_splits(const momfbd_group_s* g) {
+  if (g->grad_splits > 0) return g->grad_splits;
+  // the automatic count of a plan with all the group's rows
+  Dims d{g->N, (int)std::min<long>(g->rows, 1L << 30), 1, 1, 1, 1};
+  d.grad_waves = 4;
+  d.grad_rt = g->grad_rt == 3 ? 3 : 0;
+  d.zc = g->zc_max;
+  return grad_splits_auto(d);
+}
+
+// One loss+gradient evaluation of every field (fd: evaluation or solver table).
+hipError_t group_chain(const momfbd_group_s* g, const FieldDesc* fd, hipStream_t s) {
+  hipError_t e = launch_phase_group(group_args(g, fd, kGsPhaseTiles), g->zc_max, g->Mp_max, s);
+  if (e == hipSuccess) e = launch_forward_group(g->N, group_args(g, fd, kGsUnits), g->xcd_fwd, s);
+  if (e == hipSuccess)
+    e = launch_object_group(g->N, group_args(g, fd, kGsObjBlocks),
+                            group_args(g, fd, kGsPatches), s);
+  if (e == hipSuccess) e = launch_adjoint_group(g->N, group_args(g, fd, kGsUnits), g->xcd_adj, s);
+  if (e == hipSuccess)
+    e = launch_grad_group(group_args(g, fd, g->grad_rt == 3 ? kGsGradTiles3 : kGsGradTiles4),
+                          group_args(g, fd, kGsElems), g->mt_max, g->grad_rt, group_splits(g),
+                          s);
+  return e;
+}
+
+void group_free(momfbd_group_s* g) {
+  if (g->fd_eval) (void)hipFree(g->fd_eval);
+  if (g->fd_solve) (void)hipFree(g->fd_solve);
+  if (g->begin) (void)hipFree(g->begin);
+  delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_params* params,
+                        momfbd_group* out) {
+  if (!out || !fields || n < 1) return MOMFBD_EINVAL;
+  if (params && !lbfgs_params_ok(params)) return MOMFBD_EINVAL;
+  const int N = fields[0].plan ? fields[0].plan->d.N : 0;
+  const int dev = fields[0].plan ? fields[0].plan->device : -1;
+  long totals[kGsCount] = {0};
+  std::vector<FieldDesc> ev(n), so(n);
+  std::vector<int> hb((size_t)kGsCount * (n + 1), 0);
+  std::vector<char> has_eval(n, 0);
+  int zc_max = 1, Mp_max = 16, mt_max = 1;
+  long rows = 0;
+  for (int f = 0; f < n; ++f) {
+    const momfbd_field& a = fields[f];
+    const momfbd_plan pl = a.plan;
+    if (!pl || !a.alpha || !a.D) return MOMFBD_EINVAL;
+    if (pl->d.N != N || pl->device != dev) return MOMFBD_EINVAL;
+    if (!a.ws || reinterpret_cast<uintptr_t>(a.ws) % 256 || a.ws_bytes < workspace_bytes(pl->d))
+      return MOMFBD_EWORKSPACE;
+    const Dims& d = pl->d;
+    FieldDesc F;
+    std::memset(&F, 0, sizeof(F));
+    F.d = d;
+    F.Mp = pl->Mp;
+    F.ct = pl->ct;
+    F.la = LossArgs{static_cast<const float2*>(a.D), a.gamma, a.gamma_scalar, a.weights, pl->supp};
+    F.Ab = pl->Ab;
+    F.Zt = pl->Zt;
+    F.ZtT = pl->ZtT;
+    F.thetat = pl->thetat;
+    F.alpha = a.alpha;
+    F.w = carve_workspace(d, a.ws);
+    F.loss = a.loss;
+    F.grad = a.grad;
+    has_eval[f] = a.loss && a.grad;
+    ev[f] = F;
+    if (params) {
+      const LbfgsLayout L = lbfgs_layout(d, params->m, params->max_evals);
+      const int st = check_state(a.state, a.state_bytes, L.total);
+      if (st) return st;
+      char* b = static_cast<char*>(a.state);
+      F.state = a.state;
+      F.L = L;
+      F.active = reinterpret_cast<const int*>(b + L.active);
+      F.loss = reinterpret_cast<double*>(b + L.ft);
+      F.grad = reinterpret_cast<float*>(b + L.gt);
+      F.loss_accepted = a.loss_accepted;
+      F.status = a.status;
+      F.alpha_accepted = a.alpha_accepted;
+    }
+    so[f] = F;
+    const long R = (long)d.P * d.J;
+    const long items[kGsCount] = {(long)d.P * d.C * d.J,
+                                  d.P,
+                                  (R + kPhaseCols - 1) / kPhaseCols,
+                                  (long)d.P * d.K * object_blocks(N, 1),
+                                  (R + 63) / 64,
+                                  (R + 47) / 48,
+                                  R * d.M};
+    for (int s = 0; s < kGsCount; ++s) {
+      totals[s] += items[s];
+      if (totals[s] > (1L << 30)) return MOMFBD_EUNSUPPORTED;
+      hb[(size_t)s * (n + 1) + f + 1] = (int)totals[s];
+    }
+    zc_max = std::max(zc_max, d.zc > 0 ? d.zc : d.C);
+    Mp_max = std::max(Mp_max, pl->Mp);
+    mt_max = std::max(mt_max, (d.M + 15) / 16);
+    rows += R;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return MOMFBD_EDEVICE;
+  if (cur != dev) return MOMFBD_EINVAL;
+  if (int st = pending_error()) return st;
+  momfbd_group_s* g = new (std::nothrow) momfbd_group_s();
+  if (!g) return MOMFBD_EDEVICE;
+  g->n = n;
+  g->N = N;
+  g->device = dev;
+  g->solver = params != nullptr;
+  if (params) g->params = *params;
+  g->hbegin = hb;
+  g->has_eval = has_eval;
+  g->zc_max = zc_max;
+  g->Mp_max = Mp_max;
+  g->mt_max = mt_max;
+  g->rows = rows;
+  const bool ok =
+      hipMalloc(&g->fd_eval, n * sizeof(FieldDesc)) == hipSuccess &&
+      hipMalloc(&g->fd_solve, n * sizeof(FieldDesc)) == hipSuccess &&
+      hipMalloc(&g->begin, hb.size() * sizeof(int)) == hipSuccess &&
+      hipMemcpy(g->fd_eval, ev.data(), n * sizeof(FieldDesc), hipMemcpyHostToDevice) ==
+          hipSuccess &&
+      hipMemcpy(g->fd_solve, so.data(), n * sizeof(FieldDesc), hipMemcpyHostToDevice) ==
+          hipSuccess &&
+      hipMemcpy(g->begin, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    group_free(g);
+    return MOMFBD_EDEVICE;
+  }
+  *out = g;
+  return MOMFBD_OK;
+}
+
+int momfbd_group_destroy(momfbd_group g) {
+  if (!g) return MOMFBD_OK;
+  group_free(g);
+  return MOMFBD_OK;
+}
+
+int momfbd_group_loss_grad(momfbd_group g, void* stream) {
+  if (!g) return MOMFBD_EINVAL;
+  for (int f = 0; f < g->n; ++f)
+    if (!g->has_eval[f]) return MOMFBD_EINVAL;
+  if (int st = pending_error()) return st;
+  return to_status(group_chain(g, g->fd_eval, (hipStream_t)stream));
+}
+
+int momfbd_group_lbfgs_rounds(momfbd_group g, int rounds, void* stream) {
+  if (!g || !g->solver || rounds < 0) return MOMFBD_EINVAL;
+  if (int st = pending_error()) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const FieldDesc* fd = g->fd_solve;
+  hipError_t e = hipSuccess;
+  for (int r = 0; e == hipSuccess && r < rounds; ++r) {
+    e = launch_lbfgs_prep_group(group_args(g, fd, kGsPatches), s);
+    if (e == hipSuccess) e = group_chain(g, fd, s);
+    if (e == hipSuccess)
+      e = launch_lbfgs_search_group(group_args(g, fd, kGsPatches), g->params.c1, g->params.c2,
+                                    g->params.max_evals, g->params.ftol, s);
+  }
+  if (e == hipSuccess) e = launch_lbfgs_publish_group(group_args(g, fd, kGsElems), s);
+  if (e == hipSuccess) e = launch_lbfgs_finish_group(group_args(g, fd, kGsPatches), s);
+  return to_status(e);
+}
+
+int momfbd_group_set_tuning(momfbd_group g, const momfbd_tuning* t) {
+  if (!g || !tuning_ok(t) || t->grad_waves != 4) return MOMFBD_EINVAL;
+  g->xcd_fwd = t->xcd_forward;
+  g->xcd_adj = t->xcd_adjoint;
+  g->grad_rt = t->grad_row_tiles == 3 ? 3 : 4;
+  g->grad_splits = t->grad_splits;
+  return MOMFBD_OK;
+}
+
+int momfbd_group_get_tuning(momfbd_group g, momfbd_tuning* t) {
+  if (!g || !t) return MOMFBD_EINVAL;
+  t->xcd_forward = g->xcd_fwd;
+  t->xcd_adjoint = g->xcd_adj;
+  t->object_pairs_per_thread = 1;
+  t->grad_waves = 4;
+  t->grad_splits = group_splits(g);
+  t->grad_row_tiles = g->grad_rt;
+  return MOMFBD_OK;
+}
+
+int momfbd_group_autotune(momfbd_group g, int reps, void* stream, momfbd_tuning* chosen) {
+  if (!g || reps < 1) return MOMFBD_EINVAL;
+  for (int f = 0; f < g->n; ++f)
+    if (!g->has_eval[f]) return MOMFBD_EINVAL;
+  if (int st = pending_error()) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreateWithFlags(&e0, hipEventReleaseToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&e1, hipEventReleaseToDevice) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return MOMFBD_EDEVICE;
+  }
+  int st = MOMFBD_OK;
+  auto timed = [&](float* ms) -> int {
+    if (group_chain(g, g->fd_eval, s) != hipSuccess) return MOMFBD_EDEVICE;
+    if (hipEventRecord(e0, s) != hipSuccess) return MOMFBD_EDEVICE;
+    for (int i = 0; i < reps; ++i)
+      if (group_chain(g, g->fd_eval, s) != hipSuccess) return MOMFBD_EDEVICE;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return MOMFBD_EDEVICE;
+    return MOMFBD_OK;
+  };
+  // the plan tuner's method: one knob at a time, candidates interleaved over
+  // three rounds, each keeping its fastest; the default first, replaced only
+  // by a value at least 1% faster
+  int* knobs[4] = {&g->xcd_adj, &g->xcd_fwd, &g->grad_rt, &g->grad_splits};
+  std::vector<int> values[4] = {{1, 0}, {0, 1}, {4, 3}, {}};
+  for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
+    if (k == 3) {
+      g->grad_splits = 0;
+      const int a = group_splits(g);
+      values[3] = {a};
+      for (int v = 1; v <= kMaxGradSplits; v *= 2)
+        if (v != a) values[3].push_back(v);
+    }
+    const int keep = *knobs[k];
+    std::vector<float> fastest(values[k].size(), 0.f);
+    for (int r = 0; r < 3 && st == MOMFBD_OK; ++r)
+      for (size_t i = 0; i < values[k].size(); ++i) {
+        *knobs[k] = values[k][i];
+        float ms = 0.f;
+        if ((st = timed(&ms))) break;
+        if (r == 0 || ms < fastest[i]) fastest[i] = ms;
+      }
+    if (st) {
+      *knobs[k] = keep;
+      break;
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < values[k].size(); ++i)
+      if (fastest[i] < 0.99f * fastest[best]) best = i;
+    *knobs[k] = values[k][best];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (chosen) momfbd_group_get_tuning(g, chosen);
+  return MOMFBD_OK;
+}
+
+}  // extern "C"

@@ -37,18 +37,21 @@ __device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) 
   a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
 }
 
+// Block `blk` of a field: plane blk / kBlocks = (patch, object), part
+// blk % kBlocks of that plane; its loss partial goes to loss_part[blk].
 template <int NN, int PPT>
-__global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, ChanTab ct,
-                                                LossArgs la, const int* __restrict__ active,
-                                                const float2* __restrict__ S,
-                                                float2* __restrict__ O,
-                                                double* __restrict__ loss_part) {
+__device__ __forceinline__ void object_block(int blk, int C, int J, int K, const ChanTab& ct,
+                                             const LossArgs& la,
+                                             const int* __restrict__ active,
+                                             const float2* __restrict__ S,
+                                             float2* __restrict__ O,
+                                             double* __restrict__ loss_part) {
   constexpr int HC = NN / 2 + 1;
   constexpr int kUnitF2 = NN * HC;
   constexpr int kPairs = kUnitF2 / 2;
   constexpr int kBlocks = object_blocks(NN, PPT);
   __shared__ double red[256];
-  const int plane = blockIdx.x / kBlocks, part = blockIdx.x % kBlocks;
+  const int plane = blk / kBlocks, part = blk % kBlocks;
   const int p = plane / K, k = plane % K;
   if (active && !active[p]) return;
   const int tid = threadIdx.x;
@@ -106,18 +109,52 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
     if (tid < s2) red[tid] += red[tid + s2];
     __syncthreads();
   }
-  if (tid == 0) loss_part[blockIdx.x] = red[0];
+  if (tid == 0) loss_part[blk] = red[0];
+}
+
+template <int NN, int PPT>
+__global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, ChanTab ct,
+                                                LossArgs la, const int* __restrict__ active,
+                                                const float2* __restrict__ S,
+                                                float2* __restrict__ O,
+                                                double* __restrict__ loss_part) {
+  object_block<NN, PPT>(blockIdx.x, C, J, K, ct, la, active, S, O, loss_part);
+}
+
+// Every (patch, object) plane of every field of a group (one pair per thread).
+template <int NN>
+__global__ __launch_bounds__(256) void k_object_group(GroupArgs ga) {
+  const int g = blockIdx.x;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  object_block<NN, 1>(g - ga.begin[f], F.d.C, F.d.J, F.d.K, F.ct, F.la, F.active, F.w.S, F.w.O,
+                      F.w.loss_pk);
 }
 
 // loss[p] = sum over objects and their blocks, in order
+__device__ __forceinline__ void loss_sum_patch(int p, int nper, const int* __restrict__ active,
+                                               const double* __restrict__ loss_part,
+                                               double* __restrict__ loss) {
+  if (active && !active[p]) return;
+  double s = 0.0;
+  for (int i = 0; i < nper; ++i) s += loss_part[(size_t)p * nper + i];
+  loss[p] = s;
+}
+
 __global__ __launch_bounds__(256) void k_loss_sum(int P, int nper, const int* __restrict__ active,
                                                   const double* __restrict__ loss_part,
                                                   double* __restrict__ loss) {
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= P || (active && !active[p])) return;
-  double s = 0.0;
-  for (int i = 0; i < nper; ++i) s += loss_part[(size_t)p * nper + i];
-  loss[p] = s;
+  if (p >= P) return;
+  loss_sum_patch(p, nper, active, loss_part, loss);
+}
+
+__global__ __launch_bounds__(256) void k_loss_sum_group(GroupArgs ga, int nb) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= ga.total) return;
+  const int f = group_field(ga, g);
+  const FieldDesc& F = ga.fd[f];
+  loss_sum_patch(g - ga.begin[f], F.d.K * nb, F.active, F.w.loss_pk, F.loss);
 }
 
 // gamma_k(u) = gamma0_k + lambda_k (4 sin^2(pi u_x/N) + 4 sin^2(pi u_y/N)) on
@@ -171,6 +208,32 @@ hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, c
   hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K * nb, active,
                      loss_pk, loss);
   return hipGetLastError();
+}
+
+hipError_t launch_object_group(int N, const GroupArgs& ga_blocks, const GroupArgs& ga_patches,
+                               hipStream_t s) {
+  const dim3 grid(ga_blocks.total);
+  if (N == 64)
+    hipLaunchKernelGGL(k_object_group<64>, grid, dim3(256), 0, s, ga_blocks);
+  else if (N == 96)
+    hipLaunchKernelGGL(k_object_group<96>, grid, dim3(256), 0, s, ga_blocks);
+  else
+    hipLaunchKernelGGL(k_object_group<128>, grid, dim3(256), 0, s, ga_blocks);
+  hipLaunchKernelGGL(k_loss_sum_group, dim3((ga_patches.total + 255) / 256), dim3(256), 0, s,
+                     ga_patches, object_blocks(N, 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_group(int N, const GroupArgs& ga, int xcd, hipStream_t s) {
+  return N == 64   ? launch_forward64_group(ga, xcd, s)
+         : N == 96 ? launch_forward96_group(ga, xcd, s)
+                   : launch_forward128_group(ga, xcd, s);
+}
+
+hipError_t launch_adjoint_group(int N, const GroupArgs& ga, int xcd, hipStream_t s) {
+  return N == 64   ? launch_adjoint64_group(ga, xcd, s)
+         : N == 96 ? launch_adjoint96_group(ga, xcd, s)
+                   : launch_adjoint128_group(ga, xcd, s);
 }
 
 hipError_t launch_forward(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,

@@ -86,3 +86,93 @@ def test_uneven_fields_in_one_graph(dev):
         assert_grad_close(grad.cpu().numpy()[[p]], ref["grad"], f"field {i}")
     eager.close()
     graph.close()
+
+
+def _set_alpha(fields, problems, seed):
+    rng = np.random.default_rng(seed)
+    for f, (pr, _) in zip(fields, problems):
+        a = (pr.alpha_true + 0.3 * rng.standard_normal(pr.alpha_true.shape)).astype(np.float32)
+        f.alpha.copy_(torch.from_numpy(a))
+
+
+def test_group_evaluation_equals_each_plan(dev):
+    """One launch per stage over every field of a patch size gives each
+    field's loss and gradient bit for bit as its own plan does (same
+    gradient splits), and they match the oracle on a sampled patch."""
+    from paper_2505_10639_amd.batch import FieldGroup
+    problems = make_problems()
+    fields = make_fields(dev, problems)
+    _set_alpha(fields, problems, 5)
+    groups = {}
+    for f in fields:
+        groups.setdefault(f.plan.N, []).append(f)
+    for N, fs in sorted(groups.items()):
+        g = FieldGroup(fs)
+        from paper_2505_10639_amd import _lib
+        _lib.momfbd_group_set_tuning(g.handle, 0, 1, grad_splits=1, grad_row_tiles=4)
+        print(f"[group] N={N}: {len(fs)} fields", flush=True)
+        g.loss_grad()
+        torch.cuda.synchronize()
+        for f in fs:
+            f.plan.set_tuning(0, 1, 1, 4, 1)
+            loss, grad = f.plan.loss_grad(f.alpha, f.D, f.gamma)
+            torch.cuda.synchronize()
+            assert torch.equal(f.loss_eval, loss), (N, (f.loss_eval - loss).abs().max())
+            assert torch.equal(f.grad_eval, grad), (N, (f.grad_eval - grad).abs().max())
+        # another schedule of the group: same losses, gradients to rounding
+        _lib.momfbd_group_set_tuning(g.handle, 1, 0, grad_splits=4, grad_row_tiles=3)
+        ref = [(f.loss_eval.clone(), f.grad_eval.clone()) for f in fs]
+        g.loss_grad()
+        torch.cuda.synchronize()
+        for f, (l0, g0) in zip(fs, ref):
+            assert torch.equal(f.loss_eval, l0)
+            assert float((f.grad_eval - g0).abs().max()) <= 1e-5 * float(g0.abs().max())
+        g.close()
+    for i, (f, (pr, D_np)) in enumerate(zip(fields, problems)):
+        p = (2 * i + 1) % pr.P
+        ref = oracle.evaluate(f.alpha.cpu().numpy(), D_np, pr.basis, pr.diversity, pr.pupil,
+                              pr.channel_object, pr.gamma, patches=[p])
+        assert abs(float(f.loss_eval[p]) - ref["loss"][0]) < LOSS_RTOL * abs(ref["loss"][0])
+        assert_grad_close(f.grad_eval.cpu().numpy()[[p]], ref["grad"], f"group field {i}")
+    for f in fields:
+        f.close()
+
+
+def test_group_rounds_equal_field_rounds_and_replay_from_a_graph(dev):
+    """Solver rounds of a group (one launch per stage per patch size) follow
+    each field's own solver rounds bit for bit, eagerly and replayed from a
+    HIP graph; sampled patches match the oracle at the accepted point."""
+    from paper_2505_10639_amd import _lib
+    from paper_2505_10639_amd.batch import FieldBatch
+    problems = make_problems()
+    per_field = FieldBatch(make_fields(dev, problems), rounds_per_launch=3, mode="branches")
+    for f in per_field.fields:
+        f.plan.set_tuning(0, 1, 1, 4, 1)
+    ref = []
+    for _ in range(3):
+        per_field.eager()
+        torch.cuda.synchronize()
+        ref.append([(f.accepted.clone(), f.solver.loss.clone(), f.solver.status.clone())
+                    for f in per_field.fields])
+    for mode_graph in (False, True):
+        grouped = FieldBatch(make_fields(dev, problems), rounds_per_launch=3, mode="group")
+        for g in grouped.groups:
+            _lib.momfbd_group_set_tuning(g.handle, 0, 1, grad_splits=1, grad_row_tiles=4)
+        if mode_graph:
+            grouped.capture()
+        for k in range(3):
+            print(f"[group rounds] graph={mode_graph} launch {k}", flush=True)
+            grouped.launch() if mode_graph else grouped.eager()
+            torch.cuda.synchronize()
+            for i, (f, (a, l, s)) in enumerate(zip(grouped.fields, ref[k])):
+                assert torch.equal(f.accepted, a), (mode_graph, k, i)
+                assert torch.equal(f.solver.loss, l), (mode_graph, k, i)
+                assert torch.equal(f.solver.status, s), (mode_graph, k, i)
+        if mode_graph:
+            for i, (f, (pr, D_np)) in enumerate(zip(grouped.fields, problems)):
+                p = i % pr.P
+                r = oracle.evaluate(f.accepted.cpu().numpy(), D_np, pr.basis, pr.diversity,
+                                    pr.pupil, pr.channel_object, pr.gamma, patches=[p])
+                assert abs(float(f.solver.loss[p]) - r["loss"][0]) < LOSS_RTOL * abs(r["loss"][0])
+        grouped.close()
+    per_field.close()

@@ -25,7 +25,7 @@ OUT = os.path.join(PKG, "_build", "sanitize")
 SANITIZED = ["momfbd_api.hip", "object.hip", "lbfgs.hip", "postproc.hip", "cnn.hip",
              "spectra.hip"]
 # taken from the regular build: host code that only sets up launches
-REGULAR = ["kernels64.o", "kernels96.o", "kernels128.o", "gemm_mfma.o"]
+REGULAR = ["kernels64.o", "kernels96.o", "kernels128.o", "gemm_mfma.o", "gemm_group.o"]
 # host side only: each sanitizer flag applies to the host compilation
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=undefined",

@@ -178,7 +178,7 @@ def test_binding_structs_match_the_header():
     same order (the library reads them by position)."""
     from paper_2505_10639_amd import _lib
     text = open(HEADER).read()
-    for cname in ("momfbd_tuning", "momfbd_desc"):
+    for cname in ("momfbd_tuning", "momfbd_desc", "momfbd_field"):
         body = re.search(r"typedef struct\s*\{((?:(?!typedef struct).)*?)\}\s*" + cname + r"\s*;",
                          text, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
