@@ -368,7 +368,7 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     import torch
 
     import synth
-    from paper_2505_10639_amd import Plan
+    from paper_2505_10639_amd import Plan, _lib
     from paper_2505_10639_amd.batch import Field, FieldBatch
 
     rng = np.random.default_rng(synth.SEED_ROOT + 8)
@@ -425,11 +425,18 @@ def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     out["ms_per_round_group_eager"] = 1e3 * timed(grouped, False)
     grouped.close()
     grouped = FieldBatch(fields(), mode="group")
-    for g, sch in zip(grouped.groups, out["group_schedules"].values()):
-        from paper_2505_10639_amd import _lib
+    for g in grouped.groups:
+        sch = out["group_schedules"][str(g.N)]
         _lib.momfbd_group_set_tuning(g.handle, sch["xcd_forward"], sch["xcd_adjoint"],
                                      sch["grad_splits"], sch["grad_row_tiles"])
     out["ms_per_round_group_graph"] = 1e3 * timed(grouped, True)
+    grouped.close()
+    grouped = FieldBatch(fields(), mode="group", parallel_sizes=False)
+    for g in grouped.groups:
+        sch = out["group_schedules"][str(g.N)]
+        _lib.momfbd_group_set_tuning(g.handle, sch["xcd_forward"], sch["xcd_adjoint"],
+                                     sch["grad_splits"], sch["grad_row_tiles"])
+    out["ms_per_round_group_graph_one_stream"] = 1e3 * timed(grouped, True)
     grouped.close()
     branches = FieldBatch(fields(), mode="branches")
     out["ms_per_round_field_branches_graph"] = 1e3 * timed(branches, True)

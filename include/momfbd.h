@@ -485,7 +485,7 @@ typedef struct {
  * that only evaluates.  Allocates the group's device tables.
  * Errors: EINVAL (NULL, mixed N or devices, bad params), EWORKSPACE (a
  * field's workspace or state missing, misaligned or short), EUNSUPPORTED
- * (more than 2^30 work items in one stage), EDEVICE. */
+ * (more than 2^28 work items in one stage), EDEVICE. */
 int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_params* params,
                         momfbd_group* out);
 int momfbd_group_destroy(momfbd_group group);

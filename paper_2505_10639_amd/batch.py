@@ -101,7 +101,8 @@ class FieldGroup:
 class FieldBatch:
     """Solver rounds of many fields, eagerly or replayed from one HIP graph."""
 
-    def __init__(self, fields, rounds_per_launch=1, branches=4, mode="group"):
+    def __init__(self, fields, rounds_per_launch=1, branches=4, mode="group",
+                 parallel_sizes=True):
         if mode not in ("group", "branches"):
             raise ValueError("mode is 'group' or 'branches'")
         self.fields = list(fields)
@@ -113,8 +114,10 @@ class FieldBatch:
             by_n = {}
             for f in self.fields:
                 by_n.setdefault(f.plan.N, []).append(f)
-            self.groups = [FieldGroup(by_n[n]) for n in sorted(by_n)]
-            self.branches = len(self.groups)
+            # largest patch size first: its kernels need the most LDS per
+            # workgroup and are the last to find room beside the others
+            self.groups = [FieldGroup(by_n[n]) for n in sorted(by_n, reverse=True)]
+            self.branches = len(self.groups) if parallel_sizes else 1
         else:
             self.groups = []
             self.branches = max(1, int(branches))

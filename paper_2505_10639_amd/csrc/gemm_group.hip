@@ -17,34 +17,32 @@ __device__ __forceinline__ int zc_of(const Dims& d) { return d.zc > 0 ? d.zc : d
 
 // grid (4 * largest zc, phase tiles of all fields)
 __global__ __launch_bounds__(256) void k_phase_group(GroupArgs ga) {
-  const int g = blockIdx.y;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
+  const int2 it = ga.item[blockIdx.y];
+  const FieldDesc& F = ga.fd[it.x];
   const int zc = zc_of(F.d);
   if ((int)blockIdx.x >= 4 * zc) return;
-  contract::phase_block(blockIdx.x, g - ga.begin[f], F.d.P * F.d.J, F.d.J, F.d.C, zc, F.d.M,
+  contract::phase_block(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc, F.d.M,
                         F.Mp, F.d.bandpix(), F.ZtT, F.thetat, F.alpha, F.w.phi);
 }
 
 // grid (row tiles of all fields, splits); W = 4 waves, RT row tiles each
 template <int MT, int RT>
 __global__ __launch_bounds__(256) void k_grad_group(GroupArgs ga) {
-  const int g = blockIdx.x;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  contract::grad_block<MT, RT, 4, 2, -1>(g - ga.begin[f], blockIdx.y, gridDim.y,
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  contract::grad_block<MT, RT, 4, 2, -1>(it.y, blockIdx.y, gridDim.y,
                                          (F.d.M + 15) / 16, F.d.P * F.d.J, F.d.J, F.d.C,
                                          zc_of(F.d), F.d.M, F.d.bandpix(), F.Zt, F.w.gphi,
                                          F.grad, F.w.gpart);
 }
 
-// grad = 2 pi (part[0] + ... + part[splits-1]) per field, in split order
+// grad = 2 pi (part[0] + ... + part[splits-1]) per field, in split order;
+// blocks of 256 coefficients of one field
 __global__ __launch_bounds__(256) void k_grad_combine_group(GroupArgs ga, int splits) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  const long n = (long)F.d.P * F.d.J * F.d.M, i = g - ga.begin[f];
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  const long n = (long)F.d.P * F.d.J * F.d.M, i = (long)it.y * 256 + threadIdx.x;
+  if (i >= n) return;
   float v = F.w.gpart[i];
   for (int s = 1; s < splits; ++s) v += F.w.gpart[(size_t)s * n + i];
   F.grad[i] = 6.283185307179586f * v;
@@ -72,7 +70,8 @@ hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mp_max, hipSt
   return hipGetLastError();
 }
 
-// ga_tiles: row tiles of 16 * row_tiles rows per field; ga_elems: P J M per field
+// ga_tiles: row tiles of 16 * row_tiles rows per field; ga_elems: blocks of
+// 256 of the P J M coefficients per field
 hipError_t launch_grad_group(const GroupArgs& ga_tiles, const GroupArgs& ga_elems, int mt_max,
                              int row_tiles, int splits, hipStream_t s) {
   switch (mt_max) {
@@ -85,8 +84,8 @@ hipError_t launch_grad_group(const GroupArgs& ga_tiles, const GroupArgs& ga_elem
     default: return hipErrorInvalidValue;
   }
   if (splits > 1)
-    hipLaunchKernelGGL(k_grad_combine_group, dim3((ga_elems.total + 255) / 256), dim3(256), 0, s,
-                       ga_elems, splits);
+    hipLaunchKernelGGL(k_grad_combine_group, dim3(ga_elems.total), dim3(256), 0, s, ga_elems,
+                       splits);
   return hipGetLastError();
 }
 

@@ -135,9 +135,8 @@ struct LbfgsLayout {
 // rounds run together, one launch per stage for all of them.  Each field
 // keeps its own plan tables, data, workspace and solver state; FieldDesc
 // holds every per-field argument of the kernels in device memory.  Per
-// stage the group keeps the prefix sums of the work items (units, patches,
-// ...) over its fields: work item g of a launch belongs to the field f with
-// begin[f] <= g < begin[f + 1] and is item g - begin[f] of that field.
+// stage the group keeps an item map: work item g of a launch (a block, or
+// a unit) is item map[g].y of field map[g].x, one load away.
 struct FieldDesc {
   Dims d;
   int Mp;                  // modes rounded up to 16 (rows of the basis tables)
@@ -160,23 +159,14 @@ struct FieldDesc {
 };
 // work items per field: units P C J; patches P; phase tiles of 32 (patch,
 // frame) rows; object blocks P K object_blocks(N); gradient row tiles of
-// 64 or 48 rows; coefficients P J M
+// 64 or 48 rows; blocks of 256 patches; blocks of 256 coefficients (P J M)
 enum GroupStage { kGsUnits, kGsPatches, kGsPhaseTiles, kGsObjBlocks, kGsGradTiles4,
-                  kGsGradTiles3, kGsElems, kGsCount };
+                  kGsGradTiles3, kGsPatchBlocks, kGsElemBlocks, kGsCount };
 struct GroupArgs {
-  const FieldDesc* fd;     // [nf] (device)
-  const int* begin;        // [nf + 1] prefix sums of one stage's work items (device)
-  int nf, total;
+  const FieldDesc* fd;     // [fields] (device)
+  const int2* item;        // [total] (field, item of that field) per work item (device)
+  int total;
 };
-// The field of work item g (0 <= g < total): binary search over the prefix sums.
-__device__ __forceinline__ int group_field(const GroupArgs& ga, int g) {
-  int lo = 0, hi = ga.nf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (ga.begin[mid] <= g) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // The gradient contraction's pixel sum may be split over up to this many
 // blocks per row tile; grad_splits_of gives the plan's split count.

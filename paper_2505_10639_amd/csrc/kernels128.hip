@@ -126,9 +126,9 @@ __global__ __launch_bounds__(kThreads) void k_forward128_group(GroupArgs ga, int
   const int per = (ga.total + kXcds - 1) / kXcds;
   const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  forward128_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  forward128_unit<false>(it.y, F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
                         F.w.S);
 }
 
@@ -256,9 +256,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint128_group(GroupArgs ga, int
   const int per = (ga.total + kXcds - 1) / kXcds;
   const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  adjoint128_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  adjoint128_unit(it.y, F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
                   F.w.S, F.w.O, F.w.gphi);
 }
 

@@ -154,9 +154,9 @@ __global__ __launch_bounds__(64) void k_forward64(int units, int xcd, ChanTab ct
 __global__ __launch_bounds__(64) void k_forward64_group(GroupArgs ga, int xcd) {
   const int g = xcd ? xcd_unit(xcd_per(ga.total)) : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  forward64_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  forward64_unit<false>(it.y, F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
                         F.w.S);
 }
 
@@ -257,9 +257,9 @@ __global__ __launch_bounds__(64) void k_adjoint64(int units, int xcd, ChanTab ct
 __global__ __launch_bounds__(64) void k_adjoint64_group(GroupArgs ga, int xcd) {
   const int g = xcd ? xcd_unit(xcd_per(ga.total)) : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  adjoint64_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  adjoint64_unit(it.y, F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
                  F.w.S, F.w.O, F.w.gphi);
 }
 

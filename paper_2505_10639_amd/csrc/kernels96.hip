@@ -120,9 +120,9 @@ __global__ __launch_bounds__(kThreads) void k_forward96_group(GroupArgs ga, int 
   const int per = (ga.total + kXcds - 1) / kXcds;
   const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  forward96_unit<false>(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  forward96_unit<false>(it.y, F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
                         F.w.S);
 }
 
@@ -216,9 +216,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const int per = (ga.total + kXcds - 1) / kXcds;
   const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  adjoint96_unit(g - ga.begin[f], F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
+  const int2 it = ga.item[g];
+  const FieldDesc& F = ga.fd[it.x];
+  adjoint96_unit(it.y, F.ct, F.d.C, F.d.J, F.d.K, F.la, F.active, F.Ab, F.w.phi,
                   F.w.S, F.w.O, F.w.gphi);
 }
 

@@ -338,10 +338,9 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_prep(LbfgsLayout L, void* st
 
 // Every patch of every field of a group.
 __global__ __launch_bounds__(kThreads) void k_lbfgs_prep_group(GroupArgs ga) {
-  const int g = blockIdx.x;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  prep_patch(g - ga.begin[f], F.L, F.state, F.alpha);
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  prep_patch(it.y, F.L, F.state, F.alpha);
 }
 
 __device__ __forceinline__ void search_patch(int p, const LbfgsLayout& L, void* state,
@@ -470,10 +469,9 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_search(LbfgsLayout L, void* 
 __global__ __launch_bounds__(kThreads) void k_lbfgs_search_group(GroupArgs ga, double c1,
                                                                  double c2, int max_evals,
                                                                  double ftol) {
-  const int g = blockIdx.x;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  search_patch(g - ga.begin[f], F.L, F.state, F.alpha, -1, c1, c2, max_evals, ftol);
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  search_patch(it.y, F.L, F.state, F.alpha, -1, c1, c2, max_evals, ftol);
 }
 
 // The accepted point of every patch: x0 while inside a line search.
@@ -497,26 +495,24 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_finish(int P, LbfgsLayout L,
   if (status_out) status_out[p] = v.hdr[p].status;
 }
 
-// The accepted point of element g of the group's coefficients.
+// The accepted point of the group's coefficients, blocks of 256 of one field.
 __global__ __launch_bounds__(kThreads) void k_lbfgs_publish_group(GroupArgs ga) {
-  const int g = blockIdx.x * kThreads + threadIdx.x;
-  if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  if (!F.alpha_accepted) return;
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  const long i = (long)it.y * kThreads + threadIdx.x;
+  if (!F.alpha_accepted || i >= (long)F.d.P * F.L.n) return;
   View v = view(F.L, F.state);
-  const long i = g - ga.begin[f];
   const int p = (int)(i / F.L.n);
   F.alpha_accepted[i] = v.active[p] ? v.x0[i] : F.alpha[i];
 }
 
+// blocks of 256 patches of one field
 __global__ __launch_bounds__(kThreads) void k_lbfgs_finish_group(GroupArgs ga) {
-  const int g = blockIdx.x * kThreads + threadIdx.x;
-  if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  const int p = it.y * kThreads + threadIdx.x;
+  if (p >= F.d.P) return;
   View v = view(F.L, F.state);
-  const int p = g - ga.begin[f];
   if (F.loss_accepted) F.loss_accepted[p] = v.hdr[p].f;
   if (F.status) F.status[p] = v.hdr[p].status;
 }
@@ -594,14 +590,14 @@ hipError_t launch_lbfgs_search_group(const GroupArgs& ga, double c1, double c2, 
 }
 
 hipError_t launch_lbfgs_publish_group(const GroupArgs& ga_elems, hipStream_t s) {
-  hipLaunchKernelGGL(k_lbfgs_publish_group, dim3((ga_elems.total + kThreads - 1) / kThreads),
-                     dim3(kThreads), 0, s, ga_elems);
+  hipLaunchKernelGGL(k_lbfgs_publish_group, dim3(ga_elems.total), dim3(kThreads), 0, s,
+                     ga_elems);
   return hipGetLastError();
 }
 
 hipError_t launch_lbfgs_finish_group(const GroupArgs& ga_patches, hipStream_t s) {
-  hipLaunchKernelGGL(k_lbfgs_finish_group, dim3((ga_patches.total + kThreads - 1) / kThreads),
-                     dim3(kThreads), 0, s, ga_patches);
+  hipLaunchKernelGGL(k_lbfgs_finish_group, dim3(ga_patches.total), dim3(kThreads), 0, s,
+                     ga_patches);
   return hipGetLastError();
 }
 

@@ -894,8 +894,9 @@ struct momfbd_group_s {
   momfbd_lbfgs_params params{};
   FieldDesc* fd_eval = nullptr;   // device [n]: evaluation into the bound loss/grad
   FieldDesc* fd_solve = nullptr;  // device [n]: solver trial (state ft/gt, active flags)
-  int* begin = nullptr;           // device [kGsCount][n + 1]
-  std::vector<int> hbegin;        // host copy
+  int2* items = nullptr;          // device: the item maps of all stages, one after another
+  size_t item_off[kGsCount] = {};  // offset of each stage's map in `items`
+  int item_count[kGsCount] = {};   // work items of each stage
   std::vector<char> has_eval;     // per field: loss and grad bound
   int zc_max = 1, Mp_max = 16, mt_max = 1;
   long rows = 0;                  // (patch, frame) rows of all fields
@@ -907,9 +908,8 @@ namespace {
 GroupArgs group_args(const momfbd_group_s* g, const FieldDesc* fd, int stage) {
   GroupArgs a;
   a.fd = fd;
-  a.begin = g->begin + (size_t)stage * (g->n + 1);
-  a.nf = g->n;
-  a.total = g->hbegin[(size_t)stage * (g->n + 1) + g->n];
+  a.item = g->items + g->item_off[stage];
+  a.total = g->item_count[stage];
   return a;
 }
 
@@ -929,19 +929,19 @@ hipError_t group_chain(const momfbd_group_s* g, const FieldDesc* fd, hipStream_t
   if (e == hipSuccess) e = launch_forward_group(g->N, group_args(g, fd, kGsUnits), g->xcd_fwd, s);
   if (e == hipSuccess)
     e = launch_object_group(g->N, group_args(g, fd, kGsObjBlocks),
-                            group_args(g, fd, kGsPatches), s);
+                            group_args(g, fd, kGsPatchBlocks), s);
   if (e == hipSuccess) e = launch_adjoint_group(g->N, group_args(g, fd, kGsUnits), g->xcd_adj, s);
   if (e == hipSuccess)
     e = launch_grad_group(group_args(g, fd, g->grad_rt == 3 ? kGsGradTiles3 : kGsGradTiles4),
-                          group_args(g, fd, kGsElems), g->mt_max, g->grad_rt, group_splits(g),
-                          s);
+                          group_args(g, fd, kGsElemBlocks), g->mt_max, g->grad_rt,
+                          group_splits(g), s);
   return e;
 }
 
 void group_free(momfbd_group_s* g) {
   if (g->fd_eval) (void)hipFree(g->fd_eval);
   if (g->fd_solve) (void)hipFree(g->fd_solve);
-  if (g->begin) (void)hipFree(g->begin);
+  if (g->items) (void)hipFree(g->items);
   delete g;
 }
 
@@ -955,9 +955,8 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
   if (params && !lbfgs_params_ok(params)) return MOMFBD_EINVAL;
   const int N = fields[0].plan ? fields[0].plan->d.N : 0;
   const int dev = fields[0].plan ? fields[0].plan->device : -1;
-  long totals[kGsCount] = {0};
   std::vector<FieldDesc> ev(n), so(n);
-  std::vector<int> hb((size_t)kGsCount * (n + 1), 0);
+  std::vector<int2> maps[kGsCount];
   std::vector<char> has_eval(n, 0);
   int zc_max = 1, Mp_max = 16, mt_max = 1;
   long rows = 0;
@@ -1007,11 +1006,11 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
                                   (long)d.P * d.K * object_blocks(N, 1),
                                   (R + 63) / 64,
                                   (R + 47) / 48,
-                                  R * d.M};
+                                  (d.P + 255) / 256,
+                                  (R * d.M + 255) / 256};
     for (int s = 0; s < kGsCount; ++s) {
-      totals[s] += items[s];
-      if (totals[s] > (1L << 30)) return MOMFBD_EUNSUPPORTED;
-      hb[(size_t)s * (n + 1) + f + 1] = (int)totals[s];
+      if ((long)maps[s].size() + items[s] > (1L << 28)) return MOMFBD_EUNSUPPORTED;
+      for (long i = 0; i < items[s]; ++i) maps[s].push_back(make_int2(f, (int)i));
     }
     zc_max = std::max(zc_max, d.zc > 0 ? d.zc : d.C);
     Mp_max = std::max(Mp_max, pl->Mp);
@@ -1029,8 +1028,13 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
   g->device = dev;
   g->solver = params != nullptr;
   if (params) g->params = *params;
-  g->hbegin = hb;
   g->has_eval = has_eval;
+  std::vector<int2> all;
+  for (int st = 0; st < kGsCount; ++st) {
+    g->item_off[st] = all.size();
+    g->item_count[st] = (int)maps[st].size();
+    all.insert(all.end(), maps[st].begin(), maps[st].end());
+  }
   g->zc_max = zc_max;
   g->Mp_max = Mp_max;
   g->mt_max = mt_max;
@@ -1038,12 +1042,13 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
   const bool ok =
       hipMalloc(&g->fd_eval, n * sizeof(FieldDesc)) == hipSuccess &&
       hipMalloc(&g->fd_solve, n * sizeof(FieldDesc)) == hipSuccess &&
-      hipMalloc(&g->begin, hb.size() * sizeof(int)) == hipSuccess &&
+      hipMalloc(&g->items, all.size() * sizeof(int2)) == hipSuccess &&
       hipMemcpy(g->fd_eval, ev.data(), n * sizeof(FieldDesc), hipMemcpyHostToDevice) ==
           hipSuccess &&
       hipMemcpy(g->fd_solve, so.data(), n * sizeof(FieldDesc), hipMemcpyHostToDevice) ==
           hipSuccess &&
-      hipMemcpy(g->begin, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+      hipMemcpy(g->items, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice) ==
+          hipSuccess;
   if (!ok) {
     group_free(g);
     return MOMFBD_EDEVICE;
@@ -1079,8 +1084,8 @@ int momfbd_group_lbfgs_rounds(momfbd_group g, int rounds, void* stream) {
       e = launch_lbfgs_search_group(group_args(g, fd, kGsPatches), g->params.c1, g->params.c2,
                                     g->params.max_evals, g->params.ftol, s);
   }
-  if (e == hipSuccess) e = launch_lbfgs_publish_group(group_args(g, fd, kGsElems), s);
-  if (e == hipSuccess) e = launch_lbfgs_finish_group(group_args(g, fd, kGsPatches), s);
+  if (e == hipSuccess) e = launch_lbfgs_publish_group(group_args(g, fd, kGsElemBlocks), s);
+  if (e == hipSuccess) e = launch_lbfgs_finish_group(group_args(g, fd, kGsPatchBlocks), s);
   return to_status(e);
 }
 

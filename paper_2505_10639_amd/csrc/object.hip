@@ -124,10 +124,9 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
 // Every (patch, object) plane of every field of a group (one pair per thread).
 template <int NN>
 __global__ __launch_bounds__(256) void k_object_group(GroupArgs ga) {
-  const int g = blockIdx.x;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  object_block<NN, 1>(g - ga.begin[f], F.d.C, F.d.J, F.d.K, F.ct, F.la, F.active, F.w.S, F.w.O,
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  object_block<NN, 1>(it.y, F.d.C, F.d.J, F.d.K, F.ct, F.la, F.active, F.w.S, F.w.O,
                       F.w.loss_pk);
 }
 
@@ -149,12 +148,13 @@ __global__ __launch_bounds__(256) void k_loss_sum(int P, int nper, const int* __
   loss_sum_patch(p, nper, active, loss_part, loss);
 }
 
+// blocks of 256 patches of one field
 __global__ __launch_bounds__(256) void k_loss_sum_group(GroupArgs ga, int nb) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= ga.total) return;
-  const int f = group_field(ga, g);
-  const FieldDesc& F = ga.fd[f];
-  loss_sum_patch(g - ga.begin[f], F.d.K * nb, F.active, F.w.loss_pk, F.loss);
+  const int2 it = ga.item[blockIdx.x];
+  const FieldDesc& F = ga.fd[it.x];
+  const int p = it.y * 256 + threadIdx.x;
+  if (p >= F.d.P) return;
+  loss_sum_patch(p, F.d.K * nb, F.active, F.w.loss_pk, F.loss);
 }
 
 // gamma_k(u) = gamma0_k + lambda_k (4 sin^2(pi u_x/N) + 4 sin^2(pi u_y/N)) on
@@ -219,8 +219,8 @@ hipError_t launch_object_group(int N, const GroupArgs& ga_blocks, const GroupArg
     hipLaunchKernelGGL(k_object_group<96>, grid, dim3(256), 0, s, ga_blocks);
   else
     hipLaunchKernelGGL(k_object_group<128>, grid, dim3(256), 0, s, ga_blocks);
-  hipLaunchKernelGGL(k_loss_sum_group, dim3((ga_patches.total + 255) / 256), dim3(256), 0, s,
-                     ga_patches, object_blocks(N, 1));
+  hipLaunchKernelGGL(k_loss_sum_group, dim3(ga_patches.total), dim3(256), 0, s, ga_patches,
+                     object_blocks(N, 1));
   return hipGetLastError();
 }
 
