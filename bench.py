@@ -356,6 +356,103 @@ def warm_start_block(dev, steps, patches=961):
     }
 
 
+def warm_start_large_block(dev, steps, patches=128, batch=64, m_net=44):
+    """Learned warm start vs the plain zero start on the large multi-object
+    workload's shape: 128 x 128 patches, 24 frames, four objects at
+    lambda/lambda0 = 1.0/0.95/1.05/1.1 sharing the wavefront, 150 Zernike
+    modes, D/r0 = 15, smoothness prior; the first `patches` patches of the
+    2048^2 field (one GPU's share when 961 patches are spread over eight).
+    The network reads the wideband channel (lambda0) and predicts the lowest
+    `m_net` modes of the 24 frames (the others start at zero); it is trained
+    for `steps` Adam steps of `batch` single-channel bursts of the same
+    pupil, 150-mode wavefronts with D/r0 uniform in 10..20 and SNR 50..200,
+    made by the library's forward model and generator.  Plain and warm
+    starts are then timed as in the 64 x 64 block: L-BFGS solver rounds to
+    sum L <= 1.001 L_conv, inference included."""
+    import torch
+
+    import synth
+    from paper_2505_10639_amd import Plan
+    from paper_2505_10639_amd.warmstart import (BurstSource, WarmStartNet, mode_scale,
+                                                solve_rounds_until)
+
+    g = synth.config4_geometry()
+    pr = synth.config4_template()
+    N, C, J, M, K = g["N"], g["C"], g["J"], g["M"], g["K"]
+    P = patches
+    win = torch.from_numpy(pr.window).to(dev)
+    # data: the first P patches of the large field (rows of the patch grid)
+    rows = (P + g["nx"] - 1) // g["nx"]
+    H = (rows - 1) * g["stride"] + N
+    scenes = torch.from_numpy(np.ascontiguousarray(synth.config4_objects()[:, :H])).to(dev)
+    P_rows = rows * g["nx"]
+    aux = Plan(N, P_rows, 1, list(range(C)), pr.pupil, pr.basis[:, :1], None, dev)
+    Ohat = aux.prepare_data(scenes.reshape(C, 1, H, g["W"]).contiguous(), g["stride"], win)[:P]
+    aux.close()
+    a_true = torch.from_numpy(np.ascontiguousarray(synth.config4_alpha()[:P])).to(dev)
+    plan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis, None, dev)
+    _, S = plan.forward(a_true, want_psf=False)
+    noise = torch.empty((P, C, J, N, N), dtype=torch.float32, device=dev)
+    from paper_2505_10639_amd import _lib
+    _lib.momfbd_random_normal(synth.SEED_ROOT + 44, 1, 0, noise)
+    noise *= 0.01
+    # noise spectra through the data preparation of a one-column field
+    nplan = Plan(N, P, J, pr.channel_object, pr.pupil, pr.basis[:, :1], None, dev)
+    Nhat = nplan.prepare_data(noise.permute(1, 2, 0, 3, 4).reshape(C, J, P * N, N).contiguous(),
+                              N, win)
+    nplan.close()
+    D = (Ohat * S + Nhat).contiguous()
+    del S, Nhat, Ohat, noise, scenes
+    gamma = plan.smoothness_gamma([g["gamma"]] * K, [g["smooth"]] * K)
+    # the network: single-channel bursts of the wideband pupil
+    r0_range = (10.0, 20.0)
+    scale = mode_scale(m_net, r0_range)
+    rng = np.random.default_rng(synth.SEED_ROOT + 45)
+    train_scenes = [synth.object_field(rng, 1024, 1024) for _ in range(4)]
+    src = BurstSource(pr.pupil[:1], pr.basis[:1], pr.window, J, batch, train_scenes,
+                      crop_stride=32, seed=11, r0_range=r0_range, device=dev)
+    net = WarmStartNet(J, m_net, scale, batch_max=batch, device=dev, N=N)
+    net.init(seed=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        Db, ab = src.next()
+        loss = net.train_step(Db, ab[:, :, :m_net].contiguous(),
+                              1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 2e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    final_train = float(loss.cpu()[0])
+    src.close()
+    zero = torch.zeros((P, J, M), dtype=torch.float32, device=dev)
+    h_conv, t_conv, _, r_conv = solve_rounds_until(plan, zero, D, gamma, None, max_rounds=12000,
+                                                   chunk=8, stall=5, rtol=1e-10)
+    L_conv = h_conv[-1]
+    target = 1.001 * L_conv
+    hp, tp, _, rp = solve_rounds_until(plan, zero, D, gamma, target, max_rounds=12000, chunk=8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a0 = torch.zeros((P, J, M), dtype=torch.float32, device=dev)
+    a0[:, :, :m_net] = net.predict(D)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t1
+    hw, tw, _, rw = solve_rounds_until(plan, a0, D, gamma, target, max_rounds=12000, chunk=8)
+    L_true = float(plan.loss_grad(a_true, D, gamma)[0].sum())
+    plan.close()
+    net.close()
+    return {
+        "workload": f"{P} patches of the 2048^2 field: 128x128, 24 frames, 4 objects at "
+                    "lambda/lambda0 1.0/0.95/1.05/1.1, 150 modes, D/r0 15, smoothness prior; "
+                    f"network on the wideband channel, lowest {m_net} modes",
+        "train_steps": steps, "train_batch": batch, "train_bursts_per_s": steps * batch / t_train,
+        "train_s": t_train, "train_loss_final": final_train,
+        "L_conv": L_conv, "L_conv_rounds": r_conv, "L_conv_s": t_conv,
+        "L_zero": hp[0], "L_cnn": hw[0], "L_true": L_true,
+        "plain_s_to_1.001": tp, "plain_rounds": rp,
+        "warm_s_to_1.001": tw + t_inf, "warm_rounds": rw, "inference_s": t_inf,
+        "speedup": tp / (tw + t_inf),
+    }
+
+
 def uneven_fields_block(dev, n_fields=64, fov=512, rounds=20):
     """Independent 512^2 fields with patch sizes 64, 96 or 128 (stride N/2),
     frame counts 6..24, 44..88 modes and 1..3 objects (one channel each),
@@ -568,7 +665,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (for scaling "
                          "hardware byte counters) and exit")
-    ap.add_argument("--only", choices=["uneven", "warm", "large"],
+    ap.add_argument("--warm-large-steps", type=int, default=2000,
+                    help="training steps of the 128 x 128 warm-start network (0: skip)")
+    ap.add_argument("--only", choices=["uneven", "warm", "large", "warm_large"],
                     help="run one secondary block alone and print its JSON (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -595,6 +694,8 @@ def main():
             res = uneven_fields_block(dev)
         elif args.only == "warm":
             res = warm_start_block(dev, args.warm_steps)
+        elif args.only == "warm_large":
+            res = warm_start_large_block(dev, args.warm_large_steps)
         else:
             plan4, D4, alpha4, gamma4, g4 = build_large(dev)
             ms4, kern4, _, _, _ = time_steps(plan4, D4, alpha4, gamma4, max(2, args.steps // 2),
@@ -678,6 +779,10 @@ def main():
     if args.warm_steps > 0:
         log(f"warm start: {args.warm_steps} training steps, then time to converged loss")
         out["warm_start"] = warm_start_block(dev, args.warm_steps)
+
+    if args.warm_large_steps > 0 and not args.no_large:
+        log(f"warm start at the large workload's shape: {args.warm_large_steps} training steps")
+        out["warm_start_large"] = warm_start_large_block(dev, args.warm_large_steps)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

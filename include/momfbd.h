@@ -319,18 +319,37 @@ int momfbd_lbfgs_rounds(momfbd_plan plan, const momfbd_lbfgs_params* params, voi
  *   apod    [N][N] float (device)
  *   frames  [C][J][P*N][N] float (device): receives the noisy frames
  *   D       [P][C][J][N][N/2+1] complex64 (device): receives the spectra
- * N = 64 only (EUNSUPPORTED otherwise).  Errors: EINVAL, EWORKSPACE, EDEVICE. */
+ * Every patch size and channel count of the plan.  Errors: EINVAL,
+ * EWORKSPACE, EDEVICE. */
 int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const float* noise,
                       const float* sigma, const float* apod, float* frames, void* D, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* Standard normal draws for synthetic bursts (the noise of
+ * momfbd_synthesize, the network's initial weights): Philox4x32-10 (Salmon
+ * et al., SC 2011) with key = seed and counter = (counter0 + i/4, stream_id)
+ * as 64-bit halves, low word first, and the Box-Muller transform of each
+ * pair of words: draw i uses word i % 4 of block counter0 + i/4, paired with
+ * its neighbour (words 0,1 give cos and sin of one pair, words 2,3 of the
+ * next), u = ((x >> 8) + 1/2) 2^-24, r = sqrt(-2 ln u_first),
+ * angle 2 pi u_second.  A call of n draws from counter0 continues exactly
+ * where a call ending at counter0 stopped, when n is a multiple of 4.
+ *   out   [n] float (device) receives the draws
+ *   bits  [n] uint32 (device) receives the generator's word of each draw,
+ *         or NULL
+ * Errors: EINVAL (NULL, n = 0 or n > 2^40), EDEVICE. */
+int momfbd_random_normal(unsigned long long seed, unsigned long long stream_id,
+                         unsigned long long counter0, size_t n, float* out, unsigned int* bits,
+                         void* stream);
+
 /* Warm-start network: a 6-layer convolutional regressor from a burst of J
- * frames (64 x 64) to J x M modal coefficients (Noll j = 2..M+1), with
- * bfloat16 weights and activations and FP32 accumulation on the matrix
- * cores.  Layers: four 3x3 stride-2 convolutions (J->32->64->128->128
- * channels, ReLU), dense 2048->512 (ReLU), dense 512->J*M, times mode_scale.
- * The input of every burst is its data half spectra D [B][1][J][64][33]
- * (as for momfbd_loss_grad with one channel); the network sees the
+ * frames (N x N, N = 64, 96 or 128) to J x M modal coefficients (Noll
+ * j = 2..M+1, the lowest M modes of the solve), with bfloat16 weights and
+ * activations and FP32 accumulation on the matrix cores.  Layers: four 3x3
+ * stride-2 convolutions (J->32->64->128->128 channels, ReLU), dense
+ * 128 (N/16)^2 -> 512 (ReLU), dense 512->J*M, times mode_scale.
+ * The input of every burst is the first channel of its data half spectra
+ * D [B][C][J][N][N/2+1] (as for momfbd_loss_grad); the network sees the
  * apodized frames IDFT(D)/N^2, each divided by its mean.
  * Training loss per frame: sum over modes of mode_scale_m^2 / mean(
  * mode_scale^2) times the squared error in units of mode_scale, after
@@ -343,8 +362,10 @@ int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const
  * by the kernels, refreshed by momfbd_cnn_init, momfbd_cnn_load and
  * momfbd_cnn_adam. */
 typedef struct momfbd_cnn_s* momfbd_cnn;
-/* mode_scale HOST [M] > 0; J <= 64, J*M <= 1024; batch_max bursts per call. */
-int momfbd_cnn_create(int J, int M, int batch_max, const float* mode_scale, momfbd_cnn* out);
+/* mode_scale HOST [M] > 0; J <= 64, J*M <= 2048; batch_max bursts per call.
+ * Errors: EINVAL, EUNSUPPORTED (N), EDEVICE. */
+int momfbd_cnn_create(int N, int J, int M, int batch_max, const float* mode_scale,
+                      momfbd_cnn* out);
 int momfbd_cnn_destroy(momfbd_cnn net);
 int momfbd_cnn_sizes(momfbd_cnn net, size_t* n_params, size_t* workspace_bytes);
 /* params = normals * He standard deviation per weight (biases 0; the last
@@ -354,14 +375,15 @@ int momfbd_cnn_init(momfbd_cnn net, const float* normals, float* params, void* w
 /* refresh the workspace's bfloat16 weights from FP32 params */
 int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, size_t ws_bytes,
                     void* stream);
-/* alpha [B][J][M] float (device) predicted from D; B <= batch_max */
-int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, float* alpha,
-                       void* ws, size_t ws_bytes, void* stream);
+/* alpha [B][J][M] float (device) predicted from D [B][C][J][N][N/2+1]
+ * (channel 0 is read); B <= batch_max */
+int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, int C,
+                       float* alpha, void* ws, size_t ws_bytes, void* stream);
 /* loss (one FP64, device) and grad [n_params] (device) for targets
- * [B][J][M] float (device) */
-int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, const float* target,
-                         int B, double* loss, float* grad, void* ws, size_t ws_bytes,
-                         void* stream);
+ * [B][J][M] float (device); D as momfbd_cnn_forward */
+int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, int C,
+                         const float* target, int B, double* loss, float* grad, void* ws,
+                         size_t ws_bytes, void* stream);
 /* one Adam step (FP32 moments m1, m2 [n_params]; step >= 1) */
 int momfbd_cnn_adam(momfbd_cnn net, float* params, const float* grad, float* m1, float* m2,
                     int step, float lr, float beta1, float beta2, float eps, void* ws,

@@ -112,14 +112,14 @@ def lib():
         L.momfbd_power_spectrum.argtypes = [i, _vp, _vp, _vp, _vp, _vp, i, _vp, z, _vp]
         L.momfbd_lbfgs_rounds.argtypes = [_vp, ctypes.POINTER(momfbd_lbfgs_params), _vp, z, _vp,
                                           _vp, _vp, f, _vp, i, _vp, _vp, _vp, _vp, z, _vp]
-        L.momfbd_cnn_create.argtypes = [i, i, i, _vp, ctypes.POINTER(_vp)]
+        L.momfbd_cnn_create.argtypes = [i, i, i, i, _vp, ctypes.POINTER(_vp)]
         L.momfbd_cnn_destroy.argtypes = [_vp]
         L.momfbd_cnn_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(ctypes.c_size_t)]
         L.momfbd_cnn_init.argtypes = [_vp] * 4 + [z, _vp]
         L.momfbd_cnn_load.argtypes = [_vp] * 3 + [z, _vp]
-        L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, _vp, _vp, z, _vp]
-        L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, i, _vp, _vp, _vp, z, _vp]
+        L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, i, _vp, _vp, z, _vp]
+        L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, i, _vp, i, _vp, _vp, _vp, z, _vp]
         L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, z, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
@@ -131,6 +131,8 @@ def lib():
                                         _vp]
         L.momfbd_profile_stop.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_char_p),
                                           ctypes.POINTER(d), ctypes.POINTER(i)]
+        u64 = ctypes.c_ulonglong
+        L.momfbd_random_normal.argtypes = [u64, u64, u64, z, _vp, _vp, _vp]
         L.momfbd_group_create.argtypes = [ctypes.POINTER(momfbd_field), i, pp,
                                           ctypes.POINTER(_vp)]
         L.momfbd_group_destroy.argtypes = [_vp]
@@ -152,7 +154,8 @@ def lib():
                      "momfbd_plan_autotune", "momfbd_loss_grad_noalloc",
                      "momfbd_group_create", "momfbd_group_destroy", "momfbd_group_loss_grad",
                      "momfbd_group_lbfgs_rounds", "momfbd_group_set_tuning",
-                     "momfbd_group_get_tuning", "momfbd_group_autotune"):
+                     "momfbd_group_get_tuning", "momfbd_group_autotune",
+                     "momfbd_random_normal"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -351,10 +354,10 @@ def momfbd_synthesize(plan, alpha, O, noise, sigma, apod, frames, D, ws, stream=
                                    _stream(stream, alpha)), "momfbd_synthesize")
 
 
-def momfbd_cnn_create(J, M, batch_max, mode_scale):
+def momfbd_cnn_create(N, J, M, batch_max, mode_scale):
     sc = np.ascontiguousarray(mode_scale, np.float32)
     out = _vp()
-    _check(lib().momfbd_cnn_create(int(J), int(M), int(batch_max), sc.ctypes.data,
+    _check(lib().momfbd_cnn_create(int(N), int(J), int(M), int(batch_max), sc.ctypes.data,
                                    ctypes.byref(out)), "momfbd_cnn_create")
     return out.value
 
@@ -380,13 +383,14 @@ def momfbd_cnn_load(net, params, ws, stream=None):
            "momfbd_cnn_load")
 
 
-def momfbd_cnn_forward(net, params, D, B, alpha, ws, stream=None):
-    _check(lib().momfbd_cnn_forward(net, _ptr(params), _ptr(D), int(B), _ptr(alpha), _ptr(ws),
-                                    _nbytes(ws), _stream(stream, params)), "momfbd_cnn_forward")
+def momfbd_cnn_forward(net, params, D, B, C, alpha, ws, stream=None):
+    _check(lib().momfbd_cnn_forward(net, _ptr(params), _ptr(D), int(B), int(C), _ptr(alpha),
+                                    _ptr(ws), _nbytes(ws), _stream(stream, params)),
+           "momfbd_cnn_forward")
 
 
-def momfbd_cnn_loss_grad(net, params, D, target, B, loss, grad, ws, stream=None):
-    _check(lib().momfbd_cnn_loss_grad(net, _ptr(params), _ptr(D), _ptr(target), int(B),
+def momfbd_cnn_loss_grad(net, params, D, C, target, B, loss, grad, ws, stream=None):
+    _check(lib().momfbd_cnn_loss_grad(net, _ptr(params), _ptr(D), int(C), _ptr(target), int(B),
                                       _ptr(loss), _ptr(grad), _ptr(ws), _nbytes(ws),
                                       _stream(stream, params)),
            "momfbd_cnn_loss_grad")
@@ -492,3 +496,12 @@ def momfbd_group_autotune(group, reps, stream):
     _check(lib().momfbd_group_autotune(group, int(reps), stream, ctypes.byref(t)),
            "momfbd_group_autotune")
     return t.as_dict()
+
+
+def momfbd_random_normal(seed, stream_id, counter0, out, bits=None, stream=None):
+    """Fill the float32 device tensor `out` with standard normal draws (and
+    `bits`, uint32 as int32 storage, with the generator words) from the
+    library's counter-based generator."""
+    _check(lib().momfbd_random_normal(int(seed), int(stream_id), int(counter0), out.numel(),
+                                      _ptr(out), _ptr(bits), _stream(stream, out)),
+           "momfbd_random_normal")

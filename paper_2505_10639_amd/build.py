@@ -19,7 +19,7 @@ EMU = os.path.join(HERE, "libmomfbd_hostemu.so")
 
 ARCH = "gfx950"
 SOURCES = ["momfbd_api.hip", "kernels64.hip", "kernels96.hip", "kernels128.hip", "object.hip", "gemm_mfma.hip", "gemm_group.hip",
-           "lbfgs.hip", "postproc.hip", "cnn.hip", "spectra.hip"]
+           "lbfgs.hip", "postproc.hip", "cnn.hip", "spectra.hip", "rng.hip"]
 # Packed FP32 instructions are kept out of every code object; clang forms
 # them from ordinary float code otherwise.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

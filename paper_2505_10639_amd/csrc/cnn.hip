@@ -2,12 +2,13 @@
 // per-frame modal coefficients, trained and run on the matrix cores
 // (BF16 operands, FP32 accumulation: v_mfma_f32_16x16x16_bf16).
 //
-// Architecture (input: J frames of 64 x 64, NHWC with the frames as channels):
-//   conv 3x3 stride 2 pad 1, J -> 32, ReLU        64 -> 32
-//   conv 3x3 stride 2 pad 1, 32 -> 64, ReLU       32 -> 16
-//   conv 3x3 stride 2 pad 1, 64 -> 128, ReLU      16 -> 8
-//   conv 3x3 stride 2 pad 1, 128 -> 128, ReLU      8 -> 4
-//   dense 2048 -> 512, ReLU
+// Architecture (input: J frames of N x N, N = 64, 96 or 128, NHWC with the
+// frames as channels):
+//   conv 3x3 stride 2 pad 1, J -> 32, ReLU        N -> N/2
+//   conv 3x3 stride 2 pad 1, 32 -> 64, ReLU       N/2 -> N/4
+//   conv 3x3 stride 2 pad 1, 64 -> 128, ReLU      N/4 -> N/8
+//   conv 3x3 stride 2 pad 1, 128 -> 128, ReLU     N/8 -> N/16
+//   dense 128 (N/16)^2 -> 512, ReLU               (2048 at N = 64)
 //   dense 512 -> J*M (linear), times the per-mode scale
 // Convolutions are an explicit im2col followed by one GEMM; the backward
 // pass is two GEMMs per layer (weights: dZ^T col, data: dZ W) and a gather
@@ -232,31 +233,32 @@ __global__ __launch_bounds__(256) void k_colsum(int M, int N, const uint16_t* __
   if (tid == 0) db[n] = red[0];
 }
 
-// frames [B*J][64][64] FP32 -> NHWC bfloat16 [B][64][64][J]:
+// frames [B*J][npix] FP32 -> NHWC bfloat16 [B][npix][J]:
 // 10 (f / mean - 1) per frame; one block per frame
-__global__ __launch_bounds__(256) void k_norm_frames(int J, const float* __restrict__ f,
+__global__ __launch_bounds__(256) void k_norm_frames(int J, int npix, const float* __restrict__ f,
                                                      uint16_t* __restrict__ x) {
   __shared__ float red[256];
   const int u = blockIdx.x, tid = threadIdx.x;
   const int b = u / J, j = u % J;
-  const float* fu = f + (long)u * 4096;
+  const float* fu = f + (long)u * npix;
   float s = 0.f;
-  for (int i = tid; i < 4096; i += 256) s += fu[i];
+  for (int i = tid; i < npix; i += 256) s += fu[i];
   red[tid] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h) red[tid] += red[tid + h];
     __syncthreads();
   }
-  const float inv = 4096.f / red[0];
-  for (int i = tid; i < 4096; i += 256)
-    x[((long)b * 4096 + i) * J + j] = f2bf(10.f * (fu[i] * inv - 1.f));
+  const float inv = (float)npix / red[0];
+  for (int i = tid; i < npix; i += 256)
+    x[((long)b * npix + i) * J + j] = f2bf(10.f * (fu[i] * inv - 1.f));
 }
 
-constexpr int kMaxJM = 1024;
+constexpr int kMaxJM = 2048;
 
 // Per burst: scaled prediction alpha = z * scale, loss and dL/dz.
-// One block per burst; thread t handles (j, m) = (t / M, t % M).
+// One block per burst; thread t handles (j, m) = (t / M, t % M) for
+// t = tid, tid + 1024.
 __global__ __launch_bounds__(1024) void k_burst_loss(int B, int J, int M,
                                                      const float* __restrict__ z,
                                                      const float* __restrict__ target,
@@ -268,49 +270,54 @@ __global__ __launch_bounds__(1024) void k_burst_loss(int B, int J, int M,
   __shared__ float p[kMaxJM], q[kMaxJM], d1[kMaxJM], d2[kMaxJM], g[kMaxJM];
   __shared__ float e1[64], e2[64];
   __shared__ float tm[4];
-  const int b = blockIdx.x, t = threadIdx.x, JM = J * M;
-  const bool act = t < JM;
-  const int j = act ? t / M : 0, m = act ? t % M : 0;
+  const int b = blockIdx.x, tid = threadIdx.x, JM = J * M;
   // work in units of the per-mode scale (the network's own output units)
-  if (act) {
+  for (int t = tid; t < JM; t += 1024) {
     p[t] = z[(long)b * JM + t];
-    q[t] = target[(long)b * JM + t] / scale[m];
+    q[t] = target[(long)b * JM + t] / scale[t % M];
   }
   __syncthreads();
-  if (t < 4) {           // burst means of the two tilt modes
-    const int mm = t & 1;
-    const float* src = t < 2 ? p : q;
+  if (tid < 4) {           // burst means of the two tilt modes
+    const int mm = tid & 1;
+    const float* src = tid < 2 ? p : q;
     float s = 0.f;
     for (int jj = 0; jj < J; ++jj) s += src[jj * M + mm];
-    tm[t] = s / J;
+    tm[tid] = s / J;
   }
   __syncthreads();
-  float pv = 0.f, qv = 0.f, sg = 1.f;
-  if (act) {
-    pv = p[t] - (m < 2 ? tm[m] : 0.f);
-    qv = q[t] - (m < 2 ? tm[2 + m] : 0.f);
-    sg = even[m] ? -1.f : 1.f;
+  // tilt-centred values replace p and q (each element is read and written by
+  // its own thread only)
+  for (int t = tid; t < JM; t += 1024) {
+    const int m = t % M;
+    const float pv = p[t] - (m < 2 ? tm[m] : 0.f);
+    const float qv = q[t] - (m < 2 ? tm[2 + m] : 0.f);
+    const float sg = even[m] ? -1.f : 1.f;
     d1[t] = weight[m] * (pv - qv) * (pv - qv);
     d2[t] = weight[m] * (pv - sg * qv) * (pv - sg * qv);
+    p[t] = pv;
+    q[t] = qv;
   }
   __syncthreads();
-  if (t < J) {
+  if (tid < J) {
     float a = 0.f, c = 0.f;
     for (int mm = 0; mm < M; ++mm) {
-      a += d1[t * M + mm];
-      c += d2[t * M + mm];
+      a += d1[tid * M + mm];
+      c += d2[tid * M + mm];
     }
-    e1[t] = a;
-    e2[t] = c;
+    e1[tid] = a;
+    e2[tid] = c;
   }
   __syncthreads();
   const float inv = 1.f / ((float)B * J);
-  if (act) {
+  for (int t = tid; t < JM; t += 1024) {
+    const int j = t / M, m = t % M;
+    const float sg = even[m] ? -1.f : 1.f;
     const bool flip = e2[j] < e1[j];
-    g[t] = 2.f * weight[m] * (pv - (flip ? sg * qv : qv)) * inv;
+    g[t] = 2.f * weight[m] * (p[t] - (flip ? sg * q[t] : q[t])) * inv;
   }
   __syncthreads();
-  if (act) {
+  for (int t = tid; t < JM; t += 1024) {
+    const int m = t % M;
     float gv = g[t];
     if (m < 2) {
       float s = 0.f;
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_burst_loss(int B, int J, int M,
     }
     dz[(long)b * JM + t] = gv;
   }
-  if (t == 0) {
+  if (tid == 0) {
     double s = 0.0;
     for (int jj = 0; jj < J; ++jj) s += (double)fminf(e1[jj], e2[jj]);
     loss_b[b] = s * (double)inv;
@@ -382,7 +389,7 @@ struct Layer {
 };
 
 struct momfbd_cnn_s {
-  int J, M, batch_max;
+  int N, J, M, batch_max;
   long n_params;
   std::vector<Layer> layers;
   float* scale = nullptr;     // [M] device
@@ -422,20 +429,20 @@ hipError_t gemm(const momfbd_cnn_s* n, char* ws, int M, int N, int K, const uint
   return hipGetLastError();
 }
 
-// frames of the bursts: the apodized patches W(x - m) + m = IDFT(D) / N^2
-hipError_t frames_from_spectra(const momfbd_cnn_s* n, int B, const void* D, char* ws,
+// frames of the bursts' first channel: the apodized patches
+// W(x - m) + m = IDFT(D) / N^2 of D [B][C][J][N][N/2+1], channel 0
+hipError_t frames_from_spectra(const momfbd_cnn_s* n, int B, int C, const void* D, char* ws,
                                hipStream_t s) {
-  Dims d{64, B, 1, n->J, n->J, 1};
-  return launch_objimg64(d, static_cast<const float2*>(D), reinterpret_cast<float*>(ws + n->o_frames),
-                         s);
+  return launch_frames(n->N, B * n->J, n->J, C * n->J, static_cast<const float2*>(D),
+                       reinterpret_cast<float*>(ws + n->o_frames), s);
 }
 
-hipError_t run_forward(const momfbd_cnn_s* n, const float* params, const void* D, int B,
+hipError_t run_forward(const momfbd_cnn_s* n, const float* params, const void* D, int B, int C,
                        char* ws, hipStream_t s) {
-  hipError_t e = frames_from_spectra(n, B, D, ws, s);
+  hipError_t e = frames_from_spectra(n, B, C, D, ws, s);
   if (e != hipSuccess) return e;
   uint16_t* x0 = reinterpret_cast<uint16_t*>(ws + n->o_x0);
-  hipLaunchKernelGGL(k_norm_frames, dim3(B * n->J), dim3(256), 0, s, n->J,
+  hipLaunchKernelGGL(k_norm_frames, dim3(B * n->J), dim3(256), 0, s, n->J, n->N * n->N,
                      reinterpret_cast<const float*>(ws + n->o_frames), x0);
   const uint16_t* w16 = reinterpret_cast<const uint16_t*>(ws + n->o_w16);
   const uint16_t* h = x0;
@@ -487,20 +494,23 @@ int status_of(hipError_t e) { return e == hipSuccess ? MOMFBD_OK : MOMFBD_EDEVIC
 
 extern "C" {
 
-int momfbd_cnn_create(int J, int M, int batch_max, const float* mode_scale, momfbd_cnn* out) {
+int momfbd_cnn_create(int N, int J, int M, int batch_max, const float* mode_scale,
+                      momfbd_cnn* out) {
   if (!out || !mode_scale || J < 1 || M < 2 || batch_max < 1 || (long)J * M > kMaxJM ||
       J > 64)
     return MOMFBD_EINVAL;
+  if (N != 64 && N != 96 && N != 128) return MOMFBD_EUNSUPPORTED;
   for (int m = 0; m < M; ++m)
     if (!(mode_scale[m] > 0.f) || !std::isfinite(mode_scale[m])) return MOMFBD_EINVAL;
   momfbd_cnn_s* n = new (std::nothrow) momfbd_cnn_s();
   if (!n) return MOMFBD_EDEVICE;
+  n->N = N;
   n->J = J;
   n->M = M;
   n->batch_max = batch_max;
   const int chans[5] = {J, 32, 64, 128, 128};
   long off = 0;
-  int side = 64;
+  int side = N;
   for (int l = 0; l < 4; ++l) {
     Layer L{};
     L.conv = true;
@@ -516,7 +526,7 @@ int momfbd_cnn_create(int J, int M, int batch_max, const float* mode_scale, momf
     n->layers.push_back(L);
     side /= 2;
   }
-  const int dense_in[2] = {128 * 4 * 4, 512}, dense_out[2] = {512, J * M};
+  const int dense_in[2] = {128 * side * side, 512}, dense_out[2] = {512, J * M};
   for (int l = 0; l < 2; ++l) {
     Layer L{};
     L.conv = false;
@@ -535,9 +545,9 @@ int momfbd_cnn_create(int J, int M, int batch_max, const float* mode_scale, momf
   const long Bm = batch_max;
   size_t o = 0;
   n->o_frames = o;
-  o = al256(o + (size_t)Bm * J * 4096 * sizeof(float));
+  o = al256(o + (size_t)Bm * J * N * N * sizeof(float));
   n->o_x0 = o;
-  o = al256(o + (size_t)Bm * J * 4096 * sizeof(uint16_t));
+  o = al256(o + (size_t)Bm * J * N * N * sizeof(uint16_t));
   size_t max_dh = 0;
   for (int l = 0; l < 4; ++l) {
     const Layer& L = n->layers[l];
@@ -654,14 +664,14 @@ int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, size_t ws_byt
   return status_of(hipGetLastError());
 }
 
-int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, float* alpha,
-                       void* ws, size_t ws_bytes, void* stream) {
+int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, int C,
+                       float* alpha, void* ws, size_t ws_bytes, void* stream) {
   int st = check_net(net, ws, ws_bytes, B);
   if (st) return st;
-  if (!params || !D || !alpha) return MOMFBD_EINVAL;
+  if (!params || !D || !alpha || C < 1) return MOMFBD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
-  hipError_t e = run_forward(net, params, D, B, w, s);
+  hipError_t e = run_forward(net, params, D, B, C, w, s);
   if (e != hipSuccess) return MOMFBD_EDEVICE;
   const long n = (long)B * net->J * net->M;
   hipLaunchKernelGGL(k_scale_pred, dim3(blocks(n)), dim3(256), 0, s, n, net->M,
@@ -669,15 +679,15 @@ int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B
   return status_of(hipGetLastError());
 }
 
-int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, const float* target,
-                         int B, double* loss, float* grad, void* ws, size_t ws_bytes,
-                         void* stream) {
+int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, int C,
+                         const float* target, int B, double* loss, float* grad, void* ws,
+                         size_t ws_bytes, void* stream) {
   int st = check_net(net, ws, ws_bytes, B);
   if (st) return st;
-  if (!params || !D || !target || !loss || !grad) return MOMFBD_EINVAL;
+  if (!params || !D || !target || !loss || !grad || C < 1) return MOMFBD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
-  hipError_t e = run_forward(net, params, D, B, w, s);
+  hipError_t e = run_forward(net, params, D, B, C, w, s);
   if (e != hipSuccess) return MOMFBD_EDEVICE;
   const int J = net->J, M = net->M, JM = J * M;
   float* dh = reinterpret_cast<float*>(w + net->o_dh);

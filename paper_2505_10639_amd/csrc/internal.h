@@ -196,6 +196,23 @@ hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float*
 hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
                           const float* apod, float2* D, hipStream_t s);
 hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s);
+// frames IDFT(D)/N^2 of `items` half spectra: item it is spectrum
+// (it / per) * stride + it % per of D (channel 0 of bursts [B][C][J]: per = J,
+// stride = C J)
+hipError_t launch_frames(int N, int items, int per, int stride, const float2* D, float* out,
+                         hipStream_t s);
+hipError_t launch_synth(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                        const float* noise, const float* sigma, float* field, hipStream_t s);
+hipError_t launch_frames64(int items, int per, int stride, const float2* D, float* out,
+                           hipStream_t s);
+hipError_t launch_frames96(int items, int per, int stride, const float2* D, float* out,
+                           hipStream_t s);
+hipError_t launch_frames128(int items, int per, int stride, const float2* D, float* out,
+                            hipStream_t s);
+hipError_t launch_synth96(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                          const float* noise, const float* sigma, float* field, hipStream_t s);
+hipError_t launch_synth128(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                           const float* noise, const float* sigma, float* field, hipStream_t s);
 
 // per-size implementations
 hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,

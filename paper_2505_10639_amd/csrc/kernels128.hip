@@ -326,19 +326,21 @@ __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_objimg128(int items, const float2* __restrict__ O,
-                                                        float* __restrict__ obj) {
+// out = IDFT(A B) / N^2 + sg nz for one half spectrum A (times B when B is
+// given; plus sg times the noise image nz when nz is given).
+__device__ __forceinline__ void inverse_item(const float2* __restrict__ A,
+                                             const float2* __restrict__ B,
+                                             float* __restrict__ out,
+                                             const float* __restrict__ nz, float sg) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int it = blockIdx.x;
-  if (it >= items) return;
   const int lane = threadIdx.x;
-  const float2* Oi = O + (size_t)it * kUnitF2;
   float2 X[64];
   if (lane < 128) {
 #pragma unroll
-    for (int m = 0; m < 64; ++m) X[m] = Oi[sl_index(lane, m)];
-    Taux[lane] = Oi[sl_index64(lane)];
+    for (int m = 0; m < 64; ++m)
+      X[m] = B ? cmul(A[sl_index(lane, m)], B[sl_index(lane, m)]) : A[sl_index(lane, m)];
+    Taux[lane] = B ? cmul(A[sl_index64(lane)], B[sl_index64(lane)]) : A[sl_index64(lane)];
   }
   sync();
   if (lane < 128) op3_cols(X, Taux, T, lane);
@@ -353,11 +355,39 @@ __global__ __launch_bounds__(kThreads) void k_objimg128(int items, const float2*
     xget(reinterpret_cast<const float*>(T), lane, other);
     op3_rows_finish(keep, other, lane, g);
   }
-  float* row = obj + (size_t)it * N * N + (lane >> 1) * N;
-  const int e = lane & 1;
+  const int r = (lane >> 1) * N, e = lane & 1;
+  float* row = out + r;
   const float inv = 1.0f / (N * N);
 #pragma unroll
-  for (int m = 0; m < 64; ++m) row[2 * m + e] = g[m] * inv;
+  for (int m = 0; m < 64; ++m)
+    row[2 * m + e] = g[m] * inv + (nz ? sg * nz[r + 2 * m + e] : 0.f);
+}
+
+// Item it = (it / per, it % per), `stride` items between consecutive values
+// of it / per (object images: per = items, stride 0).
+__global__ __launch_bounds__(kThreads) void k_objimg128(int items, int per, int stride,
+                                                        const float2* __restrict__ O,
+                                                        float* __restrict__ obj) {
+  const int it = blockIdx.x;
+  if (it >= items) return;
+  inverse_item(O + ((size_t)(it / per) * stride + it % per) * kUnitF2, nullptr,
+               obj + (size_t)it * N * N, nullptr, 0.f);
+}
+
+// Synthetic frames i = IDFT(O_k S_u) / N^2 + sigma_p n_u into [C][J][P*N][N].
+__global__ __launch_bounds__(kThreads) void k_synth128(int units, int P, int C, int J, int K,
+                                                       ChanTab ct,
+                                                       const float2* __restrict__ O,
+                                                       const float2* __restrict__ S,
+                                                       const float* __restrict__ noise,
+                                                       const float* __restrict__ sigma,
+                                                       float* __restrict__ field) {
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int j = u % J, c = (u / J) % C, p = u / (J * C);
+  inverse_item(O + ((size_t)p * K + ct.chan_obj[c]) * kUnitF2, S + (size_t)u * kUnitF2,
+               field + ((size_t)(c * J + j) * P + p) * N * N, noise + (size_t)u * N * N,
+               sigma[p]);
 }
 
 }  // namespace
@@ -411,7 +441,21 @@ hipError_t launch_prepare128(const Dims& d, const float* frames, int H, int W, i
 
 hipError_t launch_objimg128(const Dims& d, const float2* O, float* obj, hipStream_t s) {
   const int items = d.P * d.K;
-  hipLaunchKernelGGL(k_objimg128, dim3(items), dim3(kThreads), 0, s, items, O, obj);
+  hipLaunchKernelGGL(k_objimg128, dim3(items), dim3(kThreads), 0, s, items, items, 0, O, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames128(int items, int per, int stride, const float2* D, float* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_objimg128, dim3(items), dim3(kThreads), 0, s, items, per, stride, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth128(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                           const float* noise, const float* sigma, float* field, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  hipLaunchKernelGGL(k_synth128, dim3(units), dim3(kThreads), 0, s, units, d.P, d.C, d.J, d.K,
+                     ct, O, S, noise, sigma, field);
   return hipGetLastError();
 }
 

@@ -312,30 +312,55 @@ __global__ __launch_bounds__(64) void k_prepare64(int units, int C, int J, int H
   out[sl_index32(lane)] = x32;
 }
 
-__global__ __launch_bounds__(64) void k_objimg64(int items, const float2* __restrict__ O,
-                                                 float* __restrict__ obj) {
+// out = IDFT(A B) / N^2 + sg nz for one half spectrum A (times B when B is
+// given; plus sg times the noise image nz when nz is given): the restored
+// object image, or a synthetic frame.
+__device__ __forceinline__ void inverse_item(const float2* __restrict__ A,
+                                             const float2* __restrict__ B,
+                                             float* __restrict__ out,
+                                             const float* __restrict__ nz, float sg) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int it = blockIdx.x;
-  if (it >= items) return;
   const int lane = threadIdx.x;
-  const float2* Oi = O + (size_t)it * kUnitF2;
   float2 X[32];
 #pragma unroll
-  for (int m = 0; m < 32; ++m) X[m] = Oi[sl_index(lane, m)];
-  op3_gather(Oi[sl_index32(lane)], Taux, lane);
+  for (int m = 0; m < 32; ++m)
+    X[m] = B ? cmul(A[sl_index(lane, m)], B[sl_index(lane, m)]) : A[sl_index(lane, m)];
+  op3_gather(B ? cmul(A[sl_index32(lane)], B[sl_index32(lane)]) : A[sl_index32(lane)], Taux,
+             lane);
   wave_sync();
   op3_cols(X, Taux, T, lane);
   wave_sync();
   float ge[32], go[32];
   op3_rows(T, lane, ge, go);
-  float* row = obj + (size_t)it * N * N + lane * N;
+  float* row = out + lane * N;
   const float inv = 1.0f / (N * N);
+  if (nz) {
+    const float* nr = nz + lane * N;
 #pragma unroll
-  for (int n = 0; n < 32; ++n) {
-    row[2 * n] = ge[n] * inv;
-    row[2 * n + 1] = go[n] * inv;
+    for (int n = 0; n < 32; ++n) {
+      row[2 * n] = ge[n] * inv + sg * nr[2 * n];
+      row[2 * n + 1] = go[n] * inv + sg * nr[2 * n + 1];
+    }
+  } else {
+#pragma unroll
+    for (int n = 0; n < 32; ++n) {
+      row[2 * n] = ge[n] * inv;
+      row[2 * n + 1] = go[n] * inv;
+    }
   }
+}
+
+// Item it = (it / per, it % per) of spectra laid out with `stride` items
+// between consecutive values of it / per (object images: per = items,
+// stride 0; channel 0 of bursts [B][C][J]: per = J, stride = C J).
+__global__ __launch_bounds__(64) void k_objimg64(int items, int per, int stride,
+                                                 const float2* __restrict__ O,
+                                                 float* __restrict__ obj) {
+  const int it = blockIdx.x;
+  if (it >= items) return;
+  inverse_item(O + ((size_t)(it / per) * stride + it % per) * kUnitF2, nullptr,
+               obj + (size_t)it * N * N, nullptr, 0.f);
 }
 
 // Synthetic frames: i = IDFT(O_k S_u) / N^2 + sigma_p n_u for unit u = (p, c, j),
@@ -347,32 +372,12 @@ __global__ __launch_bounds__(64) void k_synth64(int units, int P, int C, int J, 
                                                 const float* __restrict__ noise,
                                                 const float* __restrict__ sigma,
                                                 float* __restrict__ field) {
-  __shared__ float2 T[LDS_MAIN];
-  __shared__ float2 Taux[LDS_AUX];
   const int u = blockIdx.x;
   if (u >= units) return;
-  const int lane = threadIdx.x;
   const int j = u % J, c = (u / J) % C, p = u / (J * C);
-  const float2* Ok = O + ((size_t)p * K + ct.chan_obj[c]) * kUnitF2;
-  const float2* Su = S + (size_t)u * kUnitF2;
-  auto cmul = [](float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
-  float2 X[32];
-#pragma unroll
-  for (int m = 0; m < 32; ++m) X[m] = cmul(Ok[sl_index(lane, m)], Su[sl_index(lane, m)]);
-  op3_gather(cmul(Ok[sl_index32(lane)], Su[sl_index32(lane)]), Taux, lane);
-  wave_sync();
-  op3_cols(X, Taux, T, lane);
-  wave_sync();
-  float ge[32], go[32];
-  op3_rows(T, lane, ge, go);
-  const float inv = 1.0f / (N * N), sg = sigma[p];
-  const float* nz = noise + ((size_t)u * N + lane) * N;
-  float* row = field + (((size_t)(c * J + j) * P + p) * N + lane) * N;
-#pragma unroll
-  for (int n = 0; n < 32; ++n) {
-    row[2 * n] = ge[n] * inv + sg * nz[2 * n];
-    row[2 * n + 1] = go[n] * inv + sg * nz[2 * n + 1];
-  }
+  inverse_item(O + ((size_t)p * K + ct.chan_obj[c]) * kUnitF2, S + (size_t)u * kUnitF2,
+               field + ((size_t)(c * J + j) * P + p) * N * N, noise + (size_t)u * N * N,
+               sigma[p]);
 }
 
 }  // namespace
@@ -431,7 +436,13 @@ hipError_t launch_prepare64(const Dims& d, const float* frames, int H, int W, in
 
 hipError_t launch_objimg64(const Dims& d, const float2* O, float* obj, hipStream_t s) {
   const int items = d.P * d.K;
-  hipLaunchKernelGGL(k_objimg64, dim3(items), dim3(64), 0, s, items, O, obj);
+  hipLaunchKernelGGL(k_objimg64, dim3(items), dim3(64), 0, s, items, items, 0, O, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames64(int items, int per, int stride, const float2* D, float* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_objimg64, dim3(items), dim3(64), 0, s, items, per, stride, D, out);
   return hipGetLastError();
 }
 

@@ -280,20 +280,23 @@ __global__ __launch_bounds__(kThreads) void k_prepare96(int units, int C, int J,
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_objimg96(int items, const float2* __restrict__ O,
-                                                       float* __restrict__ obj) {
+// out = IDFT(A B) / N^2 + sg nz for one half spectrum A (times B when B is
+// given; plus sg times the noise image nz when nz is given).
+__device__ __forceinline__ void inverse_item(const float2* __restrict__ A,
+                                             const float2* __restrict__ B,
+                                             float* __restrict__ out,
+                                             const float* __restrict__ nz, float sg) {
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
-  const int it = blockIdx.x;
-  if (it >= items) return;
   const int lane = threadIdx.x;
   const bool on = lane < LANES;
-  const float2* Oi = O + (size_t)it * kUnitF2;
   float2 X[48];
   if (on) {
 #pragma unroll
-    for (int m = 0; m < 48; ++m) X[m] = Oi[sl_index(lane, m)];
-    op3_gather(Oi[sl_index48(lane)], Taux, lane);
+    for (int m = 0; m < 48; ++m)
+      X[m] = B ? cmul(A[sl_index(lane, m)], B[sl_index(lane, m)]) : A[sl_index(lane, m)];
+    op3_gather(B ? cmul(A[sl_index48(lane)], B[sl_index48(lane)]) : A[sl_index48(lane)], Taux,
+               lane);
   }
   sync();
   if (on) op3_cols(X, Taux, T, lane);
@@ -301,14 +304,41 @@ __global__ __launch_bounds__(kThreads) void k_objimg96(int items, const float2* 
   if (on) {
     float ge[48], go[48];
     op3_rows(T, lane, ge, go);
-    float* row = obj + (size_t)it * N * N + lane * N;
+    float* row = out + lane * N;
     const float inv = 1.0f / (N * N);
 #pragma unroll
     for (int n = 0; n < 48; ++n) {
-      row[2 * n] = ge[n] * inv;
-      row[2 * n + 1] = go[n] * inv;
+      row[2 * n] = ge[n] * inv + (nz ? sg * nz[lane * N + 2 * n] : 0.f);
+      row[2 * n + 1] = go[n] * inv + (nz ? sg * nz[lane * N + 2 * n + 1] : 0.f);
     }
   }
+}
+
+// Item it = (it / per, it % per), `stride` items between consecutive values
+// of it / per (object images: per = items, stride 0).
+__global__ __launch_bounds__(kThreads) void k_objimg96(int items, int per, int stride,
+                                                       const float2* __restrict__ O,
+                                                       float* __restrict__ obj) {
+  const int it = blockIdx.x;
+  if (it >= items) return;
+  inverse_item(O + ((size_t)(it / per) * stride + it % per) * kUnitF2, nullptr,
+               obj + (size_t)it * N * N, nullptr, 0.f);
+}
+
+// Synthetic frames i = IDFT(O_k S_u) / N^2 + sigma_p n_u into [C][J][P*N][N].
+__global__ __launch_bounds__(kThreads) void k_synth96(int units, int P, int C, int J, int K,
+                                                      ChanTab ct,
+                                                      const float2* __restrict__ O,
+                                                      const float2* __restrict__ S,
+                                                      const float* __restrict__ noise,
+                                                      const float* __restrict__ sigma,
+                                                      float* __restrict__ field) {
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int j = u % J, c = (u / J) % C, p = u / (J * C);
+  inverse_item(O + ((size_t)p * K + ct.chan_obj[c]) * kUnitF2, S + (size_t)u * kUnitF2,
+               field + ((size_t)(c * J + j) * P + p) * N * N, noise + (size_t)u * N * N,
+               sigma[p]);
 }
 
 }  // namespace
@@ -362,7 +392,21 @@ hipError_t launch_prepare96(const Dims& d, const float* frames, int H, int W, in
 
 hipError_t launch_objimg96(const Dims& d, const float2* O, float* obj, hipStream_t s) {
   const int items = d.P * d.K;
-  hipLaunchKernelGGL(k_objimg96, dim3(items), dim3(kThreads), 0, s, items, O, obj);
+  hipLaunchKernelGGL(k_objimg96, dim3(items), dim3(kThreads), 0, s, items, items, 0, O, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames96(int items, int per, int stride, const float2* D, float* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_objimg96, dim3(items), dim3(kThreads), 0, s, items, per, stride, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth96(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                          const float* noise, const float* sigma, float* field, hipStream_t s) {
+  const int units = d.P * d.C * d.J;
+  hipLaunchKernelGGL(k_synth96, dim3(units), dim3(kThreads), 0, s, units, d.P, d.C, d.J, d.K, ct,
+                     O, S, noise, sigma, field);
   return hipGetLastError();
 }
 

@@ -597,7 +597,6 @@ int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const
   int st = check_call(plan, ws, ws_bytes);
   if (st) return st;
   if (!alpha || !O || !noise || !sigma || !apod || !frames || !D) return MOMFBD_EINVAL;
-  if (plan->d.N != 64) return MOMFBD_EUNSUPPORTED;
   if ((st = pending_error())) return st;
   hipStream_t s = (hipStream_t)stream;
   const Workspace w = carve_workspace(plan->d, ws);
@@ -605,8 +604,8 @@ int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const
   hipError_t e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
   if (e == hipSuccess) e = launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
   if (e == hipSuccess)
-    e = launch_synth64(plan->d, plan->ct, static_cast<const float2*>(O), w.S, noise, sigma, frames,
-                       s);
+    e = launch_synth(plan->d, plan->ct, static_cast<const float2*>(O), w.S, noise, sigma, frames,
+                     s);
   if (e == hipSuccess)
     e = launch_prepare(plan->d, frames, plan->d.P * N, N, N, apod, static_cast<float2*>(D), s);
   return to_status(e);

@@ -258,6 +258,20 @@ hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int 
                      : launch_prepare128(d, frames, H, W, stride, apod, D, s);
 }
 
+hipError_t launch_frames(int N, int items, int per, int stride, const float2* D, float* out,
+                         hipStream_t s) {
+  return N == 64   ? launch_frames64(items, per, stride, D, out, s)
+         : N == 96 ? launch_frames96(items, per, stride, D, out, s)
+                   : launch_frames128(items, per, stride, D, out, s);
+}
+
+hipError_t launch_synth(const Dims& d, const ChanTab& ct, const float2* O, const float2* S,
+                        const float* noise, const float* sigma, float* field, hipStream_t s) {
+  return d.N == 64   ? launch_synth64(d, ct, O, S, noise, sigma, field, s)
+         : d.N == 96 ? launch_synth96(d, ct, O, S, noise, sigma, field, s)
+                     : launch_synth128(d, ct, O, S, noise, sigma, field, s);
+}
+
 hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s) {
   return d.N == 64   ? launch_objimg64(d, O, obj, s)
          : d.N == 96 ? launch_objimg96(d, O, obj, s)

@@ -2,8 +2,10 @@
 trained on bursts made by the library's own forward model
 (momfbd_synthesize), and used as the start point of the per-patch L-BFGS.
 
-All arithmetic runs in libmomfbd's kernels; this module allocates tensors,
-draws the random inputs (normals, uniforms) with torch, and sequences calls.
+All arithmetic runs in libmomfbd's kernels, random normals included
+(momfbd_random_normal); this module allocates tensors, draws the per-burst
+parameters (turbulence strength, noise level, scene crop) on the host from
+a seeded generator, and sequences calls.
 """
 
 from __future__ import annotations
@@ -17,15 +19,22 @@ from . import _lib
 from .plan import Plan, Solver
 
 
-class WarmStartNet:
-    """The network with its FP32 parameters, Adam moments and workspace."""
+# generator streams of the library's normal draws
+STREAM_INIT, STREAM_NOISE = 0x1417, 0x2050
 
-    def __init__(self, J, M, mode_scale, batch_max=256, device="cuda:0"):
+
+class WarmStartNet:
+    """The network with its FP32 parameters, Adam moments and workspace.
+    N: side of the input frames (64, 96 or 128); J frames; M modes (the
+    lowest M of the solve)."""
+
+    def __init__(self, J, M, mode_scale, batch_max=256, device="cuda:0", N=64):
         self.device = torch.device(device)
-        self.J, self.M, self.batch_max = int(J), int(M), int(batch_max)
+        self.N, self.J, self.M, self.batch_max = int(N), int(J), int(M), int(batch_max)
         self.mode_scale = np.asarray(mode_scale, np.float32)
         with torch.cuda.device(self.device):
-            self.handle = _lib.momfbd_cnn_create(self.J, self.M, self.batch_max, self.mode_scale)
+            self.handle = _lib.momfbd_cnn_create(self.N, self.J, self.M, self.batch_max,
+                                                 self.mode_scale)
             n_params, ws_bytes = _lib.momfbd_cnn_sizes(self.handle)
             self.n_params = n_params
             self.params = torch.zeros(n_params, dtype=torch.float32, device=self.device)
@@ -49,9 +58,8 @@ class WarmStartNet:
             pass
 
     def init(self, seed: int):
-        g = torch.Generator(device=self.device)
-        g.manual_seed(int(seed))
-        normals = torch.randn(self.n_params, generator=g, device=self.device)
+        normals = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _lib.momfbd_random_normal(int(seed), STREAM_INIT, 0, normals)
         _lib.momfbd_cnn_init(self.handle, normals, self.params, self.ws)
         self.m1.zero_()
         self.m2.zero_()
@@ -62,18 +70,19 @@ class WarmStartNet:
         _lib.momfbd_cnn_load(self.handle, self.params, self.ws)
 
     def predict(self, D):
-        """alpha [B][J][M] from data spectra D [B][1][J][64][33]."""
-        B = D.shape[0]
+        """alpha [B][J][M] from data spectra D [B][C][J][N][N/2+1] (the
+        network reads channel 0)."""
+        B, C = D.shape[0], D.shape[1]
         out = torch.empty((B, self.J, self.M), dtype=torch.float32, device=self.device)
         for b0 in range(0, B, self.batch_max):
             b1 = min(B, b0 + self.batch_max)
-            _lib.momfbd_cnn_forward(self.handle, self.params, D[b0:b1], b1 - b0, out[b0:b1],
+            _lib.momfbd_cnn_forward(self.handle, self.params, D[b0:b1], b1 - b0, C, out[b0:b1],
                                     self.ws)
         return out
 
     def loss_grad(self, D, target):
-        _lib.momfbd_cnn_loss_grad(self.handle, self.params, D, target, D.shape[0], self.loss,
-                                  self.grad, self.ws)
+        _lib.momfbd_cnn_loss_grad(self.handle, self.params, D, D.shape[1], target, D.shape[0],
+                                  self.loss, self.grad, self.ws)
         return self.loss, self.grad
 
     def train_step(self, D, target, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -85,38 +94,43 @@ class WarmStartNet:
 
 
 class BurstSource:
-    """Bursts of the single-object 64 x 64 forward model: object crops of
-    large k^-3 scenes (their spectra precomputed on the GPU), Kolmogorov
-    wavefronts with D/r0 uniform in [r_lo, r_hi], white noise with SNR
-    uniform in [snr_lo, snr_hi] (relative to the unit scene mean)."""
+    """Bursts of the single-object N x N forward model (one channel: the
+    given pupil and basis): object crops of large k^-3 scenes (their spectra
+    precomputed on the GPU), Kolmogorov wavefronts with D/r0 uniform in
+    [r_lo, r_hi], white noise with SNR uniform in [snr_lo, snr_hi] (relative
+    to the unit scene mean) drawn by the library's generator."""
 
     def __init__(self, pupil, basis, window, J, batch, scenes, crop_stride=16, seed=0,
                  r0_range=(4.0, 20.0), snr_range=(50.0, 200.0), device="cuda:0"):
         import synth
         self.device = torch.device(device)
+        self.N = int(np.asarray(pupil).shape[-1])
+        N, H2 = self.N, self.N // 2 + 1
         self.J, self.batch = int(J), int(batch)
         self.M = int(np.asarray(basis).shape[1])
         self.r0_range, self.snr_range = r0_range, snr_range
         self.rng = np.random.default_rng(seed)
-        self.gen = torch.Generator(device=self.device)
-        self.gen.manual_seed(int(seed) + 17)
-        self.plan = Plan(64, self.batch, self.J, [0], pupil, basis, None, self.device)
+        self.seed = int(seed)
+        self.counter = 0
+        self.plan = Plan(N, self.batch, self.J, [0], pupil, basis, None, self.device)
         self.window = torch.as_tensor(np.asarray(window, np.float32), device=self.device)
-        ones = torch.ones((64, 64), dtype=torch.float32, device=self.device)
+        self.noise = torch.empty((self.batch, 1, self.J, N, N), dtype=torch.float32,
+                                 device=self.device)
+        ones = torch.ones((N, N), dtype=torch.float32, device=self.device)
         banks = []
         for sc in scenes:
             H, W = sc.shape
-            ny, nx = (H - 64) // crop_stride + 1, (W - 64) // crop_stride + 1
-            aux = Plan(64, ny * nx, 1, [0], pupil, np.asarray(basis)[:, :1], None, self.device)
+            ny, nx = (H - N) // crop_stride + 1, (W - N) // crop_stride + 1
+            aux = Plan(N, ny * nx, 1, [0], pupil, np.asarray(basis)[:, :1], None, self.device)
             t = torch.as_tensor(np.asarray(sc, np.float32), device=self.device)
             banks.append(aux.prepare_data(t.reshape(1, 1, H, W).contiguous(), crop_stride, ones)
-                         .reshape(ny * nx, 1, 64, 33))
+                         .reshape(ny * nx, 1, N, H2))
             aux.close()
         self.bank = torch.cat(banks)
         self._draw = synth.draw_kolmogorov
 
     def next(self):
-        """(D [B][1][J][64][33], alpha [B][J][M]) of a fresh batch."""
+        """(D [B][1][J][N][N/2+1], alpha [B][J][M]) of a fresh batch."""
         B, J, M = self.batch, self.J, self.M
         r0 = self.rng.uniform(*self.r0_range, size=B)
         alpha = self._draw(self.rng, B * J, M, np.repeat(r0, J)).reshape(B, J, M)
@@ -125,8 +139,9 @@ class BurstSource:
         O = self.bank[idx].contiguous()
         snr = self.rng.uniform(*self.snr_range, size=B)
         sigma = torch.as_tensor((1.0 / snr).astype(np.float32), device=self.device)
-        noise = torch.randn((B, 1, J, 64, 64), generator=self.gen, device=self.device)
-        _, D = self.plan.synthesize(alpha, O, noise, sigma, self.window)
+        _lib.momfbd_random_normal(self.seed, STREAM_NOISE, self.counter, self.noise)
+        self.counter += self.noise.numel() // 4
+        _, D = self.plan.synthesize(alpha, O, self.noise, sigma, self.window)
         return D, alpha
 
     def close(self):

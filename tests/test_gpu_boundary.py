@@ -100,7 +100,7 @@ def test_short_workspace_and_state_leave_outputs_untouched(dev):
 def test_short_network_workspace(dev):
     from paper_2505_10639_amd import _lib
     L = _lib.lib()
-    net = _lib.momfbd_cnn_create(4, 10, 2, np.ones(10, np.float32))
+    net = _lib.momfbd_cnn_create(64, 4, 10, 2, np.ones(10, np.float32))
     n_params, need = _lib.momfbd_cnn_sizes(net)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     params = _filled((n_params,), torch.float32, dev, 0x11)

@@ -32,21 +32,27 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_synthesize_matches_oracle(dev):
+@pytest.mark.parametrize("N,channels,lam", [
+    (64, ((0, 0.0), (0, 1.0)), None),
+    (96, ((0, 0.0), (1, 0.0)), (1.0, 1.0 / 1.05)),
+    (128, ((0, 0.0), (1, 0.0), (2, 1.0)), (1.0, 1.0 / 0.95, 1.0 / 1.1))])
+def test_synthesize_matches_oracle(dev, N, channels, lam):
     from paper_2505_10639_amd import Plan
-    pr = synth.make_problem(80, N=64, P=3, J=5, M=20, channels=((0, 0.0), (0, 1.0)),
-                            d_over_r0=np.array([6.0, 10.0, 16.0]))
-    plan = Plan(64, pr.P, pr.J, pr.channel_object, pr.pupil, pr.basis, pr.diversity, dev)
+    pr = synth.make_problem(80 + N, N=N, P=3, J=5, M=20, channels=channels,
+                            d_over_r0=np.array([6.0, 10.0, 16.0]), lam_ratios=lam,
+                            border=N // 10)
+    plan = Plan(N, pr.P, pr.J, pr.channel_object, pr.pupil, pr.basis, pr.diversity, dev)
     rng = np.random.default_rng(3)
-    normals = rng.standard_normal((pr.P, pr.C, pr.J, 64, 64)).astype(np.float32)
+    normals = rng.standard_normal((pr.P, pr.C, pr.J, N, N)).astype(np.float32)
     sigma = np.array([0.01, 0.02, 0.005], np.float32)
-    O_in = np.fft.fft2(pr.objects)[..., :33].astype(np.complex64)       # input spectra
+    O_in = np.fft.fft2(pr.objects)[..., :N // 2 + 1].astype(np.complex64)   # input spectra
+    print(f"[synth] N={N} C={pr.C} K={pr.K}", flush=True)
     frames, D = plan.synthesize(torch.from_numpy(pr.alpha_true).to(dev),
                                 torch.from_numpy(O_in).to(dev), torch.from_numpy(normals).to(dev),
                                 torch.from_numpy(sigma).to(dev),
                                 torch.from_numpy(pr.window).to(dev))
     torch.cuda.synchronize()
-    frames = frames.cpu().numpy().reshape(pr.C, pr.J, pr.P, 64, 64).transpose(2, 0, 1, 3, 4)
+    frames = frames.cpu().numpy().reshape(pr.C, pr.J, pr.P, N, N).transpose(2, 0, 1, 3, 4)
     noise = normals.astype(np.float64) * sigma[:, None, None, None, None]
     ref = oracle.simulate_frames(pr.objects, pr.alpha_true, pr.basis, pr.diversity, pr.pupil,
                                  pr.channel_object, noise)
@@ -65,20 +71,32 @@ def _he_params(net, rng):
     return np.concatenate(out).astype(np.float32)
 
 
-def test_network_matches_oracle(dev):
+def _layers(N, J, M):
+    return [("conv", J, 32), ("conv", 32, 64), ("conv", 64, 128), ("conv", 128, 128),
+            ("dense", 128 * (N // 16) ** 2, 512), ("dense", 512, J * M)]
+
+
+@pytest.mark.parametrize("N,J,M,B,channels,tnoise,tseed", [
+    (64, 12, 44, 3, ((0, 0.0),), 0.4, 6),
+    (128, 4, 12, 2, ((0, 0.0), (1, 0.0)), 1.0, 16)])
+def test_network_matches_oracle(dev, N, J, M, B, channels, tnoise, tseed):
+    """Prediction, loss and every parameter gradient against the oracle
+    network (bfloat16 rounding at the kernels' points); at 128 x 128 the
+    bursts have two channels and the network reads the first."""
     from paper_2505_10639_amd import WarmStartNet
     from paper_2505_10639_amd.warmstart import mode_scale
-    J, M, B = 12, 44, 3
-    pr = synth.make_problem(81, N=64, P=B, J=J, M=M, d_over_r0=np.array([5.0, 10.0, 15.0]))
+    LAYERS = _layers(N, J, M)
+    pr = synth.make_problem(81, N=N, P=B, J=J, M=M, channels=channels,
+                            d_over_r0=np.array([5.0, 10.0, 15.0])[:B], border=N // 10)
     D_np = fast_simulate_D(pr)
     scale = mode_scale(M)
     onet = cnn.Network(LAYERS)
     params = _he_params(onet, np.random.default_rng(4))
-    net = WarmStartNet(J, M, scale, batch_max=4, device=dev)
+    net = WarmStartNet(J, M, scale, batch_max=4, device=dev, N=N)
     assert net.n_params == onet.count() == params.size
     net.load(torch.from_numpy(params).to(dev))
     D = torch.from_numpy(D_np).to(dev)
-    frames = oracle.idft2_un(oracle.expand_half(D_np[:, 0], 64)).real / 4096.0
+    frames = oracle.idft2_un(oracle.expand_half(D_np[:, 0], N)).real / float(N * N)
     x = cnn.normalize_frames(frames)
     even = cnn.even_mode_mask(M)
     p64 = params.astype(np.float64)
@@ -86,9 +104,9 @@ def test_network_matches_oracle(dev):
     # even-mode flip (the loss takes that choice by comparing two sums): the
     # oracle's own prediction, flipped on every third frame, plus noise.
     p_o = onet.forward(x, p64, bf16=True)[0][-1].reshape(B, J, M)
-    rng = np.random.default_rng(6)
+    rng = np.random.default_rng(tseed)
     flip = np.where((np.arange(J) % 3 == 0)[None, :, None] & even[None, None, :], -1.0, 1.0)
-    t_n = p_o * flip + 0.4 * np.std(p_o) * rng.standard_normal(p_o.shape)
+    t_n = p_o * flip + tnoise * np.std(p_o) * rng.standard_normal(p_o.shape)
     wt = scale.astype(np.float64) ** 2 / np.mean(scale.astype(np.float64) ** 2)
     _, _, use2 = cnn.burst_loss(p_o, t_n, even, weight=wt)
     q = t_n.copy()
@@ -112,14 +130,39 @@ def test_network_matches_oracle(dev):
     # FP32 and FP64 accumulation can round a value to neighbouring bfloat16
     # numbers, so each rounding point may add up to 2^-8 of relative
     # discrepancy: 6 x 2 x 2^-8 = 4.7e-2 for the gradient of the first layer.
+    # The last three layers' gradients pass fewer backward rounding points
+    # (at most 5 + 3), 3.1e-2; 2e-2 holds them with twice the measured margin.
+    #
+    # At 128 x 128 the bfloat16 network is far more sensitive to the last
+    # bits of its input: the oracle's own layer gradients move by s_l ~ 0.1
+    # when its FP64 frames are perturbed by 1e-6 of their maximum (the size
+    # of an FP32 transform's rounding, which separates the GPU's frames from
+    # the oracle's), through flipped roundings and ReLU masks.  There the
+    # GPU gradient must lie within 2 s_l + 2^-8 of the oracle's, s_l
+    # measured here.
+    if N == 64:
+        tols = [4.7e-2] * 3 + [2e-2] * 3
+    else:
+        f2 = frames + 1e-6 * np.abs(frames).max() * np.random.default_rng(2).standard_normal(
+            frames.shape)
+        _, g_p, _ = onet.loss_grad(cnn.normalize_frames(f2), p64, target / scale, even,
+                                   bf16=True, weight=wt)
+        tols, o = [], 0
+        for (kind, a, b) in LAYERS:
+            n = b * (9 * a if kind == "conv" else a) + b
+            tols.append(2.0 * rel(g_p[o:o + n], g_o[o:o + n]) + 2.0 ** -8)
+            o += n
+        print(f"[cnn] N={N} tolerances from the oracle's sensitivity",
+              [f"{t:.2e}" for t in tols], flush=True)
     errs, o = [], 0
-    for (kind, a, b) in LAYERS:
+    for li, (kind, a, b) in enumerate(LAYERS):
         nw = b * (9 * a if kind == "conv" else a)
-        for name, n, tol in (("w", nw, 4.7e-2), ("b", b, 4.7e-2)):
+        t = tols[li]
+        for name, n, tol in (("w", nw, t), ("b", b, t)):
             errs.append((kind, a, b, name, rel(grad[o:o + n], g_o[o:o + n]), tol))
             o += n
-    print("[cnn] gradient errors", [(k, a, b, n, f"{e:.2e}") for k, a, b, n, e, _ in errs],
-          flush=True)
+    print(f"[cnn] N={N} gradient errors",
+          [(k, a, b, n, f"{e:.2e}") for k, a, b, n, e, _ in errs], flush=True)
     assert all(e < tol for *_, e, tol in errs), errs
     net.close()
 

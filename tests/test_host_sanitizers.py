@@ -23,7 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build", "sanitize")
 # rebuilt with the sanitizers: every file with host logic beyond a launch
 SANITIZED = ["momfbd_api.hip", "object.hip", "lbfgs.hip", "postproc.hip", "cnn.hip",
-             "spectra.hip"]
+             "spectra.hip", "rng.hip"]
 # taken from the regular build: host code that only sets up launches
 REGULAR = ["kernels64.o", "kernels96.o", "kernels128.o", "gemm_mfma.o", "gemm_group.o"]
 # host side only: each sanitizer flag applies to the host compilation
