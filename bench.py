@@ -47,44 +47,52 @@ def unit_flops(N):
     return 2 * c2c + 2 * real, {"forward": c2c + real, "adjoint": c2c + real}
 
 
-# HBM traffic per launch of the dominant kernels on the headline workload,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
-# the reading of the same counter for a plain 256 MiB device copy (FETCH_SIZE
-# reads half the copied bytes: factor 2.0; WRITE_SIZE factor 1.0).  Valid
-# only for the kernel sources they were taken on (a changed source hash
-# reports null) and looked up by the value of the launch-schedule knob that
-# changes the kernel's traffic.
+# HBM traffic per launch of the transform and object kernels on the two
+# timed workloads, from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch), each scaled by the reading of the same counter for a plain
+# 256 MiB device copy (FETCH_SIZE reads half the copied bytes: factor 2.0;
+# WRITE_SIZE factor 1.0).  Valid only for the kernel sources they were taken
+# on (a changed source hash reports null) and looked up by patch size and by
+# the value of the launch-schedule knob that changes the kernel's traffic.
 KERNEL_SOURCES = {
-    "adjoint": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
-    "forward": ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
-    "object": ["object.hip", "internal.h"],
+    ("adjoint", 64): ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    ("forward", 64): ["kernels64.hip", "ops64.h", "fft_lane.h", "internal.h"],
+    ("object", 64): ["object.hip", "internal.h"],
+    ("adjoint", 128): ["kernels128.hip", "ops128.h", "fft_lane.h", "internal.h"],
+    ("forward", 128): ["kernels128.hip", "ops128.h", "fft_lane.h", "internal.h"],
+    ("object", 128): ["object.hip", "internal.h"],
 }
-COPY_FETCH_SCALE = 1.9997752760060412   # 256 MiB copy: FETCH_SIZE read 131086.7 KiB
+COPY_FETCH_SCALE = 1.9997991127905397   # 256 MiB copy: FETCH_SIZE read 131085.2 KiB
 COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
-# per kernel: the knob and, per value of it, (HBM bytes read, written) per
-# launch
+# per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
+# per launch
 COUNTED_TRAFFIC = {
-    "adjoint": {"sources_sha1": "74eb310aefd5", "knob": "xcd_adjoint",
-                "by_value": {1: (895470860, 94470144), 0: (1094358814, 94470144)}},
-    "forward": {"sources_sha1": "74eb310aefd5", "knob": "xcd_forward",
-                "by_value": {0: (94882586, 400063360), 1: (94881306, 400211848)}},
-    "object": {"sources_sha1": "2f75b2c786e8", "knob": "object_pairs_per_thread",
-               "by_value": {1: (729195683, 32782515), 2: (729196555, 32666627),
-                            4: (729195742, 32597448)}},
+    ("adjoint", 64): {"sources_sha1": "ba92e81ba74a", "knob": "xcd_adjoint",
+                      "by_value": {1: (895388542, 94470144), 0: (1094425920, 94470144)}},
+    ("forward", 64): {"sources_sha1": "ba92e81ba74a", "knob": "xcd_forward",
+                      "by_value": {0: (94920707, 403193326)}},
+    ("object", 64): {"sources_sha1": "eb8c3f1ada21", "knob": "object_pairs_per_thread",
+                     "by_value": {1: (729207124, 32782473)}},
+    ("adjoint", 128): {"sources_sha1": "234a21b1ccbc", "knob": "xcd_adjoint",
+                       "by_value": {1: (12023725246, 1511522304)}},
+    ("forward", 128): {"sources_sha1": "234a21b1ccbc", "knob": "xcd_forward",
+                       "by_value": {0: (1554319630, 6522697194)}},
+    ("object", 128): {"sources_sha1": "eb8c3f1ada21", "knob": "object_pairs_per_thread",
+                      "by_value": {1: (10901721867, 257958827)}},
 }
 
 
-def sources_sha(kernel):
+def sources_sha(kernel, N=64):
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES.get(kernel, []):
+    for f in KERNEL_SOURCES.get((kernel, N), []):
         with open(os.path.join(ROOT, "paper_2505_10639_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
 
 
-def counted_traffic(kernel, schedule):
-    rec = COUNTED_TRAFFIC.get(kernel)
-    if rec is None or rec["sources_sha1"] != sources_sha(kernel):
+def counted_traffic(kernel, schedule, N=64):
+    rec = COUNTED_TRAFFIC.get((kernel, N))
+    if rec is None or rec["sources_sha1"] != sources_sha(kernel, N):
         return None
     rw = rec["by_value"].get(schedule.get(rec["knob"]))
     return None if rw is None else rw[0] + rw[1]
@@ -176,17 +184,22 @@ def build_large(dev):
 KINDS = ("phase", "forward", "object", "adjoint", "grad")
 
 
-def time_steps(plan, D, alpha, gamma, steps, warmup, tune=True, reps=10):
+def time_steps(plan, D, alpha, gamma, steps, warmup, tune=True, reps=10, schedule=None):
     """ms per loss+grad step (HIP events on the launch stream) and two sets
     of per-kernel average durations from the library's event pairs on the
     same stream: back to back (each launch of one kind issued `reps` times
     in a row inside one pair, as the kernels run inside a step, with no idle
     gap in front) and isolated (one pair around every launch).  The plan's
     launch schedules are first chosen by the library's autotuner on the
-    same data (a setup step, outside the timed region)."""
+    same data (a setup step, outside the timed region), unless `schedule`
+    (a momfbd_tuning dict) fixes them."""
     import torch
 
-    if tune:
+    if schedule:
+        s = dict(plan.tuning(), **schedule)
+        plan.set_tuning(s["xcd_forward"], s["xcd_adjoint"], s["object_pairs_per_thread"],
+                        s["grad_waves"], s["grad_splits"], s["grad_row_tiles"])
+    elif tune:
         plan.autotune(alpha, D, gamma, None, reps=3)
 
     from paper_2505_10639_amd import (momfbd_profile_repeat, momfbd_profile_start,
@@ -665,6 +678,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (for scaling "
                          "hardware byte counters) and exit")
+    ap.add_argument("--schedule", type=json.loads, default=None,
+                    help="fix launch-schedule fields (JSON, momfbd_tuning names) instead of "
+                         "autotuning, e.g. for hardware-counter runs of one schedule")
     ap.add_argument("--warm-large-steps", type=int, default=2000,
                     help="training steps of the 128 x 128 warm-start network (0: skip)")
     ap.add_argument("--only", choices=["uneven", "warm", "large", "warm_large"],
@@ -699,7 +715,8 @@ def main():
         else:
             plan4, D4, alpha4, gamma4, g4 = build_large(dev)
             ms4, kern4, _, _, _ = time_steps(plan4, D4, alpha4, gamma4, max(2, args.steps // 2),
-                                             min(args.warmup, 2), not args.no_tune)
+                                             min(args.warmup, 2), not args.no_tune,
+                                             schedule=args.schedule)
             res = {"ms_per_step": ms4, "kernels_avg_ms": kern4, "launch_schedule": plan4.tuning()}
             plan4.close()
         print(json.dumps({args.only: res}), flush=True)
@@ -711,11 +728,11 @@ def main():
     units = P * C * J
     log(f"timing {args.steps} steps after {args.warmup} warm-up")
     ms, kern_avg, kern_iso, _, _ = time_steps(plan, D, alpha, gamma, args.steps, args.warmup,
-                                              not args.no_tune)
+                                              not args.no_tune, schedule=args.schedule)
     sched = plan.tuning()
     roof = roofline(kern_avg, units, N, kernel_io_bytes(N, P, J, g["channel_object"],
                                                         g["support_frac"]),
-                    lambda k: counted_traffic(k, sched))
+                    lambda k: counted_traffic(k, sched, N))
     flop_unit, _ = unit_flops(N)
     step_tflops = flop_unit * units / (ms * 1e-3) / 1e12
     out = {
@@ -764,7 +781,8 @@ def main():
             "step_nominal_fft_tflops": t4, "step_frac_of_fp32_peak": t4 / PEAK_FP32_VECTOR_TFLOPS,
             "roofline": roofline(kern4, units4, g4["N"],
                                  kernel_io_bytes(g4["N"], g4["P"], g4["J"], g4["channel_object"],
-                                                 g4["support_frac"]), lambda k: None),
+                                                 g4["support_frac"]),
+                                 lambda k: counted_traffic(k, plan4.tuning(), g4["N"])),
             "launch_schedule": plan4.tuning(),
             "kernels_avg_ms": kern4,
             "kernels_avg_ms_isolated": kern4_iso,

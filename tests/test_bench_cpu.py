@@ -24,20 +24,22 @@ def bench():
 
 def test_counted_traffic_follows_schedule(bench):
     sched = {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1, "grad_waves": 4}
-    for kern, rec in bench.COUNTED_TRAFFIC.items():
-        if rec["sources_sha1"] != bench.sources_sha(kern):
-            assert bench.counted_traffic(kern, sched) is None
+    for (kern, N), rec in bench.COUNTED_TRAFFIC.items():
+        if rec["sources_sha1"] != bench.sources_sha(kern, N):
+            assert bench.counted_traffic(kern, sched, N) is None
             continue
         for v, (rd, wr) in rec["by_value"].items():
-            assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: v})) == rd + wr
+            assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: v}), N) == rd + wr
         # a knob value the counters were not taken for reports nothing
-        assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: 99})) is None
+        assert bench.counted_traffic(kern, dict(sched, **{rec["knob"]: 99}), N) is None
     assert bench.counted_traffic("no_such_kernel", sched) is None
+    assert bench.counted_traffic("adjoint", sched, 96) is None
 
 
 def test_counted_traffic_stale_source(bench, monkeypatch):
-    monkeypatch.setitem(bench.COUNTED_TRAFFIC, "adjoint",
-                        dict(bench.COUNTED_TRAFFIC["adjoint"], sources_sha1="000000000000"))
+    key = ("adjoint", 64)
+    monkeypatch.setitem(bench.COUNTED_TRAFFIC, key,
+                        dict(bench.COUNTED_TRAFFIC[key], sources_sha1="000000000000"))
     assert bench.counted_traffic("adjoint", {"xcd_adjoint": 1}) is None
 
 
