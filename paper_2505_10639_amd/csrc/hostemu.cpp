@@ -328,22 +328,24 @@ void pupil_to_p(WG& w, const float* A, const float* ph, float2 (&p)[L][64]) {
   for (int l = 0; l < L; ++l) n128::op1_rows(w.T, l, p[l]);
 }
 
-void r2c(WG& w, const float (&s)[L][64], float2 (&X)[128][64], float2 (&x64)[128]) {
+void r2c(WG& w, const float (&s)[L][64], float2 (&X)[L][32], float2 (&x64)[128]) {
   static float keep[L][32], send[L][32], other[L][32];
   for (int l = 0; l < L; ++l) n128::op2_rows_fold(s[l], keep[l], send[l], l);
   float* Xf = reinterpret_cast<float*>(w.T);
   for (int l = 0; l < L; ++l) n128::xput(send[l], Xf, l);
   for (int l = 0; l < L; ++l) n128::xget(Xf, l, other[l]);
   for (int l = 0; l < L; ++l) n128::op2_rows_finish(keep[l], other[l], w.T, l);
-  for (int l = 0; l < 128; ++l) n128::op2_cols(w.T, w.Taux, l, X[l]);
+  for (int l = 0; l < L; ++l) n128::op2_cols(w.T, w.Taux, l, X[l]);
   for (int l = 0; l < 128; ++l) x64[l] = n128::op2_unpack(w.Taux, w.T, l);
-  for (int l = 0; l < 128; ++l) n128::op2_collect(w.T, l, X[l]);
+  for (int l = 0; l < L; ++l) n128::op2_collect(w.T, l, X[l]);
 }
 
-void c2r(WG& w, float2 (&X)[128][64], const float2 (&x64)[128], float (&g)[L][64]) {
+void c2r(WG& w, float2 (&X)[L][32], const float2 (&x64)[128], float (&g)[L][64]) {
   static float keep[L][32], send[L][32], other[L][32];
   for (int l = 0; l < 128; ++l) w.Taux[l] = x64[l];
-  for (int l = 0; l < 128; ++l) n128::op3_cols(X[l], w.Taux, w.T, l);
+  for (int l = 0; l < L; ++l) n128::op3_cols(X[l], w.Taux, w.T, l);
+  for (int l = 0; l < L; ++l) n128::op3_cols_combine(w.T, l, X[l]);
+  for (int l = 0; l < L; ++l) n128::op3_cols_put(X[l], w.T, l);
   for (int l = 0; l < L; ++l) n128::op3_rows_compute(w.T, l, keep[l], send[l]);
   float* Xf = reinterpret_cast<float*>(w.T);
   for (int l = 0; l < L; ++l) n128::xput(send[l], Xf, l);
@@ -351,12 +353,12 @@ void c2r(WG& w, float2 (&X)[128][64], const float2 (&x64)[128], float (&g)[L][64
   for (int l = 0; l < L; ++l) n128::op3_rows_finish(keep[l], other[l], l, g[l]);
 }
 
-void to_band(WG& w, float2 (&H)[L][64], float2 (&GP)[128][32]) {
+void to_band(WG& w, float2 (&H)[L][64], float2 (&GP)[L][16]) {
   static float2 keep[L][32], other[L][32];
   for (int l = 0; l < L; ++l) n128::op4_rows_fft(H[l], keep[l], w.T, l);
   for (int l = 0; l < L; ++l) n128::xget(w.T, l, other[l]);
   for (int l = 0; l < L; ++l) n128::op4_rows_finish(keep[l], other[l], w.T, l);
-  for (int l = 0; l < 128; ++l) n128::op4_cols(w.T, l, GP[l]);
+  for (int l = 0; l < L; ++l) n128::op4_cols(w.T, l, GP[l]);
 }
 }  // namespace e128
 
@@ -372,26 +374,24 @@ void emu128_pupil_ifft(const float* A, const float* ph, float* p) {
 void emu128_r2c(const float* img, float* half) {
   static e128::WG w;
   static float s[256][64];
-  static float2 X[128][64], x64[128];
+  static float2 X[256][32], x64[128];
   for (int l = 0; l < 256; ++l)
     for (int m = 0; m < 64; ++m) s[l][m] = img[(l >> 1) * 128 + 2 * m + (l & 1)];
   e128::r2c(w, s, X, x64);
   float2* h = reinterpret_cast<float2*>(half);
-  for (int l = 0; l < 128; ++l) {
-    for (int m = 0; m < 64; ++m) h[n128::sl_index(l, m)] = X[l][m];
-    h[n128::sl_index64(l)] = x64[l];
-  }
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 32; ++m) h[n128::sl_index(l, m)] = X[l][m];
+  for (int l = 0; l < 128; ++l) h[n128::sl_index64(l)] = x64[l];
 }
 
 void emu128_c2r(const float* half, float* img) {
   static e128::WG w;
   static float g[256][64];
-  static float2 X[128][64], x64[128];
+  static float2 X[256][32], x64[128];
   const float2* h = reinterpret_cast<const float2*>(half);
-  for (int l = 0; l < 128; ++l) {
-    for (int m = 0; m < 64; ++m) X[l][m] = h[n128::sl_index(l, m)];
-    x64[l] = h[n128::sl_index64(l)];
-  }
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 32; ++m) X[l][m] = h[n128::sl_index(l, m)];
+  for (int l = 0; l < 128; ++l) x64[l] = h[n128::sl_index64(l)];
   e128::c2r(w, X, x64, g);
   for (int l = 0; l < 256; ++l)
     for (int m = 0; m < 64; ++m) img[(l >> 1) * 128 + 2 * m + (l & 1)] = g[l][m];
@@ -399,14 +399,14 @@ void emu128_c2r(const float* half, float* img) {
 
 void emu128_fft_to_band(const float* hc, float* band) {
   static e128::WG w;
-  static float2 H[256][64], GP[128][32];
+  static float2 H[256][64], GP[256][16];
   const float2* h = reinterpret_cast<const float2*>(hc);
   for (int l = 0; l < 256; ++l)
     for (int m = 0; m < 64; ++m) H[l][m] = h[(l >> 1) * 128 + 2 * m + (l & 1)];
   e128::to_band(w, H, GP);
   float2* o = reinterpret_cast<float2*>(band);
-  for (int l = 0; l < 128; ++l)
-    for (int i = 0; i < 32; ++i) o[(2 * i + (l & 1)) * 64 + (l >> 1)] = GP[l][i];
+  for (int l = 0; l < 256; ++l)
+    for (int i = 0; i < 16; ++i) o[(4 * i + (l >> 6)) * 64 + (l & 63)] = GP[l][i];
 }
 
 }  // extern "C"

@@ -46,10 +46,10 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A,
   }
 }
 
-// |.|^2 of the PSF amplitude, then the real forward transform; lanes < 128
-// end with S in spectral layout.
+// |.|^2 of the PSF amplitude, then the real forward transform; ends with S
+// in spectral layout (x64 on lanes < 128).
 __device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* psf_row_or_null,
-                                           float2* T, float2* Taux, int lane, float2 (&X)[64],
+                                           float2* T, float2* Taux, int lane, float2 (&X)[32],
                                            float2& x64) {
   float s[64];
 #pragma unroll
@@ -67,11 +67,11 @@ __device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* ps
   sync();
   op2_rows_finish(keep, other, T, lane);
   sync();
-  if (lane < 128) op2_cols(T, Taux, lane, X);
+  op2_cols(T, Taux, lane, X);
   sync();
   if (lane < 128) x64 = op2_unpack(Taux, T, lane);
   sync();
-  if (lane < 128) op2_collect(T, lane, X);
+  op2_collect(T, lane, X);
 }
 
 template <bool WANT_PSF>
@@ -97,15 +97,13 @@ __device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C,
   float2 p[64];
   op1_rows(T, lane, p);
   sync();
-  float2 X[64], x64;
+  float2 X[32], x64;
   float* row = WANT_PSF ? psf + (size_t)u * N * N + (lane >> 1) * N : nullptr;
   psf_to_otf(p, ct.kappa[c], row, T, Taux, lane, X, x64);
-  if (lane < 128) {
-    float2* out = S + (size_t)u * kUnitF2;
+  float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
-    for (int m = 0; m < 64; ++m) out[sl_index(lane, m)] = X[m];
-    out[sl_index64(lane)] = x64;
-  }
+  for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];
+  if (lane < 128) out[sl_index64(lane)] = x64;
 }
 
 template <bool WANT_PSF>
@@ -150,47 +148,39 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
   const int k = ct.chan_obj[c];
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
 
-  // G = -2 w conj(O)(D - O S) in spectral layout, held by lanes < 128.  All
-  // four waves load: spectral lane sl = lane & 127 takes m in [0,32) on the
-  // lower half of the workgroup and m in [32,64) on the upper half, which
-  // passes its values on through LDS.
-  // Zero outside the object's spectral support, where D, S and O are not
-  // read.
-  float2 G[64];
+  // G = -2 w conj(O)(D - O S) in spectral layout (G(ky, 64) of lanes < 128
+  // into Taux[ky]); zero outside the object's spectral support, where D, S
+  // and O are not read
+  float2 G[32];
   __builtin_amdgcn_s_setprio(2);
   {
-    const int upper = lane >> 7, sl = lane & 127;
+    const int r = wave_of(lane);
     constexpr int kOut = kUnitF2 * 8;
     const __amdgpu_buffer_rsrc_t rS = raw_buffer(S + (size_t)u * kUnitF2, kOut),
                                  rD = raw_buffer(la.D + (size_t)u * kUnitF2, kOut),
                                  rO = raw_buffer(O + ((size_t)p * K + k) * kUnitF2, kOut);
-    const int fm = la.supp[k * HC + (sl >> 1)];
+    const int fm = la.supp[k * HC + (lane & 63)];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      const int m = i + 32 * upper;
-      const int off = in_support(2 * m + (sl & 1), N, fm) ? sl_index(sl, m) * 8 : kOut;
+    for (int m = 0; m < 32; ++m) {
+      const int off = in_support(4 * m + r, N, fm) ? sl_index(lane, m) * 8 : kOut;
       const float2 o = buffer_load_f2(rO, off);
-      G[i] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+      G[m] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
                     w2);
     }
-    if (upper) {
-#pragma unroll
-      for (int i = 0; i < 32; ++i) T[sl * 33 + i] = G[i];
-    } else {
-      const int off = in_support(sl, N, la.supp[k * HC + 64]) ? sl_index64(sl) * 8 : kOut;
+    if (lane < 128) {
+      const int off = in_support(lane, N, la.supp[k * HC + 64]) ? sl_index64(lane) * 8 : kOut;
       const float2 o = buffer_load_f2(rO, off);
-      Taux[sl] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
-                        w2);
+      Taux[lane] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
+                          w2);
     }
   }
   __builtin_amdgcn_s_setprio(0);
   sync();
-  if (lane < 128) {
-#pragma unroll
-    for (int i = 0; i < 32; ++i) G[32 + i] = T[lane * 33 + i];
-  }
+  op3_cols(G, Taux, T, lane);
   sync();
-  if (lane < 128) op3_cols(G, Taux, T, lane);
+  op3_cols_combine(T, lane, G);
+  sync();
+  op3_cols_put(G, T, lane);
   sync();
   float g[64];
   {
@@ -227,14 +217,14 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
     op4_rows_finish(keep, other, T, lane);
   }
   sync();
-  if (lane < 128) {
-    float2 GP[32];
+  {
+    float2 GP[16];
     op4_cols(T, lane, GP);
-    const int b = lane & 1, q = lane >> 1;
+    const int r = wave_of(lane), q = lane & 63;
     float* gout = gphi + (size_t)u * kBP;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      const int n = 2 * i + b;
+    for (int i = 0; i < 16; ++i) {
+      const int n = 4 * i + r;
       const float2 pk = cscale(expi_turns(phu[n * kB + q]), Ac[n * kB + q]);
       gout[n * kB + q] = pk.x * GP[i].y - pk.y * GP[i].x;   // Im(conj(P) G_P)
     }
@@ -302,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J
   const float* wr = apod + y * N;
 #pragma unroll
   for (int m = 0; m < 64; ++m) s[m] = wr[2 * m + e] * (s[m] - mean) + mean;
-  float2 X[64], x64;
+  float2 X[32], x64;
   {
     float keep[32], send[32], other[32];
     op2_rows_fold(s, keep, send, lane);
@@ -313,17 +303,15 @@ __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J
     op2_rows_finish(keep, other, T, lane);
   }
   sync();
-  if (lane < 128) op2_cols(T, Taux, lane, X);
+  op2_cols(T, Taux, lane, X);
   sync();
   if (lane < 128) x64 = op2_unpack(Taux, T, lane);
   sync();
-  if (lane < 128) {
-    op2_collect(T, lane, X);
-    float2* out = D + (size_t)u * kUnitF2;
+  op2_collect(T, lane, X);
+  float2* out = D + (size_t)u * kUnitF2;
 #pragma unroll
-    for (int m = 0; m < 64; ++m) out[sl_index(lane, m)] = X[m];
-    out[sl_index64(lane)] = x64;
-  }
+  for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];
+  if (lane < 128) out[sl_index64(lane)] = x64;
 }
 
 // out = IDFT(A B) / N^2 + sg nz for one half spectrum A (times B when B is
@@ -335,15 +323,18 @@ __device__ __forceinline__ void inverse_item(const float2* __restrict__ A,
   __shared__ float2 T[LDS_MAIN];
   __shared__ float2 Taux[LDS_AUX];
   const int lane = threadIdx.x;
-  float2 X[64];
-  if (lane < 128) {
+  float2 X[32];
 #pragma unroll
-    for (int m = 0; m < 64; ++m)
-      X[m] = B ? cmul(A[sl_index(lane, m)], B[sl_index(lane, m)]) : A[sl_index(lane, m)];
+  for (int m = 0; m < 32; ++m)
+    X[m] = B ? cmul(A[sl_index(lane, m)], B[sl_index(lane, m)]) : A[sl_index(lane, m)];
+  if (lane < 128)
     Taux[lane] = B ? cmul(A[sl_index64(lane)], B[sl_index64(lane)]) : A[sl_index64(lane)];
-  }
   sync();
-  if (lane < 128) op3_cols(X, Taux, T, lane);
+  op3_cols(X, Taux, T, lane);
+  sync();
+  op3_cols_combine(T, lane, X);
+  sync();
+  op3_cols_put(X, T, lane);
   sync();
   float g[64];
   {

@@ -5,20 +5,23 @@
 //   band-column  lane (q = l>>2, r = l&3): pupil band column vx = 32 + q, output
 //                rows of residue r mod 4 (first pass of op1);
 //   row-parity   lane (y = l>>1, e = l&1): image row y, columns 2m + e, m in [0,64);
-//   column-pair  lane (q = l>>1, b = l&1), l < 128: spectral column q, rows of
-//                parity b (the column passes of op2, op3, op4; lanes 128..255
-//                idle there);
-//   spectral SL  lanes l < 128: X(ky = 2m + b, kx = q), m in [0,64) (kx = 0 for
-//                q = 0) plus X(ky = l, kx = 64).
+//   column-quad  lane (r = l>>6, the wave, q = l&63): spectral column q, rows of
+//                residue r mod 4 (the column passes of op2, op3, op4);
+//   spectral SL  every lane: X(ky = 4m + r, kx = q), m in [0,32) (kx = 0 for
+//                q = 0), and lanes l < 128 also X(ky = l, kx = 64).
 //
 // The pupil support lies in the central band [32,96) of both axes (diameter
 // below N/2).  64- and 128-point sums fold into in-lane 32- and 64-point FFTs:
 // band-limited inputs fold by output residue (the modulation of the folded
-// sequence is a phase ramp the caller adds before the exponential), columns
-// split by output parity over a lane pair, and the real row transforms pack
-// even/odd samples into one complex sequence, with the halves exchanged
-// between the two lanes of a row through LDS.  Every phase is a per-lane
-// function; phases are separated by a workgroup barrier.
+// sequence is a phase ramp the caller adds before the exponential), the
+// 128-point column transforms split into four residue classes, one per wave
+// (forward: a radix-4 fold of the inputs before a 32-point FFT; inverse: a
+// 32-point FFT per class, then the radix-4 butterfly across the four waves
+// through LDS), and the real row transforms pack even/odd samples into one
+// complex sequence, with the halves exchanged between the two lanes of a row
+// through LDS.  Every phase is a per-lane function; phases are separated by a
+// workgroup barrier.  The residue class r is the wave index, so its twiddles
+// W128^{nr} come from a table at a wave-uniform index (scalar loads).
 #pragma once
 
 #include "fft_lane.h"
@@ -34,12 +37,81 @@ constexpr int BW = 64;
 // LDS strides (float2 units)
 constexpr int U1 = 132;         // [q][ky]      op1 column pass -> rows
 constexpr int U2 = 66;          // [y][kx]      rows -> columns (op2, op4)
-constexpr int U3 = 129;         // [r'][2q+b]   op3 columns -> rows
-constexpr int LDS_MAIN = 128 * U2;     // 8448 float2 (>= 64*U1, 64*U3)
+constexpr int U3 = 65;          // [y][kx]      op3 columns -> rows
+constexpr int LDS_MAIN = 128 * U2;     // 8448 float2 (>= 64*U1, 128*U3)
 constexpr int LDS_AUX = 128;
 
-MFBD_HDI int sl_index(int lane, int m) { return (2 * m + (lane & 1)) * HC + (lane >> 1); }
+// Residue class of a lane in the column-quad layout: its wave, uniform
+// across the wave (a scalar register on the device).
+MFBD_HDI int wave_of(int lane) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_readfirstlane(lane >> 6);
+#else
+  return lane >> 6;
+#endif
+}
+
+MFBD_HDI int sl_index(int lane, int m) { return (4 * m + (lane >> 6)) * HC + (lane & 63); }
 MFBD_HDI int sl_index64(int lane) { return lane * HC + 64; }
+
+// cos and sin of 2 pi n r / 128 for the residue classes r in [0,4) and
+// n in [0,32), rounded once from the FP64 constexpr evaluation.
+struct Tw4 {
+  float c[4][32];
+  float s[4][32];
+};
+constexpr Tw4 make_tw4() {
+  Tw4 t{};
+  for (int r = 0; r < 4; ++r)
+    for (int n = 0; n < 32; ++n) {
+      const detail::CS cs = detail::cossin_2pi(n * r, 128);
+      t.c[r][n] = float(cs.c);
+      t.s[r][n] = float(cs.s);
+    }
+  return t;
+}
+constexpr Tw4 kTw4 = make_tw4();
+
+// a * W128^{n r} (DIR as in twmul) for a wave-uniform r.
+template <int DIR, int n>
+MFBD_HDI float2 twmul_r(float2 a, int r) {
+  const float c = kTw4.c[r][n], s = DIR * kTw4.s[r][n];
+  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// Forward radix-4 fold of column q of rows stored at T[y * U + q] for the
+// lane's residue class r:
+//   z[n] = W128^{-n r} sum_t (-i)^{t r} x(n + 32 t),   n in [0,32),
+// so that X(4m + r) = FFT32(z)[m].  With a = x0 + (-1)^r x2 and
+// b = x1 + (-1)^r x3, the sum is a + (-i)^r b.
+template <int U>
+MFBD_HDI void fold4_fwd(const float2* T, int q, int r, float2 (&z)[32]) {
+  const float s = (r & 1) ? -1.0f : 1.0f;
+  const float sg = (r & 2) ? -1.0f : 1.0f;
+  auto ab = [&](int n, float2& a, float2& b) {
+    const float2 x0 = T[n * U + q], x1 = T[(n + 32) * U + q];
+    const float2 x2 = T[(n + 64) * U + q], x3 = T[(n + 96) * U + q];
+    a = make_float2(x0.x + s * x2.x, x0.y + s * x2.y);
+    b = make_float2(x1.x + s * x3.x, x1.y + s * x3.y);
+  };
+  if (r & 1) {         // (-i)^r b = sg (b.y, -b.x)
+    static_for<0, 32>([&](auto I) {
+      float2 a, b;
+      ab(decltype(I)::value, a, b);
+      z[decltype(I)::value] = make_float2(a.x + sg * b.y, a.y - sg * b.x);
+    });
+  } else {             // (-i)^r b = sg b
+    static_for<0, 32>([&](auto I) {
+      float2 a, b;
+      ab(decltype(I)::value, a, b);
+      z[decltype(I)::value] = make_float2(a.x + sg * b.x, a.y + sg * b.y);
+    });
+  }
+  static_for<1, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    z[n] = twmul_r<-1, n>(z[n], r);
+  });
+}
 
 // ---------------------------------------------------------------------------
 // Op 1: inverse DFT of the band-limited pupil field.
@@ -148,27 +220,16 @@ MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32],
   }
 }
 
-// Column pass (lanes < 128): X[m] = S(2m + b, q), m in [0,64), for q >= 1;
+// Column pass (all lanes): X[m] = S(4m + r, q), m in [0,32), for q >= 1;
 // q = 0 holds the packed real columns 0 and 64 (see op2_unpack).
-MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[64]) {
-  const int q = lane >> 1, b = lane & 1;
-  const float sb = b ? -1.0f : 1.0f;
-  static_for<0, 64>([&](auto I) {
-    constexpr int n = decltype(I)::value;
-    float2 lo = T[n * U2 + q], hi = T[(n + 64) * U2 + q];
-    X[n] = make_float2(lo.x + sb * hi.x, lo.y + sb * hi.y);
-  });
-  if (b) {
-    static_for<1, 64>([&](auto I) {
-      constexpr int n = decltype(I)::value;
-      X[n] = twmul<-1, 128, n>(X[n]);
-    });
-  }
-  fft64<-1>(X);
+MFBD_HDI void op2_cols(const float2* T, float2* Taux, int lane, float2 (&X)[32]) {
+  const int r = wave_of(lane), q = lane & 63;
+  fold4_fwd<U2>(T, q, r, X);
+  fft32<-1>(X);
   // column 0 packs the real columns kx = 0 and 64 (F = S0 + i S64, both
   // Hermitian in ky): left in Taux[ky] for op2_unpack
   if (q == 0) {
-    static_for<0, 64>([&](auto I) { Taux[2 * decltype(I)::value + b] = X[decltype(I)::value]; });
+    static_for<0, 32>([&](auto I) { Taux[4 * decltype(I)::value + r] = X[decltype(I)::value]; });
   }
 }
 
@@ -181,43 +242,81 @@ MFBD_HDI float2 op2_unpack(const float2* Taux, float2* T, int lane) {
   return make_float2(0.5f * d.y, -0.5f * d.x);
 }
 
-// After another barrier, the lanes of column 0 take X[m] = S(2m+b, 0).
-MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[64]) {
-  if ((lane >> 1) == 0) {
-    static_for<0, 64>([&](auto I) { X[decltype(I)::value] = T[2 * decltype(I)::value + (lane & 1)]; });
+// After another barrier, the lanes of column 0 take X[m] = S(4m + r, 0).
+MFBD_HDI void op2_collect(const float2* T, int lane, float2 (&X)[32]) {
+  if ((lane & 63) == 0) {
+    const int r = wave_of(lane);
+    static_for<0, 32>([&](auto I) { X[decltype(I)::value] = T[4 * decltype(I)::value + r]; });
   }
 }
 
 // ---------------------------------------------------------------------------
-// Op 3: inverse DFT of a Hermitian half spectrum (SL, lanes < 128) -> real
-// image in row-parity layout.
+// Op 3: inverse DFT of a Hermitian half spectrum (SL; X(ky, 64) in Taux[ky])
+// -> real image in row-parity layout.
+// Column pass in three steps separated by barriers.  First, the lane's
+// residue class: Y_r[n] = W128^{+n r} sum_m X(4m + r, q) W32^{+n m} into
+// T[(32 r + n) U3 + q] (column 0 packs X(ky, 64) as its imaginary part).
+// Then the radix-4 butterfly across the column's four lanes,
+// x(32 r + n, q) = sum_r' i^{r r'} Y_r'[n], held in registers, and after a
+// barrier written over T[(32 r + n) U3 + q]: T then holds the column
+// transforms in natural row order.
 // ---------------------------------------------------------------------------
-MFBD_HDI void op3_cols(float2 (&X)[64], const float2* Taux, float2* T, int lane) {
-  const int q = lane >> 1, b = lane & 1;
+MFBD_HDI void op3_cols_put(const float2 (&X)[32], float2* T, int lane) {
+  const int r = wave_of(lane), q = lane & 63;
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    T[(32 * r + n) * U3 + q] = X[n];
+  });
+}
+
+MFBD_HDI void op3_cols(float2 (&X)[32], const float2* Taux, float2* T, int lane) {
+  const int r = wave_of(lane), q = lane & 63;
   if (q == 0) {
-    static_for<0, 64>([&](auto I) {
+    static_for<0, 32>([&](auto I) {
       constexpr int m = decltype(I)::value;
-      float2 g64 = Taux[2 * m + b];
+      const float2 g64 = Taux[4 * m + r];
       X[m] = make_float2(X[m].x - g64.y, X[m].y + g64.x);
     });
   }
-  fft64<+1>(X);
-  if (b) {
-    static_for<1, 64>([&](auto I) {
-      constexpr int r = decltype(I)::value;
-      X[r] = twmul<+1, 128, r>(X[r]);
+  fft32<+1>(X);
+  static_for<1, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    X[n] = twmul_r<+1, n>(X[n], r);
+  });
+  op3_cols_put(X, T, lane);
+}
+
+// With a = Y0 + (-1)^r Y2 and b = Y1 + (-1)^r Y3, the sum is a + i^r b.
+MFBD_HDI void op3_cols_combine(const float2* T, int lane, float2 (&X)[32]) {
+  const int r = wave_of(lane), q = lane & 63;
+  const float s = (r & 1) ? -1.0f : 1.0f;
+  const float sg = (r & 2) ? -1.0f : 1.0f;
+  auto ab = [&](int n, float2& a, float2& b) {
+    const float2 y0 = T[n * U3 + q], y1 = T[(32 + n) * U3 + q];
+    const float2 y2 = T[(64 + n) * U3 + q], y3 = T[(96 + n) * U3 + q];
+    a = make_float2(y0.x + s * y2.x, y0.y + s * y2.y);
+    b = make_float2(y1.x + s * y3.x, y1.y + s * y3.y);
+  };
+  if (r & 1) {         // i^r b = sg (-b.y, b.x)
+    static_for<0, 32>([&](auto I) {
+      float2 a, b;
+      ab(decltype(I)::value, a, b);
+      X[decltype(I)::value] = make_float2(a.x - sg * b.y, a.y + sg * b.x);
+    });
+  } else {             // i^r b = sg b
+    static_for<0, 32>([&](auto I) {
+      float2 a, b;
+      ab(decltype(I)::value, a, b);
+      X[decltype(I)::value] = make_float2(a.x + sg * b.x, a.y + sg * b.y);
     });
   }
-  static_for<0, 64>([&](auto I) {
-    constexpr int r = decltype(I)::value;
-    T[r * U3 + lane] = X[r];
-  });
 }
 
 // Row pass (all lanes): lane (y, f) forms the row half spectrum, then the
 // parity-f half of the packed inverse, z[2n'+f], n' in [0,32).  It keeps the
 // part of z that belongs to its own column parity and sends the other part.
-//   X[k] (k in [0,64]) from the column pass: X(r,k) +- X(r,k+64) folded;
+//   X[k] (k in [0,64]) from the column pass (row y of T; column 0 packs the
+//   real columns 0 and 64);
 //   Z[k] = (X[k] + X[k+64]) + i W128^{+k} (X[k] - X[k+64]), X[k+64] = conj X[64-k];
 //   w[k'] = Z[k'] + (-1)^f Z[k'+32], k' in [0,32).
 // The values are read from LDS in groups {k, 64-k, 32+k, 32-k}, which give
@@ -225,13 +324,8 @@ MFBD_HDI void op3_cols(float2 (&X)[64], const float2* Taux, float2* T, int lane)
 // ever held whole (register pressure).
 MFBD_HDI void op3_rows_compute(const float2* T, int lane, float (&keep)[32], float (&send)[32]) {
   const int y = lane >> 1, f = lane & 1;
-  const int rp = y & 63;
-  const float sg = (y < 64) ? 1.0f : -1.0f;
   const float sf = f ? -1.0f : 1.0f;
-  auto xr = [&](int q) {
-    const float2 ev = T[rp * U3 + 2 * q], wo = T[rp * U3 + 2 * q + 1];
-    return make_float2(ev.x + sg * wo.x, ev.y + sg * wo.y);
-  };
+  auto xr = [&](int q) { return T[y * U3 + q]; };
   // Z at k and 64 - k from X[k], X[64-k] (1 <= k <= 63)
   auto zpair = [&](auto K, float2 xa, float2 xb, float2& za, float2& zb) {
     constexpr int k = decltype(K)::value;
@@ -361,24 +455,13 @@ MFBD_HDI void op4_rows_finish(const float2 (&keep)[32], const float2 (&other)[32
   }
 }
 
-// Column pass (lanes < 128): GP[i] = G(vy = 32 + 2i + b, vx = 32 + q), i in [0,32).
-MFBD_HDI void op4_cols(const float2* T, int lane, float2 (&GP)[32]) {
-  const int q = lane >> 1, b = lane & 1;
-  const float sb = b ? -1.0f : 1.0f;
-  float2 X[64];
-  static_for<0, 64>([&](auto I) {
-    constexpr int n = decltype(I)::value;
-    float2 lo = T[n * U2 + q], hi = T[(n + 64) * U2 + q];
-    X[n] = make_float2(lo.x + sb * hi.x, lo.y + sb * hi.y);
-  });
-  if (b) {
-    static_for<1, 64>([&](auto I) {
-      constexpr int n = decltype(I)::value;
-      X[n] = twmul<-1, 128, n>(X[n]);
-    });
-  }
-  fft64<-1>(X);
-  static_for<0, 32>([&](auto I) { GP[decltype(I)::value] = X[16 + decltype(I)::value]; });
+// Column pass (all lanes): GP[i] = G(vy = 32 + 4i + r, vx = 32 + q), i in [0,16).
+MFBD_HDI void op4_cols(const float2* T, int lane, float2 (&GP)[16]) {
+  const int r = wave_of(lane), q = lane & 63;
+  float2 X[32];
+  fold4_fwd<U2>(T, q, r, X);
+  fft32<-1>(X);
+  static_for<0, 16>([&](auto I) { GP[decltype(I)::value] = X[8 + decltype(I)::value]; });
 }
 
 }  // namespace n128
