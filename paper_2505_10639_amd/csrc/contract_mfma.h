@@ -1,6 +1,6 @@
-// Bodies of the dense modal contractions on the matrix cores (FP32 MFMA,
-// gfx950), shared by the kernels of one plan (gemm_mfma.hip) and of a group
-// of fields (gemm_group.hip).
+// Bodies of the dense modal contractions on the matrix cores (gfx950),
+// shared by the kernels of one plan (gemm_mfma.hip) and of a group of fields
+// (gemm_group.hip).
 //
 //   phase : phi[p][c][j][px] = theta_c[px] + sum_m Z_c[m][px] alpha[p][j][m]
 //           (Eq. wavefront on the (N/2)^2 pupil band, in turns)
@@ -11,56 +11,88 @@
 // gradient contracts Z with sum_c gphi[p][c][j][px] (channels summed first,
 // in channel order): half the matrix-core work at two channels.
 //
-// Both use v_mfma_f32_16x16x4f32.  Operand layout of that instruction: lane l
-// supplies A[i = l%16][k = l/16] and B[k = l/16][j = l%16]; the 16x16 result
-// sits in 4 registers per lane, D[4 (l/16) + e][l%16], e = 0..3.
-// The k order is free, so lane group g = l/16 takes k = k0 + 4g + s at step s:
-// every lane then loads its four operands of a 16-wide k chunk as one float4.
+// FP32 operands on the bf16 matrix cores: every operand is split exactly
+// into three bf16 parts (bf16split.h), and each 16x16x32 product is the sum
+// of the six partial products hh, hm, mh, hl, lh, mm (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation).  The basis tables are split once, at plan creation;
+// alpha is split as it is staged, gphi as it is loaded.  Operand layout of
+// the instruction: lane l supplies A[i = l%16][k] and B[k][j = l%16] for the
+// eight k of its lane group g = l/16, as eight packed bf16 (a uint4); the
+// 16x16 result sits in 4 registers per lane, D[4g + e][l%16], e = 0..3.
+// The k order is free as long as A and B agree, so lane group g takes the
+// eight consecutive k = k0 + 8g .. k0 + 8g + 7 of a 32-wide chunk: one 16-byte
+// load per part.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "bf16split.h"
 #include "internal.h"
 
 namespace mfbd {
 namespace contract {
 
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ floatx4 mfma4(const floatx4& a, const floatx4& b, floatx4 acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
-  return acc;
+// The three parts of eight k values of one operand row or column.
+struct Op3 {
+  uint4 h, m, l;
+};
+
+__device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, floatx4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+
+// acc + A B over one 32-wide k chunk, from the six partial products.
+__device__ __forceinline__ floatx4 mfma6(const Op3& a, const Op3& b, floatx4 acc) {
+  acc = mfma_bf16(a.m, b.m, acc);
+  acc = mfma_bf16(a.l, b.h, acc);
+  acc = mfma_bf16(a.h, b.l, acc);
+  acc = mfma_bf16(a.m, b.h, acc);
+  acc = mfma_bf16(a.h, b.m, acc);
+  return mfma_bf16(a.h, b.h, acc);
+}
+
+__device__ __forceinline__ Op3 load_op3(const uint4* p) { return Op3{p[0], p[1], p[2]}; }
+
+__device__ __forceinline__ Op3 split_op3(const float4& lo, const float4& hi) {
+  const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const Split8 s = split8(v);
+  return Op3{make_uint4(s.h[0], s.h[1], s.h[2], s.h[3]), make_uint4(s.m[0], s.m[1], s.m[2], s.m[3]),
+             make_uint4(s.l[0], s.l[1], s.l[2], s.l[3])};
 }
 
 // One block = W waves x RT row tiles (16 RT rows (p,j)) x all mode columns
 // x one of `splits` parts of the k range (blockIdx.y).  The k = c*bp + px
-// range, in 16-wide chunks, is cut into W*splits nearly equal slices; wave w
+// range, in 32-wide chunks, is cut into W*splits nearly equal slices; wave w
 // of split s sums slice s*W + w for all RT row tiles, so every basis chunk it
 // loads serves RT x 16 rows (the basis reads through L2 are what bound this
 // contraction).  Splitting k over blocks fills the chip when there are few
-// row tiles.  Operands are loaded DEPTH chunks ahead.  The partial sums of a
-// block are added in wave order (wave 0, then 1, ..., W-1) in one LDS buffer;
-// with one split the block writes 2 pi times its sum to grad, otherwise its
-// sum to part[s][R][M], which k_grad_combine adds in split order.  The
-// basis rows are zero-padded to a multiple of 16 per basis, so no mode test
-// is needed inside the loop; rows past R read row R-1 and are not written.
-// Schedules: W = 4 with RT = 4 and DEPTH = 2, or W = 8 with RT = 2 and
-// DEPTH = 1.  CS is the number of channels summed per load when they share
-// one basis (0: the run-time C), fixed at compile time where it can be so
-// that the loads of a chunk issue together.
+// row tiles.  The gphi values of the next chunk are loaded while the
+// current one is multiplied, and the basis parts of the next mode tile
+// while the current tile is.  The partial sums of a block are added in wave
+// order (wave 0, then 1, ..., W-1) in one LDS buffer; with one split the
+// block writes 2 pi times its sum to grad, otherwise its sum to
+// part[s][R][M], which k_grad_combine adds in split order.  The basis rows
+// are zero-padded to a multiple of 16 per basis, so no mode test is needed
+// inside the loop; rows past R read row R-1 and are not written.
+// Schedules: W = 4 with RT = 3 or 4, or W = 8 with RT = 2.  CS is the number
+// of channels summed per load when they share one basis (0: the run-time
+// C), fixed at compile time where it can be so that the loads of a chunk
+// issue together.
 //
 // Row tile block `bx`, part `split` of `splits` of the k range.  `mt` (at
 // most MT) is the number of 16-mode tiles the basis table holds; tiles
 // beyond it are neither loaded nor multiplied.  CS < 0 selects at run time
 // between separate bases per channel (zc == C) and one shared basis.
-template <int MT, int RT, int W, int DEPTH, int CS>
+// Zs: the split basis, [zc][16 mt][bp/8][3] uint4 (eight pixels of one
+// mode, parts hi, mid, lo).
+template <int MT, int RT, int W, int CS>
 __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt, int R, int J,
                                            int C, int zc, int M, int bp,
-                                           const float* __restrict__ Ztp,
+                                           const uint4* __restrict__ Zs,
                                            const float* __restrict__ gphi,
                                            float* __restrict__ grad,
                                            float* __restrict__ part) {
@@ -73,80 +105,68 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
     const int r = min(r0 + q * 16 + i16, R - 1);
-    grow[q] = gphi + ((size_t)(r / J) * C * J + r % J) * bp + 4 * g;
+    grow[q] = gphi + ((size_t)(r / J) * C * J + r % J) * bp + 8 * g;
   }
   floatx4 acc[RT][MT];
 #pragma unroll
   for (int q = 0; q < RT; ++q)
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int nchunk = zc * bp / 16, slices = W * splits, slice = split * W + wave;
+  const int nchunk = zc * bp / 32, slices = W * splits, slice = split * W + wave;
   const int c_begin = (int)((long)slice * nchunk / slices);
   const int n = (int)((long)(slice + 1) * nchunk / slices) - c_begin;   // chunks of this wave
-  const int k_begin = 16 * c_begin;
-  const float* zrow = Ztp + (size_t)i16 * bp + 4 * g;
-  // operands of chunk kk: a[q] from gphi row q*16 + i16 (with one shared
-  // basis, the sum over channels in channel order), b[t] from mode row
-  // t*16 + i16
-  auto load = [&](int kk, floatx4 (&a4)[RT], floatx4 (&b4)[MT]) {
+  const int bp8 = bp / 8;
+  // the eight gphi values of chunk kk in lane group g for each row tile
+  // (with one shared basis, the sum over channels in channel order)
+  auto load_a = [&](int kk, float4 (&raw)[RT][2]) {
     const int c = kk / bp, px = kk % bp;
     const bool separate = CS == 1 || (CS < 0 && zc == C);
 #pragma unroll
     for (int q = 0; q < RT; ++q) {
-      if (separate) {
-        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + c * cstride + px);
-      } else if (CS > 1) {
-        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + px);
+      const float4* p0 = reinterpret_cast<const float4*>(grow[q] + (separate ? c * cstride : 0) + px);
+      raw[q][0] = p0[0];
+      raw[q][1] = p0[1];
+      if (separate) continue;
+      auto add = [&](int ch) {
+        const float4* pc = reinterpret_cast<const float4*>(grow[q] + ch * cstride + px);
+        const float4 u = pc[0], v = pc[1];
+        raw[q][0] = make_float4(raw[q][0].x + u.x, raw[q][0].y + u.y, raw[q][0].z + u.z,
+                                raw[q][0].w + u.w);
+        raw[q][1] = make_float4(raw[q][1].x + v.x, raw[q][1].y + v.y, raw[q][1].z + v.z,
+                                raw[q][1].w + v.w);
+      };
+      if constexpr (CS > 1) {
 #pragma unroll
-        for (int ch = 1; ch < CS; ++ch)
-          a4[q] += *reinterpret_cast<const floatx4*>(grow[q] + ch * cstride + px);
+        for (int ch = 1; ch < CS; ++ch) add(ch);
       } else {
-        a4[q] = *reinterpret_cast<const floatx4*>(grow[q] + px);
-        for (int ch = 1; ch < C; ++ch)
-          a4[q] += *reinterpret_cast<const floatx4*>(grow[q] + ch * cstride + px);
+        for (int ch = 1; ch < C; ++ch) add(ch);
       }
     }
-    const float* zb = zrow + (size_t)c * mt * 16 * bp + px;   // bases of mt * 16 rows
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-      b4[t] = t < mt ? *reinterpret_cast<const floatx4*>(zb + (size_t)t * 16 * bp)
-                     : floatx4{0.f, 0.f, 0.f, 0.f};
   };
-  auto compute = [&](const floatx4 (&a4)[RT], const floatx4 (&b4)[MT]) {
-#pragma unroll
-    for (int q = 0; q < RT; ++q)
-#pragma unroll
-      for (int t = 0; t < MT; ++t)
-        if (t < mt) acc[q][t] = mfma4(a4[q], b4[t], acc[q][t]);
+  // basis parts of mode tile t for chunk kk: row t*16 + i16, pixels kk + 8g ..
+  auto zs_at = [&](int kk, int t) {
+    const int c = kk / bp, px = kk % bp;
+    return Zs + (((size_t)c * mt * 16 + t * 16 + i16) * bp8 + px / 8 + g) * 3;
   };
-  if constexpr (DEPTH == 1) {
-    floatx4 a_cur[RT], b_cur[MT];
-    if (n > 0) load(k_begin, a_cur, b_cur);
-    for (int i = 0; i < n; ++i) {
-      floatx4 a_nxt[RT], b_nxt[MT];
-      if (i + 1 < n) load(k_begin + 16 * (i + 1), a_nxt, b_nxt);
-      compute(a_cur, b_cur);
-      if (i + 1 < n) {
+  float4 raw[RT][2];
+  if (n > 0) load_a(32 * c_begin, raw);
+  for (int i = 0; i < n; ++i) {
+    const int kk = 32 * (c_begin + i);
+    Op3 a[RT];
 #pragma unroll
-        for (int q = 0; q < RT; ++q) a_cur[q] = a_nxt[q];
+    for (int q = 0; q < RT; ++q) a[q] = split_op3(raw[q][0], raw[q][1]);
+    if (i + 1 < n) load_a(kk + 32, raw);
+    Op3 b = load_op3(zs_at(kk, 0));
 #pragma unroll
-        for (int t = 0; t < MT; ++t) b_cur[t] = b_nxt[t];
+    for (int t = 0; t < MT; ++t) {
+      if (t < mt) {
+        Op3 bn = b;
+        if (t + 1 < MT && t + 1 < mt) bn = load_op3(zs_at(kk, t + 1));
+#pragma unroll
+        for (int q = 0; q < RT; ++q) acc[q][t] = mfma6(a[q], b, acc[q][t]);
+        b = bn;
       }
     }
-  } else {
-    // two stages: chunks i and i + 1 in flight; an odd last chunk is in
-    // stage 0
-    floatx4 a0[RT], b0[MT], a1[RT], b1[MT];
-    if (n > 0) load(k_begin, a0, b0);
-    if (n > 1) load(k_begin + 16, a1, b1);
-    int i = 0;
-    for (; i + 2 <= n; i += 2) {
-      compute(a0, b0);
-      if (i + 2 < n) load(k_begin + 16 * (i + 2), a0, b0);
-      compute(a1, b1);
-      if (i + 3 < n) load(k_begin + 16 * (i + 3), a1, b1);
-    }
-    if (i < n) compute(a0, b0);
   }
   for (int w = 0; w < W; ++w) {
     if (wave == w) {
@@ -177,35 +197,49 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
   }
 }
 
-// phi^T per channel: D[px][col] = sum_m ZtT[c][px][m] alpha[col][m], col = p*J + j.
+// phi^T per channel: D[px][col] = sum_m Z_c[m][px] alpha[col][m], col = p*J + j.
 // Block = 4 waves, (basis, kCols columns, a quarter of the band pixels);
 // with one shared basis the block writes every channel's phi from one
-// product: the block's kCols coefficient rows (contiguous in alpha) are
-// staged once in LDS with the mode index padded to Mp; each wave then walks
-// tiles of 16 pixels x kCols columns, taking its B operands as float4 LDS
-// reads.  32 columns per block (twice the blocks of 64) measured 7% faster.
+// product.  The block's kCols coefficient rows (contiguous in alpha) are
+// split and staged once in LDS, [col][m/8][part] with the modes padded to
+// Mq (a multiple of 32); each wave then walks tiles of 16 pixels x kCols
+// columns, taking its A parts from the split basis table
+// ZsT[c][px][Mq/8][3] (uint4: eight modes of one pixel) and its B parts
+// from LDS.  32 columns per block (twice the blocks of 64) measured faster
+// with FP32 operands.
 constexpr int kCols = kPhaseCols, kColTiles = kCols / 16;
+
+// uint4 row stride of the staged coefficients: odd, so that the 16 columns
+// one read touches fall on distinct 16-byte bank groups.
+__host__ __device__ __forceinline__ int phase_lds_stride(int Mq) { return (3 * (Mq / 8)) | 1; }
+
 __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C, int zc, int M,
-                                            int Mp, int bp, const float* __restrict__ ZtT,
+                                            int Mq, int bp, const uint4* __restrict__ ZsT,
                                             const float* __restrict__ theta,
                                             const float* __restrict__ alpha,
                                             float* __restrict__ phi) {
-  // The coefficient tile is stored mode-major, al[m][col] with row stride
-  // ldc = kCols + 4: a B operand element (k, j) of lane (i16 = j, g) is
-  // al[(kk + 4g + s) ldc + 16t + i16], and with 4 ldc = 16 (mod 64) the 64
-  // lanes of each read fall on distinct banks.  (Column-major rows of
-  // Mp + 4 floats, read as float4, gave 4-way conflicts.)
-  extern __shared__ float al[];    // [Mp][kCols + 4]
-  constexpr int ldc = kCols + 4;
+  extern __shared__ uint4 als[];   // [kCols][phase_lds_stride(Mq)]
+  const int q8 = Mq / 8, ld = phase_lds_stride(Mq);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
   const int c = bx >> 2, quarter = bx & 3;
   const int col0 = by * kCols;
   const int ncol = min(kCols, R - col0);
   const float* src = alpha + (size_t)col0 * M;
-  for (int r = wave; r < kCols; r += 4)
-    for (int m = lane; m < Mp; m += 64)
-      al[m * ldc + r] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
+  for (int idx = threadIdx.x; idx < kCols * q8; idx += 256) {
+    const int r = idx / q8, m8 = idx % q8;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int m = 8 * m8 + e;
+      v[e] = (r < ncol && m < M) ? src[(size_t)r * M + m] : 0.f;
+    }
+    const Split8 sp = split8(v);
+    uint4* dst = als + r * ld + 3 * m8;
+    dst[0] = make_uint4(sp.h[0], sp.h[1], sp.h[2], sp.h[3]);
+    dst[1] = make_uint4(sp.m[0], sp.m[1], sp.m[2], sp.m[3]);
+    dst[2] = make_uint4(sp.l[0], sp.l[1], sp.l[2], sp.l[3]);
+  }
   __syncthreads();
   const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
   for (int tile = 0; tile < ntile; ++tile) {
@@ -213,14 +247,13 @@ __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C,
     floatx4 acc[kColTiles];
 #pragma unroll
     for (int t = 0; t < kColTiles; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* arow = ZtT + ((size_t)c * bp + px0 + i16) * Mp;
-    for (int kk = 0; kk < Mp; kk += 16) {
-      const floatx4 a4 = *reinterpret_cast<const floatx4*>(arow + kk + 4 * g);
+    const uint4* arow = ZsT + ((size_t)(c * bp + px0 + i16) * q8 + g) * 3;
+    for (int k8 = 0; k8 < q8; k8 += 4) {
+      const Op3 a = load_op3(arow + 3 * k8);
 #pragma unroll
       for (int t = 0; t < kColTiles; ++t) {
-        const float* bp4 = al + (kk + 4 * g) * ldc + t * 16 + i16;
-        const floatx4 b4 = {bp4[0], bp4[ldc], bp4[2 * ldc], bp4[3 * ldc]};
-        acc[t] = mfma4(a4, b4, acc[t]);
+        const Op3 b = load_op3(als + (t * 16 + i16) * ld + 3 * (k8 + g));
+        acc[t] = mfma6(a, b, acc[t]);
       }
     }
     const int c_lo = zc == C ? c : 0, c_hi = zc == C ? c + 1 : C;

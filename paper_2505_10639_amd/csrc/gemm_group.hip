@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_phase_group(GroupArgs ga) {
   const int zc = zc_of(F.d);
   if ((int)blockIdx.x >= 4 * zc) return;
   contract::phase_block(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc, F.d.M,
-                        F.Mp, F.d.bandpix(), F.ZtT, F.thetat, F.alpha, F.w.phi);
+                        F.Mq, F.d.bandpix(), F.ZsT, F.thetat, F.alpha, F.w.phi);
 }
 
 // grid (row tiles of all fields, splits); W = 4 waves, RT row tiles each
@@ -30,10 +30,9 @@ template <int MT, int RT>
 __global__ __launch_bounds__(256) void k_grad_group(GroupArgs ga) {
   const int2 it = ga.item[blockIdx.x];
   const FieldDesc& F = ga.fd[it.x];
-  contract::grad_block<MT, RT, 4, 2, -1>(it.y, blockIdx.y, gridDim.y,
-                                         (F.d.M + 15) / 16, F.d.P * F.d.J, F.d.J, F.d.C,
-                                         zc_of(F.d), F.d.M, F.d.bandpix(), F.Zt, F.w.gphi,
-                                         F.grad, F.w.gpart);
+  contract::grad_block<MT, RT, 4, -1>(it.y, blockIdx.y, gridDim.y, (F.d.M + 15) / 16,
+                                      F.d.P * F.d.J, F.d.J, F.d.C, zc_of(F.d), F.d.M,
+                                      F.d.bandpix(), F.Zs, F.w.gphi, F.grad, F.w.gpart);
 }
 
 // grad = 2 pi (part[0] + ... + part[splits-1]) per field, in split order;
@@ -59,8 +58,8 @@ void launch_grad_group_t(const GroupArgs& ga, int row_tiles, int splits, hipStre
 
 }  // namespace
 
-hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mp_max, hipStream_t s) {
-  const size_t lds = (size_t)Mp_max * (kCols + 4) * sizeof(float);
+hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mq_max, hipStream_t s) {
+  const size_t lds = (size_t)kCols * contract::phase_lds_stride(Mq_max) * sizeof(uint4);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_group),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -11,23 +11,23 @@ namespace {
 using contract::floatx4;
 using contract::kCols;
 
-template <int MT, int RT, int W, int DEPTH, int CS>
+template <int MT, int RT, int W, int CS>
 __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int zc, int M, int bp,
-                                                      const float* __restrict__ Ztp,
+                                                      const uint4* __restrict__ Zs,
                                                       const float* __restrict__ gphi,
                                                       float* __restrict__ grad,
                                                       float* __restrict__ part) {
-  contract::grad_block<MT, RT, W, DEPTH, CS>(blockIdx.x, blockIdx.y, gridDim.y, MT, R, J, C, zc,
-                                             M, bp, Ztp, gphi, grad, part);
+  contract::grad_block<MT, RT, W, CS>(blockIdx.x, blockIdx.y, gridDim.y, MT, R, J, C, zc, M, bp,
+                                      Zs, gphi, grad, part);
 }
 
-__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mp,
+__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mq,
                                                     int bp,
-                                                    const float* __restrict__ ZtT,
+                                                    const uint4* __restrict__ ZsT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
                                                     float* __restrict__ phi) {
-  contract::phase_block(blockIdx.x, blockIdx.y, R, J, C, zc, M, Mp, bp, ZtT, theta, alpha, phi);
+  contract::phase_block(blockIdx.x, blockIdx.y, R, J, C, zc, M, Mq, bp, ZsT, theta, alpha, phi);
 }
 
 // grad = 2 pi (part[0] + part[1] + ... + part[splits-1]), in that order.
@@ -42,22 +42,22 @@ __global__ __launch_bounds__(256) void k_grad_combine(long n, int splits,
 }
 
 template <int MT, int CS>
-void launch_grad_cs(const Dims& d, int zc, int splits, const float* Ztp, const float* gphi,
+void launch_grad_cs(const Dims& d, int zc, int splits, const uint4* Zs, const float* gphi,
                     float* grad, float* part, hipStream_t s) {
   const int R = d.P * d.J;
   if (d.grad_waves == 8)
-    hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, 1, CS>), dim3((R + 31) / 32, splits), dim3(512), 0,
-                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 2, 8, CS>), dim3((R + 31) / 32, splits), dim3(512), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Zs, gphi, grad, part);
   else if (grad_row_tiles_of(d) == 3)
-    hipLaunchKernelGGL((k_grad_mfma<MT, 3, 4, 2, CS>), dim3((R + 47) / 48, splits), dim3(256), 0,
-                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 3, 4, CS>), dim3((R + 47) / 48, splits), dim3(256), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Zs, gphi, grad, part);
   else
-    hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, 2, CS>), dim3((R + 63) / 64, splits), dim3(256), 0,
-                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Ztp, gphi, grad, part);
+    hipLaunchKernelGGL((k_grad_mfma<MT, 4, 4, CS>), dim3((R + 63) / 64, splits), dim3(256), 0,
+                       s, R, d.J, d.C, zc, d.M, d.bandpix(), Zs, gphi, grad, part);
 }
 
 template <int MT>
-void launch_grad_t(const Dims& d, int splits, const float* Ztp, const float* gphi, float* grad,
+void launch_grad_t(const Dims& d, int splits, const uint4* Ztp, const float* gphi, float* grad,
                    float* part, hipStream_t s) {
   const int zc = d.zc > 0 ? d.zc : d.C;
   if (zc == d.C)
@@ -95,7 +95,7 @@ int grad_splits_of(const Dims& d) { return d.grad_splits > 0 ? d.grad_splits : g
 
 int grad_row_tiles_of(const Dims& d) { return d.grad_waves == 8 ? 2 : d.grad_rt == 3 ? 3 : 4; }
 
-hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
+hipError_t launch_grad(const Dims& d, const uint4* Zt, const float* gphi, float* grad,
                        float* part, hipStream_t s) {
   const int mt = (d.M + 15) / 16;
   const int splits = grad_splits_of(d);
@@ -116,18 +116,18 @@ hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float*
   return hipGetLastError();
 }
 
-hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
+hipError_t launch_phase(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                         const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
   dim3 grid(zc * 4, (R + kCols - 1) / kCols);
-  const size_t lds = (size_t)Mp * (kCols + 4) * sizeof(float);
+  const size_t lds = (size_t)kCols * contract::phase_lds_stride(Mq) * sizeof(uint4);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_phase_mfma),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, zc, d.M, Mp, d.bandpix(),
-                     ZtT, thetat, alpha, phi);
+  hipLaunchKernelGGL(k_phase_mfma, grid, dim3(256), lds, s, R, d.J, d.C, zc, d.M, Mq, d.bandpix(),
+                     ZsT, thetat, alpha, phi);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "bf16split.h"
 #include "ops128.h"
 #include "ops64.h"
 #include "ops96.h"
@@ -131,6 +132,30 @@ void pupil_to_p_half(Wave& w, const float* A, const float* ph, float2 (&pe)[64][
 }  // namespace
 
 extern "C" {
+
+// The exact three-way bf16 split of n values (bf16split.h): parts as FP32
+// words, [n][3].
+void emu_split3(const float* x, int n, float* parts) {
+  for (int i = 0; i < n; ++i) {
+    uint32_t h, m, l;
+    mfbd::split3_words(x[i], h, m, l);
+    parts[3 * i] = mfbd::u2f(h);
+    parts[3 * i + 1] = mfbd::u2f(m);
+    parts[3 * i + 2] = mfbd::u2f(l);
+  }
+}
+
+// The packed form of eight values (one MFMA operand per part): [3][4] words.
+void emu_split8(const float* x, uint32_t* words) {
+  float v[8];
+  for (int e = 0; e < 8; ++e) v[e] = x[e];
+  const mfbd::Split8 s = mfbd::split8(v);
+  for (int w = 0; w < 4; ++w) {
+    words[w] = s.h[w];
+    words[4 + w] = s.m[w];
+    words[8 + w] = s.l[w];
+  }
+}
 
 // fft32 in place on 32 interleaved complex values; dir = -1 or +1
 void emu_fft32(float* x, int dir) {

@@ -139,12 +139,12 @@ struct LbfgsLayout {
 // a unit) is item map[g].y of field map[g].x, one load away.
 struct FieldDesc {
   Dims d;
-  int Mp;                  // modes rounded up to 16 (rows of the basis tables)
+  int Mq;                  // modes rounded up to 32 (k extent of the phase contraction)
   ChanTab ct;
   LossArgs la;
   const float* Ab;
-  const float* Zt;
-  const float* ZtT;
+  const uint4* Zs;         // split basis tables (bf16split.h, contract_mfma.h)
+  const uint4* ZsT;
   const float* thetat;
   float* alpha;            // [P][J][M] coefficients (solver trial point)
   Workspace w;
@@ -179,7 +179,9 @@ size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);
 
 // Launchers (return hipSuccess or the launch error); dispatch on d.N.
-hipError_t launch_phase(const Dims& d, const float* alpha, const float* ZtT, int Mp,
+// ZsT: [C][(N/2)^2][Mq/8][3] and Zs: [C][Mp][(N/2)^2/8][3], the band bases in
+// turns split into three bf16 parts (eight values per uint4; contract_mfma.h).
+hipError_t launch_phase(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                         const float* thetat, float* phi, hipStream_t s);
 // `active` (nullable, [P]) restricts the unit kernels to patches with a
 // nonzero entry; the others are neither computed nor written.
@@ -191,7 +193,7 @@ hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, c
 hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                           const float* Ab, const float* phi, const float2* S, const float2* O,
                           float* gphi, hipStream_t s);
-hipError_t launch_grad(const Dims& d, const float* Zt, const float* gphi, float* grad,
+hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float* grad,
                        float* gpart, hipStream_t s);
 hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
                           const float* apod, float2* D, hipStream_t s);
@@ -261,7 +263,7 @@ hipError_t launch_lbfgs_finish(const Dims& d, const LbfgsLayout& L, void* state,
 // Group launches: one launch per stage over every field of a group (all of
 // one patch size).  `ga` carries the stage's prefix sums; the schedules
 // (XCD order, gradient row tiles and splits) are the group's.
-hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mp_max, hipStream_t s);
+hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mq_max, hipStream_t s);
 hipError_t launch_forward_group(int N, const GroupArgs& ga, int xcd, hipStream_t s);
 hipError_t launch_object_group(int N, const GroupArgs& ga_blocks, const GroupArgs& ga_patches,
                                hipStream_t s);

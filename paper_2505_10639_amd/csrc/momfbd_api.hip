@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "bf16split.h"
 #include "internal.h"
 #include "momfbd.h"
 
@@ -38,9 +39,14 @@ struct momfbd_plan_s {
   int shift_y[kMaxC];      // translation applied to each channel's pupil
   int shift_x[kMaxC];
   float* Ab = nullptr;     // [C][N/2][N/2]    aperture on the band
-  float* Zt = nullptr;     // [C][Mp][N/2][N/2] modes in turns, rows M..Mp-1 zero
-  float* ZtT = nullptr;    // [C][(N/2)^2][Mp] the same, mode index fastest, zero padded
+  // the band modes in turns, split into three bf16 parts (bf16split.h),
+  // eight values per uint4: Zs [C][Mp][(N/2)^2/8][3] (pixel index fastest,
+  // rows M..Mp-1 zero) for the gradient, ZsT [C][(N/2)^2][Mq/8][3] (mode
+  // index fastest, modes M..Mq-1 zero) for the phase
+  uint4* Zs = nullptr;
+  uint4* ZsT = nullptr;
   int Mp = 0;              // M rounded up to a multiple of 16
+  int Mq = 0;              // M rounded up to a multiple of 32
   float* thetat = nullptr; // [C][N/2][N/2]    diversity in turns
   int* hflag = nullptr;    // pinned host word for the solver's "still searching" count
   int* supp = nullptr;     // [K][N/2+1] spectral support of each object (see LossArgs)
@@ -319,31 +325,48 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
                          (size_t)M * BP * sizeof(float)) == 0;
   pl->d.zc = shared ? 1 : C;
   pl->Mp = (M + 15) / 16 * 16;
-  std::vector<float> hZT((size_t)C * BP * pl->Mp, 0.f), hZp((size_t)C * pl->Mp * BP, 0.f);
-  for (int c = 0; c < C; ++c)
-    std::copy(hZ.begin() + (size_t)c * M * BP, hZ.begin() + (size_t)(c + 1) * M * BP,
-              hZp.begin() + (size_t)c * pl->Mp * BP);
-  for (int c = 0; c < C; ++c)
-    for (int m = 0; m < M; ++m)
-      for (size_t px = 0; px < BP; ++px)
-        hZT[((size_t)c * BP + px) * pl->Mp + m] = hZ[((size_t)c * M + m) * BP + px];
+  pl->Mq = (M + 31) / 32 * 32;
+  const int Mp = pl->Mp, Mq = pl->Mq;
+  auto zval = [&](int c, int m, size_t px) {
+    return m < M ? hZ[((size_t)c * M + m) * BP + px] : 0.f;
+  };
+  auto put = [](uint4* dst, const Split8& sp) {
+    dst[0] = make_uint4(sp.h[0], sp.h[1], sp.h[2], sp.h[3]);
+    dst[1] = make_uint4(sp.m[0], sp.m[1], sp.m[2], sp.m[3]);
+    dst[2] = make_uint4(sp.l[0], sp.l[1], sp.l[2], sp.l[3]);
+  };
+  std::vector<uint4> hZs((size_t)C * Mp * (BP / 8) * 3), hZsT((size_t)C * BP * (Mq / 8) * 3);
+  for (int c = 0; c < C; ++c) {
+    for (int m = 0; m < Mp; ++m)
+      for (size_t p8 = 0; p8 < BP / 8; ++p8) {
+        float v[8];
+        for (int e = 0; e < 8; ++e) v[e] = zval(c, m, 8 * p8 + e);
+        put(&hZs[(((size_t)c * Mp + m) * (BP / 8) + p8) * 3], split8(v));
+      }
+    for (size_t px = 0; px < BP; ++px)
+      for (int m8 = 0; m8 < Mq / 8; ++m8) {
+        float v[8];
+        for (int e = 0; e < 8; ++e) v[e] = zval(c, 8 * m8 + e, px);
+        put(&hZsT[(((size_t)c * BP + px) * (Mq / 8) + m8) * 3], split8(v));
+      }
+  }
   if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   // the scratch of momfbd_loss_grad_noalloc on this device (a failure here
   // only disables that entry point, which then reports EDEVICE)
   (void)scratch_setup(pl->device);
   if (hipHostMalloc(&pl->hflag, sizeof(int)) != hipSuccess) { delete pl; return MOMFBD_EDEVICE; }
   bool ok = hipMalloc(&pl->Ab, hA.size() * sizeof(float)) == hipSuccess &&
-            hipMalloc(&pl->Zt, hZp.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->Zs, hZs.size() * sizeof(uint4)) == hipSuccess &&
             hipMalloc(&pl->thetat, hT.size() * sizeof(float)) == hipSuccess &&
-            hipMalloc(&pl->ZtT, hZT.size() * sizeof(float)) == hipSuccess &&
+            hipMalloc(&pl->ZsT, hZsT.size() * sizeof(uint4)) == hipSuccess &&
             hipMalloc(&pl->supp, hS.size() * sizeof(int)) == hipSuccess &&
             hipMemcpy(pl->supp, hS.data(), hS.size() * sizeof(int), hipMemcpyHostToDevice) ==
                 hipSuccess &&
-            hipMemcpy(pl->ZtT, hZT.data(), hZT.size() * sizeof(float), hipMemcpyHostToDevice) ==
+            hipMemcpy(pl->ZsT, hZsT.data(), hZsT.size() * sizeof(uint4), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->Ab, hA.data(), hA.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess &&
-            hipMemcpy(pl->Zt, hZp.data(), hZp.size() * sizeof(float), hipMemcpyHostToDevice) ==
+            hipMemcpy(pl->Zs, hZs.data(), hZs.size() * sizeof(uint4), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(pl->thetat, hT.data(), hT.size() * sizeof(float), hipMemcpyHostToDevice) ==
                 hipSuccess;
@@ -359,9 +382,9 @@ int momfbd_plan_destroy(momfbd_plan plan) {
   if (!plan) return MOMFBD_OK;
   profile_free(plan->prof);
   if (plan->Ab) (void)hipFree(plan->Ab);
-  if (plan->Zt) (void)hipFree(plan->Zt);
+  if (plan->Zs) (void)hipFree(plan->Zs);
   if (plan->thetat) (void)hipFree(plan->thetat);
-  if (plan->ZtT) (void)hipFree(plan->ZtT);
+  if (plan->ZsT) (void)hipFree(plan->ZsT);
   if (plan->supp) (void)hipFree(plan->supp);
   if (plan->hflag) (void)hipHostFree(plan->hflag);
   delete plan;
@@ -445,7 +468,7 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   const Workspace w = carve_workspace(plan->d, ws);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
-    return launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+    return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
   });
   if (e == hipSuccess)
     e = prof_launch(plan, KK_FORWARD, s, [&] {
@@ -461,7 +484,7 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
   const Workspace w = carve_workspace(plan->d, ws);
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
   hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
-    return launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+    return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
   });
   if (e == hipSuccess)
     e = prof_launch(plan, KK_FORWARD, s, [&] {
@@ -488,7 +511,7 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
   });
   if (e == hipSuccess)
     e = prof_launch(plan, KK_GRAD, s, [&] {
-      return launch_grad(plan->d, plan->Zt, w.gphi, grad, w.gpart, s);
+      return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
     });
   return to_status(e);
 }
@@ -601,7 +624,7 @@ int momfbd_synthesize(momfbd_plan plan, const float* alpha, const void* O, const
   hipStream_t s = (hipStream_t)stream;
   const Workspace w = carve_workspace(plan->d, ws);
   const int N = plan->d.N;
-  hipError_t e = launch_phase(plan->d, alpha, plan->ZtT, plan->Mp, plan->thetat, w.phi, s);
+  hipError_t e = launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
   if (e == hipSuccess) e = launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
   if (e == hipSuccess)
     e = launch_synth(plan->d, plan->ct, static_cast<const float2*>(O), w.S, noise, sigma, frames,
@@ -897,7 +920,7 @@ struct momfbd_group_s {
   size_t item_off[kGsCount] = {};  // offset of each stage's map in `items`
   int item_count[kGsCount] = {};   // work items of each stage
   std::vector<char> has_eval;     // per field: loss and grad bound
-  int zc_max = 1, Mp_max = 16, mt_max = 1;
+  int zc_max = 1, Mq_max = 32, mt_max = 1;
   long rows = 0;                  // (patch, frame) rows of all fields
   int xcd_fwd = 0, xcd_adj = 1, grad_rt = 4, grad_splits = 0;
 };
@@ -924,7 +947,7 @@ int group_splits(const momfbd_group_s* g) {
 
 // One loss+gradient evaluation of every field (fd: evaluation or solver table).
 hipError_t group_chain(const momfbd_group_s* g, const FieldDesc* fd, hipStream_t s) {
-  hipError_t e = launch_phase_group(group_args(g, fd, kGsPhaseTiles), g->zc_max, g->Mp_max, s);
+  hipError_t e = launch_phase_group(group_args(g, fd, kGsPhaseTiles), g->zc_max, g->Mq_max, s);
   if (e == hipSuccess) e = launch_forward_group(g->N, group_args(g, fd, kGsUnits), g->xcd_fwd, s);
   if (e == hipSuccess)
     e = launch_object_group(g->N, group_args(g, fd, kGsObjBlocks),
@@ -957,7 +980,7 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
   std::vector<FieldDesc> ev(n), so(n);
   std::vector<int2> maps[kGsCount];
   std::vector<char> has_eval(n, 0);
-  int zc_max = 1, Mp_max = 16, mt_max = 1;
+  int zc_max = 1, Mq_max = 32, mt_max = 1;
   long rows = 0;
   for (int f = 0; f < n; ++f) {
     const momfbd_field& a = fields[f];
@@ -970,12 +993,12 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
     FieldDesc F;
     std::memset(&F, 0, sizeof(F));
     F.d = d;
-    F.Mp = pl->Mp;
+    F.Mq = pl->Mq;
     F.ct = pl->ct;
     F.la = LossArgs{static_cast<const float2*>(a.D), a.gamma, a.gamma_scalar, a.weights, pl->supp};
     F.Ab = pl->Ab;
-    F.Zt = pl->Zt;
-    F.ZtT = pl->ZtT;
+    F.Zs = pl->Zs;
+    F.ZsT = pl->ZsT;
     F.thetat = pl->thetat;
     F.alpha = a.alpha;
     F.w = carve_workspace(d, a.ws);
@@ -1012,7 +1035,7 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
       for (long i = 0; i < items[s]; ++i) maps[s].push_back(make_int2(f, (int)i));
     }
     zc_max = std::max(zc_max, d.zc > 0 ? d.zc : d.C);
-    Mp_max = std::max(Mp_max, pl->Mp);
+    Mq_max = std::max(Mq_max, pl->Mq);
     mt_max = std::max(mt_max, (d.M + 15) / 16);
     rows += R;
   }
@@ -1035,7 +1058,7 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
     all.insert(all.end(), maps[st].begin(), maps[st].end());
   }
   g->zc_max = zc_max;
-  g->Mp_max = Mp_max;
+  g->Mq_max = Mq_max;
   g->mt_max = mt_max;
   g->rows = rows;
   const bool ok =

@@ -247,3 +247,70 @@ def test_n96_unit_chain_matches_oracle_gradient(emu):
     g_s = oracle.idft2_un(oracle.expand_half(Gh, 96)).real
     ref = (np.conj(P) * oracle.dft2(2 * kap * g_s * p)).imag[24:72, 24:72]
     assert np.abs(gphi - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+# ------------------------------------------------ bf16 split of FP32 values
+def _split3(emu, x):
+    x = np.ascontiguousarray(x, np.float32)
+    parts = np.zeros((x.size, 3), np.float32)
+    emu.emu_split3(ptr(x), ctypes.c_int(x.size), ptr(parts))
+    return parts
+
+
+def _split_inputs():
+    r = rng(40)
+    mags = 2.0 ** r.integers(-100, 100, 4000)
+    x = (r.standard_normal(4000) * mags).astype(np.float32)
+    # exact for 0 and |x| >= 2^-110 (below, the bits under 2^-133 are lost)
+    special = np.array([0.0, -0.0, 1.0, -1.0, 3.0e38, -3.0e38, 2.0 ** -110, -(2.0 ** -110),
+                        1.1754944e-38, np.float32(1) + np.float32(2 ** -23), 65504.0, 1.0 / 3.0],
+                       np.float32)
+    return np.concatenate([x, special])
+
+
+def test_bf16_split_is_exact(emu):
+    """hi + mid + lo equals x exactly and every part is a bf16 (low 16 bits
+    zero): the contractions' operands lose nothing in the split."""
+    x = _split_inputs()
+    p = _split3(emu, x)
+    assert np.all((p.view(np.uint32) & 0xFFFF) == 0)
+    assert np.array_equal(p.astype(np.float64).sum(1), x.astype(np.float64))
+    # the parts shrink by at least 2^7 and 2^15 relative to |x|
+    ax = np.abs(x.astype(np.float64))
+    assert np.all(np.abs(p[:, 1]) <= ax * 2.0 ** -7)
+    assert np.all(np.abs(p[:, 2]) <= ax * 2.0 ** -15)
+
+
+def test_six_partial_products_keep_fp32_accuracy(emu):
+    """The six products with part orders adding to at most 2 reproduce x y
+    within 2^-21 |x y| (the bound the contraction code states)."""
+    r = rng(41)
+    x = (r.standard_normal(5000) * 2.0 ** r.integers(-20, 20, 5000)).astype(np.float32)
+    y = (r.standard_normal(5000) * 2.0 ** r.integers(-20, 20, 5000)).astype(np.float32)
+    a, b = _split3(emu, x).astype(np.float64), _split3(emu, y).astype(np.float64)
+    six = (a[:, 0] * b[:, 0] + a[:, 0] * b[:, 1] + a[:, 1] * b[:, 0] + a[:, 0] * b[:, 2]
+           + a[:, 2] * b[:, 0] + a[:, 1] * b[:, 1])
+    exact = x.astype(np.float64) * y.astype(np.float64)
+    assert np.all(np.abs(six - exact) <= 2.0 ** -21 * np.abs(exact))
+
+
+@pytest.mark.parametrize("tiny", [False, True])
+def test_bf16_split_packing(emu, tiny):
+    """Eight values pack two per word, element e in bits 16 (e & 1) of word
+    e >> 1, one group of four words per part.  Values below 2^-110 (which a
+    basis holds as rounding noise where a mode vanishes) leave their packed
+    neighbours intact."""
+    x = (rng(42).standard_normal(8) * 10).astype(np.float32)
+    if tiny:
+        x[1], x[4], x[7] = -8.803836e-35, 1.3159354e-33, 3e-38
+    words = np.zeros(12, np.uint32)
+    emu.emu_split8(ptr(x), words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    p = _split3(emu, x).view(np.uint32)
+    assert np.all((p & 0xFFFF) == 0)
+    for part in range(3):
+        w = words[4 * part:4 * part + 4]
+        got = np.stack([w & 0xFFFF, w >> 16], 1).reshape(8)
+        assert np.array_equal(got, p[:, part] >> 16)
+    # the parts of the values of normal size still add up to them exactly
+    ok = np.abs(x.astype(np.float64)) >= 2.0 ** -110
+    assert np.array_equal(p.view(np.float32).astype(np.float64).sum(1)[ok], x.astype(np.float64)[ok])
