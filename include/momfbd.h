@@ -426,14 +426,18 @@ typedef struct {
   int xcd_forward;              /* 1: units of a patch-object on one XCD (L2)   */
   int xcd_adjoint;              /* same for the adjoint kernel                  */
   int object_pairs_per_thread;  /* 1, 2 or 4 frequency pairs per thread         */
-  int grad_waves;               /* gradient contraction: 4 waves x 4 (or 3) row
-                                   tiles, or 8 waves x 2 row tiles per workgroup */
-  int grad_splits;              /* workgroups sharing one row tile's pixel sum:
-                                   1, 2, 4 or 8; 0 on input picks the smallest
-                                   count that gives every CU two workgroups
-                                   (get_tuning reports the count in use)      */
+  int grad_waves;               /* gradient contraction: 4 waves x 4, 3 or 2
+                                   row tiles, or 8 waves x 2 row tiles per
+                                   workgroup; every wave owns its rows, and
+                                   each basis chunk staged in LDS serves all
+                                   the workgroup's rows                       */
+  int grad_splits;              /* workgroups sharing one row block's pixel
+                                   sum: 1, 2, 4 or 8; 0 on input picks the
+                                   count from the number of row blocks and
+                                   pixel chunks (get_tuning reports the count
+                                   in use)                                    */
   int grad_row_tiles;           /* row tiles of 16 (patch, frame) rows per
-                                   workgroup: 4 or 3 with 4 waves (3: more,
+                                   wave: 4, 3 or 2 with 4 waves (fewer: more,
                                    smaller workgroups, each basis chunk
                                    serving fewer rows), 2 with 8 waves; 0 on
                                    input is 4 or 2 (get_tuning reports the
@@ -525,7 +529,7 @@ int momfbd_group_loss_grad(momfbd_group group, void* stream);
 int momfbd_group_lbfgs_rounds(momfbd_group group, int rounds, void* stream);
 
 /* Launch schedules of a group (the fields of momfbd_tuning that apply:
- * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4 or 3; grad_waves
+ * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4, 3 or 2; grad_waves
  * must be 4).  The autotuner times momfbd_group_loss_grad over `reps`
  * evaluations per candidate with the plan autotuner's method and keeps the
  * fastest schedule.  Errors: EINVAL, EDEVICE. */

@@ -33,6 +33,7 @@ namespace mfbd {
 namespace contract {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // The three parts of eight k values of one operand row or column.
@@ -64,31 +65,32 @@ __device__ __forceinline__ Op3 split_op3(const float4& lo, const float4& hi) {
              make_uint4(s.l[0], s.l[1], s.l[2], s.l[3])};
 }
 
-// One block = W waves x RT row tiles (16 RT rows (p,j)) x all mode columns
-// x one of `splits` parts of the k range (blockIdx.y).  The k = c*bp + px
-// range, in 32-wide chunks, is cut into W*splits nearly equal slices; wave w
-// of split s sums slice s*W + w for all RT row tiles, so every basis chunk it
-// loads serves RT x 16 rows (the basis reads through L2 are what bound this
-// contraction).  Splitting k over blocks fills the chip when there are few
-// row tiles.  The gphi values of the next chunk are loaded while the
-// current one is multiplied, and the basis parts of the next mode tile
-// while the current tile is.  The partial sums of a block are added in wave
-// order (wave 0, then 1, ..., W-1) in one LDS buffer; with one split the
-// block writes 2 pi times its sum to grad, otherwise its sum to
-// part[s][R][M], which k_grad_combine adds in split order.  The basis rows
-// are zero-padded to a multiple of 16 per basis, so no mode test is needed
-// inside the loop; rows past R read row R-1 and are not written.
-// Schedules: W = 4 with RT = 3 or 4, or W = 8 with RT = 2.  CS is the number
-// of channels summed per load when they share one basis (0: the run-time
-// C), fixed at compile time where it can be so that the loads of a chunk
-// issue together.
-//
-// Row tile block `bx`, part `split` of `splits` of the k range.  `mt` (at
-// most MT) is the number of 16-mode tiles the basis table holds; tiles
-// beyond it are neither loaded nor multiplied.  CS < 0 selects at run time
-// between separate bases per channel (zc == C) and one shared basis.
+// Gradient.  One block = W waves; wave w owns RT row tiles (16 RT rows
+// (p, j)), so a block covers 16 W RT rows, for all mode columns and one of
+// `splits` parts of the k = c*bp + px range (blockIdx.y), in 32-wide
+// chunks.  The basis parts of a chunk (16 mt modes x 32 pixels x 3 parts)
+// are staged in LDS once per block and serve every wave's rows; the stage
+// is double-buffered (the next chunk's loads are in flight while the
+// current one is multiplied; one barrier per chunk), and each wave loads
+// the gphi values of its next chunk ahead as well.  A wave's sums are
+// complete for its rows over the block's k range: with one split the wave
+// writes 2 pi times them to grad, otherwise them to part[s][R][M], which
+// k_grad_combine adds in split order.  The basis rows are zero-padded to a
+// multiple of 16 per basis, so no mode test is needed inside the loop; rows
+// past R read row R-1 and are not written.  CS is the number of channels
+// summed per load when they share one basis (0: the run-time C), fixed at
+// compile time where it can be so that the loads of a chunk issue together;
+// CS < 0 selects at run time between separate bases per channel (zc == C)
+// and one shared basis.  `mt` (at most MT) is the number of 16-mode tiles
+// the basis table holds; tiles beyond it are neither loaded nor multiplied.
 // Zs: the split basis, [zc][16 mt][bp/8][3] uint4 (eight pixels of one
-// mode, parts hi, mid, lo).
+// mode, parts hi, mid, lo).  LDS: two stages of 16 MT x kStageLd uint4.
+constexpr int kStageLd = 13;   // uint4 per staged mode row: 4 groups x 3 parts, + 1 (banks)
+
+__host__ __device__ __forceinline__ size_t grad_lds_bytes(int mt) {
+  return (size_t)2 * 16 * mt * kStageLd * 16;
+}
+
 template <int MT, int RT, int W, int CS>
 __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt, int R, int J,
                                            int C, int zc, int M, int bp,
@@ -96,10 +98,10 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
                                            const float* __restrict__ gphi,
                                            float* __restrict__ grad,
                                            float* __restrict__ part) {
-  __shared__ floatx4 red[RT * MT][64];
+  extern __shared__ uint4 zst[];   // [2][16 mt][kStageLd]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i16 = lane & 15, g = lane >> 4;
-  const int r0 = bx * 16 * RT;
+  const int r0 = (bx * W + wave) * 16 * RT;
   const size_t cstride = (size_t)J * bp;   // between the channels of one (p, j)
   const float* grow[RT];
 #pragma unroll
@@ -112,10 +114,34 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
   for (int q = 0; q < RT; ++q)
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int nchunk = zc * bp / 32, slices = W * splits, slice = split * W + wave;
-  const int c_begin = (int)((long)slice * nchunk / slices);
-  const int n = (int)((long)(slice + 1) * nchunk / slices) - c_begin;   // chunks of this wave
+  const int nchunk = zc * bp / 32;
+  const int c_begin = (int)((long)split * nchunk / splits);
+  const int n = (int)((long)(split + 1) * nchunk / splits) - c_begin;   // chunks of this block
   const int bp8 = bp / 8;
+  const int stage_n = 16 * mt * 12;                                     // uint4 per chunk
+  constexpr int kPer = (16 * MT * 12 + 64 * W - 1) / (64 * W);          // per thread, at most
+  const int sz = 16 * mt * kStageLd;
+  // the basis parts of chunk kk: mode row m, 12 consecutive uint4 (groups
+  // 0..3 x parts) from pixel kk % bp of basis kk / bp
+  // (held in native vectors, which stay in registers)
+  auto stage_load = [&](int kk, u32x4 (&v)[kPer]) {
+    const int c = kk / bp, px = kk % bp;
+    const u32x4* src =
+        reinterpret_cast<const u32x4*>(Zs + ((size_t)c * mt * 16 * bp8 + px / 8) * 3);
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + e * 64 * W;
+      if (idx < stage_n) v[e] = src[(size_t)(idx / 12) * bp8 * 3 + idx % 12];
+    }
+  };
+  auto stage_store = [&](int buf, const u32x4 (&v)[kPer]) {
+    u32x4* dst = reinterpret_cast<u32x4*>(zst + buf * sz);
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + e * 64 * W;
+      if (idx < stage_n) dst[(idx / 12) * kStageLd + idx % 12] = v[e];
+    }
+  };
   // the eight gphi values of chunk kk in lane group g for each row tile
   // (with one shared basis, the sum over channels in channel order)
   auto load_a = [&](int kk, float4 (&raw)[RT][2]) {
@@ -143,81 +169,75 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
       }
     }
   };
-  // basis parts of mode tile t for chunk kk: row t*16 + i16, pixels kk + 8g ..
-  auto zs_at = [&](int kk, int t) {
-    const int c = kk / bp, px = kk % bp;
-    return Zs + (((size_t)c * mt * 16 + t * 16 + i16) * bp8 + px / 8 + g) * 3;
-  };
+  if (n > 0) {
+    u32x4 v[kPer];
+    stage_load(32 * c_begin, v);
+    stage_store(0, v);
+  }
   float4 raw[RT][2];
   if (n > 0) load_a(32 * c_begin, raw);
+  __syncthreads();
   for (int i = 0; i < n; ++i) {
     const int kk = 32 * (c_begin + i);
+    u32x4 v[kPer];
+    if (i + 1 < n) stage_load(kk + 32, v);
     Op3 a[RT];
 #pragma unroll
     for (int q = 0; q < RT; ++q) a[q] = split_op3(raw[q][0], raw[q][1]);
     if (i + 1 < n) load_a(kk + 32, raw);
-    Op3 b = load_op3(zs_at(kk, 0));
+    const uint4* zb = zst + (i & 1) * sz + i16 * kStageLd + 3 * g;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       if (t < mt) {
-        Op3 bn = b;
-        if (t + 1 < MT && t + 1 < mt) bn = load_op3(zs_at(kk, t + 1));
+        const Op3 b = load_op3(zb + t * 16 * kStageLd);
 #pragma unroll
         for (int q = 0; q < RT; ++q) acc[q][t] = mfma6(a[q], b, acc[q][t]);
-        b = bn;
       }
     }
-  }
-  for (int w = 0; w < W; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int q = 0; q < RT; ++q)
-#pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          if (w == 0)
-            red[q * MT + t][lane] = acc[q][t];
-          else
-            red[q * MT + t][lane] += acc[q][t];
-        }
-    }
+    if (i + 1 < n) stage_store((i + 1) & 1, v);
     __syncthreads();
   }
   float* out = splits == 1 ? grad : part + (size_t)split * R * M;
   const float scale = splits == 1 ? 6.283185307179586f : 1.0f;
-  for (int qt = wave; qt < RT * MT; qt += W) {
-    const int q = qt / MT, t = qt % MT;
-    const floatx4 v = red[qt][lane];
-    const int m = t * 16 + i16;
-    if (m >= M) continue;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = r0 + q * 16 + 4 * g + e;
-      if (row < R) out[(size_t)row * M + m] = scale * v[e];
+  for (int q = 0; q < RT; ++q)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int m = t * 16 + i16;
+      if (t >= mt || m >= M) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = r0 + q * 16 + 4 * g + e;
+        if (row < R) out[(size_t)row * M + m] = scale * acc[q][t][e];
+      }
     }
-  }
 }
 
 // phi^T per channel: D[px][col] = sum_m Z_c[m][px] alpha[col][m], col = p*J + j.
-// Block = 4 waves, (basis, kCols columns, a quarter of the band pixels);
+// Block = 4 waves, (basis, 16 CT columns, a quarter of the band pixels);
 // with one shared basis the block writes every channel's phi from one
-// product.  The block's kCols coefficient rows (contiguous in alpha) are
-// split and staged once in LDS, [col][m/8][part] with the modes padded to
-// Mq (a multiple of 32); each wave then walks tiles of 16 pixels x kCols
-// columns, taking its A parts from the split basis table
-// ZsT[c][px][Mq/8][3] (uint4: eight modes of one pixel) and its B parts
-// from LDS.  32 columns per block (twice the blocks of 64) measured faster
-// with FP32 operands.
-constexpr int kCols = kPhaseCols, kColTiles = kCols / 16;
-
+// product.  The block's coefficient rows (contiguous in alpha) are split
+// and staged once in LDS, [col][m/8][part] with the modes padded to Mq (a
+// multiple of 32); each wave then walks tiles of 16 pixels x 16 CT columns,
+// taking its A parts from the split basis table ZsT[c][px][Mq/8][3] (uint4:
+// eight modes of one pixel, loaded one step ahead) and its B parts from
+// LDS.  Every basis part a wave loads serves CT column tiles, so the basis
+// reads through L2 fall as 1 / CT.
 // uint4 row stride of the staged coefficients: odd, so that the 16 columns
 // one read touches fall on distinct 16-byte bank groups.
 __host__ __device__ __forceinline__ int phase_lds_stride(int Mq) { return (3 * (Mq / 8)) | 1; }
 
+__host__ __device__ __forceinline__ size_t phase_lds_bytes(int ct, int Mq) {
+  return (size_t)16 * ct * phase_lds_stride(Mq) * 16;
+}
+
+template <int CT>
 __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C, int zc, int M,
                                             int Mq, int bp, const uint4* __restrict__ ZsT,
                                             const float* __restrict__ theta,
                                             const float* __restrict__ alpha,
                                             float* __restrict__ phi) {
+  constexpr int kCols = 16 * CT;
   extern __shared__ uint4 als[];   // [kCols][phase_lds_stride(Mq)]
   const int q8 = Mq / 8, ld = phase_lds_stride(Mq);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -242,33 +262,50 @@ __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C,
   }
   __syncthreads();
   const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
-  for (int tile = 0; tile < ntile; ++tile) {
-    const int px0 = quarter * (bp / 4) + (tile * 4 + wave) * 16;
-    floatx4 acc[kColTiles];
+  const int nct = (ncol + 15) / 16;  // column tiles holding columns
+  const int nk = q8 / 4;             // 32-mode chunks per tile
+  // (tile, chunk) steps in order; the A parts of the next step are loaded
+  // while the current one is multiplied
+  auto px_of = [&](int tile) { return quarter * (bp / 4) + (tile * 4 + wave) * 16; };
+  auto load_a = [&](int it) {
+    const int px0 = px_of(it / nk), k8 = (it % nk) * 4;
+    return load_op3(ZsT + ((size_t)(c * bp + px0 + i16) * q8 + g + k8) * 3);
+  };
+  const int steps = ntile * nk;
+  floatx4 acc[CT];
 #pragma unroll
-    for (int t = 0; t < kColTiles; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const uint4* arow = ZsT + ((size_t)(c * bp + px0 + i16) * q8 + g) * 3;
-    for (int k8 = 0; k8 < q8; k8 += 4) {
-      const Op3 a = load_op3(arow + 3 * k8);
+  for (int t = 0; t < CT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  Op3 a = load_a(0);
+  for (int it = 0; it < steps; ++it) {
+    Op3 an = a;
+    if (it + 1 < steps) an = load_a(it + 1);
+    const int k8 = (it % nk) * 4;
 #pragma unroll
-      for (int t = 0; t < kColTiles; ++t) {
+    for (int t = 0; t < CT; ++t) {
+      if (t < nct) {
         const Op3 b = load_op3(als + (t * 16 + i16) * ld + 3 * (k8 + g));
         acc[t] = mfma6(a, b, acc[t]);
       }
     }
+    a = an;
+    if (it % nk != nk - 1) continue;
+    // the tile is complete: theta added, phi written, sums cleared
+    const int px0 = px_of(it / nk);
     const int c_lo = zc == C ? c : 0, c_hi = zc == C ? c + 1 : C;
     for (int ch = c_lo; ch < c_hi; ++ch) {
       const floatx4 th =
           *reinterpret_cast<const floatx4*>(theta + (size_t)ch * bp + px0 + 4 * g);
 #pragma unroll
-      for (int t = 0; t < kColTiles; ++t) {
+      for (int t = 0; t < CT; ++t) {
         const int col = col0 + t * 16 + i16;
-        if (col >= R) continue;
+        if (t >= nct || col >= R) continue;
         const int p = col / J, j = col % J;
         *reinterpret_cast<floatx4*>(phi + (((size_t)p * C + ch) * J + j) * bp + px0 + 4 * g) =
             acc[t] + th;
       }
     }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
 }
 

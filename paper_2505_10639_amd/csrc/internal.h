@@ -158,10 +158,11 @@ struct FieldDesc {
   float* alpha_accepted;   // [P][J][M] or null
 };
 // work items per field: units P C J; patches P; phase tiles of 32 (patch,
-// frame) rows; object blocks P K object_blocks(N); gradient row tiles of
-// 64 or 48 rows; blocks of 256 patches; blocks of 256 coefficients (P J M)
+// frame) rows; object blocks P K object_blocks(N); gradient blocks of 256,
+// 192 or 128 rows (4 waves of 4, 3 or 2 row tiles); blocks of 256 patches;
+// blocks of 256 coefficients (P J M)
 enum GroupStage { kGsUnits, kGsPatches, kGsPhaseTiles, kGsObjBlocks, kGsGradTiles4,
-                  kGsGradTiles3, kGsPatchBlocks, kGsElemBlocks, kGsCount };
+                  kGsGradTiles3, kGsGradTiles2, kGsPatchBlocks, kGsElemBlocks, kGsCount };
 struct GroupArgs {
   const FieldDesc* fd;     // [fields] (device)
   const int2* item;        // [total] (field, item of that field) per work item (device)

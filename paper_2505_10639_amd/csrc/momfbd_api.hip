@@ -400,7 +400,7 @@ static bool tuning_ok(const momfbd_tuning* t) {
          (t->grad_splits == 0 || t->grad_splits == 1 || t->grad_splits == 2 ||
           t->grad_splits == 4 || t->grad_splits == 8) &&
          (t->grad_row_tiles == 0 ||
-          (t->grad_waves == 4 ? t->grad_row_tiles == 3 || t->grad_row_tiles == 4
+          (t->grad_waves == 4 ? t->grad_row_tiles >= 2 && t->grad_row_tiles <= 4
                               : t->grad_row_tiles == 2));
 }
 
@@ -411,7 +411,7 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   plan->d.obj_ppt = t->object_pairs_per_thread;
   plan->d.grad_waves = t->grad_waves;
   plan->d.grad_splits = t->grad_splits;
-  plan->d.grad_rt = t->grad_row_tiles == 3 ? 3 : 0;
+  plan->d.grad_rt = t->grad_row_tiles == 3 || t->grad_row_tiles == 2 ? t->grad_row_tiles : 0;
   return MOMFBD_OK;
 }
 
@@ -782,7 +782,8 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // far only when at least 1% faster, so that timing noise between
   // near-equal schedules does not decide (the XCD-grouped orders read less
   // from HBM at equal speed).
-  // The gradient's row tiles (4 or 3) are a choice only with 4 waves.  Its
+  // The gradient's row tiles per wave (4, 3 or 2) are a choice only with 4
+  // waves.  Its
   // split count starts from the automatic one for the chosen waves and row
   // tiles; the others follow in increasing order.
   constexpr int kRounds = 3;
@@ -792,7 +793,7 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   for (int k = 0; k < 6 && st == MOMFBD_OK; ++k) {
     if (k == 4) {
       plan->d.grad_rt = 0;
-      values[4] = plan->d.grad_waves == 8 ? std::vector<int>{0} : std::vector<int>{0, 3};
+      values[4] = plan->d.grad_waves == 8 ? std::vector<int>{0} : std::vector<int>{0, 3, 2};
     }
     if (k == 5) {
       plan->d.grad_splits = 0;
@@ -940,7 +941,7 @@ int group_splits(const momfbd_group_s* g) {
   // the automatic count of a plan with all the group's rows
   Dims d{g->N, (int)std::min<long>(g->rows, 1L << 30), 1, 1, 1, 1};
   d.grad_waves = 4;
-  d.grad_rt = g->grad_rt == 3 ? 3 : 0;
+  d.grad_rt = g->grad_rt == 4 ? 0 : g->grad_rt;
   d.zc = g->zc_max;
   return grad_splits_auto(d);
 }
@@ -954,7 +955,9 @@ hipError_t group_chain(const momfbd_group_s* g, const FieldDesc* fd, hipStream_t
                             group_args(g, fd, kGsPatchBlocks), s);
   if (e == hipSuccess) e = launch_adjoint_group(g->N, group_args(g, fd, kGsUnits), g->xcd_adj, s);
   if (e == hipSuccess)
-    e = launch_grad_group(group_args(g, fd, g->grad_rt == 3 ? kGsGradTiles3 : kGsGradTiles4),
+    e = launch_grad_group(group_args(g, fd, g->grad_rt == 3   ? kGsGradTiles3
+                                            : g->grad_rt == 2 ? kGsGradTiles2
+                                                              : kGsGradTiles4),
                           group_args(g, fd, kGsElemBlocks), g->mt_max, g->grad_rt,
                           group_splits(g), s);
   return e;
@@ -1026,8 +1029,9 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
                                   d.P,
                                   (R + kPhaseCols - 1) / kPhaseCols,
                                   (long)d.P * d.K * object_blocks(N, 1),
-                                  (R + 63) / 64,
-                                  (R + 47) / 48,
+                                  (R + 255) / 256,
+                                  (R + 191) / 192,
+                                  (R + 127) / 128,
                                   (d.P + 255) / 256,
                                   (R * d.M + 255) / 256};
     for (int s = 0; s < kGsCount; ++s) {
@@ -1115,7 +1119,7 @@ int momfbd_group_set_tuning(momfbd_group g, const momfbd_tuning* t) {
   if (!g || !tuning_ok(t) || t->grad_waves != 4) return MOMFBD_EINVAL;
   g->xcd_fwd = t->xcd_forward;
   g->xcd_adj = t->xcd_adjoint;
-  g->grad_rt = t->grad_row_tiles == 3 ? 3 : 4;
+  g->grad_rt = t->grad_row_tiles == 3 || t->grad_row_tiles == 2 ? t->grad_row_tiles : 4;
   g->grad_splits = t->grad_splits;
   return MOMFBD_OK;
 }
@@ -1158,7 +1162,7 @@ int momfbd_group_autotune(momfbd_group g, int reps, void* stream, momfbd_tuning*
   // three rounds, each keeping its fastest; the default first, replaced only
   // by a value at least 1% faster
   int* knobs[4] = {&g->xcd_adj, &g->xcd_fwd, &g->grad_rt, &g->grad_splits};
-  std::vector<int> values[4] = {{1, 0}, {0, 1}, {4, 3}, {}};
+  std::vector<int> values[4] = {{1, 0}, {0, 1}, {4, 3, 2}, {}};
   for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
     if (k == 3) {
       g->grad_splits = 0;

@@ -506,26 +506,29 @@ def test_launch_schedules_and_autotune(dev, N):
     """Every launch schedule gives the default results: bit for bit where
     only the order of the work changes (unit order), to the rounding of a
     regrouped sum where the grouping of partial sums changes (object pairs
-    per thread: FP64 loss; gradient waves and pixel-sum splits: FP32
-    gradient).  The split counts include ones that leave waves with
-    different chunk counts (N = 96: 144 chunks over 4 x 8 or 8 x 8 slices).
-    Three row tiles per workgroup in place of four give the same sums bit
-    for bit (same slices, same order).  The autotuned plan still matches
-    the oracle."""
+    per thread: FP64 loss; gradient pixel-sum splits: FP32 gradient).  The
+    gradient's waves and row tiles per wave change which wave sums a row,
+    not the order of its sum, so they give the same gradient bit for bit at
+    equal splits.  The split counts include ones that leave workgroups with
+    different chunk counts (N = 96: 72 chunks of 32 pixels over 8 splits).
+    The autotuned plan still matches the oracle."""
     pr = synth.make_problem(70 + N, N=N, P=3, J=3, M=28, channels=((0, 0.0), (1, 1.0)),
                             d_over_r0=np.array([7.0, 11.0, 15.0]), border=N // 10)
     D_np = simulate_D(pr)
     D = to_dev(D_np, dev)
     a = to_dev(alpha_points(pr, 10)["perturbed"], dev)
     plan = make_plan(pr, dev)
-    # 9 rows (p, j): one row-tile block, so the automatic split count is the
-    # largest that leaves every wave a chunk of 16 pixels (8)
+    # 9 rows (p, j): one row block, so the automatic split count is the
+    # largest that leaves every split at least 8 chunks of 32 pixels (one
+    # shared basis: 32 chunks at N = 64, 72 at N = 96, 128 at N = 128)
+    auto = {64: 4, 96: 8, 128: 8}[N]
     assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
-                             "grad_waves": 4, "grad_splits": 8, "grad_row_tiles": 4}
+                             "grad_waves": 4, "grad_splits": auto, "grad_row_tiles": 4}
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
     for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
                   (1, 0, 4, 8), (0, 1, 1, 4, 8), (0, 1, 1, 4, 1), (0, 1, 1, 4, 2),
-                  (0, 1, 1, 8, 8), (0, 1, 1, 8, 1), (0, 1, 1, 4, 8, 3), (0, 1, 1, 4, 2, 3)]:
+                  (0, 1, 1, 8, 8), (0, 1, 1, 8, 1), (0, 1, 1, 4, 8, 3), (0, 1, 1, 4, 2, 3),
+                  (0, 1, 1, 4, auto, 2), (0, 1, 1, 4, 1, 2), (0, 1, 1, 8, auto)]:
         print(f"[tuning] N={N} {knobs}", flush=True)
         plan.set_tuning(*knobs)
         l1, g1 = plan.loss_grad(a, D, pr.gamma)
@@ -534,7 +537,7 @@ def test_launch_schedules_and_autotune(dev, N):
             assert torch.equal(l1, l0)
         else:
             assert float(((l1 - l0).abs() / l0.abs()).max()) < 1e-12
-        if knobs[3] == 4 and plan.tuning()["grad_splits"] == 8:
+        if plan.tuning()["grad_splits"] == auto:
             assert torch.equal(g1, g0)
         else:
             assert float((g1 - g0).norm() / g0.norm()) < 1e-6
@@ -554,7 +557,7 @@ def test_launch_schedules_and_autotune(dev, N):
     with pytest.raises(Exception):
         plan.set_tuning(0, 1, 1, 8, 0, 3)
     with pytest.raises(Exception):
-        plan.set_tuning(0, 1, 1, 4, 0, 2)
+        plan.set_tuning(0, 1, 1, 4, 0, 1)
     plan.close()
 
 
