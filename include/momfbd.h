@@ -447,15 +447,16 @@ typedef struct {
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
 int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
 /* Choose the schedules by timing: one knob at a time, every candidate value
- * is timed over `reps` loss+gradient evaluations of the caller's data (HIP
- * events on `stream`, which this call synchronises), in three interleaved
- * rounds; each candidate keeps its fastest round, and the fastest
- * candidate is kept.  The first candidate of each knob is the library
- * default, and another value replaces the best so far only when at least
- * 1% faster.
- * loss [P] and grad [P][J][M] (device) receive the last evaluation.  The
- * choice is stored in the plan and, if `chosen` is not NULL, returned.
- * Errors: EINVAL, EWORKSPACE, EDEVICE. */
+ * is timed on the caller's data (HIP events on `stream`, which this call
+ * synchronises) by the one kernel the knob changes, run 4 x `reps` times
+ * back to back after a whole evaluation under that candidate's schedule,
+ * in three interleaved rounds; each candidate keeps its fastest round, and
+ * the fastest candidate is kept.  The first candidate of each knob is the
+ * library default, and another value replaces the best so far only when at
+ * least 1% faster.
+ * loss [P] and grad [P][J][M] (device) receive an evaluation under the
+ * chosen schedules.  The choice is stored in the plan and, if `chosen` is
+ * not NULL, returned.  Errors: EINVAL, EWORKSPACE, EDEVICE. */
 int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                          float gamma_scalar, const float* weights, int reps, double* loss,
                          float* grad, void* ws, size_t ws_bytes, void* stream,

@@ -214,7 +214,7 @@ __device__ __forceinline__ void grad_block(int bx, int split, int splits, int mt
 }
 
 // phi^T per channel: D[px][col] = sum_m Z_c[m][px] alpha[col][m], col = p*J + j.
-// Block = 4 waves, (basis, 16 CT columns, a quarter of the band pixels);
+// Block = W waves, (basis, 16 CT columns, a quarter of the band pixels);
 // with one shared basis the block writes every channel's phi from one
 // product.  The block's coefficient rows (contiguous in alpha) are split
 // and staged once in LDS, [col][m/8][part] with the modes padded to Mq (a
@@ -231,7 +231,7 @@ __host__ __device__ __forceinline__ size_t phase_lds_bytes(int ct, int Mq) {
   return (size_t)16 * ct * phase_lds_stride(Mq) * 16;
 }
 
-template <int CT>
+template <int CT, int W>
 __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C, int zc, int M,
                                             int Mq, int bp, const uint4* __restrict__ ZsT,
                                             const float* __restrict__ theta,
@@ -246,7 +246,7 @@ __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C,
   const int col0 = by * kCols;
   const int ncol = min(kCols, R - col0);
   const float* src = alpha + (size_t)col0 * M;
-  for (int idx = threadIdx.x; idx < kCols * q8; idx += 256) {
+  for (int idx = threadIdx.x; idx < kCols * q8; idx += 64 * W) {
     const int r = idx / q8, m8 = idx % q8;
     float v[8];
 #pragma unroll
@@ -261,12 +261,14 @@ __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C,
     dst[2] = make_uint4(sp.l[0], sp.l[1], sp.l[2], sp.l[3]);
   }
   __syncthreads();
-  const int ntile = bp / 256;        // 16-pixel tiles per wave in a quarter
+  // 16-pixel tiles of the quarter: wave w takes tiles w, w + W, ...
+  const int qtiles = bp / 64;
+  const int ntile = (qtiles - wave + W - 1) / W;
   const int nct = (ncol + 15) / 16;  // column tiles holding columns
   const int nk = q8 / 4;             // 32-mode chunks per tile
   // (tile, chunk) steps in order; the A parts of the next step are loaded
   // while the current one is multiplied
-  auto px_of = [&](int tile) { return quarter * (bp / 4) + (tile * 4 + wave) * 16; };
+  auto px_of = [&](int tile) { return quarter * (bp / 4) + (tile * W + wave) * 16; };
   auto load_a = [&](int it) {
     const int px0 = px_of(it / nk), k8 = (it % nk) * 4;
     return load_op3(ZsT + ((size_t)(c * bp + px0 + i16) * q8 + g + k8) * 3);
@@ -275,7 +277,8 @@ __device__ __forceinline__ void phase_block(int bx, int by, int R, int J, int C,
   floatx4 acc[CT];
 #pragma unroll
   for (int t = 0; t < CT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  Op3 a = load_a(0);
+  Op3 a;
+  if (steps > 0) a = load_a(0);
   for (int it = 0; it < steps; ++it) {
     Op3 an = a;
     if (it + 1 < steps) an = load_a(it + 1);

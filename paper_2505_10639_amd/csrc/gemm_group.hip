@@ -20,7 +20,7 @@ __global__ __launch_bounds__(256) void k_phase_group(GroupArgs ga) {
   const FieldDesc& F = ga.fd[it.x];
   const int zc = zc_of(F.d);
   if ((int)blockIdx.x >= 4 * zc) return;
-  contract::phase_block<kPhaseCols / 16>(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc,
+  contract::phase_block<kPhaseCols / 16, 4>(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc,
                                         F.d.M, F.Mq, F.d.bandpix(), F.ZsT, F.thetat, F.alpha,
                                         F.w.phi);
 }

@@ -20,15 +20,15 @@ __global__ __launch_bounds__(64 * W) void k_grad_mfma(int R, int J, int C, int z
                                       Zs, gphi, grad, part);
 }
 
-template <int CT>
-__global__ __launch_bounds__(256) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mq,
+template <int CT, int W>
+__global__ __launch_bounds__(64 * W) void k_phase_mfma(int R, int J, int C, int zc, int M, int Mq,
                                                     int bp,
                                                     const uint4* __restrict__ ZsT,
                                                     const float* __restrict__ theta,
                                                     const float* __restrict__ alpha,
                                                     float* __restrict__ phi) {
-  contract::phase_block<CT>(blockIdx.x, blockIdx.y, R, J, C, zc, M, Mq, bp, ZsT, theta, alpha,
-                            phi);
+  contract::phase_block<CT, W>(blockIdx.x, blockIdx.y, R, J, C, zc, M, Mq, bp, ZsT, theta,
+                               alpha, phi);
 }
 
 // Dynamic LDS beyond the default 64 KB needs the kernel's attribute.
@@ -125,34 +125,30 @@ hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float*
   return hipGetLastError();
 }
 
-// Column tiles per phase block: the most (up to 8) whose staged
-// coefficients fit the default 64 KB of LDS.
-int phase_col_tiles(int Mq) {
-  for (int ct = 8; ct > 2; ct /= 2)
-    if (contract::phase_lds_bytes(ct, Mq) <= 64 * 1024) return ct;
-  return 2;
-}
-
-template <int CT>
+// Phase blocks: 128 columns and 8 waves when the staged coefficients fit
+// 128 KB of LDS, else 64 columns (4 waves) within 64 KB, else 32.  Every
+// basis part read serves all the block's columns, so the widest block that
+// fits reads the basis least often.
+template <int CT, int W>
 hipError_t launch_phase_ct(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                            const float* thetat, float* phi, hipStream_t s) {
   const int R = d.P * d.J, zc = d.zc > 0 ? d.zc : d.C;
   const dim3 grid(zc * 4, (R + 16 * CT - 1) / (16 * CT));
   const size_t lds = contract::phase_lds_bytes(CT, Mq);
-  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_phase_mfma<CT>), lds);
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_phase_mfma<CT, W>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phase_mfma<CT>, grid, dim3(256), lds, s, R, d.J, d.C, zc, d.M, Mq,
+  hipLaunchKernelGGL((k_phase_mfma<CT, W>), grid, dim3(64 * W), lds, s, R, d.J, d.C, zc, d.M, Mq,
                      d.bandpix(), ZsT, thetat, alpha, phi);
   return hipGetLastError();
 }
 
 hipError_t launch_phase(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                         const float* thetat, float* phi, hipStream_t s) {
-  switch (phase_col_tiles(Mq)) {
-    case 8: return launch_phase_ct<8>(d, alpha, ZsT, Mq, thetat, phi, s);
-    case 4: return launch_phase_ct<4>(d, alpha, ZsT, Mq, thetat, phi, s);
-    default: return launch_phase_ct<2>(d, alpha, ZsT, Mq, thetat, phi, s);
-  }
+  if (contract::phase_lds_bytes(8, Mq) <= 128 * 1024)
+    return launch_phase_ct<8, 8>(d, alpha, ZsT, Mq, thetat, phi, s);
+  if (contract::phase_lds_bytes(4, Mq) <= 64 * 1024)
+    return launch_phase_ct<4, 4>(d, alpha, ZsT, Mq, thetat, phi, s);
+  return launch_phase_ct<2, 4>(d, alpha, ZsT, Mq, thetat, phi, s);
 }
 
 }  // namespace mfbd

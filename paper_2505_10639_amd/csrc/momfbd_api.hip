@@ -762,14 +762,28 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
     if (e0) (void)hipEventDestroy(e0);
     return MOMFBD_EDEVICE;
   }
-  auto timed = [&](float* ms) -> int {
+  // A knob changes one kernel's launch only, so a candidate is timed by
+  // that kernel alone: one whole evaluation under the candidate's schedule
+  // fills the workspace, then the kernel runs 4 reps times back to back
+  // (every kernel overwrites its outputs from unchanged inputs).
+  const Workspace w = carve_workspace(plan->d, ws);
+  const LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
+  auto launch_knob = [&](int knob) -> hipError_t {
+    switch (knob) {
+      case 0:
+        return launch_adjoint(plan->d, plan->ct, la, nullptr, plan->Ab, w.phi, w.S, w.O, w.gphi,
+                              s);
+      case 1: return launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
+      case 2: return launch_object(plan->d, plan->ct, la, nullptr, w.S, w.O, w.loss_pk, loss, s);
+      default: return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
+    }
+  };
+  auto timed = [&](int knob, float* ms) -> int {
     int r = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws, s);
     if (r) return r;
     if (hipEventRecord(e0, s) != hipSuccess) return MOMFBD_EDEVICE;
-    for (int i = 0; i < reps; ++i) {
-      r = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws, s);
-      if (r) return r;
-    }
+    for (int i = 0; i < 4 * reps; ++i)
+      if (launch_knob(knob) != hipSuccess) return MOMFBD_EDEVICE;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(ms, e0, e1) != hipSuccess)
       return MOMFBD_EDEVICE;
@@ -782,47 +796,60 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // far only when at least 1% faster, so that timing noise between
   // near-equal schedules does not decide (the XCD-grouped orders read less
   // from HBM at equal speed).
-  // The gradient's row tiles per wave (4, 3 or 2) are a choice only with 4
-  // waves.  Its
-  // split count starts from the automatic one for the chosen waves and row
-  // tiles; the others follow in increasing order.
+  // The gradient's shape is one knob: 4 waves with 4, 3 or 2 row tiles, or
+  // 8 waves with 2 (each with its automatic split count); its split count
+  // is the next knob, starting from the automatic one for the chosen shape,
+  // the others following in increasing order.  After the last knob, one
+  // whole evaluation under the chosen schedules leaves the loss and
+  // gradient outputs of that schedule.  Knobs 0-4 time the adjoint, the
+  // forward, the object kernel and (3, 4) the gradient contraction.
   constexpr int kRounds = 3;
-  int* knobs[6] = {&plan->d.xcd_adj, &plan->d.xcd_fwd,  &plan->d.obj_ppt,
-                   &plan->d.grad_waves, &plan->d.grad_rt, &plan->d.grad_splits};
-  std::vector<int> values[6] = {{1, 0}, {0, 1}, {1, 2, 4}, {4, 8}, {}, {}};
-  for (int k = 0; k < 6 && st == MOMFBD_OK; ++k) {
-    if (k == 4) {
-      plan->d.grad_rt = 0;
-      values[4] = plan->d.grad_waves == 8 ? std::vector<int>{0} : std::vector<int>{0, 3, 2};
+  static const int kShapes[4][2] = {{4, 0}, {4, 3}, {4, 2}, {8, 0}};
+  auto set_knob = [&](int k, int v) {
+    switch (k) {
+      case 0: plan->d.xcd_adj = v; break;
+      case 1: plan->d.xcd_fwd = v; break;
+      case 2: plan->d.obj_ppt = v; break;
+      case 3:
+        plan->d.grad_waves = kShapes[v][0];
+        plan->d.grad_rt = kShapes[v][1];
+        plan->d.grad_splits = 0;
+        break;
+      default: plan->d.grad_splits = v; break;
     }
-    if (k == 5) {
+  };
+  const Dims keep_d = plan->d;
+  std::vector<int> values[5] = {{1, 0}, {0, 1}, {1, 2, 4}, {0, 1, 2, 3}, {}};
+  for (int k = 0; k < 5 && st == MOMFBD_OK; ++k) {
+    if (k == 4) {
       plan->d.grad_splits = 0;
       const int a = grad_splits_auto(plan->d);
-      values[5] = {a};
+      values[4] = {a};
       for (int v = 1; v <= kMaxGradSplits; v *= 2)
-        if (v != a) values[5].push_back(v);
+        if (v != a) values[4].push_back(v);
     }
-    const int keep = *knobs[k];
     std::vector<float> fastest(values[k].size(), 0.f);
     for (int r = 0; r < kRounds && st == MOMFBD_OK; ++r) {
       for (size_t i = 0; i < values[k].size(); ++i) {
-        *knobs[k] = values[k][i];
+        set_knob(k, values[k][i]);
         float ms = 0.f;
-        if ((st = timed(&ms))) break;
+        if ((st = timed(k < 3 ? k : 3, &ms))) break;
         if (r == 0 || ms < fastest[i]) fastest[i] = ms;
       }
     }
     if (st) {
-      *knobs[k] = keep;
+      plan->d = keep_d;
       break;
     }
     size_t best = 0;
     for (size_t i = 1; i < values[k].size(); ++i)
       if (fastest[i] < 0.99f * fastest[best]) best = i;
-    *knobs[k] = values[k][best];
+    set_knob(k, values[k][best]);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (st) return st;
+  st = run_loss_grad(plan, alpha, D, gamma, gamma_scalar, weights, nullptr, loss, grad, ws, s);
   if (st) return st;
   if (chosen) momfbd_plan_get_tuning(plan, chosen);
   return MOMFBD_OK;
