@@ -67,18 +67,18 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "ba92e81ba74a", "knob": "xcd_adjoint",
-                      "by_value": {1: (895388542, 94470144), 0: (1094425920, 94470144)}},
-    ("forward", 64): {"sources_sha1": "ba92e81ba74a", "knob": "xcd_forward",
-                      "by_value": {0: (94920707, 403193326)}},
-    ("object", 64): {"sources_sha1": "eb8c3f1ada21", "knob": "object_pairs_per_thread",
-                     "by_value": {1: (729207124, 32782473)}},
-    ("adjoint", 128): {"sources_sha1": "234a21b1ccbc", "knob": "xcd_adjoint",
-                       "by_value": {1: (12023725246, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "234a21b1ccbc", "knob": "xcd_forward",
-                       "by_value": {0: (1554319630, 6522697194)}},
-    ("object", 128): {"sources_sha1": "eb8c3f1ada21", "knob": "object_pairs_per_thread",
-                      "by_value": {1: (10901721867, 257958827)}},
+    ("adjoint", 64): {"sources_sha1": "bb116f9343cf", "knob": "xcd_adjoint",
+                      "by_value": {1: (895416936, 94470144), 0: (1094435590, 94470144)}},
+    ("forward", 64): {"sources_sha1": "bb116f9343cf", "knob": "xcd_forward",
+                      "by_value": {0: (94921217, 403049941), 1: (94920028, 398984793)}},
+    ("object", 64): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
+                     "by_value": {1: (729207024, 32782492)}},
+    ("adjoint", 128): {"sources_sha1": "796bb8104eb1", "knob": "xcd_adjoint",
+                       "by_value": {1: (12001317328, 1511522304), 0: (13412394412, 1511522304)}},
+    ("forward", 128): {"sources_sha1": "796bb8104eb1", "knob": "xcd_forward",
+                       "by_value": {0: (1528739883, 6320632672), 1: (1574018260, 6156851616)}},
+    ("object", 128): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
+                      "by_value": {1: (10901716579, 257958892)}},
 }
 
 
