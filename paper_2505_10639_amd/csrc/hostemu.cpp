@@ -365,6 +365,51 @@ void r2c(WG& w, const float (&s)[L][64], float2 (&X)[L][32], float2 (&x64)[128])
   for (int l = 0; l < L; ++l) n128::op2_collect(w.T, l, X[l]);
 }
 
+// the forward kernel's form: both transposes through the half-size buffer
+struct WGH {
+  float Th[n128::LDS_HALF];
+  float2 Taux[n128::LDS_AUX];
+};
+
+void pupil_to_p_half(WGH& w, const float* A, const float* ph, float2 (&p)[L][64]) {
+  static float2 z[L][32];
+  for (int l = 0; l < L; ++l) {
+    const int q = l >> 2, r = l & 3;
+    for (int n = 0; n < 32; ++n) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int h = 0; h < 2; ++h) {
+        const int nn = n + 32 * h;
+        const double ang = 2.0 * M_PI * ((double)ph[nn * 64 + q] + (32.0 + nn) * r / 128.0);
+        const float a = A[nn * 64 + q];
+        acc = cadd(acc, make_float2(a * (float)std::cos(ang), a * (float)std::sin(ang)));
+      }
+      z[l][n] = acc;
+    }
+    fft32<+1>(z[l]);
+  }
+  for (int l = 0; l < L; ++l) n128::op1_cols_put<0>(z[l], w.Th, l);
+  for (int l = 0; l < L; ++l) n128::op1_rows_get<0>(w.Th, l, p[l]);
+  for (int l = 0; l < L; ++l) n128::op1_cols_put<1>(z[l], w.Th, l);
+  for (int l = 0; l < L; ++l) n128::op1_rows_get<1>(w.Th, l, p[l]);
+  for (int l = 0; l < L; ++l) n128::op1_rows_fft(p[l], l);
+}
+
+void r2c_half(WGH& w, const float (&s)[L][64], float2 (&X)[L][32], float2 (&x64)[128]) {
+  static float keep[L][32], send[L][32], other[L][32], ax[L][32], bx[L][32];
+  static float2 v[L][32];
+  for (int l = 0; l < L; ++l) n128::op2_rows_fold(s[l], keep[l], send[l], l);
+  for (int l = 0; l < L; ++l) n128::xput(send[l], w.Th, l);
+  for (int l = 0; l < L; ++l) n128::xget(w.Th, l, other[l]);
+  for (int l = 0; l < L; ++l) n128::op2_rows_values(keep[l], other[l], l, v[l]);
+  for (int l = 0; l < L; ++l) n128::op2_rows_put<0>(v[l], w.Th, l);
+  for (int l = 0; l < L; ++l) n128::op2_cols_half_x(w.Th, l, ax[l], bx[l]);
+  for (int l = 0; l < L; ++l) n128::op2_rows_put<1>(v[l], w.Th, l);
+  for (int l = 0; l < L; ++l) n128::op2_cols_half_y(w.Th, w.Taux, l, ax[l], bx[l], X[l]);
+  float2* T2 = reinterpret_cast<float2*>(w.Th);
+  for (int l = 0; l < 128; ++l) x64[l] = n128::op2_unpack(w.Taux, T2, l);
+  for (int l = 0; l < L; ++l) n128::op2_collect(T2, l, X[l]);
+}
+
 void c2r(WG& w, float2 (&X)[L][32], const float2 (&x64)[128], float (&g)[L][64]) {
   static float keep[L][32], send[L][32], other[L][32];
   for (int l = 0; l < 128; ++l) w.Taux[l] = x64[l];
@@ -394,6 +439,28 @@ void emu128_pupil_ifft(const float* A, const float* ph, float* p) {
   float2* o = reinterpret_cast<float2*>(p);
   for (int l = 0; l < 256; ++l)
     for (int m = 0; m < 64; ++m) o[(l >> 1) * 128 + 2 * m + (l & 1)] = pp[l][m];
+}
+
+void emu128_pupil_ifft_half(const float* A, const float* ph, float* p) {
+  static e128::WGH w;
+  static float2 pp[256][64];
+  e128::pupil_to_p_half(w, A, ph, pp);
+  float2* o = reinterpret_cast<float2*>(p);
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) o[(l >> 1) * 128 + 2 * m + (l & 1)] = pp[l][m];
+}
+
+void emu128_r2c_half(const float* img, float* half) {
+  static e128::WGH w;
+  static float s[256][64];
+  static float2 X[256][32], x64[128];
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 64; ++m) s[l][m] = img[(l >> 1) * 128 + 2 * m + (l & 1)];
+  e128::r2c_half(w, s, X, x64);
+  float2* h = reinterpret_cast<float2*>(half);
+  for (int l = 0; l < 256; ++l)
+    for (int m = 0; m < 32; ++m) h[n128::sl_index(l, m)] = X[l][m];
+  for (int l = 0; l < 128; ++l) h[n128::sl_index64(l)] = x64[l];
 }
 
 void emu128_r2c(const float* img, float* half) {

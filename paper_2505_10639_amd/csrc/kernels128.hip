@@ -46,34 +46,10 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A,
   }
 }
 
-// |.|^2 of the PSF amplitude, then the real forward transform; ends with S
-// in spectral layout (x64 on lanes < 128).
-__device__ __forceinline__ void psf_to_otf(float2 (&p)[64], float kap, float* psf_row_or_null,
-                                           float2* T, float2* Taux, int lane, float2 (&X)[32],
-                                           float2& x64) {
-  float s[64];
-#pragma unroll
-  for (int m = 0; m < 64; ++m) s[m] = kap * cabs2(p[m]);
-  if (psf_row_or_null) {
-    const int e = lane & 1;
-#pragma unroll
-    for (int m = 0; m < 64; ++m) psf_row_or_null[2 * m + e] = s[m];
-  }
-  float keep[32], send[32], other[32];
-  op2_rows_fold(s, keep, send, lane);
-  xput(send, reinterpret_cast<float*>(T), lane);
-  sync();
-  xget(reinterpret_cast<const float*>(T), lane, other);
-  sync();
-  op2_rows_finish(keep, other, T, lane);
-  sync();
-  op2_cols(T, Taux, lane, X);
-  sync();
-  if (lane < 128) x64 = op2_unpack(Taux, T, lane);
-  sync();
-  op2_collect(T, lane, X);
-}
-
+// The forward unit transforms through a half-size buffer of floats (real
+// parts, then imaginary parts, for both transposes): 34.8 KB of LDS per
+// workgroup instead of 68.6 KB, so that registers, not LDS, set how many
+// workgroups a CU holds.
 template <bool WANT_PSF>
 __device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C, int J,
                                                 const int* __restrict__ active,
@@ -81,25 +57,62 @@ __device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C,
                                                 const float* __restrict__ phi,
                                                 float* __restrict__ psf,
                                                 float2* __restrict__ S) {
-  __shared__ float2 T[LDS_MAIN];
+  __shared__ float Th[LDS_HALF];
   __shared__ float2 Taux[LDS_AUX];
   if (active && !active[u / (J * C)]) return;
   const int lane = threadIdx.x;
   const int c = (u / J) % C;
+  float2 p[64];
   {
     float2 z[32];
     __builtin_amdgcn_s_setprio(2);
     build_pupil(Ab + (size_t)c * kBP, phi + (size_t)u * kBP, lane, z);
     __builtin_amdgcn_s_setprio(0);
-    op1_cols(z, T, lane);
+    fft32<+1>(z);
+    op1_cols_put<0>(z, Th, lane);
+    sync();
+    op1_rows_get<0>(Th, lane, p);
+    sync();
+    op1_cols_put<1>(z, Th, lane);
   }
   sync();
-  float2 p[64];
-  op1_rows(T, lane, p);
+  op1_rows_get<1>(Th, lane, p);
+  op1_rows_fft(p, lane);
+  float s[64];
+  const float kap = ct.kappa[c];
+#pragma unroll
+  for (int m = 0; m < 64; ++m) s[m] = kap * cabs2(p[m]);
+  if (WANT_PSF) {
+    float* row = psf + (size_t)u * N * N + (lane >> 1) * N;
+    const int e = lane & 1;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) row[2 * m + e] = s[m];
+  }
+  float2 v[32];
+  {
+    float keep[32], send[32], other[32];
+    op2_rows_fold(s, keep, send, lane);
+    sync();
+    xput(send, Th, lane);
+    sync();
+    xget(Th, lane, other);
+    op2_rows_values(keep, other, lane, v);
+  }
+  sync();
+  op2_rows_put<0>(v, Th, lane);
+  sync();
+  float ax[32], bx[32];
+  op2_cols_half_x(Th, lane, ax, bx);
+  sync();
+  op2_rows_put<1>(v, Th, lane);
   sync();
   float2 X[32], x64;
-  float* row = WANT_PSF ? psf + (size_t)u * N * N + (lane >> 1) * N : nullptr;
-  psf_to_otf(p, ct.kappa[c], row, T, Taux, lane, X, x64);
+  op2_cols_half_y(Th, Taux, lane, ax, bx, X);
+  sync();
+  float2* T2 = reinterpret_cast<float2*>(Th);
+  if (lane < 128) x64 = op2_unpack(Taux, T2, lane);
+  sync();
+  op2_collect(T2, lane, X);
   float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
   for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];
@@ -107,7 +120,7 @@ __device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C,
 }
 
 template <bool WANT_PSF>
-__global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, ChanTab ct, int C,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_forward128(int units, int xcd, ChanTab ct, int C,
                                                         int J, const int* __restrict__ active,
                                                         const float* __restrict__ Ab,
                                                         const float* __restrict__ phi,
@@ -120,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_forward128(int units, int xcd, Cha
 }
 
 // Every unit of every field of a group (XCD order over the group's units).
-__global__ __launch_bounds__(kThreads) void k_forward128_group(GroupArgs ga, int xcd) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_forward128_group(GroupArgs ga, int xcd) {
   const int per = (ga.total + kXcds - 1) / kXcds;
   const int g = xcd ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
   if (g >= ga.total) return;

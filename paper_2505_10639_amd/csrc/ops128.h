@@ -39,6 +39,7 @@ constexpr int U1 = 132;         // [q][ky]      op1 column pass -> rows
 constexpr int U2 = 66;          // [y][kx]      rows -> columns (op2, op4)
 constexpr int U3 = 65;          // [y][kx]      op3 columns -> rows
 constexpr int LDS_MAIN = 128 * U2;     // 8448 float2 (>= 64*U1, 128*U3)
+constexpr int LDS_HALF = 128 * U2;     // 8448 floats: the forward's half-size buffer
 constexpr int LDS_AUX = 128;
 
 // Residue class of a lane in the column-quad layout: its wave, uniform
@@ -127,7 +128,25 @@ MFBD_HDI void op1_cols(float2 (&z)[32], float2* T, int lane) {
   });
 }
 
-// Row pass: lane (y, e) -> p(y, 2m + e), m in [0,64).
+// Row pass: lane (y, e) -> p(y, 2m + e), m in [0,64), from the row's band
+// values p[q] = column pass output at (y, q).
+MFBD_HDI void op1_rows_fft(float2 (&p)[64], int lane) {
+  const int e = lane & 1;
+  if (e) {
+    static_for<0, 64>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      p[q] = twmul<+1, 128, 32 + q>(p[q]);
+    });
+  }
+  fft64<+1>(p);
+  static_for<0, 64>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    if constexpr (m & 1) p[m] = cneg(p[m]);
+  });
+}
+
+// (The same steps written out for the full buffer: the 128x128 adjoint's
+// register allocation depends on this form.)
 MFBD_HDI void op1_rows(const float2* T, int lane, float2 (&p)[64]) {
   const int y = lane >> 1, e = lane & 1;
   static_for<0, 64>([&](auto Q) {
@@ -144,6 +163,28 @@ MFBD_HDI void op1_rows(const float2* T, int lane, float2 (&p)[64]) {
   static_for<0, 64>([&](auto M) {
     constexpr int m = decltype(M)::value;
     if constexpr (m & 1) p[m] = cneg(p[m]);
+  });
+}
+
+// Half-buffer form of the op 1 transpose (the forward kernel): the column
+// results go through a buffer of floats, real parts (P = 0), then
+// imaginary parts (P = 1); the caller has run fft32<+1> on z, and puts
+// after the buffer's previous readers are done, gets after a barrier.
+template <int P>
+MFBD_HDI void op1_cols_put(const float2 (&z)[32], float* Tf, int lane) {
+  const int q = lane >> 2, r = lane & 3;
+  static_for<0, 32>([&](auto M) {
+    constexpr int m = decltype(M)::value;
+    Tf[q * U1 + 4 * m + r] = P ? z[m].y : z[m].x;
+  });
+}
+template <int P>
+MFBD_HDI void op1_rows_get(const float* Tf, int lane, float2 (&p)[64]) {
+  const int y = lane >> 1;
+  static_for<0, 64>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    if (P) p[q].y = Tf[q * U1 + y];
+    else p[q].x = Tf[q * U1 + y];
   });
 }
 
@@ -182,9 +223,11 @@ MFBD_HDI void op2_rows_fold(const float (&s)[64], float (&keep)[32], float (&sen
   });
 }
 
-MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32], float2* T,
-                              int lane) {
-  const int y = lane >> 1, e = lane & 1;
+// The row's half spectrum as the lane's 32 values: v[kp] = Sr(y, 2 kp + e)
+// (lane e = 0, kp = 0: the packed (Sr0, Sr64)).
+MFBD_HDI void op2_rows_values(const float (&keep)[32], const float (&other)[32], int lane,
+                              float2 (&v)[32]) {
+  const int e = lane & 1;
   float2 w[32];
   static_for<0, 32>([&](auto I) {
     constexpr int n = decltype(I)::value;
@@ -199,14 +242,14 @@ MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32],
   fft32<-1>(w);   // w[k'] = Z[2k' + e]
   // Sr[k] = (Z[k] + conj Z[64-k])/2 + W128^{-k} (Z[k] - conj Z[64-k])/(2i), k = e mod 2
   if (e == 0) {
-    T[y * U2 + 0] = make_float2(w[0].x + w[0].y, w[0].x - w[0].y);    // (Sr0, Sr64)
+    v[0] = make_float2(w[0].x + w[0].y, w[0].x - w[0].y);    // (Sr0, Sr64)
     static_for<1, 32>([&](auto K) {
       constexpr int kp = decltype(K)::value;      // k = 2 kp
       float2 a = w[kp], c = cconj(w[32 - kp]);
       float2 se = cscale(cadd(a, c), 0.5f);
       float2 d = csub(a, c);
       float2 so = make_float2(0.5f * d.y, -0.5f * d.x);
-      T[y * U2 + 2 * kp] = cadd(se, twmul<-1, 128, 2 * kp>(so));
+      v[kp] = cadd(se, twmul<-1, 128, 2 * kp>(so));
     });
   } else {
     static_for<0, 32>([&](auto K) {
@@ -215,8 +258,79 @@ MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32],
       float2 se = cscale(cadd(a, c), 0.5f);
       float2 d = csub(a, c);
       float2 so = make_float2(0.5f * d.y, -0.5f * d.x);
-      T[y * U2 + 2 * kp + 1] = cadd(se, twmul<-1, 128, 2 * kp + 1>(so));
+      v[kp] = cadd(se, twmul<-1, 128, 2 * kp + 1>(so));
     });
+  }
+}
+
+MFBD_HDI void op2_rows_finish(const float (&keep)[32], const float (&other)[32], float2* T,
+                              int lane) {
+  const int y = lane >> 1, e = lane & 1;
+  float2 v[32];
+  op2_rows_values(keep, other, lane, v);
+  static_for<0, 32>([&](auto K) {
+    constexpr int kp = decltype(K)::value;
+    T[y * U2 + 2 * kp + e] = v[kp];
+  });
+}
+
+// Half-buffer form of the op 2 transpose: real parts (P = 0), then
+// imaginary parts (P = 1), of the row values; the column pass folds each
+// part as it arrives (op2_cols_half_x, then op2_cols_half_y, which finishes
+// the column transform).
+template <int P>
+MFBD_HDI void op2_rows_put(const float2 (&v)[32], float* Tf, int lane) {
+  const int y = lane >> 1, e = lane & 1;
+  static_for<0, 32>([&](auto K) {
+    constexpr int kp = decltype(K)::value;
+    Tf[y * U2 + 2 * kp + e] = P ? v[kp].y : v[kp].x;
+  });
+}
+
+// Real parts of the radix-4 fold's a = x0 + (-1)^r x2 and b = x1 + (-1)^r x3.
+MFBD_HDI void op2_cols_half_x(const float* Tf, int lane, float (&ax)[32], float (&bx)[32]) {
+  const int r = wave_of(lane), q = lane & 63;
+  const float s = (r & 1) ? -1.0f : 1.0f;
+  static_for<0, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    ax[n] = Tf[n * U2 + q] + s * Tf[(n + 64) * U2 + q];
+    bx[n] = Tf[(n + 32) * U2 + q] + s * Tf[(n + 96) * U2 + q];
+  });
+}
+
+// Imaginary parts, the fold z = a + (-i)^r b, its twiddle and the 32-point
+// FFT: X[m] = S(4m + r, q); column 0 left in Taux as in op2_cols.
+MFBD_HDI void op2_cols_half_y(const float* Tf, float2* Taux, int lane, const float (&ax)[32],
+                              const float (&bx)[32], float2 (&X)[32]) {
+  const int r = wave_of(lane), q = lane & 63;
+  const float s = (r & 1) ? -1.0f : 1.0f;
+  const float sg = (r & 2) ? -1.0f : 1.0f;
+  auto ab_y = [&](int n, float& ay, float& by) {
+    ay = Tf[n * U2 + q] + s * Tf[(n + 64) * U2 + q];
+    by = Tf[(n + 32) * U2 + q] + s * Tf[(n + 96) * U2 + q];
+  };
+  if (r & 1) {         // (-i)^r b = sg (b.y, -b.x)
+    static_for<0, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      float ay, by;
+      ab_y(n, ay, by);
+      X[n] = make_float2(ax[n] + sg * by, ay - sg * bx[n]);
+    });
+  } else {             // (-i)^r b = sg b
+    static_for<0, 32>([&](auto I) {
+      constexpr int n = decltype(I)::value;
+      float ay, by;
+      ab_y(n, ay, by);
+      X[n] = make_float2(ax[n] + sg * bx[n], ay + sg * by);
+    });
+  }
+  static_for<1, 32>([&](auto I) {
+    constexpr int n = decltype(I)::value;
+    X[n] = twmul_r<-1, n>(X[n], r);
+  });
+  fft32<-1>(X);
+  if (q == 0) {
+    static_for<0, 32>([&](auto I) { Taux[4 * decltype(I)::value + r] = X[decltype(I)::value]; });
   }
 }
 

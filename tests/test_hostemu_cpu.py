@@ -173,6 +173,27 @@ def test_n128_real_forward(emu):
     assert np.abs(half - ref).max() <= 5e-7 * np.abs(ref).max()
 
 
+def test_n128_band_pupil_inverse_half_buffer(emu):
+    """The forward kernel's form at 128: both transposes through a half-size
+    buffer, real parts then imaginary parts."""
+    A = synth.pupil_mask(128)[32:96, 32:96].astype(np.float32)
+    ph = (0.2 * rng(16).standard_normal((64, 64))).astype(np.float32)
+    p = np.zeros((128, 128), np.complex64)
+    emu.emu128_pupil_ifft_half(ptr(A), ptr(ph), ptr(p.view(np.float32)))
+    P = np.zeros((128, 128), complex)
+    P[32:96, 32:96] = A * np.exp(2j * np.pi * ph.astype(np.float64))
+    ref = oracle.idft2_un(P)
+    assert np.abs(p - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
+def test_n128_real_forward_half_buffer(emu):
+    img = rng(17).standard_normal((128, 128)).astype(np.float32)
+    half = np.zeros((128, 65), np.complex64)
+    emu.emu128_r2c_half(ptr(img), ptr(half.view(np.float32)))
+    ref = oracle.dft2(img)[:, :65]
+    assert np.abs(half - ref).max() <= 5e-7 * np.abs(ref).max()
+
+
 def test_n128_hermitian_inverse(emu):
     H = oracle.dft2(rng(13).standard_normal((128, 128)))
     half = H[:, :65].astype(np.complex64)
