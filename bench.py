@@ -73,10 +73,10 @@ COUNTED_TRAFFIC = {
                       "by_value": {0: (94921217, 403049941), 1: (94920028, 398984793)}},
     ("object", 64): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
                      "by_value": {1: (729207024, 32782492)}},
-    ("adjoint", 128): {"sources_sha1": "796bb8104eb1", "knob": "xcd_adjoint",
-                       "by_value": {1: (12001317328, 1511522304), 0: (13412394412, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "796bb8104eb1", "knob": "xcd_forward",
-                       "by_value": {0: (1528739883, 6320632672), 1: (1574018260, 6156851616)}},
+    ("adjoint", 128): {"sources_sha1": "9bfd95aacae8", "knob": "xcd_adjoint",
+                       "by_value": {1: (12001064036, 1511522304), 0: (13418923772, 1511522304)}},
+    ("forward", 128): {"sources_sha1": "9bfd95aacae8", "knob": "xcd_forward",
+                       "by_value": {0: (3230831499, 8795109502), 1: (3243827559, 8713346863)}},
     ("object", 128): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
                       "by_value": {1: (10901716579, 257958892)}},
 }
