@@ -67,17 +67,17 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "bb116f9343cf", "knob": "xcd_adjoint",
+    ("adjoint", 64): {"sources_sha1": "7fff06369e6f", "knob": "xcd_adjoint",
                       "by_value": {1: (895416936, 94470144), 0: (1094435590, 94470144)}},
-    ("forward", 64): {"sources_sha1": "bb116f9343cf", "knob": "xcd_forward",
+    ("forward", 64): {"sources_sha1": "7fff06369e6f", "knob": "xcd_forward",
                       "by_value": {0: (94921217, 403049941), 1: (94920028, 398984793)}},
-    ("object", 64): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
+    ("object", 64): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
                      "by_value": {1: (729207024, 32782492)}},
-    ("adjoint", 128): {"sources_sha1": "9bfd95aacae8", "knob": "xcd_adjoint",
+    ("adjoint", 128): {"sources_sha1": "b8ed2e330bfb", "knob": "xcd_adjoint",
                        "by_value": {1: (12001064036, 1511522304), 0: (13418923772, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "9bfd95aacae8", "knob": "xcd_forward",
+    ("forward", 128): {"sources_sha1": "b8ed2e330bfb", "knob": "xcd_forward",
                        "by_value": {0: (3230831499, 8795109502), 1: (3243827559, 8713346863)}},
-    ("object", 128): {"sources_sha1": "547896625dee", "knob": "object_pairs_per_thread",
+    ("object", 128): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
                       "by_value": {1: (10901716579, 257958892)}},
 }
 
@@ -198,7 +198,8 @@ def time_steps(plan, D, alpha, gamma, steps, warmup, tune=True, reps=10, schedul
     if schedule:
         s = dict(plan.tuning(), **schedule)
         plan.set_tuning(s["xcd_forward"], s["xcd_adjoint"], s["object_pairs_per_thread"],
-                        s["grad_waves"], s["grad_splits"], s["grad_row_tiles"])
+                        s["grad_waves"], s["grad_splits"], s["grad_row_tiles"],
+                        s["phase_col_tiles"], s["phase_waves"])
     elif tune:
         plan.autotune(alpha, D, gamma, None, reps=3)
 

@@ -442,8 +442,19 @@ typedef struct {
                                    serving fewer rows), 2 with 8 waves; 0 on
                                    input is 4 or 2 (get_tuning reports the
                                    count in use)                              */
+  int phase_col_tiles;          /* phase contraction (Eq. wavefront): 16-column
+                                   tiles of (patch, frame) columns per
+                                   workgroup, whose coefficients it stages in
+                                   LDS, each basis part read serving them all */
+  int phase_waves;              /* and its waves: 8 x 8, 4 x 8 or 8 x 16
+                                   (tiles x waves) while the staged
+                                   coefficients fit 128 KB of LDS; 0, 0 on
+                                   input picks 8 x 8 where it fits, else 4 x 4
+                                   or 2 x 4 (get_tuning reports the shape in
+                                   use)                                       */
 } momfbd_tuning;
-/* Errors: EINVAL (NULL or a value out of range). */
+/* Errors: EINVAL (NULL, a value out of range, or a phase shape whose
+ * staged coefficients do not fit). */
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
 int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
 /* Choose the schedules by timing: one knob at a time, every candidate value
@@ -531,7 +542,8 @@ int momfbd_group_lbfgs_rounds(momfbd_group group, int rounds, void* stream);
 
 /* Launch schedules of a group (the fields of momfbd_tuning that apply:
  * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4, 3 or 2; grad_waves
- * must be 4).  The autotuner times momfbd_group_loss_grad over `reps`
+ * must be 4; the phase fields are ignored: a group's phase blocks are 2
+ * tiles x 4 waves).  The autotuner times momfbd_group_loss_grad over `reps`
  * evaluations per candidate with the plan autotuner's method and keeps the
  * fastest schedule.  Errors: EINVAL, EDEVICE. */
 int momfbd_group_set_tuning(momfbd_group group, const momfbd_tuning* tuning);

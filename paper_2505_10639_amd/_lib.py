@@ -48,7 +48,8 @@ class momfbd_filter(ctypes.Structure):
 class momfbd_tuning(ctypes.Structure):
     _fields_ = [("xcd_forward", ctypes.c_int), ("xcd_adjoint", ctypes.c_int),
                 ("object_pairs_per_thread", ctypes.c_int), ("grad_waves", ctypes.c_int),
-                ("grad_splits", ctypes.c_int), ("grad_row_tiles", ctypes.c_int)]
+                ("grad_splits", ctypes.c_int), ("grad_row_tiles", ctypes.c_int),
+                ("phase_col_tiles", ctypes.c_int), ("phase_waves", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -326,9 +327,9 @@ def momfbd_power_spectrum(image, window=None, nbins=None, stream=None):
 
 
 def momfbd_plan_set_tuning(plan, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves,
-                           grad_splits=0, grad_row_tiles=0):
+                           grad_splits=0, grad_row_tiles=0, phase_col_tiles=0, phase_waves=0):
     t = momfbd_tuning(xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves, grad_splits,
-                      grad_row_tiles)
+                      grad_row_tiles, phase_col_tiles, phase_waves)
     _check(lib().momfbd_plan_set_tuning(plan, ctypes.byref(t)), "momfbd_plan_set_tuning")
 
 

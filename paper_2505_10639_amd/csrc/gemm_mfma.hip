@@ -125,10 +125,12 @@ hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float*
   return hipGetLastError();
 }
 
-// Phase blocks: 128 columns and 8 waves when the staged coefficients fit
-// 128 KB of LDS, else 64 columns (4 waves) within 64 KB, else 32.  Every
-// basis part read serves all the block's columns, so the widest block that
-// fits reads the basis least often.
+// Phase blocks.  Automatic shape: 128 columns and 8 waves when the staged
+// coefficients fit 128 KB of LDS, else 64 columns (4 waves) within 64 KB,
+// else 32.  Every basis part read serves all the block's columns, so the
+// widest block that fits reads the basis least often.  A plan may select
+// 64 columns with 8 waves (two blocks per CU where their LDS allows) or
+// 128 columns with 16 waves (more waves issuing matrix-core work per CU).
 template <int CT, int W>
 hipError_t launch_phase_ct(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                            const float* thetat, float* phi, hipStream_t s) {
@@ -142,12 +144,35 @@ hipError_t launch_phase_ct(const Dims& d, const float* alpha, const uint4* ZsT, 
   return hipGetLastError();
 }
 
+bool phase_shape_fits(int ct, int waves, int Mq) {
+  const bool listed = (ct == 8 && waves == 8) || (ct == 4 && waves == 8) || (ct == 8 && waves == 16);
+  return listed && contract::phase_lds_bytes(ct, Mq) <= 128 * 1024;
+}
+
+void phase_shape_of(const Dims& d, int Mq, int* ct, int* waves) {
+  if (d.phase_ct > 0 && phase_shape_fits(d.phase_ct, d.phase_waves, Mq)) {
+    *ct = d.phase_ct;
+    *waves = d.phase_waves;
+  } else if (contract::phase_lds_bytes(8, Mq) <= 128 * 1024) {
+    *ct = 8;
+    *waves = 8;
+  } else if (contract::phase_lds_bytes(4, Mq) <= 64 * 1024) {
+    *ct = 4;
+    *waves = 4;
+  } else {
+    *ct = 2;
+    *waves = 4;
+  }
+}
+
 hipError_t launch_phase(const Dims& d, const float* alpha, const uint4* ZsT, int Mq,
                         const float* thetat, float* phi, hipStream_t s) {
-  if (contract::phase_lds_bytes(8, Mq) <= 128 * 1024)
-    return launch_phase_ct<8, 8>(d, alpha, ZsT, Mq, thetat, phi, s);
-  if (contract::phase_lds_bytes(4, Mq) <= 64 * 1024)
-    return launch_phase_ct<4, 4>(d, alpha, ZsT, Mq, thetat, phi, s);
+  int ct = 0, w = 0;
+  phase_shape_of(d, Mq, &ct, &w);
+  if (ct == 8 && w == 16) return launch_phase_ct<8, 16>(d, alpha, ZsT, Mq, thetat, phi, s);
+  if (ct == 8) return launch_phase_ct<8, 8>(d, alpha, ZsT, Mq, thetat, phi, s);
+  if (ct == 4 && w == 8) return launch_phase_ct<4, 8>(d, alpha, ZsT, Mq, thetat, phi, s);
+  if (ct == 4) return launch_phase_ct<4, 4>(d, alpha, ZsT, Mq, thetat, phi, s);
   return launch_phase_ct<2, 4>(d, alpha, ZsT, Mq, thetat, phi, s);
 }
 

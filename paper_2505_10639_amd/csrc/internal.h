@@ -29,6 +29,9 @@ struct Dims {
   // its row tiles per block (0: 4 with 4 waves; 3 is the other 4-wave choice;
   // 8 waves always take 2)
   int xcd_fwd = 0, xcd_adj = 1, obj_ppt = 1, grad_waves = 4, grad_splits = 0, grad_rt = 0;
+  // the phase contraction's block: 16-column tiles and waves per workgroup
+  // (0, 0: the widest block whose staged coefficients fit; phase_shape_of)
+  int phase_ct = 0, phase_waves = 0;
   // distinct modal bases on the band: 1 when every channel's band-sampled
   // basis is the same (the contractions then run once for all channels),
   // else C; 0 is read as C
@@ -175,6 +178,10 @@ constexpr int kMaxGradSplits = 8;
 int grad_splits_auto(const Dims& d);
 int grad_splits_of(const Dims& d);
 int grad_row_tiles_of(const Dims& d);
+// The phase contraction's block in use (column tiles, waves), and whether a
+// selectable one (8 x 8, 4 x 8 or 8 x 16) fits the LDS for Mq staged modes.
+void phase_shape_of(const Dims& d, int Mq, int* ct, int* waves);
+bool phase_shape_fits(int ct, int waves, int Mq);
 
 size_t workspace_bytes(const Dims& d);
 Workspace carve_workspace(const Dims& d, void* base);

@@ -406,6 +406,11 @@ static bool tuning_ok(const momfbd_tuning* t) {
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   if (!plan || !tuning_ok(t)) return MOMFBD_EINVAL;
+  const bool phase_auto = t->phase_col_tiles == 0 && t->phase_waves == 0;
+  if (!phase_auto && !phase_shape_fits(t->phase_col_tiles, t->phase_waves, plan->Mq))
+    return MOMFBD_EINVAL;
+  plan->d.phase_ct = phase_auto ? 0 : t->phase_col_tiles;
+  plan->d.phase_waves = phase_auto ? 0 : t->phase_waves;
   plan->d.xcd_fwd = t->xcd_forward;
   plan->d.xcd_adj = t->xcd_adjoint;
   plan->d.obj_ppt = t->object_pairs_per_thread;
@@ -423,6 +428,7 @@ int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* t) {
   t->grad_waves = plan->d.grad_waves;
   t->grad_splits = grad_splits_of(plan->d);
   t->grad_row_tiles = grad_row_tiles_of(plan->d);
+  phase_shape_of(plan->d, plan->Mq, &t->phase_col_tiles, &t->phase_waves);
   return MOMFBD_OK;
 }
 
@@ -775,7 +781,8 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
                               s);
       case 1: return launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
       case 2: return launch_object(plan->d, plan->ct, la, nullptr, w.S, w.O, w.loss_pk, loss, s);
-      default: return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
+      case 3: return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
+      default: return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
     }
   };
   auto timed = [&](int knob, float* ms) -> int {
@@ -801,10 +808,13 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // is the next knob, starting from the automatic one for the chosen shape,
   // the others following in increasing order.  After the last knob, one
   // whole evaluation under the chosen schedules leaves the loss and
-  // gradient outputs of that schedule.  Knobs 0-4 time the adjoint, the
-  // forward, the object kernel and (3, 4) the gradient contraction.
+  // gradient outputs of that schedule.  Knobs 0-5 time the adjoint, the
+  // forward, the object kernel, (3, 4) the gradient contraction and (5) the
+  // phase contraction, whose candidates are its automatic block and the
+  // selectable blocks (4 x 8, 8 x 16 tiles x waves) that fit.
   constexpr int kRounds = 3;
   static const int kShapes[4][2] = {{4, 0}, {4, 3}, {4, 2}, {8, 0}};
+  static const int kPhaseShapes[3][2] = {{0, 0}, {4, 8}, {8, 16}};
   auto set_knob = [&](int k, int v) {
     switch (k) {
       case 0: plan->d.xcd_adj = v; break;
@@ -815,12 +825,18 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
         plan->d.grad_rt = kShapes[v][1];
         plan->d.grad_splits = 0;
         break;
-      default: plan->d.grad_splits = v; break;
+      case 4: plan->d.grad_splits = v; break;
+      default:
+        plan->d.phase_ct = kPhaseShapes[v][0];
+        plan->d.phase_waves = kPhaseShapes[v][1];
+        break;
     }
   };
   const Dims keep_d = plan->d;
-  std::vector<int> values[5] = {{1, 0}, {0, 1}, {1, 2, 4}, {0, 1, 2, 3}, {}};
-  for (int k = 0; k < 5 && st == MOMFBD_OK; ++k) {
+  std::vector<int> values[6] = {{1, 0}, {0, 1}, {1, 2, 4}, {0, 1, 2, 3}, {}, {0}};
+  for (int v = 1; v < 3; ++v)
+    if (phase_shape_fits(kPhaseShapes[v][0], kPhaseShapes[v][1], plan->Mq)) values[5].push_back(v);
+  for (int k = 0; k < 6 && st == MOMFBD_OK; ++k) {
     if (k == 4) {
       plan->d.grad_splits = 0;
       const int a = grad_splits_auto(plan->d);
@@ -833,7 +849,7 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       for (size_t i = 0; i < values[k].size(); ++i) {
         set_knob(k, values[k][i]);
         float ms = 0.f;
-        if ((st = timed(k < 3 ? k : 3, &ms))) break;
+        if ((st = timed(k < 3 ? k : k < 5 ? 3 : 4, &ms))) break;
         if (r == 0 || ms < fastest[i]) fastest[i] = ms;
       }
     }
@@ -1159,6 +1175,8 @@ int momfbd_group_get_tuning(momfbd_group g, momfbd_tuning* t) {
   t->grad_waves = 4;
   t->grad_splits = group_splits(g);
   t->grad_row_tiles = g->grad_rt;
+  t->phase_col_tiles = kPhaseCols / 16;
+  t->phase_waves = 4;
   return MOMFBD_OK;
 }
 

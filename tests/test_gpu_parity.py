@@ -511,7 +511,9 @@ def test_launch_schedules_and_autotune(dev, N):
     not the order of its sum, so they give the same gradient bit for bit at
     equal splits.  The split counts include ones that leave workgroups with
     different chunk counts (N = 96: 72 chunks of 32 pixels over 8 splits).
-    The autotuned plan still matches the oracle."""
+    The phase contraction's block shape changes which wave forms a value of
+    phi, not its sum: bit for bit as well.  The autotuned plan still
+    matches the oracle."""
     pr = synth.make_problem(70 + N, N=N, P=3, J=3, M=28, channels=((0, 0.0), (1, 1.0)),
                             d_over_r0=np.array([7.0, 11.0, 15.0]), border=N // 10)
     D_np = simulate_D(pr)
@@ -523,12 +525,15 @@ def test_launch_schedules_and_autotune(dev, N):
     # shared basis: 32 chunks at N = 64, 72 at N = 96, 128 at N = 128)
     auto = {64: 4, 96: 8, 128: 8}[N]
     assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
-                             "grad_waves": 4, "grad_splits": auto, "grad_row_tiles": 4}
+                             "grad_waves": 4, "grad_splits": auto, "grad_row_tiles": 4,
+                             "phase_col_tiles": 8, "phase_waves": 8}
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
     for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
                   (1, 0, 4, 8), (0, 1, 1, 4, 8), (0, 1, 1, 4, 1), (0, 1, 1, 4, 2),
                   (0, 1, 1, 8, 8), (0, 1, 1, 8, 1), (0, 1, 1, 4, 8, 3), (0, 1, 1, 4, 2, 3),
-                  (0, 1, 1, 4, auto, 2), (0, 1, 1, 4, 1, 2), (0, 1, 1, 8, auto)]:
+                  (0, 1, 1, 4, auto, 2), (0, 1, 1, 4, 1, 2), (0, 1, 1, 8, auto),
+                  (0, 1, 1, 4, auto, 0, 4, 8), (0, 1, 1, 4, auto, 0, 8, 16),
+                  (0, 1, 1, 4, auto, 0, 8, 8)]:
         print(f"[tuning] N={N} {knobs}", flush=True)
         plan.set_tuning(*knobs)
         l1, g1 = plan.loss_grad(a, D, pr.gamma)
@@ -558,6 +563,10 @@ def test_launch_schedules_and_autotune(dev, N):
         plan.set_tuning(0, 1, 1, 8, 0, 3)
     with pytest.raises(Exception):
         plan.set_tuning(0, 1, 1, 4, 0, 1)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 4, 0, 0, 4, 4)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 4, 0, 0, 8, 0)
     plan.close()
 
 
