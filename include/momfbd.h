@@ -379,6 +379,14 @@ int momfbd_cnn_load(momfbd_cnn net, const float* params, void* ws, size_t ws_byt
  * (channel 0 is read); B <= batch_max */
 int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B, int C,
                        float* alpha, void* ws, size_t ws_bytes, void* stream);
+/* The network's input for D (as momfbd_cnn_forward): x [B][N][N][J] float
+ * (device, frames as channels), each frame of channel 0 (IDFT(D) / N^2)
+ * divided by its mean, minus one, times ten, rounded to bfloat16 as the
+ * first layer reads it (the values returned as floats).  For checking the
+ * layers on exactly the values they read.  Errors: EINVAL, EWORKSPACE,
+ * EDEVICE. */
+int momfbd_cnn_input(momfbd_cnn net, const void* D, int B, int C, float* x, void* ws,
+                     size_t ws_bytes, void* stream);
 /* loss (one FP64, device) and grad [n_params] (device) for targets
  * [B][J][M] float (device); D as momfbd_cnn_forward */
 int momfbd_cnn_loss_grad(momfbd_cnn net, const float* params, const void* D, int C,

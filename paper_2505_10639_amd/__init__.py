@@ -13,7 +13,7 @@ from ._lib import (MomfbdError, LIB_PATH, momfbd_status_string, momfbd_plan_crea
                    momfbd_plan_set_tuning, momfbd_plan_get_tuning, momfbd_plan_autotune,
                    momfbd_cnn_create, momfbd_cnn_destroy,
                    momfbd_cnn_sizes, momfbd_cnn_init, momfbd_cnn_load, momfbd_cnn_forward,
-                   momfbd_cnn_loss_grad, momfbd_cnn_adam,
+                   momfbd_cnn_loss_grad, momfbd_cnn_adam, momfbd_cnn_input,
                    momfbd_smoothness_gamma,
                    momfbd_prepare_data, momfbd_forward, momfbd_loss_grad,
                    momfbd_object_estimate, momfbd_profile_start, momfbd_profile_repeat,
@@ -28,6 +28,7 @@ __all__ = [
     "momfbd_plan_get_tuning", "momfbd_plan_autotune",
     "momfbd_cnn_create", "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
     "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad", "momfbd_cnn_adam",
+    "momfbd_cnn_input",
     "WarmStartNet",
     "momfbd_prepare_data",
     "momfbd_forward", "momfbd_loss_grad", "momfbd_object_estimate", "momfbd_profile_start",

@@ -121,6 +121,7 @@ def lib():
         L.momfbd_cnn_load.argtypes = [_vp] * 3 + [z, _vp]
         L.momfbd_cnn_forward.argtypes = [_vp, _vp, _vp, i, i, _vp, _vp, z, _vp]
         L.momfbd_cnn_loss_grad.argtypes = [_vp, _vp, _vp, i, _vp, i, _vp, _vp, _vp, z, _vp]
+        L.momfbd_cnn_input.argtypes = [_vp, _vp, i, i, _vp, _vp, z, _vp]
         L.momfbd_cnn_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, i, f, f, f, f, _vp, z, _vp]
         L.momfbd_smoothness_gamma.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.momfbd_profile_start.argtypes = [_vp, i]
@@ -150,6 +151,7 @@ def lib():
                      "momfbd_object_filtered", "momfbd_mosaic", "momfbd_synthesize", "momfbd_cnn_create",
                      "momfbd_cnn_destroy", "momfbd_cnn_sizes", "momfbd_cnn_init",
                      "momfbd_cnn_load", "momfbd_cnn_forward", "momfbd_cnn_loss_grad",
+                     "momfbd_cnn_input",
                      "momfbd_cnn_adam", "momfbd_lbfgs_rounds", "momfbd_power_spectrum_workspace",
                      "momfbd_power_spectrum", "momfbd_plan_set_tuning", "momfbd_plan_get_tuning",
                      "momfbd_plan_autotune", "momfbd_loss_grad_noalloc",
@@ -388,6 +390,12 @@ def momfbd_cnn_forward(net, params, D, B, C, alpha, ws, stream=None):
     _check(lib().momfbd_cnn_forward(net, _ptr(params), _ptr(D), int(B), int(C), _ptr(alpha),
                                     _ptr(ws), _nbytes(ws), _stream(stream, params)),
            "momfbd_cnn_forward")
+
+
+def momfbd_cnn_input(net, D, B, C, x, ws, stream=None):
+    _check(lib().momfbd_cnn_input(net, _ptr(D), int(B), int(C), _ptr(x), _ptr(ws), _nbytes(ws),
+                                  _stream(stream, x)),
+           "momfbd_cnn_input")
 
 
 def momfbd_cnn_loss_grad(net, params, D, C, target, B, loss, grad, ws, stream=None):

@@ -235,8 +235,11 @@ __global__ __launch_bounds__(256) void k_colsum(int M, int N, const uint16_t* __
 
 // frames [B*J][npix] FP32 -> NHWC bfloat16 [B][npix][J]:
 // 10 (f / mean - 1) per frame; one block per frame
+// (WIDE: the rounded values as floats, for momfbd_cnn_input)
+template <bool WIDE = false>
 __global__ __launch_bounds__(256) void k_norm_frames(int J, int npix, const float* __restrict__ f,
-                                                     uint16_t* __restrict__ x) {
+                                                     uint16_t* __restrict__ x,
+                                                     float* __restrict__ xw = nullptr) {
   __shared__ float red[256];
   const int u = blockIdx.x, tid = threadIdx.x;
   const int b = u / J, j = u % J;
@@ -250,8 +253,11 @@ __global__ __launch_bounds__(256) void k_norm_frames(int J, int npix, const floa
     __syncthreads();
   }
   const float inv = (float)npix / red[0];
-  for (int i = tid; i < npix; i += 256)
-    x[((long)b * npix + i) * J + j] = f2bf(10.f * (fu[i] * inv - 1.f));
+  for (int i = tid; i < npix; i += 256) {
+    const uint16_t h = f2bf(10.f * (fu[i] * inv - 1.f));
+    if (WIDE) xw[((long)b * npix + i) * J + j] = bf2f(h);
+    else x[((long)b * npix + i) * J + j] = h;
+  }
 }
 
 constexpr int kMaxJM = 2048;
@@ -442,8 +448,8 @@ hipError_t run_forward(const momfbd_cnn_s* n, const float* params, const void* D
   hipError_t e = frames_from_spectra(n, B, C, D, ws, s);
   if (e != hipSuccess) return e;
   uint16_t* x0 = reinterpret_cast<uint16_t*>(ws + n->o_x0);
-  hipLaunchKernelGGL(k_norm_frames, dim3(B * n->J), dim3(256), 0, s, n->J, n->N * n->N,
-                     reinterpret_cast<const float*>(ws + n->o_frames), x0);
+  hipLaunchKernelGGL(k_norm_frames<false>, dim3(B * n->J), dim3(256), 0, s, n->J, n->N * n->N,
+                     reinterpret_cast<const float*>(ws + n->o_frames), x0, nullptr);
   const uint16_t* w16 = reinterpret_cast<const uint16_t*>(ws + n->o_w16);
   const uint16_t* h = x0;
   for (size_t l = 0; l < n->layers.size(); ++l) {
@@ -676,6 +682,21 @@ int momfbd_cnn_forward(momfbd_cnn net, const float* params, const void* D, int B
   const long n = (long)B * net->J * net->M;
   hipLaunchKernelGGL(k_scale_pred, dim3(blocks(n)), dim3(256), 0, s, n, net->M,
                      reinterpret_cast<const float*>(w + net->o_z), net->scale, alpha);
+  return status_of(hipGetLastError());
+}
+
+int momfbd_cnn_input(momfbd_cnn net, const void* D, int B, int C, float* x, void* ws,
+                     size_t ws_bytes, void* stream) {
+  int st = check_net(net, ws, ws_bytes, B);
+  if (st) return st;
+  if (!D || !x || C < 1) return MOMFBD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = static_cast<char*>(ws);
+  hipError_t e = frames_from_spectra(net, B, C, D, w, s);
+  if (e != hipSuccess) return MOMFBD_EDEVICE;
+  hipLaunchKernelGGL(k_norm_frames<true>, dim3(B * net->J), dim3(256), 0, s, net->J,
+                     net->N * net->N, reinterpret_cast<const float*>(w + net->o_frames), nullptr,
+                     x);
   return status_of(hipGetLastError());
 }
 

@@ -244,6 +244,46 @@ MFBD_HDI void fft32(float2 (&x)[32]) {
   static_for<0, 32>([&](auto I) { x[decltype(I)::value] = y[decltype(I)::value]; });
 }
 
+// Input factors of a transform whose input x[n] is c[n] W_L^{E0 + n} (a
+// phase ramp), passed as x[n] = twu(c[n]) with the factor f(n) left out.
+template <int DIR, int L, int E0>
+struct RampFactors {
+  static MFBD_HDI constexpr float f(int n) {
+    return float(detail::twfact(DIR, (((E0 + n) % L) + L) % L, L).f);
+  }
+};
+
+// fft32 of (f(0) x[0], f(1) x[1], ..., f(31) x[31]) for the compile-time
+// input factors SC::f, with f(0) = 1: the factors enter the FMAs of the
+// first-stage 8-point DFTs (relative to the first input of each) and of the
+// second stage, so they cost nothing.
+template <int DIR, class SC>
+MFBD_HDI void fft32s(float2 (&x)[32]) {
+  static_assert(SC::f(0) == 1.0f, "the first input factor must be 1");
+  static_for<0, 4>([&](auto N2) {
+    constexpr int n2 = decltype(N2)::value;
+    constexpr float s0 = SC::f(n2);
+    dft8s<DIR>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2], x[16 + n2], x[20 + n2], x[24 + n2],
+               x[28 + n2], SC::f(4 + n2) / s0, SC::f(8 + n2) / s0, SC::f(12 + n2) / s0,
+               SC::f(16 + n2) / s0, SC::f(20 + n2) / s0, SC::f(24 + n2) / s0,
+               SC::f(28 + n2) / s0);
+  });
+  // first-stage output k1 of column n2 carries the factor f(n2)
+  float2 y[32];
+  static_for<0, 8>([&](auto K1) {
+    constexpr int k1 = decltype(K1)::value;
+    float2 a0 = x[4 * k1 + 0], a1 = twu<DIR, 32, k1>(x[4 * k1 + 1]),
+           a2 = twu<DIR, 32, 2 * k1>(x[4 * k1 + 2]), a3 = twu<DIR, 32, 3 * k1>(x[4 * k1 + 3]);
+    dft4s<DIR>(a0, a1, a2, a3, twf<DIR, 32, k1>() * SC::f(1), twf<DIR, 32, 2 * k1>() * SC::f(2),
+               twf<DIR, 32, 3 * k1>() * SC::f(3));
+    y[k1 + 0] = a0;
+    y[k1 + 8] = a1;
+    y[k1 + 16] = a2;
+    y[k1 + 24] = a3;
+  });
+  static_for<0, 32>([&](auto I) { x[decltype(I)::value] = y[decltype(I)::value]; });
+}
+
 // 64-point DFT in natural order, 8 x 8 decomposition (n = 8 n1 + n2), the
 // twiddles W64^{n2 k1} in factored form in the second-stage 8-point DFTs.
 template <int DIR>

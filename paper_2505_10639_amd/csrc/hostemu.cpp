@@ -59,10 +59,10 @@ void r2c_half(Wave& w, const float* img, float2 (&X)[64][32], float2 (&x32)[64])
   static float2 v[64][32];
   float* Tf = reinterpret_cast<float*>(w.T);
   for (int l = 0; l < 64; ++l) {
-    float se[32], so[32];
+    float se[32], so[32];   // half the image (op2_rows_values' input)
     for (int n = 0; n < 32; ++n) {
-      se[n] = img[l * 64 + 2 * n];
-      so[n] = img[l * 64 + 2 * n + 1];
+      se[n] = 0.5f * img[l * 64 + 2 * n];
+      so[n] = 0.5f * img[l * 64 + 2 * n + 1];
     }
     op2_rows_values(se, so, v[l]);
   }
@@ -353,9 +353,12 @@ void pupil_to_p(WG& w, const float* A, const float* ph, float2 (&p)[L][64]) {
   for (int l = 0; l < L; ++l) n128::op1_rows(w.T, l, p[l]);
 }
 
+// (the row values are formed from half the image, as in the kernels)
 void r2c(WG& w, const float (&s)[L][64], float2 (&X)[L][32], float2 (&x64)[128]) {
-  static float keep[L][32], send[L][32], other[L][32];
-  for (int l = 0; l < L; ++l) n128::op2_rows_fold(s[l], keep[l], send[l], l);
+  static float keep[L][32], send[L][32], other[L][32], hs[L][64];
+  for (int l = 0; l < L; ++l)
+    for (int m = 0; m < 64; ++m) hs[l][m] = 0.5f * s[l][m];
+  for (int l = 0; l < L; ++l) n128::op2_rows_fold(hs[l], keep[l], send[l], l);
   float* Xf = reinterpret_cast<float*>(w.T);
   for (int l = 0; l < L; ++l) n128::xput(send[l], Xf, l);
   for (int l = 0; l < L; ++l) n128::xget(Xf, l, other[l]);
@@ -395,9 +398,11 @@ void pupil_to_p_half(WGH& w, const float* A, const float* ph, float2 (&p)[L][64]
 }
 
 void r2c_half(WGH& w, const float (&s)[L][64], float2 (&X)[L][32], float2 (&x64)[128]) {
-  static float keep[L][32], send[L][32], other[L][32], ax[L][32], bx[L][32];
+  static float keep[L][32], send[L][32], other[L][32], ax[L][32], bx[L][32], hs[L][64];
   static float2 v[L][32];
-  for (int l = 0; l < L; ++l) n128::op2_rows_fold(s[l], keep[l], send[l], l);
+  for (int l = 0; l < L; ++l)
+    for (int m = 0; m < 64; ++m) hs[l][m] = 0.5f * s[l][m];
+  for (int l = 0; l < L; ++l) n128::op2_rows_fold(hs[l], keep[l], send[l], l);
   for (int l = 0; l < L; ++l) n128::xput(send[l], w.Th, l);
   for (int l = 0; l < L; ++l) n128::xget(w.Th, l, other[l]);
   for (int l = 0; l < L; ++l) n128::op2_rows_values(keep[l], other[l], l, v[l]);

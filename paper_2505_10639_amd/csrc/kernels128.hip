@@ -78,15 +78,16 @@ __device__ __forceinline__ void forward128_unit(int u, const ChanTab& ct, int C,
   sync();
   op1_rows_get<1>(Th, lane, p);
   op1_rows_fft(p, lane);
+  // half the PSF row (op2_rows_values takes s / 2; the factor is exact)
   float s[64];
-  const float kap = ct.kappa[c];
+  const float kap_half = 0.5f * ct.kappa[c];
 #pragma unroll
-  for (int m = 0; m < 64; ++m) s[m] = kap * cabs2(p[m]);
+  for (int m = 0; m < 64; ++m) s[m] = kap_half * cabs2(p[m]);
   if (WANT_PSF) {
     float* row = psf + (size_t)u * N * N + (lane >> 1) * N;
     const int e = lane & 1;
 #pragma unroll
-    for (int m = 0; m < 64; ++m) row[2 * m + e] = s[m];
+    for (int m = 0; m < 64; ++m) row[2 * m + e] = 2.0f * s[m];
   }
   float2 v[32];
   {
@@ -303,8 +304,9 @@ __global__ __launch_bounds__(kThreads) void k_prepare128(int units, int C, int J
   }
   const float mean = red[0] * (1.0f / (N * N));
   const float* wr = apod + y * N;
+  // half the apodized row (op2_rows_values takes s / 2)
 #pragma unroll
-  for (int m = 0; m < 64; ++m) s[m] = wr[2 * m + e] * (s[m] - mean) + mean;
+  for (int m = 0; m < 64; ++m) s[m] = 0.5f * (wr[2 * m + e] * (s[m] - mean) + mean);
   float2 X[32], x64;
   {
     float keep[32], send[32], other[32];

@@ -100,19 +100,20 @@ __device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, 
   }
   wave_sync();
   op1_rows_get1(Tf, lane, pe, po);
-  const float kap = ct.kappa[c];
+  // half the PSF row (op2_rows_values takes s / 2; the factor is exact)
+  const float kap_half = 0.5f * ct.kappa[c];
   float se[32], so[32];
 #pragma unroll
   for (int n = 0; n < 32; ++n) {
-    se[n] = kap * cabs2(pe[n]);
-    so[n] = kap * cabs2(po[n]);
+    se[n] = kap_half * cabs2(pe[n]);
+    so[n] = kap_half * cabs2(po[n]);
   }
   if (WANT_PSF) {
     float* row = psf + (size_t)u * N * N + lane * N;
 #pragma unroll
     for (int n = 0; n < 32; ++n) {
-      row[2 * n] = se[n];
-      row[2 * n + 1] = so[n];
+      row[2 * n] = 2.0f * se[n];
+      row[2 * n + 1] = 2.0f * so[n];
     }
   }
   float2 v[32];

@@ -224,7 +224,9 @@ MFBD_HDI void op2_rows_fold(const float (&s)[64], float (&keep)[32], float (&sen
 }
 
 // The row's half spectrum as the lane's 32 values: v[kp] = Sr(y, 2 kp + e)
-// (lane e = 0, kp = 0: the packed (Sr0, Sr64)).
+// (lane e = 0, kp = 0: the packed (Sr0, Sr64)), from the folds of HALF the
+// image row (s / 2): then Sr[k] = (Z[k] + conj Z[64-k]) + W128^{-k} (Z[k] -
+// conj Z[64-k]) / i with no factor 1/2, the twiddle in factored form.
 MFBD_HDI void op2_rows_values(const float (&keep)[32], const float (&other)[32], int lane,
                               float2 (&v)[32]) {
   const int e = lane & 1;
@@ -240,25 +242,23 @@ MFBD_HDI void op2_rows_values(const float (&keep)[32], const float (&other)[32],
     });
   }
   fft32<-1>(w);   // w[k'] = Z[2k' + e]
-  // Sr[k] = (Z[k] + conj Z[64-k])/2 + W128^{-k} (Z[k] - conj Z[64-k])/(2i), k = e mod 2
+  // (a + c) + W128^{-k} (a - c) / i with a = Z[k], c = conj Z[64-k], k = e mod 2
+  auto val = [](auto K, float2 a, float2 c) {
+    constexpr int k = decltype(K)::value;
+    const float2 t = twu<-1, 128, k>(make_float2(a.y - c.y, c.x - a.x));
+    constexpr float f = twf<-1, 128, k>();
+    return make_float2((a.x + c.x) + f * t.x, (a.y + c.y) + f * t.y);
+  };
   if (e == 0) {
-    v[0] = make_float2(w[0].x + w[0].y, w[0].x - w[0].y);    // (Sr0, Sr64)
+    v[0] = make_float2(2.0f * (w[0].x + w[0].y), 2.0f * (w[0].x - w[0].y));    // (Sr0, Sr64)
     static_for<1, 32>([&](auto K) {
       constexpr int kp = decltype(K)::value;      // k = 2 kp
-      float2 a = w[kp], c = cconj(w[32 - kp]);
-      float2 se = cscale(cadd(a, c), 0.5f);
-      float2 d = csub(a, c);
-      float2 so = make_float2(0.5f * d.y, -0.5f * d.x);
-      v[kp] = cadd(se, twmul<-1, 128, 2 * kp>(so));
+      v[kp] = val(std::integral_constant<int, 2 * kp>{}, w[kp], cconj(w[32 - kp]));
     });
   } else {
     static_for<0, 32>([&](auto K) {
       constexpr int kp = decltype(K)::value;      // k = 2 kp + 1, partner 63 - 2kp
-      float2 a = w[kp], c = cconj(w[31 - kp]);
-      float2 se = cscale(cadd(a, c), 0.5f);
-      float2 d = csub(a, c);
-      float2 so = make_float2(0.5f * d.y, -0.5f * d.x);
-      v[kp] = cadd(se, twmul<-1, 128, 2 * kp + 1>(so));
+      v[kp] = val(std::integral_constant<int, 2 * kp + 1>{}, w[kp], cconj(w[31 - kp]));
     });
   }
 }
@@ -443,17 +443,19 @@ MFBD_HDI void op3_rows_compute(const float2* T, int lane, float (&keep)[32], flo
   // Z at k and 64 - k from X[k], X[64-k] (1 <= k <= 63)
   auto zpair = [&](auto K, float2 xa, float2 xb, float2& za, float2& zb) {
     constexpr int k = decltype(K)::value;
-    {
+    {   // s + i W128^k (xa - c), the twiddle in factored form
       const float2 c = cconj(xb);
       const float2 s = cadd(xa, c);
-      const float2 t = twmul<+1, 128, k>(csub(xa, c));
-      za = make_float2(s.x - t.y, s.y + t.x);
+      const float2 t = twu<+1, 128, k>(csub(xa, c));
+      constexpr float f = twf<+1, 128, k>();
+      za = make_float2(s.x - f * t.y, s.y + f * t.x);
     }
     {
       const float2 c = cconj(xa);
       const float2 s = cadd(xb, c);
-      const float2 t = twmul<+1, 128, 64 - k>(csub(xb, c));
-      zb = make_float2(s.x - t.y, s.y + t.x);
+      const float2 t = twu<+1, 128, 64 - k>(csub(xb, c));
+      constexpr float f = twf<+1, 128, 64 - k>();
+      zb = make_float2(s.x - f * t.y, s.y + f * t.x);
     }
   };
   auto wmix = [&](float2 za, float2 zb) {
@@ -534,16 +536,18 @@ MFBD_HDI void op4_rows_fft(float2 (&H)[64], float2 (&keep)[32], float2* X, int l
     constexpr int n2 = decltype(N2)::value;
     dft8<-1>(H[n2], H[8 + n2], H[16 + n2], H[24 + n2], H[32 + n2], H[40 + n2], H[48 + n2],
              H[56 + n2]);
-    static_for<1, 8>([&](auto K1) {
-      constexpr int k1 = decltype(K1)::value;
-      H[8 * k1 + n2] = twmul<-1, 64, n2 * k1>(H[8 * k1 + n2]);
-    });
   });
+  // second stage: the twiddles W64^{n2 k1} in factored form (as fft64)
   static_for<0, 8>([&](auto K1) {
-    constexpr int k1 = decltype(K1)::value;
-    float2 a0 = H[8 * k1 + 0], a1 = H[8 * k1 + 1], a2 = H[8 * k1 + 2], a3 = H[8 * k1 + 3];
-    float2 a4 = H[8 * k1 + 4], a5 = H[8 * k1 + 5], a6 = H[8 * k1 + 6], a7 = H[8 * k1 + 7];
-    dft8<-1>(a0, a1, a2, a3, a4, a5, a6, a7);
+    constexpr int k = decltype(K1)::value;
+    float2 a0 = H[8 * k + 0], a1 = twu<-1, 64, k>(H[8 * k + 1]),
+           a2 = twu<-1, 64, 2 * k>(H[8 * k + 2]), a3 = twu<-1, 64, 3 * k>(H[8 * k + 3]),
+           a4 = twu<-1, 64, 4 * k>(H[8 * k + 4]), a5 = twu<-1, 64, 5 * k>(H[8 * k + 5]),
+           a6 = twu<-1, 64, 6 * k>(H[8 * k + 6]), a7 = twu<-1, 64, 7 * k>(H[8 * k + 7]);
+    dft8s<-1>(a0, a1, a2, a3, a4, a5, a6, a7, twf<-1, 64, k>(), twf<-1, 64, 2 * k>(),
+              twf<-1, 64, 3 * k>(), twf<-1, 64, 4 * k>(), twf<-1, 64, 5 * k>(),
+              twf<-1, 64, 6 * k>(), twf<-1, 64, 7 * k>());
+    constexpr int k1 = k;
     const float2 lo[4] = {a0, a1, a2, a3}, hi[4] = {a4, a5, a6, a7};   // F[v], F[32 + v]
     static_for<0, 4>([&](auto J) {
       constexpr int j = decltype(J)::value, v = k1 + 8 * j;
@@ -556,15 +560,22 @@ MFBD_HDI void op4_rows_fft(float2 (&H)[64], float2 (&keep)[32], float2* X, int l
 MFBD_HDI void op4_rows_finish(const float2 (&keep)[32], const float2 (&other)[32], float2* T,
                               int lane) {
   const int y = lane >> 1, e = lane & 1;
+  // a + W128^-E b, the twiddle in factored form
+  auto comb = [](auto E, float2 a, float2 b) {
+    constexpr int E_ = decltype(E)::value;
+    const float2 t = twu<-1, 128, E_>(b);
+    constexpr float f = twf<-1, 128, E_>();
+    return make_float2(a.x + f * t.x, a.y + f * t.y);
+  };
   if (e == 0) {
     static_for<0, 32>([&](auto I) {
       constexpr int v = decltype(I)::value;       // keep = F_0[v], other = F_1[v]
-      T[y * U2 + v] = cadd(keep[v], twmul<-1, 128, 32 + v>(other[v]));
+      T[y * U2 + v] = comb(std::integral_constant<int, 32 + v>{}, keep[v], other[v]);
     });
   } else {
     static_for<0, 32>([&](auto I) {
       constexpr int v = decltype(I)::value;       // keep = F_1[32+v], other = F_0[32+v]
-      T[y * U2 + 32 + v] = cadd(other[v], twmul<-1, 128, 64 + v>(keep[v]));
+      T[y * U2 + 32 + v] = comb(std::integral_constant<int, 64 + v>{}, other[v], keep[v]);
     });
   }
 }

@@ -61,15 +61,19 @@ MFBD_HDI void op1_cols(float2 (&y)[32], float2* T, int lane) {
 }
 
 // Output: pe[m] = p(r, 2m), po[m] = p(r, 2m+1) for row r = lane.
+// The odd half's input is c[q] W64^{16+q}: the ramp enters fft32s as
+// factored twiddles (RampFactors).
+using Ramp16 = RampFactors<+1, 64, 16>;
+
 MFBD_HDI void op1_rows(const float2* T, int lane, float2 (&pe)[32], float2 (&po)[32]) {
   static_for<0, 32>([&](auto Q) {
     constexpr int q = decltype(Q)::value;
     float2 c = T[q * T1 + lane];
     pe[q] = c;
-    po[q] = twmul<+1, 64, 16 + q>(c);
+    po[q] = twu<+1, 64, 16 + q>(c);
   });
   fft32<+1>(pe);
-  fft32<+1>(po);
+  fft32s<+1, Ramp16>(po);
   static_for<0, 32>([&](auto M) {
     constexpr int m = decltype(M)::value;
     if constexpr (m & 1) {
@@ -171,10 +175,10 @@ MFBD_HDI void op1_rows_get1(const float* Tf, int lane, float2 (&pe)[32], float2 
   static_for<0, 32>([&](auto Q) {
     constexpr int q = decltype(Q)::value;
     pe[q].y = Tf[q * T1 + lane];
-    po[q] = twmul<+1, 64, 16 + q>(pe[q]);
+    po[q] = twu<+1, 64, 16 + q>(pe[q]);
   });
   fft32<+1>(pe);
-  fft32<+1>(po);
+  fft32s<+1, Ramp16>(po);
   static_for<0, 32>([&](auto M) {
     constexpr int m = decltype(M)::value;
     if constexpr (m & 1) {
@@ -184,20 +188,23 @@ MFBD_HDI void op1_rows_get1(const float* Tf, int lane, float2 (&pe)[32], float2 
   });
 }
 
-// the values op2_rows writes: v[k] for k in [0,32), v[0] packing columns 0 and 32
+// the values op2_rows writes for an image s, v[k] for k in [0,32) (v[0]
+// packing columns 0 and 32), from HALF the image: se[n] = s(r, 2n) / 2,
+// so[n] = s(r, 2n+1) / 2.  Then the even- and odd-sample spectra are a + c
+// and (a - c) / i (a = z[k], c = conj z[32-k]), with no factor 1/2, and
+// v[k] = (a + c) + W64^-k (a - c) / i takes the twiddle in factored form.
 MFBD_HDI void op2_rows_values(const float (&se)[32], const float (&so)[32], float2 (&v)[32]) {
   float2 z[32];
   static_for<0, 32>([&](auto I) { z[decltype(I)::value] = make_float2(se[decltype(I)::value],
                                                                      so[decltype(I)::value]); });
   fft32<-1>(z);
-  v[0] = make_float2(z[0].x + z[0].y, z[0].x - z[0].y);
+  v[0] = make_float2(2.0f * (z[0].x + z[0].y), 2.0f * (z[0].x - z[0].y));
   static_for<1, 32>([&](auto K) {
     constexpr int k = decltype(K)::value;
-    float2 a = z[k], c = cconj(z[32 - k]);
-    float2 se_k = cscale(cadd(a, c), 0.5f);
-    float2 d = csub(a, c);
-    float2 so_k = make_float2(0.5f * d.y, -0.5f * d.x);
-    v[k] = cadd(se_k, twmul<-1, 64, k>(so_k));
+    const float2 a = z[k], c = cconj(z[32 - k]);
+    const float2 e = twu<-1, 64, k>(make_float2(a.y - c.y, c.x - a.x));   // (a - c) / i, times u
+    constexpr float f = twf<-1, 64, k>();
+    v[k] = make_float2((a.x + c.x) + f * e.x, (a.y + c.y) + f * e.y);
   });
 }
 
@@ -279,10 +286,11 @@ MFBD_HDI void op3_rows(const float2* T, int lane, float (&ge)[32], float (&go)[3
   Z[0] = make_float2(Xr[0].x + Xr[0].y, Xr[0].x - Xr[0].y);
   static_for<1, 32>([&](auto K) {
     constexpr int k = decltype(K)::value;
-    float2 a = Xr[k], c = cconj(Xr[32 - k]);
-    float2 s = cadd(a, c);
-    float2 t = twmul<+1, 64, k>(csub(a, c));
-    Z[k] = make_float2(s.x - t.y, s.y + t.x);    // s + i t
+    const float2 a = Xr[k], c = cconj(Xr[32 - k]);
+    const float2 s = cadd(a, c);
+    const float2 t = twu<+1, 64, k>(csub(a, c));   // t f = W64^k (a - c)
+    constexpr float f = twf<+1, 64, k>();
+    Z[k] = make_float2(s.x - f * t.y, s.y + f * t.x);    // s + i W64^k (a - c)
   });
   fft32<+1>(Z);
   static_for<0, 32>([&](auto I) {
@@ -348,9 +356,10 @@ MFBD_HDI void op14_half(const float2* T, int lane, const float (&g)[32], float k
   static_for<0, 32>([&](auto Q) {
     constexpr int q = decltype(Q)::value;
     float2 c = T[q * T1 + lane];
-    A[q] = E ? twmul<+1, 64, 16 + q>(c) : c;
+    A[q] = E ? twu<+1, 64, 16 + q>(c) : c;
   });
-  fft32<+1>(A);
+  if constexpr (E) fft32s<+1, Ramp16>(A);
+  else fft32<+1>(A);
   static_for<0, 32>([&](auto M) {
     constexpr int m = decltype(M)::value;
     A[m] = cscale(A[m], kap2 * g[m]);
@@ -365,7 +374,9 @@ MFBD_HDI void op14_rows(const float2* T, int lane, const float (&ge)[32], const 
   op14_half<1>(T, lane, go, kap2, B);
   static_for<0, 32>([&](auto V) {
     constexpr int v = decltype(V)::value;
-    Gr[v] = cadd(Gr[v], twmul<-1, 64, 16 + v>(B[v]));
+    const float2 b = twu<-1, 64, 16 + v>(B[v]);
+    constexpr float f = twf<-1, 64, 16 + v>();
+    Gr[v] = make_float2(Gr[v].x + f * b.x, Gr[v].y + f * b.y);
   });
 }
 

@@ -80,6 +80,16 @@ class WarmStartNet:
                                     self.ws)
         return out
 
+    def input(self, D):
+        """The network's input x [B][N][N][J] for data spectra D (bfloat16
+        values as floats; momfbd_cnn_input)."""
+        B, C = D.shape[0], D.shape[1]
+        x = torch.empty((B, self.N, self.N, self.J), dtype=torch.float32, device=self.device)
+        for b0 in range(0, B, self.batch_max):
+            b1 = min(B, b0 + self.batch_max)
+            _lib.momfbd_cnn_input(self.handle, D[b0:b1], b1 - b0, C, x[b0:b1], self.ws)
+        return x
+
     def loss_grad(self, D, target):
         _lib.momfbd_cnn_loss_grad(self.handle, self.params, D, D.shape[1], target, D.shape[0],
                                   self.loss, self.grad, self.ws)
