@@ -67,18 +67,18 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "7fff06369e6f", "knob": "xcd_adjoint",
-                      "by_value": {1: (895416936, 94470144), 0: (1094435590, 94470144)}},
-    ("forward", 64): {"sources_sha1": "7fff06369e6f", "knob": "xcd_forward",
-                      "by_value": {0: (94921217, 403049941), 1: (94920028, 398984793)}},
+    ("adjoint", 64): {"sources_sha1": "07bc10acc653", "knob": "xcd_adjoint",
+                      "by_value": {1: (895469405, 94470144), 0: (1094480242, 94470144)}},
+    ("forward", 64): {"sources_sha1": "07bc10acc653", "knob": "xcd_forward",
+                      "by_value": {0: (94910090, 404845519), 1: (94911276, 400968493)}},
     ("object", 64): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
-                     "by_value": {1: (729207024, 32782492)}},
-    ("adjoint", 128): {"sources_sha1": "b8ed2e330bfb", "knob": "xcd_adjoint",
-                       "by_value": {1: (12001064036, 1511522304), 0: (13418923772, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "b8ed2e330bfb", "knob": "xcd_forward",
-                       "by_value": {0: (3230831499, 8795109502), 1: (3243827559, 8713346863)}},
+                     "by_value": {1: (729206980, 32782422)}},
+    ("adjoint", 128): {"sources_sha1": "1b51b605f66c", "knob": "xcd_adjoint",
+                       "by_value": {1: (11972387207, 1511522304), 0: (13316000157, 1511522304)}},
+    ("forward", 128): {"sources_sha1": "1b51b605f66c", "knob": "xcd_forward",
+                       "by_value": {0: (3215722139, 8836415903), 1: (3230446399, 8747885187)}},
     ("object", 128): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
-                      "by_value": {1: (10901716579, 257958892)}},
+                      "by_value": {1: (10901721952, 257958847)}},
 }
 
 
