@@ -39,34 +39,36 @@ MFBD_HDI int sl_index(int lane, int m) { return (2 * m + (lane & 1)) * HC + (lan
 MFBD_HDI int sl_index48(int lane) { return lane * HC + 48; }
 
 // ---------------------------------------------------------------- FFTs
-// 3-point DFT: X1 = a0 - (a1+a2)/2 + DIR i (sqrt 3 / 2)(a1 - a2), X2 the conjugate rotation.
+// 3-point DFT of (a0, s1 a1, s2 a2) for real constants s1, s2 (factors of
+// twiddles applied to a1, a2 as twu), every add an FMA:
+//   X0 = a0 + s1 p, X1,2 = a0 - (s1/2) p +- DIR i h s1 m,
+// with p = a1 + (s2/s1) a2, m = a1 - (s2/s1) a2.
 template <int DIR>
-MFBD_HDI void dft3(float2& a0, float2& a1, float2& a2) {
+MFBD_HDI void dft3s(float2& a0, float2& a1, float2& a2, float s1, float s2) {
   constexpr float h = 0.86602540378443864676f;   // sqrt(3)/2
-  const float2 s = cadd(a1, a2), d = csub(a1, a2);
-  const float2 t = make_float2(a0.x - 0.5f * s.x, a0.y - 0.5f * s.y);
-  const float2 u = make_float2(-DIR * h * d.y, DIR * h * d.x);
-  a0 = cadd(a0, s);
-  a1 = cadd(t, u);
-  a2 = csub(t, u);
+  const float r = s2 / s1, hs = 0.5f * s1, d = DIR * h * s1;
+  const float2 p = make_float2(a1.x + r * a2.x, a1.y + r * a2.y);
+  const float2 m = make_float2(a1.x - r * a2.x, a1.y - r * a2.y);
+  const float2 t = make_float2(a0.x - hs * p.x, a0.y - hs * p.y);
+  a0 = make_float2(a0.x + s1 * p.x, a0.y + s1 * p.y);
+  a1 = make_float2(t.x - d * m.y, t.y + d * m.x);
+  a2 = make_float2(t.x + d * m.y, t.y - d * m.x);
 }
 
-// 16-point DFT in natural order, 4 x 4 (n = 4 a + b, k = c + 4 d).
+// 16-point DFT in natural order, 4 x 4 (n = 4 a + b, k = c + 4 d), the
+// twiddles W16^{bc} in factored form in the second-stage 4-point DFTs.
 template <int DIR>
 MFBD_HDI void fft16(float2 (&x)[16]) {
   static_for<0, 4>([&](auto B) {
     constexpr int b = decltype(B)::value;
     dft4<DIR>(x[b], x[4 + b], x[8 + b], x[12 + b]);
-    static_for<1, 4>([&](auto Cc) {
-      constexpr int c = decltype(Cc)::value;
-      x[4 * c + b] = twmul<DIR, 16, b * c>(x[4 * c + b]);
-    });
   });
   float2 y[16];
   static_for<0, 4>([&](auto Cc) {
     constexpr int c = decltype(Cc)::value;
-    float2 a0 = x[4 * c], a1 = x[4 * c + 1], a2 = x[4 * c + 2], a3 = x[4 * c + 3];
-    dft4<DIR>(a0, a1, a2, a3);
+    float2 a0 = x[4 * c], a1 = twu<DIR, 16, c>(x[4 * c + 1]), a2 = twu<DIR, 16, 2 * c>(x[4 * c + 2]),
+           a3 = twu<DIR, 16, 3 * c>(x[4 * c + 3]);
+    dft4s<DIR>(a0, a1, a2, a3, twf<DIR, 16, c>(), twf<DIR, 16, 2 * c>(), twf<DIR, 16, 3 * c>());
     y[c] = a0;
     y[c + 4] = a1;
     y[c + 8] = a2;
@@ -77,7 +79,8 @@ MFBD_HDI void fft16(float2 (&x)[16]) {
 
 // 48-point DFT in natural order, 16 x 3:
 //   n = 3 n1 + n2, k = k1 + 16 k2;
-//   X[k1 + 16 k2] = sum_n2 W48^{n2 k1} W3^{n2 k2} sum_n1 x[3 n1 + n2] W16^{n1 k1}.
+//   X[k1 + 16 k2] = sum_n2 W48^{n2 k1} W3^{n2 k2} sum_n1 x[3 n1 + n2] W16^{n1 k1},
+// the twiddles W48^{n2 k1} in factored form in the 3-point DFTs.
 template <int DIR>
 MFBD_HDI void fft48(float2 (&x)[48]) {
   static_for<0, 3>([&](auto N2) {
@@ -87,14 +90,14 @@ MFBD_HDI void fft48(float2 (&x)[48]) {
     fft16<DIR>(t);
     static_for<0, 16>([&](auto K1) {
       constexpr int k1 = decltype(K1)::value;
-      x[3 * k1 + n2] = twmul<DIR, 48, n2 * k1>(t[k1]);
+      x[3 * k1 + n2] = twu<DIR, 48, n2 * k1>(t[k1]);
     });
   });
   float2 y[48];
   static_for<0, 16>([&](auto K1) {
     constexpr int k1 = decltype(K1)::value;
     float2 a0 = x[3 * k1], a1 = x[3 * k1 + 1], a2 = x[3 * k1 + 2];
-    dft3<DIR>(a0, a1, a2);
+    dft3s<DIR>(a0, a1, a2, twf<DIR, 48, k1>(), twf<DIR, 48, 2 * k1>());
     y[k1] = a0;
     y[k1 + 16] = a1;
     y[k1 + 32] = a2;
@@ -148,11 +151,11 @@ MFBD_HDI void op2_rows(const float (&se)[48], const float (&so)[48], float2* T, 
   T[lane * T2 + 0] = make_float2(z[0].x + z[0].y, z[0].x - z[0].y);   // kx = 0 and 48, packed
   static_for<1, 48>([&](auto K) {
     constexpr int k = decltype(K)::value;
+    // (a + c) / 2 + W96^-k (a - c) / (2i), the twiddle in factored form
     const float2 a = z[k], c = cconj(z[48 - k]);
-    const float2 e = cscale(cadd(a, c), 0.5f);
-    const float2 d = csub(a, c);
-    const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);   // d / (2i)
-    T[lane * T2 + k] = cadd(e, twmul<-1, 96, k>(o));
+    const float2 e = twu<-1, 96, k>(make_float2(a.y - c.y, c.x - a.x));
+    constexpr float f = 0.5f * twf<-1, 96, k>();
+    T[lane * T2 + k] = make_float2(0.5f * (a.x + c.x) + f * e.x, 0.5f * (a.y + c.y) + f * e.y);
   });
 }
 
@@ -239,8 +242,9 @@ MFBD_HDI void op3_rows(const float2* T, int lane, float (&ge)[48], float (&go)[4
     constexpr int k = decltype(K)::value;
     const float2 a = Xr[k], c = cconj(Xr[48 - k]);
     const float2 s = cadd(a, c);
-    const float2 t = twmul<+1, 96, k>(csub(a, c));
-    Z[k] = make_float2(s.x - t.y, s.y + t.x);   // s + i t
+    const float2 t = twu<+1, 96, k>(csub(a, c));   // t f = W96^k (a - c)
+    constexpr float f = twf<+1, 96, k>();
+    Z[k] = make_float2(s.x - f * t.y, s.y + f * t.x);   // s + i W96^k (a - c)
   });
   fft48<+1>(Z);
   static_for<0, 48>([&](auto I) {
@@ -322,16 +326,23 @@ MFBD_HDI void op14_rows(float2* T, int lane, const float (&ge)[48], const float 
     fft16<-1>(t);
     static_for<0, 16>([&](auto K1) {
       constexpr int k1 = decltype(K1)::value;
-      B[3 * k1 + n2] = twmul<-1, 48, n2 * k1>(t[k1]);
+      B[3 * k1 + n2] = twu<-1, 48, n2 * k1>(t[k1]);
     });
   });
+  // y + W96^-E x with the twiddle in factored form
+  auto comb = [](auto E, float2 y, float2 x) {
+    constexpr int e = decltype(E)::value;
+    const float2 u = twu<-1, 96, e>(x);
+    constexpr float f = twf<-1, 96, e>();
+    return make_float2(y.x + f * u.x, y.y + f * u.y);
+  };
   static_for<0, 16>([&](auto K1) {
     constexpr int k1 = decltype(K1)::value;
     float2 a0 = B[3 * k1], a1 = B[3 * k1 + 1], a2 = B[3 * k1 + 2];
-    dft3<-1>(a0, a1, a2);      // outputs k1, k1 + 16, k1 + 32 of the transform
-    Gr[k1] = cadd(T[k1 * T1 + lane], twmul<-1, 96, 24 + k1>(a0));
-    Gr[k1 + 16] = cadd(T[(k1 + 16) * T1 + lane], twmul<-1, 96, 40 + k1>(a1));
-    Gr[k1 + 32] = cadd(T[(k1 + 32) * T1 + lane], twmul<-1, 96, 56 + k1>(a2));
+    dft3s<-1>(a0, a1, a2, twf<-1, 48, k1>(), twf<-1, 48, 2 * k1>());   // outputs k1, k1 + 16, k1 + 32
+    Gr[k1] = comb(std::integral_constant<int, 24 + k1>{}, T[k1 * T1 + lane], a0);
+    Gr[k1 + 16] = comb(std::integral_constant<int, 40 + k1>{}, T[(k1 + 16) * T1 + lane], a1);
+    Gr[k1 + 32] = comb(std::integral_constant<int, 56 + k1>{}, T[(k1 + 32) * T1 + lane], a2);
   });
 }
 
