@@ -67,18 +67,18 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "07bc10acc653", "knob": "xcd_adjoint",
-                      "by_value": {1: (895469405, 94470144), 0: (1094480242, 94470144)}},
-    ("forward", 64): {"sources_sha1": "07bc10acc653", "knob": "xcd_forward",
-                      "by_value": {0: (94910090, 404845519), 1: (94911276, 400968493)}},
-    ("object", 64): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
-                     "by_value": {1: (729206980, 32782422)}},
-    ("adjoint", 128): {"sources_sha1": "1b51b605f66c", "knob": "xcd_adjoint",
-                       "by_value": {1: (11972387207, 1511522304), 0: (13316000157, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "1b51b605f66c", "knob": "xcd_forward",
-                       "by_value": {0: (3215722139, 8836415903), 1: (3230446399, 8747885187)}},
-    ("object", 128): {"sources_sha1": "565d80445c53", "knob": "object_pairs_per_thread",
-                      "by_value": {1: (10901721952, 257958847)}},
+    ("adjoint", 64): {"sources_sha1": "0c16b518d153", "knob": "xcd_adjoint",
+                      "by_value": {1: (895283239, 94470144), 0: (1094347538, 94470144)}},
+    ("forward", 64): {"sources_sha1": "0c16b518d153", "knob": "xcd_forward",
+                      "by_value": {0: (94914058, 404911877), 1: (94914583, 401073992)}},
+    ("object", 64): {"sources_sha1": "f0c07e1fa905", "knob": "object_pairs_per_thread",
+                     "by_value": {1: (729206988, 32782503)}},
+    ("adjoint", 128): {"sources_sha1": "1e372a93e25b", "knob": "xcd_adjoint",
+                       "by_value": {1: (11990566468, 1511522304), 0: (13298084803, 1511522304)}},
+    ("forward", 128): {"sources_sha1": "1e372a93e25b", "knob": "xcd_forward",
+                       "by_value": {0: (3214363495, 8835688080), 1: (3231126616, 8752537446)}},
+    ("object", 128): {"sources_sha1": "f0c07e1fa905", "knob": "object_pairs_per_thread",
+                      "by_value": {1: (10901716509, 257958680)}},
 }
 
 

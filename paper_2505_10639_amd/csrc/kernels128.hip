@@ -162,7 +162,8 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
   const int k = ct.chan_obj[c];
   const float w2 = -2.0f * (la.weights ? la.weights[c * J + j] : 1.0f);
 
-  // G = -2 w conj(O)(D - O S) in spectral layout (G(ky, 64) of lanes < 128
+  // G = conj(O)(D - O S) in spectral layout (the frame factor -2 w is applied
+  // with 2 kappa after the inverse transform; G(ky, 64) of lanes < 128
   // into Taux[ky]); zero outside the object's spectral support, where D, S
   // and O are not read
   float2 G[32];
@@ -177,15 +178,13 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
 #pragma unroll
     for (int m = 0; m < 32; ++m) {
       const int off = in_support(4 * m + r, N, fm) ? sl_index(lane, m) * 8 : kOut;
-      const float2 o = buffer_load_f2(rO, off);
-      G[m] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
-                    w2);
+      G[m] = adjoint_input(buffer_load_f2(rD, off), buffer_load_f2(rS, off),
+                           buffer_load_f2(rO, off));
     }
     if (lane < 128) {
       const int off = in_support(lane, N, la.supp[k * HC + 64]) ? sl_index64(lane) * 8 : kOut;
-      const float2 o = buffer_load_f2(rO, off);
-      Taux[lane] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
-                          w2);
+      Taux[lane] = adjoint_input(buffer_load_f2(rD, off), buffer_load_f2(rS, off),
+                                 buffer_load_f2(rO, off));
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -207,7 +206,7 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
     sync();
     op3_rows_finish(keep, other, lane, g);
   }
-  // recompute the PSF amplitude p and form H = 2 kappa g p
+  // recompute the PSF amplitude p and form H = -4 w kappa g p
   const float* Ac = Ab + (size_t)c * kBP;
   const float* phu = phi + (size_t)u * kBP;
   {
@@ -218,7 +217,7 @@ __device__ __forceinline__ void adjoint128_unit(int u, const ChanTab& ct, int C,
   sync();
   float2 H[64];
   op1_rows(T, lane, H);
-  const float k2 = 2.0f * ct.kappa[c];
+  const float k2 = 2.0f * ct.kappa[c] * w2;   // w2: the frame's -2 w
 #pragma unroll
   for (int m = 0; m < 64; ++m) H[m] = cscale(H[m], k2 * g[m]);
   sync();

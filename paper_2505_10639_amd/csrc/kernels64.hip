@@ -5,7 +5,7 @@
 //             -> forward 2-D DFT (OTF half spectrum)
 //   object  : Wiener object O_k = N_k / Q_k and the residual-form loss of the
 //             patch, accumulated in FP64
-//   adjoint : G = -2 w conj(O)(D - O S) -> inverse DFT -> H = 2 kappa g p
+//   adjoint : G = conj(O)(D - O S) -> inverse DFT -> H = -4 w kappa g p
 //             -> forward DFT on the pupil band -> dL/dphi = Im(conj(P) G_P)
 //   prepare : patch cut, mean removal, apodization, mean restore, 2-D DFT
 //   objimg  : object spectrum -> real image / N^2
@@ -190,7 +190,8 @@ __device__ __forceinline__ void adjoint64_unit(int u, const ChanTab& ct, int C, 
   float2 y[32];
   build_pupil(Ac, phu, lane, y);
 
-  // G = -2 w conj(O) (D - O S) in spectral layout; zero outside the
+  // G = conj(O) (D - O S) in spectral layout (the frame factor -2 w is
+  // applied with 2 kappa after the inverse transform); zero outside the
   // object's spectral support, where D, S and O are not read
   constexpr int kOut = kUnitF2 * 8;
   const __amdgpu_buffer_rsrc_t rD = raw_buffer(Du, kOut), rS = raw_buffer(Su, kOut),
@@ -201,15 +202,13 @@ __device__ __forceinline__ void adjoint64_unit(int u, const ChanTab& ct, int C, 
   for (int m = 0; m < 32; ++m) {
     const int off = in_support(2 * m + (lane & 1), N, fm) ? sl_index(lane, m) * 8 : kOut;
     const float2 o = buffer_load_f2(rO, off);
-    const float2 r = csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)));
-    G[m] = cscale(cmul(cconj(o), r), w2);
+    G[m] = cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off))));
   }
   float2 g32;
   {
     const int off = in_support(lane, N, la.supp[k * HC + 32]) ? sl_index32(lane) * 8 : kOut;
     const float2 o = buffer_load_f2(rO, off);
-    const float2 r = csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)));
-    g32 = cscale(cmul(cconj(o), r), w2);
+    g32 = cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off))));
   }
   __builtin_amdgcn_s_setprio(0);
   op3_gather(g32, Taux, lane);
@@ -220,12 +219,12 @@ __device__ __forceinline__ void adjoint64_unit(int u, const ChanTab& ct, int C, 
   op3_rows(T, lane, ge, go);
   wave_sync();
 
-  // recompute the pupil band transform, then H = 2 kappa g p and its
+  // recompute the pupil band transform, then H = -4 w kappa g p and its
   // forward transform to the band, half a row spectrum at a time
   op1_cols(y, T, lane);
   wave_sync();
   float2 Gr[32];
-  op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c], Gr);
+  op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c] * w2, Gr);   // w2: the frame's -2 w
   wave_sync();
   op14_write(Gr, T, lane);
   wave_sync();

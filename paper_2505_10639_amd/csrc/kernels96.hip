@@ -4,7 +4,7 @@
 // lanes 0..95 carry the lines of the 96-point transforms, lanes 96..127 only
 // take part in the barriers.  Same stages as the 64x64 kernels:
 //   forward : phase -> pupil -> inverse 2-D DFT -> |.|^2 -> forward 2-D DFT
-//   adjoint : G = -2 w conj(O)(D - O S) -> inverse DFT -> H = 2 kappa g p
+//   adjoint : G = conj(O)(D - O S) -> inverse DFT -> H = -4 w kappa g p
 //             -> forward DFT on the pupil band -> dL/dphi = Im(conj(P) G_P)
 //   prepare : patch cut, mean removal, apodization, mean restore, 2-D DFT
 //   objimg  : object spectrum -> real image / N^2
@@ -157,14 +157,12 @@ __device__ __forceinline__ void adjoint96_unit(int u, const ChanTab& ct, int C, 
 #pragma unroll
     for (int m = 0; m < 48; ++m) {
       const int off = in_support(2 * m + (lane & 1), N, fm) ? sl_index(lane, m) * 8 : kOut;
-      const float2 o = buffer_load_f2(rO, off);
-      G[m] = cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
-                    w2);
+      G[m] = adjoint_input(buffer_load_f2(rD, off), buffer_load_f2(rS, off),
+                           buffer_load_f2(rO, off));
     }
     const int off = in_support(lane, N, la.supp[k * HC + 48]) ? sl_index48(lane) * 8 : kOut;
-    const float2 o = buffer_load_f2(rO, off);
-    op3_gather(cscale(cmul(cconj(o), csub(buffer_load_f2(rD, off), cmul(o, buffer_load_f2(rS, off)))),
-                      w2),
+    op3_gather(adjoint_input(buffer_load_f2(rD, off), buffer_load_f2(rS, off),
+                             buffer_load_f2(rO, off)),
                Taux, lane);
   }
   __builtin_amdgcn_s_setprio(0);
@@ -183,7 +181,7 @@ __device__ __forceinline__ void adjoint96_unit(int u, const ChanTab& ct, int C, 
   }
   sync();
   float2 Gr[48];
-  if (on) op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c], Gr);
+  if (on) op14_rows(T, lane, ge, go, 2.0f * ct.kappa[c] * w2, Gr);   // w2: the frame's -2 w
   sync();
   if (on) op14_write(Gr, T, lane);
   sync();
