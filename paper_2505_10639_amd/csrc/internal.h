@@ -93,8 +93,17 @@ __device__ __forceinline__ bool in_support(int ky, int n, int fmax) {
 // elements): a load at an offset at or beyond `bytes` returns zero without
 // a memory access, which skips the spectrum outside the support without a
 // branch.
+// The resource lives in scalar registers.  Every caller passes one base per
+// wave, so the base is read from the first active lane: a pointer the
+// compiler holds in vector registers (read from a field descriptor in a
+// group kernel) then costs two readfirstlane, not a loop over the distinct
+// lanes around every load.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* base, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+  const unsigned long long a = reinterpret_cast<unsigned long long>(base);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+  void* const p = reinterpret_cast<void*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 typedef unsigned int mfbd_u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int mfbd_u32x4 __attribute__((ext_vector_type(4)));
