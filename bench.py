@@ -71,14 +71,14 @@ COUNTED_TRAFFIC = {
                       "by_value": {1: (895283239, 94470144), 0: (1094347538, 94470144)}},
     ("forward", 64): {"sources_sha1": "b061a2f0bb8c", "knob": "xcd_forward",
                       "by_value": {0: (94914058, 404911877), 1: (94914583, 401073992)}},
-    ("object", 64): {"sources_sha1": "9c3889f2d2d6", "knob": "object_pairs_per_thread",
-                     "by_value": {1: (729206988, 32782503)}},
+    ("object", 64): {"sources_sha1": "b9a336b58455", "knob": "object_pairs_per_thread",
+                     "by_value": {1: (729197152, 32782698)}},
     ("adjoint", 128): {"sources_sha1": "f2cf15c7cc44", "knob": "xcd_adjoint",
                        "by_value": {1: (11990566468, 1511522304), 0: (13298084803, 1511522304)}},
     ("forward", 128): {"sources_sha1": "f2cf15c7cc44", "knob": "xcd_forward",
                        "by_value": {0: (3214363495, 8835688080), 1: (3231126616, 8752537446)}},
-    ("object", 128): {"sources_sha1": "9c3889f2d2d6", "knob": "object_pairs_per_thread",
-                      "by_value": {1: (10901716509, 257958680)}},
+    ("object", 128): {"sources_sha1": "b9a336b58455", "knob": "object_pairs_per_thread",
+                      "by_value": {1: (10901716100, 257960012)}},
 }
 
 

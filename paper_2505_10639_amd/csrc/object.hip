@@ -118,7 +118,11 @@ __global__ __launch_bounds__(256) void k_object(int P, int C, int J, int K, Chan
                                                 const float2* __restrict__ S,
                                                 float2* __restrict__ O,
                                                 double* __restrict__ loss_part) {
-  object_block<NN, PPT>(blockIdx.x, C, J, K, ct, la, active, S, O, loss_part);
+  // planes from the last patch to the first: the forward kernel has just
+  // written S from the first unit to the last, so the most recently written
+  // OTFs, the ones still held by the memory-side cache, are read first (and
+  // the adjoint, walking forward, meets first the spectra read here last)
+  object_block<NN, PPT>(gridDim.x - 1 - blockIdx.x, C, J, K, ct, la, active, S, O, loss_part);
 }
 
 // Every (patch, object) plane of every field of a group (one pair per thread).
