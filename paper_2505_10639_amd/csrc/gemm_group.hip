@@ -15,12 +15,12 @@ namespace {
 __device__ __forceinline__ int zc_of(const Dims& d) { return d.zc > 0 ? d.zc : d.C; }
 
 // grid (4 * largest zc, phase tiles of all fields)
-__global__ __launch_bounds__(256) void k_phase_group(GroupArgs ga) {
+__global__ __launch_bounds__(64 * kPhaseWaves) void k_phase_group(GroupArgs ga) {
   const int2 it = ga.item[blockIdx.y];
   const FieldDesc& F = ga.fd[it.x];
   const int zc = zc_of(F.d);
   if ((int)blockIdx.x >= 4 * zc) return;
-  contract::phase_block<kPhaseCols / 16, 4>(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc,
+  contract::phase_block<kPhaseCols / 16, kPhaseWaves>(blockIdx.x, it.y, F.d.P * F.d.J, F.d.J, F.d.C, zc,
                                         F.d.M, F.Mq, F.d.bandpix(), F.ZsT, F.thetat, F.alpha,
                                         F.w.phi);
 }
@@ -76,7 +76,8 @@ hipError_t launch_phase_group(const GroupArgs& ga, int zc_max, int Mq_max, hipSt
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_phase_group, dim3(4 * zc_max, ga.total), dim3(256), lds, s, ga);
+  hipLaunchKernelGGL(k_phase_group, dim3(4 * zc_max, ga.total), dim3(64 * kPhaseWaves), lds, s,
+                     ga);
   return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ constexpr int kMaxK = 32;
 constexpr int kMaxM = 256;
 constexpr int kBand = 32;            // band width for N = 64
 constexpr int kBandPix = kBand * kBand;
-constexpr int kPhaseCols = 32;       // (patch, frame) columns per phase-contraction block
+constexpr int kPhaseCols = 64;       // (patch, frame) columns per group phase-contraction block
+constexpr int kPhaseWaves = 8;       // and its waves
 
 // Blocks of 256 threads, `ppt` frequency pairs per thread, covering one
 // half spectrum of side n.

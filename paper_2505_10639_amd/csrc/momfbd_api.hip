@@ -1176,7 +1176,7 @@ int momfbd_group_get_tuning(momfbd_group g, momfbd_tuning* t) {
   t->grad_splits = group_splits(g);
   t->grad_row_tiles = g->grad_rt;
   t->phase_col_tiles = kPhaseCols / 16;
-  t->phase_waves = 4;
+  t->phase_waves = kPhaseWaves;
   return MOMFBD_OK;
 }
 
