@@ -549,9 +549,10 @@ int momfbd_group_loss_grad(momfbd_group group, void* stream);
 int momfbd_group_lbfgs_rounds(momfbd_group group, int rounds, void* stream);
 
 /* Launch schedules of a group (the fields of momfbd_tuning that apply:
- * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4, 3 or 2; grad_waves
- * must be 4; the phase fields are ignored: a group's phase blocks are 4
- * tiles x 8 waves).  The autotuner times momfbd_group_loss_grad over `reps`
+ * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4, 3 or 2 (0: 4, or
+ * 3 and 2 where the group's largest mode count reaches 176 and 224, whose
+ * accumulators would not fit four tiles); grad_waves must be 4; the phase
+ * fields are ignored: a group's phase blocks are 4 tiles x 8 waves).  The autotuner times momfbd_group_loss_grad over `reps`
  * evaluations per candidate with the plan autotuner's method and keeps the
  * fastest schedule.  Errors: EINVAL, EDEVICE. */
 int momfbd_group_set_tuning(momfbd_group group, const momfbd_tuning* tuning);

@@ -979,6 +979,8 @@ GroupArgs group_args(const momfbd_group_s* g, const FieldDesc* fd, int stage) {
   return a;
 }
 
+int group_default_rt(int mt_max) { return mt_max <= 10 ? 4 : mt_max <= 13 ? 3 : 2; }
+
 int group_splits(const momfbd_group_s* g) {
   if (g->grad_splits > 0) return g->grad_splits;
   // the automatic count of a plan with all the group's rows
@@ -1107,6 +1109,9 @@ int momfbd_group_create(const momfbd_field* fields, int n, const momfbd_lbfgs_pa
   g->zc_max = zc_max;
   g->Mq_max = Mq_max;
   g->mt_max = mt_max;
+  // default row tiles per wave: fewer for the widest mode counts, where
+  // four tiles of 16 x mt_max accumulators would spill (176 modes and up)
+  g->grad_rt = group_default_rt(mt_max);
   g->rows = rows;
   const bool ok =
       hipMalloc(&g->fd_eval, n * sizeof(FieldDesc)) == hipSuccess &&
@@ -1162,7 +1167,8 @@ int momfbd_group_set_tuning(momfbd_group g, const momfbd_tuning* t) {
   if (!g || !tuning_ok(t) || t->grad_waves != 4) return MOMFBD_EINVAL;
   g->xcd_fwd = t->xcd_forward;
   g->xcd_adj = t->xcd_adjoint;
-  g->grad_rt = t->grad_row_tiles == 3 || t->grad_row_tiles == 2 ? t->grad_row_tiles : 4;
+  g->grad_rt = t->grad_row_tiles == 0 ? group_default_rt(g->mt_max)
+                : t->grad_row_tiles == 3 || t->grad_row_tiles == 2 ? t->grad_row_tiles : 4;
   g->grad_splits = t->grad_splits;
   return MOMFBD_OK;
 }
@@ -1207,7 +1213,10 @@ int momfbd_group_autotune(momfbd_group g, int reps, void* stream, momfbd_tuning*
   // three rounds, each keeping its fastest; the default first, replaced only
   // by a value at least 1% faster
   int* knobs[4] = {&g->xcd_adj, &g->xcd_fwd, &g->grad_rt, &g->grad_splits};
-  std::vector<int> values[4] = {{1, 0}, {0, 1}, {4, 3, 2}, {}};
+  const int rt0 = group_default_rt(g->mt_max);
+  std::vector<int> values[4] = {{1, 0}, {0, 1}, {rt0}, {}};
+  for (int v = 4; v >= 2; --v)
+    if (v != rt0) values[2].push_back(v);
   for (int k = 0; k < 4 && st == MOMFBD_OK; ++k) {
     if (k == 3) {
       g->grad_splits = 0;

@@ -138,6 +138,40 @@ def test_group_evaluation_equals_each_plan(dev):
         f.close()
 
 
+def test_group_wide_mode_counts(dev):
+    """Fields of up to 200 modes (13 tiles of 16): the group's default row
+    tiles per wave drop to 3, so that the accumulators fit the registers,
+    and its loss and gradient are still each field's own plan's bit for bit
+    (same gradient splits), and the oracle's on a sampled patch."""
+    from paper_2505_10639_amd import _lib
+    from paper_2505_10639_amd.batch import FieldGroup
+    problems = []
+    for i, M in enumerate((200, 180)):
+        pr = synth.make_problem(130 + i, N=64, P=2, J=2, M=M, channels=((0, 0.0),),
+                                d_over_r0=np.array([6.0, 9.0]))
+        problems.append((pr, fast_simulate_D(pr)))
+    fields = make_fields(dev, problems)
+    _set_alpha(fields, problems, 7)
+    g = FieldGroup(fields)
+    assert _lib.momfbd_group_get_tuning(g.handle)["grad_row_tiles"] == 3
+    _lib.momfbd_group_set_tuning(g.handle, 0, 1, grad_splits=1, grad_row_tiles=0)
+    assert _lib.momfbd_group_get_tuning(g.handle)["grad_row_tiles"] == 3
+    g.loss_grad()
+    torch.cuda.synchronize()
+    for i, (f, (pr, D_np)) in enumerate(zip(fields, problems)):
+        f.plan.set_tuning(0, 1, 1, 4, 1)
+        loss, grad = f.plan.loss_grad(f.alpha, f.D, f.gamma)
+        torch.cuda.synchronize()
+        assert torch.equal(f.loss_eval, loss) and torch.equal(f.grad_eval, grad), i
+        ref = oracle.evaluate(f.alpha.cpu().numpy(), D_np, pr.basis, pr.diversity, pr.pupil,
+                              pr.channel_object, pr.gamma, patches=[i])
+        assert abs(float(f.loss_eval[i]) - ref["loss"][0]) < LOSS_RTOL * abs(ref["loss"][0])
+        assert_grad_close(f.grad_eval.cpu().numpy()[[i]], ref["grad"], f"wide field {i}")
+    g.close()
+    for f in fields:
+        f.close()
+
+
 def test_group_rounds_equal_field_rounds_and_replay_from_a_graph(dev):
     """Solver rounds of a group (one launch per stage per patch size) follow
     each field's own solver rounds bit for bit, eagerly and replayed from a
