@@ -37,10 +37,17 @@ hipError_t allow_lds(const void* kernel, size_t bytes) {
   return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// grad = 2 pi (part[0] + part[1] + ... + part[splits-1]), in that order.
-__global__ __launch_bounds__(256) void k_grad_combine(long n, int splits,
+// grad = 2 pi (part[0] + part[1] + ... + part[splits-1]), in that order;
+// the blocks past the gradient's (`cblocks`) sum the per-patch loss when the
+// call asks for it (ls.P > 0), saving that sum a launch of its own.
+__global__ __launch_bounds__(256) void k_grad_combine(long n, int splits, int cblocks,
                                                       const float* __restrict__ part,
-                                                      float* __restrict__ grad) {
+                                                      float* __restrict__ grad, LossSum ls) {
+  if ((int)blockIdx.x >= cblocks) {
+    const int p = ((int)blockIdx.x - cblocks) * 256 + threadIdx.x;
+    if (p < ls.P) loss_sum_patch(p, ls.nper, ls.active, ls.loss_part, ls.loss);
+    return;
+  }
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   float v = part[i];
@@ -103,7 +110,7 @@ int grad_row_tiles_of(const Dims& d) {
 }
 
 hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float* grad,
-                       float* part, hipStream_t s) {
+                       float* part, hipStream_t s, const LossSum* ls) {
   const int mt = (d.M + 15) / 16;
   const int splits = grad_splits_of(d);
   hipError_t e;
@@ -119,9 +126,14 @@ hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float*
   if (e != hipSuccess) return e;
   if (splits > 1) {
     const long n = (long)d.P * d.J * d.M;
-    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       splits, part, grad);
+    const int cblocks = (int)((n + 255) / 256);
+    const LossSum none{0, 0, nullptr, nullptr, nullptr};
+    const LossSum& l = ls ? *ls : none;
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)(cblocks + (l.P + 255) / 256)), dim3(256),
+                       0, s, n, splits, cblocks, part, grad, l);
+    return hipGetLastError();
   }
+  if (ls) return launch_loss_sum(*ls, s);
   return hipGetLastError();
 }
 

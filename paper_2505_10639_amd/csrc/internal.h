@@ -216,14 +216,34 @@ hipError_t launch_phase(const Dims& d, const float* alpha, const uint4* ZsT, int
 // nonzero entry; the others are neither computed nor written.
 hipError_t launch_forward(const Dims& d, const ChanTab& ct, const int* active, const float* Ab,
                           const float* phi, float* psf, float2* S, hipStream_t s);
+// The per-patch loss: the object kernel's FP64 block partials summed per
+// patch in block order.  launch_object sums them itself unless asked to
+// leave them (sum_loss false) to launch_grad, which then folds the sum into
+// its combine launch (or launches it after the contraction).
+struct LossSum {
+  int P, nper;               // patches, partials per patch
+  const int* active;         // nullable patch mask
+  const double* loss_part;   // [P][nper]
+  double* loss;              // [P]
+};
+__device__ __forceinline__ void loss_sum_patch(int p, int nper, const int* __restrict__ active,
+                                               const double* __restrict__ loss_part,
+                                               double* __restrict__ loss) {
+  if (active && !active[p]) return;
+  double s = 0.0;
+  for (int i = 0; i < nper; ++i) s += loss_part[(size_t)p * nper + i];
+  loss[p] = s;
+}
+LossSum loss_sum_of(const Dims& d, const int* active, const double* loss_pk, double* loss);
+hipError_t launch_loss_sum(const LossSum& ls, hipStream_t s);
 hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                          const float2* S, float2* O, double* loss_pk, double* loss,
-                         hipStream_t s);
+                         hipStream_t s, bool sum_loss = true);
 hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                           const float* Ab, const float* phi, const float2* S, const float2* O,
                           float* gphi, hipStream_t s);
 hipError_t launch_grad(const Dims& d, const uint4* Zs, const float* gphi, float* grad,
-                       float* gpart, hipStream_t s);
+                       float* gpart, hipStream_t s, const LossSum* ls = nullptr);
 hipError_t launch_prepare(const Dims& d, const float* frames, int H, int W, int stride,
                           const float* apod, float2* D, hipStream_t s);
 hipError_t launch_objimg(const Dims& d, const float2* O, float* obj, hipStream_t s);

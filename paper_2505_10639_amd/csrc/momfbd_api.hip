@@ -484,9 +484,10 @@ int momfbd_forward(momfbd_plan plan, const float* alpha, float* psf, void* otf, 
   return to_status(e);
 }
 
+// (sum_loss false: the per-patch loss sum is left to the gradient stage)
 static int run_object(momfbd_plan plan, const float* alpha, const void* D, const float* gamma,
                       float gamma_scalar, const float* weights, const int* active, double* loss,
-                      void* ws, hipStream_t s, Workspace* wout) {
+                      void* ws, hipStream_t s, Workspace* wout, bool sum_loss = true) {
   const Workspace w = carve_workspace(plan->d, ws);
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
   hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
@@ -498,7 +499,8 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
     });
   if (e == hipSuccess)
     e = prof_launch(plan, KK_OBJECT, s, [&] {
-      return launch_object(plan->d, plan->ct, la, active, w.S, w.O, w.loss_pk, loss, s);
+      return launch_object(plan->d, plan->ct, la, active, w.S, w.O, w.loss_pk, loss, s,
+                           sum_loss);
     });
   *wout = w;
   return to_status(e);
@@ -509,15 +511,18 @@ static int run_loss_grad(momfbd_plan plan, const float* alpha, const void* D, co
                          float gamma_scalar, const float* weights, const int* active,
                          double* loss, float* grad, void* ws, hipStream_t s) {
   Workspace w;
-  int st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, active, loss, ws, s, &w);
+  int st = run_object(plan, alpha, D, gamma, gamma_scalar, weights, active, loss, ws, s, &w,
+                      grad == nullptr);
   if (st || !grad) return st;
   LossArgs la{static_cast<const float2*>(D), gamma, gamma_scalar, weights, plan->supp};
   hipError_t e = prof_launch(plan, KK_ADJOINT, s, [&] {
     return launch_adjoint(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O, w.gphi, s);
   });
+  // the gradient stage also sums the per-patch loss (in its combine launch)
+  const LossSum ls = loss_sum_of(plan->d, active, w.loss_pk, loss);
   if (e == hipSuccess)
     e = prof_launch(plan, KK_GRAD, s, [&] {
-      return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
+      return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s, &ls);
     });
   return to_status(e);
 }

@@ -134,16 +134,7 @@ __global__ __launch_bounds__(256) void k_object_group(GroupArgs ga) {
                       F.w.loss_pk);
 }
 
-// loss[p] = sum over objects and their blocks, in order
-__device__ __forceinline__ void loss_sum_patch(int p, int nper, const int* __restrict__ active,
-                                               const double* __restrict__ loss_part,
-                                               double* __restrict__ loss) {
-  if (active && !active[p]) return;
-  double s = 0.0;
-  for (int i = 0; i < nper; ++i) s += loss_part[(size_t)p * nper + i];
-  loss[p] = s;
-}
-
+// loss[p] = sum over objects and their blocks, in order (loss_sum_patch)
 __global__ __launch_bounds__(256) void k_loss_sum(int P, int nper, const int* __restrict__ active,
                                                   const double* __restrict__ loss_part,
                                                   double* __restrict__ loss) {
@@ -199,19 +190,27 @@ void launch_object_n(const Dims& d, const ChanTab& ct, const LossArgs& la, const
                        active, S, O, loss_pk);
 }
 
+LossSum loss_sum_of(const Dims& d, const int* active, const double* loss_pk, double* loss) {
+  return LossSum{d.P, d.K * object_blocks(d.N, d.obj_ppt), active, loss_pk, loss};
+}
+
+hipError_t launch_loss_sum(const LossSum& ls, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_sum, dim3((ls.P + 255) / 256), dim3(256), 0, s, ls.P, ls.nper,
+                     ls.active, ls.loss_part, ls.loss);
+  return hipGetLastError();
+}
+
 hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                          const float2* S, float2* O, double* loss_pk, double* loss,
-                         hipStream_t s) {
+                         hipStream_t s, bool sum_loss) {
   if (d.N == 64)
     launch_object_n<64>(d, ct, la, active, S, O, loss_pk, s);
   else if (d.N == 96)
     launch_object_n<96>(d, ct, la, active, S, O, loss_pk, s);
   else
     launch_object_n<128>(d, ct, la, active, S, O, loss_pk, s);
-  const int nb = object_blocks(d.N, d.obj_ppt);
-  hipLaunchKernelGGL(k_loss_sum, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.K * nb, active,
-                     loss_pk, loss);
-  return hipGetLastError();
+  if (!sum_loss) return hipGetLastError();
+  return launch_loss_sum(loss_sum_of(d, active, loss_pk, loss), s);
 }
 
 hipError_t launch_object_group(int N, const GroupArgs& ga_blocks, const GroupArgs& ga_patches,
