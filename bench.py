@@ -67,17 +67,17 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "04bb42a87580", "knob": "xcd_adjoint",
+    ("adjoint", 64): {"sources_sha1": "13c77fb8801d", "knob": "xcd_adjoint",
                       "by_value": {1: (895283239, 94470144), 0: (1094347538, 94470144)}},
-    ("forward", 64): {"sources_sha1": "04bb42a87580", "knob": "xcd_forward",
+    ("forward", 64): {"sources_sha1": "13c77fb8801d", "knob": "xcd_forward",
                       "by_value": {0: (94914058, 404911877), 1: (94914583, 401073992)}},
-    ("object", 64): {"sources_sha1": "c70ef55b10a9", "knob": "object_pairs_per_thread",
+    ("object", 64): {"sources_sha1": "8e15878e19b8", "knob": "object_pairs_per_thread",
                      "by_value": {1: (729197152, 32782698)}},
-    ("adjoint", 128): {"sources_sha1": "6d7094083033", "knob": "xcd_adjoint",
+    ("adjoint", 128): {"sources_sha1": "265260c40a1b", "knob": "xcd_adjoint",
                        "by_value": {1: (11990566468, 1511522304), 0: (13298084803, 1511522304)}},
-    ("forward", 128): {"sources_sha1": "6d7094083033", "knob": "xcd_forward",
+    ("forward", 128): {"sources_sha1": "265260c40a1b", "knob": "xcd_forward",
                        "by_value": {0: (3214363495, 8835688080), 1: (3231126616, 8752537446)}},
-    ("object", 128): {"sources_sha1": "c70ef55b10a9", "knob": "object_pairs_per_thread",
+    ("object", 128): {"sources_sha1": "8e15878e19b8", "knob": "object_pairs_per_thread",
                       "by_value": {1: (10901716100, 257960012)}},
 }
 
