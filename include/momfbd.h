@@ -460,6 +460,15 @@ typedef struct {
                                    input picks 8 x 8 where it fits, else 4 x 4
                                    or 2 x 4 (get_tuning reports the shape in
                                    use)                                       */
+  int object_fused;             /* 1: the forward transforms and the Wiener
+                                   object and loss (Eqs. object_optimization,
+                                   loss_momfbd) in one launch, a workgroup per
+                                   (patch, object) that reads its own OTFs back
+                                   from the caches; 0 (default): two launches.
+                                   Applies to 64x64 patches with at most 12
+                                   units (channels x frames) per object;
+                                   results are the same bit for bit.
+                                   get_tuning reports 1 only where in use    */
 } momfbd_tuning;
 /* Errors: EINVAL (NULL, a value out of range, or a phase shape whose
  * staged coefficients do not fit). */

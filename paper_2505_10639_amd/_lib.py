@@ -49,7 +49,8 @@ class momfbd_tuning(ctypes.Structure):
     _fields_ = [("xcd_forward", ctypes.c_int), ("xcd_adjoint", ctypes.c_int),
                 ("object_pairs_per_thread", ctypes.c_int), ("grad_waves", ctypes.c_int),
                 ("grad_splits", ctypes.c_int), ("grad_row_tiles", ctypes.c_int),
-                ("phase_col_tiles", ctypes.c_int), ("phase_waves", ctypes.c_int)]
+                ("phase_col_tiles", ctypes.c_int), ("phase_waves", ctypes.c_int),
+                ("object_fused", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -329,9 +330,10 @@ def momfbd_power_spectrum(image, window=None, nbins=None, stream=None):
 
 
 def momfbd_plan_set_tuning(plan, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves,
-                           grad_splits=0, grad_row_tiles=0, phase_col_tiles=0, phase_waves=0):
+                           grad_splits=0, grad_row_tiles=0, phase_col_tiles=0, phase_waves=0,
+                           object_fused=0):
     t = momfbd_tuning(xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves, grad_splits,
-                      grad_row_tiles, phase_col_tiles, phase_waves)
+                      grad_row_tiles, phase_col_tiles, phase_waves, object_fused)
     _check(lib().momfbd_plan_set_tuning(plan, ctypes.byref(t)), "momfbd_plan_set_tuning")
 
 

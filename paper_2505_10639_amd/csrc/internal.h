@@ -33,6 +33,12 @@ struct Dims {
   // the phase contraction's block: 16-column tiles and waves per workgroup
   // (0, 0: the widest block whose staged coefficients fit; phase_shape_of)
   int phase_ct = 0, phase_waves = 0;
+  // the object pass in the forward launch (k_fwdobj64) where it applies
+  // (fuse_ok, set at plan creation: 64x64 patches, at most 12 units per
+  // (patch, object)); fuse_obj is the schedule, 0 by default: measured
+  // slower than the two launches at the 64x64 full-field workload
+  int fuse_obj = 0;
+  bool fuse_ok = false;
   // distinct modal bases on the band: 1 when every channel's band-sampled
   // basis is the same (the contractions then run once for all channels),
   // else C; 0 is read as C
@@ -68,13 +74,6 @@ struct LossArgs {
   const int* supp;         // [K][N/2+1] spectral support of each object (plan table)
 };
 
-// Spectral support of an object.  A channel's OTF is the autocorrelation of
-// its pupil, so it vanishes outside the pupil's difference set; supp[k][kx]
-// is the largest |ky| (ky taken in (-N/2, N/2]) at which any channel of
-// object k can have a nonzero OTF in column kx of the half spectrum (-1:
-// none).  Outside it the Wiener object is zero, the residual is D and G =
-// -2 w conj(O) R vanishes, so the object kernel needs no S and the adjoint
-// no D, S or O there.
 // conj(O) (D - O S) at one frequency, the residual D - O S formed with two
 // FMAs per component (the 96x96 and 128x128 adjoint kernels' input; the
 // factor -2 w of the frame is applied after the inverse transform, which is
@@ -86,6 +85,13 @@ __device__ __forceinline__ float2 adjoint_input(float2 d, float2 s, float2 o) {
   return make_float2(o.x * rx + o.y * ry, o.x * ry - o.y * rx);
 }
 
+// Spectral support of an object.  A channel's OTF is the autocorrelation of
+// its pupil, so it vanishes outside the pupil's difference set; supp[k][kx]
+// is the largest |ky| (ky taken in (-N/2, N/2]) at which any channel of
+// object k can have a nonzero OTF in column kx of the half spectrum (-1:
+// none).  Outside it the Wiener object is zero, the residual is D and G =
+// -2 w conj(O) R vanishes, so the object kernel needs no S and the adjoint
+// no D, S or O there.
 __device__ __forceinline__ bool in_support(int ky, int n, int fmax) {
   return (ky <= n / 2 ? ky : n - ky) <= fmax;
 }
@@ -114,6 +120,92 @@ __device__ __forceinline__ float2 buffer_load_f2(__amdgpu_buffer_rsrc_t r, int o
 // 16 bytes with the nontemporal hint (data read once per launch)
 __device__ __forceinline__ float4 buffer_load_f4_stream(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2));
+}
+
+// FP64 sums of one frequency pair of a (patch, object) plane over its
+// units: N = sum w D conj(S), Q = gamma + sum w |S|^2, E = sum w |D|^2.
+// Products of FP32 inputs are exact in FP64.  The object kernel and the
+// fused forward/object kernel both use these two functions, in the same
+// unit order, so that their results agree bit for bit.
+struct Acc2 {
+  double nr[2], ni[2], q[2], e[2];
+};
+__device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
+  const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
+  const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
+  a.nr[0] += w * (dx0 * sx0 + dy0 * sy0);
+  a.ni[0] += w * (dy0 * sx0 - dx0 * sy0);
+  a.q[0] += w * (sx0 * sx0 + sy0 * sy0);
+  a.e[0] += w * (dx0 * dx0 + dy0 * dy0);
+  a.nr[1] += w * (dx1 * sx1 + dy1 * sy1);
+  a.ni[1] += w * (dy1 * sx1 - dx1 * sy1);
+  a.q[1] += w * (sx1 * sx1 + sy1 * sy1);
+  a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
+}
+// The Wiener object O = N / Q of the pair (f, f + 1) and its loss term
+// E - |N|^2 / Q, columns 1..N/2-1 of the half spectrum counting twice.
+__device__ __forceinline__ float4 wiener_pair(const Acc2& a, int f, int hc, double& loss) {
+  const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
+  const int kx0 = f % hc, kx1 = (f + 1) % hc;
+  const double h0 = (kx0 == 0 || kx0 == hc - 1) ? 1.0 : 2.0;
+  const double h1 = (kx1 == 0 || kx1 == hc - 1) ? 1.0 : 2.0;
+  loss += h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
+          h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
+  return make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0), (float)(a.nr[1] * inv1),
+                     (float)(a.ni[1] * inv1));
+}
+
+// Frequency pair f2 (frequencies f = 2 f2 and f + 1 of the half spectrum)
+// of the (patch p, object k) plane: N, Q and E over the object's units in
+// order (its channels in order, each channel's frames in order), reading D
+// and, within the object's spectral support, S; writes the pair of O and
+// returns its loss term.  Outside the support every S of the pair is zero
+// and is not read (N = 0, Q = gamma, O = 0, loss term E).
+template <int NN>
+__device__ __forceinline__ double object_pair(int f2, int p, int k, int C, int J, int K,
+                                              const ChanTab& ct, const LossArgs& la,
+                                              const float2* __restrict__ S,
+                                              float2* __restrict__ O) {
+  constexpr int HC = NN / 2 + 1;
+  constexpr int kUnitF2 = NN * HC;
+  const int f = 2 * f2;
+  Acc2 a;
+  for (int i = 0; i < 2; ++i) {
+    a.nr[i] = a.ni[i] = a.e[i] = 0.0;
+    a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
+  }
+  const bool sup = in_support(f / HC, NN, la.supp[k * HC + f % HC]) ||
+                   in_support((f + 1) / HC, NN, la.supp[k * HC + (f + 1) % HC]);
+  const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
+  for (int ci = c0; ci < c1; ++ci) {
+    const int c = ct.obj_chans[ci];
+    const float4* Dc =
+        reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
+    const int s_bytes = J * kUnitF2 * 8;
+    const __amdgpu_buffer_rsrc_t rS =
+        raw_buffer(S + ((size_t)(p * C + c) * J) * kUnitF2, s_bytes);
+    const int s_off = sup ? f * 8 : s_bytes;
+    constexpr int kStep = kUnitF2 * 8;   // bytes between frames
+    const float* wc = la.weights ? la.weights + c * J : nullptr;
+    int j = 0;
+    for (; j + 6 <= J; j += 6) {
+      float4 d[6], s[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        d[u] = stream_load(Dc + (size_t)(j + u) * (kUnitF2 / 2));
+        s[u] = buffer_load_f4_stream(rS, sup ? s_off + (j + u) * kStep : s_bytes);
+      }
+#pragma unroll
+      for (int u = 0; u < 6; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
+    }
+    for (; j < J; ++j)
+      acc_unit(a, wc ? (double)wc[j] : 1.0, stream_load(Dc + (size_t)j * (kUnitF2 / 2)),
+               buffer_load_f4_stream(rS, sup ? s_off + j * kStep : s_bytes));
+  }
+  double loss = 0.0;
+  const float4 o = wiener_pair(a, f, HC, loss);
+  reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
+  return loss;
 }
 
 // Smoothness prior constants per object.
@@ -241,6 +333,14 @@ hipError_t launch_loss_sum(const LossSum& ls, hipStream_t s);
 hipError_t launch_object(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                          const float2* S, float2* O, double* loss_pk, double* loss,
                          hipStream_t s, bool sum_loss = true);
+// Forward and object pass in one launch (64x64 patches, one workgroup per
+// (patch, object)): S, O and the loss partials equal those of launch_forward
+// followed by launch_object with one pair per thread, bit for bit.
+constexpr int kFusedWaves = 12;   // units per (patch, object) it takes at most
+inline bool fused_object(const Dims& d) { return d.fuse_ok && d.fuse_obj; }
+hipError_t launch_fwdobj64(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                           const int* active, const float* Ab, const float* phi, float2* S,
+                           float2* O, double* loss_pk, hipStream_t s);
 hipError_t launch_adjoint(const Dims& d, const ChanTab& ct, const LossArgs& la, const int* active,
                           const float* Ab, const float* phi, const float2* S, const float2* O,
                           float* gphi, hipStream_t s);

@@ -27,6 +27,22 @@ constexpr int kUnitF2 = N * HC;   // float2 elements per half spectrum (2112)
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
+// Ordering of a unit's LDS exchanges: SYNC 0, the workgroup barrier (a
+// one-wave workgroup); SYNC 1, for a unit that is one wave of a larger
+// workgroup, the wave's own order only: a wave's LDS accesses complete in
+// issue order, so fences at wavefront scope that keep the compiler from
+// moving accesses across them are enough.
+template <int SYNC>
+__device__ __forceinline__ void unit_sync() {
+  if constexpr (SYNC == 0) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Remapping block b to unit (b mod 8) * per + b / 8 gives every XCD a
 // contiguous run of units, so the frames of one patch-object (which share the
@@ -68,20 +84,19 @@ __device__ __forceinline__ void build_pupil(const float* __restrict__ A, const f
 // The two transposes go through a half-size buffer (real parts, then
 // imaginary parts): 9.2 KB of LDS per wave lets a CU hold the 12 waves its
 // registers allow, against 9 with the full-size buffer.
-// Unit u of a field (the kernel of one plan and the group kernel both
-// resolve u, then run this).
-template <bool WANT_PSF>
-__device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, int J,
-                                               const int* __restrict__ active,
+// Unit u of a field on the wave's LDS (Th, Taux); the OTF is stored to S and
+// left in X (lane's values at sl_index) and x32 (at sl_index32).
+template <bool WANT_PSF, int SYNC>
+__device__ __forceinline__ void forward64_core(float2* Th, float2* Taux, int u, const ChanTab& ct,
+                                               int C, int J, const int* __restrict__ active,
                                                const float* __restrict__ Ab,
                                                const float* __restrict__ phi,
                                                float* __restrict__ psf,
-                                               float2* __restrict__ S) {
-  __shared__ float2 Th[LDS_HALF / 2];
-  __shared__ float2 Taux[LDS_AUX];
+                                               float2* __restrict__ S, float2 (&X)[32],
+                                               float2& x32) {
   float* Tf = reinterpret_cast<float*>(Th);
   if (active && !active[u / (J * C)]) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int c = (u / J) % C;
   float2 pe[32], po[32];
   {
@@ -93,12 +108,12 @@ __device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, 
     __builtin_amdgcn_s_setprio(0);
     fft32<+1>(y);
     op1_cols_put<0>(y, Tf, lane);
-    wave_sync();
+    unit_sync<SYNC>();
     op1_rows_get0(Tf, lane, pe);
-    wave_sync();
+    unit_sync<SYNC>();
     op1_cols_put<1>(y, Tf, lane);
   }
-  wave_sync();
+  unit_sync<SYNC>();
   op1_rows_get1(Tf, lane, pe, po);
   // half the PSF row (op2_rows_values takes s / 2; the factor is exact)
   const float kap_half = 0.5f * ct.kappa[c];
@@ -118,24 +133,38 @@ __device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, 
   }
   float2 v[32];
   op2_rows_values(se, so, v);
-  wave_sync();
+  unit_sync<SYNC>();
   op2_rows_put<0>(v, Tf, lane);
-  wave_sync();
-  float2 X[32];
+  unit_sync<SYNC>();
   op2_cols_get<0>(Tf, lane, X);
-  wave_sync();
+  unit_sync<SYNC>();
   op2_rows_put<1>(v, Tf, lane);
-  wave_sync();
+  unit_sync<SYNC>();
   op2_cols_get<1>(Tf, lane, X);
   op2_cols_finish(X, Taux, lane);
-  wave_sync();
-  const float2 x32 = op2_unpack(Taux, Th, lane);
-  wave_sync();
+  unit_sync<SYNC>();
+  x32 = op2_unpack(Taux, Th, lane);
+  unit_sync<SYNC>();
   op2_collect(Th, lane, X);
   float2* out = S + (size_t)u * kUnitF2;
 #pragma unroll
   for (int m = 0; m < 32; ++m) out[sl_index(lane, m)] = X[m];
   out[sl_index32(lane)] = x32;
+}
+
+// Unit u of a field (the kernel of one plan and the group kernel both
+// resolve u, then run this).
+template <bool WANT_PSF>
+__device__ __forceinline__ void forward64_unit(int u, const ChanTab& ct, int C, int J,
+                                               const int* __restrict__ active,
+                                               const float* __restrict__ Ab,
+                                               const float* __restrict__ phi,
+                                               float* __restrict__ psf,
+                                               float2* __restrict__ S) {
+  __shared__ float2 Th[LDS_HALF / 2];
+  __shared__ float2 Taux[LDS_AUX];
+  float2 X[32], x32;
+  forward64_core<WANT_PSF, 0>(Th, Taux, u, ct, C, J, active, Ab, phi, psf, S, X, x32);
 }
 
 template <bool WANT_PSF>
@@ -159,6 +188,66 @@ __global__ __launch_bounds__(64) void k_forward64_group(GroupArgs ga, int xcd) {
   const FieldDesc& F = ga.fd[it.x];
   forward64_unit<false>(it.y, F.ct, F.d.C, F.d.J, F.active, F.Ab, F.w.phi, nullptr,
                         F.w.S);
+}
+
+// Forward and Wiener object of one (patch, object) plane per workgroup of
+// kFusedWaves waves.  Wave w computes unit w of the plane (the object's
+// channels in order, each channel's frames in order) and stores its OTF to
+// S as k_forward64 does; after the barrier the workgroup's threads take the
+// plane's frequency pairs as k_object<64, 1> does (blocks of 256 pairs, one
+// pair per thread, the same per-pair code and the same tree sums of the loss
+// terms), so that O and the loss partials equal those of the two separate
+// launches bit for bit.  The OTFs it reads back were written by its own
+// waves moments before and come from the caches, not HBM: per step S
+// crosses HBM once less, and one launch is saved.  The workgroup holds
+// 110.6 KB of LDS, so a CU runs one at a time: the 12 waves its registers
+// allow the forward transforms in any case.
+constexpr int kWaveLds = LDS_HALF / 2 + LDS_AUX;   // float2 per wave (transforms)
+constexpr int kObjParts = object_blocks(N, 1);     // 256-pair blocks of a plane
+constexpr int kFusedThreads = 64 * kFusedWaves;
+static_assert(kObjParts * 256 * sizeof(double) <= kFusedWaves * kWaveLds * sizeof(float2),
+              "the loss terms of a plane fit the transforms' LDS");
+
+__global__ __launch_bounds__(kFusedThreads) void k_fwdobj64(int K, ChanTab ct, int C, int J,
+                                                            LossArgs la,
+                                                            const int* __restrict__ active,
+                                                            const float* __restrict__ Ab,
+                                                            const float* __restrict__ phi,
+                                                            float2* __restrict__ S,
+                                                            float2* __restrict__ O,
+                                                            double* __restrict__ loss_part) {
+  __shared__ float2 lds[kFusedWaves * kWaveLds];
+  const int plane = blockIdx.x, p = plane / K, k = plane % K;
+  if (active && !active[p]) return;
+  const int w = threadIdx.x >> 6;
+  const int c0 = ct.obj_first[k];
+  if (w < (ct.obj_first[k + 1] - c0) * J) {
+    float2 X[32], x32;
+    const int u = (p * C + ct.obj_chans[c0 + w / J]) * J + w % J;
+    forward64_core<false, 1>(lds + w * kWaveLds, lds + w * kWaveLds + LDS_HALF / 2, u, ct, C,
+                             J, nullptr, Ab, phi, nullptr, S, X, x32);
+  }
+  // every unit's S is written (visible to the workgroup after the barrier)
+  // and the transforms are done with LDS
+  __syncthreads();
+  constexpr int kPairs = kUnitF2 / 2;
+  double* red = reinterpret_cast<double*>(lds);
+  for (int f2 = threadIdx.x; f2 < kObjParts * 256; f2 += kFusedThreads) {
+    double acc = 0.0;
+    if (f2 < kPairs) acc += object_pair<N>(f2, p, k, C, J, K, ct, la, S, O);
+    red[f2] = acc;
+  }
+  __syncthreads();
+  // the object kernel's sums over each block of 256 pairs, all blocks at once
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    for (int t = threadIdx.x; t < kObjParts * s2; t += kFusedThreads) {
+      const int part = t / s2, i = t % s2;
+      red[part * 256 + i] += red[part * 256 + i + s2];
+    }
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < kObjParts)
+    loss_part[(size_t)plane * kObjParts + threadIdx.x] = red[threadIdx.x * 256];
 }
 
 __device__ __forceinline__ void adjoint64_unit(int u, const ChanTab& ct, int C, int J, int K,
@@ -400,6 +489,14 @@ hipError_t launch_forward64(const Dims& d, const ChanTab& ct, const int* active,
   else
     hipLaunchKernelGGL(k_forward64<false>, grid, dim3(64), 0, s, units, d.xcd_fwd, ct, d.C, d.J,
                        active, Ab, phi, psf, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwdobj64(const Dims& d, const ChanTab& ct, const LossArgs& la,
+                           const int* active, const float* Ab, const float* phi, float2* S,
+                           float2* O, double* loss_pk, hipStream_t s) {
+  hipLaunchKernelGGL(k_fwdobj64, dim3(d.P * d.K), dim3(kFusedThreads), 0, s, d.K, ct, d.C, d.J,
+                     la, active, Ab, phi, S, O, loss_pk);
   return hipGetLastError();
 }
 

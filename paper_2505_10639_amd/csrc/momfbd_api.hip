@@ -16,9 +16,10 @@
 using namespace mfbd;
 
 enum KernelKind { KK_PHASE, KK_FORWARD, KK_OBJECT, KK_ADJOINT, KK_GRAD, KK_PREPARE, KK_OBJIMG,
-                  KK_FILTER, KK_MOSAIC, KK_COUNT };
+                  KK_FILTER, KK_MOSAIC, KK_FWDOBJ, KK_COUNT };
 static const char* kKernelNames[KK_COUNT] = {"phase", "forward", "object", "adjoint", "grad",
-                                             "prepare", "objimg", "filter", "mosaic"};
+                                             "prepare", "objimg", "filter", "mosaic",
+                                             "forward_object"};
 
 // Optional kernel timing: an event pair around every launch, on its stream;
 // or, with a repeat kind set, only around the launches of that kind, each
@@ -249,6 +250,11 @@ int momfbd_plan_create(const momfbd_desc* desc, const float* pupil, const float*
       if (desc->channel_object[c] == k) pl->ct.obj_chans[nfill++] = c;
   }
   pl->ct.obj_first[K] = nfill;
+  // the forward/object launch takes a (patch, object) per workgroup, one
+  // wave per unit
+  pl->d.fuse_ok = N == 64;
+  for (int k = 0; k < K; ++k)
+    if ((pl->ct.obj_first[k + 1] - pl->ct.obj_first[k]) * J > kFusedWaves) pl->d.fuse_ok = false;
 
   const int B = N / 2, B0 = N / 4;
   const size_t BP = (size_t)B * B;
@@ -401,7 +407,8 @@ static bool tuning_ok(const momfbd_tuning* t) {
           t->grad_splits == 4 || t->grad_splits == 8) &&
          (t->grad_row_tiles == 0 ||
           (t->grad_waves == 4 ? t->grad_row_tiles >= 2 && t->grad_row_tiles <= 4
-                              : t->grad_row_tiles == 2));
+                              : t->grad_row_tiles == 2)) &&
+         (t->object_fused == 0 || t->object_fused == 1);
 }
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
@@ -417,6 +424,7 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   plan->d.grad_waves = t->grad_waves;
   plan->d.grad_splits = t->grad_splits;
   plan->d.grad_rt = t->grad_row_tiles == 3 || t->grad_row_tiles == 2 ? t->grad_row_tiles : 0;
+  plan->d.fuse_obj = t->object_fused;
   return MOMFBD_OK;
 }
 
@@ -429,6 +437,7 @@ int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* t) {
   t->grad_splits = grad_splits_of(plan->d);
   t->grad_row_tiles = grad_row_tiles_of(plan->d);
   phase_shape_of(plan->d, plan->Mq, &t->phase_col_tiles, &t->phase_waves);
+  t->object_fused = fused_object(plan->d) ? 1 : 0;
   return MOMFBD_OK;
 }
 
@@ -493,6 +502,16 @@ static int run_object(momfbd_plan plan, const float* alpha, const void* D, const
   hipError_t e = prof_launch(plan, KK_PHASE, s, [&] {
     return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
   });
+  if (e == hipSuccess && fused_object(plan->d)) {
+    e = prof_launch(plan, KK_FWDOBJ, s, [&] {
+      return launch_fwdobj64(plan->d, plan->ct, la, active, plan->Ab, w.phi, w.S, w.O,
+                             w.loss_pk, s);
+    });
+    if (e == hipSuccess && sum_loss)
+      e = launch_loss_sum(loss_sum_of(plan->d, active, w.loss_pk, loss), s);
+    *wout = w;
+    return to_status(e);
+  }
   if (e == hipSuccess)
     e = prof_launch(plan, KK_FORWARD, s, [&] {
       return launch_forward(plan->d, plan->ct, active, plan->Ab, w.phi, nullptr, w.S, s);
@@ -787,7 +806,18 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       case 1: return launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
       case 2: return launch_object(plan->d, plan->ct, la, nullptr, w.S, w.O, w.loss_pk, loss, s);
       case 3: return launch_grad(plan->d, plan->Zs, w.gphi, grad, w.gpart, s);
-      default: return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
+      case 4: return launch_phase(plan->d, alpha, plan->ZsT, plan->Mq, plan->thetat, w.phi, s);
+      default: {
+        // the forward and object pass, in one launch or two
+        if (fused_object(plan->d))
+          return launch_fwdobj64(plan->d, plan->ct, la, nullptr, plan->Ab, w.phi, w.S, w.O,
+                                 w.loss_pk, s);
+        const hipError_t e =
+            launch_forward(plan->d, plan->ct, nullptr, plan->Ab, w.phi, nullptr, w.S, s);
+        return e != hipSuccess ? e
+                               : launch_object(plan->d, plan->ct, la, nullptr, w.S, w.O,
+                                               w.loss_pk, loss, s);
+      }
     }
   };
   auto timed = [&](int knob, float* ms) -> int {
@@ -816,7 +846,9 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
   // gradient outputs of that schedule.  Knobs 0-5 time the adjoint, the
   // forward, the object kernel, (3, 4) the gradient contraction and (5) the
   // phase contraction, whose candidates are its automatic block and the
-  // selectable blocks (4 x 8, 8 x 16 tiles x waves) that fit.
+  // selectable blocks (4 x 8, 8 x 16 tiles x waves) that fit; knob 6, where
+  // the plan allows it, the forward and object pass in two launches (the
+  // default, under the schedules chosen for them) against one.
   constexpr int kRounds = 3;
   static const int kShapes[4][2] = {{4, 0}, {4, 3}, {4, 2}, {8, 0}};
   static const int kPhaseShapes[3][2] = {{0, 0}, {4, 8}, {8, 16}};
@@ -831,17 +863,20 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
         plan->d.grad_splits = 0;
         break;
       case 4: plan->d.grad_splits = v; break;
-      default:
+      case 5:
         plan->d.phase_ct = kPhaseShapes[v][0];
         plan->d.phase_waves = kPhaseShapes[v][1];
         break;
+      default: plan->d.fuse_obj = v; break;
     }
   };
   const Dims keep_d = plan->d;
-  std::vector<int> values[6] = {{1, 0}, {0, 1}, {1, 2, 4}, {0, 1, 2, 3}, {}, {0}};
+  std::vector<int> values[7] = {{1, 0}, {0, 1}, {1, 2, 4}, {0, 1, 2, 3}, {}, {0}, {}};
+  if (plan->d.fuse_ok) values[6] = {0, 1};
   for (int v = 1; v < 3; ++v)
     if (phase_shape_fits(kPhaseShapes[v][0], kPhaseShapes[v][1], plan->Mq)) values[5].push_back(v);
-  for (int k = 0; k < 6 && st == MOMFBD_OK; ++k) {
+  for (int k = 0; k < 7 && st == MOMFBD_OK; ++k) {
+    if (k == 6 && values[6].empty()) break;
     if (k == 4) {
       plan->d.grad_splits = 0;
       const int a = grad_splits_auto(plan->d);
@@ -854,7 +889,7 @@ int momfbd_plan_autotune(momfbd_plan plan, const float* alpha, const void* D, co
       for (size_t i = 0; i < values[k].size(); ++i) {
         set_knob(k, values[k][i]);
         float ms = 0.f;
-        if ((st = timed(k < 3 ? k : k < 5 ? 3 : 4, &ms))) break;
+        if ((st = timed(k < 3 ? k : k < 5 ? 3 : k - 1, &ms))) break;
         if (r == 0 || ms < fastest[i]) fastest[i] = ms;
       }
     }
@@ -1188,6 +1223,7 @@ int momfbd_group_get_tuning(momfbd_group g, momfbd_tuning* t) {
   t->grad_row_tiles = g->grad_rt;
   t->phase_col_tiles = kPhaseCols / 16;
   t->phase_waves = kPhaseWaves;
+  t->object_fused = 0;
   return MOMFBD_OK;
 }
 

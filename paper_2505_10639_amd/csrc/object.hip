@@ -19,24 +19,6 @@ namespace mfbd {
 
 namespace {
 
-struct Acc2 {
-  double nr[2], ni[2], q[2], e[2];
-};
-
-
-__device__ __forceinline__ void acc_unit(Acc2& a, double w, float4 d, float4 s) {
-  const double dx0 = d.x, dy0 = d.y, sx0 = s.x, sy0 = s.y;
-  const double dx1 = d.z, dy1 = d.w, sx1 = s.z, sy1 = s.w;
-  a.nr[0] += w * (dx0 * sx0 + dy0 * sy0);
-  a.ni[0] += w * (dy0 * sx0 - dx0 * sy0);
-  a.q[0] += w * (sx0 * sx0 + sy0 * sy0);
-  a.e[0] += w * (dx0 * dx0 + dy0 * dy0);
-  a.nr[1] += w * (dx1 * sx1 + dy1 * sy1);
-  a.ni[1] += w * (dy1 * sx1 - dx1 * sy1);
-  a.q[1] += w * (sx1 * sx1 + sy1 * sy1);
-  a.e[1] += w * (dx1 * dx1 + dy1 * dy1);
-}
-
 // Block `blk` of a field: plane blk / kBlocks = (patch, object), part
 // blk % kBlocks of that plane; its loss partial goes to loss_part[blk].
 template <int NN, int PPT>
@@ -46,9 +28,7 @@ __device__ __forceinline__ void object_block(int blk, int C, int J, int K, const
                                              const float2* __restrict__ S,
                                              float2* __restrict__ O,
                                              double* __restrict__ loss_part) {
-  constexpr int HC = NN / 2 + 1;
-  constexpr int kUnitF2 = NN * HC;
-  constexpr int kPairs = kUnitF2 / 2;
+  constexpr int kPairs = NN * (NN / 2 + 1) / 2;
   constexpr int kBlocks = object_blocks(NN, PPT);
   __shared__ double red[256];
   const int plane = blk / kBlocks, part = blk % kBlocks;
@@ -56,52 +36,10 @@ __device__ __forceinline__ void object_block(int blk, int C, int J, int K, const
   if (active && !active[p]) return;
   const int tid = threadIdx.x;
   double acc = 0.0;
-  const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
   for (int e = 0; e < PPT; ++e) {
     const int f2 = (part * PPT + e) * 256 + tid;
     if (f2 >= kPairs) break;
-    const int f = 2 * f2;
-    Acc2 a;
-    for (int i = 0; i < 2; ++i) {
-      a.nr[i] = a.ni[i] = a.e[i] = 0.0;
-      a.q[i] = la.gamma ? (double)la.gamma[(size_t)k * kUnitF2 + f + i] : (double)la.gamma_scalar;
-    }
-    // outside the object's spectral support every S of the pair is zero:
-    // it is not read (N = 0, Q = gamma, O = 0, loss term E)
-    const bool sup = in_support(f / HC, NN, la.supp[k * HC + f % HC]) ||
-                     in_support((f + 1) / HC, NN, la.supp[k * HC + (f + 1) % HC]);
-    for (int ci = c0; ci < c1; ++ci) {
-      const int c = ct.obj_chans[ci];
-      const float4* Dc = reinterpret_cast<const float4*>(la.D + ((size_t)(p * C + c) * J) * kUnitF2 + f);
-      const int s_bytes = J * kUnitF2 * 8;
-      const __amdgpu_buffer_rsrc_t rS = raw_buffer(S + ((size_t)(p * C + c) * J) * kUnitF2, s_bytes);
-      const int s_off = sup ? f * 8 : s_bytes;
-      constexpr int kStep = kUnitF2 * 8;   // bytes between frames
-      const float* wc = la.weights ? la.weights + c * J : nullptr;
-      int j = 0;
-      for (; j + 6 <= J; j += 6) {
-        float4 d[6], s[6];
-#pragma unroll
-        for (int u = 0; u < 6; ++u) {
-          d[u] = stream_load(Dc + (size_t)(j + u) * (kUnitF2 / 2));
-          s[u] = buffer_load_f4_stream(rS, sup ? s_off + (j + u) * kStep : s_bytes);
-        }
-#pragma unroll
-        for (int u = 0; u < 6; ++u) acc_unit(a, wc ? (double)wc[j + u] : 1.0, d[u], s[u]);
-      }
-      for (; j < J; ++j)
-        acc_unit(a, wc ? (double)wc[j] : 1.0, stream_load(Dc + (size_t)j * (kUnitF2 / 2)),
-                 buffer_load_f4_stream(rS, sup ? s_off + j * kStep : s_bytes));
-    }
-    const double inv0 = 1.0 / a.q[0], inv1 = 1.0 / a.q[1];
-    const float4 o = make_float4((float)(a.nr[0] * inv0), (float)(a.ni[0] * inv0),
-                                 (float)(a.nr[1] * inv1), (float)(a.ni[1] * inv1));
-    const int kx0 = f % HC, kx1 = (f + 1) % HC;
-    const double h0 = (kx0 == 0 || kx0 == HC - 1) ? 1.0 : 2.0;
-    const double h1 = (kx1 == 0 || kx1 == HC - 1) ? 1.0 : 2.0;
-    acc += h0 * (a.e[0] - (a.nr[0] * a.nr[0] + a.ni[0] * a.ni[0]) * inv0) +
-           h1 * (a.e[1] - (a.nr[1] * a.nr[1] + a.ni[1] * a.ni[1]) * inv1);
-    reinterpret_cast<float4*>(O + ((size_t)p * K + k) * kUnitF2)[f2] = o;
+    acc += object_pair<NN>(f2, p, k, C, J, K, ct, la, S, O);
   }
   red[tid] = acc;
   __syncthreads();
@@ -191,7 +129,9 @@ void launch_object_n(const Dims& d, const ChanTab& ct, const LossArgs& la, const
 }
 
 LossSum loss_sum_of(const Dims& d, const int* active, const double* loss_pk, double* loss) {
-  return LossSum{d.P, d.K * object_blocks(d.N, d.obj_ppt), active, loss_pk, loss};
+  // the fused forward/object kernel leaves the partials of one pair per thread
+  const int ppt = fused_object(d) ? 1 : d.obj_ppt;
+  return LossSum{d.P, d.K * object_blocks(d.N, ppt), active, loss_pk, loss};
 }
 
 hipError_t launch_loss_sum(const LossSum& ls, hipStream_t s) {

@@ -96,13 +96,15 @@ class Plan:
         return _lib.momfbd_plan_get_tuning(self.handle)
 
     def set_tuning(self, xcd_forward, xcd_adjoint, object_pairs_per_thread, grad_waves,
-                   grad_splits=0, grad_row_tiles=0, phase_col_tiles=0, phase_waves=0):
+                   grad_splits=0, grad_row_tiles=0, phase_col_tiles=0, phase_waves=0,
+                   object_fused=0):
         """Launch schedules (see momfbd_tuning); grad_splits 0 is automatic,
         grad_row_tiles 0 the default for the waves, phase_col_tiles and
-        phase_waves 0 the widest phase block that fits."""
+        phase_waves 0 the widest phase block that fits, object_fused 1 the
+        forward and object pass in one launch where the plan allows it."""
         _lib.momfbd_plan_set_tuning(self.handle, xcd_forward, xcd_adjoint,
                                     object_pairs_per_thread, grad_waves, grad_splits,
-                                    grad_row_tiles, phase_col_tiles, phase_waves)
+                                    grad_row_tiles, phase_col_tiles, phase_waves, object_fused)
 
     def autotune(self, alpha, D, gamma=1e-3, weights=None, reps=5):
         """Time the launch schedules on this data and keep the fastest."""

@@ -526,19 +526,25 @@ def test_launch_schedules_and_autotune(dev, N):
     auto = {64: 4, 96: 8, 128: 8}[N]
     assert plan.tuning() == {"xcd_forward": 0, "xcd_adjoint": 1, "object_pairs_per_thread": 1,
                              "grad_waves": 4, "grad_splits": auto, "grad_row_tiles": 4,
-                             "phase_col_tiles": 8, "phase_waves": 8}
+                             "phase_col_tiles": 8, "phase_waves": 8, "object_fused": 0}
+    # the forward and object pass in one launch applies at N = 64 (3 units per
+    # (patch, object) here)
+    fused = 1 if N == 64 else 0
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
     for knobs in [(1, 1, 1, 4), (0, 0, 1, 4), (0, 1, 2, 4), (0, 1, 4, 4), (0, 1, 1, 8),
                   (1, 0, 4, 8), (0, 1, 1, 4, 8), (0, 1, 1, 4, 1), (0, 1, 1, 4, 2),
                   (0, 1, 1, 8, 8), (0, 1, 1, 8, 1), (0, 1, 1, 4, 8, 3), (0, 1, 1, 4, 2, 3),
                   (0, 1, 1, 4, auto, 2), (0, 1, 1, 4, 1, 2), (0, 1, 1, 8, auto),
                   (0, 1, 1, 4, auto, 0, 4, 8), (0, 1, 1, 4, auto, 0, 8, 16),
-                  (0, 1, 1, 4, auto, 0, 8, 8)]:
+                  (0, 1, 1, 4, auto, 0, 8, 8), (0, 1, 1, 4, auto, 0, 0, 0, 1),
+                  (1, 0, 1, 4, auto, 0, 0, 0, 1), (0, 1, 2, 4, auto, 0, 4, 8, 1)]:
         print(f"[tuning] N={N} {knobs}", flush=True)
         plan.set_tuning(*knobs)
         l1, g1 = plan.loss_grad(a, D, pr.gamma)
         torch.cuda.synchronize()
-        if knobs[2] == 1:
+        # the one-launch pass is the two-launch pass with one pair per thread
+        assert plan.tuning()["object_fused"] == (fused if len(knobs) == 9 else 0)
+        if knobs[2] == 1 or plan.tuning()["object_fused"]:
             assert torch.equal(l1, l0)
         else:
             assert float(((l1 - l0).abs() / l0.abs()).max()) < 1e-12
@@ -567,6 +573,8 @@ def test_launch_schedules_and_autotune(dev, N):
         plan.set_tuning(0, 1, 1, 4, 0, 0, 4, 4)
     with pytest.raises(Exception):
         plan.set_tuning(0, 1, 1, 4, 0, 0, 8, 0)
+    with pytest.raises(Exception):
+        plan.set_tuning(0, 1, 1, 4, 0, 0, 0, 0, 2)
     plan.close()
 
 
@@ -582,21 +590,25 @@ def test_kernel_timing_leaves_results_unchanged(dev):
     a = to_dev(alpha_points(pr, 11)["perturbed"], dev)
     plan = make_plan(pr, dev)
     l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
-    momfbd_profile_start(plan.handle, 64)
-    l1, g1 = plan.loss_grad(a, D, pr.gamma)
-    kern = momfbd_profile_stop(plan.handle)
-    assert torch.equal(l1, l0) and torch.equal(g1, g0)
-    assert {k: v[1] for k, v in kern.items()} == {"phase": 1, "forward": 1, "object": 1,
-                                                  "adjoint": 1, "grad": 1}
-    for kind in ("phase", "forward", "object", "adjoint", "grad"):
-        print(f"[timing] repeat {kind}", flush=True)
-        momfbd_profile_start(plan.handle, 8)
-        momfbd_profile_repeat(plan.handle, kind, 3)
-        for _ in range(2):
-            l1, g1 = plan.loss_grad(a, D, pr.gamma)
+    # the forward and object pass in one launch (3 units per (patch, object)),
+    # then in two
+    for fused, kinds in ((1, ("phase", "forward_object", "adjoint", "grad")),
+                         (0, ("phase", "forward", "object", "adjoint", "grad"))):
+        plan.set_tuning(0, 1, 1, 4, object_fused=fused)
+        momfbd_profile_start(plan.handle, 64)
+        l1, g1 = plan.loss_grad(a, D, pr.gamma)
         kern = momfbd_profile_stop(plan.handle)
         assert torch.equal(l1, l0) and torch.equal(g1, g0)
-        assert list(kern) == [kind] and kern[kind][1] == 6 and kern[kind][0] > 0
+        assert {k: v[1] for k, v in kern.items()} == {k: 1 for k in kinds}
+        for kind in kinds:
+            print(f"[timing] repeat {kind}", flush=True)
+            momfbd_profile_start(plan.handle, 8)
+            momfbd_profile_repeat(plan.handle, kind, 3)
+            for _ in range(2):
+                l1, g1 = plan.loss_grad(a, D, pr.gamma)
+            kern = momfbd_profile_stop(plan.handle)
+            assert torch.equal(l1, l0) and torch.equal(g1, g0)
+            assert list(kern) == [kind] and kern[kind][1] == 6 and kern[kind][0] > 0
     momfbd_profile_start(plan.handle, 8)
     with pytest.raises(Exception):
         momfbd_profile_repeat(plan.handle, "filter", 2)
