@@ -69,17 +69,17 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per launch
 COUNTED_TRAFFIC = {
     ("adjoint", 64): {"sources_sha1": "fe8edcc74963", "knob": "xcd_adjoint",
-                      "by_value": {1: (895283239, 94470144), 0: (1094347538, 94470144)}},
-    ("forward", 64): {"sources_sha1": "13c77fb8801d", "knob": "xcd_forward",
-                      "by_value": {0: (94914058, 404911877), 1: (94914583, 401073992)}},
-    ("object", 64): {"sources_sha1": "8e15878e19b8", "knob": "object_pairs_per_thread",
-                     "by_value": {1: (729197152, 32782698)}},
+                      "by_value": {1: (895264574, 94470144), 0: (1094290663, 94470144)}},
+    ("forward", 64): {"sources_sha1": "fe8edcc74963", "knob": "xcd_forward",
+                      "by_value": {0: (94923414, 405011347), 1: (94926936, 401195873)}},
+    ("object", 64): {"sources_sha1": "380df0fcb916", "knob": "object_pairs_per_thread",
+                     "by_value": {1: (729207247, 32782494)}},
     ("adjoint", 128): {"sources_sha1": "64d2e7533f56", "knob": "xcd_adjoint",
-                       "by_value": {1: (11990566468, 1511522304), 0: (13298084803, 1511522304)}},
+                       "by_value": {1: (11984010648, 1511522304), 0: (13304748748, 1511522304)}},
     ("forward", 128): {"sources_sha1": "64d2e7533f56", "knob": "xcd_forward",
-                       "by_value": {0: (3214363495, 8835688080), 1: (3231126616, 8752537446)}},
-    ("object", 128): {"sources_sha1": "8e15878e19b8", "knob": "object_pairs_per_thread",
-                      "by_value": {1: (10901716100, 257960012)}},
+                       "by_value": {0: (3215663020, 8833985947), 1: (3230672758, 8745003407)}},
+    ("object", 128): {"sources_sha1": "380df0fcb916", "knob": "object_pairs_per_thread",
+                      "by_value": {1: (10901727308, 257959848)}},
 }
 
 
