@@ -3,8 +3,10 @@
 // One workgroup = one wavefront = one unit (patch p, channel c, frame j).
 //   forward : phase -> pupil -> inverse 2-D DFT -> |.|^2 (unit-sum PSF)
 //             -> forward 2-D DFT (OTF half spectrum)
-//   object  : Wiener object O_k = N_k / Q_k and the residual-form loss of the
-//             patch, accumulated in FP64
+//   fwdobj  : (a launch schedule) one workgroup of up to 12 waves per
+//             (patch, object): the forward of its units, then the Wiener
+//             object O_k = N_k / Q_k and the patch loss in FP64 with the
+//             object kernel's own per-pair code (object.hip)
 //   adjoint : G = conj(O)(D - O S) -> inverse DFT -> H = -4 w kappa g p
 //             -> forward DFT on the pupil band -> dL/dphi = Im(conj(P) G_P)
 //   prepare : patch cut, mean removal, apodization, mean restore, 2-D DFT
