@@ -459,7 +459,8 @@ typedef struct {
                                    coefficients fit 128 KB of LDS; 0, 0 on
                                    input picks 8 x 8 where it fits, else 4 x 4
                                    or 2 x 4 (get_tuning reports the shape in
-                                   use)                                       */
+                                   use; set_tuning also takes the automatic
+                                   shape as reported)                         */
   int object_fused;             /* 1: the forward transforms and the Wiener
                                    object and loss (Eqs. object_optimization,
                                    loss_momfbd) in one launch, a workgroup per

@@ -413,7 +413,13 @@ static bool tuning_ok(const momfbd_tuning* t) {
 
 int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* t) {
   if (!plan || !tuning_ok(t)) return MOMFBD_EINVAL;
-  const bool phase_auto = t->phase_col_tiles == 0 && t->phase_waves == 0;
+  // the automatic phase block, as get_tuning reports it, is accepted too
+  Dims dauto = plan->d;
+  dauto.phase_ct = dauto.phase_waves = 0;
+  int act = 0, awaves = 0;
+  phase_shape_of(dauto, plan->Mq, &act, &awaves);
+  const bool phase_auto = (t->phase_col_tiles == 0 && t->phase_waves == 0) ||
+                          (t->phase_col_tiles == act && t->phase_waves == awaves);
   if (!phase_auto && !phase_shape_fits(t->phase_col_tiles, t->phase_waves, plan->Mq))
     return MOMFBD_EINVAL;
   plan->d.phase_ct = phase_auto ? 0 : t->phase_col_tiles;

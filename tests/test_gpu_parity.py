@@ -39,7 +39,20 @@ def run_gpu(plan, alpha, D, gamma, weights, dev):
     return loss.cpu().numpy(), grad.cpu().numpy()
 
 
+def set_object_fused(plan, on):
+    """Switch the one-launch forward/object pass on or off, keeping the other
+    launch schedules; returns whether it is in use."""
+    t = plan.tuning()
+    plan.set_tuning(t["xcd_forward"], t["xcd_adjoint"], t["object_pairs_per_thread"],
+                    t["grad_waves"], t["grad_splits"], t["grad_row_tiles"], t["phase_col_tiles"],
+                    t["phase_waves"], int(on))
+    return bool(plan.tuning()["object_fused"])
+
+
 def check_patchwise(pr, D_np, alphas, dev, gamma=None, weights=None, patches=None):
+    """Loss and gradient against the oracle on every (or the sampled)
+    patch; where the plan allows the forward and object pass in one launch,
+    that schedule must give the same loss and gradient bit for bit."""
     plan = make_plan(pr, dev)
     D = to_dev(D_np, dev)
     g = pr.gamma if gamma is None else gamma
@@ -47,6 +60,10 @@ def check_patchwise(pr, D_np, alphas, dev, gamma=None, weights=None, patches=Non
         print(f"[parity] N={pr.N} P={pr.P} C={pr.C} K={pr.K} J={pr.J} M={pr.M} alpha={name}",
               flush=True)
         loss, grad = run_gpu(plan, a, D, g if np.isscalar(g) else to_dev(g, dev), weights, dev)
+        if set_object_fused(plan, True):
+            l1, g1 = run_gpu(plan, a, D, g if np.isscalar(g) else to_dev(g, dev), weights, dev)
+            assert np.array_equal(l1, loss) and np.array_equal(g1, grad), name
+            set_object_fused(plan, False)
         idx = range(pr.P) if patches is None else patches
         g_ref = g if np.isscalar(g) else oracle.expand_half(g, pr.N).real
         ref = oracle.evaluate(a, D_np, pr.basis, pr.diversity, pr.pupil, pr.channel_object,
@@ -430,6 +447,20 @@ def test_lbfgs_rounds_follow_the_step_trajectories(dev):
     assert torch.equal(s1.status, s2.status)
     assert torch.equal(s1.loss, s2.loss)
     assert torch.equal(x1, out)
+    # the forward and object pass in one launch, with the solver's per-patch
+    # masks (patches stop at different rounds): the same trajectories
+    assert set_object_fused(plan, True)
+    x3 = torch.zeros_like(x1)
+    out3 = torch.empty_like(x1)
+    s3 = Solver(plan, x3, D, pr.gamma, ftol=1e-4)
+    for _ in range(100):
+        s3.rounds(25, out3)
+        if bool((s3.status != 0).all()):
+            break
+    torch.cuda.synchronize()
+    assert torch.equal(s1.status, s3.status)
+    assert torch.equal(s1.loss, s3.loss)
+    assert torch.equal(x1, out3)
     plan.close()
 
 
