@@ -68,9 +68,9 @@ COPY_WRITE_SCALE = 1.0    # 256 MiB copy: WRITE_SIZE read 262144 KiB
 # per (kernel, N): the knob and, per value of it, (HBM bytes read, written)
 # per launch
 COUNTED_TRAFFIC = {
-    ("adjoint", 64): {"sources_sha1": "fa22212400ac", "knob": "xcd_adjoint",
+    ("adjoint", 64): {"sources_sha1": "0a485a0ac71b", "knob": "xcd_adjoint",
                       "by_value": {1: (895264574, 94470144), 0: (1094290663, 94470144)}},
-    ("forward", 64): {"sources_sha1": "fa22212400ac", "knob": "xcd_forward",
+    ("forward", 64): {"sources_sha1": "0a485a0ac71b", "knob": "xcd_forward",
                       "by_value": {0: (94923414, 405011347), 1: (94926936, 401195873)}},
     ("object", 64): {"sources_sha1": "380df0fcb916", "knob": "object_pairs_per_thread",
                      "by_value": {1: (729207247, 32782494)}},

@@ -203,7 +203,10 @@ __global__ __launch_bounds__(64) void k_forward64_group(GroupArgs ga, int xcd) {
 // waves moments before and come from the caches, not HBM: per step S
 // crosses HBM once less, and one launch is saved.  The workgroup holds
 // 110.6 KB of LDS, so a CU runs one at a time: the 12 waves its registers
-// allow the forward transforms in any case.
+// allow the forward transforms in any case.  But every CU then alternates a
+// transform phase and a memory phase in step with the others, and no second
+// workgroup fills the gaps: measured no faster than the two launches, it is
+// a launch schedule (object_fused), off by default.
 constexpr int kWaveLds = LDS_HALF / 2 + LDS_AUX;   // float2 per wave (transforms)
 constexpr int kObjParts = object_blocks(N, 1);     // 256-pair blocks of a plane
 constexpr int kFusedThreads = 64 * kFusedWaves;
