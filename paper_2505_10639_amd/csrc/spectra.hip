@@ -21,19 +21,37 @@
 namespace mfbd {
 namespace {
 
-__global__ __launch_bounds__(1024) void k_mean(long n, const float* __restrict__ x,
-                                               double* __restrict__ mean) {
-  __shared__ double red[1024];
+// The image mean in two passes: kMeanBlocks contiguous chunks, each summed
+// by one block (strided per thread, then a tree), and the chunk sums by one
+// block; every sum in a fixed order.
+constexpr int kMeanBlocks = 256;
+__device__ __forceinline__ double block_sum256(double v, double* red) {
   const int t = threadIdx.x;
-  double s = 0.0;
-  for (long i = t; i < n; i += 1024) s += (double)x[i];
-  red[t] = s;
+  red[t] = v;
   __syncthreads();
-  for (int h = 512; h > 0; h >>= 1) {
+  for (int h = 128; h > 0; h >>= 1) {
     if (t < h) red[t] += red[t + h];
     __syncthreads();
   }
-  if (t == 0) *mean = red[0] / (double)n;
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_mean_part(long n, const float* __restrict__ x,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  const long chunk = (n + kMeanBlocks - 1) / kMeanBlocks;
+  const long lo = (long)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += 256) s += (double)x[i];
+  const double tot = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_mean_final(long n, const double* __restrict__ part,
+                                                    double* __restrict__ mean) {
+  __shared__ double red[256];
+  const double tot = block_sum256(part[threadIdx.x], red);
+  if (threadIdx.x == 0) *mean = tot / (double)n;
 }
 
 // One row per block: FFT of length L in LDS, written transposed
@@ -124,21 +142,32 @@ __global__ __launch_bounds__(256) void k_sector_rows(int L, int nbins,
   }
 }
 
+// One block per bin: the per-row sums and counts of the bin over all rows
+// (strided per thread, then a tree).
 __global__ __launch_bounds__(256) void k_sector_bins(int L, int nbins,
                                                      const double* __restrict__ rsum,
                                                      const int* __restrict__ rcnt,
                                                      double* __restrict__ out,
                                                      int* __restrict__ counts) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= nbins) return;
+  __shared__ double red[256];
+  __shared__ long redc[256];
+  const int k = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
   long c = 0;
-  for (int y = 0; y < L; ++y) {
+  for (int y = t; y < L; y += 256) {
     s += rsum[(long)y * nbins + k];
     c += rcnt[(long)y * nbins + k];
   }
-  out[k] = c > 0 ? s / (double)c : 0.0;
-  if (counts) counts[k] = (int)c;
+  redc[t] = c;
+  const double tot = block_sum256(s, red);   // its barriers also order redc
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) redc[t] += redc[t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[k] = redc[0] > 0 ? tot / (double)redc[0] : 0.0;
+    if (counts) counts[k] = (int)redc[0];
+  }
 }
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -154,7 +183,7 @@ extern "C" {
 
 int momfbd_power_spectrum_workspace(int L, int nbins, size_t* bytes) {
   if (!bytes || !pow2(L) || nbins < 1 || nbins > L) return MOMFBD_EINVAL;
-  *bytes = al256(sizeof(double)) + al256((size_t)L * L * sizeof(float2)) +
+  *bytes = al256((kMeanBlocks + 1) * sizeof(double)) + al256((size_t)L * L * sizeof(float2)) +
            al256((size_t)L * nbins * sizeof(double)) + al256((size_t)L * nbins * sizeof(int));
   return MOMFBD_OK;
 }
@@ -171,7 +200,8 @@ int momfbd_power_spectrum(int L, const float* image, const float* window, float*
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
   double* mean = reinterpret_cast<double*>(w);
-  size_t o = al256(sizeof(double));
+  double* mean_part = mean + 1;
+  size_t o = al256((kMeanBlocks + 1) * sizeof(double));
   float2* T = reinterpret_cast<float2*>(w + o);
   o += al256((size_t)L * L * sizeof(float2));
   double* rsum = reinterpret_cast<double*>(w + o);
@@ -185,15 +215,17 @@ int momfbd_power_spectrum(int L, const float* image, const float* window, float*
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return MOMFBD_EDEVICE;
   }
-  hipLaunchKernelGGL(k_mean, dim3(1), dim3(1024), 0, s, (long)L * L, image, mean);
+  hipLaunchKernelGGL(k_mean_part, dim3(kMeanBlocks), dim3(256), 0, s, (long)L * L, image,
+                     mean_part);
+  hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(256), 0, s, (long)L * L, mean_part, mean);
   hipLaunchKernelGGL(k_fft_rows<true>, dim3(L), dim3(256), lds, s, L, image, window, mean,
                      nullptr, T, nullptr);
   hipLaunchKernelGGL(k_fft_rows<false>, dim3(L), dim3(256), lds, s, L, nullptr, nullptr, nullptr,
                      T, nullptr, power);
   if (sector) {
     hipLaunchKernelGGL(k_sector_rows, dim3(L), dim3(256), 0, s, L, nbins, power, rsum, rcnt);
-    hipLaunchKernelGGL(k_sector_bins, dim3((nbins + 255) / 256), dim3(256), 0, s, L, nbins, rsum,
-                       rcnt, sector, counts);
+    hipLaunchKernelGGL(k_sector_bins, dim3(nbins), dim3(256), 0, s, L, nbins, rsum, rcnt, sector,
+                       counts);
   }
   return hipGetLastError() == hipSuccess ? MOMFBD_OK : MOMFBD_EDEVICE;
 }
