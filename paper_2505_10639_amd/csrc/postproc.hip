@@ -15,7 +15,8 @@
 //
 // The filter works on the full N x N grid in LDS (H is symmetric under
 // u -> -u, so the half spectrum reads suffice); the island search is a
-// label propagation from the origin repeated until no label changes.
+// label propagation from the origin repeated until no label changes (at
+// N = 64 on one 64-bit word per row, in one wave).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -48,6 +49,31 @@ __device__ inline float median9(float v[9]) {
   return v[4];
 }
 
+// Cells of m reachable from x by steps toward higher (up) or lower (down)
+// bits through m: a doubling fill, six shifts for any run length.
+__device__ inline unsigned long long fill_up(unsigned long long x, unsigned long long m) {
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    x |= m & (x << s);
+    m &= m << s;
+  }
+  return x;
+}
+__device__ inline unsigned long long fill_down(unsigned long long x, unsigned long long m) {
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    x |= m & (x >> s);
+    m &= m >> s;
+  }
+  return x;
+}
+__device__ inline unsigned long long shfl64(unsigned long long v, int lane) {
+  const int lo = __shfl(static_cast<int>(v & 0xffffffffull), lane);
+  const int hi = __shfl(static_cast<int>(v >> 32), lane);
+  return (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+         static_cast<unsigned>(lo);
+}
+
 template <int NN>
 __global__ __launch_bounds__(256) void k_filter(int C, int J, int K, ChanTab ct, FilterTab ft,
                                                 const float2* __restrict__ D,
@@ -74,28 +100,46 @@ __global__ __launch_bounds__(256) void k_filter(int C, int J, int K, ChanTab ct,
     return;
   }
   const int c0 = ct.obj_first[k], c1 = ct.obj_first[k + 1];
-  for (int i = tid; i < GRID; i += 256) {
-    const int y = i / NN, x = i % NN;
-    // a frequency right of the half spectrum reads its mirror -u (the
-    // conjugate pair gives the same |num| and den)
-    const int hy = x > NN / 2 ? (NN - y) % NN : y, hx = x > NN / 2 ? NN - x : x;
-    const size_t off = (size_t)hy * HC + hx;
+  // the clipped H on the half spectrum (into B), the loads of four frames
+  // issued before their sums (which run in frame order)
+  auto acc = [&](double w, float2 d, float2 s, double& nr, double& ni, double& den) {
+    nr += w * ((double)d.x * s.x + (double)d.y * s.y);
+    ni += w * ((double)d.y * s.x - (double)d.x * s.y);
+    den += w * ((double)s.x * s.x + (double)s.y * s.y);
+  };
+  for (int i = tid; i < UNIT; i += 256) {
     double nr = 0.0, ni = 0.0, den = 0.0;
     for (int ci = c0; ci < c1; ++ci) {
       const int c = ct.obj_chans[ci];
-      for (int j = 0; j < J; ++j) {
-        const size_t u = ((size_t)(p * C + c) * J + j) * UNIT + off;
-        const double w = weights ? (double)weights[c * J + j] : 1.0;
-        const float2 d = D[u], s = S[u];
-        nr += w * ((double)d.x * s.x + (double)d.y * s.y);
-        ni += w * ((double)d.y * s.x - (double)d.x * s.y);
-        den += w * ((double)s.x * s.x + (double)s.y * s.y);
+      const size_t u0 = (size_t)(p * C + c) * J * UNIT + i;
+      const float* wc = weights ? weights + c * J : nullptr;
+      int j = 0;
+      for (; j + 4 <= J; j += 4) {
+        float2 d[4], s[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          d[e] = D[u0 + (size_t)(j + e) * UNIT];
+          s[e] = S[u0 + (size_t)(j + e) * UNIT];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc(wc ? (double)wc[j + e] : 1.0, d[e], s[e], nr, ni, den);
       }
+      for (; j < J; ++j)
+        acc(wc ? (double)wc[j] : 1.0, D[u0 + (size_t)j * UNIT], S[u0 + (size_t)j * UNIT], nr, ni,
+            den);
     }
     const double mag = nr * nr + ni * ni;
     double h = mag > 0.0 ? 1.0 - (double)f.noise_power * den / mag : 0.0;
     h = h < 0.2 ? 0.0 : (h > 1.0 ? 1.0 : h);
-    A[i] = (float)h;
+    B[i] = (float)h;
+  }
+  __syncthreads();
+  // the full grid: a frequency right of the half spectrum takes its mirror
+  // -u (the conjugate pair has the same |num| and den)
+  for (int i = tid; i < GRID; i += 256) {
+    const int y = i / NN, x = i % NN;
+    const int hy = x > NN / 2 ? (NN - y) % NN : y, hx = x > NN / 2 ? NN - x : x;
+    A[i] = B[hy * HC + hx];
   }
   __syncthreads();
   for (int i = tid; i < GRID; i += 256) {
@@ -110,6 +154,43 @@ __global__ __launch_bounds__(256) void k_filter(int C, int J, int K, ChanTab ct,
     B[i] = median9(v);
   }
   __syncthreads();
+  if constexpr (NN == 64) {
+    // the island search on bit masks: row y of the grid is a 64-bit word,
+    // held by lane y of the first wave; each sweep takes the rows above and
+    // below, the periodic neighbours within the row, and the runs of the
+    // row, until no word changes (the same 4-connected set as the label
+    // propagation below)
+    __shared__ unsigned long long Mrow[NN];
+    for (int y = tid >> 6; y < NN; y += 4) {
+      const unsigned long long m = __ballot(B[y * NN + (tid & 63)] > 0.f);
+      if ((tid & 63) == 0) Mrow[y] = m;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int y = tid;
+      const unsigned long long m = Mrow[y];
+      unsigned long long l = y == 0 ? (m & 1ull) : 0ull;
+      for (int it = 0; it < GRID; ++it) {
+        const unsigned long long v = shfl64(l, (y + NN - 1) % NN) | shfl64(l, (y + 1) % NN);
+        unsigned long long x = l | (v & m);
+        x |= ((x << 1) | (x >> 63) | (x >> 1) | (x << 63)) & m;
+        x = fill_down(fill_up(x, m), m);
+        const int ch = x != l;
+        l = x;
+        if (!__any(ch)) break;
+      }
+      Mrow[y] = l;
+    }
+    __syncthreads();
+    for (int i = tid; i < UNIT; i += 256) {
+      const int y = i / HC, x = i % HC;
+      const float h = (Mrow[y] >> x) & 1ull ? B[y * NN + x] : 0.f;
+      float2 o = Ok[i];
+      Ok[i] = make_float2(o.x * h, o.y * h);
+      if (Hk) Hk[i] = h;
+    }
+    return;
+  }
   int* L = reinterpret_cast<int*>(A);
   for (int i = tid; i < GRID; i += 256) L[i] = (i == 0 && B[0] > 0.f) ? 1 : 0;
   __syncthreads();
