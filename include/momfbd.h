@@ -477,8 +477,9 @@ int momfbd_plan_set_tuning(momfbd_plan plan, const momfbd_tuning* tuning);
 int momfbd_plan_get_tuning(momfbd_plan plan, momfbd_tuning* tuning);
 /* Choose the schedules by timing: one knob at a time, every candidate value
  * is timed on the caller's data (HIP events on `stream`, which this call
- * synchronises) by the one kernel the knob changes, run 4 x `reps` times
- * back to back after a whole evaluation under that candidate's schedule,
+ * synchronises) by the one kernel the knob changes (object_fused: the
+ * forward and object launches together), run 4 x `reps` times back to back
+ * after a whole evaluation under that candidate's schedule,
  * in three interleaved rounds; each candidate keeps its fastest round, and
  * the fastest candidate is kept.  The first candidate of each knob is the
  * library default, and another value replaces the best so far only when at
