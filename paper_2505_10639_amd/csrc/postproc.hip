@@ -234,6 +234,10 @@ __global__ __launch_bounds__(256) void k_mosaic(int N, int K, int nx, int ny, in
                                                 int border, int Hm, int Wm,
                                                 const float* __restrict__ obj,
                                                 float* __restrict__ out) {
+  // the 1-D taper of the block's patches, once per block (N <= 128)
+  __shared__ double tw[128];
+  for (int e = threadIdx.x; e < N; e += 256) tw[e] = taper1(e, N, border);
+  __syncthreads();
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (long)K * Hm * Wm) return;
   const int k = (int)(idx / ((long)Hm * Wm));
@@ -245,10 +249,10 @@ __global__ __launch_bounds__(256) void k_mosaic(int N, int K, int nx, int ny, in
   double acc = 0.0, ws = 0.0;
   for (int iy = iy0; iy <= iy1; ++iy) {
     const int ey = y - iy * stride;
-    const double wy = taper1(ey, N, border);
+    const double wy = tw[ey];
     for (int ix = ix0; ix <= ix1; ++ix) {
       const int ex = x - ix * stride;
-      const double w = wy * taper1(ex, N, border);
+      const double w = wy * tw[ex];
       acc += w * (double)obj[(((size_t)(iy * nx + ix) * K + k) * N + ey) * N + ex];
       ws += w;
     }
