@@ -609,6 +609,24 @@ def test_launch_schedules_and_autotune(dev, N):
     plan.close()
 
 
+def test_one_launch_pass_applies_up_to_twelve_units_per_object(dev):
+    """The forward/object pass in one launch takes a (patch, object) per
+    workgroup of at most 12 waves: a plan with 13 frames of one object keeps
+    the two launches when asked for it (get_tuning reports 0) and gives the
+    same results; with 12 frames it runs in one launch, bit for bit."""
+    for J, fused in ((13, False), (12, True)):
+        pr = synth.make_problem(230 + J, N=64, P=2, J=J, M=12, d_over_r0=8.0)
+        D = to_dev(simulate_D(pr), dev)
+        a = to_dev(alpha_points(pr, 1)["perturbed"], dev)
+        plan = make_plan(pr, dev)
+        l0, g0 = (t.clone() for t in plan.loss_grad(a, D, pr.gamma))
+        assert set_object_fused(plan, True) == fused
+        l1, g1 = plan.loss_grad(a, D, pr.gamma)
+        torch.cuda.synchronize()
+        assert torch.equal(l1, l0) and torch.equal(g1, g0)
+        plan.close()
+
+
 def test_kernel_timing_leaves_results_unchanged(dev):
     """The library's kernel timing (an event pair per launch, or one kind
     repeated back to back inside its pair) changes no result bit."""
