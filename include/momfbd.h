@@ -563,9 +563,11 @@ int momfbd_group_lbfgs_rounds(momfbd_group group, int rounds, void* stream);
  * xcd_forward, xcd_adjoint, grad_splits, grad_row_tiles 4, 3 or 2 (0: 4, or
  * 3 and 2 where the group's largest mode count reaches 176 and 224, whose
  * accumulators would not fit four tiles); grad_waves must be 4; the phase
- * fields are ignored: a group's phase blocks are 4 tiles x 8 waves).  The autotuner times momfbd_group_loss_grad over `reps`
- * evaluations per candidate with the plan autotuner's method and keeps the
- * fastest schedule.  Errors: EINVAL, EDEVICE. */
+ * fields are ignored: a group's phase blocks are 4 tiles x 8 waves; a group
+ * runs the forward and object pass in two launches, object_fused is
+ * ignored and reported 0).  The autotuner times momfbd_group_loss_grad over
+ * `reps` evaluations per candidate with the plan autotuner's method and
+ * keeps the fastest schedule.  Errors: EINVAL, EDEVICE. */
 int momfbd_group_set_tuning(momfbd_group group, const momfbd_tuning* tuning);
 int momfbd_group_get_tuning(momfbd_group group, momfbd_tuning* tuning);
 int momfbd_group_autotune(momfbd_group group, int reps, void* stream, momfbd_tuning* chosen);
