@@ -34,19 +34,24 @@ __device__ inline float tophat_value(int uy, int ux, int N, const FilterSpec& f)
   return (float)(0.5 * (1.0 + cos(kPi * (r - (double)f.f_lo) / ((double)f.f_hi - (double)f.f_lo))));
 }
 
-__device__ inline float median9(float v[9]) {
-  // insertion sort; the median is one of the inputs, so it is exact
+// The median of nine values without branches: sort each of the three
+// triples, then the median of (largest low, median middle, smallest high)
+// is the median of all nine; it is one of the inputs, so it is exact.
+__device__ inline float med3(float a, float b, float c) {
+  return fmaxf(fminf(a, b), fminf(fmaxf(a, b), c));
+}
+__device__ inline float median9(const float v[9]) {
+  float lo[3], mi[3], hi[3];
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const float x = v[i];
-    int j = i - 1;
-    while (j >= 0 && v[j] > x) {
-      v[j + 1] = v[j];
-      --j;
-    }
-    v[j + 1] = x;
+  for (int t = 0; t < 3; ++t) {
+    const float a = v[3 * t], b = v[3 * t + 1], c = v[3 * t + 2];
+    const float l = fminf(a, b), h = fmaxf(a, b);
+    lo[t] = fminf(l, c);
+    mi[t] = fmaxf(l, fminf(h, c));
+    hi[t] = fmaxf(h, c);
   }
-  return v[4];
+  return med3(fmaxf(fmaxf(lo[0], lo[1]), lo[2]), med3(mi[0], mi[1], mi[2]),
+              fminf(fminf(hi[0], hi[1]), hi[2]));
 }
 
 // Cells of m reachable from x by steps toward higher (up) or lower (down)

@@ -1,4 +1,7 @@
-"""The 64x64 island search of the Loefdahl-Scharmer filter works on one
+"""Word and min/max operations of the Loefdahl-Scharmer filter kernel,
+written out in Python and checked against plain definitions.
+
+The 64x64 island search of the filter works on one
 64-bit word per grid row: each sweep ORs in the rows above and below, the
 periodic neighbours within the row, and the runs of the row by a doubling
 fill, until no word changes.  Here the same word operations, written out in
@@ -86,3 +89,33 @@ def test_row_word_fill_matches_breadth_first_search():
     B[2, 2:N - 3] = True
     B[5, 40] = True   # isolated
     np.testing.assert_array_equal(island_words(B), island_bfs(B))
+
+
+def _med3(a, b, c):
+    return np.maximum(np.minimum(a, b), np.minimum(np.maximum(a, b), c))
+
+
+def median9_by_triples(v):
+    """The kernel's median of nine: sort each triple, then the median of
+    (largest low, median middle, smallest high)."""
+    lo, mi, hi = [], [], []
+    for t in range(3):
+        a, b, c = v[3 * t], v[3 * t + 1], v[3 * t + 2]
+        lo_ab, hi_ab = np.minimum(a, b), np.maximum(a, b)
+        lo.append(np.minimum(lo_ab, c))
+        mi.append(np.maximum(lo_ab, np.minimum(hi_ab, c)))
+        hi.append(np.maximum(hi_ab, c))
+    return _med3(np.maximum(np.maximum(lo[0], lo[1]), lo[2]), _med3(*mi),
+                 np.minimum(np.minimum(hi[0], hi[1]), hi[2]))
+
+
+def test_median_of_nine_by_triples_is_the_median():
+    rng = np.random.default_rng(1)
+    for trial in range(6):
+        if trial % 3 == 0:   # clipped filter values: many exact zeros and ones
+            v = rng.random((9, 50000)).astype(np.float32)
+            v[v < 0.3] = 0.0
+            v[v > 0.9] = 1.0
+        else:                # small integers: many ties
+            v = rng.integers(0, 4 if trial % 2 else 1000, size=(9, 50000)).astype(np.float32)
+        np.testing.assert_array_equal(median9_by_triples(v), np.sort(v, axis=0)[4])
